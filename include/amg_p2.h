@@ -1,0 +1,216 @@
+/*
+ * amg_p2.h -- C ABI of the MI355X (gfx950) algebraic multigrid library for
+ * hierarchical quadratic finite element systems.
+ *
+ * Method: H. Yang, "An algebraic multigrid method for quadratic finite element
+ * equations of elliptic and saddle point systems in 3D", arXiv:1503.01287.
+ *
+ *   amg_setup  builds the multigrid hierarchy of Section 3.2: separate
+ *              coarse/fine splits of the linear-node graph (pattern of K_ll)
+ *              and the quadratic-node graph (pattern of K_qq), block-diagonal
+ *              prolongation P = diag(I, J) (saddle: diag(I, J, H)) and
+ *              Galerkin coarse operators P^T K_l P computed on the GPU.
+ *   amg_solve  runs the AMG-preconditioned Krylov method of Sections 3.1 and
+ *              4: Algorithm 1 (the basic AMG iteration, V-cycle for nu = 1)
+ *              as the preconditioner of CG (SPD systems, equation for A u = f
+ *              in Section 2.4) or of flexible GMRES (saddle point systems
+ *              [[A, B^T], [B, -C]] [u; p] = [f; g], Section 2.4).
+ *
+ * Conventions for every entry point
+ *  - Status: 0 on success, > 0 a solver outcome (AMG_NOT_CONVERGED, ...),
+ *    < 0 an error (invalid argument, HIP failure, out of memory, unsupported
+ *    input). amg_last_error() returns a text for the last error of the
+ *    calling thread. No entry point aborts the process.
+ *  - Index type: int32 (row pointers, column indices).
+ *  - Node vectors: every velocity/displacement node carries 3 components,
+ *    stored interleaved (x[3*i + c]); pressure vectors carry one value per
+ *    pressure node; a saddle vector is [u (3*N values); p (Np values)].
+ *  - Node order: linear nodes (mesh vertices) first, then quadratic nodes
+ *    (mesh edges), as in the DOF vector [u_l; u_q] of Section 2.4.
+ *  - Streams: a stream argument is a hipStream_t (NULL = legacy default
+ *    stream). All device work is ordered on it; the call returns after the
+ *    work it needs on the host is complete (see each call).
+ *  - Ownership: the library copies whatever it keeps; it never retains a
+ *    caller pointer after a call returns. Handles are freed by amg_destroy.
+ *  - Threading: a handle may be used by one host thread at a time.
+ */
+#ifndef AMG_P2_H
+#define AMG_P2_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct amg_ctx *amg_handle;
+typedef void *amg_stream; /* hipStream_t */
+
+/* ---- status codes ---------------------------------------------------- */
+#define AMG_OK 0
+#define AMG_NOT_CONVERGED 1 /* maxit reached before tol */
+#define AMG_BREAKDOWN 2     /* Krylov breakdown (e.g. <p, A p> <= 0 in CG) */
+#define AMG_DIVERGED 3      /* NaN/Inf or relative residual above 1e3 */
+#define AMG_EINVAL (-1)
+#define AMG_EHIP (-2)
+#define AMG_ENOMEM (-3)
+#define AMG_EUNSUPPORTED (-4)
+
+/* ---- smoothers (Section 3.3) ----------------------------------------- */
+#define AMG_SMOOTH_JA 0  /* damped block Jacobi ("JA-m-m-omega")            */
+#define AMG_SMOOTH_GS 1  /* block Gauss-Seidel by colours ("GS-m-m")        */
+#define AMG_SMOOTH_SGS 2 /* segregated Gauss-Seidel / Uzawa ("sGS-m-m")     */
+#define AMG_SMOOTH_BS 3  /* Braess-Sarazin ("Braess-Sarazin-m-m")           */
+
+/* ---- outer iterations ------------------------------------------------ */
+#define AMG_KRYLOV_PCG 0    /* preconditioned CG, FP64 (SPD)                 */
+#define AMG_KRYLOV_FCG 1    /* flexible CG (one-term), FP64 outer loop (SPD) */
+#define AMG_KRYLOV_FGMRES 2 /* right-preconditioned flexible GMRES(m)        */
+#define AMG_KRYLOV_NONE 3   /* stand-alone AMG: repeated Algorithm 1         */
+
+/* ---- arithmetic of the preconditioner -------------------------------- */
+#define AMG_PREC_FP64 0  /* every level in FP64                               */
+#define AMG_PREC_MIXED 1 /* FP32 cycle vectors, FP32 finest operator, BF16
+                            coarse operators with per-row FP32 scales; outer
+                            Krylov loop, its dots and the coarsest solve FP64 */
+
+/*
+ * The linear system (Section 2.4). All pointers are HOST pointers; the
+ * library copies the data to the device.
+ *
+ * A (velocity/displacement block): square over N = n_lin + n_quad nodes, CSR
+ *   over nodes with sorted column indices and every diagonal entry present.
+ *   bs = 3: each entry is a 3x3 block, A_val holds 9 doubles per entry in
+ *           row-major order (A_val[9*k + 3*r + c]).
+ *   bs = 1: A = A_s (x) I_3 (the vector Laplacian); A_val holds one double per
+ *           entry, applied to each of the 3 components.
+ *   The pattern is the STRUCTURAL pattern (all node pairs coupled through an
+ *   element); entries whose value is zero must be kept, because coarsening
+ *   uses the connectivity graph of the matrix (Section 3.2).
+ * B (saddle only, n_pres > 0): n_pres rows (pressure nodes = mesh vertices,
+ *   the same order as the linear velocity nodes, so n_pres == n_lin) times N
+ *   node columns, 1x3 blocks (B_val[3*k + c]). Requires bs = 3.
+ * C (saddle only, optional): n_pres x n_pres scalar CSR; NULL pointers mean
+ *   C = 0 (Stokes, Section 2.4).
+ * pressure_kernel: 1 when constant pressures lie in the kernel (velocity
+ *   Dirichlet data on the whole boundary, C = 0); the coarsest solve then
+ *   pins its last pressure unknown.
+ */
+typedef struct {
+    int32_t n_lin, n_quad, n_pres;
+    int32_t bs;
+    const int32_t *A_rowptr, *A_col;
+    const double *A_val;
+    const int32_t *B_rowptr, *B_col;
+    const double *B_val;
+    const int32_t *C_rowptr, *C_col;
+    const double *C_val;
+    int32_t pressure_kernel;
+} amg_system;
+
+/*
+ * Parameters. amg_default_params fills the paper's defaults: GS-1-1, JA damping
+ * 0.5 (Section 4.2), sGS omega 0.125 with block-Jacobi damping 0.5 (Sections
+ * 3.3 and 4.4), one V-cycle per preconditioner application, separated
+ * coarsening, coarsening until at most 300 unknowns or 10 levels, PCG, FP64.
+ */
+typedef struct {
+    int32_t smoother;     /* AMG_SMOOTH_*                                    */
+    int32_t pre, post;    /* m_pre, m_post of Algorithm 1                    */
+    double omega;         /* JA damping                                      */
+    double sgs_omega;     /* sGS pressure parameter omega                    */
+    double sgs_damping;   /* sGS M_A: damped block Jacobi damping            */
+    int32_t cycles;       /* Algorithm 1 applications per preconditioning    */
+    int32_t nu;           /* recursive calls per level: 1 = V, 2 = W         */
+    int32_t max_levels;   /* including the finest                            */
+    int32_t coarse_max;   /* stop when a level has <= this many unknowns     */
+    int32_t separate;     /* 1 = the paper's separated linear/quadratic
+                             graphs, 0 = one graph over all nodes            */
+    int32_t krylov;       /* AMG_KRYLOV_*                                    */
+    int32_t restart;      /* FGMRES restart length                           */
+    int32_t precision;    /* AMG_PREC_*                                      */
+    int32_t n_level_omega;        /* > 0: per-level JA damping follows     */
+    const double *level_omega;    /* host, n_level_omega values (copied)   */
+} amg_params;
+
+typedef struct {
+    int32_t iters;     /* outer iterations performed                         */
+    int32_t status;    /* AMG_OK / AMG_NOT_CONVERGED / AMG_BREAKDOWN / ...   */
+    double relres;     /* true relative residual ||b - K x|| / ||b - K x0||  */
+    double solve_ms;   /* wall time of the solve on the host clock           */
+} amg_result;
+
+typedef struct {
+    int32_t n_lin, n_quad, n_pres; /* nodes on the level                      */
+    int32_t bs;                    /* 3 or 1                                   */
+    int64_t nnz_A, nnz_B, nnz_C;   /* stored entries (blocks)                  */
+    int64_t nnz_P;                 /* entries of the scalar prolongation to
+                                      this level from the next coarser one
+                                      (0 on the coarsest level)               */
+    int32_t n_colors;              /* Gauss-Seidel colours (0 if not built)    */
+    int32_t is_coarsest;
+} amg_level_info;
+
+/* Fill *p with the defaults listed above. */
+void amg_default_params(amg_params *p);
+
+/* Build the hierarchy for *sys (Section 3.2). Device work runs on `stream`;
+ * returns after setup is complete. On success *out owns all device memory of
+ * the hierarchy. Errors: AMG_EINVAL (inconsistent sizes, missing diagonal,
+ * unsorted columns), AMG_EUNSUPPORTED (a coarse row beyond the Galerkin
+ * kernel's capacity), AMG_ENOMEM, AMG_EHIP. */
+int amg_setup(const amg_system *sys, const amg_params *params, amg_stream stream, amg_handle *out);
+
+/* Solve K x = b to ||b - K x_k|| <= tol ||b - K x_0|| (Section 4's stopping
+ * rule, Euclidean norm of the whole residual). b and x are DEVICE pointers of
+ * 3N (+ n_pres) doubles; x holds x_0 on entry and the solution on return.
+ * maxit bounds the outer iterations. Returns the solver status (also stored
+ * in res->status, with iterations and the true relative residual). Blocks
+ * until the solve has finished. */
+int amg_solve(amg_handle h, const double *b, double *x, double tol, int32_t maxit,
+              amg_stream stream, amg_result *res);
+
+/* z = M^{-1} r: `cycles` applications of Algorithm 1 from a zero initial
+ * guess on the finest level (the preconditioner used inside amg_solve).
+ * r, z: device pointers, same layout as amg_solve's b and x. FP64 in and
+ * out; under AMG_PREC_MIXED the cycle itself runs in the mixed arithmetic. */
+int amg_precondition(amg_handle h, const double *r, double *z, amg_stream stream);
+
+/* y = K_l x on hierarchy level l (device pointers, level-l layout). */
+int amg_apply(amg_handle h, int32_t level, const double *x, double *y, amg_stream stream);
+
+/* One smoothing step S_l(x, b) of the configured smoother on level l, in
+ * place on x (device pointers). forward = 1 for a pre-smoothing step (colours
+ * ascending), 0 for a post-smoothing step (colours descending). */
+int amg_smooth(amg_handle h, int32_t level, const double *b, double *x, int32_t forward,
+               amg_stream stream);
+
+int amg_num_levels(amg_handle h);
+int amg_get_level_info(amg_handle h, int32_t level, amg_level_info *info);
+
+/* Copy a level operator to HOST arrays sized from amg_get_level_info:
+ * which = 0: A (rowptr n+1, col nnz_A, val nnz_A*bs*bs), 1: B (1x3 blocks),
+ * 2: C, 3: P (scalar prolongation from level+1 to level, n rows). */
+int amg_get_level_matrix(amg_handle h, int32_t level, int32_t which, int32_t *rowptr,
+                         int32_t *col, double *val);
+
+/* Colour of every node of level l (host array of n_lin + n_quad int32). */
+int amg_get_level_colors(amg_handle h, int32_t level, int32_t *colors);
+
+/* Per-kernel timing of the hot loops with HIP events recorded on the
+ * library's launch stream. enable = 1 starts (and clears) the counters. */
+int amg_profile_enable(amg_handle h, int32_t enable);
+/* Kernel classes: "spmv", "gs", "jacobi", "resid", "restrict", "prolong",
+ * "coarse", "blas". Returns launches, total ms and algorithmic bytes. */
+int amg_profile_read(amg_handle h, const char *kernel_class, int64_t *launches, double *total_ms,
+                     double *bytes);
+
+void amg_destroy(amg_handle h);
+const char *amg_status_string(int status);
+const char *amg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AMG_P2_H */

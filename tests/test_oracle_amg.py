@@ -1,0 +1,375 @@
+"""Pins of the oracle's multigrid method: exact coarsening counts of the
+paper, closed forms, brute-force dense formulas and textbook Krylov facts."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import synth
+from oracle import amg, cloops, fem, krylov, mesh as M, workloads
+
+
+# ---------------------------------------------------------------- coarsening
+@pytest.fixture(scope="module")
+def l4_pattern():
+    m = M.kuhn_mesh(32)
+    return m, fem.structural_pattern(m)
+
+
+def test_table2_linear_and_nonseparating_exact(golden, l4_pattern):
+    """Section 4.1's coarse-DOF table on L4: the linear row and the
+    non-separating row are reproduced exactly."""
+    rows = {r[0]: [int(v) for v in r[1:]] for r in golden("table2_coarse_dofs.txt")}
+    m, pat = l4_pattern
+    sep = amg.structural_sizes(pat, m.nv, m.ne)
+    assert [3 * nl for nl, _ in sep] == rows["linear"]
+    non = amg.structural_sizes(pat, m.nv, m.ne, separate=False)
+    assert [3 * (a + b) for a, b in non] == rows["nonseparating"]
+    # the quadratic row depends on the unstated node order: same level count,
+    # same finest and coarsest sizes, every level within 30%
+    quad = [3 * nq for _, nq in sep]
+    assert len(quad) == len(rows["quadratic"])
+    assert quad[0] == rows["quadratic"][0]
+    for ours, paper in zip(quad, rows["quadratic"]):
+        assert abs(ours - paper) <= 0.3 * paper
+
+
+def test_mis_independent_maximal_and_interpolation():
+    s = workloads.laplace(4)
+    ip, ix = amg.node_graph(s.A, 0, s.nlin + s.nquad)
+    c = cloops.greedy_mis(ip, ix)
+    rows = np.repeat(np.arange(len(c)), np.diff(ip))
+    assert not np.any(c[rows] & c[ix]), "two coarse neighbours"
+    has_c = np.bincount(rows[c[ix]], minlength=len(c)) > 0
+    assert np.all(c | has_c), "fine node without coarse neighbour (not maximal)"
+    P = amg.averaging_prolongation(ip, ix, c)
+    assert np.allclose(np.asarray(P.sum(axis=1)).ravel(), 1.0)
+    # brute-force greedy in pure Python
+    st = np.zeros(len(c), dtype=int)
+    for i in range(len(c)):
+        if st[i] == 0:
+            st[i] = 1
+            for j in ix[ip[i]:ip[i + 1]]:
+                if st[j] == 0:
+                    st[j] = 2
+    assert np.array_equal(st == 1, c)
+
+
+def test_level1_linear_block_is_p1_stiffness_on_2h_mesh():
+    """The linear graph's split keeps the even lattice, every fine vertex has
+    exactly two coarse neighbours, so P is P1 interpolation and the Galerkin
+    K_ll on level 1 equals the P1 stiffness of the 2h Kuhn mesh."""
+    n = 8
+    s = fem.vector_laplacian(n, lambda X: np.zeros((X.shape[0], 3)),
+                             lambda m: np.zeros(m.nv, dtype=bool))
+    h = amg.setup(s.A, s.nlin, s.nquad)
+    lev1 = h.levels[1]
+    coarse = fem.assemble_velocity_block(M.kuhn_mesh(n // 2), "laplace")
+    nl = lev1.nlin
+    assert nl == (n // 2 + 1) ** 3
+    K1 = lev1.A.dense()[: 3 * nl, : 3 * nl]
+    K2h = coarse.dense()[: 3 * nl, : 3 * nl]
+    assert np.abs(K1 - K2h).max() < 1e-13 * np.abs(K2h).max()
+
+
+def test_galerkin_equals_dense_and_symmetric():
+    s = workloads.elasticity(2)
+    h = amg.setup(s.A, s.nlin, s.nquad, coarse_max=30)
+    assert h.L >= 1
+    A0 = s.A.dense()
+    P = h.levels[0].P.toarray()
+    Pk = np.kron(P, np.eye(3))
+    assert np.abs(h.levels[1].A.dense() - Pk.T @ A0 @ Pk).max() < 1e-14 * np.abs(A0).max()
+    s8 = workloads.elasticity(8)
+    h8 = amg.setup(s8.A, s8.nlin, s8.nquad)
+    for lev in h8.levels:
+        Ad = lev.A.scipy()
+        assert spla.norm(Ad - Ad.T) <= 1e-14 * spla.norm(Ad)
+
+
+def test_colouring_valid():
+    s = workloads.elasticity(4)
+    h = amg.setup(s.A, s.nlin, s.nquad)
+    for lev in h.levels:
+        rows = lev.A.row_of()
+        off = rows != lev.A.indices
+        assert not np.any(lev.colors[rows[off]] == lev.colors[lev.A.indices[off]])
+
+
+# ---------------------------------------------------------------- smoothers
+def _blocks_dense(lev):
+    A = lev.A.dense()
+    n = lev.n
+    return A, n
+
+
+def test_gauss_seidel_is_dense_block_lower_solve():
+    """One forward block GS sweep in node order pi equals
+    x + (L + D)^{-1} (b - A x) with L + D the block-lower part of the
+    symmetrically permuted matrix."""
+    s = workloads.elasticity(2)
+    h = amg.setup(s.A, s.nlin, s.nquad, coloured=False)
+    lev = h.levels[0]
+    A, n = _blocks_dense(lev)
+    rng = np.random.default_rng(0)
+    b, x = rng.standard_normal((n, 3)), rng.standard_normal((n, 3))
+    blk = np.arange(3 * n) // 3
+    LD = np.where(blk[:, None] >= blk[None, :], A, 0.0)
+    expect = x.ravel() + np.linalg.solve(LD, b.ravel() - A @ x.ravel())
+    got = amg.gauss_seidel(lev, b, x, forward=True)
+    assert np.abs(got.ravel() - expect).max() < 1e-12
+    UD = np.where(blk[:, None] <= blk[None, :], A, 0.0)
+    expect_b = x.ravel() + np.linalg.solve(UD, b.ravel() - A @ x.ravel())
+    assert np.abs(amg.gauss_seidel(lev, b, x, forward=False).ravel() - expect_b).max() < 1e-12
+
+
+def test_coloured_gs_independent_of_order_within_colour():
+    s = workloads.elasticity(3)
+    h = amg.setup(s.A, s.nlin, s.nquad)
+    lev = h.levels[0]
+    rng = np.random.default_rng(1)
+    b, x = rng.standard_normal((lev.n, 3)), rng.standard_normal((lev.n, 3))
+    ref = amg.gauss_seidel(lev, b, x, forward=True)
+    shuffled = np.lexsort((rng.permutation(lev.n), lev.colors))
+    x2 = np.ascontiguousarray(x.copy())
+    cloops.block_gs(shuffled, lev.A.indptr, lev.A.indices, lev.A.vals, lev.dinv, b, x2)
+    assert np.array_equal(ref, x2)
+
+
+def test_jacobi_dense_formula():
+    s = workloads.laplace(2)
+    h = amg.setup(s.A, s.nlin, s.nquad)
+    lev = h.levels[0]
+    A = lev.A.dense()
+    D = np.zeros_like(A)
+    for i in range(lev.n):
+        D[3 * i:3 * i + 3, 3 * i:3 * i + 3] = A[3 * i:3 * i + 3, 3 * i:3 * i + 3]
+    rng = np.random.default_rng(2)
+    b, x = rng.standard_normal(3 * lev.n), rng.standard_normal(3 * lev.n)
+    expect = x + 0.5 * np.linalg.solve(D, b - A @ x)
+    got = amg.jacobi(lev, b.reshape(-1, 3), x.reshape(-1, 3), 0.5).ravel()
+    assert np.abs(got - expect).max() < 1e-12
+
+
+# ---------------------------------------------------------------- cycle
+def _dense_operator(apply, n):
+    return np.stack([apply(e).ravel() for e in np.eye(n)], axis=1)
+
+
+@pytest.mark.parametrize("name", ["GS-1-1", "JA-1-1-0.5", "GS-2-2"])
+def test_vcycle_preconditioner_symmetric_positive(name):
+    """Forward pre-/backward post-smoothing makes the V-cycle operator
+    symmetric; it is positive definite (usable inside CG)."""
+    s = workloads.elasticity(2)
+    h = amg.setup(s.A, s.nlin, s.nquad, coarse_max=60)
+    assert h.L >= 1
+    Mi = _dense_operator(amg.preconditioner(h, amg.Smoother.parse(name)), 3 * s.A.nrows)
+    assert np.abs(Mi - Mi.T).max() < 1e-12 * np.abs(Mi).max()
+    assert np.linalg.eigvalsh(0.5 * (Mi + Mi.T)).min() > 0
+
+
+def test_two_level_rate_matches_error_operator():
+    """Stand-alone AMG error reduction per cycle approaches the spectral radius
+    of the dense two-level error operator E = I - M^{-1} A."""
+    s = workloads.laplace(2)
+    h = amg.setup(s.A, s.nlin, s.nquad, coarse_max=200)
+    assert h.L == 1
+    sm = amg.Smoother.parse("GS-1-1")
+    A = s.A.dense()
+    Mi = _dense_operator(amg.preconditioner(h, sm), A.shape[0])
+    rho = np.abs(np.linalg.eigvals(np.eye(A.shape[0]) - Mi @ A)).max()
+    rng = np.random.default_rng(4)
+    e = rng.standard_normal(A.shape[0])
+    for _ in range(60):
+        e = e - Mi @ (A @ e)
+    n0 = np.linalg.norm(e)
+    for _ in range(20):
+        e = e - Mi @ (A @ e)
+    rate = (np.linalg.norm(e) / n0) ** (1 / 20)
+    assert abs(rate - rho) < 0.02 and rho < 1
+
+
+# ---------------------------------------------------------------- Krylov
+def test_pcg_exact_preconditioner_one_iteration():
+    s = workloads.laplace(2)
+    A = s.A.dense()
+    Ainv = np.linalg.inv(A)
+    r = krylov.pcg(lambda x: A @ x, lambda r: Ainv @ r, s.b.ravel(), tol=1e-12)
+    assert r.iters == 1 and r.relres < 1e-12
+
+
+def test_fcg_matches_pcg_with_fixed_spd_preconditioner():
+    s = workloads.elasticity(2)
+    h = amg.setup(s.A, s.nlin, s.nquad, coarse_max=60)
+    prec = amg.preconditioner(h, amg.Smoother.parse("GS-1-1"))
+    mv = lambda x: s.A.matvec(x).ravel()
+    p = krylov.pcg(mv, lambda r: prec(r).ravel(), s.b.ravel(), tol=1e-10)
+    f = krylov.fcg(mv, lambda r: prec(r).ravel(), s.b.ravel(), tol=1e-10)
+    assert abs(p.iters - f.iters) <= 1
+    assert np.allclose(p.history[:6], f.history[:6], rtol=1e-6)
+
+
+def test_fgmres_minimal_residual_property():
+    """Unpreconditioned FGMRES iterate k minimises ||b - A x|| over the Krylov
+    space K_k(A, b); checked by a dense least-squares solve."""
+    rng = np.random.default_rng(5)
+    n = 40
+    A = rng.standard_normal((n, n)) + 8 * np.eye(n)
+    b = rng.standard_normal(n)
+    for k in (3, 7):
+        res = krylov.fgmres(lambda x: A @ x, lambda r: r, b, tol=0.0, maxit=k, restart=50)
+        K = np.stack([np.linalg.matrix_power(A, j) @ b for j in range(k)], axis=1)
+        Q, _ = np.linalg.qr(K)
+        y = np.linalg.lstsq(A @ Q, b, rcond=None)[0]
+        best = np.linalg.norm(b - A @ Q @ y) / np.linalg.norm(b)
+        assert abs(res.relres - best) < 1e-10
+
+
+@pytest.mark.parametrize("which", ["laplace", "elasticity"])
+def test_amg_pcg_solution_vs_superlu(which):
+    s = workloads.laplace(4) if which == "laplace" else workloads.elasticity(4)
+    h = amg.setup(s.A, s.nlin, s.nquad)
+    prec = amg.preconditioner(h, amg.Smoother.parse("GS-1-1"))
+    res = krylov.pcg(lambda x: s.A.matvec(x).ravel(), lambda r: prec(r).ravel(), s.b.ravel(), tol=1e-12)
+    ref = spla.spsolve(s.A.scipy().tocsc(), s.b.ravel())
+    assert res.converged
+    assert np.linalg.norm(res.x - ref) / np.linalg.norm(ref) < 1e-10
+
+
+def _pcg_iters(s, name, coloured=True, tol=1e-11):
+    h = amg.setup(s.A, s.nlin, s.nquad, coloured=coloured)
+    prec = amg.preconditioner(h, amg.Smoother.parse(name))
+    res = krylov.pcg(lambda x: s.A.matvec(x).ravel(), lambda r: prec(r).ravel(), s.b.ravel(), tol=tol)
+    assert res.converged
+    return res.iters
+
+
+def test_mesh_independent_iterations_paper_bc(golden):
+    """Section 4.2: AMG-PCG iteration counts do not grow with refinement.
+    Soft check against the paper's table: the same order of magnitude."""
+    paper = {r[0]: [int(v) for v in r[1:5]] for r in golden("paper_iterations.txt")}
+    its = [_pcg_iters(fem.paper_spd(n, "laplace"), "GS-1-1") for n in (4, 8, 16)]
+    assert max(its) - min(its) <= 3
+    ref = paper["lap_pcg_v_GS-1-1"][:3]
+    assert all(0.3 * p <= i <= 2 * p for i, p in zip(its, ref))
+
+
+@pytest.mark.parametrize("n", [4, 8])
+def test_coloured_vs_lexicographic_iterations(n):
+    s = workloads.elasticity(n)
+    a = _pcg_iters(s, "GS-1-1", coloured=True, tol=1e-8)
+    b = _pcg_iters(s, "GS-1-1", coloured=False, tol=1e-8)
+    assert abs(a - b) <= 1
+
+
+# ---------------------------------------------------------------- saddle
+def _saddle_hierarchy(s, coarse_max=300):
+    return amg.setup(s.A, s.nlin, s.nquad, B=s.B, C=s.C, singular=s.singular, coarse_max=coarse_max)
+
+
+def test_saddle_galerkin_blocks():
+    s = workloads.mixed_elasticity(2)
+    h = _saddle_hierarchy(s, coarse_max=60)
+    lev0, lev1 = h.levels[0], h.levels[1]
+    Pk = np.kron(lev0.P.toarray(), np.eye(3))
+    H = lev0.H.toarray()
+    assert np.abs(lev1.B.dense() - H.T @ s.B.dense() @ Pk).max() < 1e-15
+    assert np.abs(lev1.C.dense() - H.T @ s.C.dense() @ H).max() < 1e-15
+    assert lev1.npres == lev1.nlin
+
+
+def test_sgs_step_dense_formula():
+    s = workloads.mixed_elasticity(2)
+    h = _saddle_hierarchy(s, coarse_max=60)
+    lev = h.levels[0]
+    sm = amg.Smoother.parse("sGS-1-1")
+    A, B, C = lev.A.dense(), lev.B.dense(), lev.C.dense()
+    nv, npr = A.shape[0], B.shape[0]
+    D = np.zeros_like(A)
+    for i in range(lev.n):
+        D[3 * i:3 * i + 3, 3 * i:3 * i + 3] = A[3 * i:3 * i + 3, 3 * i:3 * i + 3]
+    Sd = np.diag(np.diag(B @ (sm.sgs_damping * np.linalg.inv(D)) @ B.T + C))
+    Khat = np.block([[D / sm.sgs_damping, np.zeros((nv, npr))], [B, -Sd / sm.sgs_omega]])
+    K = np.block([[A, B.T], [B, -C]])
+    rng = np.random.default_rng(6)
+    f, g = rng.standard_normal(nv), rng.standard_normal(npr)
+    u, p = rng.standard_normal(nv), rng.standard_normal(npr)
+    z = np.concatenate([u, p])
+    expect = z + np.linalg.solve(Khat, np.concatenate([f, g]) - K @ z)
+    u2, p2 = amg.sgs_step(lev, sm, f.reshape(-1, 3), g, u.reshape(-1, 3), p)
+    assert np.abs(np.concatenate([u2.ravel(), p2]) - expect).max() < 1e-12
+
+
+def test_bs_step_dense_formula():
+    s = workloads.mixed_elasticity(2)
+    h = _saddle_hierarchy(s, coarse_max=100)
+    amg.prepare_bs(h)
+    lev = h.levels[0]
+    sm = amg.Smoother.parse("BS-1-1")
+    A, B, C = lev.A.dense(), lev.B.dense(), lev.C.dense()
+    nv, npr = A.shape[0], B.shape[0]
+    Ahat = np.diag(2 * np.diag(A))
+    Shat_inv = _dense_operator(lambda e: amg.scalar_vcycle(lev.schur, 0, e, np.zeros(npr)), npr)
+    Shat = np.linalg.inv(Shat_inv)
+    Khat = np.block([[Ahat, B.T], [B, B @ np.linalg.solve(Ahat, B.T) - Shat]])
+    K = np.block([[A, B.T], [B, -C]])
+    rng = np.random.default_rng(7)
+    f, g = rng.standard_normal(nv), rng.standard_normal(npr)
+    u, p = rng.standard_normal(nv), rng.standard_normal(npr)
+    z = np.concatenate([u, p])
+    expect = z + np.linalg.solve(Khat, np.concatenate([f, g]) - K @ z)
+    u2, p2 = amg.bs_step(lev, sm, f.reshape(-1, 3), g, u.reshape(-1, 3), p)
+    got = np.concatenate([u2.ravel(), p2])
+    assert np.abs(got - expect).max() < 1e-9 * np.abs(expect).max()
+    # the Schur operator is C + B (2D)^{-1} B^T
+    S = lev.schur[0][0].S.dense()
+    assert np.abs(S - (C + B @ np.linalg.solve(Ahat, B.T))).max() < 1e-14 * np.abs(S).max()
+
+
+def _saddle_matvec(s):
+    A, B = s.A, s.B
+    Bt = B.transpose()
+    nv = 3 * A.nrows
+
+    def mv(z):
+        u, p = z[:nv].reshape(-1, 3), z[nv:]
+        top = A.matvec(u).ravel() + Bt.matvec(p.reshape(-1, 1)).ravel()
+        bot = B.matvec(u)[:, 0]
+        if s.C is not None:
+            bot = bot - s.C.matvec(p.reshape(-1, 1))[:, 0]
+        return np.concatenate([top, bot])
+    return mv
+
+
+@pytest.mark.parametrize("smoother", ["sGS-1-1", "BS-1-1"])
+def test_fgmres_mixed_elasticity_solution(smoother):
+    s = workloads.mixed_elasticity(4, nu=0.3)
+    h = _saddle_hierarchy(s)
+    if smoother.startswith("BS"):
+        amg.prepare_bs(h)
+    prec = amg.preconditioner(h, amg.Smoother.parse(smoother))
+    rhs = np.concatenate([s.f.ravel(), s.g])
+    res = krylov.fgmres(_saddle_matvec(s), prec, rhs, tol=1e-11, maxit=300)
+    assert res.converged, res.iters
+    A, B, C = s.A.scipy(), s.B.scipy(), s.C.scipy()
+    K = sp.bmat([[A, B.T], [B, -C]]).tocsc()
+    ref = spla.spsolve(K, rhs)
+    assert np.linalg.norm(res.x - ref) / np.linalg.norm(ref) < 1e-8
+
+
+def test_fgmres_stokes_cavity_bs():
+    s = workloads.stokes(4, 1.0)
+    h = _saddle_hierarchy(s)
+    amg.prepare_bs(h)
+    prec = amg.preconditioner(h, amg.Smoother.parse("BS-1-1"))
+    rhs = np.concatenate([s.f.ravel(), s.g])
+    res = krylov.fgmres(_saddle_matvec(s), prec, rhs, tol=1e-10, maxit=300)
+    assert res.converged, res.iters
+    nv = 3 * s.A.nrows
+    A, B = s.A.scipy(), s.B.scipy()
+    K = sp.bmat([[A, B.T], [B, None]]).toarray()
+    ref = np.linalg.lstsq(K, rhs, rcond=None)[0]
+    u, p = res.x[:nv], res.x[nv:] - res.x[nv:].mean()
+    assert np.linalg.norm(u - ref[:nv]) / np.linalg.norm(ref[:nv]) < 1e-8
+    pr = ref[nv:] - ref[nv:].mean()
+    assert np.linalg.norm(p - pr) / np.linalg.norm(pr) < 1e-7
