@@ -1,0 +1,254 @@
+// C ABI entry points (include/amg_p2.h). Every call catches library errors
+// and returns an AMG_* code; the message is kept per thread for
+// amg_last_error().
+#include <cstring>
+
+#include "context.h"
+
+namespace amgp2 {
+static thread_local std::string g_last_error;
+void set_last_error(const std::string &msg) { g_last_error = msg; }
+}  // namespace amgp2
+
+using namespace amgp2;
+
+amg_ctx::~amg_ctx() {
+    for (auto &pe : pending) {
+        (void)hipEventDestroy(pe.a);
+        (void)hipEventDestroy(pe.b);
+    }
+    for (hipEvent_t e : event_pool) (void)hipEventDestroy(e);
+    if (h_sc) (void)hipHostFree(h_sc);
+}
+
+template <typename F>
+static int guarded(F &&f) {
+    try {
+        return f();
+    } catch (const Error &e) {
+        set_last_error(e.what());
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        set_last_error("host allocation failed");
+        return AMG_ENOMEM;
+    } catch (const std::exception &e) {
+        set_last_error(e.what());
+        return AMG_EHIP;
+    }
+}
+
+extern "C" {
+
+void amg_default_params(amg_params *p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->smoother = AMG_SMOOTH_GS;
+    p->pre = 1;
+    p->post = 1;
+    p->omega = 0.5;
+    p->sgs_omega = 0.125;
+    p->sgs_damping = 0.5;
+    p->cycles = 1;
+    p->nu = 1;
+    p->max_levels = 10;
+    p->coarse_max = 300;
+    p->separate = 1;
+    p->krylov = AMG_KRYLOV_PCG;
+    p->restart = 100;
+    p->precision = AMG_PREC_FP64;
+    p->n_level_omega = 0;
+    p->level_omega = nullptr;
+}
+
+int amg_setup(const amg_system *sys, const amg_params *params, amg_stream stream, amg_handle *out) {
+    return guarded([&]() -> int {
+        AMG_REQUIRE(out != nullptr, AMG_EINVAL, "amg_setup: null output handle");
+        *out = nullptr;
+        AMG_REQUIRE(params != nullptr, AMG_EINVAL, "amg_setup: null params");
+        const amg_params &p = *params;
+        AMG_REQUIRE(p.smoother == AMG_SMOOTH_JA || p.smoother == AMG_SMOOTH_GS, AMG_EUNSUPPORTED,
+                    "amg_setup: smoother not available for SPD systems");
+        AMG_REQUIRE(p.pre >= 0 && p.post >= 0 && p.cycles >= 1 && p.nu >= 1 && p.nu <= 2, AMG_EINVAL,
+                    "amg_setup: invalid smoothing/cycle counts");
+        AMG_REQUIRE(p.precision == AMG_PREC_FP64, AMG_EUNSUPPORTED, "amg_setup: precision mode");
+        auto *h = new amg_ctx();
+        h->prm = p;
+        h->prm.level_omega = nullptr;
+        if (p.n_level_omega > 0 && p.level_omega)
+            h->level_omega.assign(p.level_omega, p.level_omega + p.n_level_omega);
+        h->stream = static_cast<hipStream_t>(stream);
+        try {
+            build_hierarchy(h, sys);
+        } catch (...) {
+            delete h;
+            throw;
+        }
+        *out = h;
+        return AMG_OK;
+    });
+}
+
+int amg_solve(amg_handle h, const double *b, double *x, double tol, int32_t maxit, amg_stream stream,
+              amg_result *res) {
+    return guarded([&]() -> int {
+        AMG_REQUIRE(h && b && x, AMG_EINVAL, "amg_solve: null argument");
+        AMG_REQUIRE(tol > 0.0 && maxit >= 0, AMG_EINVAL, "amg_solve: tol must be > 0, maxit >= 0");
+        h->stream = static_cast<hipStream_t>(stream);
+        switch (h->prm.krylov) {
+            case AMG_KRYLOV_PCG: return solve_pcg(h, b, x, tol, maxit, res);
+            case AMG_KRYLOV_FCG: return solve_fcg(h, b, x, tol, maxit, res);
+            case AMG_KRYLOV_NONE: return solve_stationary(h, b, x, tol, maxit, res);
+            default: throw Error(AMG_EUNSUPPORTED, "amg_solve: Krylov method not available for SPD systems");
+        }
+    });
+}
+
+int amg_precondition(amg_handle h, const double *r, double *z, amg_stream stream) {
+    return guarded([&]() -> int {
+        AMG_REQUIRE(h && r && z, AMG_EINVAL, "amg_precondition: null argument");
+        h->stream = static_cast<hipStream_t>(stream);
+        precondition(h, r, z);
+        AMG_HIP(hipStreamSynchronize(h->stream));
+        profile_collect(h);
+        return AMG_OK;
+    });
+}
+
+int amg_apply(amg_handle h, int32_t level, const double *x, double *y, amg_stream stream) {
+    return guarded([&]() -> int {
+        AMG_REQUIRE(h && x && y, AMG_EINVAL, "amg_apply: null argument");
+        AMG_REQUIRE(level >= 0 && level < static_cast<int>(h->lv.size()), AMG_EINVAL, "amg_apply: bad level");
+        h->stream = static_cast<hipStream_t>(stream);
+        apply_level(h, level, x, y);
+        AMG_HIP(hipStreamSynchronize(h->stream));
+        profile_collect(h);
+        return AMG_OK;
+    });
+}
+
+int amg_smooth(amg_handle h, int32_t level, const double *b, double *x, int32_t forward, amg_stream stream) {
+    return guarded([&]() -> int {
+        AMG_REQUIRE(h && b && x, AMG_EINVAL, "amg_smooth: null argument");
+        AMG_REQUIRE(level >= 0 && level < static_cast<int>(h->lv.size()) - 1, AMG_EINVAL,
+                    "amg_smooth: level has no smoother (coarsest or out of range)");
+        h->stream = static_cast<hipStream_t>(stream);
+        // one step: temporarily force a single pre/post step
+        amg_params save = h->prm;
+        h->prm.pre = h->prm.post = 1;
+        try {
+            smooth(h, level, b, x, forward != 0, false);
+        } catch (...) {
+            h->prm = save;
+            throw;
+        }
+        h->prm = save;
+        AMG_HIP(hipStreamSynchronize(h->stream));
+        profile_collect(h);
+        return AMG_OK;
+    });
+}
+
+int amg_num_levels(amg_handle h) { return h ? static_cast<int>(h->lv.size()) : AMG_EINVAL; }
+
+int amg_get_level_info(amg_handle h, int32_t level, amg_level_info *info) {
+    return guarded([&]() -> int {
+        AMG_REQUIRE(h && info, AMG_EINVAL, "amg_get_level_info: null argument");
+        AMG_REQUIRE(level >= 0 && level < static_cast<int>(h->lv.size()), AMG_EINVAL, "bad level");
+        const Level &L = h->lv[level];
+        std::memset(info, 0, sizeof(*info));
+        info->n_lin = L.n_lin;
+        info->n_quad = L.n_quad;
+        info->n_pres = L.n_pres;
+        info->bs = L.mode;
+        info->nnz_A = L.A.nnz;
+        info->nnz_P = L.coarsest ? 0 : L.P.nnz;
+        info->n_colors = L.cptr.empty() ? 0 : static_cast<int>(L.cptr.size()) - 1;
+        info->is_coarsest = L.coarsest ? 1 : 0;
+        return AMG_OK;
+    });
+}
+
+int amg_get_level_matrix(amg_handle h, int32_t level, int32_t which, int32_t *rowptr, int32_t *col, double *val) {
+    return guarded([&]() -> int {
+        AMG_REQUIRE(h && rowptr && col && val, AMG_EINVAL, "amg_get_level_matrix: null argument");
+        AMG_REQUIRE(level >= 0 && level < static_cast<int>(h->lv.size()), AMG_EINVAL, "bad level");
+        const Level &L = h->lv[level];
+        const DMat *m = nullptr;
+        if (which == 0) m = &L.A;
+        if (which == 3) {
+            AMG_REQUIRE(!L.coarsest, AMG_EINVAL, "coarsest level has no prolongation");
+            m = &L.P;
+        }
+        AMG_REQUIRE(m != nullptr, AMG_EUNSUPPORTED, "amg_get_level_matrix: operator not present");
+        std::vector<int> rp = m->rowptr.download(h->stream), c = m->col.download(h->stream);
+        std::vector<double> v = m->val.download(h->stream);
+        std::memcpy(rowptr, rp.data(), rp.size() * sizeof(int));
+        std::memcpy(col, c.data(), static_cast<size_t>(m->nnz) * sizeof(int));
+        for (int64_t k = 0; k < m->nnz; ++k)
+            for (int p = 0; p < m->np; ++p) val[k * m->np + p] = v[static_cast<size_t>(p) * m->nnz + k];
+        return AMG_OK;
+    });
+}
+
+int amg_get_level_colors(amg_handle h, int32_t level, int32_t *colors) {
+    return guarded([&]() -> int {
+        AMG_REQUIRE(h && colors, AMG_EINVAL, "amg_get_level_colors: null argument");
+        AMG_REQUIRE(level >= 0 && level < static_cast<int>(h->lv.size()), AMG_EINVAL, "bad level");
+        const Level &L = h->lv[level];
+        AMG_REQUIRE(!L.colour.empty(), AMG_EUNSUPPORTED, "no colouring on this level");
+        std::memcpy(colors, L.colour.data(), L.colour.size() * sizeof(int));
+        return AMG_OK;
+    });
+}
+
+int amg_profile_enable(amg_handle h, int32_t enable) {
+    return guarded([&]() -> int {
+        AMG_REQUIRE(h, AMG_EINVAL, "amg_profile_enable: null handle");
+        profile_collect(h);
+        h->prof = enable != 0;
+        if (h->prof) h->stats.clear();
+        return AMG_OK;
+    });
+}
+
+int amg_profile_read(amg_handle h, const char *cls, int64_t *launches, double *total_ms, double *bytes) {
+    return guarded([&]() -> int {
+        AMG_REQUIRE(h && cls && launches && total_ms && bytes, AMG_EINVAL, "amg_profile_read: null argument");
+        profile_collect(h);
+        auto it = h->stats.find(cls);
+        if (it == h->stats.end()) {
+            *launches = 0;
+            *total_ms = 0.0;
+            *bytes = 0.0;
+        } else {
+            *launches = it->second.launches;
+            *total_ms = it->second.ms;
+            *bytes = it->second.bytes;
+        }
+        return AMG_OK;
+    });
+}
+
+void amg_destroy(amg_handle h) {
+    if (!h) return;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    delete h;
+}
+
+const char *amg_status_string(int status) {
+    switch (status) {
+        case AMG_OK: return "converged";
+        case AMG_NOT_CONVERGED: return "not converged within maxit";
+        case AMG_BREAKDOWN: return "Krylov breakdown";
+        case AMG_DIVERGED: return "diverged (NaN/Inf or residual growth)";
+        case AMG_EINVAL: return "invalid argument";
+        case AMG_EHIP: return "HIP runtime error";
+        case AMG_ENOMEM: return "out of memory";
+        case AMG_EUNSUPPORTED: return "unsupported input or option";
+        default: return "unknown status";
+    }
+}
+
+const char *amg_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,100 @@
+// The hierarchy held by an amg_handle and the routines that build and run it.
+#pragma once
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "host_setup.h"
+#include "kernels.h"
+
+namespace amgp2 {
+
+// Block-CSR operator on the device, values stored as planes (see kernels.h).
+struct DMat {
+    int nrows = 0, ncols = 0;
+    int64_t nnz = 0;
+    int np = 1;  // planes per entry: 9 (3x3), 3 (1x3 / 3x1), 1 (scalar)
+    DevBuf<int> rowptr, col;
+    DevBuf<double> val;
+};
+
+struct Level {
+    int n_lin = 0, n_quad = 0, n = 0, n_pres = 0;
+    int mode = 3;             // 3: 3x3 blocks; 1: scalar operator applied per component
+    bool coarsest = false;
+    DMat A;                   // natural node order
+    HostCSR hpat;             // structural pattern of A (host)
+    // smoother data
+    DevBuf<double> dinv;      // inverted diagonal blocks, planes of stride n
+    std::vector<int> colour;  // per node
+    std::vector<int> cptr;    // grouped rows of colour c: [cptr[c], cptr[c+1])
+    std::vector<int64_t> colour_nnz;  // stored entries in the rows of colour c
+    DMat Ag;                  // rows of A grouped by colour
+    DevBuf<int> g_rowid;      // node of grouped row g
+    // transfer between this level and the next coarser one
+    DMat P, R;                // P: n x n_c scalar, R = P^T
+    HostCSR hP;
+    // work vectors (3n doubles each)
+    DevBuf<double> x, b, r, t;
+    int G = 16, Gg = 16, Gp = 4, Gr = 8;  // lanes per row: A, grouped A, P, R
+};
+
+struct ProfStat {
+    int64_t launches = 0;
+    double ms = 0.0, bytes = 0.0;
+};
+
+struct amg_ctx_impl;
+
+}  // namespace amgp2
+
+struct amg_ctx {
+    amg_params prm{};
+    std::vector<double> level_omega;
+    hipStream_t stream = nullptr;
+    std::vector<amgp2::Level> lv;
+    // coarsest level: explicit dense inverse
+    amgp2::DevBuf<double> coarse_inv;
+    int coarse_m = 0, coarse_nc = 1;
+    // Krylov workspace
+    amgp2::DevBuf<double> kr, kz, kp, kq, kw;
+    amgp2::DevBuf<double> partial, sc;
+    double *h_sc = nullptr;  // pinned host copy of the scalars
+    int n_dof = 0;           // length of a solve vector
+    // profiling
+    bool prof = false;
+    struct Pending {
+        std::string cls;
+        hipEvent_t a, b;
+        double bytes;
+    };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> event_pool;
+    std::map<std::string, amgp2::ProfStat> stats;
+    ~amg_ctx();
+};
+
+namespace amgp2 {
+
+void build_hierarchy(amg_ctx *h, const amg_system *sys);
+void vcycle(amg_ctx *h, int l, const double *b, double *x);
+void precondition(amg_ctx *h, const double *r, double *z);
+void apply_level(amg_ctx *h, int l, const double *x, double *y);
+void smooth(amg_ctx *h, int l, const double *b, double *x, bool pre, bool zero_init);
+int solve_pcg(amg_ctx *h, const double *b, double *x, double tol, int maxit, amg_result *res);
+int solve_fcg(amg_ctx *h, const double *b, double *x, double tol, int maxit, amg_result *res);
+int solve_stationary(amg_ctx *h, const double *b, double *x, double tol, int maxit, amg_result *res);
+double true_relres(amg_ctx *h, const double *b, const double *x, double r0norm);
+
+// profiling helpers (no-ops unless enabled)
+struct ProfScope {
+    amg_ctx *h;
+    size_t idx;
+    ProfScope(amg_ctx *h, const std::string &cls, double bytes);
+    ~ProfScope();
+};
+void profile_collect(amg_ctx *h);
+
+}  // namespace amgp2

@@ -1,0 +1,268 @@
+// amg_setup: the level hierarchy of Section 3.2.
+//   host : separated graphs (K_ll and K_qq patterns), greedy independent sets,
+//          averaging interpolation, colouring, the coarsest dense inverse;
+//   GPU  : Galerkin products P^T A P (k_spgemm.hip), diagonal-block inverses,
+//          colour-grouped copies of the operators.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "context.h"
+
+namespace amgp2 {
+
+static void upload_pattern(DMat &m, const HostCSR &h, hipStream_t s) {
+    m.nrows = h.nrows;
+    m.ncols = h.ncols;
+    m.nnz = h.nnz();
+    m.rowptr.upload(h.rowptr, s);
+    m.col.upload(h.col, s);
+}
+
+// Scalar host matrix -> device (1 plane).
+static void upload_scalar(DMat &m, const HostCSR &h, hipStream_t s) {
+    upload_pattern(m, h, s);
+    m.np = 1;
+    m.val.upload(h.val, s);
+}
+
+// Row-major blocks (np values per entry) -> planes.
+static void upload_blocks(DMat &m, int nrows, int ncols, const int32_t *rowptr, const int32_t *col,
+                          const double *val, int np, hipStream_t s) {
+    m.nrows = nrows;
+    m.ncols = ncols;
+    m.nnz = rowptr[nrows];
+    m.np = np;
+    m.rowptr.upload(rowptr, nrows + 1, s);
+    m.col.upload(col, static_cast<size_t>(m.nnz), s);
+    std::vector<double> planes(static_cast<size_t>(np) * m.nnz);
+    for (int64_t k = 0; k < m.nnz; ++k)
+        for (int p = 0; p < np; ++p) planes[static_cast<size_t>(p) * m.nnz + k] = val[k * np + p];
+    m.val.upload(planes, s);
+    AMG_HIP(hipStreamSynchronize(s));  // `planes` goes out of scope
+}
+
+static HostCSR download_pattern(const DMat &m, hipStream_t s) {
+    HostCSR h;
+    h.nrows = m.nrows;
+    h.ncols = m.ncols;
+    h.rowptr = m.rowptr.download(s);
+    h.col = m.col.download(s);
+    return h;
+}
+
+// C = X Y, one of X / Y scalar (np = 1), the other with np planes.
+// search_y: Y's rows are long (binary search in them); otherwise Y is a
+// prolongation with a few entries per row (linear scan).
+static DMat spgemm(const DMat &X, const DMat &Y, bool search_y, hipStream_t s) {
+    AMG_REQUIRE(X.ncols == Y.nrows, AMG_EINVAL, "spgemm: shape mismatch");
+    AMG_REQUIRE(X.np == 1 || Y.np == 1, AMG_EINVAL, "spgemm: one factor must be scalar");
+    DMat C;
+    C.nrows = X.nrows;
+    C.ncols = Y.ncols;
+    C.np = std::max(X.np, Y.np);
+    DevBuf<int> cnt(std::max(1, C.nrows)), flag(1);
+    flag.zero(s);
+    launch_spgemm_count(C.nrows, X.rowptr.p, X.col.p, Y.rowptr.p, Y.col.p, cnt.p, flag.p, s);
+    std::vector<int> hc = cnt.download(s);
+    std::vector<int> hf = flag.download(s);
+    AMG_REQUIRE(hf[0] == 0, AMG_EUNSUPPORTED,
+                "Galerkin product: a coarse row has more distinct columns than the LDS hash holds");
+    std::vector<int> rp(C.nrows + 1, 0);
+    for (int i = 0; i < C.nrows; ++i) rp[i + 1] = rp[i] + hc[i];
+    C.nnz = rp[C.nrows];
+    C.rowptr.upload(rp, s);
+    C.col.alloc(std::max<int64_t>(1, C.nnz));
+    launch_spgemm_fill(C.nrows, X.rowptr.p, X.col.p, Y.rowptr.p, Y.col.p, C.rowptr.p, C.col.p, s);
+    C.val.alloc(std::max<int64_t>(1, C.nnz * C.np));
+    AMG_REQUIRE(search_y ? X.np == 1 : Y.np == 1, AMG_EINVAL, "spgemm: factor layout");
+    if (!search_y)
+        launch_spgemm_numeric_bx(X.np, C.nrows, X.rowptr.p, X.col.p, X.val.p, X.nnz, Y.rowptr.p, Y.col.p,
+                                 Y.val.p, C.rowptr.p, C.col.p, C.val.p, C.nnz, s);
+    else
+        launch_spgemm_numeric_by(Y.np, C.nrows, X.rowptr.p, X.col.p, X.val.p, Y.rowptr.p, Y.col.p,
+                                 Y.val.p, Y.nnz, C.rowptr.p, C.col.p, C.val.p, C.nnz, s);
+    AMG_HIP(hipStreamSynchronize(s));
+    return C;
+}
+
+// Lanes per row for a row kernel: the smallest power of two (4..64) not
+// below the mean entries per row.
+static int lanes_for(int64_t nnz, int nrows) {
+    const double avg = nrows > 0 ? static_cast<double>(nnz) / nrows : 1.0;
+    int G = 4;
+    while (G < 64 && G < avg) G *= 2;
+    return G;
+}
+
+static void check_system(const amg_system *sys) {
+    AMG_REQUIRE(sys != nullptr, AMG_EINVAL, "amg_setup: null system");
+    AMG_REQUIRE(sys->n_lin >= 0 && sys->n_quad >= 0 && sys->n_lin + sys->n_quad > 0, AMG_EINVAL,
+                "amg_setup: node counts must be positive");
+    AMG_REQUIRE(sys->bs == 1 || sys->bs == 3, AMG_EINVAL, "amg_setup: bs must be 1 or 3");
+    AMG_REQUIRE(sys->A_rowptr && sys->A_col && sys->A_val, AMG_EINVAL, "amg_setup: A is missing");
+    AMG_REQUIRE(sys->n_pres == 0, AMG_EUNSUPPORTED, "amg_setup: saddle systems need the saddle build");
+    const int n = sys->n_lin + sys->n_quad;
+    AMG_REQUIRE(sys->A_rowptr[0] == 0, AMG_EINVAL, "amg_setup: A_rowptr[0] != 0");
+    for (int i = 0; i < n; ++i) {
+        const int b = sys->A_rowptr[i], e = sys->A_rowptr[i + 1];
+        AMG_REQUIRE(e >= b, AMG_EINVAL, "amg_setup: A_rowptr not monotone");
+        bool diag = false;
+        for (int k = b; k < e; ++k) {
+            const int j = sys->A_col[k];
+            AMG_REQUIRE(j >= 0 && j < n, AMG_EINVAL, "amg_setup: column index out of range");
+            AMG_REQUIRE(k == b || sys->A_col[k - 1] < j, AMG_EINVAL, "amg_setup: columns not sorted/unique");
+            diag |= j == i;
+        }
+        AMG_REQUIRE(diag, AMG_EINVAL, "amg_setup: missing diagonal entry in row " + std::to_string(i));
+    }
+}
+
+static void setup_smoother(amg_ctx *h, Level &L) {
+    hipStream_t s = h->stream;
+    const int nb = L.mode == 3 ? 9 : 1;
+    L.dinv.alloc(static_cast<size_t>(nb) * L.n);
+    DevBuf<int> flag(1);
+    flag.zero(s);
+    launch_diag_inverse(L.mode, L.n, L.A.rowptr.p, L.A.col.p, L.A.val.p, L.A.nnz, L.dinv.p, flag.p, s);
+    std::vector<int> hf = flag.download(s);
+    AMG_REQUIRE(hf[0] == 0, AMG_EINVAL, "amg_setup: singular or missing diagonal block");
+    L.G = lanes_for(L.A.nnz, L.n);
+    if (h->prm.smoother != AMG_SMOOTH_GS) return;
+    // colour-grouped copy of A for the Gauss-Seidel sweeps
+    const int ncol = greedy_colouring(L.hpat, L.colour);
+    std::vector<int> order(L.n);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return L.colour[a] < L.colour[b]; });
+    L.cptr.assign(ncol + 1, 0);
+    for (int i = 0; i < L.n; ++i) ++L.cptr[L.colour[i] + 1];
+    std::partial_sum(L.cptr.begin(), L.cptr.end(), L.cptr.begin());
+    std::vector<int> grp(L.n + 1, 0);
+    L.colour_nnz.assign(ncol, 0);
+    for (int g = 0; g < L.n; ++g) {
+        const int len = L.hpat.rowptr[order[g] + 1] - L.hpat.rowptr[order[g]];
+        grp[g + 1] = grp[g] + len;
+        L.colour_nnz[L.colour[order[g]]] += len;
+    }
+    L.Ag.nrows = L.n;
+    L.Ag.ncols = L.n;
+    L.Ag.nnz = L.A.nnz;
+    L.Ag.np = L.A.np;
+    L.Ag.rowptr.upload(grp, s);
+    L.Ag.col.alloc(static_cast<size_t>(L.A.nnz));
+    L.Ag.val.alloc(static_cast<size_t>(L.A.nnz) * L.A.np);
+    L.g_rowid.upload(order, s);
+    launch_gather_rows(L.A.np, L.n, L.g_rowid.p, L.A.rowptr.p, L.A.col.p, L.A.val.p, L.A.nnz, L.Ag.rowptr.p,
+                       L.Ag.col.p, L.Ag.val.p, s);
+    AMG_HIP(hipStreamSynchronize(s));
+    // rows of one colour form one launch: size the groups for their mean length
+    L.Gg = L.G;
+}
+
+static void setup_coarsest(amg_ctx *h, Level &L) {
+    hipStream_t s = h->stream;
+    const int np = L.A.np;
+    std::vector<int> rp = L.A.rowptr.download(s), cl = L.A.col.download(s);
+    std::vector<double> v = L.A.val.download(s);
+    if (L.mode == 3) {
+        const int m = 3 * L.n;
+        std::vector<double> M(static_cast<size_t>(m) * m, 0.0);
+        for (int i = 0; i < L.n; ++i)
+            for (int k = rp[i]; k < rp[i + 1]; ++k)
+                for (int r = 0; r < 3; ++r)
+                    for (int c = 0; c < 3; ++c)
+                        M[static_cast<size_t>(3 * i + r) * m + 3 * cl[k] + c] = v[static_cast<size_t>(r * 3 + c) * L.A.nnz + k];
+        AMG_REQUIRE(dense_inverse(M, m), AMG_EINVAL, "amg_setup: singular coarsest matrix");
+        h->coarse_m = m;
+        h->coarse_nc = 1;
+        h->coarse_inv.upload(M, s);
+    } else {
+        const int m = L.n;
+        std::vector<double> M(static_cast<size_t>(m) * m, 0.0);
+        for (int i = 0; i < L.n; ++i)
+            for (int k = rp[i]; k < rp[i + 1]; ++k) M[static_cast<size_t>(i) * m + cl[k]] = v[k];
+        AMG_REQUIRE(dense_inverse(M, m), AMG_EINVAL, "amg_setup: singular coarsest matrix");
+        h->coarse_m = m;
+        h->coarse_nc = 3;
+        h->coarse_inv.upload(M, s);
+    }
+    (void)np;
+    AMG_HIP(hipStreamSynchronize(s));
+}
+
+void build_hierarchy(amg_ctx *h, const amg_system *sys) {
+    check_system(sys);
+    hipStream_t s = h->stream;
+    const amg_params &p = h->prm;
+    h->lv.clear();
+    h->lv.emplace_back();
+    {
+        Level &L0 = h->lv.back();
+        L0.n_lin = sys->n_lin;
+        L0.n_quad = sys->n_quad;
+        L0.n = sys->n_lin + sys->n_quad;
+        L0.mode = sys->bs;
+        upload_blocks(L0.A, L0.n, L0.n, sys->A_rowptr, sys->A_col, sys->A_val, sys->bs * sys->bs, s);
+        L0.hpat.nrows = L0.hpat.ncols = L0.n;
+        L0.hpat.rowptr.assign(sys->A_rowptr, sys->A_rowptr + L0.n + 1);
+        L0.hpat.col.assign(sys->A_col, sys->A_col + L0.A.nnz);
+    }
+    const int max_levels = std::max(1, p.max_levels);
+    while (true) {
+        Level &L = h->lv.back();
+        if (3 * L.n <= p.coarse_max || static_cast<int>(h->lv.size()) >= max_levels) break;
+        HostCSR P;
+        int ncl = 0, ncq = 0;
+        if (p.separate) {
+            HostCSR gl = subgraph(L.hpat, 0, L.n_lin), gq = subgraph(L.hpat, L.n_lin, L.n);
+            HostCSR pl = averaging_interpolation(gl, greedy_independent_set(gl));
+            HostCSR pq = averaging_interpolation(gq, greedy_independent_set(gq));
+            ncl = pl.ncols;
+            ncq = pq.ncols;
+            P = block_diagonal(pl, pq);
+        } else {
+            HostCSR g = subgraph(L.hpat, 0, L.n);
+            P = averaging_interpolation(g, greedy_independent_set(g));
+            ncl = P.ncols;
+        }
+        if (P.ncols > 0.9 * L.n || P.ncols == 0) break;
+        upload_scalar(L.P, P, s);
+        HostCSR R = transpose(P);
+        upload_scalar(L.R, R, s);
+        L.hP = std::move(P);
+        L.Gp = lanes_for(L.P.nnz, L.P.nrows);
+        L.Gr = lanes_for(L.R.nnz, L.R.nrows);
+        DMat AP = spgemm(L.A, L.P, false, s);
+        DMat Ac = spgemm(L.R, AP, true, s);
+        Level next;
+        next.n_lin = ncl;
+        next.n_quad = ncq;
+        next.n = ncl + ncq;
+        next.mode = L.mode;
+        next.A = std::move(Ac);
+        next.hpat = download_pattern(next.A, s);
+        h->lv.push_back(std::move(next));
+    }
+    h->lv.back().coarsest = true;
+    for (Level &L : h->lv) {
+        L.x.alloc(3 * static_cast<size_t>(L.n));
+        L.b.alloc(3 * static_cast<size_t>(L.n));
+        L.r.alloc(3 * static_cast<size_t>(L.n));
+        L.t.alloc(3 * static_cast<size_t>(L.n));
+        if (!L.coarsest) setup_smoother(h, L);
+    }
+    setup_coarsest(h, h->lv.back());
+    h->n_dof = 3 * h->lv[0].n;
+    const size_t nd = static_cast<size_t>(h->n_dof);
+    h->kr.alloc(nd);
+    h->kz.alloc(nd);
+    h->kp.alloc(nd);
+    h->kq.alloc(nd);
+    h->kw.alloc(nd);
+    h->partial.alloc(static_cast<size_t>(std::max(1024, row_blocks(h->lv[0].n, 64))));
+    h->sc.alloc(SC_COUNT);
+    if (!h->h_sc) AMG_HIP(hipHostMalloc(reinterpret_cast<void **>(&h->h_sc), SC_COUNT * sizeof(double)));
+    AMG_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace amgp2

@@ -1,0 +1,400 @@
+// Row kernels (SpMV, residual, damped block Jacobi, coloured block
+// Gauss-Seidel, restriction, prolongation), Krylov vector kernels, the
+// coarsest-level dense solve and smoother setup kernels. gfx950, wave64.
+//
+// All of these are bound by HBM bandwidth: a 3x3 FP64 block costs 76 bytes
+// (72 value bytes + a 4-byte column index) for 18 flops. The row kernels give
+// each matrix row a group of G lanes; lane t of the group walks the row's
+// entries t, t+G, ..., so each plane load of the group is one contiguous
+// segment, and the 3 partial sums are reduced across the group with
+// cross-lane shuffles.
+#include "common.h"
+#include "kernels.h"
+
+namespace amgp2 {
+
+constexpr int BLOCK = 256;
+
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
+    return v;
+}
+
+// Sum over the 256 threads of a block (deterministic order); result in thread 0.
+__device__ __forceinline__ double block_sum(double v) {
+    __shared__ double red[BLOCK / 64];
+    v = group_sum<64>(v);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < BLOCK / 64; ++i) t += red[i];
+    }
+    return t;
+}
+
+template <int MODE, int G, int OP>
+__global__ void __launch_bounds__(BLOCK) k_row(const RowArgs a) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * BLOCK + threadIdx.x;
+    const int g = static_cast<int>(t / G);
+    const int lane = static_cast<int>(t % G);
+    const bool active = g < a.nrows;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    if (active) {
+        const int beg = a.rowptr[g], end = a.rowptr[g + 1];
+        const int64_t nz = a.nnz;
+        for (int k = beg + lane; k < end; k += G) {
+            const int j = a.col[k];
+            const double x0 = a.x[3 * j], x1 = a.x[3 * j + 1], x2 = a.x[3 * j + 2];
+            if constexpr (MODE == 3) {
+                const double *v = a.val + k;
+                s0 += v[0] * x0 + v[nz] * x1 + v[2 * nz] * x2;
+                s1 += v[3 * nz] * x0 + v[4 * nz] * x1 + v[5 * nz] * x2;
+                s2 += v[6 * nz] * x0 + v[7 * nz] * x1 + v[8 * nz] * x2;
+            } else {
+                const double v = a.val[k];
+                s0 += v * x0;
+                s1 += v * x1;
+                s2 += v * x2;
+            }
+        }
+    }
+    s0 = group_sum<G>(s0);
+    s1 = group_sum<G>(s1);
+    s2 = group_sum<G>(s2);
+
+    const int i = active ? (a.rowid ? a.rowid[g] : g) : 0;
+    if constexpr (OP == OP_SPMV_DOT) {
+        double c = 0.0;
+        if (active && lane < 3) {
+            const double sv = lane == 0 ? s0 : (lane == 1 ? s1 : s2);
+            a.y[3 * i + lane] = sv;
+            c = a.x[3 * i + lane] * sv;
+        }
+        const double tot = block_sum(c);
+        if (threadIdx.x == 0) a.partial[blockIdx.x] = tot;
+        return;
+    }
+    if (!active || lane >= 3) return;
+    const int c = lane;
+    const double sc = c == 0 ? s0 : (c == 1 ? s1 : s2);
+    if constexpr (OP == OP_SPMV) {
+        a.y[3 * i + c] = sc;
+    } else if constexpr (OP == OP_SPMV_ADD) {
+        a.y[3 * i + c] += sc;
+    } else if constexpr (OP == OP_RESID) {
+        a.y[3 * i + c] = a.b[3 * i + c] - sc;
+    } else {
+        const double r0 = a.b[3 * i] - s0, r1 = a.b[3 * i + 1] - s1, r2 = a.b[3 * i + 2] - s2;
+        double d;
+        if constexpr (MODE == 3) {
+            const double *D = a.dinv + i;
+            const int64_t dn = a.dinv_n;
+            d = D[(3 * c) * dn] * r0 + D[(3 * c + 1) * dn] * r1 + D[(3 * c + 2) * dn] * r2;
+        } else {
+            d = a.dinv[i] * (c == 0 ? r0 : (c == 1 ? r1 : r2));
+        }
+        if constexpr (OP == OP_JACOBI) {
+            a.y[3 * i + c] = a.x[3 * i + c] + a.omega * d;
+        } else {  // OP_GS: in place (a.y aliases a.x)
+            a.y[3 * i + c] += d;
+        }
+    }
+}
+
+int row_blocks(int nrows, int G) { return ceil_div(static_cast<int64_t>(nrows) * G, BLOCK); }
+
+template <int MODE, int G>
+static void launch_row_g(RowOp op, const RowArgs &a, hipStream_t s) {
+    const int nb = row_blocks(a.nrows, G);
+    if (nb == 0) return;
+    switch (op) {
+        case OP_SPMV: k_row<MODE, G, OP_SPMV><<<nb, BLOCK, 0, s>>>(a); break;
+        case OP_SPMV_ADD: k_row<MODE, G, OP_SPMV_ADD><<<nb, BLOCK, 0, s>>>(a); break;
+        case OP_RESID: k_row<MODE, G, OP_RESID><<<nb, BLOCK, 0, s>>>(a); break;
+        case OP_JACOBI: k_row<MODE, G, OP_JACOBI><<<nb, BLOCK, 0, s>>>(a); break;
+        case OP_GS: k_row<MODE, G, OP_GS><<<nb, BLOCK, 0, s>>>(a); break;
+        case OP_SPMV_DOT: k_row<MODE, G, OP_SPMV_DOT><<<nb, BLOCK, 0, s>>>(a); break;
+    }
+    AMG_CHECK_LAUNCH();
+}
+
+template <int MODE>
+static void launch_row_m(RowOp op, int G, const RowArgs &a, hipStream_t s) {
+    switch (G) {
+        case 4: launch_row_g<MODE, 4>(op, a, s); break;
+        case 8: launch_row_g<MODE, 8>(op, a, s); break;
+        case 16: launch_row_g<MODE, 16>(op, a, s); break;
+        case 32: launch_row_g<MODE, 32>(op, a, s); break;
+        case 64: launch_row_g<MODE, 64>(op, a, s); break;
+        default: throw Error(AMG_EINVAL, "row kernel: unsupported group size");
+    }
+}
+
+void launch_row(int mode, RowOp op, int G, const RowArgs &a, hipStream_t s) {
+    if (mode == 3)
+        launch_row_m<3>(op, G, a, s);
+    else
+        launch_row_m<1>(op, G, a, s);
+}
+
+// ---------------------------------------------------------------- vectors
+__global__ void k_fill(double *x, double v, int64_t n) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * BLOCK + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * BLOCK)
+        x[i] = v;
+}
+
+static int grid_for(int64_t n) {
+    int64_t nb = (n + BLOCK - 1) / BLOCK;
+    if (nb > 4096) nb = 4096;
+    return static_cast<int>(nb < 1 ? 1 : nb);
+}
+
+void launch_fill(double *x, double v, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    k_fill<<<grid_for(n), BLOCK, 0, s>>>(x, v, n);
+    AMG_CHECK_LAUNCH();
+}
+
+__global__ void k_copy(double *d, const double *src, int64_t n) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * BLOCK + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * BLOCK)
+        d[i] = src[i];
+}
+
+void launch_copy(double *dst, const double *src, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    k_copy<<<grid_for(n), BLOCK, 0, s>>>(dst, src, n);
+    AMG_CHECK_LAUNCH();
+}
+
+template <int MODE>
+__global__ void k_jacobi_zero(int64_t nn, const double *dinv, const double *b, double omega, double *x) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * BLOCK + threadIdx.x;
+    if (t >= 3 * nn) return;
+    const int64_t i = t / 3;
+    const int c = static_cast<int>(t % 3);
+    double d;
+    if constexpr (MODE == 3) {
+        d = dinv[(3 * c) * nn + i] * b[3 * i] + dinv[(3 * c + 1) * nn + i] * b[3 * i + 1] +
+            dinv[(3 * c + 2) * nn + i] * b[3 * i + 2];
+    } else {
+        d = dinv[i] * b[t];
+    }
+    x[t] = omega * d;
+}
+
+void launch_jacobi_zero(int mode, int64_t nn, const double *dinv, const double *b, double omega,
+                        double *x, hipStream_t s) {
+    if (nn <= 0) return;
+    const int nb = ceil_div(3 * nn, BLOCK);
+    if (mode == 3)
+        k_jacobi_zero<3><<<nb, BLOCK, 0, s>>>(nn, dinv, b, omega, x);
+    else
+        k_jacobi_zero<1><<<nb, BLOCK, 0, s>>>(nn, dinv, b, omega, x);
+    AMG_CHECK_LAUNCH();
+}
+
+int dot_blocks(int64_t n) { return grid_for(n) > 1024 ? 1024 : grid_for(n); }
+
+__global__ void k_dot_partial(const double *a, const double *b, int64_t n, double *partial) {
+    double acc = 0.0;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * BLOCK + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * BLOCK)
+        acc += a[i] * b[i];
+    const double t = block_sum(acc);
+    if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+int launch_dot_partial(const double *a, const double *b, int64_t n, double *partial, hipStream_t s) {
+    const int nb = dot_blocks(n);
+    k_dot_partial<<<nb, BLOCK, 0, s>>>(a, b, n, partial);
+    AMG_CHECK_LAUNCH();
+    return nb;
+}
+
+__global__ void k_reduce(const double *partial, int np, double *sc, int dst) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < np; i += BLOCK) acc += partial[i];
+    const double t = block_sum(acc);
+    if (threadIdx.x == 0) sc[dst] = t;
+}
+
+void launch_reduce(const double *partial, int np, double *sc, int dst, hipStream_t s) {
+    k_reduce<<<1, BLOCK, 0, s>>>(partial, np, sc, dst);
+    AMG_CHECK_LAUNCH();
+}
+
+__global__ void k_cg_alpha(double *sc) { sc[SC_ALPHA] = sc[SC_RZ] / sc[SC_PQ]; }
+__global__ void k_cg_beta(double *sc) {
+    sc[SC_BETA] = sc[SC_TMP] / sc[SC_RZ];
+    sc[SC_RZ] = sc[SC_TMP];
+}
+__global__ void k_fcg_beta(double *sc) { sc[SC_BETA] = -sc[SC_TMP] / sc[SC_RZ_OLD]; }
+__global__ void k_fcg_alpha(double *sc) {
+    sc[SC_ALPHA] = sc[SC_PR] / sc[SC_PQ];
+    sc[SC_RZ_OLD] = sc[SC_PQ];
+}
+
+void launch_cg_alpha(double *sc, hipStream_t s) { k_cg_alpha<<<1, 1, 0, s>>>(sc); AMG_CHECK_LAUNCH(); }
+void launch_cg_beta(double *sc, hipStream_t s) { k_cg_beta<<<1, 1, 0, s>>>(sc); AMG_CHECK_LAUNCH(); }
+void launch_fcg_beta(double *sc, hipStream_t s) { k_fcg_beta<<<1, 1, 0, s>>>(sc); AMG_CHECK_LAUNCH(); }
+void launch_fcg_alpha(double *sc, hipStream_t s) { k_fcg_alpha<<<1, 1, 0, s>>>(sc); AMG_CHECK_LAUNCH(); }
+
+__global__ void k_cg_update(double *x, double *r, const double *p, const double *q, const double *sc,
+                            int64_t n, double *partial) {
+    const double al = sc[SC_ALPHA];
+    double acc = 0.0;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * BLOCK + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * BLOCK) {
+        x[i] += al * p[i];
+        const double ri = r[i] - al * q[i];
+        r[i] = ri;
+        acc += ri * ri;
+    }
+    const double t = block_sum(acc);
+    if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+int launch_cg_update(double *x, double *r, const double *p, const double *q, const double *sc,
+                     int64_t n, double *partial, hipStream_t s) {
+    const int nb = dot_blocks(n);
+    k_cg_update<<<nb, BLOCK, 0, s>>>(x, r, p, q, sc, n, partial);
+    AMG_CHECK_LAUNCH();
+    return nb;
+}
+
+__global__ void k_cg_direction(double *p, const double *z, const double *sc, int64_t n) {
+    const double be = sc[SC_BETA];
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * BLOCK + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * BLOCK)
+        p[i] = z[i] + be * p[i];
+}
+
+void launch_cg_direction(double *p, const double *z, const double *sc, int64_t n, hipStream_t s) {
+    k_cg_direction<<<grid_for(n), BLOCK, 0, s>>>(p, z, sc, n);
+    AMG_CHECK_LAUNCH();
+}
+
+__global__ void k_axpby(double *y, const double *x, double a, double b, int64_t n) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * BLOCK + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * BLOCK)
+        y[i] = a * x[i] + b * y[i];
+}
+
+void launch_axpby(double *y, const double *x, double a, double b, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    k_axpby<<<grid_for(n), BLOCK, 0, s>>>(y, x, a, b, n);
+    AMG_CHECK_LAUNCH();
+}
+
+// ---------------------------------------------------------------- dense
+// One wavefront per output row; lanes stride over the columns.
+__global__ void __launch_bounds__(BLOCK) k_dense_gemv(const double *M, int m, int nc, const double *X,
+                                                      double *Y) {
+    const int row = blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= m) return;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    const double *Mr = M + static_cast<int64_t>(row) * m;
+    for (int j = lane; j < m; j += 64) {
+        const double v = Mr[j];
+        a0 += v * X[j * nc];
+        if (nc > 1) {
+            a1 += v * X[j * nc + 1];
+            a2 += v * X[j * nc + 2];
+        }
+    }
+    a0 = group_sum<64>(a0);
+    a1 = group_sum<64>(a1);
+    a2 = group_sum<64>(a2);
+    if (lane < nc) Y[row * nc + lane] = lane == 0 ? a0 : (lane == 1 ? a1 : a2);
+}
+
+void launch_dense_gemv(const double *M, int m, int nc, const double *X, double *Y, hipStream_t s) {
+    if (m <= 0) return;
+    k_dense_gemv<<<ceil_div(m, BLOCK / 64), BLOCK, 0, s>>>(M, m, nc, X, Y);
+    AMG_CHECK_LAUNCH();
+}
+
+// ---------------------------------------------------------------- setup
+template <int MODE>
+__global__ void k_diag_inverse(int n, const int *rowptr, const int *col, const double *val, int64_t nnz,
+                               double *dinv, int *flag) {
+    const int i = blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= n) return;
+    int k = -1;
+    for (int q = rowptr[i]; q < rowptr[i + 1]; ++q)
+        if (col[q] == i) { k = q; break; }
+    if (k < 0) { atomicOr(flag, 1); return; }
+    if constexpr (MODE == 1) {
+        const double d = val[k];
+        if (d == 0.0) atomicOr(flag, 2);
+        dinv[i] = 1.0 / d;
+    } else {
+        double a[9];
+#pragma unroll
+        for (int p = 0; p < 9; ++p) a[p] = val[p * nnz + k];
+        // inverse by the adjugate: inv = adj(a) / det(a)
+        const double c00 = a[4] * a[8] - a[5] * a[7];
+        const double c01 = a[5] * a[6] - a[3] * a[8];
+        const double c02 = a[3] * a[7] - a[4] * a[6];
+        const double det = a[0] * c00 + a[1] * c01 + a[2] * c02;
+        if (det == 0.0) { atomicOr(flag, 2); return; }
+        const double id = 1.0 / det;
+        double inv[9];
+        inv[0] = c00 * id;
+        inv[1] = (a[2] * a[7] - a[1] * a[8]) * id;
+        inv[2] = (a[1] * a[5] - a[2] * a[4]) * id;
+        inv[3] = c01 * id;
+        inv[4] = (a[0] * a[8] - a[2] * a[6]) * id;
+        inv[5] = (a[2] * a[3] - a[0] * a[5]) * id;
+        inv[6] = c02 * id;
+        inv[7] = (a[1] * a[6] - a[0] * a[7]) * id;
+        inv[8] = (a[0] * a[4] - a[1] * a[3]) * id;
+#pragma unroll
+        for (int p = 0; p < 9; ++p) dinv[static_cast<int64_t>(p) * n + i] = inv[p];
+    }
+}
+
+void launch_diag_inverse(int mode, int n, const int *rowptr, const int *col, const double *val,
+                         int64_t nnz, double *dinv, int *flag, hipStream_t s) {
+    if (n <= 0) return;
+    if (mode == 3)
+        k_diag_inverse<3><<<ceil_div(n, BLOCK), BLOCK, 0, s>>>(n, rowptr, col, val, nnz, dinv, flag);
+    else
+        k_diag_inverse<1><<<ceil_div(n, BLOCK), BLOCK, 0, s>>>(n, rowptr, col, val, nnz, dinv, flag);
+    AMG_CHECK_LAUNCH();
+}
+
+// one wavefront per grouped row
+__global__ void k_gather_rows(int np, int nrows, const int *order, const int *rowptr, const int *col,
+                              const double *val, int64_t nnz, const int *g_rowptr, int *g_col,
+                              double *g_val) {
+    const int g = blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (g >= nrows) return;
+    const int i = order[g];
+    const int src = rowptr[i], len = rowptr[i + 1] - rowptr[i];
+    const int dst = g_rowptr[g];
+    for (int q = lane; q < len; q += 64) {
+        g_col[dst + q] = col[src + q];
+        for (int p = 0; p < np; ++p) g_val[p * nnz + dst + q] = val[p * nnz + src + q];
+    }
+}
+
+void launch_gather_rows(int np, int nrows, const int *order, const int *rowptr, const int *col,
+                        const double *val, int64_t nnz, const int *g_rowptr, int *g_col, double *g_val,
+                        hipStream_t s) {
+    if (nrows <= 0) return;
+    k_gather_rows<<<ceil_div(nrows, BLOCK / 64), BLOCK, 0, s>>>(np, nrows, order, rowptr, col, val, nnz,
+                                                                 g_rowptr, g_col, g_val);
+    AMG_CHECK_LAUNCH();
+}
+
+}  // namespace amgp2

@@ -1,0 +1,366 @@
+// amg_solve: Algorithm 1 (the basic AMG iteration) and the outer Krylov
+// drivers. Every vector operation runs on the GPU; Krylov scalars stay in a
+// device array, and the host reads one residual norm per iteration for the
+// stopping test.
+#include <chrono>
+#include <cmath>
+
+#include "context.h"
+
+namespace amgp2 {
+
+// ---------------------------------------------------------------- profiling
+ProfScope::ProfScope(amg_ctx *hh, const std::string &cls, double bytes) : h(hh), idx(0) {
+    if (!h->prof) return;
+    amg_ctx::Pending pe;
+    pe.cls = cls;
+    pe.bytes = bytes;
+    for (hipEvent_t *e : {&pe.a, &pe.b}) {
+        if (!h->event_pool.empty()) {
+            *e = h->event_pool.back();
+            h->event_pool.pop_back();
+        } else {
+            AMG_HIP(hipEventCreate(e));
+        }
+    }
+    AMG_HIP(hipEventRecord(pe.a, h->stream));
+    h->pending.push_back(pe);
+    idx = h->pending.size();
+}
+
+ProfScope::~ProfScope() {
+    if (!h->prof || idx == 0) return;
+    (void)hipEventRecord(h->pending[idx - 1].b, h->stream);
+}
+
+void profile_collect(amg_ctx *h) {
+    if (h->pending.empty()) return;
+    AMG_HIP(hipStreamSynchronize(h->stream));
+    for (auto &pe : h->pending) {
+        float ms = 0.f;
+        AMG_HIP(hipEventElapsedTime(&ms, pe.a, pe.b));
+        ProfStat &st = h->stats[pe.cls];
+        st.launches += 1;
+        st.ms += ms;
+        st.bytes += pe.bytes;
+        h->event_pool.push_back(pe.a);
+        h->event_pool.push_back(pe.b);
+    }
+    h->pending.clear();
+}
+
+// algorithmic bytes of one pass over rows [.., ..) of a block operator
+static double row_bytes(const DMat &m, int64_t nnz, int nrows) {
+    return static_cast<double>(nnz) * (m.np * 8.0 + 4.0) + nrows * 4.0;
+}
+
+static RowArgs row_args(const DMat &m) {
+    RowArgs a;
+    a.nrows = m.nrows;
+    a.rowptr = m.rowptr.p;
+    a.col = m.col.p;
+    a.val = m.val.p;
+    a.nnz = m.nnz;
+    return a;
+}
+
+static std::string tag(const char *cls, int l) { return std::string(cls) + ".L" + std::to_string(l); }
+
+// ---------------------------------------------------------------- level ops
+void apply_level(amg_ctx *h, int l, const double *x, double *y) {
+    Level &L = h->lv[l];
+    RowArgs a = row_args(L.A);
+    a.x = x;
+    a.y = y;
+    ProfScope ps(h, tag("spmv", l), row_bytes(L.A, L.A.nnz, L.n) + 3.0 * L.n * 16.0);
+    launch_row(L.mode, OP_SPMV, L.G, a, h->stream);
+}
+
+static void residual(amg_ctx *h, int l, const double *b, const double *x, double *r) {
+    Level &L = h->lv[l];
+    RowArgs a = row_args(L.A);
+    a.x = x;
+    a.b = b;
+    a.y = r;
+    ProfScope ps(h, tag("resid", l), row_bytes(L.A, L.A.nnz, L.n) + 3.0 * L.n * 24.0);
+    launch_row(L.mode, OP_RESID, L.G, a, h->stream);
+}
+
+static double level_omega(amg_ctx *h, int l) {
+    if (!h->level_omega.empty())
+        return h->level_omega[std::min<size_t>(l, h->level_omega.size() - 1)];
+    return h->prm.omega;
+}
+
+static void jacobi_step(amg_ctx *h, int l, const double *b, double *x, bool zero_init) {
+    Level &L = h->lv[l];
+    const double om = level_omega(h, l);
+    const int nb = L.mode == 3 ? 9 : 1;
+    if (zero_init) {
+        ProfScope ps(h, tag("jacobi0", l), 3.0 * L.n * 16.0 + nb * 8.0 * L.n);
+        launch_jacobi_zero(L.mode, L.n, L.dinv.p, b, om, x, h->stream);
+        return;
+    }
+    RowArgs a = row_args(L.A);
+    a.x = x;
+    a.b = b;
+    a.y = L.t.p;
+    a.dinv = L.dinv.p;
+    a.dinv_n = L.n;
+    a.omega = om;
+    {
+        ProfScope ps(h, tag("jacobi", l), row_bytes(L.A, L.A.nnz, L.n) + 3.0 * L.n * 24.0 + nb * 8.0 * L.n);
+        launch_row(L.mode, OP_JACOBI, L.G, a, h->stream);
+    }
+    launch_copy(x, L.t.p, 3 * static_cast<int64_t>(L.n), h->stream);
+}
+
+static void gs_sweep(amg_ctx *h, int l, const double *b, double *x, bool forward) {
+    Level &L = h->lv[l];
+    const int ncol = static_cast<int>(L.cptr.size()) - 1;
+    const int nb = L.mode == 3 ? 9 : 1;
+    for (int q = 0; q < ncol; ++q) {
+        const int c = forward ? q : ncol - 1 - q;
+        const int r0 = L.cptr[c], r1 = L.cptr[c + 1];
+        if (r1 == r0) continue;
+        RowArgs a;
+        a.nrows = r1 - r0;
+        a.rowptr = L.Ag.rowptr.p + r0;
+        a.col = L.Ag.col.p;
+        a.val = L.Ag.val.p;
+        a.nnz = L.Ag.nnz;
+        a.rowid = L.g_rowid.p + r0;
+        a.x = x;
+        a.b = b;
+        a.y = x;
+        a.dinv = L.dinv.p;
+        a.dinv_n = L.n;
+        // matrix rows of this colour + row pointer, row id, b_i, x_i read and
+        // write, inverted diagonal block
+        const double bytes = static_cast<double>(L.colour_nnz[c]) * (L.Ag.np * 8.0 + 4.0) +
+                             a.nrows * (8.0 + 24.0 + 48.0 + nb * 8.0);
+        ProfScope ps(h, tag("gs", l), bytes);
+        launch_row(L.mode, OP_GS, L.Gg, a, h->stream);
+    }
+}
+
+void smooth(amg_ctx *h, int l, const double *b, double *x, bool pre, bool zero_init) {
+    const amg_params &p = h->prm;
+    const int steps = pre ? p.pre : p.post;
+    Level &L = h->lv[l];
+    for (int k = 0; k < steps; ++k) {
+        const bool z = zero_init && k == 0;
+        if (p.smoother == AMG_SMOOTH_JA) {
+            jacobi_step(h, l, b, x, z);
+        } else {
+            if (z) launch_fill(x, 0.0, 3 * static_cast<int64_t>(L.n), h->stream);
+            gs_sweep(h, l, b, x, pre);
+        }
+    }
+    if (steps == 0 && zero_init) launch_fill(x, 0.0, 3 * static_cast<int64_t>(L.n), h->stream);
+}
+
+static void coarse_solve(amg_ctx *h, const double *b, double *x) {
+    ProfScope ps(h, "coarse", static_cast<double>(h->coarse_m) * h->coarse_m * 8.0);
+    launch_dense_gemv(h->coarse_inv.p, h->coarse_m, h->coarse_nc, b, x, h->stream);
+}
+
+// Algorithm 1: AMG(K_l, x_l, b_l). x_zero says that x_l is zero on entry
+// (then the first smoothing step needs no operator pass for Jacobi).
+static void cycle(amg_ctx *h, int l, const double *b, double *x, bool x_zero) {
+    Level &L = h->lv[l];
+    if (L.coarsest) {
+        coarse_solve(h, b, x);
+        return;
+    }
+    smooth(h, l, b, x, true, x_zero);
+    residual(h, l, b, x, L.r.p);
+    Level &C = h->lv[l + 1];
+    {
+        RowArgs a = row_args(L.R);
+        a.x = L.r.p;
+        a.y = C.b.p;
+        ProfScope ps(h, tag("restrict", l), row_bytes(L.R, L.R.nnz, L.R.nrows) + 3.0 * (L.n + C.n) * 8.0);
+        launch_row(1, OP_SPMV, L.Gr, a, h->stream);
+    }
+    if (C.coarsest) {
+        coarse_solve(h, C.b.p, C.x.p);
+    } else {
+        // x_{l+1} = 0, then nu recursive calls (nu = 1: V-cycle, 2: W-cycle)
+        const int nu = std::max(1, h->prm.nu);
+        for (int k = 0; k < nu; ++k) cycle(h, l + 1, C.b.p, C.x.p, k == 0);
+    }
+    {
+        RowArgs a = row_args(L.P);
+        a.x = C.x.p;
+        a.y = x;
+        ProfScope ps(h, tag("prolong", l), row_bytes(L.P, L.P.nnz, L.P.nrows) + 3.0 * (2.0 * L.n + C.n) * 8.0);
+        launch_row(1, OP_SPMV_ADD, L.Gp, a, h->stream);
+    }
+    smooth(h, l, b, x, false, false);
+}
+
+void vcycle(amg_ctx *h, int l, const double *b, double *x) { cycle(h, l, b, x, true); }
+
+// z = M^{-1} r: `cycles` successive applications of Algorithm 1 on the
+// finest level, the first from z = 0, each further one from the current z.
+void precondition(amg_ctx *h, const double *r, double *z) {
+    const int cyc = std::max(1, h->prm.cycles);
+    for (int k = 0; k < cyc; ++k) cycle(h, 0, r, z, k == 0);
+}
+
+}  // namespace amgp2
+
+// ---------------------------------------------------------------- Krylov
+namespace amgp2 {
+
+static double read_scalar(amg_ctx *h, int idx) {
+    AMG_HIP(hipMemcpyAsync(h->h_sc, h->sc.p, SC_COUNT * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    AMG_HIP(hipStreamSynchronize(h->stream));
+    return h->h_sc[idx];
+}
+
+static void dot_into(amg_ctx *h, const double *a, const double *b, int dst) {
+    ProfScope ps(h, "blas", 2.0 * h->n_dof * 8.0);
+    const int nb = launch_dot_partial(a, b, h->n_dof, h->partial.p, h->stream);
+    launch_reduce(h->partial.p, nb, h->sc.p, dst, h->stream);
+}
+
+// q = A p on the finest level and <p, q> into sc[SC_PQ]
+static void spmv_dot(amg_ctx *h, const double *p, double *q) {
+    Level &L = h->lv[0];
+    RowArgs a = row_args(L.A);
+    a.x = p;
+    a.y = q;
+    a.partial = h->partial.p;
+    {
+        ProfScope ps(h, "spmv.L0", row_bytes(L.A, L.A.nnz, L.n) + 3.0 * L.n * 16.0);
+        launch_row(L.mode, OP_SPMV_DOT, L.G, a, h->stream);
+    }
+    launch_reduce(h->partial.p, row_blocks(L.n, L.G), h->sc.p, SC_PQ, h->stream);
+}
+
+static void cg_update(amg_ctx *h, double *x, double *r, const double *p, const double *q) {
+    ProfScope ps(h, "blas", 6.0 * h->n_dof * 8.0);
+    const int nb = launch_cg_update(x, r, p, q, h->sc.p, h->n_dof, h->partial.p, h->stream);
+    launch_reduce(h->partial.p, nb, h->sc.p, SC_RR, h->stream);
+}
+
+double true_relres(amg_ctx *h, const double *b, const double *x, double r0norm) {
+    residual(h, 0, b, x, h->kw.p);
+    dot_into(h, h->kw.p, h->kw.p, SC_TMP);
+    const double rr = read_scalar(h, SC_TMP);
+    return r0norm > 0.0 ? std::sqrt(rr) / r0norm : 0.0;
+}
+
+static int finish(amg_ctx *h, const double *b, const double *x, double r0, int it, int status,
+                  std::chrono::steady_clock::time_point t0, amg_result *res) {
+    const double rel = true_relres(h, b, x, r0);
+    if (status == AMG_OK && !(rel == rel)) status = AMG_DIVERGED;
+    if (res) {
+        res->iters = it;
+        res->status = status;
+        res->relres = rel;
+        res->solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    profile_collect(h);
+    return status;
+}
+
+// classify the recursive residual: converged, diverged, or continue (-1)
+static int check(double rr, double rr0, double tol) {
+    if (!(rr == rr) || std::isinf(rr)) return AMG_DIVERGED;
+    const double rel = std::sqrt(rr / rr0);
+    if (rel > 1e3) return AMG_DIVERGED;
+    if (rel <= tol) return AMG_OK;
+    return -1;
+}
+
+int solve_pcg(amg_ctx *h, const double *b, double *x, double tol, int maxit, amg_result *res) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const int64_t n = h->n_dof;
+    double *r = h->kr.p, *z = h->kz.p, *p = h->kp.p, *q = h->kq.p;
+    residual(h, 0, b, x, r);
+    dot_into(h, r, r, SC_RR);
+    const double rr0 = read_scalar(h, SC_RR);
+    const double r0 = std::sqrt(rr0);
+    if (rr0 == 0.0) return finish(h, b, x, r0, 0, AMG_OK, t0, res);
+    if (!(rr0 == rr0)) return finish(h, b, x, r0, 0, AMG_DIVERGED, t0, res);
+    precondition(h, r, z);
+    dot_into(h, r, z, SC_RZ);
+    launch_copy(p, z, n, h->stream);
+    int it = 0, status = AMG_NOT_CONVERGED;
+    while (it < maxit) {
+        spmv_dot(h, p, q);
+        launch_cg_alpha(h->sc.p, h->stream);
+        cg_update(h, x, r, p, q);
+        ++it;
+        const double rr = read_scalar(h, SC_RR);
+        if (!(h->h_sc[SC_PQ] > 0.0)) { status = AMG_BREAKDOWN; break; }
+        const int c = check(rr, rr0, tol);
+        if (c >= 0) { status = c; break; }
+        precondition(h, r, z);
+        dot_into(h, r, z, SC_TMP);
+        launch_cg_beta(h->sc.p, h->stream);
+        launch_cg_direction(p, z, h->sc.p, n, h->stream);
+    }
+    return finish(h, b, x, r0, it, status, t0, res);
+}
+
+int solve_fcg(amg_ctx *h, const double *b, double *x, double tol, int maxit, amg_result *res) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const int64_t n = h->n_dof;
+    double *r = h->kr.p, *z = h->kz.p, *p = h->kp.p, *q = h->kq.p;
+    residual(h, 0, b, x, r);
+    dot_into(h, r, r, SC_RR);
+    const double rr0 = read_scalar(h, SC_RR);
+    const double r0 = std::sqrt(rr0);
+    if (rr0 == 0.0) return finish(h, b, x, r0, 0, AMG_OK, t0, res);
+    if (!(rr0 == rr0)) return finish(h, b, x, r0, 0, AMG_DIVERGED, t0, res);
+    int it = 0, status = AMG_NOT_CONVERGED;
+    while (it < maxit) {
+        precondition(h, r, z);
+        if (it == 0) {
+            launch_copy(p, z, n, h->stream);
+        } else {
+            // p = z - (<z, q_prev> / <p_prev, q_prev>) p_prev
+            dot_into(h, z, q, SC_TMP);
+            launch_fcg_beta(h->sc.p, h->stream);
+            launch_cg_direction(p, z, h->sc.p, n, h->stream);
+        }
+        spmv_dot(h, p, q);
+        dot_into(h, p, r, SC_PR);
+        launch_fcg_alpha(h->sc.p, h->stream);
+        cg_update(h, x, r, p, q);
+        ++it;
+        const double rr = read_scalar(h, SC_RR);
+        if (!(h->h_sc[SC_PQ] > 0.0)) { status = AMG_BREAKDOWN; break; }
+        const int c = check(rr, rr0, tol);
+        if (c >= 0) { status = c; break; }
+    }
+    return finish(h, b, x, r0, it, status, t0, res);
+}
+
+// Stand-alone AMG: repeated Algorithm 1 from the current iterate.
+int solve_stationary(amg_ctx *h, const double *b, double *x, double tol, int maxit, amg_result *res) {
+    const auto t0 = std::chrono::steady_clock::now();
+    double *r = h->kr.p;
+    residual(h, 0, b, x, r);
+    dot_into(h, r, r, SC_RR);
+    const double rr0 = read_scalar(h, SC_RR);
+    const double r0 = std::sqrt(rr0);
+    if (rr0 == 0.0) return finish(h, b, x, r0, 0, AMG_OK, t0, res);
+    int it = 0, status = AMG_NOT_CONVERGED;
+    const int cyc = std::max(1, h->prm.cycles);
+    while (it < maxit) {
+        for (int k = 0; k < cyc; ++k) cycle(h, 0, b, x, false);
+        residual(h, 0, b, x, r);
+        dot_into(h, r, r, SC_RR);
+        ++it;
+        const int c = check(read_scalar(h, SC_RR), rr0, tol);
+        if (c >= 0) { status = c; break; }
+    }
+    return finish(h, b, x, r0, it, status, t0, res);
+}
+
+}  // namespace amgp2

@@ -1,0 +1,195 @@
+"""Python handle around the C ABI: setup, solve and the introspection calls.
+
+Vectors are torch CUDA float64 tensors; the library runs on the caller's
+current torch stream unless another stream is given.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _lib as C
+from .problems import LinearSystem
+
+
+def parse_smoother(name: str) -> dict:
+    """The paper's smoother names: 'JA-1-1-0.5', 'GS-2-2', 'sGS-1-1',
+    'Braess-Sarazin-1-1' (alias 'BS-1-1')."""
+    parts = name.split("-")
+    if parts[0] == "Braess":
+        parts = ["BS"] + parts[2:]
+    kind = {"JA": "JA", "GS": "GS", "sGS": "SGS", "SGS": "SGS", "BS": "BS"}[parts[0]]
+    out = dict(smoother=kind, pre=int(parts[1]), post=int(parts[2]))
+    if kind == "JA" and len(parts) > 3:
+        out["omega"] = float(parts[3])
+    return out
+
+
+@dataclass
+class SolveResult:
+    iters: int
+    status: int
+    relres: float
+    solve_ms: float
+
+    @property
+    def converged(self) -> bool:
+        return self.status == C.AMG_OK
+
+
+def _stream_handle(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_ptr(t, n: int, name: str):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise TypeError(f"{name}: expected a contiguous float64 CUDA tensor")
+    if t.numel() != n:
+        raise ValueError(f"{name}: expected {n} values, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class AMGSolver:
+    """amg_setup on construction; amg_solve / amg_precondition / ... on call."""
+
+    def __init__(self, system: LinearSystem, smoother: str = "GS-1-1", krylov: str = "PCG",
+                 precision: str = "FP64", cycles: int = 1, nu: int = 1, coarse_max: int = 300,
+                 max_levels: int = 10, separate: bool = True, level_omega=None,
+                 sgs_omega: float = 0.125, sgs_damping: float = 0.5, restart: int = 100,
+                 omega: float | None = None, stream=None):
+        L = C.lib()
+        p = C.default_params()
+        sm = parse_smoother(smoother)
+        p.smoother = C.SMOOTH[sm["smoother"]]
+        p.pre, p.post = sm["pre"], sm["post"]
+        p.omega = omega if omega is not None else sm.get("omega", 0.5)
+        p.sgs_omega, p.sgs_damping = sgs_omega, sgs_damping
+        p.cycles, p.nu = cycles, nu
+        p.coarse_max, p.max_levels = coarse_max, max_levels
+        p.separate = 1 if separate else 0
+        p.krylov = C.KRYLOV[krylov]
+        p.restart = restart
+        p.precision = C.PREC[precision]
+        self._omega_buf = None
+        if level_omega is not None:
+            self._omega_buf = np.ascontiguousarray(level_omega, dtype=np.float64)
+            p.n_level_omega = self._omega_buf.shape[0]
+            p.level_omega = C._ptr(self._omega_buf, ctypes.c_double)
+        self.params = p
+        self.system = system
+        keep = []
+
+        def arr(a, dtype, ctype):
+            if a is None:
+                return None
+            a = np.ascontiguousarray(a, dtype=dtype)
+            keep.append(a)
+            return C._ptr(a, ctype)
+
+        s = C.AmgSystem()
+        s.n_lin, s.n_quad, s.n_pres, s.bs = system.n_lin, system.n_quad, system.n_pres, system.bs
+        s.A_rowptr = arr(system.A_rowptr, np.int32, ctypes.c_int32)
+        s.A_col = arr(system.A_col, np.int32, ctypes.c_int32)
+        s.A_val = arr(system.A_val, np.float64, ctypes.c_double)
+        s.B_rowptr = arr(system.B_rowptr, np.int32, ctypes.c_int32)
+        s.B_col = arr(system.B_col, np.int32, ctypes.c_int32)
+        s.B_val = arr(system.B_val, np.float64, ctypes.c_double)
+        s.C_rowptr = arr(system.C_rowptr, np.int32, ctypes.c_int32)
+        s.C_col = arr(system.C_col, np.int32, ctypes.c_int32)
+        s.C_val = arr(system.C_val, np.float64, ctypes.c_double)
+        s.pressure_kernel = 1 if system.pressure_kernel else 0
+        self._stream = stream
+        h = ctypes.c_void_p()
+        C.check(L.amg_setup(ctypes.byref(s), ctypes.byref(p), _stream_handle(stream), ctypes.byref(h)),
+                "amg_setup")
+        self.h = h
+        self.n = system.dofs
+
+    # ---------------------------------------------------------------- calls
+    def solve(self, b, x, tol: float = 1e-8, maxit: int = 500) -> SolveResult:
+        r = C.AmgResult()
+        code = C.lib().amg_solve(self.h, _dev_ptr(b, self.n, "b"), _dev_ptr(x, self.n, "x"), float(tol),
+                                 int(maxit), _stream_handle(self._stream), ctypes.byref(r))
+        C.check(code, "amg_solve")
+        return SolveResult(r.iters, r.status, r.relres, r.solve_ms)
+
+    def precondition(self, r, z) -> None:
+        C.check(C.lib().amg_precondition(self.h, _dev_ptr(r, self.n, "r"), _dev_ptr(z, self.n, "z"),
+                                         _stream_handle(self._stream)), "amg_precondition")
+
+    def level_dofs(self, level: int) -> int:
+        i = self.level_info(level)
+        return 3 * (i.n_lin + i.n_quad) + i.n_pres
+
+    def apply(self, level: int, x, y) -> None:
+        n = self.level_dofs(level)
+        C.check(C.lib().amg_apply(self.h, level, _dev_ptr(x, n, "x"), _dev_ptr(y, n, "y"),
+                                  _stream_handle(self._stream)), "amg_apply")
+
+    def smooth(self, level: int, b, x, forward: bool = True) -> None:
+        n = self.level_dofs(level)
+        C.check(C.lib().amg_smooth(self.h, level, _dev_ptr(b, n, "b"), _dev_ptr(x, n, "x"),
+                                   1 if forward else 0, _stream_handle(self._stream)), "amg_smooth")
+
+    @property
+    def num_levels(self) -> int:
+        return C.check(C.lib().amg_num_levels(self.h), "amg_num_levels")
+
+    def level_info(self, level: int) -> C.AmgLevelInfo:
+        info = C.AmgLevelInfo()
+        C.check(C.lib().amg_get_level_info(self.h, level, ctypes.byref(info)), "amg_get_level_info")
+        return info
+
+    def level_matrix(self, level: int, which: str = "A"):
+        """(rowptr, col, val) of a level operator; val has shape (nnz, np)."""
+        info = self.level_info(level)
+        code = {"A": 0, "B": 1, "C": 2, "P": 3}[which]
+        n = info.n_lin + info.n_quad
+        if which == "A":
+            nnz, width, nrows = info.nnz_A, info.bs * info.bs, n
+        elif which == "P":
+            nnz, width, nrows = info.nnz_P, 1, n
+        elif which == "B":
+            nnz, width, nrows = info.nnz_B, 3, info.n_pres
+        else:
+            nnz, width, nrows = info.nnz_C, 1, info.n_pres
+        rowptr = np.zeros(nrows + 1, dtype=np.int32)
+        col = np.zeros(max(1, nnz), dtype=np.int32)
+        val = np.zeros(max(1, nnz * width), dtype=np.float64)
+        C.check(C.lib().amg_get_level_matrix(self.h, level, code, C._ptr(rowptr, ctypes.c_int32),
+                                             C._ptr(col, ctypes.c_int32), C._ptr(val, ctypes.c_double)),
+                "amg_get_level_matrix")
+        return rowptr, col[:nnz], val[: nnz * width].reshape(nnz, width)
+
+    def level_colors(self, level: int) -> np.ndarray:
+        info = self.level_info(level)
+        out = np.zeros(info.n_lin + info.n_quad, dtype=np.int32)
+        C.check(C.lib().amg_get_level_colors(self.h, level, C._ptr(out, ctypes.c_int32)), "amg_get_level_colors")
+        return out
+
+    def profile(self, enable: bool = True) -> None:
+        C.check(C.lib().amg_profile_enable(self.h, 1 if enable else 0), "amg_profile_enable")
+
+    def profile_read(self, cls: str) -> dict:
+        n = ctypes.c_int64()
+        ms = ctypes.c_double()
+        by = ctypes.c_double()
+        C.check(C.lib().amg_profile_read(self.h, cls.encode(), ctypes.byref(n), ctypes.byref(ms),
+                                         ctypes.byref(by)), "amg_profile_read")
+        return dict(launches=n.value, ms=ms.value, bytes=by.value)
+
+    def close(self) -> None:
+        if getattr(self, "h", None):
+            C.lib().amg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
