@@ -199,10 +199,14 @@ int amg_get_level_matrix(amg_handle h, int32_t level, int32_t which, int32_t *ro
 int amg_get_level_colors(amg_handle h, int32_t level, int32_t *colors);
 
 /* Per-kernel timing of the hot loops with HIP events recorded on the
- * library's launch stream. enable = 1 starts (and clears) the counters. */
+ * library's launch stream (the stream of the call that launches them).
+ * enable = 1 times every launch, enable = 2 only the finest level's launches
+ * (fewer events in flight), 0 stops; a nonzero value clears the counters. */
 int amg_profile_enable(amg_handle h, int32_t enable);
-/* Kernel classes: "spmv", "gs", "jacobi", "resid", "restrict", "prolong",
- * "coarse", "blas". Returns launches, total ms and algorithmic bytes. */
+/* Kernel classes "<op>.L<level>" with op one of spmv, gs, jacobi, jacobi0,
+ * resid, restrict, prolong; plus "coarse" and "blas". Returns launches,
+ * total ms and algorithmic bytes (bytes the operation must move at least:
+ * every stored entry and index once, every vector once). */
 int amg_profile_read(amg_handle h, const char *kernel_class, int64_t *launches, double *total_ms,
                      double *bytes);
 

@@ -206,6 +206,7 @@ int amg_profile_enable(amg_handle h, int32_t enable) {
         AMG_REQUIRE(h, AMG_EINVAL, "amg_profile_enable: null handle");
         profile_collect(h);
         h->prof = enable != 0;
+        h->prof_finest_only = enable == 2;
         if (h->prof) h->stats.clear();
         return AMG_OK;
     });

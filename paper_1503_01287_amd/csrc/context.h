@@ -65,6 +65,7 @@ struct amg_ctx {
     int n_dof = 0;           // length of a solve vector
     // profiling
     bool prof = false;
+    bool prof_finest_only = false;
     struct Pending {
         std::string cls;
         hipEvent_t a, b;

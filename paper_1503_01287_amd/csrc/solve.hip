@@ -12,6 +12,7 @@ namespace amgp2 {
 // ---------------------------------------------------------------- profiling
 ProfScope::ProfScope(amg_ctx *hh, const std::string &cls, double bytes) : h(hh), idx(0) {
     if (!h->prof) return;
+    if (h->prof_finest_only && cls.size() > 3 && cls.compare(cls.size() - 3, 3, ".L0") != 0) return;
     amg_ctx::Pending pe;
     pe.cls = cls;
     pe.bytes = bytes;

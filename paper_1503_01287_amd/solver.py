@@ -172,8 +172,9 @@ class AMGSolver:
         C.check(C.lib().amg_get_level_colors(self.h, level, C._ptr(out, ctypes.c_int32)), "amg_get_level_colors")
         return out
 
-    def profile(self, enable: bool = True) -> None:
-        C.check(C.lib().amg_profile_enable(self.h, 1 if enable else 0), "amg_profile_enable")
+    def profile(self, mode: int = 1) -> None:
+        """1: time every launch, 2: only the finest level's launches, 0: off."""
+        C.check(C.lib().amg_profile_enable(self.h, int(mode)), "amg_profile_enable")
 
     def profile_read(self, cls: str) -> dict:
         n = ctypes.c_int64()
