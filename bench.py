@@ -121,7 +121,8 @@ def main() -> int:
     levels = []
     for l in range(solver.num_levels):
         i = solver.level_info(l)
-        levels.append(dict(nodes=i.n_lin + i.n_quad, nnz=int(i.nnz_A), colors=int(i.n_colors)))
+        levels.append(dict(nodes=i.n_lin + i.n_quad, nnz=int(i.nnz_A), colors=int(i.n_colors),
+                           lanes=[int(i.lanes_A), int(i.lanes_gs)], fused=bool(i.fused)))
     print(f"# setup {setup_ms:.0f} ms, levels {levels}", file=sys.stderr, flush=True)
 
     def step():

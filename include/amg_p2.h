@@ -132,6 +132,13 @@ typedef struct {
     int32_t precision;    /* AMG_PREC_*                                      */
     int32_t n_level_omega;        /* > 0: per-level JA damping follows     */
     const double *level_omega;    /* host, n_level_omega values (copied)   */
+    int32_t fuse_coarse;  /* 1 (default): the coarse end of a V-cycle runs as
+                             one kernel (an explicit operator assembled at
+                             setup, or a single-workgroup kernel); 0: one
+                             launch per operation. Same arithmetic, up to
+                             rounding order.                                  */
+    int32_t autotune;     /* 1 (default): time the row kernels' lanes-per-row
+                             choices on each level at setup; 0: heuristic.   */
 } amg_params;
 
 typedef struct {
@@ -150,6 +157,10 @@ typedef struct {
                                       (0 on the coarsest level)               */
     int32_t n_colors;              /* Gauss-Seidel colours (0 if not built)    */
     int32_t is_coarsest;
+    int32_t lanes_A, lanes_gs;     /* lanes per row chosen for the level's
+                                      natural-order and colour-sweep kernels  */
+    int32_t fused;                 /* 1 if a V-cycle reaching this level runs
+                                      it inside the fused coarse kernel       */
 } amg_level_info;
 
 /* Fill *p with the defaults listed above. */

@@ -45,6 +45,7 @@ class AmgParams(ctypes.Structure):
         ("coarse_max", ctypes.c_int32), ("separate", ctypes.c_int32), ("krylov", ctypes.c_int32),
         ("restart", ctypes.c_int32), ("precision", ctypes.c_int32),
         ("n_level_omega", ctypes.c_int32), ("level_omega", _f64p),
+        ("fuse_coarse", ctypes.c_int32), ("autotune", ctypes.c_int32),
     ]
 
 
@@ -60,6 +61,7 @@ class AmgLevelInfo(ctypes.Structure):
         ("nnz_A", ctypes.c_int64), ("nnz_B", ctypes.c_int64), ("nnz_C", ctypes.c_int64),
         ("nnz_P", ctypes.c_int64),
         ("n_colors", ctypes.c_int32), ("is_coarsest", ctypes.c_int32),
+        ("lanes_A", ctypes.c_int32), ("lanes_gs", ctypes.c_int32), ("fused", ctypes.c_int32),
     ]
 
 

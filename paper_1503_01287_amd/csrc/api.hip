@@ -58,6 +58,8 @@ void amg_default_params(amg_params *p) {
     p->precision = AMG_PREC_FP64;
     p->n_level_omega = 0;
     p->level_omega = nullptr;
+    p->fuse_coarse = 1;
+    p->autotune = 1;
 }
 
 int amg_setup(const amg_system *sys, const amg_params *params, amg_stream stream, amg_handle *out) {
@@ -136,7 +138,7 @@ int amg_smooth(amg_handle h, int32_t level, const double *b, double *x, int32_t 
         amg_params save = h->prm;
         h->prm.pre = h->prm.post = 1;
         try {
-            smooth(h, level, b, x, forward != 0, false);
+            smooth(h, level, b, x, forward != 0, false, false);
         } catch (...) {
             h->prm = save;
             throw;
@@ -164,6 +166,10 @@ int amg_get_level_info(amg_handle h, int32_t level, amg_level_info *info) {
         info->nnz_P = L.coarsest ? 0 : L.P.nnz;
         info->n_colors = L.cptr.empty() ? 0 : static_cast<int>(L.cptr.size()) - 1;
         info->is_coarsest = L.coarsest ? 1 : 0;
+        info->lanes_A = L.G;
+        info->lanes_gs = L.Gg;
+        const int fs = h->tail_start >= 0 ? h->tail_start : h->dense_start;
+        info->fused = (fs >= 0 && level >= fs) ? 1 : 0;
         return AMG_OK;
     });
 }

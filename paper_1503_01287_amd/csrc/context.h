@@ -8,6 +8,7 @@
 #include "common.h"
 #include "host_setup.h"
 #include "kernels.h"
+#include "tail.h"
 
 namespace amgp2 {
 
@@ -33,6 +34,7 @@ struct Level {
     std::vector<int64_t> colour_nnz;  // stored entries in the rows of colour c
     DMat Ag;                  // rows of A grouped by colour
     DevBuf<int> g_rowid;      // node of grouped row g
+    DevBuf<int> d_cptr;       // cptr on the device (tail kernel)
     // transfer between this level and the next coarser one
     DMat P, R;                // P: n x n_c scalar, R = P^T
     HostCSR hP;
@@ -58,6 +60,17 @@ struct amg_ctx {
     // coarsest level: explicit dense inverse
     amgp2::DevBuf<double> coarse_inv;
     int coarse_m = 0, coarse_nc = 1;
+    // single-workgroup tail: levels tail_start.. run in one kernel (-1: none)
+    int tail_start = -1;
+    amgp2::TailArgs tail_args;
+    amgp2::DevBuf<amgp2::TailLevel> tail_levels;
+    int tail_lds = 0;
+    double tail_bytes = 0.0;
+    // the V-cycle from level dense_start (>= 1) down, as an explicit
+    // operator x = T b (tail_m x tail_m, applied to tail_nc components)
+    int dense_start = -1;
+    amgp2::DevBuf<double> tail_dense;
+    int tail_m = 0, tail_nc = 1;
     // Krylov workspace
     amgp2::DevBuf<double> kr, kz, kp, kq, kw;
     amgp2::DevBuf<double> partial, sc;
@@ -83,7 +96,7 @@ void build_hierarchy(amg_ctx *h, const amg_system *sys);
 void vcycle(amg_ctx *h, int l, const double *b, double *x);
 void precondition(amg_ctx *h, const double *r, double *z);
 void apply_level(amg_ctx *h, int l, const double *x, double *y);
-void smooth(amg_ctx *h, int l, const double *b, double *x, bool pre, bool zero_init);
+void smooth(amg_ctx *h, int l, const double *b, double *x, bool pre, bool zero_init, bool filled);
 int solve_pcg(amg_ctx *h, const double *b, double *x, double tol, int maxit, amg_result *res);
 int solve_fcg(amg_ctx *h, const double *b, double *x, double tol, int maxit, amg_result *res);
 int solve_stationary(amg_ctx *h, const double *b, double *x, double tol, int maxit, amg_result *res);

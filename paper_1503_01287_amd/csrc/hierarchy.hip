@@ -152,11 +152,89 @@ static void setup_smoother(amg_ctx *h, Level &L) {
     L.Ag.col.alloc(static_cast<size_t>(L.A.nnz));
     L.Ag.val.alloc(static_cast<size_t>(L.A.nnz) * L.A.np);
     L.g_rowid.upload(order, s);
+    L.d_cptr.upload(L.cptr, s);
     launch_gather_rows(L.A.np, L.n, L.g_rowid.p, L.A.rowptr.p, L.A.col.p, L.A.val.p, L.A.nnz, L.Ag.rowptr.p,
                        L.Ag.col.p, L.Ag.val.p, s);
     AMG_HIP(hipStreamSynchronize(s));
-    // rows of one colour form one launch: size the groups for their mean length
     L.Gg = L.G;
+}
+
+// Autotuner: lanes per row for the level's row kernels, measured with HIP
+// events on the level's own operators (residual on the natural rows, one
+// Gauss-Seidel launch on the largest colour). Runs on scratch vectors.
+static void autotune_level(amg_ctx *h, Level &L) {
+    hipStream_t s = h->stream;
+    const int cand[] = {8, 16, 32, 64};
+    hipEvent_t e0, e1;
+    AMG_HIP(hipEventCreate(&e0));
+    AMG_HIP(hipEventCreate(&e1));
+    launch_fill(L.x.p, 0.0, 3 * static_cast<int64_t>(L.n), s);
+    launch_fill(L.b.p, 1.0, 3 * static_cast<int64_t>(L.n), s);
+    launch_fill(L.t.p, 0.0, 3 * static_cast<int64_t>(L.n), s);
+    // best of 7 timed repetitions after 2 warm-up runs (short kernels are noisy)
+    auto time_it = [&](auto &&launch) {
+        launch();
+        launch();
+        float best_ms = 1e30f;
+        for (int r = 0; r < 7; ++r) {
+            AMG_HIP(hipEventRecord(e0, s));
+            launch();
+            AMG_HIP(hipEventRecord(e1, s));
+            AMG_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            AMG_HIP(hipEventElapsedTime(&ms, e0, e1));
+            best_ms = std::min(best_ms, ms);
+        }
+        return best_ms;
+    };
+    float best = 1e30f;
+    for (int G : cand) {
+        RowArgs a;
+        a.nrows = L.n;
+        a.rowptr = L.A.rowptr.p;
+        a.col = L.A.col.p;
+        a.val = L.A.val.p;
+        a.nnz = L.A.nnz;
+        a.x = L.x.p;
+        a.b = L.b.p;
+        a.y = L.r.p;
+        const float ms = time_it([&] { launch_row(L.mode, OP_RESID, G, a, s); });
+        if (ms < best) {
+            best = ms;
+            L.G = G;
+        }
+    }
+    if (!L.cptr.empty()) {
+        // a whole forward sweep, colour by colour, as the smoother runs it
+        best = 1e30f;
+        for (int G : cand) {
+            auto sweep = [&] {
+                for (size_t c = 0; c + 1 < L.cptr.size(); ++c) {
+                    if (L.cptr[c + 1] == L.cptr[c]) continue;
+                    RowArgs a;
+                    a.nrows = L.cptr[c + 1] - L.cptr[c];
+                    a.rowptr = L.Ag.rowptr.p + L.cptr[c];
+                    a.col = L.Ag.col.p;
+                    a.val = L.Ag.val.p;
+                    a.nnz = L.Ag.nnz;
+                    a.rowid = L.g_rowid.p + L.cptr[c];
+                    a.x = L.t.p;
+                    a.b = L.b.p;
+                    a.y = L.t.p;
+                    a.dinv = L.dinv.p;
+                    a.dinv_n = L.n;
+                    launch_row(L.mode, OP_GS, G, a, s);
+                }
+            };
+            const float ms = time_it(sweep);
+            if (ms < best) {
+                best = ms;
+                L.Gg = G;
+            }
+        }
+    }
+    AMG_HIP(hipEventDestroy(e0));
+    AMG_HIP(hipEventDestroy(e1));
 }
 
 static void setup_coarsest(amg_ctx *h, Level &L) {
@@ -188,6 +266,125 @@ static void setup_coarsest(amg_ctx *h, Level &L) {
     }
     (void)np;
     AMG_HIP(hipStreamSynchronize(s));
+}
+
+// Descriptors of levels t..L for the tail kernel; returns the doubles of
+// level vectors one workgroup needs (x, b, r: 9 per node).
+static int tail_descriptors(amg_ctx *h, int t, DevBuf<TailLevel> &buf, TailArgs &a, double &algo) {
+    const amg_params &p = h->prm;
+    const int L = static_cast<int>(h->lv.size()) - 1;
+    std::vector<TailLevel> d(L - t + 1);
+    int off = 0;
+    algo = 0.0;
+    for (int k = t; k <= L; ++k) {
+        Level &V = h->lv[k];
+        TailLevel &q = d[k - t];
+        q.n = V.n;
+        q.lds_off = off;
+        off += 9 * V.n;
+        if (k == L) break;
+        q.nc = h->lv[k + 1].n;
+        if (p.smoother == AMG_SMOOTH_GS) {
+            q.ncolors = static_cast<int>(V.cptr.size()) - 1;
+            q.cptr = V.d_cptr.p;
+            q.g_rowptr = V.Ag.rowptr.p;
+            q.g_col = V.Ag.col.p;
+            q.g_val = V.Ag.val.p;
+            q.g_nnz = V.Ag.nnz;
+            q.g_rowid = V.g_rowid.p;
+        }
+        q.a_rowptr = V.A.rowptr.p;
+        q.a_col = V.A.col.p;
+        q.a_val = V.A.val.p;
+        q.a_nnz = V.A.nnz;
+        q.dinv = V.dinv.p;
+        q.r_rowptr = V.R.rowptr.p;
+        q.r_col = V.R.col.p;
+        q.r_val = V.R.val.p;
+        q.p_rowptr = V.P.rowptr.p;
+        q.p_col = V.P.col.p;
+        q.p_val = V.P.val.p;
+        q.omega = h->level_omega.empty() ? p.omega
+                                         : h->level_omega[std::min<size_t>(k, h->level_omega.size() - 1)];
+        const double mat = static_cast<double>(V.A.nnz) * (V.A.np * 8.0 + 4.0);
+        algo += (p.pre + p.post + 1) * mat + 2.0 * V.P.nnz * 12.0;
+    }
+    algo += static_cast<double>(h->coarse_m) * h->coarse_m * 8.0;
+    buf.upload(d, h->stream);
+    AMG_HIP(hipStreamSynchronize(h->stream));
+    a = TailArgs();
+    a.nlev = L - t + 1;
+    a.smoother = p.smoother;
+    a.pre = p.pre;
+    a.post = p.post;
+    a.lv = buf.p;
+    a.cinv = h->coarse_inv.p;
+    a.cm = h->coarse_m;
+    a.cnc = h->coarse_nc;
+    return off;
+}
+
+// The coarse end of the V-cycle is handled in one of two ways:
+//  * dense tail: below the finest level a cycle always starts from x = 0, so
+//    the V-cycle from level d down is a fixed linear map T of b_d
+//    (pre-smoothing, restriction, coarser levels, prolongation,
+//    post-smoothing). T is assembled once, one unit right-hand side per
+//    workgroup of the tail kernel, and applied as a single GEMV.
+//  * LDS tail: if even the finest level is small, the whole V-cycle runs in
+//    one workgroup with the vectors in LDS.
+static void setup_tail(amg_ctx *h) {
+    h->tail_start = -1;
+    h->dense_start = -1;
+    h->tail_m = 0;
+    h->tail_dense.release();
+    const amg_params &p = h->prm;
+    if (!p.fuse_coarse || p.nu != 1) return;
+    if (p.smoother != AMG_SMOOTH_JA && p.smoother != AMG_SMOOTH_GS) return;
+    const int L = static_cast<int>(h->lv.size()) - 1;
+    if (L == 0) return;
+    // dense tail: the first level d >= 1 whose operator has at most TAIL_DENSE_MAX rows
+    int d = -1;
+    for (int k = 1; k < L; ++k) {
+        const int m = h->lv[k].mode == 3 ? 3 * h->lv[k].n : h->lv[k].n;
+        if (m <= TAIL_DENSE_MAX) {
+            d = k;
+            break;
+        }
+    }
+    if (d > 0) {
+        TailArgs u;
+        double algo = 0.0;
+        DevBuf<TailLevel> desc;
+        const int stride = tail_descriptors(h, d, desc, u, algo);
+        const int mode = h->lv[d].mode;
+        const int m = mode == 3 ? 3 * h->lv[d].n : h->lv[d].n;
+        h->tail_dense.alloc(static_cast<size_t>(m) * m);
+        const int chunk = 2048;
+        DevBuf<double> scratch(static_cast<size_t>(std::min(chunk, m)) * stride);
+        u.unit_rhs = 1;
+        u.m = m;
+        u.x_out = h->tail_dense.p;
+        u.gscratch = scratch.p;
+        u.gstride = stride;
+        for (int j0 = 0; j0 < m; j0 += chunk) {
+            u.unit_base = j0;
+            launch_tail(mode, u, 0, std::min(chunk, m - j0), h->stream);
+        }
+        AMG_HIP(hipStreamSynchronize(h->stream));
+        h->tail_m = m;
+        h->tail_nc = mode == 3 ? 1 : 3;
+        h->dense_start = d;
+    }
+    // LDS tail from the finest level, if everything fits
+    int64_t bytes = 0;
+    for (int k = 0; k <= L; ++k) bytes += 72 * static_cast<int64_t>(h->lv[k].n);
+    if (bytes <= TAIL_LDS_MAX && h->lv[0].A.nnz <= TAIL_NNZ_MAX) {
+        double algo = 0.0;
+        const int off = tail_descriptors(h, 0, h->tail_levels, h->tail_args, algo);
+        h->tail_lds = off * static_cast<int>(sizeof(double));
+        h->tail_bytes = algo;
+        h->tail_start = 0;
+    }
 }
 
 void build_hierarchy(amg_ctx *h, const amg_system *sys) {
@@ -249,9 +446,13 @@ void build_hierarchy(amg_ctx *h, const amg_system *sys) {
         L.b.alloc(3 * static_cast<size_t>(L.n));
         L.r.alloc(3 * static_cast<size_t>(L.n));
         L.t.alloc(3 * static_cast<size_t>(L.n));
-        if (!L.coarsest) setup_smoother(h, L);
+        if (!L.coarsest) {
+            setup_smoother(h, L);
+            if (p.autotune) autotune_level(h, L);
+        }
     }
     setup_coarsest(h, h->lv.back());
+    setup_tail(h);
     h->n_dof = 3 * h->lv[0].n;
     const size_t nd = static_cast<size_t>(h->n_dof);
     h->kr.alloc(nd);

@@ -22,9 +22,10 @@ __device__ __forceinline__ double group_sum(double v) {
     return v;
 }
 
-// Sum over the 256 threads of a block (deterministic order); result in thread 0.
+// Sum over the NT threads of a block (deterministic order); result in thread 0.
+template <int NT = BLOCK>
 __device__ __forceinline__ double block_sum(double v) {
-    __shared__ double red[BLOCK / 64];
+    __shared__ double red[NT / 64];
     v = group_sum<64>(v);
     const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) red[w] = v;
@@ -32,21 +33,55 @@ __device__ __forceinline__ double block_sum(double v) {
     double t = 0.0;
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int i = 0; i < BLOCK / 64; ++i) t += red[i];
+        for (int i = 0; i < NT / 64; ++i) t += red[i];
     }
     return t;
 }
 
 template <int MODE, int G, int OP>
 __global__ void __launch_bounds__(BLOCK) k_row(const RowArgs a) {
+    // Workgroups are dispatched round-robin over the 8 XCDs, so consecutive
+    // row blocks run on different XCDs at the same time and the whole chip
+    // streams through one region of the matrix. (Remapping ids to give each
+    // XCD a contiguous range measured 1.9x slower on the finest level.)
     const int64_t t = static_cast<int64_t>(blockIdx.x) * BLOCK + threadIdx.x;
     const int g = static_cast<int>(t / G);
     const int lane = static_cast<int>(t % G);
     const bool active = g < a.nrows;
+    constexpr bool NEEDS_B = OP == OP_RESID || OP == OP_JACOBI || OP == OP_GS;
+    constexpr bool NEEDS_D = OP == OP_JACOBI || OP == OP_GS;
+    constexpr bool NEEDS_OWN = OP == OP_SPMV_ADD || OP == OP_JACOBI || OP == OP_GS || OP == OP_SPMV_DOT;
+    // Row-local operands of the epilogue are loaded first so that their
+    // latency overlaps the row's matrix loads instead of following them.
+    const int i = active ? (a.rowid ? a.rowid[g] : g) : 0;
+    const bool ep = active && lane < 3;
+    const int c = ep ? lane : 0;
+    double b0 = 0.0, b1 = 0.0, b2 = 0.0, d0 = 0.0, d1 = 0.0, d2 = 0.0, own = 0.0;
+    if (ep) {
+        if constexpr (NEEDS_B) {
+            b0 = a.b[3 * i];
+            b1 = a.b[3 * i + 1];
+            b2 = a.b[3 * i + 2];
+        }
+        if constexpr (NEEDS_D) {
+            if constexpr (MODE == 3) {
+                const double *D = a.dinv + i;
+                const int64_t dn = a.dinv_n;
+                d0 = D[(3 * c) * dn];
+                d1 = D[(3 * c + 1) * dn];
+                d2 = D[(3 * c + 2) * dn];
+            } else {
+                d0 = a.dinv[i];
+            }
+        }
+        if constexpr (NEEDS_OWN) own = (OP == OP_SPMV_ADD || OP == OP_GS) ? a.y[3 * i + c] : a.x[3 * i + c];
+    }
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     if (active) {
         const int beg = a.rowptr[g], end = a.rowptr[g + 1];
         const int64_t nz = a.nnz;
+        // (a two-entries-per-trip variant measured slower on gfx950: the
+        // extra registers cost more occupancy than the overlap gained)
         for (int k = beg + lane; k < end; k += G) {
             const int j = a.col[k];
             const double x0 = a.x[3 * j], x1 = a.x[3 * j + 1], x2 = a.x[3 * j + 2];
@@ -67,41 +102,38 @@ __global__ void __launch_bounds__(BLOCK) k_row(const RowArgs a) {
     s1 = group_sum<G>(s1);
     s2 = group_sum<G>(s2);
 
-    const int i = active ? (a.rowid ? a.rowid[g] : g) : 0;
     if constexpr (OP == OP_SPMV_DOT) {
-        double c = 0.0;
-        if (active && lane < 3) {
+        double cd = 0.0;
+        if (ep) {
             const double sv = lane == 0 ? s0 : (lane == 1 ? s1 : s2);
             a.y[3 * i + lane] = sv;
-            c = a.x[3 * i + lane] * sv;
+            cd = own * sv;
         }
-        const double tot = block_sum(c);
+        const double tot = block_sum(cd);
         if (threadIdx.x == 0) a.partial[blockIdx.x] = tot;
         return;
     }
-    if (!active || lane >= 3) return;
-    const int c = lane;
+    if (!ep) return;
     const double sc = c == 0 ? s0 : (c == 1 ? s1 : s2);
+    if (a.zero_out) a.zero_out[3 * i + c] = 0.0;
     if constexpr (OP == OP_SPMV) {
         a.y[3 * i + c] = sc;
     } else if constexpr (OP == OP_SPMV_ADD) {
-        a.y[3 * i + c] += sc;
+        a.y[3 * i + c] = own + sc;
     } else if constexpr (OP == OP_RESID) {
-        a.y[3 * i + c] = a.b[3 * i + c] - sc;
+        a.y[3 * i + c] = (c == 0 ? b0 : (c == 1 ? b1 : b2)) - sc;
     } else {
-        const double r0 = a.b[3 * i] - s0, r1 = a.b[3 * i + 1] - s1, r2 = a.b[3 * i + 2] - s2;
+        const double r0 = b0 - s0, r1 = b1 - s1, r2 = b2 - s2;
         double d;
         if constexpr (MODE == 3) {
-            const double *D = a.dinv + i;
-            const int64_t dn = a.dinv_n;
-            d = D[(3 * c) * dn] * r0 + D[(3 * c + 1) * dn] * r1 + D[(3 * c + 2) * dn] * r2;
+            d = d0 * r0 + d1 * r1 + d2 * r2;
         } else {
-            d = a.dinv[i] * (c == 0 ? r0 : (c == 1 ? r1 : r2));
+            d = d0 * (c == 0 ? r0 : (c == 1 ? r1 : r2));
         }
         if constexpr (OP == OP_JACOBI) {
-            a.y[3 * i + c] = a.x[3 * i + c] + a.omega * d;
+            a.y[3 * i + c] = own + a.omega * d;
         } else {  // OP_GS: in place (a.y aliases a.x)
-            a.y[3 * i + c] += d;
+            a.y[3 * i + c] = own + d;
         }
     }
 }
@@ -174,6 +206,32 @@ void launch_copy(double *dst, const double *src, int64_t n, hipStream_t s) {
 }
 
 template <int MODE>
+__global__ void k_diag_solve(int nrows, const int *rowid, const double *dinv, int64_t n, const double *b,
+                             double *x) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * BLOCK + threadIdx.x;
+    if (t >= 3 * static_cast<int64_t>(nrows)) return;
+    const int i = rowid[t / 3];
+    const int c = static_cast<int>(t % 3);
+    if constexpr (MODE == 3) {
+        x[3 * i + c] = dinv[(3 * c) * n + i] * b[3 * i] + dinv[(3 * c + 1) * n + i] * b[3 * i + 1] +
+                       dinv[(3 * c + 2) * n + i] * b[3 * i + 2];
+    } else {
+        x[3 * i + c] = dinv[i] * b[3 * i + c];
+    }
+}
+
+void launch_diag_solve(int mode, int nrows, const int *rowid, const double *dinv, int64_t n, const double *b,
+                       double *x, hipStream_t s) {
+    if (nrows <= 0) return;
+    const int nb = ceil_div(3 * static_cast<int64_t>(nrows), BLOCK);
+    if (mode == 3)
+        k_diag_solve<3><<<nb, BLOCK, 0, s>>>(nrows, rowid, dinv, n, b, x);
+    else
+        k_diag_solve<1><<<nb, BLOCK, 0, s>>>(nrows, rowid, dinv, n, b, x);
+    AMG_CHECK_LAUNCH();
+}
+
+template <int MODE>
 __global__ void k_jacobi_zero(int64_t nn, const double *dinv, const double *b, double omega, double *x) {
     const int64_t t = static_cast<int64_t>(blockIdx.x) * BLOCK + threadIdx.x;
     if (t >= 3 * nn) return;
@@ -218,36 +276,42 @@ int launch_dot_partial(const double *a, const double *b, int64_t n, double *part
     return nb;
 }
 
-__global__ void k_reduce(const double *partial, int np, double *sc, int dst) {
+constexpr int RBLOCK = 1024;
+
+template <int POST>
+__global__ void __launch_bounds__(RBLOCK) k_reduce(const double *partial, int np, double *sc, int dst) {
     double acc = 0.0;
-    for (int i = threadIdx.x; i < np; i += BLOCK) acc += partial[i];
-    const double t = block_sum(acc);
-    if (threadIdx.x == 0) sc[dst] = t;
+    for (int i = threadIdx.x; i < np; i += RBLOCK) acc += partial[i];
+    const double t = block_sum<RBLOCK>(acc);
+    if (threadIdx.x != 0) return;
+    sc[dst] = t;
+    if constexpr (POST == RED_CG_ALPHA) {
+        sc[SC_ALPHA] = sc[SC_RZ] / t;
+    } else if constexpr (POST == RED_CG_BETA) {
+        sc[SC_BETA] = t / sc[SC_RZ];
+        sc[SC_RZ] = t;
+    } else if constexpr (POST == RED_FCG_BETA) {
+        sc[SC_BETA] = -t / sc[SC_RZ_OLD];
+    } else if constexpr (POST == RED_FCG_ALPHA) {
+        sc[SC_ALPHA] = t / sc[SC_PQ];
+        sc[SC_RZ_OLD] = sc[SC_PQ];
+    }
 }
 
-void launch_reduce(const double *partial, int np, double *sc, int dst, hipStream_t s) {
-    k_reduce<<<1, BLOCK, 0, s>>>(partial, np, sc, dst);
+void launch_reduce(const double *partial, int np, double *sc, int dst, hipStream_t s, int post) {
+    switch (post) {
+        case RED_NONE: k_reduce<RED_NONE><<<1, RBLOCK, 0, s>>>(partial, np, sc, dst); break;
+        case RED_CG_ALPHA: k_reduce<RED_CG_ALPHA><<<1, RBLOCK, 0, s>>>(partial, np, sc, dst); break;
+        case RED_CG_BETA: k_reduce<RED_CG_BETA><<<1, RBLOCK, 0, s>>>(partial, np, sc, dst); break;
+        case RED_FCG_BETA: k_reduce<RED_FCG_BETA><<<1, RBLOCK, 0, s>>>(partial, np, sc, dst); break;
+        case RED_FCG_ALPHA: k_reduce<RED_FCG_ALPHA><<<1, RBLOCK, 0, s>>>(partial, np, sc, dst); break;
+        default: throw Error(AMG_EINVAL, "reduce: unknown post operation");
+    }
     AMG_CHECK_LAUNCH();
 }
 
-__global__ void k_cg_alpha(double *sc) { sc[SC_ALPHA] = sc[SC_RZ] / sc[SC_PQ]; }
-__global__ void k_cg_beta(double *sc) {
-    sc[SC_BETA] = sc[SC_TMP] / sc[SC_RZ];
-    sc[SC_RZ] = sc[SC_TMP];
-}
-__global__ void k_fcg_beta(double *sc) { sc[SC_BETA] = -sc[SC_TMP] / sc[SC_RZ_OLD]; }
-__global__ void k_fcg_alpha(double *sc) {
-    sc[SC_ALPHA] = sc[SC_PR] / sc[SC_PQ];
-    sc[SC_RZ_OLD] = sc[SC_PQ];
-}
-
-void launch_cg_alpha(double *sc, hipStream_t s) { k_cg_alpha<<<1, 1, 0, s>>>(sc); AMG_CHECK_LAUNCH(); }
-void launch_cg_beta(double *sc, hipStream_t s) { k_cg_beta<<<1, 1, 0, s>>>(sc); AMG_CHECK_LAUNCH(); }
-void launch_fcg_beta(double *sc, hipStream_t s) { k_fcg_beta<<<1, 1, 0, s>>>(sc); AMG_CHECK_LAUNCH(); }
-void launch_fcg_alpha(double *sc, hipStream_t s) { k_fcg_alpha<<<1, 1, 0, s>>>(sc); AMG_CHECK_LAUNCH(); }
-
 __global__ void k_cg_update(double *x, double *r, const double *p, const double *q, const double *sc,
-                            int64_t n, double *partial) {
+                            int64_t n, double *partial, double *zero) {
     const double al = sc[SC_ALPHA];
     double acc = 0.0;
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * BLOCK + threadIdx.x; i < n;
@@ -256,15 +320,16 @@ __global__ void k_cg_update(double *x, double *r, const double *p, const double 
         const double ri = r[i] - al * q[i];
         r[i] = ri;
         acc += ri * ri;
+        if (zero) zero[i] = 0.0;
     }
     const double t = block_sum(acc);
     if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
 int launch_cg_update(double *x, double *r, const double *p, const double *q, const double *sc,
-                     int64_t n, double *partial, hipStream_t s) {
+                     int64_t n, double *partial, double *zero, hipStream_t s) {
     const int nb = dot_blocks(n);
-    k_cg_update<<<nb, BLOCK, 0, s>>>(x, r, p, q, sc, n, partial);
+    k_cg_update<<<nb, BLOCK, 0, s>>>(x, r, p, q, sc, n, partial, zero);
     AMG_CHECK_LAUNCH();
     return nb;
 }
@@ -302,7 +367,21 @@ __global__ void __launch_bounds__(BLOCK) k_dense_gemv(const double *M, int m, in
     if (row >= m) return;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
     const double *Mr = M + static_cast<int64_t>(row) * m;
-    for (int j = lane; j < m; j += 64) {
+    // four loads in flight per lane per trip
+    int j = lane;
+    for (; j + 192 < m; j += 256) {
+        const double v0 = Mr[j], v1 = Mr[j + 64], v2 = Mr[j + 128], v3 = Mr[j + 192];
+        if (nc == 1) {
+            a0 += v0 * X[j] + v1 * X[j + 64] + v2 * X[j + 128] + v3 * X[j + 192];
+        } else {
+            a0 += v0 * X[3 * j] + v1 * X[3 * (j + 64)] + v2 * X[3 * (j + 128)] + v3 * X[3 * (j + 192)];
+            a1 += v0 * X[3 * j + 1] + v1 * X[3 * (j + 64) + 1] + v2 * X[3 * (j + 128) + 1] +
+                  v3 * X[3 * (j + 192) + 1];
+            a2 += v0 * X[3 * j + 2] + v1 * X[3 * (j + 64) + 2] + v2 * X[3 * (j + 128) + 2] +
+                  v3 * X[3 * (j + 192) + 2];
+        }
+    }
+    for (; j < m; j += 64) {
         const double v = Mr[j];
         a0 += v * X[j * nc];
         if (nc > 1) {

@@ -38,6 +38,7 @@ struct RowArgs {
     int64_t dinv_n = 0;
     double omega = 1.0;
     double *partial = nullptr;      // per-block partial sums (SPMV_DOT)
+    double *zero_out = nullptr;     // if set: zero_out_i = 0 for every row i written
 };
 
 // mode: 3 = 3x3 blocks; 1 = scalar entries applied to 3-component vectors.
@@ -50,6 +51,10 @@ int row_blocks(int nrows, int G);
 // ---------------------------------------------------------------- vectors
 void launch_fill(double *x, double v, int64_t n, hipStream_t s);
 void launch_copy(double *dst, const double *src, int64_t n, hipStream_t s);
+// x_i = D_i^{-1} b_i for the nodes rowid[0..nrows) (first colour of a
+// Gauss-Seidel sweep from x = 0); dinv planes of stride n
+void launch_diag_solve(int mode, int nrows, const int *rowid, const double *dinv, int64_t n, const double *b,
+                       double *x, hipStream_t s);
 // x = omega D^{-1} b (first Jacobi step from x = 0)
 void launch_jacobi_zero(int mode, int64_t nnodes, const double *dinv, const double *b, double omega,
                         double *x, hipStream_t s);
@@ -61,16 +66,19 @@ int dot_blocks(int64_t n);
 enum Scalar : int {
     SC_RZ = 0, SC_PQ, SC_ALPHA, SC_BETA, SC_RR, SC_TMP, SC_RZ_OLD, SC_PR, SC_COUNT
 };
-// sum partial[0..np) into sc[dst] (fixed order: deterministic)
-void launch_reduce(const double *partial, int np, double *sc, int dst, hipStream_t s);
-// CG step scalars
-void launch_cg_alpha(double *sc, hipStream_t s);   // alpha = rz / pq
-void launch_cg_beta(double *sc, hipStream_t s);    // beta = rz_new / rz_old (rz_new in SC_TMP)
-void launch_fcg_beta(double *sc, hipStream_t s);   // beta = -<z,q_prev>/<p_prev,q_prev>
-void launch_fcg_alpha(double *sc, hipStream_t s);  // alpha = <p, r> / <p, q>
-// x += alpha p; r -= alpha q; partial of <r, r>
+// Sum partial[0..np) into sc[dst] in a fixed order (deterministic), then
+// derive the Krylov step scalars from it:
+enum ReducePost : int {
+    RED_NONE = 0,
+    RED_CG_ALPHA,   // dst = PQ:  alpha = rz / pq
+    RED_CG_BETA,    // dst = TMP: beta = tmp / rz, rz = tmp
+    RED_FCG_BETA,   // dst = TMP: beta = -tmp / pq_prev
+    RED_FCG_ALPHA,  // dst = PR:  alpha = pr / pq, pq_prev = pq
+};
+void launch_reduce(const double *partial, int np, double *sc, int dst, hipStream_t s, int post = RED_NONE);
+// x += alpha p; r -= alpha q; partial of <r, r>; zero[i] = 0 if zero != nullptr
 int launch_cg_update(double *x, double *r, const double *p, const double *q, const double *sc,
-                     int64_t n, double *partial, hipStream_t s);
+                     int64_t n, double *partial, double *zero, hipStream_t s);
 // p = z + beta p  (beta from sc)
 void launch_cg_direction(double *p, const double *z, const double *sc, int64_t n, hipStream_t s);
 // y = a x + b y with host scalars

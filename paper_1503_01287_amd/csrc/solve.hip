@@ -116,7 +116,10 @@ static void jacobi_step(amg_ctx *h, int l, const double *b, double *x, bool zero
     launch_copy(x, L.t.p, 3 * static_cast<int64_t>(L.n), h->stream);
 }
 
-static void gs_sweep(amg_ctx *h, int l, const double *b, double *x, bool forward) {
+// One block Gauss-Seidel sweep by colours. x_zero: x is zero on entry (and
+// its buffer holds the zeros), so the first colour's rows see only zero
+// neighbours: x_i = D_i^{-1} b_i without reading their matrix rows.
+static void gs_sweep(amg_ctx *h, int l, const double *b, double *x, bool forward, bool x_zero) {
     Level &L = h->lv[l];
     const int ncol = static_cast<int>(L.cptr.size()) - 1;
     const int nb = L.mode == 3 ? 9 : 1;
@@ -124,6 +127,11 @@ static void gs_sweep(amg_ctx *h, int l, const double *b, double *x, bool forward
         const int c = forward ? q : ncol - 1 - q;
         const int r0 = L.cptr[c], r1 = L.cptr[c + 1];
         if (r1 == r0) continue;
+        if (q == 0 && x_zero) {
+            ProfScope ps(h, tag("gs", l), (r1 - r0) * (4.0 + 48.0 + nb * 8.0));
+            launch_diag_solve(L.mode, r1 - r0, L.g_rowid.p + r0, L.dinv.p, L.n, b, x, h->stream);
+            continue;
+        }
         RowArgs a;
         a.nrows = r1 - r0;
         a.rowptr = L.Ag.rowptr.p + r0;
@@ -145,20 +153,19 @@ static void gs_sweep(amg_ctx *h, int l, const double *b, double *x, bool forward
     }
 }
 
-void smooth(amg_ctx *h, int l, const double *b, double *x, bool pre, bool zero_init) {
+// zero_init: x is zero on entry; filled: its buffer already holds the zeros
+void smooth(amg_ctx *h, int l, const double *b, double *x, bool pre, bool zero_init, bool filled) {
     const amg_params &p = h->prm;
     const int steps = pre ? p.pre : p.post;
     Level &L = h->lv[l];
+    const bool need_fill = zero_init && !filled && (steps == 0 || p.smoother != AMG_SMOOTH_JA);
+    if (need_fill) launch_fill(x, 0.0, 3 * static_cast<int64_t>(L.n), h->stream);
     for (int k = 0; k < steps; ++k) {
-        const bool z = zero_init && k == 0;
-        if (p.smoother == AMG_SMOOTH_JA) {
-            jacobi_step(h, l, b, x, z);
-        } else {
-            if (z) launch_fill(x, 0.0, 3 * static_cast<int64_t>(L.n), h->stream);
-            gs_sweep(h, l, b, x, pre);
-        }
+        if (p.smoother == AMG_SMOOTH_JA)
+            jacobi_step(h, l, b, x, zero_init && k == 0);
+        else
+            gs_sweep(h, l, b, x, pre, pre && zero_init && k == 0);
     }
-    if (steps == 0 && zero_init) launch_fill(x, 0.0, 3 * static_cast<int64_t>(L.n), h->stream);
 }
 
 static void coarse_solve(amg_ctx *h, const double *b, double *x) {
@@ -166,22 +173,46 @@ static void coarse_solve(amg_ctx *h, const double *b, double *x) {
     launch_dense_gemv(h->coarse_inv.p, h->coarse_m, h->coarse_nc, b, x, h->stream);
 }
 
-// Algorithm 1: AMG(K_l, x_l, b_l). x_zero says that x_l is zero on entry
-// (then the first smoothing step needs no operator pass for Jacobi).
-static void cycle(amg_ctx *h, int l, const double *b, double *x, bool x_zero) {
+static void run_dense_tail(amg_ctx *h, const double *b, double *x) {
+    ProfScope ps(h, "dense_tail", static_cast<double>(h->tail_m) * h->tail_m * 8.0);
+    launch_dense_gemv(h->tail_dense.p, h->tail_m, h->tail_nc, b, x, h->stream);
+}
+
+static void run_tail(amg_ctx *h, const double *b, double *x, bool x_zero) {
+    TailArgs a = h->tail_args;
+    a.b_in = b;
+    a.x_out = x;
+    a.x_in_zero = x_zero ? 1 : 0;
+    ProfScope ps(h, "tail", h->tail_bytes);
+    launch_tail(h->lv[0].mode, a, h->tail_lds, 1, h->stream);
+}
+
+// Algorithm 1: AMG(K_l, x_l, b_l). x_zero: x_l is zero on entry (the first
+// Jacobi step then needs no operator pass); filled: its buffer holds the zeros.
+static void cycle(amg_ctx *h, int l, const double *b, double *x, bool x_zero, bool filled) {
     Level &L = h->lv[l];
     if (L.coarsest) {
         coarse_solve(h, b, x);
         return;
     }
-    smooth(h, l, b, x, true, x_zero);
+    if (l == h->tail_start) {
+        run_tail(h, b, x, x_zero);
+        return;
+    }
+    if (l == h->dense_start && x_zero) {
+        run_dense_tail(h, b, x);
+        return;
+    }
+    smooth(h, l, b, x, true, x_zero, filled);
     residual(h, l, b, x, L.r.p);
     Level &C = h->lv[l + 1];
     {
+        // b_{l+1} = P^T r; the same pass zeroes x_{l+1} for the recursion
         RowArgs a = row_args(L.R);
         a.x = L.r.p;
         a.y = C.b.p;
-        ProfScope ps(h, tag("restrict", l), row_bytes(L.R, L.R.nnz, L.R.nrows) + 3.0 * (L.n + C.n) * 8.0);
+        a.zero_out = C.x.p;
+        ProfScope ps(h, tag("restrict", l), row_bytes(L.R, L.R.nnz, L.R.nrows) + 3.0 * (L.n + 2 * C.n) * 8.0);
         launch_row(1, OP_SPMV, L.Gr, a, h->stream);
     }
     if (C.coarsest) {
@@ -189,7 +220,7 @@ static void cycle(amg_ctx *h, int l, const double *b, double *x, bool x_zero) {
     } else {
         // x_{l+1} = 0, then nu recursive calls (nu = 1: V-cycle, 2: W-cycle)
         const int nu = std::max(1, h->prm.nu);
-        for (int k = 0; k < nu; ++k) cycle(h, l + 1, C.b.p, C.x.p, k == 0);
+        for (int k = 0; k < nu; ++k) cycle(h, l + 1, C.b.p, C.x.p, k == 0, k == 0);
     }
     {
         RowArgs a = row_args(L.P);
@@ -198,17 +229,20 @@ static void cycle(amg_ctx *h, int l, const double *b, double *x, bool x_zero) {
         ProfScope ps(h, tag("prolong", l), row_bytes(L.P, L.P.nnz, L.P.nrows) + 3.0 * (2.0 * L.n + C.n) * 8.0);
         launch_row(1, OP_SPMV_ADD, L.Gp, a, h->stream);
     }
-    smooth(h, l, b, x, false, false);
+    smooth(h, l, b, x, false, false, false);
 }
 
-void vcycle(amg_ctx *h, int l, const double *b, double *x) { cycle(h, l, b, x, true); }
+void vcycle(amg_ctx *h, int l, const double *b, double *x) { cycle(h, l, b, x, true, false); }
 
 // z = M^{-1} r: `cycles` successive applications of Algorithm 1 on the
 // finest level, the first from z = 0, each further one from the current z.
-void precondition(amg_ctx *h, const double *r, double *z) {
+// z_filled: z already holds zeros.
+static void precondition_impl(amg_ctx *h, const double *r, double *z, bool z_filled) {
     const int cyc = std::max(1, h->prm.cycles);
-    for (int k = 0; k < cyc; ++k) cycle(h, 0, r, z, k == 0);
+    for (int k = 0; k < cyc; ++k) cycle(h, 0, r, z, k == 0, k == 0 && z_filled);
 }
+
+void precondition(amg_ctx *h, const double *r, double *z) { precondition_impl(h, r, z, false); }
 
 }  // namespace amgp2
 
@@ -221,14 +255,14 @@ static double read_scalar(amg_ctx *h, int idx) {
     return h->h_sc[idx];
 }
 
-static void dot_into(amg_ctx *h, const double *a, const double *b, int dst) {
+static void dot_into(amg_ctx *h, const double *a, const double *b, int dst, int post = RED_NONE) {
     ProfScope ps(h, "blas", 2.0 * h->n_dof * 8.0);
     const int nb = launch_dot_partial(a, b, h->n_dof, h->partial.p, h->stream);
-    launch_reduce(h->partial.p, nb, h->sc.p, dst, h->stream);
+    launch_reduce(h->partial.p, nb, h->sc.p, dst, h->stream, post);
 }
 
 // q = A p on the finest level and <p, q> into sc[SC_PQ]
-static void spmv_dot(amg_ctx *h, const double *p, double *q) {
+static void spmv_dot(amg_ctx *h, const double *p, double *q, int post) {
     Level &L = h->lv[0];
     RowArgs a = row_args(L.A);
     a.x = p;
@@ -238,12 +272,14 @@ static void spmv_dot(amg_ctx *h, const double *p, double *q) {
         ProfScope ps(h, "spmv.L0", row_bytes(L.A, L.A.nnz, L.n) + 3.0 * L.n * 16.0);
         launch_row(L.mode, OP_SPMV_DOT, L.G, a, h->stream);
     }
-    launch_reduce(h->partial.p, row_blocks(L.n, L.G), h->sc.p, SC_PQ, h->stream);
+    launch_reduce(h->partial.p, row_blocks(L.n, L.G), h->sc.p, SC_PQ, h->stream, post);
 }
 
-static void cg_update(amg_ctx *h, double *x, double *r, const double *p, const double *q) {
-    ProfScope ps(h, "blas", 6.0 * h->n_dof * 8.0);
-    const int nb = launch_cg_update(x, r, p, q, h->sc.p, h->n_dof, h->partial.p, h->stream);
+// x += alpha p, r -= alpha q, <r, r> into sc[SC_RR]; zeroes z for the next
+// preconditioner application
+static void cg_update(amg_ctx *h, double *x, double *r, const double *p, const double *q, double *z) {
+    ProfScope ps(h, "blas", 7.0 * h->n_dof * 8.0);
+    const int nb = launch_cg_update(x, r, p, q, h->sc.p, h->n_dof, h->partial.p, z, h->stream);
     launch_reduce(h->partial.p, nb, h->sc.p, SC_RR, h->stream);
 }
 
@@ -292,17 +328,15 @@ int solve_pcg(amg_ctx *h, const double *b, double *x, double tol, int maxit, amg
     launch_copy(p, z, n, h->stream);
     int it = 0, status = AMG_NOT_CONVERGED;
     while (it < maxit) {
-        spmv_dot(h, p, q);
-        launch_cg_alpha(h->sc.p, h->stream);
-        cg_update(h, x, r, p, q);
+        spmv_dot(h, p, q, RED_CG_ALPHA);
+        cg_update(h, x, r, p, q, z);
         ++it;
         const double rr = read_scalar(h, SC_RR);
         if (!(h->h_sc[SC_PQ] > 0.0)) { status = AMG_BREAKDOWN; break; }
         const int c = check(rr, rr0, tol);
         if (c >= 0) { status = c; break; }
-        precondition(h, r, z);
-        dot_into(h, r, z, SC_TMP);
-        launch_cg_beta(h->sc.p, h->stream);
+        precondition_impl(h, r, z, true);
+        dot_into(h, r, z, SC_TMP, RED_CG_BETA);
         launch_cg_direction(p, z, h->sc.p, n, h->stream);
     }
     return finish(h, b, x, r0, it, status, t0, res);
@@ -320,19 +354,17 @@ int solve_fcg(amg_ctx *h, const double *b, double *x, double tol, int maxit, amg
     if (!(rr0 == rr0)) return finish(h, b, x, r0, 0, AMG_DIVERGED, t0, res);
     int it = 0, status = AMG_NOT_CONVERGED;
     while (it < maxit) {
-        precondition(h, r, z);
+        precondition_impl(h, r, z, it > 0);
         if (it == 0) {
             launch_copy(p, z, n, h->stream);
         } else {
             // p = z - (<z, q_prev> / <p_prev, q_prev>) p_prev
-            dot_into(h, z, q, SC_TMP);
-            launch_fcg_beta(h->sc.p, h->stream);
+            dot_into(h, z, q, SC_TMP, RED_FCG_BETA);
             launch_cg_direction(p, z, h->sc.p, n, h->stream);
         }
-        spmv_dot(h, p, q);
-        dot_into(h, p, r, SC_PR);
-        launch_fcg_alpha(h->sc.p, h->stream);
-        cg_update(h, x, r, p, q);
+        spmv_dot(h, p, q, RED_NONE);
+        dot_into(h, p, r, SC_PR, RED_FCG_ALPHA);
+        cg_update(h, x, r, p, q, z);
         ++it;
         const double rr = read_scalar(h, SC_RR);
         if (!(h->h_sc[SC_PQ] > 0.0)) { status = AMG_BREAKDOWN; break; }
@@ -354,7 +386,7 @@ int solve_stationary(amg_ctx *h, const double *b, double *x, double tol, int max
     int it = 0, status = AMG_NOT_CONVERGED;
     const int cyc = std::max(1, h->prm.cycles);
     while (it < maxit) {
-        for (int k = 0; k < cyc; ++k) cycle(h, 0, b, x, false);
+        for (int k = 0; k < cyc; ++k) cycle(h, 0, b, x, false, false);
         residual(h, 0, b, x, r);
         dot_into(h, r, r, SC_RR);
         ++it;

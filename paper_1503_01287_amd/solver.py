@@ -61,7 +61,8 @@ class AMGSolver:
                  precision: str = "FP64", cycles: int = 1, nu: int = 1, coarse_max: int = 300,
                  max_levels: int = 10, separate: bool = True, level_omega=None,
                  sgs_omega: float = 0.125, sgs_damping: float = 0.5, restart: int = 100,
-                 omega: float | None = None, stream=None):
+                 omega: float | None = None, fuse_coarse: bool = True, autotune: bool = True,
+                 stream=None):
         L = C.lib()
         p = C.default_params()
         sm = parse_smoother(smoother)
@@ -75,6 +76,8 @@ class AMGSolver:
         p.krylov = C.KRYLOV[krylov]
         p.restart = restart
         p.precision = C.PREC[precision]
+        p.fuse_coarse = 1 if fuse_coarse else 0
+        p.autotune = 1 if autotune else 0
         self._omega_buf = None
         if level_omega is not None:
             self._omega_buf = np.ascontiguousarray(level_omega, dtype=np.float64)

@@ -109,25 +109,42 @@ def test_smoother_step(case, smoother):
             assert rel(host(xd), ref.ravel()) < 1e-12, (name, smoother, l, fwd)
 
 
-@pytest.mark.parametrize("smoother", ["GS-1-1", "JA-1-1-0.5", "GS-2-2"])
-def test_vcycle(case, smoother):
+@pytest.mark.parametrize("fuse", [True, False])
+@pytest.mark.parametrize("smoother", ["GS-1-1", "JA-1-1-0.5", "GS-2-2", "JA-2-2-0.5"])
+def test_vcycle(case, smoother, fuse):
+    """One preconditioner application; fuse=True runs the smallest levels in
+    the single-workgroup tail kernel, fuse=False launches every operation."""
     name, hsys, o = case
-    s = amg.AMGSolver(hsys, smoother=smoother)
+    s = amg.AMGSolver(hsys, smoother=smoother, fuse_coarse=fuse)
     h = _oracle_hierarchy(o)
     prec = oamg.preconditioner(h, oamg.Smoother.parse(smoother))
     r = np.random.default_rng(13).standard_normal(hsys.dofs)
     z = torch.zeros(hsys.dofs, dtype=torch.float64, device=DEV)
     s.precondition(dev(r), z)
-    assert rel(host(z), prec(r).ravel()) < 1e-11, (name, smoother)
+    assert rel(host(z), prec(r).ravel()) < 1e-11, (name, smoother, fuse)
 
 
-@pytest.mark.parametrize("smoother,kry", [("GS-1-1", "PCG"), ("JA-1-1-0.5", "PCG"), ("GS-1-1", "FCG"),
-                                          ("GS-1-1", "NONE")])
-def test_solve_matches_oracle(case, smoother, kry):
+@pytest.mark.parametrize("cycles,nu", [(2, 1), (1, 2), (2, 2)])
+def test_multiple_cycles_and_w_cycle(case, cycles, nu):
+    """'2 V-cycles' per preconditioner application and the W-cycle (nu = 2)."""
+    name, hsys, o = case
+    s = amg.AMGSolver(hsys, smoother="GS-1-1", cycles=cycles, nu=nu)
+    h = _oracle_hierarchy(o)
+    prec = oamg.preconditioner(h, oamg.Smoother.parse("GS-1-1"), cycles=cycles, nu=nu)
+    r = np.random.default_rng(14).standard_normal(hsys.dofs)
+    z = torch.zeros(hsys.dofs, dtype=torch.float64, device=DEV)
+    s.precondition(dev(r), z)
+    assert rel(host(z), prec(r).ravel()) < 1e-11, (name, cycles, nu)
+
+
+@pytest.mark.parametrize("smoother,kry,fuse", [("GS-1-1", "PCG", True), ("GS-1-1", "PCG", False),
+                                               ("JA-1-1-0.5", "PCG", True), ("GS-1-1", "FCG", True),
+                                               ("GS-1-1", "NONE", True)])
+def test_solve_matches_oracle(case, smoother, kry, fuse):
     name, hsys, o = case
     # the stand-alone iteration contracts by ~0.95 per cycle on elasticity
     tol = 1e-10 if kry != "NONE" else 1e-8
-    s = amg.AMGSolver(hsys, smoother=smoother, krylov=kry)
+    s = amg.AMGSolver(hsys, smoother=smoother, krylov=kry, fuse_coarse=fuse)
     b = dev(hsys.rhs)
     x = torch.zeros_like(b)
     res = s.solve(b, x, tol=tol, maxit=1000)
