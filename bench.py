@@ -94,6 +94,9 @@ def main() -> int:
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the event-timed pass")
+    ap.add_argument("--precision", default="MIXED", choices=["MIXED", "FP32", "FP64"],
+                    help="cycle arithmetic of the timed solve (FP64 outer loop always); "
+                         "the FP64 PCG solve is timed beside it for comparison")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -110,80 +113,106 @@ def main() -> int:
     print(f"# assembled {sysm.name}: {sysm.dofs} DOF in {t_asm:.1f}s", file=sys.stderr, flush=True)
 
     dev = torch.device("cuda:0")
-    stream = torch.cuda.current_stream(dev)
     b = torch.from_numpy(sysm.rhs).to(dev)
     x = torch.zeros_like(b)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    solver = amg.AMGSolver(sysm, smoother=wl["smoother"], krylov="PCG", precision="FP64")
-    torch.cuda.synchronize()
-    setup_ms = (time.perf_counter() - t0) * 1e3
-    levels = []
-    for l in range(solver.num_levels):
-        i = solver.level_info(l)
-        levels.append(dict(nodes=i.n_lin + i.n_quad, nnz=int(i.nnz_A), colors=int(i.n_colors),
-                           lanes=[int(i.lanes_A), int(i.lanes_gs)], fused=bool(i.fused)))
-    print(f"# setup {setup_ms:.0f} ms, levels {levels}", file=sys.stderr, flush=True)
 
-    def step():
-        x.zero_()
-        return solver.solve(b, x, tol=args.tol, maxit=1000)
-
-    for _ in range(args.warmup):
-        r = step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    results = [step() for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    bad = [r for r in results if not (r.converged and r.relres <= args.tol * 1.0001)]
-    if bad:
-        print(f"# solve did not converge: {bad[0]}", file=sys.stderr)
-        return 1
-    ms = elapsed * 1e3 / args.steps
-    value = sysm.dofs * args.steps / elapsed
-    iters = results[-1].iters
-    print(f"# {args.steps} solves: {ms:.2f} ms/solve, {iters} iterations, relres {results[-1].relres:.2e}",
-          file=sys.stderr, flush=True)
-
-    roofline = None
-    vcycle = None
-    if not args.no_profile:
-        # the same steps again with HIP events around every finest-level launch
-        solver.profile(2)
+    def run_variant(precision: str, krylov: str, profile: bool) -> dict:
+        """amg_setup (timed once), W warm-up and K timed solves; optionally
+        the same K solves again with HIP events on the finest level."""
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(args.steps):
+        solver = amg.AMGSolver(sysm, smoother=wl["smoother"], krylov=krylov, precision=precision)
+        torch.cuda.synchronize()
+        setup_ms = (time.perf_counter() - t0) * 1e3
+        levels = []
+        for l in range(solver.num_levels):
+            i = solver.level_info(l)
+            levels.append(dict(nodes=i.n_lin + i.n_quad, nnz=int(i.nnz_A), colors=int(i.n_colors),
+                               lanes=[int(i.lanes_A), int(i.lanes_gs)], fused=bool(i.fused)))
+        print(f"# {precision}/{krylov} setup {setup_ms:.0f} ms, levels {levels}", file=sys.stderr, flush=True)
+
+        def step():
+            x.zero_()
+            return solver.solve(b, x, tol=args.tol, maxit=1000)
+
+        for _ in range(args.warmup):
             step()
         torch.cuda.synchronize()
-        prof_ms = (time.perf_counter() - t0) * 1e3 / args.steps
-        classes = ["gs.L0", "resid.L0", "spmv.L0", "jacobi.L0", "jacobi0.L0", "restrict.L0", "prolong.L0"]
-        stats = {c: solver.profile_read(c) for c in classes}
-        solver.profile(0)
-        stats = {c: s for c, s in stats.items() if s["launches"] > 0}
-        dom = max(stats, key=lambda c: stats[c]["ms"])
-        s = stats[dom]
-        per_launch_bytes = s["bytes"] / s["launches"]
-        per_launch_ms = s["ms"] / s["launches"]
-        achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
-        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                    "kernel": dom, "launches_per_step": s["launches"] // args.steps,
-                    "bytes_per_launch": per_launch_bytes, "mean_launch_us": round(per_launch_ms * 1e3, 2),
-                    "profiled_ms_per_step": round(prof_ms, 2)}
-        tot_b = sum(v["bytes"] for v in stats.values())
-        tot_ms = sum(v["ms"] for v in stats.values())
-        vcycle = {"finest_level_GBps": round(tot_b / (tot_ms * 1e-3) / 1e9, 1),
-                  "finest_level_ms_per_step": round(tot_ms / args.steps, 3),
-                  "per_class": {c: {"launches_per_step": v["launches"] // args.steps,
-                                    "ms_per_step": round(v["ms"] / args.steps, 3),
-                                    "GBps": round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 1)}
-                                for c, v in stats.items()}}
+        t0 = time.perf_counter()
+        results = [step() for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        bad = [r for r in results if not (r.converged and r.relres <= args.tol * 1.0001)]
+        if bad:
+            raise SystemExit(f"# {precision}/{krylov}: solve did not converge: {bad[0]}")
+        ms = elapsed * 1e3 / args.steps
+        sol = x.clone()
+        out = dict(precision=precision, krylov=krylov, setup_ms=round(setup_ms, 1), ms_per_step=round(ms, 3),
+                   value=sysm.dofs * args.steps / elapsed, iterations=results[-1].iters,
+                   relres=results[-1].relres, levels=levels, solution=sol)
+        print(f"# {precision}/{krylov}: {args.steps} solves, {ms:.2f} ms/solve, {results[-1].iters} iterations, "
+              f"relres {results[-1].relres:.2e}", file=sys.stderr, flush=True)
+        if profile:
+            solver.profile(2)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                step()
+            torch.cuda.synchronize()
+            prof_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+            classes = ["gs.L0", "resid.L0", "spmv.L0", "jacobi.L0", "jacobi0.L0", "restrict.L0", "prolong.L0"]
+            stats = {c: solver.profile_read(c) for c in classes}
+            solver.profile(0)
+            stats = {c: v for c, v in stats.items() if v["launches"] > 0}
+            dom = max(stats, key=lambda c: stats[c]["ms"])
+            st = stats[dom]
+            per_launch_bytes = st["bytes"] / st["launches"]
+            per_launch_ms = st["ms"] / st["launches"]
+            achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
+            out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                               "kernel": dom, "launches_per_step": st["launches"] // args.steps,
+                               "bytes_per_launch": per_launch_bytes,
+                               "mean_launch_us": round(per_launch_ms * 1e3, 2),
+                               "profiled_ms_per_step": round(prof_ms, 2)}
+            tot_b = sum(v["bytes"] for v in stats.values())
+            tot_ms = sum(v["ms"] for v in stats.values())
+            out["vcycle_bandwidth"] = {
+                "finest_level_GBps": round(tot_b / (tot_ms * 1e-3) / 1e9, 1),
+                "finest_level_ms_per_step": round(tot_ms / args.steps, 3),
+                "per_class": {c: {"launches_per_step": v["launches"] // args.steps,
+                                  "ms_per_step": round(v["ms"] / args.steps, 3),
+                                  "GBps": round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 1)}
+                              for c, v in stats.items()}}
+        solver.close()
+        return out
+
+    primary_kry = "PCG" if args.precision == "FP64" else "FCG"
+    prim = run_variant(args.precision, primary_kry, not args.no_profile)
+    comp = run_variant("FP64", "PCG", False) if args.precision != "FP64" else None
+    # reference solution for the error of each variant: FP64 PCG to 1e-12 (untimed)
+    ref_solver = amg.AMGSolver(sysm, smoother=wl["smoother"], krylov="PCG", precision="FP64")
+    x.zero_()
+    ref_res = ref_solver.solve(b, x, tol=1e-12, maxit=2000)
+    ref = x.clone()
+    ref_solver.close()
+
+    def err(v):
+        return float(torch.linalg.norm(v["solution"] - ref) / torch.linalg.norm(ref))
+
+    prim["error_vs_fp64_reference"] = err(prim)
+    if comp:
+        comp["error_vs_fp64_reference"] = err(comp)
+    ms, value, iters = prim["ms_per_step"], prim["value"], prim["iterations"]
+    roofline = prim.get("roofline")
+    vcycle = prim.get("vcycle_bandwidth")
+    setup_ms, levels = prim["setup_ms"], prim["levels"]
+    results_relres = prim["relres"]
 
     cpu = None
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
-        cpu = cpu_baseline(args.workload, iters, args.tol)
+        cpu = cpu_baseline(args.workload, comp["iterations"] if comp else iters, args.tol)
         print(f"# cpu baseline {time.perf_counter() - t0:.0f}s: {cpu['value']:.3g} DOF-solves/s",
               file=sys.stderr, flush=True)
 
@@ -198,18 +227,24 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "FP64" else
+                 ("f32 cycle, f64 outer" if args.precision == "FP32" else "f32/bf16 cycle, f64 outer"),
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {wl['desc']}", "dofs": sysm.dofs,
-                   "smoother": wl["smoother"], "krylov": "PCG", "precision": "FP64", "tol": args.tol,
-                   "iterations": iters, "relres": results[-1].relres, "setup_ms": round(setup_ms, 1),
-                   "levels": levels, "parallelism": "single GPU"},
+                   "smoother": wl["smoother"], "krylov": primary_kry, "precision": args.precision,
+                   "tol": args.tol, "iterations": iters, "relres": results_relres,
+                   "error_vs_fp64_reference": prim["error_vs_fp64_reference"],
+                   "setup_ms": round(setup_ms, 1), "levels": levels, "parallelism": "single GPU"},
+        "fp64_comparison": None if comp is None else {
+            k: (float(f"{v:.6g}") if isinstance(v, float) else v) for k, v in comp.items()
+            if k in ("precision", "krylov", "ms_per_step", "value", "iterations", "relres", "setup_ms",
+                     "error_vs_fp64_reference")},
+        "reference": {"krylov": "PCG", "precision": "FP64", "tol": 1e-12, "iterations": ref_res.iters},
         "roofline": roofline,
         "vcycle_bandwidth": vcycle,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
-    solver.close()
     return 0
 
 

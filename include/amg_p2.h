@@ -73,7 +73,9 @@ typedef void *amg_stream; /* hipStream_t */
 #define AMG_PREC_FP64 0  /* every level in FP64                               */
 #define AMG_PREC_MIXED 1 /* FP32 cycle vectors, FP32 finest operator, BF16
                             coarse operators with per-row FP32 scales; outer
-                            Krylov loop, its dots and the coarsest solve FP64 */
+                            Krylov loop, its dots and the coarsest solve FP64.
+                            Use a flexible outer method (FCG or FGMRES).      */
+#define AMG_PREC_FP32 2  /* as AMG_PREC_MIXED with every operator in FP32    */
 
 /*
  * The linear system (Section 2.4). All pointers are HOST pointers; the

@@ -20,7 +20,7 @@ AMG_OK, AMG_NOT_CONVERGED, AMG_BREAKDOWN, AMG_DIVERGED = 0, 1, 2, 3
 AMG_EINVAL, AMG_EHIP, AMG_ENOMEM, AMG_EUNSUPPORTED = -1, -2, -3, -4
 SMOOTH = {"JA": 0, "GS": 1, "SGS": 2, "BS": 3}
 KRYLOV = {"PCG": 0, "FCG": 1, "FGMRES": 2, "NONE": 3}
-PREC = {"FP64": 0, "MIXED": 1}
+PREC = {"FP64": 0, "MIXED": 1, "FP32": 2}
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _f64p = ctypes.POINTER(ctypes.c_double)

@@ -72,7 +72,8 @@ int amg_setup(const amg_system *sys, const amg_params *params, amg_stream stream
                     "amg_setup: smoother not available for SPD systems");
         AMG_REQUIRE(p.pre >= 0 && p.post >= 0 && p.cycles >= 1 && p.nu >= 1 && p.nu <= 2, AMG_EINVAL,
                     "amg_setup: invalid smoothing/cycle counts");
-        AMG_REQUIRE(p.precision == AMG_PREC_FP64, AMG_EUNSUPPORTED, "amg_setup: precision mode");
+        AMG_REQUIRE(p.precision == AMG_PREC_FP64 || p.precision == AMG_PREC_MIXED || p.precision == AMG_PREC_FP32,
+                    AMG_EINVAL, "amg_setup: unknown precision mode");
         auto *h = new amg_ctx();
         h->prm = p;
         h->prm.level_omega = nullptr;

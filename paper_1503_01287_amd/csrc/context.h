@@ -8,6 +8,7 @@
 #include "common.h"
 #include "host_setup.h"
 #include "kernels.h"
+#include "mixed.h"
 #include "tail.h"
 
 namespace amgp2 {
@@ -19,6 +20,20 @@ struct DMat {
     int np = 1;  // planes per entry: 9 (3x3), 3 (1x3 / 3x1), 1 (scalar)
     DevBuf<int> rowptr, col;
     DevBuf<double> val;
+};
+
+// Reduced-precision copy of a level for the mixed-precision cycle.
+struct LevelMP {
+    int kind = VAL_F32;            // value kind of A and its grouped copy
+    DevBuf<float> a32, ag32;       // FP32 planes
+    DevBuf<uint16_t> a16, ag16;    // BF16 planes (values / row scale)
+    DevBuf<float> scale;           // BF16: scale of every scalar row
+    DevBuf<float> dinv;            // FP32 inverted diagonal blocks
+    DevBuf<float> pval, rval;      // FP32 transfer weights
+    DevBuf<float> x, b, r, t;      // FP32 work vectors
+    const void *aval() const { return kind == VAL_F32 ? static_cast<const void *>(a32.p) : a16.p; }
+    const void *agval() const { return kind == VAL_F32 ? static_cast<const void *>(ag32.p) : ag16.p; }
+    int vbytes() const { return kind == VAL_F32 ? 4 : 2; }
 };
 
 struct Level {
@@ -41,6 +56,7 @@ struct Level {
     // work vectors (3n doubles each)
     DevBuf<double> x, b, r, t;
     int G = 16, Gg = 16, Gp = 4, Gr = 8;  // lanes per row: A, grouped A, P, R
+    LevelMP mp;               // mixed-precision copy (AMG_PREC_MIXED / FP32)
 };
 
 struct ProfStat {
@@ -71,6 +87,9 @@ struct amg_ctx {
     int dense_start = -1;
     amgp2::DevBuf<double> tail_dense;
     int tail_m = 0, tail_nc = 1;
+    // reduced-precision cycle (precision != AMG_PREC_FP64)
+    bool mixed = false;
+    amgp2::DevBuf<float> tail_dense32;
     // Krylov workspace
     amgp2::DevBuf<double> kr, kz, kp, kq, kw;
     amgp2::DevBuf<double> partial, sc;
@@ -93,6 +112,8 @@ struct amg_ctx {
 namespace amgp2 {
 
 void build_hierarchy(amg_ctx *h, const amg_system *sys);
+void build_mixed(amg_ctx *h);
+void precondition_mp(amg_ctx *h, const double *r, double *z);
 void vcycle(amg_ctx *h, int l, const double *b, double *x);
 void precondition(amg_ctx *h, const double *r, double *z);
 void apply_level(amg_ctx *h, int l, const double *x, double *y);

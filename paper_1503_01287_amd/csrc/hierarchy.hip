@@ -453,6 +453,7 @@ void build_hierarchy(amg_ctx *h, const amg_system *sys) {
     }
     setup_coarsest(h, h->lv.back());
     setup_tail(h);
+    build_mixed(h);
     h->n_dof = 3 * h->lv[0].n;
     const size_t nd = static_cast<size_t>(h->n_dof);
     h->kr.alloc(nd);

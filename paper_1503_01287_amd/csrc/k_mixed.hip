@@ -1,0 +1,344 @@
+// Kernels of the mixed-precision cycle: the row kernels of k_row.hip on FP32
+// vectors with FP32 or BF16 (+ per-row FP32 scale) operator values, and the
+// conversions that build those copies. A 3x3 block costs 40 bytes in FP32
+// and 22 bytes in BF16 (76 in FP64), so the bandwidth-bound passes move
+// 1.9x / 3.5x fewer bytes.
+#include "common.h"
+#include "kernels.h"
+#include "mixed.h"
+
+namespace amgp2 {
+
+constexpr int MBLOCK = 256;
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t v) { return __uint_as_float(static_cast<uint32_t>(v) << 16); }
+
+// round to nearest even
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;  // NaN
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return static_cast<uint16_t>(u >> 16);
+}
+
+template <int G>
+__device__ __forceinline__ float group_sum_f(float v) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
+    return v;
+}
+
+template <int KIND>
+__device__ __forceinline__ float ld(const void *p, int64_t idx) {
+    if constexpr (KIND == VAL_F32)
+        return static_cast<const float *>(p)[idx];
+    else
+        return bf16_to_f32(static_cast<const uint16_t *>(p)[idx]);
+}
+
+template <int MODE, int G, int OP, int KIND>
+__global__ void __launch_bounds__(MBLOCK) k_row_mp(const RowArgsMP a) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * MBLOCK + threadIdx.x;
+    const int g = static_cast<int>(t / G);
+    const int lane = static_cast<int>(t % G);
+    const bool active = g < a.nrows;
+    const int i = active ? (a.rowid ? a.rowid[g] : g) : 0;
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+    if (active) {
+        const int beg = a.rowptr[g], end = a.rowptr[g + 1];
+        const int64_t nz = a.nnz;
+        for (int k = beg + lane; k < end; k += G) {
+            const int j = a.col[k];
+            const float x0 = a.x[3 * j], x1 = a.x[3 * j + 1], x2 = a.x[3 * j + 2];
+            if constexpr (MODE == 3) {
+                s0 += ld<KIND>(a.val, k) * x0 + ld<KIND>(a.val, nz + k) * x1 + ld<KIND>(a.val, 2 * nz + k) * x2;
+                s1 += ld<KIND>(a.val, 3 * nz + k) * x0 + ld<KIND>(a.val, 4 * nz + k) * x1 +
+                      ld<KIND>(a.val, 5 * nz + k) * x2;
+                s2 += ld<KIND>(a.val, 6 * nz + k) * x0 + ld<KIND>(a.val, 7 * nz + k) * x1 +
+                      ld<KIND>(a.val, 8 * nz + k) * x2;
+            } else {
+                const float v = ld<KIND>(a.val, k);
+                s0 += v * x0;
+                s1 += v * x1;
+                s2 += v * x2;
+            }
+        }
+    }
+    s0 = group_sum_f<G>(s0);
+    s1 = group_sum_f<G>(s1);
+    s2 = group_sum_f<G>(s2);
+    if (!active || lane >= 3) return;
+    if constexpr (KIND == VAL_BF16) {
+        if constexpr (MODE == 3) {
+            s0 *= a.rscale[3 * i];
+            s1 *= a.rscale[3 * i + 1];
+            s2 *= a.rscale[3 * i + 2];
+        } else {
+            const float sc = a.rscale[i];
+            s0 *= sc;
+            s1 *= sc;
+            s2 *= sc;
+        }
+    }
+    const int c = lane;
+    const float sc = c == 0 ? s0 : (c == 1 ? s1 : s2);
+    if (a.zero_out) a.zero_out[3 * i + c] = 0.f;
+    if constexpr (OP == OP_SPMV) {
+        a.y[3 * i + c] = sc;
+    } else if constexpr (OP == OP_SPMV_ADD) {
+        a.y[3 * i + c] += sc;
+    } else if constexpr (OP == OP_RESID) {
+        a.y[3 * i + c] = a.b[3 * i + c] - sc;
+    } else {
+        const float r0 = a.b[3 * i] - s0, r1 = a.b[3 * i + 1] - s1, r2 = a.b[3 * i + 2] - s2;
+        float d;
+        if constexpr (MODE == 3) {
+            const float *D = a.dinv + i;
+            const int64_t dn = a.dinv_n;
+            d = D[(3 * c) * dn] * r0 + D[(3 * c + 1) * dn] * r1 + D[(3 * c + 2) * dn] * r2;
+        } else {
+            d = a.dinv[i] * (c == 0 ? r0 : (c == 1 ? r1 : r2));
+        }
+        if constexpr (OP == OP_JACOBI)
+            a.y[3 * i + c] = a.x[3 * i + c] + a.omega * d;
+        else
+            a.y[3 * i + c] += d;
+    }
+}
+
+template <int MODE, int G, int KIND>
+static void launch_mp_g(int op, const RowArgsMP &a, hipStream_t s) {
+    const int nb = ceil_div(static_cast<int64_t>(a.nrows) * G, MBLOCK);
+    if (nb == 0) return;
+    switch (op) {
+        case OP_SPMV: k_row_mp<MODE, G, OP_SPMV, KIND><<<nb, MBLOCK, 0, s>>>(a); break;
+        case OP_SPMV_ADD: k_row_mp<MODE, G, OP_SPMV_ADD, KIND><<<nb, MBLOCK, 0, s>>>(a); break;
+        case OP_RESID: k_row_mp<MODE, G, OP_RESID, KIND><<<nb, MBLOCK, 0, s>>>(a); break;
+        case OP_JACOBI: k_row_mp<MODE, G, OP_JACOBI, KIND><<<nb, MBLOCK, 0, s>>>(a); break;
+        case OP_GS: k_row_mp<MODE, G, OP_GS, KIND><<<nb, MBLOCK, 0, s>>>(a); break;
+        default: throw Error(AMG_EINVAL, "mixed row kernel: unsupported operation");
+    }
+    AMG_CHECK_LAUNCH();
+}
+
+template <int MODE, int KIND>
+static void launch_mp_m(int op, int G, const RowArgsMP &a, hipStream_t s) {
+    switch (G) {
+        case 4: launch_mp_g<MODE, 4, KIND>(op, a, s); break;
+        case 8: launch_mp_g<MODE, 8, KIND>(op, a, s); break;
+        case 16: launch_mp_g<MODE, 16, KIND>(op, a, s); break;
+        case 32: launch_mp_g<MODE, 32, KIND>(op, a, s); break;
+        case 64: launch_mp_g<MODE, 64, KIND>(op, a, s); break;
+        default: throw Error(AMG_EINVAL, "mixed row kernel: unsupported group size");
+    }
+}
+
+void launch_row_mp(int mode, int op, int G, int kind, const RowArgsMP &a, hipStream_t s) {
+    if (mode == 3) {
+        if (kind == VAL_F32) launch_mp_m<3, VAL_F32>(op, G, a, s);
+        else launch_mp_m<3, VAL_BF16>(op, G, a, s);
+    } else {
+        if (kind == VAL_F32) launch_mp_m<1, VAL_F32>(op, G, a, s);
+        else launch_mp_m<1, VAL_BF16>(op, G, a, s);
+    }
+}
+
+// ---------------------------------------------------------------- conversions
+static int grid_n(int64_t n) {
+    int64_t nb = (n + MBLOCK - 1) / MBLOCK;
+    if (nb > 8192) nb = 8192;
+    return static_cast<int>(nb < 1 ? 1 : nb);
+}
+
+__global__ void k_to_f32(const double *src, float *dst, int64_t n) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * MBLOCK + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * MBLOCK)
+        dst[i] = static_cast<float>(src[i]);
+}
+__global__ void k_to_f64(const float *src, double *dst, int64_t n) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * MBLOCK + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * MBLOCK)
+        dst[i] = static_cast<double>(src[i]);
+}
+__global__ void k_fill_f32(float *x, float v, int64_t n) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * MBLOCK + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * MBLOCK)
+        x[i] = v;
+}
+__global__ void k_copy_f32(float *d, const float *src, int64_t n) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * MBLOCK + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * MBLOCK)
+        d[i] = src[i];
+}
+
+void launch_to_f32(const double *src, float *dst, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    k_to_f32<<<grid_n(n), MBLOCK, 0, s>>>(src, dst, n);
+    AMG_CHECK_LAUNCH();
+}
+void launch_to_f64(const float *src, double *dst, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    k_to_f64<<<grid_n(n), MBLOCK, 0, s>>>(src, dst, n);
+    AMG_CHECK_LAUNCH();
+}
+void launch_fill_f32(float *x, float v, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    k_fill_f32<<<grid_n(n), MBLOCK, 0, s>>>(x, v, n);
+    AMG_CHECK_LAUNCH();
+}
+void launch_copy_f32(float *dst, const float *src, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    k_copy_f32<<<grid_n(n), MBLOCK, 0, s>>>(dst, src, n);
+    AMG_CHECK_LAUNCH();
+}
+void launch_planes_f32(const double *src, float *dst, int64_t count, hipStream_t s) {
+    launch_to_f32(src, dst, count, s);
+}
+
+template <int MODE>
+__global__ void k_row_scales(int n, const int *rowptr, const int *col, const double *val, int64_t nnz,
+                             float *scale) {
+    const int i = blockIdx.x * MBLOCK + threadIdx.x;
+    if (i >= n) return;
+    int kd = -1;
+    for (int k = rowptr[i]; k < rowptr[i + 1]; ++k)
+        if (col[k] == i) { kd = k; break; }
+    for (int r = 0; r < MODE; ++r) {
+        double d = kd >= 0 ? fabs(val[static_cast<int64_t>(r * MODE + r) * nnz + kd]) : 0.0;
+        if (d == 0.0) {
+            // no usable diagonal: the row's largest magnitude
+            for (int k = rowptr[i]; k < rowptr[i + 1]; ++k)
+                for (int c = 0; c < MODE; ++c) d = fmax(d, fabs(val[static_cast<int64_t>(r * MODE + c) * nnz + k]));
+            if (d == 0.0) d = 1.0;
+        }
+        scale[MODE * i + r] = static_cast<float>(d);
+    }
+}
+
+void launch_row_scales(int mode, int n, const int *rowptr, const int *col, const double *val, int64_t nnz,
+                       float *scale, hipStream_t s) {
+    if (n <= 0) return;
+    if (mode == 3)
+        k_row_scales<3><<<ceil_div(n, MBLOCK), MBLOCK, 0, s>>>(n, rowptr, col, val, nnz, scale);
+    else
+        k_row_scales<1><<<ceil_div(n, MBLOCK), MBLOCK, 0, s>>>(n, rowptr, col, val, nnz, scale);
+    AMG_CHECK_LAUNCH();
+}
+
+// one wavefront per row: entry k of (grouped) row g belongs to node rowid[g]
+template <int MODE>
+__global__ void k_planes_bf16(int nrows, const int *rowptr, const int *rowid, const double *src, int64_t nnz,
+                              const float *scale, uint16_t *dst) {
+    const int g = blockIdx.x * (MBLOCK / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (g >= nrows) return;
+    const int i = rowid ? rowid[g] : g;
+    for (int k = rowptr[g] + lane; k < rowptr[g + 1]; k += 64) {
+#pragma unroll
+        for (int p = 0; p < MODE * MODE; ++p) {
+            const int r = p / MODE;
+            const double v = src[static_cast<int64_t>(p) * nnz + k] / static_cast<double>(scale[MODE * i + r]);
+            dst[static_cast<int64_t>(p) * nnz + k] = f32_to_bf16(static_cast<float>(v));
+        }
+    }
+}
+
+void launch_planes_bf16(int mode, int nrows, const int *rowptr, const int *rowid, const double *src, int64_t nnz,
+                        const float *scale, uint16_t *dst, hipStream_t s) {
+    if (nrows <= 0) return;
+    const int nb = ceil_div(nrows, MBLOCK / 64);
+    if (mode == 3)
+        k_planes_bf16<3><<<nb, MBLOCK, 0, s>>>(nrows, rowptr, rowid, src, nnz, scale, dst);
+    else
+        k_planes_bf16<1><<<nb, MBLOCK, 0, s>>>(nrows, rowptr, rowid, src, nnz, scale, dst);
+    AMG_CHECK_LAUNCH();
+}
+
+template <int MODE>
+__global__ void k_jacobi_zero_mp(int64_t nn, const float *dinv, const float *b, float omega, float *x) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * MBLOCK + threadIdx.x;
+    if (t >= 3 * nn) return;
+    const int64_t i = t / 3;
+    const int c = static_cast<int>(t % 3);
+    float d;
+    if constexpr (MODE == 3)
+        d = dinv[(3 * c) * nn + i] * b[3 * i] + dinv[(3 * c + 1) * nn + i] * b[3 * i + 1] +
+            dinv[(3 * c + 2) * nn + i] * b[3 * i + 2];
+    else
+        d = dinv[i] * b[t];
+    x[t] = omega * d;
+}
+
+void launch_jacobi_zero_mp(int mode, int64_t nn, const float *dinv, const float *b, float omega, float *x,
+                           hipStream_t s) {
+    if (nn <= 0) return;
+    const int nb = ceil_div(3 * nn, MBLOCK);
+    if (mode == 3)
+        k_jacobi_zero_mp<3><<<nb, MBLOCK, 0, s>>>(nn, dinv, b, omega, x);
+    else
+        k_jacobi_zero_mp<1><<<nb, MBLOCK, 0, s>>>(nn, dinv, b, omega, x);
+    AMG_CHECK_LAUNCH();
+}
+
+template <int MODE>
+__global__ void k_diag_solve_mp(int nrows, const int *rowid, const float *dinv, int64_t n, const float *b, float *x) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * MBLOCK + threadIdx.x;
+    if (t >= 3 * static_cast<int64_t>(nrows)) return;
+    const int i = rowid[t / 3];
+    const int c = static_cast<int>(t % 3);
+    if constexpr (MODE == 3)
+        x[3 * i + c] = dinv[(3 * c) * n + i] * b[3 * i] + dinv[(3 * c + 1) * n + i] * b[3 * i + 1] +
+                       dinv[(3 * c + 2) * n + i] * b[3 * i + 2];
+    else
+        x[3 * i + c] = dinv[i] * b[3 * i + c];
+}
+
+void launch_diag_solve_mp(int mode, int nrows, const int *rowid, const float *dinv, int64_t n, const float *b,
+                          float *x, hipStream_t s) {
+    if (nrows <= 0) return;
+    const int nb = ceil_div(3 * static_cast<int64_t>(nrows), MBLOCK);
+    if (mode == 3)
+        k_diag_solve_mp<3><<<nb, MBLOCK, 0, s>>>(nrows, rowid, dinv, n, b, x);
+    else
+        k_diag_solve_mp<1><<<nb, MBLOCK, 0, s>>>(nrows, rowid, dinv, n, b, x);
+    AMG_CHECK_LAUNCH();
+}
+
+__global__ void __launch_bounds__(MBLOCK) k_dense_gemv_f32(const float *M, int m, int nc, const float *X, float *Y) {
+    const int row = blockIdx.x * (MBLOCK / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= m) return;
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+    const float *Mr = M + static_cast<int64_t>(row) * m;
+    int j = lane;
+    for (; j + 192 < m; j += 256) {
+        const float v0 = Mr[j], v1 = Mr[j + 64], v2 = Mr[j + 128], v3 = Mr[j + 192];
+        if (nc == 1) {
+            a0 += v0 * X[j] + v1 * X[j + 64] + v2 * X[j + 128] + v3 * X[j + 192];
+        } else {
+            a0 += v0 * X[3 * j] + v1 * X[3 * (j + 64)] + v2 * X[3 * (j + 128)] + v3 * X[3 * (j + 192)];
+            a1 += v0 * X[3 * j + 1] + v1 * X[3 * (j + 64) + 1] + v2 * X[3 * (j + 128) + 1] + v3 * X[3 * (j + 192) + 1];
+            a2 += v0 * X[3 * j + 2] + v1 * X[3 * (j + 64) + 2] + v2 * X[3 * (j + 128) + 2] + v3 * X[3 * (j + 192) + 2];
+        }
+    }
+    for (; j < m; j += 64) {
+        const float v = Mr[j];
+        a0 += v * X[j * nc];
+        if (nc > 1) {
+            a1 += v * X[j * nc + 1];
+            a2 += v * X[j * nc + 2];
+        }
+    }
+    a0 = group_sum_f<64>(a0);
+    a1 = group_sum_f<64>(a1);
+    a2 = group_sum_f<64>(a2);
+    if (lane < nc) Y[row * nc + lane] = lane == 0 ? a0 : (lane == 1 ? a1 : a2);
+}
+
+void launch_dense_gemv_f32(const float *M, int m, int nc, const float *X, float *Y, hipStream_t s) {
+    if (m <= 0) return;
+    k_dense_gemv_f32<<<ceil_div(m, MBLOCK / 64), MBLOCK, 0, s>>>(M, m, nc, X, Y);
+    AMG_CHECK_LAUNCH();
+}
+
+}  // namespace amgp2

@@ -238,6 +238,10 @@ void vcycle(amg_ctx *h, int l, const double *b, double *x) { cycle(h, l, b, x, t
 // finest level, the first from z = 0, each further one from the current z.
 // z_filled: z already holds zeros.
 static void precondition_impl(amg_ctx *h, const double *r, double *z, bool z_filled) {
+    if (h->mixed) {
+        precondition_mp(h, r, z);
+        return;
+    }
     const int cyc = std::max(1, h->prm.cycles);
     for (int k = 0; k < cyc; ++k) cycle(h, 0, r, z, k == 0, k == 0 && z_filled);
 }

@@ -1,0 +1,230 @@
+// The mixed-precision preconditioner: Algorithm 1 on FP32 vectors, with the
+// finest operator in FP32 and the coarser ones in BF16 with per-row FP32
+// scales (AMG_PREC_MIXED), or FP32 everywhere (AMG_PREC_FP32). The outer
+// Krylov loop, its residual and dot products stay in FP64 (flexible CG or
+// flexible GMRES absorb the variation of the reduced-precision cycle), and
+// the coarsest solve stays the FP64 explicit inverse. The coarse end that is
+// assembled as one operator (from level dense_start down) is applied from an
+// FP32 copy of that FP64-assembled operator.
+#include <cmath>
+
+#include "context.h"
+
+namespace amgp2 {
+
+void build_mixed(amg_ctx *h) {
+    hipStream_t s = h->stream;
+    const int prec = h->prm.precision;
+    h->mixed = prec != AMG_PREC_FP64;
+    if (!h->mixed) return;
+    for (size_t l = 0; l < h->lv.size(); ++l) {
+        Level &L = h->lv[l];
+        LevelMP &M = L.mp;
+        const size_t nv = 3 * static_cast<size_t>(L.n);
+        M.x.alloc(nv);
+        M.b.alloc(nv);
+        M.r.alloc(nv);
+        M.t.alloc(nv);
+        if (L.coarsest) continue;
+        M.kind = (l == 0 || prec == AMG_PREC_FP32) ? VAL_F32 : VAL_BF16;
+        const int64_t np = L.A.np;
+        if (M.kind == VAL_F32) {
+            M.a32.alloc(np * L.A.nnz);
+            launch_planes_f32(L.A.val.p, M.a32.p, np * L.A.nnz, s);
+            if (!L.cptr.empty()) {
+                M.ag32.alloc(np * L.Ag.nnz);
+                launch_planes_f32(L.Ag.val.p, M.ag32.p, np * L.Ag.nnz, s);
+            }
+        } else {
+            M.scale.alloc(static_cast<size_t>(L.mode) * L.n);
+            launch_row_scales(L.mode, L.n, L.A.rowptr.p, L.A.col.p, L.A.val.p, L.A.nnz, M.scale.p, s);
+            M.a16.alloc(np * L.A.nnz);
+            launch_planes_bf16(L.mode, L.n, L.A.rowptr.p, nullptr, L.A.val.p, L.A.nnz, M.scale.p, M.a16.p, s);
+            if (!L.cptr.empty()) {
+                M.ag16.alloc(np * L.Ag.nnz);
+                launch_planes_bf16(L.mode, L.n, L.Ag.rowptr.p, L.g_rowid.p, L.Ag.val.p, L.Ag.nnz, M.scale.p,
+                                   M.ag16.p, s);
+            }
+        }
+        M.dinv.alloc(L.dinv.n);
+        launch_to_f32(L.dinv.p, M.dinv.p, static_cast<int64_t>(L.dinv.n), s);
+        M.pval.alloc(L.P.nnz);
+        launch_to_f32(L.P.val.p, M.pval.p, L.P.nnz, s);
+        M.rval.alloc(L.R.nnz);
+        launch_to_f32(L.R.val.p, M.rval.p, L.R.nnz, s);
+    }
+    if (h->tail_m > 0) {
+        const int64_t mm = static_cast<int64_t>(h->tail_m) * h->tail_m;
+        h->tail_dense32.alloc(mm);
+        launch_to_f32(h->tail_dense.p, h->tail_dense32.p, mm, s);
+    }
+    AMG_HIP(hipStreamSynchronize(s));
+}
+
+static std::string tag(const char *cls, int l) { return std::string(cls) + ".L" + std::to_string(l); }
+
+static RowArgsMP args_natural(Level &L) {
+    RowArgsMP a;
+    a.nrows = L.n;
+    a.rowptr = L.A.rowptr.p;
+    a.col = L.A.col.p;
+    a.val = L.mp.aval();
+    a.rscale = L.mp.scale.p;
+    a.nnz = L.A.nnz;
+    return a;
+}
+
+static double mat_bytes(const Level &L, int64_t nnz, int rows) {
+    return static_cast<double>(nnz) * (L.A.np * L.mp.vbytes() + 4.0) + rows * 4.0 +
+           (L.mp.kind == VAL_BF16 ? rows * 4.0 * L.mode : 0.0);
+}
+
+static void residual_mp(amg_ctx *h, int l, const float *b, const float *x, float *r) {
+    Level &L = h->lv[l];
+    RowArgsMP a = args_natural(L);
+    a.x = x;
+    a.b = b;
+    a.y = r;
+    ProfScope ps(h, tag("resid", l), mat_bytes(L, L.A.nnz, L.n) + 3.0 * L.n * 12.0);
+    launch_row_mp(L.mode, OP_RESID, L.G, L.mp.kind, a, h->stream);
+}
+
+static void jacobi_mp(amg_ctx *h, int l, const float *b, float *x, bool zero) {
+    Level &L = h->lv[l];
+    const float om = static_cast<float>(
+        h->level_omega.empty() ? h->prm.omega : h->level_omega[std::min<size_t>(l, h->level_omega.size() - 1)]);
+    const int nb = L.mode == 3 ? 9 : 1;
+    if (zero) {
+        ProfScope ps(h, tag("jacobi0", l), 3.0 * L.n * 8.0 + nb * 4.0 * L.n);
+        launch_jacobi_zero_mp(L.mode, L.n, L.mp.dinv.p, b, om, x, h->stream);
+        return;
+    }
+    RowArgsMP a = args_natural(L);
+    a.x = x;
+    a.b = b;
+    a.y = L.mp.t.p;
+    a.dinv = L.mp.dinv.p;
+    a.dinv_n = L.n;
+    a.omega = om;
+    {
+        ProfScope ps(h, tag("jacobi", l), mat_bytes(L, L.A.nnz, L.n) + 3.0 * L.n * 12.0 + nb * 4.0 * L.n);
+        launch_row_mp(L.mode, OP_JACOBI, L.G, L.mp.kind, a, h->stream);
+    }
+    launch_copy_f32(x, L.mp.t.p, 3 * static_cast<int64_t>(L.n), h->stream);
+}
+
+static void gs_mp(amg_ctx *h, int l, const float *b, float *x, bool forward, bool x_zero) {
+    Level &L = h->lv[l];
+    const int ncol = static_cast<int>(L.cptr.size()) - 1;
+    const int nb = L.mode == 3 ? 9 : 1;
+    for (int q = 0; q < ncol; ++q) {
+        const int c = forward ? q : ncol - 1 - q;
+        const int r0 = L.cptr[c], r1 = L.cptr[c + 1];
+        if (r1 == r0) continue;
+        if (q == 0 && x_zero) {
+            ProfScope ps(h, tag("gs", l), (r1 - r0) * (4.0 + 24.0 + nb * 4.0));
+            launch_diag_solve_mp(L.mode, r1 - r0, L.g_rowid.p + r0, L.mp.dinv.p, L.n, b, x, h->stream);
+            continue;
+        }
+        RowArgsMP a;
+        a.nrows = r1 - r0;
+        a.rowptr = L.Ag.rowptr.p + r0;
+        a.col = L.Ag.col.p;
+        a.val = L.mp.agval();
+        a.rscale = L.mp.scale.p;
+        a.nnz = L.Ag.nnz;
+        a.rowid = L.g_rowid.p + r0;
+        a.x = x;
+        a.b = b;
+        a.y = x;
+        a.dinv = L.mp.dinv.p;
+        a.dinv_n = L.n;
+        ProfScope ps(h, tag("gs", l), mat_bytes(L, L.colour_nnz[c], a.nrows) + a.nrows * (4.0 + 12.0 + 24.0 + nb * 4.0));
+        launch_row_mp(L.mode, OP_GS, L.Gg, L.mp.kind, a, h->stream);
+    }
+}
+
+static void smooth_mp(amg_ctx *h, int l, const float *b, float *x, bool pre, bool zero_init, bool filled) {
+    const amg_params &p = h->prm;
+    const int steps = pre ? p.pre : p.post;
+    Level &L = h->lv[l];
+    if (zero_init && !filled && (steps == 0 || p.smoother != AMG_SMOOTH_JA))
+        launch_fill_f32(x, 0.f, 3 * static_cast<int64_t>(L.n), h->stream);
+    for (int k = 0; k < steps; ++k) {
+        if (p.smoother == AMG_SMOOTH_JA)
+            jacobi_mp(h, l, b, x, zero_init && k == 0);
+        else
+            gs_mp(h, l, b, x, pre, pre && zero_init && k == 0);
+    }
+}
+
+// coarsest level: the FP64 explicit inverse
+static void coarse_mp(amg_ctx *h, int l, const float *b, float *x) {
+    Level &L = h->lv[l];
+    const int64_t nv = 3 * static_cast<int64_t>(L.n);
+    launch_to_f64(b, L.b.p, nv, h->stream);
+    {
+        ProfScope ps(h, "coarse", static_cast<double>(h->coarse_m) * h->coarse_m * 8.0);
+        launch_dense_gemv(h->coarse_inv.p, h->coarse_m, h->coarse_nc, L.b.p, L.x.p, h->stream);
+    }
+    launch_to_f32(L.x.p, x, nv, h->stream);
+}
+
+static void cycle_mp(amg_ctx *h, int l, const float *b, float *x, bool x_zero, bool filled) {
+    Level &L = h->lv[l];
+    if (L.coarsest) {
+        coarse_mp(h, l, b, x);
+        return;
+    }
+    if (l == h->dense_start && x_zero) {
+        ProfScope ps(h, "dense_tail", static_cast<double>(h->tail_m) * h->tail_m * 4.0);
+        launch_dense_gemv_f32(h->tail_dense32.p, h->tail_m, h->tail_nc, b, x, h->stream);
+        return;
+    }
+    smooth_mp(h, l, b, x, true, x_zero, filled);
+    residual_mp(h, l, b, x, L.mp.r.p);
+    Level &C = h->lv[l + 1];
+    {
+        RowArgsMP a;
+        a.nrows = L.R.nrows;
+        a.rowptr = L.R.rowptr.p;
+        a.col = L.R.col.p;
+        a.val = L.mp.rval.p;
+        a.nnz = L.R.nnz;
+        a.x = L.mp.r.p;
+        a.y = C.mp.b.p;
+        a.zero_out = C.mp.x.p;
+        ProfScope ps(h, tag("restrict", l), L.R.nnz * 8.0 + 3.0 * (L.n + 2 * C.n) * 4.0);
+        launch_row_mp(1, OP_SPMV, L.Gr, VAL_F32, a, h->stream);
+    }
+    if (C.coarsest) {
+        coarse_mp(h, l + 1, C.mp.b.p, C.mp.x.p);
+    } else {
+        const int nu = std::max(1, h->prm.nu);
+        for (int k = 0; k < nu; ++k) cycle_mp(h, l + 1, C.mp.b.p, C.mp.x.p, k == 0, k == 0);
+    }
+    {
+        RowArgsMP a;
+        a.nrows = L.P.nrows;
+        a.rowptr = L.P.rowptr.p;
+        a.col = L.P.col.p;
+        a.val = L.mp.pval.p;
+        a.nnz = L.P.nnz;
+        a.x = C.mp.x.p;
+        a.y = x;
+        ProfScope ps(h, tag("prolong", l), L.P.nnz * 8.0 + 3.0 * (2.0 * L.n + C.n) * 4.0);
+        launch_row_mp(1, OP_SPMV_ADD, L.Gp, VAL_F32, a, h->stream);
+    }
+    smooth_mp(h, l, b, x, false, false, false);
+}
+
+void precondition_mp(amg_ctx *h, const double *r, double *z) {
+    Level &L = h->lv[0];
+    const int64_t nv = 3 * static_cast<int64_t>(L.n);
+    launch_to_f32(r, L.mp.b.p, nv, h->stream);
+    const int cyc = std::max(1, h->prm.cycles);
+    for (int k = 0; k < cyc; ++k) cycle_mp(h, 0, L.mp.b.p, L.mp.x.p, k == 0, false);
+    launch_to_f64(L.mp.x.p, z, nv, h->stream);
+}
+
+}  // namespace amgp2

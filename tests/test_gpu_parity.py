@@ -217,3 +217,38 @@ def test_full_size_elasticity_properties():
         r[:, c] -= np.bincount(rows, weights=Ax[:, c], minlength=hsys.nodes)
     relres = np.linalg.norm(r) / np.linalg.norm(hsys.rhs)
     assert relres <= 1e-8 * 1.01 and abs(relres - res.relres) < 1e-10
+
+
+# ---------------------------------------------------------------- mixed precision
+@pytest.mark.parametrize("precision,tol_v", [("FP32", 1e-5), ("MIXED", 5e-2)])
+def test_reduced_precision_vcycle(case, precision, tol_v):
+    """FP32 / BF16-coarse V-cycle against the oracle's FP64 V-cycle: the
+    difference is the rounding of the reduced formats (FP32 ~1e-7 per
+    operation, BF16 ~4e-3 per stored coarse entry)."""
+    name, hsys, o = case
+    s = amg.AMGSolver(hsys, smoother="GS-1-1", precision=precision)
+    h = _oracle_hierarchy(o)
+    prec = oamg.preconditioner(h, oamg.Smoother.parse("GS-1-1"))
+    r = np.random.default_rng(15).standard_normal(hsys.dofs)
+    z = torch.zeros(hsys.dofs, dtype=torch.float64, device=DEV)
+    s.precondition(dev(r), z)
+    ref = prec(r).ravel()
+    assert np.linalg.norm(host(z) - ref) / np.linalg.norm(ref) < tol_v, (name, precision)
+
+
+@pytest.mark.parametrize("precision,kry", [("MIXED", "FCG"), ("FP32", "FCG"), ("MIXED", "PCG")])
+def test_reduced_precision_solve(case, precision, kry):
+    """The FP64 outer loop reaches the tolerance on the true FP64 residual;
+    the solution matches the oracle's FP64 solution."""
+    name, hsys, o = case
+    tol = 1e-10
+    s = amg.AMGSolver(hsys, smoother="GS-1-1", krylov=kry, precision=precision)
+    b = dev(hsys.rhs)
+    x = torch.zeros_like(b)
+    res = s.solve(b, x, tol=tol, maxit=500)
+    assert res.converged and res.relres <= tol * 1.01, res
+    h = _oracle_hierarchy(o)
+    prec = oamg.preconditioner(h, oamg.Smoother.parse("GS-1-1"))
+    ref = krylov.pcg(lambda v: o.A.matvec(v).ravel(), lambda r: prec(r).ravel(), o.b.ravel(), tol=1e-13)
+    err = np.linalg.norm(host(x) - ref.x) / np.linalg.norm(ref.x)
+    assert err < 1e-7, (name, precision, err)
