@@ -68,8 +68,19 @@ int amg_setup(const amg_system *sys, const amg_params *params, amg_stream stream
         *out = nullptr;
         AMG_REQUIRE(params != nullptr, AMG_EINVAL, "amg_setup: null params");
         const amg_params &p = *params;
-        AMG_REQUIRE(p.smoother == AMG_SMOOTH_JA || p.smoother == AMG_SMOOTH_GS, AMG_EUNSUPPORTED,
-                    "amg_setup: smoother not available for SPD systems");
+        AMG_REQUIRE(sys != nullptr, AMG_EINVAL, "amg_setup: null system");
+        if (sys->n_pres > 0) {
+            AMG_REQUIRE(p.smoother == AMG_SMOOTH_SGS || p.smoother == AMG_SMOOTH_BS, AMG_EINVAL,
+                        "amg_setup: saddle point systems need the sGS or Braess-Sarazin smoother");
+            AMG_REQUIRE(p.krylov == AMG_KRYLOV_FGMRES || p.krylov == AMG_KRYLOV_NONE, AMG_EINVAL,
+                        "amg_setup: saddle point systems need FGMRES or the stand-alone iteration");
+            AMG_REQUIRE(p.precision == AMG_PREC_FP64, AMG_EUNSUPPORTED,
+                        "amg_setup: saddle point systems run in FP64");
+        } else {
+            AMG_REQUIRE(p.smoother == AMG_SMOOTH_JA || p.smoother == AMG_SMOOTH_GS, AMG_EINVAL,
+                        "amg_setup: SPD systems need the JA or GS smoother");
+        }
+        AMG_REQUIRE(p.krylov != AMG_KRYLOV_FGMRES || p.restart >= 1, AMG_EINVAL, "amg_setup: restart < 1");
         AMG_REQUIRE(p.pre >= 0 && p.post >= 0 && p.cycles >= 1 && p.nu >= 1 && p.nu <= 2, AMG_EINVAL,
                     "amg_setup: invalid smoothing/cycle counts");
         AMG_REQUIRE(p.precision == AMG_PREC_FP64 || p.precision == AMG_PREC_MIXED || p.precision == AMG_PREC_FP32,
@@ -100,8 +111,11 @@ int amg_solve(amg_handle h, const double *b, double *x, double tol, int32_t maxi
         switch (h->prm.krylov) {
             case AMG_KRYLOV_PCG: return solve_pcg(h, b, x, tol, maxit, res);
             case AMG_KRYLOV_FCG: return solve_fcg(h, b, x, tol, maxit, res);
-            case AMG_KRYLOV_NONE: return solve_stationary(h, b, x, tol, maxit, res);
-            default: throw Error(AMG_EUNSUPPORTED, "amg_solve: Krylov method not available for SPD systems");
+            case AMG_KRYLOV_NONE:
+                return h->saddle ? solve_stationary_saddle(h, b, x, tol, maxit, res)
+                                 : solve_stationary(h, b, x, tol, maxit, res);
+            case AMG_KRYLOV_FGMRES: return solve_fgmres(h, b, x, tol, maxit, res);
+            default: throw Error(AMG_EINVAL, "amg_solve: unknown Krylov method");
         }
     });
 }
@@ -110,7 +124,7 @@ int amg_precondition(amg_handle h, const double *r, double *z, amg_stream stream
     return guarded([&]() -> int {
         AMG_REQUIRE(h && r && z, AMG_EINVAL, "amg_precondition: null argument");
         h->stream = static_cast<hipStream_t>(stream);
-        precondition(h, r, z);
+        precondition_any(h, r, z);
         AMG_HIP(hipStreamSynchronize(h->stream));
         profile_collect(h);
         return AMG_OK;
@@ -122,7 +136,10 @@ int amg_apply(amg_handle h, int32_t level, const double *x, double *y, amg_strea
         AMG_REQUIRE(h && x && y, AMG_EINVAL, "amg_apply: null argument");
         AMG_REQUIRE(level >= 0 && level < static_cast<int>(h->lv.size()), AMG_EINVAL, "amg_apply: bad level");
         h->stream = static_cast<hipStream_t>(stream);
-        apply_level(h, level, x, y);
+        if (h->saddle)
+            saddle_apply(h, level, x, y);
+        else
+            apply_level(h, level, x, y);
         AMG_HIP(hipStreamSynchronize(h->stream));
         profile_collect(h);
         return AMG_OK;
@@ -139,7 +156,10 @@ int amg_smooth(amg_handle h, int32_t level, const double *b, double *x, int32_t 
         amg_params save = h->prm;
         h->prm.pre = h->prm.post = 1;
         try {
-            smooth(h, level, b, x, forward != 0, false, false);
+            if (h->saddle)
+                saddle_smooth(h, level, b, x);
+            else
+                smooth(h, level, b, x, forward != 0, false, false);
         } catch (...) {
             h->prm = save;
             throw;
@@ -164,6 +184,8 @@ int amg_get_level_info(amg_handle h, int32_t level, amg_level_info *info) {
         info->n_pres = L.n_pres;
         info->bs = L.mode;
         info->nnz_A = L.A.nnz;
+        info->nnz_B = L.B.nnz;
+        info->nnz_C = L.C.nnz;
         info->nnz_P = L.coarsest ? 0 : L.P.nnz;
         info->n_colors = L.cptr.empty() ? 0 : static_cast<int>(L.cptr.size()) - 1;
         info->is_coarsest = L.coarsest ? 1 : 0;
@@ -182,6 +204,8 @@ int amg_get_level_matrix(amg_handle h, int32_t level, int32_t which, int32_t *ro
         const Level &L = h->lv[level];
         const DMat *m = nullptr;
         if (which == 0) m = &L.A;
+        if (which == 1 && L.B.nnz > 0) m = &L.B;
+        if (which == 2 && L.C.nnz > 0) m = &L.C;
         if (which == 3) {
             AMG_REQUIRE(!L.coarsest, AMG_EINVAL, "coarsest level has no prolongation");
             m = &L.P;

@@ -9,6 +9,7 @@
 #include "host_setup.h"
 #include "kernels.h"
 #include "mixed.h"
+#include "saddle.h"
 #include "tail.h"
 
 namespace amgp2 {
@@ -57,6 +58,13 @@ struct Level {
     DevBuf<double> x, b, r, t;
     int G = 16, Gg = 16, Gp = 4, Gr = 8;  // lanes per row: A, grouped A, P, R
     LevelMP mp;               // mixed-precision copy (AMG_PREC_MIXED / FP32)
+    // saddle point levels (n_pres > 0); vectors are [u (3n); p (n_pres)]
+    DMat B, Bt, C;            // B: n_pres x n (1x3), Bt: n x n_pres (3x1), C: n_pres^2 (may be empty)
+    DMat H, Ht;               // pressure prolongation to this level and its transpose
+    DevBuf<double> sgs_scale; // sGS: 1 / diag(B M_A^{-1} B^T + C)
+    DevBuf<double> bs_ahat;   // BS: 1 / (2 a_ii) per velocity unknown
+    int Gb = 16, Gbt = 16, Gc = 8, Gh = 4, Ght = 8;
+    int64_t vlen() const { return 3 * static_cast<int64_t>(n) + n_pres; }
 };
 
 struct ProfStat {
@@ -90,6 +98,12 @@ struct amg_ctx {
     // reduced-precision cycle (precision != AMG_PREC_FP64)
     bool mixed = false;
     amgp2::DevBuf<float> tail_dense32;
+    // saddle point system
+    bool saddle = false;
+    int pinned = -1;                  // coarsest unknown pinned to zero (pressure kernel), -1 none
+    // flexible GMRES workspace: V ((m+1) x n), Z (m x n), device scalars
+    amgp2::DevBuf<double> gm_V, gm_Z, gm_h, gm_y;
+    int gm_m = 0;
     // Krylov workspace
     amgp2::DevBuf<double> kr, kz, kp, kq, kw;
     amgp2::DevBuf<double> partial, sc;
@@ -114,6 +128,16 @@ namespace amgp2 {
 void build_hierarchy(amg_ctx *h, const amg_system *sys);
 void build_mixed(amg_ctx *h);
 void precondition_mp(amg_ctx *h, const double *r, double *z);
+// saddle point path
+void saddle_setup_level(amg_ctx *h, Level &L);
+void saddle_precondition(amg_ctx *h, const double *r, double *z);
+void system_matvec(amg_ctx *h, const double *x, double *y);
+void system_residual(amg_ctx *h, const double *b, const double *x, double *r);
+int solve_fgmres(amg_ctx *h, const double *b, double *x, double tol, int maxit, amg_result *res);
+int solve_stationary_saddle(amg_ctx *h, const double *b, double *x, double tol, int maxit, amg_result *res);
+void precondition_any(amg_ctx *h, const double *r, double *z);
+void saddle_apply(amg_ctx *h, int l, const double *x, double *y);
+void saddle_smooth(amg_ctx *h, int l, const double *b, double *x);
 void vcycle(amg_ctx *h, int l, const double *b, double *x);
 void precondition(amg_ctx *h, const double *r, double *z);
 void apply_level(amg_ctx *h, int l, const double *x, double *y);

@@ -42,6 +42,31 @@ static void upload_blocks(DMat &m, int nrows, int ncols, const int32_t *rowptr, 
     AMG_HIP(hipStreamSynchronize(s));  // `planes` goes out of scope
 }
 
+// B^T of a host 1x3-block matrix (nrows x ncols) as 3x1 blocks (3 planes).
+static void upload_transpose_1x3(DMat &m, int nrows, int ncols, const int32_t *rowptr, const int32_t *col,
+                                 const double *val, hipStream_t s) {
+    const int64_t nnz = rowptr[nrows];
+    std::vector<int> rp(ncols + 1, 0), cl(nnz);
+    for (int64_t k = 0; k < nnz; ++k) ++rp[col[k] + 1];
+    std::partial_sum(rp.begin(), rp.end(), rp.begin());
+    std::vector<int> next(rp.begin(), rp.end() - 1);
+    std::vector<double> planes(3 * static_cast<size_t>(nnz));
+    for (int i = 0; i < nrows; ++i)
+        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+            const int q = next[col[k]]++;
+            cl[q] = i;
+            for (int c = 0; c < 3; ++c) planes[static_cast<size_t>(c) * nnz + q] = val[3 * k + c];
+        }
+    m.nrows = ncols;
+    m.ncols = nrows;
+    m.nnz = nnz;
+    m.np = 3;
+    m.rowptr.upload(rp, s);
+    m.col.upload(cl, s);
+    m.val.upload(planes, s);
+    AMG_HIP(hipStreamSynchronize(s));
+}
+
 static HostCSR download_pattern(const DMat &m, hipStream_t s) {
     HostCSR h;
     h.nrows = m.nrows;
@@ -101,8 +126,19 @@ static void check_system(const amg_system *sys) {
                 "amg_setup: node counts must be positive");
     AMG_REQUIRE(sys->bs == 1 || sys->bs == 3, AMG_EINVAL, "amg_setup: bs must be 1 or 3");
     AMG_REQUIRE(sys->A_rowptr && sys->A_col && sys->A_val, AMG_EINVAL, "amg_setup: A is missing");
-    AMG_REQUIRE(sys->n_pres == 0, AMG_EUNSUPPORTED, "amg_setup: saddle systems need the saddle build");
     const int n = sys->n_lin + sys->n_quad;
+    if (sys->n_pres > 0) {
+        AMG_REQUIRE(sys->bs == 3, AMG_EINVAL, "amg_setup: saddle systems need 3x3 velocity blocks");
+        AMG_REQUIRE(sys->n_pres == sys->n_lin, AMG_EINVAL,
+                    "amg_setup: pressure nodes must be the linear velocity nodes (n_pres == n_lin)");
+        AMG_REQUIRE(sys->B_rowptr && sys->B_col && sys->B_val, AMG_EINVAL, "amg_setup: B is missing");
+        for (int k = 0; k < sys->B_rowptr[sys->n_pres]; ++k)
+            AMG_REQUIRE(sys->B_col[k] >= 0 && sys->B_col[k] < n, AMG_EINVAL, "amg_setup: B column out of range");
+        if (sys->C_rowptr)
+            for (int k = 0; k < sys->C_rowptr[sys->n_pres]; ++k)
+                AMG_REQUIRE(sys->C_col[k] >= 0 && sys->C_col[k] < sys->n_pres, AMG_EINVAL,
+                            "amg_setup: C column out of range");
+    }
     AMG_REQUIRE(sys->A_rowptr[0] == 0, AMG_EINVAL, "amg_setup: A_rowptr[0] != 0");
     for (int i = 0; i < n; ++i) {
         const int b = sys->A_rowptr[i], e = sys->A_rowptr[i + 1];
@@ -243,14 +279,47 @@ static void setup_coarsest(amg_ctx *h, Level &L) {
     std::vector<int> rp = L.A.rowptr.download(s), cl = L.A.col.download(s);
     std::vector<double> v = L.A.val.download(s);
     if (L.mode == 3) {
-        const int m = 3 * L.n;
+        // [[A, B^T], [B, -C]] on the saddle coarsest level, A otherwise
+        const int nu = 3 * L.n;
+        const int m = nu + L.n_pres;
         std::vector<double> M(static_cast<size_t>(m) * m, 0.0);
         for (int i = 0; i < L.n; ++i)
             for (int k = rp[i]; k < rp[i + 1]; ++k)
                 for (int r = 0; r < 3; ++r)
                     for (int c = 0; c < 3; ++c)
                         M[static_cast<size_t>(3 * i + r) * m + 3 * cl[k] + c] = v[static_cast<size_t>(r * 3 + c) * L.A.nnz + k];
+        if (L.n_pres > 0) {
+            std::vector<int> brp = L.B.rowptr.download(s), bcl = L.B.col.download(s);
+            std::vector<double> bv = L.B.val.download(s);
+            for (int q = 0; q < L.n_pres; ++q)
+                for (int k = brp[q]; k < brp[q + 1]; ++k)
+                    for (int c = 0; c < 3; ++c) {
+                        const double b = bv[static_cast<size_t>(c) * L.B.nnz + k];
+                        M[static_cast<size_t>(nu + q) * m + 3 * bcl[k] + c] = b;
+                        M[static_cast<size_t>(3 * bcl[k] + c) * m + nu + q] = b;
+                    }
+            if (L.C.nnz > 0) {
+                std::vector<int> crp = L.C.rowptr.download(s), ccl = L.C.col.download(s);
+                std::vector<double> cv = L.C.val.download(s);
+                for (int q = 0; q < L.n_pres; ++q)
+                    for (int k = crp[q]; k < crp[q + 1]; ++k)
+                        M[static_cast<size_t>(nu + q) * m + nu + ccl[k]] = -cv[k];
+            }
+            if (h->pinned >= 0) {
+                // constants in the pressure kernel: fix the last pressure unknown
+                h->pinned = m - 1;
+                for (int j = 0; j < m; ++j) {
+                    M[static_cast<size_t>(m - 1) * m + j] = 0.0;
+                    M[static_cast<size_t>(j) * m + m - 1] = 0.0;
+                }
+                M[static_cast<size_t>(m - 1) * m + m - 1] = 1.0;
+            }
+        }
         AMG_REQUIRE(dense_inverse(M, m), AMG_EINVAL, "amg_setup: singular coarsest matrix");
+        if (h->pinned >= 0) {
+            // the pinned unknown's output is zero whatever its input holds
+            for (int j = 0; j < m; ++j) M[static_cast<size_t>(m - 1) * m + j] = 0.0;
+        }
         h->coarse_m = m;
         h->coarse_nc = 1;
         h->coarse_inv.upload(M, s);
@@ -389,6 +458,8 @@ static void setup_tail(amg_ctx *h) {
 
 void build_hierarchy(amg_ctx *h, const amg_system *sys) {
     check_system(sys);
+    h->saddle = sys->n_pres > 0;
+    h->pinned = (h->saddle && sys->pressure_kernel) ? 0 : -1;
     hipStream_t s = h->stream;
     const amg_params &p = h->prm;
     h->lv.clear();
@@ -403,12 +474,20 @@ void build_hierarchy(amg_ctx *h, const amg_system *sys) {
         L0.hpat.nrows = L0.hpat.ncols = L0.n;
         L0.hpat.rowptr.assign(sys->A_rowptr, sys->A_rowptr + L0.n + 1);
         L0.hpat.col.assign(sys->A_col, sys->A_col + L0.A.nnz);
+        if (h->saddle) {
+            // B: pressure rows (the vertices, = linear velocity nodes) x velocity nodes, 1x3 blocks
+            L0.n_pres = sys->n_pres;
+            upload_blocks(L0.B, sys->n_pres, L0.n, sys->B_rowptr, sys->B_col, sys->B_val, 3, s);
+            upload_transpose_1x3(L0.Bt, sys->n_pres, L0.n, sys->B_rowptr, sys->B_col, sys->B_val, s);
+            if (sys->C_rowptr && sys->C_col && sys->C_val)
+                upload_blocks(L0.C, sys->n_pres, sys->n_pres, sys->C_rowptr, sys->C_col, sys->C_val, 1, s);
+        }
     }
     const int max_levels = std::max(1, p.max_levels);
     while (true) {
         Level &L = h->lv.back();
-        if (3 * L.n <= p.coarse_max || static_cast<int>(h->lv.size()) >= max_levels) break;
-        HostCSR P;
+        if (L.vlen() <= p.coarse_max || static_cast<int>(h->lv.size()) >= max_levels) break;
+        HostCSR P, Hp;
         int ncl = 0, ncq = 0;
         if (p.separate) {
             HostCSR gl = subgraph(L.hpat, 0, L.n_lin), gq = subgraph(L.hpat, L.n_lin, L.n);
@@ -417,6 +496,8 @@ void build_hierarchy(amg_ctx *h, const amg_system *sys) {
             ncl = pl.ncols;
             ncq = pq.ncols;
             P = block_diagonal(pl, pq);
+            // pressure: the linear-node graph and its interpolation (H = I-block of P)
+            if (h->saddle) Hp = std::move(pl);
         } else {
             HostCSR g = subgraph(L.hpat, 0, L.n);
             P = averaging_interpolation(g, greedy_independent_set(g));
@@ -438,30 +519,51 @@ void build_hierarchy(amg_ctx *h, const amg_system *sys) {
         next.mode = L.mode;
         next.A = std::move(Ac);
         next.hpat = download_pattern(next.A, s);
+        if (h->saddle) {
+            // K_{l+1} = P^T K_l P with P = diag(I, J, H): B_c = H^T B P,
+            // B_c^T = P^T B^T H, C_c = H^T C H
+            upload_scalar(L.H, Hp, s);
+            upload_scalar(L.Ht, transpose(Hp), s);
+            L.Gh = lanes_for(L.H.nnz, L.H.nrows);
+            L.Ght = lanes_for(L.Ht.nnz, L.Ht.nrows);
+            DMat BP = spgemm(L.B, L.P, false, s);
+            next.B = spgemm(L.Ht, BP, true, s);
+            DMat BtH = spgemm(L.Bt, L.H, false, s);
+            next.Bt = spgemm(L.R, BtH, true, s);
+            if (L.C.nnz > 0) {
+                DMat CH = spgemm(L.C, L.H, false, s);
+                next.C = spgemm(L.Ht, CH, true, s);
+            }
+            next.n_pres = ncl;
+        }
         h->lv.push_back(std::move(next));
     }
     h->lv.back().coarsest = true;
     for (Level &L : h->lv) {
-        L.x.alloc(3 * static_cast<size_t>(L.n));
-        L.b.alloc(3 * static_cast<size_t>(L.n));
-        L.r.alloc(3 * static_cast<size_t>(L.n));
-        L.t.alloc(3 * static_cast<size_t>(L.n));
+        const size_t nv = static_cast<size_t>(L.vlen());
+        L.x.alloc(nv);
+        L.b.alloc(nv);
+        L.r.alloc(nv);
+        L.t.alloc(nv);
         if (!L.coarsest) {
             setup_smoother(h, L);
+            if (h->saddle) saddle_setup_level(h, L);
             if (p.autotune) autotune_level(h, L);
         }
     }
     setup_coarsest(h, h->lv.back());
-    setup_tail(h);
-    build_mixed(h);
-    h->n_dof = 3 * h->lv[0].n;
+    if (!h->saddle) {
+        setup_tail(h);
+        build_mixed(h);
+    }
+    h->n_dof = static_cast<int>(h->lv[0].vlen());
     const size_t nd = static_cast<size_t>(h->n_dof);
     h->kr.alloc(nd);
     h->kz.alloc(nd);
     h->kp.alloc(nd);
     h->kq.alloc(nd);
     h->kw.alloc(nd);
-    h->partial.alloc(static_cast<size_t>(std::max(1024, row_blocks(h->lv[0].n, 64))));
+    h->partial.alloc(static_cast<size_t>(std::max(1024 * 128, row_blocks(h->lv[0].n, 64))));
     h->sc.alloc(SC_COUNT);
     if (!h->h_sc) AMG_HIP(hipHostMalloc(reinterpret_cast<void **>(&h->h_sc), SC_COUNT * sizeof(double)));
     AMG_HIP(hipStreamSynchronize(s));

@@ -1,0 +1,290 @@
+// Saddle-point kernels (see saddle.h). Like the velocity row kernels these
+// are bandwidth bound: B holds 1x3 blocks (28 bytes per entry in FP64), C
+// scalars (12 bytes); the vectors they gather are small.
+#include "common.h"
+#include "saddle.h"
+
+namespace amgp2 {
+
+constexpr int SB = 256;
+
+template <int G>
+__device__ __forceinline__ double gsum(double v) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
+    return v;
+}
+
+template <int BR, int BC, int G, int OP>
+__global__ void __launch_bounds__(SB) k_blk(const BlkArgs a) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * SB + threadIdx.x;
+    const int i = static_cast<int>(t / G);
+    const int lane = static_cast<int>(t % G);
+    const bool active = i < a.nrows;
+    double s[BR];
+#pragma unroll
+    for (int r = 0; r < BR; ++r) s[r] = 0.0;
+    if (active) {
+        const int64_t nz = a.nnz;
+        for (int k = a.rowptr[i] + lane; k < a.rowptr[i + 1]; k += G) {
+            const int j = a.col[k];
+            double xv[BC];
+#pragma unroll
+            for (int c = 0; c < BC; ++c) xv[c] = a.x[BC * j + c];
+#pragma unroll
+            for (int r = 0; r < BR; ++r)
+#pragma unroll
+                for (int c = 0; c < BC; ++c) s[r] += a.val[(r * BC + c) * nz + k] * xv[c];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < BR; ++r) s[r] = gsum<G>(s[r]);
+    if (!active || lane >= BR) return;
+    const int r = lane;
+    double sv = s[0];
+#pragma unroll
+    for (int q = 1; q < BR; ++q)
+        if (r == q) sv = s[q];
+    const int64_t o = static_cast<int64_t>(BR) * i + r;
+    if constexpr (OP == BLK_SPMV) a.y[o] = sv;
+    else if constexpr (OP == BLK_ADD) a.y[o] += sv;
+    else if constexpr (OP == BLK_SUB) a.y[o] -= sv;
+    else if constexpr (OP == BLK_RESID) a.y[o] = a.b[o] - sv;
+    else a.y[o] += a.omega * a.dscale[i] * (sv - a.b[o]);
+}
+
+template <int BR, int BC, int G>
+static void launch_blk_g(int op, const BlkArgs &a, hipStream_t s) {
+    const int nb = ceil_div(static_cast<int64_t>(a.nrows) * G, SB);
+    if (nb == 0) return;
+    switch (op) {
+        case BLK_SPMV: k_blk<BR, BC, G, BLK_SPMV><<<nb, SB, 0, s>>>(a); break;
+        case BLK_ADD: k_blk<BR, BC, G, BLK_ADD><<<nb, SB, 0, s>>>(a); break;
+        case BLK_SUB: k_blk<BR, BC, G, BLK_SUB><<<nb, SB, 0, s>>>(a); break;
+        case BLK_RESID: k_blk<BR, BC, G, BLK_RESID><<<nb, SB, 0, s>>>(a); break;
+        case BLK_SGS_P:
+            if constexpr (BR == 1) {
+                k_blk<BR, BC, G, BLK_SGS_P><<<nb, SB, 0, s>>>(a);
+                break;
+            }
+            [[fallthrough]];
+        default: throw Error(AMG_EINVAL, "block kernel: unsupported operation");
+    }
+    AMG_CHECK_LAUNCH();
+}
+
+template <int BR, int BC>
+static void launch_blk_m(int op, int G, const BlkArgs &a, hipStream_t s) {
+    switch (G) {
+        case 4: launch_blk_g<BR, BC, 4>(op, a, s); break;
+        case 8: launch_blk_g<BR, BC, 8>(op, a, s); break;
+        case 16: launch_blk_g<BR, BC, 16>(op, a, s); break;
+        case 32: launch_blk_g<BR, BC, 32>(op, a, s); break;
+        case 64: launch_blk_g<BR, BC, 64>(op, a, s); break;
+        default: throw Error(AMG_EINVAL, "block kernel: unsupported group size");
+    }
+}
+
+void launch_blk(int br, int bc, int op, int G, const BlkArgs &a, hipStream_t s) {
+    if (br == 1 && bc == 3) launch_blk_m<1, 3>(op, G, a, s);
+    else if (br == 3 && bc == 1) launch_blk_m<3, 1>(op, G, a, s);
+    else if (br == 1 && bc == 1) launch_blk_m<1, 1>(op, G, a, s);
+    else if (br == 3 && bc == 3) launch_blk_m<3, 3>(op, G, a, s);
+    else throw Error(AMG_EINVAL, "block kernel: unsupported block shape");
+}
+
+__global__ void k_sgs_u(int64_t n, const double *dinv, const double *r, double damping, double *t, double *u) {
+    const int64_t q = static_cast<int64_t>(blockIdx.x) * SB + threadIdx.x;
+    if (q >= 3 * n) return;
+    const int64_t i = q / 3;
+    const int c = static_cast<int>(q % 3);
+    const double d = dinv[(3 * c) * n + i] * r[3 * i] + dinv[(3 * c + 1) * n + i] * r[3 * i + 1] +
+                     dinv[(3 * c + 2) * n + i] * r[3 * i + 2];
+    const double v = damping * d;
+    t[q] = v;
+    u[q] += v;
+}
+
+void launch_sgs_u(int64_t n, const double *dinv, const double *r, double damping, double *t, double *u,
+                  hipStream_t s) {
+    if (n <= 0) return;
+    k_sgs_u<<<ceil_div(3 * n, SB), SB, 0, s>>>(n, dinv, r, damping, t, u);
+    AMG_CHECK_LAUNCH();
+}
+
+__global__ void k_sgs_scale(int np, const int *brow, const int *bcol, const double *bval, int64_t bnnz,
+                            const double *dinv, int64_t nv, double damping, const int *crow, const int *ccol,
+                            const double *cval, double *out) {
+    const int p = blockIdx.x * SB + threadIdx.x;
+    if (p >= np) return;
+    double acc = 0.0;
+    for (int k = brow[p]; k < brow[p + 1]; ++k) {
+        const int j = bcol[k];
+        const double b0 = bval[k], b1 = bval[bnnz + k], b2 = bval[2 * bnnz + k];
+        const double bb[3] = {b0, b1, b2};
+        for (int r = 0; r < 3; ++r) {
+            const double dr = dinv[(3 * r) * nv + j] * b0 + dinv[(3 * r + 1) * nv + j] * b1 + dinv[(3 * r + 2) * nv + j] * b2;
+            acc += bb[r] * dr;
+        }
+    }
+    acc *= damping;
+    if (crow) {
+        for (int k = crow[p]; k < crow[p + 1]; ++k)
+            if (ccol[k] == p) acc += cval[k];
+    }
+    out[p] = acc != 0.0 ? 1.0 / acc : 0.0;
+}
+
+void launch_sgs_scale(int np, const int *brow, const int *bcol, const double *bval, int64_t bnnz,
+                      const double *dinv, int64_t nv, double damping, const int *crow, const int *ccol,
+                      const double *cval, int64_t cnnz, double *out, hipStream_t s) {
+    (void)cnnz;
+    if (np <= 0) return;
+    k_sgs_scale<<<ceil_div(np, SB), SB, 0, s>>>(np, brow, bcol, bval, bnnz, dinv, nv, damping, crow, ccol, cval,
+                                                 out);
+    AMG_CHECK_LAUNCH();
+}
+
+__global__ void k_scale(int64_t n, const double *d, const double *x, double *y) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * SB + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * SB)
+        y[i] = d[i] * x[i];
+}
+__global__ void k_scale_diff(int64_t n, const double *d, const double *x, const double *z, double *y) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * SB + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * SB)
+        y[i] = d[i] * (x[i] - z[i]);
+}
+
+static int grid_s(int64_t n) {
+    int64_t nb = (n + SB - 1) / SB;
+    if (nb > 4096) nb = 4096;
+    return static_cast<int>(nb < 1 ? 1 : nb);
+}
+
+void launch_scale(int64_t n, const double *d, const double *x, double *y, hipStream_t s) {
+    if (n <= 0) return;
+    k_scale<<<grid_s(n), SB, 0, s>>>(n, d, x, y);
+    AMG_CHECK_LAUNCH();
+}
+void launch_scale_diff(int64_t n, const double *d, const double *x, const double *z, double *y, hipStream_t s) {
+    if (n <= 0) return;
+    k_scale_diff<<<grid_s(n), SB, 0, s>>>(n, d, x, z, y);
+    AMG_CHECK_LAUNCH();
+}
+
+__global__ void k_bs_diag(int n, const int *rowptr, const int *col, const double *val, int64_t nnz, double *out) {
+    const int i = blockIdx.x * SB + threadIdx.x;
+    if (i >= n) return;
+    for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+        if (col[k] == i) {
+            for (int c = 0; c < 3; ++c) {
+                const double a = val[static_cast<int64_t>(4 * c) * nnz + k];
+                out[3 * i + c] = a != 0.0 ? 1.0 / (2.0 * a) : 0.0;
+            }
+            return;
+        }
+    }
+    for (int c = 0; c < 3; ++c) out[3 * i + c] = 0.0;
+}
+
+void launch_bs_diag(int n, const int *rowptr, const int *col, const double *val, int64_t nnz, double *out,
+                    hipStream_t s) {
+    if (n <= 0) return;
+    k_bs_diag<<<ceil_div(n, SB), SB, 0, s>>>(n, rowptr, col, val, nnz, out);
+    AMG_CHECK_LAUNCH();
+}
+
+// ---------------------------------------------------------------- FGMRES
+constexpr int MD_BLOCKS = 256;
+
+__global__ void __launch_bounds__(SB) k_multidot(const double *V, int64_t ld, const double *w, int64_t n,
+                                                 double *partial) {
+    // blockIdx.y = vector index, blockIdx.x = chunk
+    const double *v = V + static_cast<int64_t>(blockIdx.y) * ld;
+    double acc = 0.0;
+    for (int64_t t = static_cast<int64_t>(blockIdx.x) * SB + threadIdx.x; t < n;
+         t += static_cast<int64_t>(gridDim.x) * SB)
+        acc += v[t] * w[t];
+    __shared__ double red[SB / 64];
+    acc = gsum<64>(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int q = 0; q < SB / 64; ++q) s += red[q];
+        partial[static_cast<int64_t>(blockIdx.y) * gridDim.x + blockIdx.x] = s;
+    }
+}
+
+int launch_multidot(const double *V, int64_t ld, int k, const double *w, int64_t n, double *partial,
+                    hipStream_t s) {
+    if (k <= 0) return 0;
+    int nb = static_cast<int>(std::min<int64_t>(MD_BLOCKS, (n + SB - 1) / SB));
+    nb = nb < 1 ? 1 : nb;
+    k_multidot<<<dim3(nb, k), SB, 0, s>>>(V, ld, w, n, partial);
+    AMG_CHECK_LAUNCH();
+    return nb;
+}
+
+__global__ void k_multidot_reduce(const double *partial, int nb, int k, double *h) {
+    // one wavefront per vector
+    const int i = blockIdx.x * (SB / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (i >= k) return;
+    double acc = 0.0;
+    for (int b = lane; b < nb; b += 64) acc += partial[static_cast<int64_t>(i) * nb + b];
+    acc = gsum<64>(acc);
+    if (lane == 0) h[i] = acc;
+}
+
+void launch_multidot_reduce(const double *partial, int nb, int k, double *h, hipStream_t s) {
+    if (k <= 0) return;
+    k_multidot_reduce<<<ceil_div(k, SB / 64), SB, 0, s>>>(partial, nb, k, h);
+    AMG_CHECK_LAUNCH();
+}
+
+__global__ void k_multi_axpy(const double *V, int64_t ld, int k, const double *h, double *w, int64_t n) {
+    for (int64_t t = static_cast<int64_t>(blockIdx.x) * SB + threadIdx.x; t < n;
+         t += static_cast<int64_t>(gridDim.x) * SB) {
+        double s = 0.0;
+        for (int i = 0; i < k; ++i) s += h[i] * V[static_cast<int64_t>(i) * ld + t];
+        w[t] -= s;
+    }
+}
+
+void launch_multi_axpy(const double *V, int64_t ld, int k, const double *h, double *w, int64_t n, hipStream_t s) {
+    if (k <= 0 || n <= 0) return;
+    k_multi_axpy<<<grid_s(n), SB, 0, s>>>(V, ld, k, h, w, n);
+    AMG_CHECK_LAUNCH();
+}
+
+__global__ void k_multi_add(const double *Z, int64_t ld, int k, const double *y, double *x, int64_t n) {
+    for (int64_t t = static_cast<int64_t>(blockIdx.x) * SB + threadIdx.x; t < n;
+         t += static_cast<int64_t>(gridDim.x) * SB) {
+        double s = 0.0;
+        for (int i = 0; i < k; ++i) s += y[i] * Z[static_cast<int64_t>(i) * ld + t];
+        x[t] += s;
+    }
+}
+
+void launch_multi_add(const double *Z, int64_t ld, int k, const double *y, double *x, int64_t n, hipStream_t s) {
+    if (k <= 0 || n <= 0) return;
+    k_multi_add<<<grid_s(n), SB, 0, s>>>(Z, ld, k, y, x, n);
+    AMG_CHECK_LAUNCH();
+}
+
+__global__ void k_scale_by_inverse(const double *x, double *y, int64_t n, const double *sc, int idx) {
+    const double a = 1.0 / sc[idx];
+    for (int64_t t = static_cast<int64_t>(blockIdx.x) * SB + threadIdx.x; t < n;
+         t += static_cast<int64_t>(gridDim.x) * SB)
+        y[t] = a * x[t];
+}
+
+void launch_scale_by_inverse(const double *x, double *y, int64_t n, const double *sc, int idx, hipStream_t s) {
+    if (n <= 0) return;
+    k_scale_by_inverse<<<grid_s(n), SB, 0, s>>>(x, y, n, sc, idx);
+    AMG_CHECK_LAUNCH();
+}
+
+}  // namespace amgp2

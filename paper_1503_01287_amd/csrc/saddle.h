@@ -1,0 +1,65 @@
+// Kernels of the saddle-point path: the off-diagonal blocks B (pressure x
+// velocity, 1x3 blocks), B^T (3x1 blocks) and C (scalar), the segregated
+// Gauss-Seidel (Uzawa) smoother's updates, the Braess-Sarazin smoother's
+// diagonal solves, and the batched inner products of flexible GMRES.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace amgp2 {
+
+enum BlkOp : int {
+    BLK_SPMV = 0,   // y = s
+    BLK_ADD = 1,    // y += s
+    BLK_SUB = 2,    // y -= s
+    BLK_RESID = 3,  // y = b - s
+    BLK_SGS_P = 4,  // (1x3 rows of B) y_p += omega * dscale_p * (s - b_p)
+};
+
+struct BlkArgs {
+    int nrows = 0;
+    const int *rowptr = nullptr, *col = nullptr;
+    const double *val = nullptr;   // planes: br*bc
+    int64_t nnz = 0;
+    const double *x = nullptr;     // bc components per column node
+    const double *b = nullptr;     // br components per row
+    double *y = nullptr;
+    const double *dscale = nullptr;
+    double omega = 1.0;
+};
+
+// br, bc in {1, 3}; G lanes per row
+void launch_blk(int br, int bc, int op, int G, const BlkArgs &a, hipStream_t s);
+
+// sGS velocity step: t_i = damping * D_i^{-1} r_i; u_i += t_i (3x3 blocks)
+void launch_sgs_u(int64_t n, const double *dinv, const double *r, double damping, double *t, double *u,
+                  hipStream_t s);
+// sGS pressure scaling 1 / (damping * sum_k b_k^T D_{col k}^{-1} b_k + C_pp)
+void launch_sgs_scale(int np, const int *brow, const int *bcol, const double *bval, int64_t bnnz,
+                      const double *dinv, int64_t nv, double damping, const int *crow, const int *ccol,
+                      const double *cval, int64_t cnnz, double *out, hipStream_t s);
+// y_i = d_i * x_i (elementwise, n doubles) / y_i = d_i * (x_i - z_i)
+void launch_scale(int64_t n, const double *d, const double *x, double *y, hipStream_t s);
+void launch_scale_diff(int64_t n, const double *d, const double *x, const double *z, double *y, hipStream_t s);
+// 1 / (2 a_ii) for every velocity unknown (Braess-Sarazin's A_hat = 2 diag(A))
+void launch_bs_diag(int n, const int *rowptr, const int *col, const double *val, int64_t nnz, double *out,
+                    hipStream_t s);
+
+// FGMRES inner products: h[i] = <V_i, w> for i < k (V_i = V + i * ld) as
+// block partials partial[i * nb + block]; returns nb
+int launch_multidot(const double *V, int64_t ld, int k, const double *w, int64_t n, double *partial,
+                    hipStream_t s);
+// h[i] = sum of partial[i * nb ...] for i < k
+void launch_multidot_reduce(const double *partial, int nb, int k, double *h, hipStream_t s);
+// w -= sum_i h[i] V_i
+void launch_multi_axpy(const double *V, int64_t ld, int k, const double *h, double *w, int64_t n,
+                       hipStream_t s);
+// x += sum_i y[i] Z_i  (y on the device)
+void launch_multi_add(const double *Z, int64_t ld, int k, const double *y, double *x, int64_t n,
+                      hipStream_t s);
+// y = a * x (device scalar a = 1 / sc[idx])
+void launch_scale_by_inverse(const double *x, double *y, int64_t n, const double *sc, int idx, hipStream_t s);
+
+}  // namespace amgp2

@@ -1,0 +1,374 @@
+// Saddle point systems K [u; p] = [f; g], K = [[A, B^T], [B, -C]]
+// (Section 2.4): Algorithm 1 with the segregated Gauss-Seidel (Uzawa)
+// smoother of Section 3.3, the saddle Galerkin hierarchy K_{l+1} = P^T K_l P
+// with P = diag(I, J, H), and right-preconditioned flexible GMRES (the
+// paper's outer method for these systems, Section 4.4).
+#include <chrono>
+#include <cmath>
+
+#include "context.h"
+
+namespace amgp2 {
+
+static int lanes(int64_t nnz, int nrows) {
+    const double avg = nrows > 0 ? static_cast<double>(nnz) / nrows : 1.0;
+    int G = 4;
+    while (G < 64 && G < avg) G *= 2;
+    return G;
+}
+
+static BlkArgs blk(const DMat &m) {
+    BlkArgs a;
+    a.nrows = m.nrows;
+    a.rowptr = m.rowptr.p;
+    a.col = m.col.p;
+    a.val = m.val.p;
+    a.nnz = m.nnz;
+    return a;
+}
+
+static std::string tag(const char *cls, int l) { return std::string(cls) + ".L" + std::to_string(l); }
+
+void saddle_setup_level(amg_ctx *h, Level &L) {
+    hipStream_t s = h->stream;
+    L.Gb = lanes(L.B.nnz, L.B.nrows);
+    L.Gbt = lanes(L.Bt.nnz, L.Bt.nrows);
+    L.Gc = L.C.nnz > 0 ? lanes(L.C.nnz, L.C.nrows) : 4;
+    L.sgs_scale.alloc(std::max(1, L.n_pres));
+    launch_sgs_scale(L.n_pres, L.B.rowptr.p, L.B.col.p, L.B.val.p, L.B.nnz, L.dinv.p, L.n, h->prm.sgs_damping,
+                     L.C.nnz > 0 ? L.C.rowptr.p : nullptr, L.C.col.p, L.C.val.p, L.C.nnz, L.sgs_scale.p, s);
+    AMG_HIP(hipStreamSynchronize(s));
+}
+
+// r = [f - A u - B^T p ; g - B u + C p] on level l
+static void saddle_residual(amg_ctx *h, int l, const double *b, const double *x, double *r) {
+    Level &L = h->lv[l];
+    const int64_t nu = 3 * static_cast<int64_t>(L.n);
+    {
+        RowArgs a;
+        a.nrows = L.n;
+        a.rowptr = L.A.rowptr.p;
+        a.col = L.A.col.p;
+        a.val = L.A.val.p;
+        a.nnz = L.A.nnz;
+        a.x = x;
+        a.b = b;
+        a.y = r;
+        ProfScope ps(h, tag("resid", l), static_cast<double>(L.A.nnz) * 76.0 + L.n * 76.0);
+        launch_row(3, OP_RESID, L.G, a, h->stream);
+    }
+    BlkArgs bt = blk(L.Bt);
+    bt.x = x + nu;
+    bt.y = r;
+    launch_blk(3, 1, BLK_SUB, L.Gbt, bt, h->stream);
+    BlkArgs bb = blk(L.B);
+    bb.x = x;
+    bb.b = b + nu;
+    bb.y = r + nu;
+    launch_blk(1, 3, BLK_RESID, L.Gb, bb, h->stream);
+    if (L.C.nnz > 0) {
+        BlkArgs cc = blk(L.C);
+        cc.x = x + nu;
+        cc.y = r + nu;
+        launch_blk(1, 1, BLK_ADD, L.Gc, cc, h->stream);
+    }
+}
+
+// y = K_l x
+void saddle_apply(amg_ctx *h, int l, const double *x, double *y) {
+    Level &L = h->lv[l];
+    const int64_t nu = 3 * static_cast<int64_t>(L.n);
+    {
+        RowArgs a;
+        a.nrows = L.n;
+        a.rowptr = L.A.rowptr.p;
+        a.col = L.A.col.p;
+        a.val = L.A.val.p;
+        a.nnz = L.A.nnz;
+        a.x = x;
+        a.y = y;
+        ProfScope ps(h, tag("spmv", l), static_cast<double>(L.A.nnz) * 76.0 + L.n * 52.0);
+        launch_row(3, OP_SPMV, L.G, a, h->stream);
+    }
+    BlkArgs bt = blk(L.Bt);
+    bt.x = x + nu;
+    bt.y = y;
+    launch_blk(3, 1, BLK_ADD, L.Gbt, bt, h->stream);
+    BlkArgs bb = blk(L.B);
+    bb.x = x;
+    bb.y = y + nu;
+    launch_blk(1, 3, BLK_SPMV, L.Gb, bb, h->stream);
+    if (L.C.nnz > 0) {
+        BlkArgs cc = blk(L.C);
+        cc.x = x + nu;
+        cc.y = y + nu;
+        launch_blk(1, 1, BLK_SUB, L.Gc, cc, h->stream);
+    }
+}
+
+// One segregated Gauss-Seidel step (reading of Section 3.3: K_hat =
+// [[M_A, 0], [B, -omega^{-1} S_d]], M_A = damped block Jacobi, S_d =
+// diag(B M_A^{-1} B^T + C)): du = M_A^{-1} r_u, dp = omega S_d^{-1}(B du - r_p).
+// x_zero: the iterate is zero, so the residual is the right-hand side.
+static void sgs_step(amg_ctx *h, int l, const double *b, double *x, bool x_zero) {
+    Level &L = h->lv[l];
+    const int64_t nu = 3 * static_cast<int64_t>(L.n);
+    const double *r = b;
+    if (!x_zero) {
+        saddle_residual(h, l, b, x, L.r.p);
+        r = L.r.p;
+    }
+    launch_sgs_u(L.n, L.dinv.p, r, h->prm.sgs_damping, L.t.p, x, h->stream);
+    BlkArgs bb = blk(L.B);
+    bb.x = L.t.p;
+    bb.b = r + nu;
+    bb.y = x + nu;
+    bb.dscale = L.sgs_scale.p;
+    bb.omega = h->prm.sgs_omega;
+    launch_blk(1, 3, BLK_SGS_P, L.Gb, bb, h->stream);
+}
+
+static void saddle_coarse(amg_ctx *h, const double *b, double *x) {
+    ProfScope ps(h, "coarse", static_cast<double>(h->coarse_m) * h->coarse_m * 8.0);
+    launch_dense_gemv(h->coarse_inv.p, h->coarse_m, 1, b, x, h->stream);
+}
+
+static void saddle_cycle(amg_ctx *h, int l, const double *b, double *x, bool x_zero) {
+    Level &L = h->lv[l];
+    if (L.coarsest) {
+        saddle_coarse(h, b, x);
+        return;
+    }
+    const amg_params &p = h->prm;
+    if (x_zero) launch_fill(x, 0.0, L.vlen(), h->stream);
+    for (int k = 0; k < p.pre; ++k) sgs_step(h, l, b, x, x_zero && k == 0);
+    saddle_residual(h, l, b, x, L.r.p);
+    Level &C = h->lv[l + 1];
+    const int64_t nu = 3 * static_cast<int64_t>(L.n), ncu = 3 * static_cast<int64_t>(C.n);
+    {
+        RowArgs a;
+        a.nrows = L.R.nrows;
+        a.rowptr = L.R.rowptr.p;
+        a.col = L.R.col.p;
+        a.val = L.R.val.p;
+        a.nnz = L.R.nnz;
+        a.x = L.r.p;
+        a.y = C.b.p;
+        launch_row(1, OP_SPMV, L.Gr, a, h->stream);
+        BlkArgs ht = blk(L.Ht);
+        ht.x = L.r.p + nu;
+        ht.y = C.b.p + ncu;
+        launch_blk(1, 1, BLK_SPMV, L.Ght, ht, h->stream);
+    }
+    if (C.coarsest) {
+        saddle_coarse(h, C.b.p, C.x.p);
+    } else {
+        const int nu_rec = std::max(1, p.nu);
+        for (int k = 0; k < nu_rec; ++k) saddle_cycle(h, l + 1, C.b.p, C.x.p, k == 0);
+    }
+    {
+        RowArgs a;
+        a.nrows = L.P.nrows;
+        a.rowptr = L.P.rowptr.p;
+        a.col = L.P.col.p;
+        a.val = L.P.val.p;
+        a.nnz = L.P.nnz;
+        a.x = C.x.p;
+        a.y = x;
+        launch_row(1, OP_SPMV_ADD, L.Gp, a, h->stream);
+        BlkArgs hh = blk(L.H);
+        hh.x = C.x.p + ncu;
+        hh.y = x + nu;
+        launch_blk(1, 1, BLK_ADD, L.Gh, hh, h->stream);
+    }
+    for (int k = 0; k < p.post; ++k) sgs_step(h, l, b, x, false);
+}
+
+void saddle_precondition(amg_ctx *h, const double *r, double *z) {
+    const int cyc = std::max(1, h->prm.cycles);
+    for (int k = 0; k < cyc; ++k) saddle_cycle(h, 0, r, z, k == 0);
+}
+
+void saddle_smooth(amg_ctx *h, int l, const double *b, double *x) { sgs_step(h, l, b, x, false); }
+
+static double norm2(amg_ctx *h, const double *v);
+
+// stand-alone AMG: repeated Algorithm 1 from the current iterate
+int solve_stationary_saddle(amg_ctx *h, const double *b, double *x, double tol, int maxit, amg_result *res) {
+    const auto t0 = std::chrono::steady_clock::now();
+    system_residual(h, b, x, h->kw.p);
+    const double r0 = norm2(h, h->kw.p);
+    int it = 0, status = AMG_NOT_CONVERGED;
+    double rel = 0.0;
+    if (r0 == 0.0) status = AMG_OK;
+    while (status == AMG_NOT_CONVERGED && it < maxit) {
+        const int cyc = std::max(1, h->prm.cycles);
+        for (int k = 0; k < cyc; ++k) saddle_cycle(h, 0, b, x, false);
+        ++it;
+        system_residual(h, b, x, h->kw.p);
+        rel = norm2(h, h->kw.p) / r0;
+        if (!(rel == rel) || rel > 1e3) status = AMG_DIVERGED;
+        else if (rel <= tol) status = AMG_OK;
+    }
+    if (res) {
+        res->iters = it;
+        res->status = status;
+        res->relres = rel;
+        res->solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    profile_collect(h);
+    return status;
+}
+
+void system_matvec(amg_ctx *h, const double *x, double *y) {
+    if (h->saddle)
+        saddle_apply(h, 0, x, y);
+    else
+        apply_level(h, 0, x, y);
+}
+
+void system_residual(amg_ctx *h, const double *b, const double *x, double *r) {
+    if (h->saddle) {
+        saddle_residual(h, 0, b, x, r);
+    } else {
+        system_matvec(h, x, r);
+        launch_axpby(r, b, 1.0, -1.0, h->n_dof, h->stream);
+    }
+}
+
+void precondition_any(amg_ctx *h, const double *r, double *z) {
+    if (h->saddle)
+        saddle_precondition(h, r, z);
+    else
+        precondition(h, r, z);
+}
+
+// ---------------------------------------------------------------- FGMRES
+static double norm2(amg_ctx *h, const double *v) {
+    const int nb = launch_dot_partial(v, v, h->n_dof, h->partial.p, h->stream);
+    launch_reduce(h->partial.p, nb, h->sc.p, SC_TMP, h->stream);
+    AMG_HIP(hipMemcpyAsync(h->h_sc, h->sc.p, SC_COUNT * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    AMG_HIP(hipStreamSynchronize(h->stream));
+    return std::sqrt(h->h_sc[SC_TMP]);
+}
+
+// Right-preconditioned flexible GMRES(m) with classical Gram-Schmidt applied
+// twice (two batched passes over the basis per iteration); the Hessenberg
+// matrix and its Givens rotations live on the host (m <= a few hundred).
+int solve_fgmres(amg_ctx *h, const double *b, double *x, double tol, int maxit, amg_result *res) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const int64_t n = h->n_dof;
+    const int m = std::max(1, h->prm.restart);
+    if (h->gm_m != m) {
+        h->gm_V.alloc(static_cast<size_t>(m + 1) * n);
+        h->gm_Z.alloc(static_cast<size_t>(m) * n);
+        h->gm_h.alloc(static_cast<size_t>(2 * (m + 2)));
+        h->gm_y.alloc(static_cast<size_t>(m + 1));
+        h->gm_m = m;
+    }
+    double *V = h->gm_V.p, *Z = h->gm_Z.p;
+    std::vector<double> H(static_cast<size_t>(m + 1) * m), cs(m), sn(m), g(m + 1), hcol(m + 2);
+    system_residual(h, b, x, V);
+    const double r0 = norm2(h, V);
+    auto finish = [&](int it, int status) {
+        system_residual(h, b, x, h->kw.p);
+        const double rel = r0 > 0.0 ? norm2(h, h->kw.p) / r0 : 0.0;
+        if (status == AMG_OK && !(rel == rel)) status = AMG_DIVERGED;
+        if (res) {
+            res->iters = it;
+            res->status = status;
+            res->relres = rel;
+            res->solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        }
+        profile_collect(h);
+        return status;
+    };
+    if (r0 == 0.0) return finish(0, AMG_OK);
+    if (!(r0 == r0)) return finish(0, AMG_DIVERGED);
+    int it = 0;
+    double beta = r0;
+    int status = AMG_NOT_CONVERGED;
+    while (it < maxit) {
+        // V_0 = r / beta (r is in V_0 already)
+        h->h_sc[SC_TMP] = beta;
+        AMG_HIP(hipMemcpyAsync(h->sc.p + SC_TMP, &h->h_sc[SC_TMP], sizeof(double), hipMemcpyHostToDevice, h->stream));
+        launch_scale_by_inverse(V, V, n, h->sc.p, SC_TMP, h->stream);
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int j = 0;
+        bool done = false;
+        for (; j < m && it < maxit; ++j) {
+            double *vj = V + static_cast<int64_t>(j) * n, *w = V + static_cast<int64_t>(j + 1) * n;
+            double *zj = Z + static_cast<int64_t>(j) * n;
+            precondition_any(h, vj, zj);
+            system_matvec(h, zj, w);
+            // classical Gram-Schmidt, twice
+            std::fill(hcol.begin(), hcol.end(), 0.0);
+            for (int pass = 0; pass < 2; ++pass) {
+                const int nb = launch_multidot(V, n, j + 1, w, n, h->partial.p, h->stream);
+                launch_multidot_reduce(h->partial.p, nb, j + 1, h->gm_h.p, h->stream);
+                launch_multi_axpy(V, n, j + 1, h->gm_h.p, w, n, h->stream);
+                std::vector<double> hp(j + 1);
+                AMG_HIP(hipMemcpyAsync(hp.data(), h->gm_h.p, (j + 1) * sizeof(double), hipMemcpyDeviceToHost,
+                                       h->stream));
+                AMG_HIP(hipStreamSynchronize(h->stream));
+                for (int i = 0; i <= j; ++i) hcol[i] += hp[i];
+            }
+            const double hn = norm2(h, w);
+            hcol[j + 1] = hn;
+            if (hn > 0.0) {
+                h->h_sc[SC_TMP] = hn;
+                AMG_HIP(hipMemcpyAsync(h->sc.p + SC_TMP, &h->h_sc[SC_TMP], sizeof(double), hipMemcpyHostToDevice,
+                                       h->stream));
+                launch_scale_by_inverse(w, w, n, h->sc.p, SC_TMP, h->stream);
+            }
+            for (int i = 0; i < j; ++i) {
+                const double t = cs[i] * hcol[i] + sn[i] * hcol[i + 1];
+                hcol[i + 1] = -sn[i] * hcol[i] + cs[i] * hcol[i + 1];
+                hcol[i] = t;
+            }
+            const double den = std::hypot(hcol[j], hcol[j + 1]);
+            cs[j] = den > 0.0 ? hcol[j] / den : 1.0;
+            sn[j] = den > 0.0 ? hcol[j + 1] / den : 0.0;
+            hcol[j] = den;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            for (int i = 0; i <= j; ++i) H[static_cast<size_t>(i) * m + j] = hcol[i];
+            ++it;
+            const double est = std::fabs(g[j + 1]) / r0;
+            if (!(est == est) || est > 1e3) {
+                status = AMG_DIVERGED;
+                done = true;
+                ++j;
+                break;
+            }
+            if (est <= tol || hn == 0.0) {
+                done = true;
+                ++j;
+                break;
+            }
+        }
+        // y = R^{-1} g, x += Z y
+        std::vector<double> y(j, 0.0);
+        for (int i = j - 1; i >= 0; --i) {
+            double s = g[i];
+            for (int k = i + 1; k < j; ++k) s -= H[static_cast<size_t>(i) * m + k] * y[k];
+            y[i] = H[static_cast<size_t>(i) * m + i] != 0.0 ? s / H[static_cast<size_t>(i) * m + i] : 0.0;
+        }
+        if (j > 0) {
+            AMG_HIP(hipMemcpyAsync(h->gm_y.p, y.data(), j * sizeof(double), hipMemcpyHostToDevice, h->stream));
+            launch_multi_add(Z, n, j, h->gm_y.p, x, n, h->stream);
+        }
+        if (status == AMG_DIVERGED) break;
+        system_residual(h, b, x, V);
+        beta = norm2(h, V);
+        if (beta / r0 <= tol) {
+            status = AMG_OK;
+            break;
+        }
+        (void)done;
+    }
+    return finish(it, status);
+}
+
+}  // namespace amgp2

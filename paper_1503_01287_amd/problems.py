@@ -317,6 +317,56 @@ def elasticity(n: int, i: int = 0, E: float = 1.0, nu: float = 0.3,
                 lambda X: np.zeros((X.shape[0], 3)), load, False)
 
 
+def _saddle(name, mesh, mu, lam_inv, vmask, g, load, closed) -> LinearSystem:
+    """[[A, B^T], [B, -C]] with A from 2 mu eps:eps, B = -int q div v,
+    C = (1/lambda) int p q (absent for Stokes); Dirichlet velocity data
+    eliminated symmetrically (B's Dirichlet columns cleared, g = -B lift)."""
+    rowptr, col, val = velocity_operator(mesh, "stokesA", 0.0, mu)
+    brow, bcol, bval = divergence_operator(mesh)
+    lift, mask = _dirichlet(mesh, vmask, g)
+    gp = -_block_matvec(brow, bcol, bval, lift, 1, 3)[:, 0]
+    N = mesh.nv + mesh.ne
+    f = _eliminate(rowptr, col, val, np.zeros((N, 3)) if load is None else load, lift, mask, False)
+    bval[mask[bcol]] = 0.0
+    sysm = LinearSystem(name, mesh.n, mesh.nv, mesh.ne, mesh.nv, 3, rowptr, col, np.ascontiguousarray(val.ravel()),
+                        np.ascontiguousarray(np.concatenate([f.ravel(), gp])), lift,
+                        B_rowptr=brow, B_col=bcol, B_val=np.ascontiguousarray(bval.ravel()),
+                        pressure_kernel=bool(closed and lam_inv == 0.0))
+    if lam_inv != 0.0:
+        crow, ccol, cval = pressure_mass(mesh, lam_inv)
+        sysm.C_rowptr, sysm.C_col, sysm.C_val = crow, ccol, np.ascontiguousarray(cval.ravel())
+    return sysm
+
+
+def mixed_elasticity(n: int, i: int = 0, E: float = 1.0, nu: float = 0.49999,
+                     workload: int = synth.MIXED_ELAST) -> LinearSystem:
+    """Mixed displacement-pressure elasticity (Section 2.1), clamped x = 0,
+    random traction on x = 1; p = -lambda div u."""
+    mesh = cube_mesh(n)
+    lam, mu = synth.lame(E, nu)
+    load = _face_x1_load(mesh, synth.face_traction(workload, i, n))
+    return _saddle(f"mixed-elasticity-{n}", mesh, mu, 1.0 / lam, mesh.xyz[:, 0] == 0.0,
+                   lambda X: np.zeros((X.shape[0], 3)), load, False)
+
+
+def stokes_cavity(n: int, speed: float, mu: float = 0.5) -> LinearSystem:
+    """Lid-driven Stokes cavity: u = (speed, 0, 0) on the open lid z = 1
+    (the lid's rim is no-slip), u = 0 on the other faces. Kuhn split reflected
+    in the upper half of each axis: on the plain split, tetrahedra with all
+    vertices on the boundary carry spurious Taylor-Hood pressure modes."""
+    mesh = cube_mesh(n, mirrored=True)
+    X = mesh.xyz
+    on_b = np.any((X == 0.0) | (X == 1.0), axis=1)
+
+    def g(P):
+        out = np.zeros((P.shape[0], 3))
+        lid = (np.abs(P[:, 2] - 1.0) < 1e-12) & (P[:, 0] > 1e-12) & (P[:, 0] < 1 - 1e-12) \
+            & (P[:, 1] > 1e-12) & (P[:, 1] < 1 - 1e-12)
+        out[lid, 0] = speed
+        return out
+    return _saddle(f"stokes-cavity-{n}", mesh, mu, 0.0, on_b, g, None, True)
+
+
 def paper_cube(n: int, kind: str = "laplace", lam: float = 1.73e6, mu: float = 1.15e6) -> LinearSystem:
     """Section 4.1's data: u = 0 on z = 0, u = (0, 0, 1) on z = 1."""
     mesh = cube_mesh(n)
