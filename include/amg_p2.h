@@ -163,6 +163,10 @@ typedef struct {
                                       natural-order and colour-sweep kernels  */
     int32_t fused;                 /* 1 if a V-cycle reaching this level runs
                                       it inside the fused coarse kernel       */
+    int32_t schur_levels;          /* Braess-Sarazin: levels of the scalar
+                                      hierarchy of this level's Schur
+                                      complement (0 if not built)             */
+    int64_t nnz_S;                 /* entries of that Schur complement S_l   */
 } amg_level_info;
 
 /* Fill *p with the defaults listed above. */
@@ -204,7 +208,9 @@ int amg_get_level_info(amg_handle h, int32_t level, amg_level_info *info);
 
 /* Copy a level operator to HOST arrays sized from amg_get_level_info:
  * which = 0: A (rowptr n+1, col nnz_A, val nnz_A*bs*bs), 1: B (1x3 blocks),
- * 2: C, 3: P (scalar prolongation from level+1 to level, n rows). */
+ * 2: C, 3: P (scalar prolongation from level+1 to level, n rows),
+ * 4: the Braess-Sarazin Schur complement S_l = C + B (2 diag A)^{-1} B^T
+ *    (n_pres rows, nnz_S scalar entries; Section 3.3). */
 int amg_get_level_matrix(amg_handle h, int32_t level, int32_t which, int32_t *rowptr,
                          int32_t *col, double *val);
 

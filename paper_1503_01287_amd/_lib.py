@@ -62,6 +62,7 @@ class AmgLevelInfo(ctypes.Structure):
         ("nnz_P", ctypes.c_int64),
         ("n_colors", ctypes.c_int32), ("is_coarsest", ctypes.c_int32),
         ("lanes_A", ctypes.c_int32), ("lanes_gs", ctypes.c_int32), ("fused", ctypes.c_int32),
+        ("schur_levels", ctypes.c_int32), ("nnz_S", ctypes.c_int64),
     ]
 
 

@@ -193,6 +193,8 @@ int amg_get_level_info(amg_handle h, int32_t level, amg_level_info *info) {
         info->lanes_gs = L.Gg;
         const int fs = h->tail_start >= 0 ? h->tail_start : h->dense_start;
         info->fused = (fs >= 0 && level >= fs) ? 1 : 0;
+        info->schur_levels = static_cast<int>(L.schur.lv.size());
+        info->nnz_S = L.schur.lv.empty() ? 0 : L.schur.lv[0].S.nnz;
         return AMG_OK;
     });
 }
@@ -210,6 +212,7 @@ int amg_get_level_matrix(amg_handle h, int32_t level, int32_t which, int32_t *ro
             AMG_REQUIRE(!L.coarsest, AMG_EINVAL, "coarsest level has no prolongation");
             m = &L.P;
         }
+        if (which == 4 && !L.schur.lv.empty()) m = &L.schur.lv[0].S;
         AMG_REQUIRE(m != nullptr, AMG_EUNSUPPORTED, "amg_get_level_matrix: operator not present");
         std::vector<int> rp = m->rowptr.download(h->stream), c = m->col.download(h->stream);
         std::vector<double> v = m->val.download(h->stream);

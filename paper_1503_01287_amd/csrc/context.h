@@ -37,6 +37,26 @@ struct LevelMP {
     int vbytes() const { return kind == VAL_F32 ? 4 : 2; }
 };
 
+// One level of the scalar hierarchy of a Braess-Sarazin Schur complement
+// S = C + B A_hat^{-1} B^T (natural row order, rows grouped by colour
+// through `rowid`).
+struct SchurLevel {
+    DMat S;
+    DevBuf<double> dinv;         // 1 / S_ii
+    std::vector<int> cptr;       // rows of colour c: rowid[cptr[c] .. cptr[c+1])
+    DevBuf<int> rowid;
+    DevBuf<double> x, b, r;
+    int G = 8;
+};
+
+// Scalar AMG for S_l: S_l, H_l^T S_l H_l, ... down to the saddle coarsest
+// level, whose Schur matrix is inverted densely.
+struct SchurHier {
+    std::vector<SchurLevel> lv;
+    DevBuf<double> inv;
+    int m = 0;
+};
+
 struct Level {
     int n_lin = 0, n_quad = 0, n = 0, n_pres = 0;
     int mode = 3;             // 3: 3x3 blocks; 1: scalar operator applied per component
@@ -63,6 +83,7 @@ struct Level {
     DMat H, Ht;               // pressure prolongation to this level and its transpose
     DevBuf<double> sgs_scale; // sGS: 1 / diag(B M_A^{-1} B^T + C)
     DevBuf<double> bs_ahat;   // BS: 1 / (2 a_ii) per velocity unknown
+    SchurHier schur;          // BS: scalar hierarchy of this level's Schur complement
     int Gb = 16, Gbt = 16, Gc = 8, Gh = 4, Ght = 8;
     int64_t vlen() const { return 3 * static_cast<int64_t>(n) + n_pres; }
 };
@@ -130,6 +151,7 @@ void build_mixed(amg_ctx *h);
 void precondition_mp(amg_ctx *h, const double *r, double *z);
 // saddle point path
 void saddle_setup_level(amg_ctx *h, Level &L);
+void setup_schur(amg_ctx *h, int l);
 void saddle_precondition(amg_ctx *h, const double *r, double *z);
 void system_matvec(amg_ctx *h, const double *x, double *y);
 void system_residual(amg_ctx *h, const double *b, const double *x, double *r);

@@ -135,9 +135,13 @@ static void check_system(const amg_system *sys) {
         for (int k = 0; k < sys->B_rowptr[sys->n_pres]; ++k)
             AMG_REQUIRE(sys->B_col[k] >= 0 && sys->B_col[k] < n, AMG_EINVAL, "amg_setup: B column out of range");
         if (sys->C_rowptr)
-            for (int k = 0; k < sys->C_rowptr[sys->n_pres]; ++k)
-                AMG_REQUIRE(sys->C_col[k] >= 0 && sys->C_col[k] < sys->n_pres, AMG_EINVAL,
-                            "amg_setup: C column out of range");
+            for (int q = 0; q < sys->n_pres; ++q)
+                for (int k = sys->C_rowptr[q]; k < sys->C_rowptr[q + 1]; ++k) {
+                    AMG_REQUIRE(sys->C_col[k] >= 0 && sys->C_col[k] < sys->n_pres, AMG_EINVAL,
+                                "amg_setup: C column out of range");
+                    AMG_REQUIRE(k == sys->C_rowptr[q] || sys->C_col[k - 1] < sys->C_col[k], AMG_EINVAL,
+                                "amg_setup: C columns not sorted/unique");
+                }
     }
     AMG_REQUIRE(sys->A_rowptr[0] == 0, AMG_EINVAL, "amg_setup: A_rowptr[0] != 0");
     for (int i = 0; i < n; ++i) {
@@ -456,6 +460,86 @@ static void setup_tail(amg_ctx *h) {
     }
 }
 
+// Braess-Sarazin on saddle level l (Section 3.3): the Schur complement
+// S_l = C_l + B_l A_hat^{-1} B_l^T on the structural pattern of B B^T (+ C),
+// its scalar Galerkin hierarchy with the pressure interpolations H_k of the
+// saddle levels below, a colouring per level for Gauss-Seidel and a dense
+// inverse on the saddle coarsest level (last pressure unknown pinned when
+// constants are in the pressure kernel).
+void setup_schur(amg_ctx *h, int l) {
+    hipStream_t s = h->stream;
+    Level &L = h->lv[l];
+    SchurHier &sh = L.schur;
+    sh.lv.clear();
+    {
+        HostCSR bp = download_pattern(L.B, s), btp = download_pattern(L.Bt, s), cp;
+        if (L.C.nnz > 0) cp = download_pattern(L.C, s);
+        HostCSR pat = pattern_product(bp, btp, L.C.nnz > 0 ? &cp : nullptr);
+        SchurLevel first;
+        upload_pattern(first.S, pat, s);
+        first.S.np = 1;
+        first.S.val.alloc(std::max<int64_t>(1, first.S.nnz));
+        const bool hc = L.C.nnz > 0;
+        launch_schur_numeric(L.n_pres, L.B.rowptr.p, L.B.col.p, L.B.val.p, L.B.nnz, L.Bt.rowptr.p, L.Bt.col.p,
+                             L.Bt.val.p, L.Bt.nnz, L.bs_ahat.p, hc ? L.C.rowptr.p : nullptr,
+                             hc ? L.C.col.p : nullptr, hc ? L.C.val.p : nullptr, first.S.rowptr.p, first.S.col.p,
+                             first.S.val.p, s);
+        sh.lv.push_back(std::move(first));
+    }
+    const int last = static_cast<int>(h->lv.size()) - 1;
+    for (int k = l; k < last; ++k) {
+        const Level &V = h->lv[k];
+        DMat SH = spgemm(sh.lv.back().S, V.H, false, s);
+        SchurLevel nx;
+        nx.S = spgemm(V.Ht, SH, true, s);
+        sh.lv.push_back(std::move(nx));
+    }
+    for (size_t k = 0; k < sh.lv.size(); ++k) {
+        SchurLevel &q = sh.lv[k];
+        const int n = q.S.nrows;
+        q.x.alloc(std::max(1, n));
+        q.b.alloc(std::max(1, n));
+        q.r.alloc(std::max(1, n));
+        if (k + 1 == sh.lv.size()) break;
+        HostCSR pat = download_pattern(q.S, s);
+        std::vector<int> colour;
+        const int nc = greedy_colouring(pat, colour);
+        q.cptr.assign(nc + 1, 0);
+        for (int i = 0; i < n; ++i) ++q.cptr[colour[i] + 1];
+        std::partial_sum(q.cptr.begin(), q.cptr.end(), q.cptr.begin());
+        std::vector<int> order(std::max(1, n)), next(q.cptr.begin(), q.cptr.end() - 1);
+        for (int i = 0; i < n; ++i) order[next[colour[i]]++] = i;
+        q.rowid.upload(order, s);
+        q.dinv.alloc(std::max(1, n));
+        DevBuf<int> flag(1);
+        flag.zero(s);
+        launch_diag_inverse(1, n, q.S.rowptr.p, q.S.col.p, q.S.val.p, q.S.nnz, q.dinv.p, flag.p, s);
+        AMG_REQUIRE(flag.download(s)[0] == 0, AMG_EINVAL,
+                    "amg_setup: Braess-Sarazin Schur complement has a zero or missing diagonal entry");
+        q.G = lanes_for(q.S.nnz, n);
+    }
+    SchurLevel &c = sh.lv.back();
+    const int m = c.S.nrows;
+    std::vector<int> rp = c.S.rowptr.download(s), cl = c.S.col.download(s);
+    std::vector<double> v = c.S.val.download(s);
+    std::vector<double> M(static_cast<size_t>(m) * m, 0.0);
+    for (int i = 0; i < m; ++i)
+        for (int k = rp[i]; k < rp[i + 1]; ++k) M[static_cast<size_t>(i) * m + cl[k]] = v[k];
+    if (h->pinned >= 0 && m > 0) {
+        for (int j = 0; j < m; ++j) {
+            M[static_cast<size_t>(m - 1) * m + j] = 0.0;
+            M[static_cast<size_t>(j) * m + m - 1] = 0.0;
+        }
+        M[static_cast<size_t>(m - 1) * m + m - 1] = 1.0;
+    }
+    AMG_REQUIRE(dense_inverse(M, m), AMG_EINVAL, "amg_setup: singular coarsest Schur complement");
+    if (h->pinned >= 0 && m > 0)
+        for (int j = 0; j < m; ++j) M[static_cast<size_t>(m - 1) * m + j] = 0.0;
+    sh.m = m;
+    sh.inv.upload(M, s);
+    AMG_HIP(hipStreamSynchronize(s));
+}
+
 void build_hierarchy(amg_ctx *h, const amg_system *sys) {
     check_system(sys);
     h->saddle = sys->n_pres > 0;
@@ -552,6 +636,8 @@ void build_hierarchy(amg_ctx *h, const amg_system *sys) {
         }
     }
     setup_coarsest(h, h->lv.back());
+    if (h->saddle && p.smoother == AMG_SMOOTH_BS)
+        for (int l = 0; l + 1 < static_cast<int>(h->lv.size()); ++l) setup_schur(h, l);
     if (!h->saddle) {
         setup_tail(h);
         build_mixed(h);

@@ -100,6 +100,33 @@ HostCSR transpose(const HostCSR &a) {
     return t;
 }
 
+HostCSR pattern_product(const HostCSR &x, const HostCSR &y, const HostCSR *extra) {
+    HostCSR c;
+    c.nrows = x.nrows;
+    c.ncols = y.ncols;
+    c.rowptr.assign(c.nrows + 1, 0);
+    std::vector<int> mark(std::max(1, c.ncols), -1), row;
+    for (int i = 0; i < x.nrows; ++i) {
+        row.clear();
+        auto put = [&](int q) {
+            if (mark[q] != i) {
+                mark[q] = i;
+                row.push_back(q);
+            }
+        };
+        for (int k = x.rowptr[i]; k < x.rowptr[i + 1]; ++k) {
+            const int j = x.col[k];
+            for (int m = y.rowptr[j]; m < y.rowptr[j + 1]; ++m) put(y.col[m]);
+        }
+        if (extra)
+            for (int k = extra->rowptr[i]; k < extra->rowptr[i + 1]; ++k) put(extra->col[k]);
+        std::sort(row.begin(), row.end());
+        c.col.insert(c.col.end(), row.begin(), row.end());
+        c.rowptr[i + 1] = static_cast<int>(c.col.size());
+    }
+    return c;
+}
+
 int greedy_colouring(const HostCSR &p, std::vector<int> &colour) {
     colour.assign(p.nrows, -1);
     std::vector<int> seen;  // seen[c] == i: colour c used by a neighbour of i

@@ -33,6 +33,10 @@ HostCSR block_diagonal(const HostCSR &a, const HostCSR &b);
 
 HostCSR transpose(const HostCSR &a);
 
+// Structural pattern of X Y (plus the pattern of `extra`, same shape, if
+// given), rows sorted.
+HostCSR pattern_product(const HostCSR &x, const HostCSR &y, const HostCSR *extra);
+
 // Greedy first-fit colouring in index order over the whole pattern (self
 // loops ignored). Returns the number of colours.
 int greedy_colouring(const HostCSR &pattern, std::vector<int> &colour);

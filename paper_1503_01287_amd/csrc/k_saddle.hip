@@ -195,6 +195,106 @@ void launch_bs_diag(int n, const int *rowptr, const int *col, const double *val,
     AMG_CHECK_LAUNCH();
 }
 
+// ---------------------------------------------------------------- Braess-Sarazin
+// one wavefront per Schur row p; lanes own the row's output entries
+__global__ void __launch_bounds__(SB) k_schur_numeric(int np, const int *brow, const int *bcol, const double *bval,
+                                                      int64_t bnnz, const int *btrow, const int *btcol,
+                                                      const double *btval, int64_t btnnz, const double *d,
+                                                      const int *crow, const int *ccol, const double *cval,
+                                                      const int *srow, const int *scol, double *sval) {
+    const int p = blockIdx.x * (SB / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (p >= np) return;
+    for (int q = srow[p] + lane; q < srow[p + 1]; q += 64) {
+        const int Q = scol[q];
+        double acc = 0.0;
+        for (int k = brow[p]; k < brow[p + 1]; ++k) {
+            const int j = bcol[k];
+            int lo = btrow[j], hi = btrow[j + 1] - 1;
+            while (lo <= hi) {
+                const int mid = (lo + hi) >> 1;
+                const int c = btcol[mid];
+                if (c == Q) {
+                    for (int cc = 0; cc < 3; ++cc)
+                        acc += bval[cc * bnnz + k] * d[3 * j + cc] * btval[cc * btnnz + mid];
+                    break;
+                }
+                if (c < Q) lo = mid + 1;
+                else hi = mid - 1;
+            }
+        }
+        if (crow) {
+            int lo = crow[p], hi = crow[p + 1] - 1;
+            while (lo <= hi) {
+                const int mid = (lo + hi) >> 1;
+                const int c = ccol[mid];
+                if (c == Q) {
+                    acc += cval[mid];
+                    break;
+                }
+                if (c < Q) lo = mid + 1;
+                else hi = mid - 1;
+            }
+        }
+        sval[q] = acc;
+    }
+}
+
+void launch_schur_numeric(int np, const int *brow, const int *bcol, const double *bval, int64_t bnnz,
+                          const int *btrow, const int *btcol, const double *btval, int64_t btnnz, const double *d,
+                          const int *crow, const int *ccol, const double *cval, const int *srow, const int *scol,
+                          double *sval, hipStream_t s) {
+    if (np <= 0) return;
+    k_schur_numeric<<<ceil_div(np, SB / 64), SB, 0, s>>>(np, brow, bcol, bval, bnnz, btrow, btcol, btval, btnnz,
+                                                          d, crow, ccol, cval, srow, scol, sval);
+    AMG_CHECK_LAUNCH();
+}
+
+template <int G>
+__global__ void __launch_bounds__(SB) k_scalar_gs(int nrows, const int *rowptr, const int *col, const double *val,
+                                                  const int *rowid, const double *dinv, const double *b, double *x) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * SB + threadIdx.x;
+    const int g = static_cast<int>(t / G);
+    const int lane = static_cast<int>(t % G);
+    const bool active = g < nrows;
+    const int i = active ? rowid[g] : 0;
+    double s = 0.0;
+    if (active)
+        for (int k = rowptr[i] + lane; k < rowptr[i + 1]; k += G) {
+            const int j = col[k];
+            if (j != i) s += val[k] * x[j];
+        }
+    s = gsum<G>(s);
+    if (!active || lane != 0) return;
+    x[i] = (b[i] - s) * dinv[i];
+}
+
+void launch_scalar_gs(int nrows, const int *rowptr, const int *col, const double *val, const int *rowid,
+                      const double *dinv, const double *b, double *x, int G, hipStream_t s) {
+    if (nrows <= 0) return;
+    const int nb = ceil_div(static_cast<int64_t>(nrows) * G, SB);
+    switch (G) {
+        case 4: k_scalar_gs<4><<<nb, SB, 0, s>>>(nrows, rowptr, col, val, rowid, dinv, b, x); break;
+        case 8: k_scalar_gs<8><<<nb, SB, 0, s>>>(nrows, rowptr, col, val, rowid, dinv, b, x); break;
+        case 16: k_scalar_gs<16><<<nb, SB, 0, s>>>(nrows, rowptr, col, val, rowid, dinv, b, x); break;
+        case 32: k_scalar_gs<32><<<nb, SB, 0, s>>>(nrows, rowptr, col, val, rowid, dinv, b, x); break;
+        default: k_scalar_gs<64><<<nb, SB, 0, s>>>(nrows, rowptr, col, val, rowid, dinv, b, x); break;
+    }
+    AMG_CHECK_LAUNCH();
+}
+
+__global__ void k_add_scaled(int64_t n, const double *d, const double *w, double *u) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * SB + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * SB)
+        u[i] += d[i] * w[i];
+}
+
+void launch_add_scaled(int64_t n, const double *d, const double *w, double *u, hipStream_t s) {
+    if (n <= 0) return;
+    k_add_scaled<<<grid_s(n), SB, 0, s>>>(n, d, w, u);
+    AMG_CHECK_LAUNCH();
+}
+
 // ---------------------------------------------------------------- FGMRES
 constexpr int MD_BLOCKS = 256;
 

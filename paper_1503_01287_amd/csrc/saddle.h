@@ -47,6 +47,20 @@ void launch_scale_diff(int64_t n, const double *d, const double *x, const double
 void launch_bs_diag(int n, const int *rowptr, const int *col, const double *val, int64_t nnz, double *out,
                     hipStream_t s);
 
+// Braess-Sarazin Schur complement on a given (sorted) pattern:
+// S_pq = sum_k sum_c B_pk[c] d[3k+c] B^T_kq[c] + C_pq (C optional, its
+// pattern contained in S's). One lane per output entry, fixed summation order.
+void launch_schur_numeric(int np, const int *brow, const int *bcol, const double *bval, int64_t bnnz,
+                          const int *btrow, const int *btcol, const double *btval, int64_t btnnz, const double *d,
+                          const int *crow, const int *ccol, const double *cval, const int *srow, const int *scol,
+                          double *sval, hipStream_t s);
+// scalar Gauss-Seidel update of the rows rowid[0..nrows) of one colour of
+// S (natural row order): x_i = dinv_i (b_i - sum_{j != i} S_ij x_j)
+void launch_scalar_gs(int nrows, const int *rowptr, const int *col, const double *val, const int *rowid,
+                      const double *dinv, const double *b, double *x, int G, hipStream_t s);
+// u += d .* w
+void launch_add_scaled(int64_t n, const double *d, const double *w, double *u, hipStream_t s);
+
 // FGMRES inner products: h[i] = <V_i, w> for i < k (V_i = V + i * ld) as
 // block partials partial[i * nb + block]; returns nb
 int launch_multidot(const double *V, int64_t ld, int k, const double *w, int64_t n, double *partial,

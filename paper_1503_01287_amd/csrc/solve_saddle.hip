@@ -1,6 +1,6 @@
 // Saddle point systems K [u; p] = [f; g], K = [[A, B^T], [B, -C]]
-// (Section 2.4): Algorithm 1 with the segregated Gauss-Seidel (Uzawa)
-// smoother of Section 3.3, the saddle Galerkin hierarchy K_{l+1} = P^T K_l P
+// (Section 2.4): Algorithm 1 with the segregated Gauss-Seidel (Uzawa) or the
+// Braess-Sarazin smoother of Section 3.3, the saddle Galerkin hierarchy K_{l+1} = P^T K_l P
 // with P = diag(I, J, H), and right-preconditioned flexible GMRES (the
 // paper's outer method for these systems, Section 4.4).
 #include <chrono>
@@ -37,6 +37,10 @@ void saddle_setup_level(amg_ctx *h, Level &L) {
     L.sgs_scale.alloc(std::max(1, L.n_pres));
     launch_sgs_scale(L.n_pres, L.B.rowptr.p, L.B.col.p, L.B.val.p, L.B.nnz, L.dinv.p, L.n, h->prm.sgs_damping,
                      L.C.nnz > 0 ? L.C.rowptr.p : nullptr, L.C.col.p, L.C.val.p, L.C.nnz, L.sgs_scale.p, s);
+    if (h->prm.smoother == AMG_SMOOTH_BS) {
+        L.bs_ahat.alloc(3 * static_cast<size_t>(std::max(1, L.n)));
+        launch_bs_diag(L.n, L.A.rowptr.p, L.A.col.p, L.A.val.p, L.A.nnz, L.bs_ahat.p, s);
+    }
     AMG_HIP(hipStreamSynchronize(s));
 }
 
@@ -128,6 +132,81 @@ static void sgs_step(amg_ctx *h, int l, const double *b, double *x, bool x_zero)
     launch_blk(1, 3, BLK_SGS_P, L.Gb, bb, h->stream);
 }
 
+// Scalar V(1,1) cycle on level k of the Schur hierarchy of saddle level l,
+// from a zero guess: Gauss-Seidel colour by colour (forward before the
+// coarse correction, backward after it), restriction with H^T and
+// prolongation with H of saddle level l + k, dense inverse at the bottom.
+static void schur_vcycle(amg_ctx *h, int l, int k, const double *b, double *x) {
+    SchurHier &sh = h->lv[l].schur;
+    SchurLevel &q = sh.lv[k];
+    hipStream_t s = h->stream;
+    if (k + 1 == static_cast<int>(sh.lv.size())) {
+        launch_dense_gemv(sh.inv.p, sh.m, 1, b, x, s);
+        return;
+    }
+    const int nc = static_cast<int>(q.cptr.size()) - 1;
+    launch_fill(x, 0.0, q.S.nrows, s);
+    for (int c = 0; c < nc; ++c)
+        launch_scalar_gs(q.cptr[c + 1] - q.cptr[c], q.S.rowptr.p, q.S.col.p, q.S.val.p, q.rowid.p + q.cptr[c],
+                         q.dinv.p, b, x, q.G, s);
+    BlkArgs ra = blk(q.S);
+    ra.x = x;
+    ra.b = b;
+    ra.y = q.r.p;
+    launch_blk(1, 1, BLK_RESID, q.G, ra, s);
+    const Level &V = h->lv[l + k];
+    SchurLevel &n = sh.lv[k + 1];
+    BlkArgs ht = blk(V.Ht);
+    ht.x = q.r.p;
+    ht.y = n.b.p;
+    launch_blk(1, 1, BLK_SPMV, V.Ght, ht, s);
+    schur_vcycle(h, l, k + 1, n.b.p, n.x.p);
+    BlkArgs hh = blk(V.H);
+    hh.x = n.x.p;
+    hh.y = x;
+    launch_blk(1, 1, BLK_ADD, V.Gh, hh, s);
+    for (int c = nc - 1; c >= 0; --c)
+        launch_scalar_gs(q.cptr[c + 1] - q.cptr[c], q.S.rowptr.p, q.S.col.p, q.S.val.p, q.rowid.p + q.cptr[c],
+                         q.dinv.p, b, x, q.G, s);
+}
+
+// One Braess-Sarazin step (Section 3.3): K_hat = [[A_hat, B^T], [B, B A_hat^{-1} B^T - S_hat]]
+// with A_hat = 2 diag(A) and S_hat^{-1} one scalar V-cycle for
+// S = C + B A_hat^{-1} B^T. Solving K_hat [du; dp] = [r_u; r_p]:
+// S_hat dp = B A_hat^{-1} r_u - r_p, du = A_hat^{-1}(r_u - B^T dp).
+// The cycle is linear and odd, so it is run on -(B A_hat^{-1} r_u - r_p)
+// and returns -dp exactly (negation commutes with every rounding).
+static void bs_step(amg_ctx *h, int l, const double *b, double *x, bool x_zero) {
+    Level &L = h->lv[l];
+    hipStream_t s = h->stream;
+    const int64_t nu = 3 * static_cast<int64_t>(L.n);
+    if (x_zero)
+        launch_copy(L.r.p, b, L.vlen(), s);
+    else
+        saddle_residual(h, l, b, x, L.r.p);
+    launch_scale(nu, L.bs_ahat.p, L.r.p, L.t.p, s);
+    SchurLevel &q0 = L.schur.lv[0];
+    BlkArgs bb = blk(L.B);
+    bb.x = L.t.p;
+    bb.b = L.r.p + nu;
+    bb.y = q0.b.p;
+    launch_blk(1, 3, BLK_RESID, L.Gb, bb, s);
+    schur_vcycle(h, l, 0, q0.b.p, q0.x.p);
+    launch_axpby(x + nu, q0.x.p, -1.0, 1.0, L.n_pres, s);
+    BlkArgs bt = blk(L.Bt);
+    bt.x = q0.x.p;
+    bt.y = L.r.p;
+    launch_blk(3, 1, BLK_ADD, L.Gbt, bt, s);
+    launch_add_scaled(nu, L.bs_ahat.p, L.r.p, x, s);
+}
+
+static void saddle_step(amg_ctx *h, int l, const double *b, double *x, bool x_zero) {
+    if (h->prm.smoother == AMG_SMOOTH_BS)
+        bs_step(h, l, b, x, x_zero);
+    else
+        sgs_step(h, l, b, x, x_zero);
+}
+
 static void saddle_coarse(amg_ctx *h, const double *b, double *x) {
     ProfScope ps(h, "coarse", static_cast<double>(h->coarse_m) * h->coarse_m * 8.0);
     launch_dense_gemv(h->coarse_inv.p, h->coarse_m, 1, b, x, h->stream);
@@ -141,7 +220,7 @@ static void saddle_cycle(amg_ctx *h, int l, const double *b, double *x, bool x_z
     }
     const amg_params &p = h->prm;
     if (x_zero) launch_fill(x, 0.0, L.vlen(), h->stream);
-    for (int k = 0; k < p.pre; ++k) sgs_step(h, l, b, x, x_zero && k == 0);
+    for (int k = 0; k < p.pre; ++k) saddle_step(h, l, b, x, x_zero && k == 0);
     saddle_residual(h, l, b, x, L.r.p);
     Level &C = h->lv[l + 1];
     const int64_t nu = 3 * static_cast<int64_t>(L.n), ncu = 3 * static_cast<int64_t>(C.n);
@@ -181,7 +260,7 @@ static void saddle_cycle(amg_ctx *h, int l, const double *b, double *x, bool x_z
         hh.y = x + nu;
         launch_blk(1, 1, BLK_ADD, L.Gh, hh, h->stream);
     }
-    for (int k = 0; k < p.post; ++k) sgs_step(h, l, b, x, false);
+    for (int k = 0; k < p.post; ++k) saddle_step(h, l, b, x, false);
 }
 
 void saddle_precondition(amg_ctx *h, const double *r, double *z) {
@@ -189,7 +268,7 @@ void saddle_precondition(amg_ctx *h, const double *r, double *z) {
     for (int k = 0; k < cyc; ++k) saddle_cycle(h, 0, r, z, k == 0);
 }
 
-void saddle_smooth(amg_ctx *h, int l, const double *b, double *x) { sgs_step(h, l, b, x, false); }
+void saddle_smooth(amg_ctx *h, int l, const double *b, double *x) { saddle_step(h, l, b, x, false); }
 
 static double norm2(amg_ctx *h, const double *v);
 

@@ -151,7 +151,7 @@ class AMGSolver:
     def level_matrix(self, level: int, which: str = "A"):
         """(rowptr, col, val) of a level operator; val has shape (nnz, np)."""
         info = self.level_info(level)
-        code = {"A": 0, "B": 1, "C": 2, "P": 3}[which]
+        code = {"A": 0, "B": 1, "C": 2, "P": 3, "S": 4}[which]
         n = info.n_lin + info.n_quad
         if which == "A":
             nnz, width, nrows = info.nnz_A, info.bs * info.bs, n
@@ -159,6 +159,8 @@ class AMGSolver:
             nnz, width, nrows = info.nnz_P, 1, n
         elif which == "B":
             nnz, width, nrows = info.nnz_B, 3, info.n_pres
+        elif which == "S":
+            nnz, width, nrows = info.nnz_S, 1, info.n_pres
         else:
             nnz, width, nrows = info.nnz_C, 1, info.n_pres
         rowptr = np.zeros(nrows + 1, dtype=np.int32)
