@@ -105,6 +105,30 @@ def training_sizes(count: int, nmin: int = 16, nmax: int = 32) -> list[int]:
     return [int(v) for v in g.integers(nmin, nmax + 1, count)]
 
 
+# --------------------------------------------------------------------------
+# Damping-weight network: initial parameters and random test batches.
+# Layer shapes 8 -> 32 -> 32 -> 1 in the flat order W1 (32x8), b1, W2 (32x32),
+# b2, W3 (32), b3; weights uniform in +-sqrt(6 / (fan_in + fan_out)), biases 0.
+# --------------------------------------------------------------------------
+MLP_LAYERS = ((8, 32), (32, 32), (32, 1))
+
+
+def mlp_init(seed: int = 0) -> np.ndarray:
+    g = rng(LAPLACE_TRAIN, 2 * 10**6 + seed)
+    parts = []
+    for fan_in, fan_out in MLP_LAYERS:
+        a = np.sqrt(6.0 / (fan_in + fan_out))
+        parts.append(g.uniform(-a, a, fan_in * fan_out))
+        parts.append(np.zeros(fan_out))
+    return np.concatenate(parts)
+
+
+def mlp_batch(n: int, seed: int = 0) -> tuple[np.ndarray, np.ndarray]:
+    """n random feature rows (uniform in [0, 1.5)) and targets in [0.3, 1.1)."""
+    g = rng(LAPLACE_TRAIN, 3 * 10**6 + seed)
+    return g.uniform(0.0, 1.5, (n, 8)), g.uniform(0.3, 1.1, n)
+
+
 WORKLOADS = {
     LAPLACE_SMALL: dict(name="vector-laplacian-4x4x4", n=4),
     ELASTICITY: dict(name="elasticity-32x32x32", n=32, E=1.0, nu=0.3, sigma=0.1),
