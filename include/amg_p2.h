@@ -45,6 +45,7 @@ extern "C" {
 #endif
 
 typedef struct amg_ctx *amg_handle;
+typedef struct amg_mlp *amg_mlp_handle; /* damping-weight network */
 typedef void *amg_stream; /* hipStream_t */
 
 /* ---- status codes ---------------------------------------------------- */
@@ -141,6 +142,13 @@ typedef struct {
                              rounding order.                                  */
     int32_t autotune;     /* 1 (default): time the row kernels' lanes-per-row
                              choices on each level at setup; 0: heuristic.   */
+    amg_mlp_handle omega_model; /* JA only, SPD only, NULL (default) = off:
+                             the damping of every non-coarsest level is the
+                             network's prediction from that level's row
+                             features (amg_level_features); a prediction
+                             that is not finite or not inside (0.2, 1.2)
+                             falls back to omega / level_omega. Only read
+                             during amg_setup.                               */
 } amg_params;
 
 typedef struct {
@@ -163,6 +171,7 @@ typedef struct {
                                       natural-order and colour-sweep kernels  */
     int32_t fused;                 /* 1 if a V-cycle reaching this level runs
                                       it inside the fused coarse kernel       */
+    double omega;                  /* JA damping used on this level          */
     int32_t schur_levels;          /* Braess-Sarazin: levels of the scalar
                                       hierarchy of this level's Schur
                                       complement (0 if not built)             */
@@ -216,6 +225,49 @@ int amg_get_level_matrix(amg_handle h, int32_t level, int32_t which, int32_t *ro
 
 /* Colour of every node of level l (host array of n_lin + n_quad int32). */
 int amg_get_level_colors(amg_handle h, int32_t level, int32_t *colors);
+
+/* ---- learned Jacobi damping -------------------------------------------
+ * Not in the paper, which damps block Jacobi with a fixed 0.5 (Section 4.2):
+ * a multilayer perceptron 8 -> 32 -> 32 -> 1 (tanh hidden units, output
+ * omega = 0.2 + sigmoid(z) in (0.2, 1.2)) maps eight statistics of the rows
+ * of A_l to a damping weight for level l. Training (full-batch Adam on the
+ * mean squared error to target weights) and inference run on the GPU in FP32.
+ *
+ * Parameters are AMG_MLP_PARAMS floats in the order W1 (32x8 row-major), b1
+ * (32), W2 (32x32 row-major), b2 (32), W3 (32), b3 (1). Feature and target
+ * arrays are HOST arrays: X is n x AMG_MLP_FEATURES row-major, y has n values.
+ */
+#define AMG_MLP_FEATURES 8
+#define AMG_MLP_PARAMS 1377
+
+/* Create a network from host parameters (copied); Adam state starts at zero.
+ * Work is ordered on `stream`. */
+int amg_mlp_create(const float *params, amg_stream stream, amg_mlp_handle *out);
+int amg_mlp_get_params(amg_mlp_handle m, float *params);
+/* omega[i] for every feature row (host arrays, n >= 1). */
+int amg_mlp_forward(amg_mlp_handle m, const float *X, int32_t n, float *omega);
+/* Mean squared error to y and its gradient (AMG_MLP_PARAMS floats). */
+int amg_mlp_gradient(amg_mlp_handle m, const float *X, const float *y, int32_t n, float *loss, float *grad);
+/* `steps` full-batch Adam steps (beta1 0.9, beta2 0.999, eps 1e-8, learning
+ * rate lr) continuing the handle's step count; loss_history (host, may be
+ * NULL) receives the loss before every step. */
+int amg_mlp_train(amg_mlp_handle m, const float *X, const float *y, int32_t n, int32_t steps, float lr,
+                  float *loss_history);
+void amg_mlp_destroy(amg_mlp_handle m);
+
+/* Replace the JA damping of every level after setup (level l uses
+ * omega[min(l, n - 1)]); rebuilds the fused coarse end of the cycle, which
+ * holds the weights. JA smoother, SPD systems only. */
+int amg_set_level_omega(amg_handle h, int32_t n, const double *omega);
+
+/* The network's input for level l of an SPD hierarchy (host array of 8):
+ * over the scalar rows of A_l (row r of node i; a bs = 1 operator stands for
+ * A_s (x) I_3), with d the diagonal entry and a_j the other stored entries,
+ * rho = sum |a_j| / |d|, sigma = (d + sum a_j) / d, tau = sqrt(sum a_j^2) / |d|
+ * (all 0 for a zero diagonal), nz = stored scalars of the row:
+ *   [mean rho, max rho, std rho, mean sigma, mean tau, mean nz / 64,
+ *    l / 10, log10(3 N_l) / 7]. */
+int amg_level_features(amg_handle h, int32_t level, double *features);
 
 /* Per-kernel timing of the hot loops with HIP events recorded on the
  * library's launch stream (the stream of the call that launches them).

@@ -24,6 +24,7 @@ PREC = {"FP64": 0, "MIXED": 1, "FP32": 2}
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _f64p = ctypes.POINTER(ctypes.c_double)
+_f32p = ctypes.POINTER(ctypes.c_float)
 
 
 class AmgSystem(ctypes.Structure):
@@ -46,6 +47,7 @@ class AmgParams(ctypes.Structure):
         ("restart", ctypes.c_int32), ("precision", ctypes.c_int32),
         ("n_level_omega", ctypes.c_int32), ("level_omega", _f64p),
         ("fuse_coarse", ctypes.c_int32), ("autotune", ctypes.c_int32),
+        ("omega_model", ctypes.c_void_p),
     ]
 
 
@@ -62,7 +64,7 @@ class AmgLevelInfo(ctypes.Structure):
         ("nnz_P", ctypes.c_int64),
         ("n_colors", ctypes.c_int32), ("is_coarsest", ctypes.c_int32),
         ("lanes_A", ctypes.c_int32), ("lanes_gs", ctypes.c_int32), ("fused", ctypes.c_int32),
-        ("schur_levels", ctypes.c_int32), ("nnz_S", ctypes.c_int64),
+        ("omega", ctypes.c_double), ("schur_levels", ctypes.c_int32), ("nnz_S", ctypes.c_int64),
     ]
 
 
@@ -86,6 +88,15 @@ SIGNATURES = {
     "amg_profile_read": (ctypes.c_int, [_H, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64),
                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "amg_destroy": (None, [_H]),
+    "amg_mlp_create": (ctypes.c_int, [_f32p, _S, ctypes.POINTER(ctypes.c_void_p)]),
+    "amg_mlp_get_params": (ctypes.c_int, [ctypes.c_void_p, _f32p]),
+    "amg_mlp_forward": (ctypes.c_int, [ctypes.c_void_p, _f32p, ctypes.c_int32, _f32p]),
+    "amg_mlp_gradient": (ctypes.c_int, [ctypes.c_void_p, _f32p, _f32p, ctypes.c_int32, _f32p, _f32p]),
+    "amg_mlp_train": (ctypes.c_int, [ctypes.c_void_p, _f32p, _f32p, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.c_float, _f32p]),
+    "amg_mlp_destroy": (None, [ctypes.c_void_p]),
+    "amg_level_features": (ctypes.c_int, [_H, ctypes.c_int32, _f64p]),
+    "amg_set_level_omega": (ctypes.c_int, [_H, ctypes.c_int32, _f64p]),
     "amg_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "amg_last_error": (ctypes.c_char_p, []),
 }

@@ -1,6 +1,7 @@
 // C ABI entry points (include/amg_p2.h). Every call catches library errors
 // and returns an AMG_* code; the message is kept per thread for
 // amg_last_error().
+#include <cmath>
 #include <cstring>
 
 #include "context.h"
@@ -60,6 +61,7 @@ void amg_default_params(amg_params *p) {
     p->level_omega = nullptr;
     p->fuse_coarse = 1;
     p->autotune = 1;
+    p->omega_model = nullptr;
 }
 
 int amg_setup(const amg_system *sys, const amg_params *params, amg_stream stream, amg_handle *out) {
@@ -80,6 +82,8 @@ int amg_setup(const amg_system *sys, const amg_params *params, amg_stream stream
             AMG_REQUIRE(p.smoother == AMG_SMOOTH_JA || p.smoother == AMG_SMOOTH_GS, AMG_EINVAL,
                         "amg_setup: SPD systems need the JA or GS smoother");
         }
+        AMG_REQUIRE(!p.omega_model || (p.smoother == AMG_SMOOTH_JA && sys->n_pres == 0), AMG_EINVAL,
+                    "amg_setup: omega_model needs the JA smoother on an SPD system");
         AMG_REQUIRE(p.krylov != AMG_KRYLOV_FGMRES || p.restart >= 1, AMG_EINVAL, "amg_setup: restart < 1");
         AMG_REQUIRE(p.pre >= 0 && p.post >= 0 && p.cycles >= 1 && p.nu >= 1 && p.nu <= 2, AMG_EINVAL,
                     "amg_setup: invalid smoothing/cycle counts");
@@ -97,6 +101,7 @@ int amg_setup(const amg_system *sys, const amg_params *params, amg_stream stream
             delete h;
             throw;
         }
+        h->prm.omega_model = nullptr;  // only read during setup
         *out = h;
         return AMG_OK;
     });
@@ -194,6 +199,7 @@ int amg_get_level_info(amg_handle h, int32_t level, amg_level_info *info) {
         const int fs = h->tail_start >= 0 ? h->tail_start : h->dense_start;
         info->fused = (fs >= 0 && level >= fs) ? 1 : 0;
         info->schur_levels = static_cast<int>(L.schur.lv.size());
+        info->omega = jacobi_omega(h, level);
         info->nnz_S = L.schur.lv.empty() ? 0 : L.schur.lv[0].S.nnz;
         return AMG_OK;
     });
@@ -268,6 +274,125 @@ void amg_destroy(amg_handle h) {
     if (!h) return;
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     delete h;
+}
+
+// ---------------------------------------------------------------- learned damping
+int amg_mlp_create(const float *params, amg_stream stream, amg_mlp_handle *out) {
+    return guarded([&]() -> int {
+        AMG_REQUIRE(params && out, AMG_EINVAL, "amg_mlp_create: null argument");
+        *out = nullptr;
+        auto *m = new amg_mlp();
+        try {
+            m->stream = static_cast<hipStream_t>(stream);
+            m->theta.upload(params, MLP_NP, m->stream);
+            m->m.alloc(MLP_NP);
+            m->v.alloc(MLP_NP);
+            m->m.zero(m->stream);
+            m->v.zero(m->stream);
+            m->grad.alloc(MLP_NP);
+            m->loss.alloc(1);
+            AMG_HIP(hipStreamSynchronize(m->stream));
+        } catch (...) {
+            delete m;
+            throw;
+        }
+        *out = m;
+        return AMG_OK;
+    });
+}
+
+int amg_mlp_get_params(amg_mlp_handle m, float *params) {
+    return guarded([&]() -> int {
+        AMG_REQUIRE(m && params, AMG_EINVAL, "amg_mlp_get_params: null argument");
+        AMG_HIP(hipMemcpyAsync(params, m->theta.p, MLP_NP * sizeof(float), hipMemcpyDeviceToHost, m->stream));
+        AMG_HIP(hipStreamSynchronize(m->stream));
+        return AMG_OK;
+    });
+}
+
+static void mlp_upload(amg_mlp *m, const float *X, const float *y, int n) {
+    AMG_REQUIRE(X && n >= 1, AMG_EINVAL, "amg_mlp: need at least one feature row");
+    m->w.reserve(n);
+    AMG_HIP(hipMemcpyAsync(m->w.X.p, X, static_cast<size_t>(n) * MLP_NF * sizeof(float), hipMemcpyHostToDevice,
+                           m->stream));
+    if (y) AMG_HIP(hipMemcpyAsync(m->w.y.p, y, static_cast<size_t>(n) * sizeof(float), hipMemcpyHostToDevice, m->stream));
+}
+
+int amg_mlp_forward(amg_mlp_handle m, const float *X, int32_t n, float *omega) {
+    return guarded([&]() -> int {
+        AMG_REQUIRE(m && omega, AMG_EINVAL, "amg_mlp_forward: null argument");
+        mlp_upload(m, X, nullptr, n);
+        mlp_forward(m->theta.p, m->w.X.p, n, m->w, m->stream);
+        AMG_HIP(hipMemcpyAsync(omega, m->w.om.p, n * sizeof(float), hipMemcpyDeviceToHost, m->stream));
+        AMG_HIP(hipStreamSynchronize(m->stream));
+        return AMG_OK;
+    });
+}
+
+int amg_mlp_gradient(amg_mlp_handle m, const float *X, const float *y, int32_t n, float *loss, float *grad) {
+    return guarded([&]() -> int {
+        AMG_REQUIRE(m && y && loss && grad, AMG_EINVAL, "amg_mlp_gradient: null argument");
+        mlp_upload(m, X, y, n);
+        mlp_forward(m->theta.p, m->w.X.p, n, m->w, m->stream);
+        mlp_backward(m->theta.p, n, m->w, m->grad.p, m->loss.p, m->stream);
+        AMG_HIP(hipMemcpyAsync(grad, m->grad.p, MLP_NP * sizeof(float), hipMemcpyDeviceToHost, m->stream));
+        AMG_HIP(hipMemcpyAsync(loss, m->loss.p, sizeof(float), hipMemcpyDeviceToHost, m->stream));
+        AMG_HIP(hipStreamSynchronize(m->stream));
+        return AMG_OK;
+    });
+}
+
+int amg_mlp_train(amg_mlp_handle m, const float *X, const float *y, int32_t n, int32_t steps, float lr,
+                  float *loss_history) {
+    return guarded([&]() -> int {
+        AMG_REQUIRE(m && y, AMG_EINVAL, "amg_mlp_train: null argument");
+        AMG_REQUIRE(steps >= 0 && lr > 0.0f, AMG_EINVAL, "amg_mlp_train: steps >= 0 and lr > 0 required");
+        mlp_upload(m, X, y, n);
+        DevBuf<float> hist(std::max(1, steps));
+        const double b1 = 0.9, b2 = 0.999;
+        for (int k = 0; k < steps; ++k) {
+            const int t = ++m->t;
+            mlp_forward(m->theta.p, m->w.X.p, n, m->w, m->stream);
+            mlp_backward(m->theta.p, n, m->w, m->grad.p, hist.p + k, m->stream);
+            mlp_adam(m->theta.p, m->grad.p, m->m.p, m->v.p, lr, static_cast<float>(b1), static_cast<float>(b2),
+                     static_cast<float>(1.0 - std::pow(b1, t)), static_cast<float>(1.0 - std::pow(b2, t)), 1e-8f,
+                     m->stream);
+        }
+        if (loss_history && steps > 0)
+            AMG_HIP(hipMemcpyAsync(loss_history, hist.p, steps * sizeof(float), hipMemcpyDeviceToHost, m->stream));
+        AMG_HIP(hipStreamSynchronize(m->stream));
+        return AMG_OK;
+    });
+}
+
+void amg_mlp_destroy(amg_mlp_handle m) {
+    if (!m) return;
+    if (m->stream) (void)hipStreamSynchronize(m->stream);
+    delete m;
+}
+
+int amg_set_level_omega(amg_handle h, int32_t n, const double *omega) {
+    return guarded([&]() -> int {
+        AMG_REQUIRE(h && omega && n >= 1, AMG_EINVAL, "amg_set_level_omega: null argument or n < 1");
+        AMG_REQUIRE(!h->saddle && h->prm.smoother == AMG_SMOOTH_JA, AMG_EINVAL,
+                    "amg_set_level_omega: needs the JA smoother on an SPD system");
+        for (int i = 0; i < n; ++i)
+            AMG_REQUIRE(std::isfinite(omega[i]), AMG_EINVAL, "amg_set_level_omega: weight not finite");
+        h->level_omega.assign(omega, omega + n);
+        setup_tail(h);
+        refresh_tail_f32(h);
+        return AMG_OK;
+    });
+}
+
+int amg_level_features(amg_handle h, int32_t level, double *features) {
+    return guarded([&]() -> int {
+        AMG_REQUIRE(h && features, AMG_EINVAL, "amg_level_features: null argument");
+        AMG_REQUIRE(level >= 0 && level < static_cast<int>(h->lv.size()), AMG_EINVAL, "bad level");
+        const Level &L = h->lv[level];
+        row_features(L.mode, L.n, L.A.rowptr.p, L.A.col.p, L.A.val.p, L.A.nnz, level, features, h->stream);
+        return AMG_OK;
+    });
 }
 
 const char *amg_status_string(int status) {

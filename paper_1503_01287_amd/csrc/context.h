@@ -8,6 +8,7 @@
 #include "common.h"
 #include "host_setup.h"
 #include "kernels.h"
+#include "learn.h"
 #include "mixed.h"
 #include "saddle.h"
 #include "tail.h"
@@ -152,6 +153,13 @@ void precondition_mp(amg_ctx *h, const double *r, double *z);
 // saddle point path
 void saddle_setup_level(amg_ctx *h, Level &L);
 void setup_schur(amg_ctx *h, int l);
+// JA damping per level from the network of prm.omega_model (fallback: prm.omega)
+void predict_level_omega(amg_ctx *h);
+double jacobi_omega(const amg_ctx *h, int l);
+// (re)build the fused coarse end of the SPD V-cycle from the current weights
+void setup_tail(amg_ctx *h);
+// FP32 copy of the assembled coarse-end operator (reduced-precision cycle)
+void refresh_tail_f32(amg_ctx *h);
 void saddle_precondition(amg_ctx *h, const double *r, double *z);
 void system_matvec(amg_ctx *h, const double *x, double *y);
 void system_residual(amg_ctx *h, const double *b, const double *x, double *r);

@@ -405,7 +405,7 @@ static int tail_descriptors(amg_ctx *h, int t, DevBuf<TailLevel> &buf, TailArgs 
 //    workgroup of the tail kernel, and applied as a single GEMV.
 //  * LDS tail: if even the finest level is small, the whole V-cycle runs in
 //    one workgroup with the vectors in LDS.
-static void setup_tail(amg_ctx *h) {
+void setup_tail(amg_ctx *h) {
     h->tail_start = -1;
     h->dense_start = -1;
     h->tail_m = 0;
@@ -540,6 +540,41 @@ void setup_schur(amg_ctx *h, int l) {
     AMG_HIP(hipStreamSynchronize(s));
 }
 
+double jacobi_omega(const amg_ctx *h, int l) {
+    if (h->level_omega.empty()) return h->prm.omega;
+    return h->level_omega[std::min<size_t>(l, h->level_omega.size() - 1)];
+}
+
+// Learned damping: the row features of every non-coarsest level go through
+// the network in one batch; predictions outside (0.2, 1.2) or not finite
+// fall back to the fixed weight of that level.
+void predict_level_omega(amg_ctx *h) {
+    amg_mlp *m = h->prm.omega_model;
+    const int L = static_cast<int>(h->lv.size()) - 1;
+    if (!m || L <= 0) return;
+    hipStream_t s = h->stream;
+    std::vector<float> X(static_cast<size_t>(L) * MLP_NF);
+    for (int l = 0; l < L; ++l) {
+        const Level &V = h->lv[l];
+        double f[MLP_NF];
+        row_features(V.mode, V.n, V.A.rowptr.p, V.A.col.p, V.A.val.p, V.A.nnz, l, f, s);
+        for (int k = 0; k < MLP_NF; ++k) X[static_cast<size_t>(l) * MLP_NF + k] = static_cast<float>(f[k]);
+    }
+    m->w.reserve(L);
+    AMG_HIP(hipMemcpyAsync(m->w.X.p, X.data(), X.size() * sizeof(float), hipMemcpyHostToDevice, s));
+    mlp_forward(m->theta.p, m->w.X.p, L, m->w, s);
+    std::vector<float> om(L);
+    AMG_HIP(hipMemcpyAsync(om.data(), m->w.om.p, L * sizeof(float), hipMemcpyDeviceToHost, s));
+    AMG_HIP(hipStreamSynchronize(s));
+    std::vector<double> w(L + 1);
+    for (int l = 0; l < L; ++l) {
+        const double o = om[l];
+        w[l] = (std::isfinite(o) && o > MLP_OMEGA_MIN && o < MLP_OMEGA_MIN + MLP_OMEGA_SPAN) ? o : jacobi_omega(h, l);
+    }
+    w[L] = w[L - 1];
+    h->level_omega = std::move(w);
+}
+
 void build_hierarchy(amg_ctx *h, const amg_system *sys) {
     check_system(sys);
     h->saddle = sys->n_pres > 0;
@@ -623,6 +658,7 @@ void build_hierarchy(amg_ctx *h, const amg_system *sys) {
         h->lv.push_back(std::move(next));
     }
     h->lv.back().coarsest = true;
+    if (p.omega_model && p.smoother == AMG_SMOOTH_JA && !h->saddle) predict_level_omega(h);
     for (Level &L : h->lv) {
         const size_t nv = static_cast<size_t>(L.vlen());
         L.x.alloc(nv);

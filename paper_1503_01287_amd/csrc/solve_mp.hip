@@ -53,12 +53,17 @@ void build_mixed(amg_ctx *h) {
         M.rval.alloc(L.R.nnz);
         launch_to_f32(L.R.val.p, M.rval.p, L.R.nnz, s);
     }
-    if (h->tail_m > 0) {
+    refresh_tail_f32(h);
+}
+
+void refresh_tail_f32(amg_ctx *h) {
+    h->tail_dense32.release();
+    if (h->mixed && h->tail_m > 0) {
         const int64_t mm = static_cast<int64_t>(h->tail_m) * h->tail_m;
         h->tail_dense32.alloc(mm);
-        launch_to_f32(h->tail_dense.p, h->tail_dense32.p, mm, s);
+        launch_to_f32(h->tail_dense.p, h->tail_dense32.p, mm, h->stream);
     }
-    AMG_HIP(hipStreamSynchronize(s));
+    AMG_HIP(hipStreamSynchronize(h->stream));
 }
 
 static std::string tag(const char *cls, int l) { return std::string(cls) + ".L" + std::to_string(l); }

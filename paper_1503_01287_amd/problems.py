@@ -97,6 +97,16 @@ def _basis_grads(G: np.ndarray) -> np.ndarray:
     return np.concatenate([lin, quad], axis=2)
 
 
+def _element_scalar_laplace(G, vol):
+    """sum_q w grad phi_k . grad phi_m per element, (nt, 10, 10)."""
+    dphi = _basis_grads(G)                                    # (nt, Q, 10, 3)
+    nt, nq = dphi.shape[0], dphi.shape[1]
+    w = vol[:, None] * _QW[None, :]
+    X = dphi.transpose(0, 2, 1, 3).reshape(nt, 10, nq * 3)
+    Xw = (dphi * w[:, :, None, None]).transpose(0, 2, 1, 3).reshape(nt, 10, nq * 3)
+    return np.matmul(Xw, np.swapaxes(X, 1, 2))
+
+
 def _element_blocks(G, vol, kind, lam, mu):
     dphi = _basis_grads(G)                                    # (nt, Q, 10, 3)
     nt = dphi.shape[0]
@@ -145,8 +155,11 @@ def velocity_operator(mesh: CubeMesh, kind: str, lam=0.0, mu=1.0, scalar=False):
     val = np.zeros((col.shape[0], width))
     for a, b in _batches(T.shape[0]):
         G, vol = _geometry(mesh, mesh.tet[a:b])
-        K = _element_blocks(G, vol, kind, lam, mu)
-        K = K[..., 0, 0] if scalar else K
+        if scalar and kind == "laplace":
+            K = _element_scalar_laplace(G, vol)
+        else:
+            K = _element_blocks(G, vol, kind, lam, mu)
+            K = K[..., 0, 0] if scalar else K
         val += _accumulate(where[a * 100:b * 100], K.reshape(-1, width), col.shape[0])
     return rowptr, col, val
 

@@ -62,7 +62,7 @@ class AMGSolver:
                  max_levels: int = 10, separate: bool = True, level_omega=None,
                  sgs_omega: float = 0.125, sgs_damping: float = 0.5, restart: int = 100,
                  omega: float | None = None, fuse_coarse: bool = True, autotune: bool = True,
-                 stream=None):
+                 omega_model=None, stream=None):
         L = C.lib()
         p = C.default_params()
         sm = parse_smoother(smoother)
@@ -78,6 +78,8 @@ class AMGSolver:
         p.precision = C.PREC[precision]
         p.fuse_coarse = 1 if fuse_coarse else 0
         p.autotune = 1 if autotune else 0
+        if omega_model is not None:
+            p.omega_model = omega_model.h
         self._omega_buf = None
         if level_omega is not None:
             self._omega_buf = np.ascontiguousarray(level_omega, dtype=np.float64)
@@ -170,6 +172,17 @@ class AMGSolver:
                                              C._ptr(col, ctypes.c_int32), C._ptr(val, ctypes.c_double)),
                 "amg_get_level_matrix")
         return rowptr, col[:nnz], val[: nnz * width].reshape(nnz, width)
+
+    def set_level_omega(self, omega) -> None:
+        """New JA damping per level (level l uses omega[min(l, len - 1)])."""
+        w = np.ascontiguousarray(omega, dtype=np.float64)
+        C.check(C.lib().amg_set_level_omega(self.h, w.size, C._ptr(w, ctypes.c_double)), "amg_set_level_omega")
+
+    def level_features(self, level: int) -> np.ndarray:
+        """The damping network's eight input features of level `level`."""
+        out = np.zeros(8, dtype=np.float64)
+        C.check(C.lib().amg_level_features(self.h, level, C._ptr(out, ctypes.c_double)), "amg_level_features")
+        return out
 
     def level_colors(self, level: int) -> np.ndarray:
         info = self.level_info(level)

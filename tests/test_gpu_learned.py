@@ -1,0 +1,174 @@
+"""Learned per-level Jacobi damping on the GPU against the FP64 oracle: row
+features, network forward, gradient and Adam training, the setup hook that
+sets the damping from the network (with its fallback), and what the trained
+network gains over the fixed weight 0.5."""
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_1503_01287_amd as amg  # noqa: E402
+import synth  # noqa: E402
+from paper_1503_01287_amd import learned  # noqa: E402
+from oracle import amg as oamg, krylov, mlp, workloads  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def f64(a):
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("name", ["laplace4", "laplace7", "elast4"])
+def test_features_match_oracle(name):
+    n = int(name[-1])
+    if name.startswith("laplace"):
+        hs, o = amg.problems.laplace(n), workloads.laplace(n)
+    else:
+        hs, o = amg.problems.elasticity(n), workloads.elasticity(n)
+    s = amg.AMGSolver(hs, smoother="JA-1-1-0.5")
+    h = oamg.setup(o.A, o.nlin, o.nquad)
+    assert s.num_levels == len(h.levels)
+    for l in range(len(h.levels)):
+        got = s.level_features(l)
+        ref = mlp.row_features(h.levels[l].A, l)
+        assert np.abs(got - ref).max() < 1e-12 * max(1.0, np.abs(ref).max()), (name, l, got, ref)
+    s.close()
+
+
+def test_forward_matches_oracle():
+    theta = synth.mlp_init(0)
+    X, _ = synth.mlp_batch(300, 4)
+    m = learned.DampingModel(theta)
+    got = m.forward(X)
+    ref, _ = mlp.forward(f64(theta), f64(X))
+    assert np.abs(got - ref).max() < 2e-6
+    m.close()
+
+
+def test_gradient_matches_oracle():
+    theta = synth.mlp_init(1)
+    X, y = synth.mlp_batch(77, 5)
+    m = learned.DampingModel(theta)
+    loss, g = m.gradient(X, y)
+    L, gref = mlp.gradient(f64(theta), f64(X), f64(y))
+    assert abs(loss - L) < 1e-5 * L
+    assert np.abs(g - gref).max() < 1e-4 * np.abs(gref).max()
+    m.close()
+
+
+def test_adam_training_matches_oracle():
+    theta = synth.mlp_init(2)
+    X, _ = synth.mlp_batch(64, 6)
+    y, _ = mlp.forward(synth.mlp_init(9), X)
+    m = learned.DampingModel(theta)
+    hist = m.train(X, y, 60, 0.01)
+    th_ref, hist_ref = mlp.train(f64(theta), f64(X), f64(y), 60, 0.01)
+    assert np.abs(hist - hist_ref).max() < 1e-3 * hist_ref[0]
+    assert hist[-1] < 0.5 * hist[0]
+    # continuing the same handle continues Adam's step count
+    more = m.train(X, y, 20, 0.01)
+    _, hist_ref2 = mlp.train(f64(theta), f64(X), f64(y), 80, 0.01)
+    assert np.abs(more - hist_ref2[60:]).max() < 1e-3 * hist_ref[0]
+    got = m.forward(X)
+    th2, _ = mlp.train(f64(theta), f64(X), f64(y), 80, 0.01)
+    ref, _ = mlp.forward(th2, f64(X))
+    assert np.abs(got - ref).max() < 1e-3
+    m.close()
+
+
+def test_setup_takes_damping_from_network_and_solve_matches_oracle():
+    hs, o = amg.problems.laplace(6), workloads.laplace(6)
+    plain = amg.AMGSolver(hs, smoother="JA-1-1-0.5")
+    F = np.array([plain.level_features(l) for l in range(plain.num_levels - 1)])
+    plain.close()
+    # a network pulled towards weights 0.6, 0.65, ... on this hierarchy's levels
+    m = learned.DampingModel(synth.mlp_init(3))
+    m.train(F, 0.6 + 0.05 * np.arange(len(F)), 300, 0.01)
+    s = amg.AMGSolver(hs, smoother="JA-1-1-0.5", omega_model=m)
+    h = oamg.setup(o.A, o.nlin, o.nquad)
+    L = s.num_levels - 1
+    feats = np.array([s.level_features(l) for l in range(L)])
+    want = m.forward(feats)
+    om = np.array([s.level_info(l).omega for l in range(L)])
+    assert np.abs(om - want).max() < 1e-7, (om, want)
+    assert np.all(np.abs(om - 0.5) > 1e-3)
+    ref_w, _ = mlp.forward(f64(m.params()), np.array([mlp.row_features(h.levels[l].A, l) for l in range(L)]))
+    assert np.abs(om - ref_w).max() < 1e-5
+    # the solve with these weights is the oracle's solve with the same weights
+    b = torch.from_numpy(hs.rhs).to(DEV)
+    x = torch.zeros_like(b)
+    res = s.solve(b, x, tol=1e-10)
+    sm = oamg.Smoother.parse("JA-1-1-0.5")
+    sm.omegas = tuple(om)
+    prec = oamg.preconditioner(h, sm)
+    ref = krylov.pcg(lambda v: o.A.matvec(v).ravel(), lambda r: prec(r).ravel(), o.b.ravel(), tol=1e-10)
+    assert abs(res.iters - ref.iters) <= 1
+    xs = x.cpu().numpy()
+    assert np.linalg.norm(xs - ref.x) / np.linalg.norm(ref.x) < 1e-8
+    s.close()
+    m.close()
+
+
+def test_fallback_when_the_network_output_is_not_finite():
+    hs = amg.problems.laplace(5)
+    bad = synth.mlp_init(0).astype(np.float32)
+    bad[-1] = np.nan   # output bias
+    m = learned.DampingModel(bad)
+    s = amg.AMGSolver(hs, smoother="JA-1-1-0.7", omega_model=m)
+    for l in range(s.num_levels - 1):
+        assert s.level_info(l).omega == 0.7
+    s.close()
+    with pytest.raises(amg.AmgError):
+        amg.AMGSolver(hs, smoother="GS-1-1", omega_model=m)
+    m.close()
+
+
+def test_set_level_omega_matches_setup_with_the_same_weights():
+    hs = amg.problems.laplace(7)
+    w = [0.71, 0.64, 0.9]
+    a = amg.AMGSolver(hs, smoother="JA-1-1-0.5", autotune=False)
+    a.set_level_omega(w)
+    b_ = amg.AMGSolver(hs, smoother="JA-1-1-0.5", level_omega=w, autotune=False)
+    r = torch.from_numpy(np.random.default_rng(3).standard_normal(hs.dofs)).to(DEV)
+    za, zb = torch.zeros_like(r), torch.zeros_like(r)
+    a.precondition(r, za)
+    b_.precondition(r, zb)
+    torch.cuda.synchronize()
+    assert torch.equal(za, zb)
+    a.close()
+    b_.close()
+
+
+@pytest.mark.skipif(not os.path.exists(learned.MODEL_PATH), reason="no trained damping model")
+@pytest.mark.parametrize("n,seed", [(12, 12), (36, 36)])
+def test_trained_network_beats_fixed_damping(n, seed):
+    """Meshes outside the training range (16..32), Dirichlet data from
+    another workload's seeds: the predicted weights save at least one PCG
+    iteration to 1e-8 (23 -> 22 at n = 12, 22 -> 21 at n = 36) and reach the
+    same solution."""
+    hs = amg.problems.laplace(n, workload=synth.LAPLACE_LARGE, i=seed)
+    m = learned.DampingModel.load()
+    b = torch.from_numpy(hs.rhs).to(DEV)
+    out = {}
+    for tag, kw in (("fixed", {}), ("learned", {"omega_model": m})):
+        s = amg.AMGSolver(hs, smoother="JA-1-1-0.5", krylov="PCG", **kw)
+        x = torch.zeros_like(b)
+        s.solve(b, x, tol=1e-8)
+        x.zero_()
+        torch.cuda.synchronize()
+        res = s.solve(b, x, tol=1e-8)
+        assert res.converged and res.relres <= 1e-8
+        out[tag] = (res.iters, res.solve_ms, x.clone())
+        s.close()
+    assert out["learned"][0] < out["fixed"][0], out
+    err = torch.linalg.norm(out["learned"][2] - out["fixed"][2]) / torch.linalg.norm(out["fixed"][2])
+    assert float(err) < 1e-6
+    m.close()
