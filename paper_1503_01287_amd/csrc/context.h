@@ -38,11 +38,46 @@ struct LevelMP {
     int vbytes() const { return kind == VAL_F32 ? 4 : 2; }
 };
 
+// Explicit inverses of the systems that end on a level: the coarsest level of
+// one hierarchy, or, in a batch, every instance whose own hierarchy ends on
+// this level (see DenseSegView).
+struct DenseSegs {
+    int count = 0, rows = 0;
+    std::vector<int> h_m, h_uoff, h_nu, h_poff;
+    std::vector<int64_t> h_moff;
+    DevBuf<int64_t> moff;
+    DevBuf<int> rstart, uoff, nu, poff;
+    DevBuf<double> inv;
+    double bytes = 0.0;  // matrix bytes read per application
+    void add(int m, int uoff_, int nu_, int poff_) {
+        h_moff.push_back(h_moff.empty() ? 0 : h_moff.back() + static_cast<int64_t>(h_m.back()) * h_m.back());
+        h_m.push_back(m);
+        h_uoff.push_back(uoff_);
+        h_nu.push_back(nu_);
+        h_poff.push_back(poff_);
+    }
+    void finalize(hipStream_t s);  // upload the tables, allocate inv
+    DenseSegView view() const {
+        DenseSegView v;
+        v.count = count;
+        v.rows = rows;
+        v.moff = moff.p;
+        v.rstart = rstart.p;
+        v.uoff = uoff.p;
+        v.nu = nu.p;
+        v.poff = poff.p;
+        v.inv = inv.p;
+        return v;
+    }
+};
+
 // One level of the scalar hierarchy of a Braess-Sarazin Schur complement
 // S = C + B A_hat^{-1} B^T (natural row order, rows grouped by colour
 // through `rowid`).
 struct SchurLevel {
     DMat S;
+    int nA = 0;                  // leading rows that are smoothed (the rest: dseg)
+    DenseSegs dseg;
     DevBuf<double> dinv;         // 1 / S_ii
     std::vector<int> cptr;       // rows of colour c: rowid[cptr[c] .. cptr[c+1])
     DevBuf<int> rowid;
@@ -84,6 +119,11 @@ struct Level {
     DMat H, Ht;               // pressure prolongation to this level and its transpose
     DevBuf<double> sgs_scale; // sGS: 1 / diag(B M_A^{-1} B^T + C)
     DevBuf<double> bs_ahat;   // BS: 1 / (2 a_ii) per velocity unknown
+    // leading velocity nodes / pressure nodes that are smoothed and coarsened
+    // (all of them except on a coarsest level; in a batch, the instances
+    // whose hierarchy continues below); the others are solved by dseg
+    int nA = 0, npA = 0;
+    DenseSegs dseg;
     SchurHier schur;          // BS: scalar hierarchy of this level's Schur complement
     int Gb = 16, Gbt = 16, Gc = 8, Gh = 4, Ght = 8;
     int64_t vlen() const { return 3 * static_cast<int64_t>(n) + n_pres; }

@@ -11,6 +11,23 @@
 
 namespace amgp2 {
 
+void DenseSegs::finalize(hipStream_t s) {
+    count = static_cast<int>(h_m.size());
+    std::vector<int> rs(count + 1, 0);
+    bytes = 0.0;
+    for (int k = 0; k < count; ++k) {
+        rs[k + 1] = rs[k] + h_m[k];
+        bytes += 8.0 * h_m[k] * h_m[k];
+    }
+    rows = rs[count];
+    moff.upload(h_moff, s);
+    rstart.upload(rs, s);
+    uoff.upload(h_uoff, s);
+    nu.upload(h_nu, s);
+    poff.upload(h_poff, s);
+    inv.alloc(count ? static_cast<size_t>(h_moff.back() + static_cast<int64_t>(h_m.back()) * h_m.back()) : 0);
+}
+
 static void upload_pattern(DMat &m, const HostCSR &h, hipStream_t s) {
     m.nrows = h.nrows;
     m.ncols = h.ncols;
@@ -327,6 +344,12 @@ static void setup_coarsest(amg_ctx *h, Level &L) {
         h->coarse_m = m;
         h->coarse_nc = 1;
         h->coarse_inv.upload(M, s);
+        if (L.n_pres > 0) {
+            L.dseg = DenseSegs();
+            L.dseg.add(m, 0, nu, 0);
+            L.dseg.finalize(s);
+            AMG_HIP(hipMemcpyAsync(L.dseg.inv.p, M.data(), M.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        }
     } else {
         const int m = L.n;
         std::vector<double> M(static_cast<size_t>(m) * m, 0.0);
@@ -537,6 +560,12 @@ void setup_schur(amg_ctx *h, int l) {
         for (int j = 0; j < m; ++j) M[static_cast<size_t>(m - 1) * m + j] = 0.0;
     sh.m = m;
     sh.inv.upload(M, s);
+    for (size_t k = 0; k + 1 < sh.lv.size(); ++k) sh.lv[k].nA = sh.lv[k].S.nrows;
+    c.nA = 0;
+    c.dseg = DenseSegs();
+    c.dseg.add(m, 0, 0, 0);
+    c.dseg.finalize(s);
+    AMG_HIP(hipMemcpyAsync(c.dseg.inv.p, M.data(), M.size() * sizeof(double), hipMemcpyHostToDevice, s));
     AMG_HIP(hipStreamSynchronize(s));
 }
 
@@ -658,6 +687,10 @@ void build_hierarchy(amg_ctx *h, const amg_system *sys) {
         h->lv.push_back(std::move(next));
     }
     h->lv.back().coarsest = true;
+    for (Level &L : h->lv) {
+        L.nA = L.coarsest ? 0 : L.n;
+        L.npA = L.coarsest ? 0 : L.n_pres;
+    }
     if (p.omega_model && p.smoother == AMG_SMOOTH_JA && !h->saddle) predict_level_omega(h);
     for (Level &L : h->lv) {
         const size_t nv = static_cast<size_t>(L.vlen());

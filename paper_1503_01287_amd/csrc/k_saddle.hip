@@ -295,6 +295,42 @@ void launch_add_scaled(int64_t n, const double *d, const double *w, double *u, h
     AMG_CHECK_LAUNCH();
 }
 
+// ---------------------------------------------------------------- dense segments
+// one wavefront per output row over all segments; lanes stride the columns
+__global__ void __launch_bounds__(SB) k_dense_segs(const DenseSegView d, const double *xu, const double *xp,
+                                                   double *yu, double *yp) {
+    const int r = blockIdx.x * (SB / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (r >= d.rows) return;
+    int lo = 0, hi = d.count - 1;
+    while (lo < hi) {  // last segment with rstart <= r
+        const int mid = (lo + hi + 1) >> 1;
+        if (d.rstart[mid] <= r) lo = mid;
+        else hi = mid - 1;
+    }
+    const int sg = lo;
+    const int m = d.rstart[sg + 1] - d.rstart[sg];
+    const int i = r - d.rstart[sg];
+    const int nu = d.nu[sg];
+    const double *xus = xu + d.uoff[sg], *xps = xp + d.poff[sg];
+    const double *row = d.inv + d.moff[sg] + static_cast<int64_t>(i) * m;
+    double acc = 0.0;
+    for (int j = lane; j < m; j += 64) acc += row[j] * (j < nu ? xus[j] : xps[j - nu]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (lane == 0) {
+        if (i < nu) yu[d.uoff[sg] + i] = acc;
+        else yp[d.poff[sg] + i - nu] = acc;
+    }
+}
+
+void launch_dense_segs(const DenseSegView &d, const double *xu, const double *xp, double *yu, double *yp,
+                       hipStream_t s) {
+    if (d.count <= 0 || d.rows <= 0) return;
+    k_dense_segs<<<ceil_div(d.rows, SB / 64), SB, 0, s>>>(d, xu, xp, yu, yp);
+    AMG_CHECK_LAUNCH();
+}
+
 // ---------------------------------------------------------------- FGMRES
 constexpr int MD_BLOCKS = 256;
 

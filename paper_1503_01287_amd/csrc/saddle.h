@@ -61,6 +61,20 @@ void launch_scalar_gs(int nrows, const int *rowptr, const int *col, const double
 // u += d .* w
 void launch_add_scaled(int64_t n, const double *d, const double *w, double *u, hipStream_t s);
 
+// Explicit inverses of the systems that end on a level ("dense segments"):
+// segment s is an m_s x m_s row-major inverse at inv + moff[s] acting on the
+// vector made of nu_s values at u + uoff[s] followed by np_s values at
+// p + poff[s] (m_s = nu_s + np_s). rstart holds the prefix sums of m_s.
+struct DenseSegView {
+    int count = 0, rows = 0;
+    const int64_t *moff = nullptr;
+    const int *rstart = nullptr, *uoff = nullptr, *nu = nullptr, *poff = nullptr;
+    const double *inv = nullptr;
+};
+// y = M_s x on every segment (x and y: u parts xu/yu, p parts xp/yp)
+void launch_dense_segs(const DenseSegView &d, const double *xu, const double *xp, double *yu, double *yp,
+                       hipStream_t s);
+
 // FGMRES inner products: h[i] = <V_i, w> for i < k (V_i = V + i * ld) as
 // block partials partial[i * nb + block]; returns nb
 int launch_multidot(const double *V, int64_t ld, int k, const double *w, int64_t n, double *partial,

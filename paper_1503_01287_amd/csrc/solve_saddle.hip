@@ -44,13 +44,15 @@ void saddle_setup_level(amg_ctx *h, Level &L) {
     AMG_HIP(hipStreamSynchronize(s));
 }
 
-// r = [f - A u - B^T p ; g - B u + C p] on level l
-static void saddle_residual(amg_ctx *h, int l, const double *b, const double *x, double *r) {
+// r = [f - A u - B^T p ; g - B u + C p] on level l for the first nrows_u
+// velocity nodes and nrows_p pressure nodes (r and b are full level vectors)
+static void saddle_residual_rows(amg_ctx *h, int l, const double *b, const double *x, double *r, int nrows_u,
+                                 int nrows_p) {
     Level &L = h->lv[l];
     const int64_t nu = 3 * static_cast<int64_t>(L.n);
     {
         RowArgs a;
-        a.nrows = L.n;
+        a.nrows = nrows_u;
         a.rowptr = L.A.rowptr.p;
         a.col = L.A.col.p;
         a.val = L.A.val.p;
@@ -62,20 +64,27 @@ static void saddle_residual(amg_ctx *h, int l, const double *b, const double *x,
         launch_row(3, OP_RESID, L.G, a, h->stream);
     }
     BlkArgs bt = blk(L.Bt);
+    bt.nrows = nrows_u;
     bt.x = x + nu;
     bt.y = r;
     launch_blk(3, 1, BLK_SUB, L.Gbt, bt, h->stream);
     BlkArgs bb = blk(L.B);
+    bb.nrows = nrows_p;
     bb.x = x;
     bb.b = b + nu;
     bb.y = r + nu;
     launch_blk(1, 3, BLK_RESID, L.Gb, bb, h->stream);
     if (L.C.nnz > 0) {
         BlkArgs cc = blk(L.C);
+        cc.nrows = nrows_p;
         cc.x = x + nu;
         cc.y = r + nu;
         launch_blk(1, 1, BLK_ADD, L.Gc, cc, h->stream);
     }
+}
+
+static void saddle_residual(amg_ctx *h, int l, const double *b, const double *x, double *r) {
+    saddle_residual_rows(h, l, b, x, r, h->lv[l].n, h->lv[l].n_pres);
 }
 
 // y = K_l x
@@ -112,18 +121,20 @@ void saddle_apply(amg_ctx *h, int l, const double *x, double *y) {
 
 // One segregated Gauss-Seidel step (reading of Section 3.3: K_hat =
 // [[M_A, 0], [B, -omega^{-1} S_d]], M_A = damped block Jacobi, S_d =
-// diag(B M_A^{-1} B^T + C)): du = M_A^{-1} r_u, dp = omega S_d^{-1}(B du - r_p).
-// x_zero: the iterate is zero, so the residual is the right-hand side.
+// diag(B M_A^{-1} B^T + C)): du = M_A^{-1} r_u, dp = omega S_d^{-1}(B du - r_p),
+// on the smoothed rows of the level. x_zero: the iterate is zero, so the
+// residual is the right-hand side.
 static void sgs_step(amg_ctx *h, int l, const double *b, double *x, bool x_zero) {
     Level &L = h->lv[l];
     const int64_t nu = 3 * static_cast<int64_t>(L.n);
     const double *r = b;
     if (!x_zero) {
-        saddle_residual(h, l, b, x, L.r.p);
+        saddle_residual_rows(h, l, b, x, L.r.p, L.nA, L.npA);
         r = L.r.p;
     }
-    launch_sgs_u(L.n, L.dinv.p, r, h->prm.sgs_damping, L.t.p, x, h->stream);
+    launch_sgs_u(L.nA, L.dinv.p, r, h->prm.sgs_damping, L.t.p, x, h->stream);
     BlkArgs bb = blk(L.B);
+    bb.nrows = L.npA;
     bb.x = L.t.p;
     bb.b = r + nu;
     bb.y = x + nu;
@@ -133,23 +144,23 @@ static void sgs_step(amg_ctx *h, int l, const double *b, double *x, bool x_zero)
 }
 
 // Scalar V(1,1) cycle on level k of the Schur hierarchy of saddle level l,
-// from a zero guess: Gauss-Seidel colour by colour (forward before the
-// coarse correction, backward after it), restriction with H^T and
-// prolongation with H of saddle level l + k, dense inverse at the bottom.
+// from a zero guess: Gauss-Seidel colour by colour on the smoothed rows
+// (forward before the coarse correction, backward after it), restriction
+// with H^T and prolongation with H of saddle level l + k; rows that end on
+// this level are solved by their explicit inverses.
 static void schur_vcycle(amg_ctx *h, int l, int k, const double *b, double *x) {
     SchurHier &sh = h->lv[l].schur;
     SchurLevel &q = sh.lv[k];
     hipStream_t s = h->stream;
-    if (k + 1 == static_cast<int>(sh.lv.size())) {
-        launch_dense_gemv(sh.inv.p, sh.m, 1, b, x, s);
-        return;
-    }
+    if (q.dseg.count > 0) launch_dense_segs(q.dseg.view(), nullptr, b, nullptr, x, s);
+    if (q.nA == 0) return;
     const int nc = static_cast<int>(q.cptr.size()) - 1;
-    launch_fill(x, 0.0, q.S.nrows, s);
+    launch_fill(x, 0.0, q.nA, s);
     for (int c = 0; c < nc; ++c)
         launch_scalar_gs(q.cptr[c + 1] - q.cptr[c], q.S.rowptr.p, q.S.col.p, q.S.val.p, q.rowid.p + q.cptr[c],
                          q.dinv.p, b, x, q.G, s);
     BlkArgs ra = blk(q.S);
+    ra.nrows = q.nA;
     ra.x = x;
     ra.b = b;
     ra.y = q.r.p;
@@ -183,21 +194,23 @@ static void bs_step(amg_ctx *h, int l, const double *b, double *x, bool x_zero) 
     if (x_zero)
         launch_copy(L.r.p, b, L.vlen(), s);
     else
-        saddle_residual(h, l, b, x, L.r.p);
-    launch_scale(nu, L.bs_ahat.p, L.r.p, L.t.p, s);
+        saddle_residual_rows(h, l, b, x, L.r.p, L.nA, L.npA);
+    launch_scale(3 * static_cast<int64_t>(L.nA), L.bs_ahat.p, L.r.p, L.t.p, s);
     SchurLevel &q0 = L.schur.lv[0];
     BlkArgs bb = blk(L.B);
+    bb.nrows = L.npA;
     bb.x = L.t.p;
     bb.b = L.r.p + nu;
     bb.y = q0.b.p;
     launch_blk(1, 3, BLK_RESID, L.Gb, bb, s);
     schur_vcycle(h, l, 0, q0.b.p, q0.x.p);
-    launch_axpby(x + nu, q0.x.p, -1.0, 1.0, L.n_pres, s);
+    launch_axpby(x + nu, q0.x.p, -1.0, 1.0, L.npA, s);
     BlkArgs bt = blk(L.Bt);
+    bt.nrows = L.nA;
     bt.x = q0.x.p;
     bt.y = L.r.p;
     launch_blk(3, 1, BLK_ADD, L.Gbt, bt, s);
-    launch_add_scaled(nu, L.bs_ahat.p, L.r.p, x, s);
+    launch_add_scaled(3 * static_cast<int64_t>(L.nA), L.bs_ahat.p, L.r.p, x, s);
 }
 
 static void saddle_step(amg_ctx *h, int l, const double *b, double *x, bool x_zero) {
@@ -207,23 +220,26 @@ static void saddle_step(amg_ctx *h, int l, const double *b, double *x, bool x_ze
         sgs_step(h, l, b, x, x_zero);
 }
 
-static void saddle_coarse(amg_ctx *h, const double *b, double *x) {
-    ProfScope ps(h, "coarse", static_cast<double>(h->coarse_m) * h->coarse_m * 8.0);
-    launch_dense_gemv(h->coarse_inv.p, h->coarse_m, 1, b, x, h->stream);
-}
-
+// Algorithm 1 on saddle level l: systems that end on this level take their
+// explicit inverse; the others are smoothed, restricted with P^T = diag(I, J, H)^T,
+// corrected from level l + 1 and smoothed again.
 static void saddle_cycle(amg_ctx *h, int l, const double *b, double *x, bool x_zero) {
     Level &L = h->lv[l];
-    if (L.coarsest) {
-        saddle_coarse(h, b, x);
-        return;
+    const int64_t nu = 3 * static_cast<int64_t>(L.n);
+    if (L.dseg.count > 0) {
+        ProfScope ps(h, "coarse", L.dseg.bytes);
+        launch_dense_segs(L.dseg.view(), b, b + nu, x, x + nu, h->stream);
     }
+    if (L.nA == 0) return;
     const amg_params &p = h->prm;
-    if (x_zero) launch_fill(x, 0.0, L.vlen(), h->stream);
+    if (x_zero) {
+        launch_fill(x, 0.0, 3 * static_cast<int64_t>(L.nA), h->stream);
+        launch_fill(x + nu, 0.0, L.npA, h->stream);
+    }
     for (int k = 0; k < p.pre; ++k) saddle_step(h, l, b, x, x_zero && k == 0);
-    saddle_residual(h, l, b, x, L.r.p);
+    saddle_residual_rows(h, l, b, x, L.r.p, L.nA, L.npA);
     Level &C = h->lv[l + 1];
-    const int64_t nu = 3 * static_cast<int64_t>(L.n), ncu = 3 * static_cast<int64_t>(C.n);
+    const int64_t ncu = 3 * static_cast<int64_t>(C.n);
     {
         RowArgs a;
         a.nrows = L.R.nrows;
@@ -239,12 +255,8 @@ static void saddle_cycle(amg_ctx *h, int l, const double *b, double *x, bool x_z
         ht.y = C.b.p + ncu;
         launch_blk(1, 1, BLK_SPMV, L.Ght, ht, h->stream);
     }
-    if (C.coarsest) {
-        saddle_coarse(h, C.b.p, C.x.p);
-    } else {
-        const int nu_rec = std::max(1, p.nu);
-        for (int k = 0; k < nu_rec; ++k) saddle_cycle(h, l + 1, C.b.p, C.x.p, k == 0);
-    }
+    const int nu_rec = C.nA > 0 ? std::max(1, p.nu) : 1;
+    for (int k = 0; k < nu_rec; ++k) saddle_cycle(h, l + 1, C.b.p, C.x.p, k == 0);
     {
         RowArgs a;
         a.nrows = L.P.nrows;
