@@ -226,6 +226,31 @@ int amg_get_level_matrix(amg_handle h, int32_t level, int32_t which, int32_t *ro
 /* Colour of every node of level l (host array of n_lin + n_quad int32). */
 int amg_get_level_colors(amg_handle h, int32_t level, int32_t *colors);
 
+/* ---- batches of independent saddle point systems ----------------------
+ * Many solves of uneven size in one set of launches. Each system gets the
+ * hierarchy amg_setup would build for it alone; the hierarchies are merged
+ * level by level into one block-diagonal hierarchy (systems ordered by
+ * decreasing depth, so those still coarsening on a level lead it and those
+ * ending on it are solved by their explicit inverses), and every kernel of a
+ * V-cycle serves the whole batch. The outer method is flexible GMRES with
+ * per-system inner products, Hessenberg matrices and convergence tests.
+ * Saddle point systems only (sGS or Braess-Sarazin smoother, FGMRES, FP64).
+ */
+int amg_setup_batched(int32_t nsys, const amg_system *systems, const amg_params *params, amg_stream stream,
+                      amg_handle *out);
+/* b, x: DEVICE arrays holding the systems one after another in the order
+ * given to amg_setup_batched, each as [u (3 N_i); p (Np_i)]; x is the initial
+ * guess on entry and the solution on return. results: HOST array of nsys
+ * (per-system iterations, status, true relative residual; solve_ms is the
+ * whole batch's). Returns the worst status. */
+int amg_solve_batched(amg_handle h, const double *b, double *x, double tol, int32_t maxit, amg_stream stream,
+                      amg_result *results);
+/* Offsets of system i's velocity and pressure values in the merged level-0
+ * vector [u (all systems); p (all systems)] that amg_precondition and
+ * amg_apply use on a batch handle (pressure offsets relative to the start
+ * of the pressure block). HOST arrays of nsys. */
+int amg_batch_offsets(amg_handle h, int64_t *u_offset, int64_t *p_offset);
+
 /* ---- learned Jacobi damping -------------------------------------------
  * Not in the paper, which damps block Jacobi with a fixed 0.5 (Section 4.2):
  * a multilayer perceptron 8 -> 32 -> 32 -> 1 (tanh hidden units, output

@@ -6,6 +6,6 @@ flexible Krylov solves. The compute path is the HIP library libamgp2.so
 """
 from . import problems
 from ._lib import AmgError, lib
-from .solver import AMGSolver, SolveResult, parse_smoother
+from .solver import AMGSolver, BatchedSolver, SolveResult, parse_smoother
 
-__all__ = ["AMGSolver", "SolveResult", "AmgError", "lib", "problems", "parse_smoother"]
+__all__ = ["AMGSolver", "BatchedSolver", "SolveResult", "AmgError", "lib", "problems", "parse_smoother"]

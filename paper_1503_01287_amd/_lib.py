@@ -88,6 +88,11 @@ SIGNATURES = {
     "amg_profile_read": (ctypes.c_int, [_H, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64),
                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "amg_destroy": (None, [_H]),
+    "amg_setup_batched": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(AmgSystem), ctypes.POINTER(AmgParams), _S,
+                                         ctypes.POINTER(_H)]),
+    "amg_solve_batched": (ctypes.c_int, [_H, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_int32, _S,
+                                         ctypes.POINTER(AmgResult)]),
+    "amg_batch_offsets": (ctypes.c_int, [_H, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
     "amg_mlp_create": (ctypes.c_int, [_f32p, _S, ctypes.POINTER(ctypes.c_void_p)]),
     "amg_mlp_get_params": (ctypes.c_int, [ctypes.c_void_p, _f32p]),
     "amg_mlp_forward": (ctypes.c_int, [ctypes.c_void_p, _f32p, ctypes.c_int32, _f32p]),

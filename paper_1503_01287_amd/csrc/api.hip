@@ -107,10 +107,78 @@ int amg_setup(const amg_system *sys, const amg_params *params, amg_stream stream
     });
 }
 
+static void check_params(const amg_params &p, bool saddle) {
+    if (saddle) {
+        AMG_REQUIRE(p.smoother == AMG_SMOOTH_SGS || p.smoother == AMG_SMOOTH_BS, AMG_EINVAL,
+                    "amg_setup: saddle point systems need the sGS or Braess-Sarazin smoother");
+        AMG_REQUIRE(p.krylov == AMG_KRYLOV_FGMRES || p.krylov == AMG_KRYLOV_NONE, AMG_EINVAL,
+                    "amg_setup: saddle point systems need FGMRES or the stand-alone iteration");
+        AMG_REQUIRE(p.precision == AMG_PREC_FP64, AMG_EUNSUPPORTED, "amg_setup: saddle point systems run in FP64");
+    }
+    AMG_REQUIRE(p.krylov != AMG_KRYLOV_FGMRES || p.restart >= 1, AMG_EINVAL, "amg_setup: restart < 1");
+    AMG_REQUIRE(p.pre >= 0 && p.post >= 0 && p.cycles >= 1 && p.nu >= 1 && p.nu <= 2, AMG_EINVAL,
+                "amg_setup: invalid smoothing/cycle counts");
+}
+
+int amg_setup_batched(int32_t nsys, const amg_system *systems, const amg_params *params, amg_stream stream,
+                      amg_handle *out) {
+    return guarded([&]() -> int {
+        AMG_REQUIRE(out != nullptr, AMG_EINVAL, "amg_setup_batched: null output handle");
+        *out = nullptr;
+        AMG_REQUIRE(systems && params && nsys >= 1, AMG_EINVAL, "amg_setup_batched: need systems and params");
+        const amg_params &p = *params;
+        check_params(p, true);
+        AMG_REQUIRE(p.krylov == AMG_KRYLOV_FGMRES, AMG_EINVAL, "amg_setup_batched: batches run FGMRES");
+        AMG_REQUIRE(!p.omega_model, AMG_EINVAL, "amg_setup_batched: omega_model is for JA on SPD systems");
+        auto *h = new amg_ctx();
+        h->prm = p;
+        h->prm.level_omega = nullptr;
+        h->prm.n_level_omega = 0;
+        h->stream = static_cast<hipStream_t>(stream);
+        try {
+            build_batch(h, nsys, systems);
+        } catch (...) {
+            delete h;
+            throw;
+        }
+        *out = h;
+        return AMG_OK;
+    });
+}
+
+int amg_solve_batched(amg_handle h, const double *b, double *x, double tol, int32_t maxit, amg_stream stream,
+                      amg_result *results) {
+    return guarded([&]() -> int {
+        AMG_REQUIRE(h && b && x, AMG_EINVAL, "amg_solve_batched: null argument");
+        AMG_REQUIRE(h->nsys > 0, AMG_EINVAL, "amg_solve_batched: handle is not a batch (use amg_solve)");
+        AMG_REQUIRE(tol > 0.0 && maxit >= 0, AMG_EINVAL, "amg_solve_batched: tol must be > 0, maxit >= 0");
+        h->stream = static_cast<hipStream_t>(stream);
+        launch_seg_copy(b, h->b_b.p, h->b_in.view(), h->b_in.dst.p, h->stream);
+        launch_seg_copy(x, h->b_x.p, h->b_in.view(), h->b_in.dst.p, h->stream);
+        const int st = solve_fgmres_batched(h, h->b_b.p, h->b_x.p, tol, maxit, results);
+        launch_seg_copy(h->b_x.p, x, h->b_out.view(), h->b_out.dst.p, h->stream);
+        AMG_HIP(hipStreamSynchronize(h->stream));
+        return st;
+    });
+}
+
+int amg_batch_offsets(amg_handle h, int64_t *u_offset, int64_t *p_offset) {
+    return guarded([&]() -> int {
+        AMG_REQUIRE(h && u_offset && p_offset, AMG_EINVAL, "amg_batch_offsets: null argument");
+        AMG_REQUIRE(h->nsys > 0, AMG_EINVAL, "amg_batch_offsets: handle is not a batch");
+        for (int j = 0; j < h->nsys; ++j) {
+            u_offset[h->b_order[j]] = h->b_uoff[j];
+            p_offset[h->b_order[j]] = h->b_poff[j];
+        }
+        return AMG_OK;
+    });
+}
+
 int amg_solve(amg_handle h, const double *b, double *x, double tol, int32_t maxit, amg_stream stream,
               amg_result *res) {
     return guarded([&]() -> int {
         AMG_REQUIRE(h && b && x, AMG_EINVAL, "amg_solve: null argument");
+        AMG_REQUIRE(h->nsys == 0, AMG_EINVAL, "amg_solve: batch handle (use amg_solve_batched)");
         AMG_REQUIRE(tol > 0.0 && maxit >= 0, AMG_EINVAL, "amg_solve: tol must be > 0, maxit >= 0");
         h->stream = static_cast<hipStream_t>(stream);
         switch (h->prm.krylov) {

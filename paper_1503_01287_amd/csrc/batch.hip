@@ -1,0 +1,534 @@
+// Batches of independent saddle point systems (many solves of uneven mesh
+// size in one set of launches).
+//
+// Every system gets its own hierarchy, built exactly as a single amg_setup
+// would build it (Section 3.2). The hierarchies are then merged level by
+// level into one block-diagonal hierarchy: level l holds the systems whose
+// hierarchy reaches level l, ordered by decreasing depth, so the systems
+// that continue below l form a leading block (smoothed, restricted,
+// corrected) and those ending on l a trailing block (solved by their
+// explicit inverses, one segmented kernel). A V-cycle of the merged
+// hierarchy is then the V-cycles of all systems at once: each kernel launch
+// serves the whole batch. The outer flexible GMRES keeps per-system inner
+// products, Hessenberg matrices, convergence tests and iteration counts.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <memory>
+#include <numeric>
+
+#include "context.h"
+
+namespace amgp2 {
+
+static int lanes_of(int64_t nnz, int nrows) {
+    const double avg = nrows > 0 ? static_cast<double>(nnz) / nrows : 1.0;
+    int G = 4;
+    while (G < 64 && G < avg) G *= 2;
+    return G;
+}
+
+// Block-diagonal concatenation: part j contributes rows[j] rows (its matrix
+// may be null or empty) with its columns shifted by coff[j].
+static void merge_mats(DMat &out, const std::vector<const DMat *> &parts, const std::vector<int> &rows,
+                       const std::vector<int> &coff, int ncols, int np, hipStream_t s) {
+    out = DMat();
+    out.np = np;
+    out.ncols = ncols;
+    std::vector<int> rp(1, 0), cl;
+    std::vector<int64_t> voff;
+    for (size_t j = 0; j < parts.size(); ++j) {
+        const DMat *m = parts[j];
+        voff.push_back(static_cast<int64_t>(cl.size()));
+        if (m && m->nnz > 0) {
+            AMG_REQUIRE(m->nrows == rows[j] && m->np == np, AMG_EINVAL, "batch: inconsistent level operators");
+            std::vector<int> r = m->rowptr.download(s), c = m->col.download(s);
+            const int base = static_cast<int>(cl.size());
+            for (int i = 0; i < m->nrows; ++i) rp.push_back(base + r[i + 1]);
+            for (int64_t k = 0; k < m->nnz; ++k) cl.push_back(c[k] + coff[j]);
+        } else {
+            for (int i = 0; i < rows[j]; ++i) rp.push_back(static_cast<int>(cl.size()));
+        }
+    }
+    out.nrows = static_cast<int>(rp.size()) - 1;
+    out.nnz = static_cast<int64_t>(cl.size());
+    out.rowptr.upload(rp, s);
+    out.col.upload(cl, s);
+    out.val.alloc(static_cast<size_t>(std::max<int64_t>(1, out.nnz * np)));
+    for (size_t j = 0; j < parts.size(); ++j) {
+        const DMat *m = parts[j];
+        if (!m || m->nnz == 0) continue;
+        for (int p = 0; p < np; ++p)
+            AMG_HIP(hipMemcpyAsync(out.val.p + p * out.nnz + voff[j], m->val.p + p * m->nnz,
+                                   m->nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+}
+
+// out[p * T + off_j + k] = src_j[p * len_j + k] (T = sum len_j); null parts -> 0
+static void merge_planes(DevBuf<double> &out, const std::vector<const double *> &src,
+                         const std::vector<int64_t> &len, int np, hipStream_t s) {
+    int64_t T = 0;
+    for (int64_t v : len) T += v;
+    out.alloc(static_cast<size_t>(std::max<int64_t>(1, T * np)));
+    int64_t off = 0;
+    for (size_t j = 0; j < src.size(); ++j) {
+        for (int p = 0; p < np; ++p) {
+            double *d = out.p + p * T + off;
+            if (src[j])
+                AMG_HIP(hipMemcpyAsync(d, src[j] + p * len[j], len[j] * sizeof(double), hipMemcpyDeviceToDevice, s));
+            else
+                launch_fill(d, 0.0, len[j], s);
+        }
+        off += len[j];
+    }
+}
+
+static void copy_segment(DenseSegs &d, int k, const DenseSegs &from, hipStream_t s) {
+    AMG_REQUIRE(from.count == 1 && from.h_m[0] == d.h_m[k], AMG_EINVAL, "batch: coarsest inverse size mismatch");
+    const size_t mm = static_cast<size_t>(d.h_m[k]) * d.h_m[k];
+    AMG_HIP(hipMemcpyAsync(d.inv.p + d.h_moff[k], from.inv.p, mm * sizeof(double), hipMemcpyDeviceToDevice, s));
+}
+
+// chunks of [base, base + len) for system q
+static void add_chunks(int64_t base, int64_t len, int q, std::vector<int64_t> &st, std::vector<int> &ln,
+                       std::vector<int> &sg, std::vector<int64_t> *dst, int64_t dbase) {
+    for (int64_t o = 0; o < len; o += BATCH_CHUNK) {
+        st.push_back(base + o);
+        ln.push_back(static_cast<int>(std::min<int64_t>(BATCH_CHUNK, len - o)));
+        sg.push_back(q);
+        if (dst) dst->push_back(dbase + o);
+    }
+}
+
+void build_batch(amg_ctx *h, int nsys, const amg_system *sys) {
+    hipStream_t s = h->stream;
+    const amg_params &p = h->prm;
+    std::vector<std::unique_ptr<amg_ctx>> inst(nsys);
+    std::vector<int> depth(nsys);
+    for (int i = 0; i < nsys; ++i) {
+        AMG_REQUIRE(sys[i].n_pres > 0, AMG_EINVAL, "amg_setup_batched: every system must be a saddle point system");
+        inst[i].reset(new amg_ctx());
+        inst[i]->prm = p;
+        inst[i]->prm.autotune = 0;
+        inst[i]->prm.omega_model = nullptr;
+        inst[i]->stream = s;
+        build_hierarchy(inst[i].get(), &sys[i]);
+        depth[i] = static_cast<int>(inst[i]->lv.size()) - 1;
+    }
+    std::vector<int> order(nsys);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return depth[a] > depth[b]; });
+    const int maxd = depth[order[0]];
+    const bool bs = p.smoother == AMG_SMOOTH_BS;
+
+    std::vector<Level> merged(maxd + 1);
+    for (int l = 0; l <= maxd; ++l) {
+        std::vector<int> P;  // systems reaching level l, in merged order
+        for (int i : order)
+            if (depth[i] >= l) P.push_back(i);
+        Level &M = merged[l];
+        M.mode = 3;
+        const size_t np_ = P.size();
+        std::vector<int> noff(np_), poff(np_), nrow(np_), prow(np_);
+        for (size_t j = 0; j < np_; ++j) {
+            const Level &V = inst[P[j]]->lv[l];
+            noff[j] = M.n;
+            poff[j] = M.n_pres;
+            nrow[j] = V.n;
+            prow[j] = V.n_pres;
+            M.n += V.n;
+            M.n_pres += V.n_pres;
+            M.n_lin += V.n_lin;
+            M.n_quad += V.n_quad;
+            if (depth[P[j]] > l) {
+                M.nA += V.n;
+                M.npA += V.n_pres;
+            }
+        }
+        M.coarsest = M.nA == 0;
+        std::vector<const DMat *> pa, pb, pbt, pc;
+        bool anyc = false;
+        for (int i : P) {
+            const Level &V = inst[i]->lv[l];
+            pa.push_back(&V.A);
+            pb.push_back(&V.B);
+            pbt.push_back(&V.Bt);
+            pc.push_back(&V.C);
+            anyc |= V.C.nnz > 0;
+        }
+        merge_mats(M.A, pa, nrow, noff, M.n, 9, s);
+        merge_mats(M.B, pb, prow, noff, M.n, 3, s);
+        merge_mats(M.Bt, pbt, nrow, poff, M.n_pres, 3, s);
+        if (anyc) merge_mats(M.C, pc, prow, poff, M.n_pres, 1, s);
+        {
+            std::vector<const double *> dv, sg, ah;
+            std::vector<int64_t> ln, lp, l3;
+            for (size_t j = 0; j < np_; ++j) {
+                const Level &V = inst[P[j]]->lv[l];
+                const bool sm = depth[P[j]] > l;
+                dv.push_back(sm ? V.dinv.p : nullptr);
+                sg.push_back(sm ? V.sgs_scale.p : nullptr);
+                ah.push_back(sm && bs ? V.bs_ahat.p : nullptr);
+                ln.push_back(V.n);
+                lp.push_back(V.n_pres);
+                l3.push_back(3 * static_cast<int64_t>(V.n));
+            }
+            merge_planes(M.dinv, dv, ln, 9, s);
+            merge_planes(M.sgs_scale, sg, lp, 1, s);
+            if (bs) merge_planes(M.bs_ahat, ah, l3, 1, s);
+        }
+        // transfers to the next level: the leading (still coarsening) systems
+        if (M.nA > 0) {
+            std::vector<const DMat *> pp, pr, ph, pht;
+            std::vector<int> rows_p, rows_r, rows_h, rows_ht, cp, cr, ch, cht;
+            int n1 = 0, np1 = 0;
+            for (size_t j = 0; j < np_; ++j) {
+                if (depth[P[j]] <= l) continue;
+                const Level &V = inst[P[j]]->lv[l];
+                const Level &W = inst[P[j]]->lv[l + 1];
+                pp.push_back(&V.P);
+                rows_p.push_back(V.n);
+                cp.push_back(n1);
+                pr.push_back(&V.R);
+                rows_r.push_back(W.n);
+                cr.push_back(noff[j]);
+                ph.push_back(&V.H);
+                rows_h.push_back(V.n_pres);
+                ch.push_back(np1);
+                pht.push_back(&V.Ht);
+                rows_ht.push_back(W.n_pres);
+                cht.push_back(poff[j]);
+                n1 += W.n;
+                np1 += W.n_pres;
+            }
+            merge_mats(M.P, pp, rows_p, cp, n1, 1, s);
+            merge_mats(M.R, pr, rows_r, cr, M.n, 1, s);
+            merge_mats(M.H, ph, rows_h, ch, np1, 1, s);
+            merge_mats(M.Ht, pht, rows_ht, cht, M.n_pres, 1, s);
+        }
+        // systems ending on this level: their explicit inverses
+        for (size_t j = 0; j < np_; ++j)
+            if (depth[P[j]] == l) {
+                const Level &V = inst[P[j]]->lv[l];
+                M.dseg.add(3 * V.n + V.n_pres, 3 * noff[j], 3 * V.n, poff[j]);
+            }
+        if (!M.dseg.h_m.empty()) {
+            M.dseg.finalize(s);
+            int k = 0;
+            for (size_t j = 0; j < np_; ++j)
+                if (depth[P[j]] == l) copy_segment(M.dseg, k++, inst[P[j]]->lv[l].dseg, s);
+        }
+        // Braess-Sarazin: the Schur hierarchies of the leading systems, merged
+        // with the same rule (level k holds the systems reaching level l + k)
+        if (bs && M.nA > 0) {
+            int K = 0;
+            for (int i : P)
+                if (depth[i] > l) K = std::max(K, depth[i] - l);
+            M.schur.lv.resize(K + 1);
+            for (int k = 0; k <= K; ++k) {
+                SchurLevel &Q = M.schur.lv[k];
+                std::vector<int> R;
+                for (int i : P)
+                    if (depth[i] > l && depth[i] >= l + k) R.push_back(i);
+                std::vector<const DMat *> ps;
+                std::vector<int> rows, off;
+                std::vector<const double *> dv;
+                std::vector<int64_t> ln;
+                int tot = 0;
+                for (int i : R) {
+                    const SchurLevel &q = inst[i]->lv[l].schur.lv[k];
+                    ps.push_back(&q.S);
+                    rows.push_back(q.S.nrows);
+                    off.push_back(tot);
+                    const bool sm = depth[i] > l + k;
+                    dv.push_back(sm ? q.dinv.p : nullptr);
+                    ln.push_back(q.S.nrows);
+                    if (sm) Q.nA += q.S.nrows;
+                    tot += q.S.nrows;
+                }
+                merge_mats(Q.S, ps, rows, off, tot, 1, s);
+                merge_planes(Q.dinv, dv, ln, 1, s);
+                // colour lists of the smoothed systems, colour by colour
+                int nc = 0;
+                std::vector<std::vector<int>> rid(R.size());
+                for (size_t j = 0; j < R.size(); ++j)
+                    if (depth[R[j]] > l + k) {
+                        const SchurLevel &q = inst[R[j]]->lv[l].schur.lv[k];
+                        nc = std::max(nc, static_cast<int>(q.cptr.size()) - 1);
+                        rid[j] = q.rowid.download(s);
+                    }
+                Q.cptr.assign(1, 0);
+                std::vector<int> order_rows;
+                for (int c = 0; c < nc; ++c) {
+                    for (size_t j = 0; j < R.size(); ++j) {
+                        if (depth[R[j]] <= l + k) continue;
+                        const SchurLevel &q = inst[R[j]]->lv[l].schur.lv[k];
+                        if (c + 1 >= static_cast<int>(q.cptr.size())) continue;
+                        for (int g = q.cptr[c]; g < q.cptr[c + 1]; ++g) order_rows.push_back(rid[j][g] + off[j]);
+                    }
+                    Q.cptr.push_back(static_cast<int>(order_rows.size()));
+                }
+                if (order_rows.empty()) order_rows.push_back(0);
+                Q.rowid.upload(order_rows, s);
+                for (size_t j = 0; j < R.size(); ++j)
+                    if (depth[R[j]] == l + k) Q.dseg.add(rows[j], 0, 0, off[j]);
+                if (!Q.dseg.h_m.empty()) {
+                    Q.dseg.finalize(s);
+                    int kk = 0;
+                    for (size_t j = 0; j < R.size(); ++j)
+                        if (depth[R[j]] == l + k) copy_segment(Q.dseg, kk++, inst[R[j]]->lv[l].schur.lv[k].dseg, s);
+                }
+                Q.G = lanes_of(Q.S.nnz, Q.S.nrows);
+                Q.x.alloc(std::max(1, tot));
+                Q.b.alloc(std::max(1, tot));
+                Q.r.alloc(std::max(1, tot));
+            }
+        }
+        M.G = lanes_of(M.A.nnz, M.n);
+        M.Gg = M.G;
+        M.Gb = lanes_of(M.B.nnz, M.B.nrows);
+        M.Gbt = lanes_of(M.Bt.nnz, M.Bt.nrows);
+        M.Gc = M.C.nnz > 0 ? lanes_of(M.C.nnz, M.C.nrows) : 4;
+        M.Gp = lanes_of(M.P.nnz, M.P.nrows);
+        M.Gr = lanes_of(M.R.nnz, M.R.nrows);
+        M.Gh = lanes_of(M.H.nnz, M.H.nrows);
+        M.Ght = lanes_of(M.Ht.nnz, M.Ht.nrows);
+        const size_t nv = static_cast<size_t>(M.vlen());
+        M.x.alloc(nv);
+        M.b.alloc(nv);
+        M.r.alloc(nv);
+        M.t.alloc(nv);
+    }
+    AMG_HIP(hipStreamSynchronize(s));
+
+    // level-0 layout of every system, chunk tables
+    h->nsys = nsys;
+    h->b_order = order;
+    const Level &L0 = merged[0];
+    const int64_t nu0 = 3 * static_cast<int64_t>(L0.n);
+    std::vector<int64_t> user(nsys + 1, 0);
+    for (int i = 0; i < nsys; ++i)
+        user[i + 1] = user[i] + 3 * static_cast<int64_t>(sys[i].n_lin + sys[i].n_quad) + sys[i].n_pres;
+    h->b_uoff.assign(nsys, 0);
+    h->b_poff.assign(nsys, 0);
+    h->b_nu.assign(nsys, 0);
+    h->b_np.assign(nsys, 0);
+    {
+        int64_t u = 0, q = 0;
+        for (int j = 0; j < nsys; ++j) {
+            const amg_system &S = sys[order[j]];
+            h->b_uoff[j] = u;
+            h->b_poff[j] = q;
+            h->b_nu[j] = 3 * static_cast<int64_t>(S.n_lin + S.n_quad);
+            h->b_np[j] = S.n_pres;
+            u += h->b_nu[j];
+            q += h->b_np[j];
+        }
+    }
+    std::vector<int64_t> st, ds, st_in, ds_in, st_out, ds_out;
+    std::vector<int> ln, sg, ln_in, sg_in, ln_out, sg_out;
+    std::vector<int> c0(nsys), c1(nsys), c2(nsys), c3(nsys);
+    for (int j = 0; j < nsys; ++j) {
+        c0[j] = static_cast<int>(st.size());
+        add_chunks(h->b_uoff[j], h->b_nu[j], j, st, ln, sg, nullptr, 0);
+        c1[j] = static_cast<int>(st.size());
+    }
+    for (int j = 0; j < nsys; ++j) {
+        c2[j] = static_cast<int>(st.size());
+        add_chunks(nu0 + h->b_poff[j], h->b_np[j], j, st, ln, sg, nullptr, 0);
+        c3[j] = static_cast<int>(st.size());
+    }
+    for (int j = 0; j < nsys; ++j) {
+        const int64_t ub = user[order[j]];
+        add_chunks(ub, h->b_nu[j], j, st_in, ln_in, sg_in, &ds_in, h->b_uoff[j]);
+        add_chunks(ub + h->b_nu[j], h->b_np[j], j, st_in, ln_in, sg_in, &ds_in, nu0 + h->b_poff[j]);
+        add_chunks(h->b_uoff[j], h->b_nu[j], j, st_out, ln_out, sg_out, &ds_out, ub);
+        add_chunks(nu0 + h->b_poff[j], h->b_np[j], j, st_out, ln_out, sg_out, &ds_out, ub + h->b_nu[j]);
+    }
+    h->b_chunks.build(st, ln, sg, {}, s);
+    h->b_c0.upload(c0, s);
+    h->b_c1.upload(c1, s);
+    h->b_c2.upload(c2, s);
+    h->b_c3.upload(c3, s);
+    h->b_in.build(st_in, ln_in, sg_in, ds_in, s);
+    h->b_out.build(st_out, ln_out, sg_out, ds_out, s);
+
+    inst.clear();
+    h->lv = std::move(merged);
+    h->saddle = true;
+    h->pinned = -1;
+    h->n_dof = static_cast<int>(h->lv[0].vlen());
+    const size_t nd = static_cast<size_t>(h->n_dof);
+    h->b_b.alloc(nd);
+    h->b_x.alloc(nd);
+    h->kr.alloc(nd);
+    h->kz.alloc(nd);
+    h->kp.alloc(nd);
+    h->kq.alloc(nd);
+    h->kw.alloc(nd);
+    h->partial.alloc(static_cast<size_t>(std::max(1024 * 128, row_blocks(h->lv[0].n, 64))));
+    h->sc.alloc(SC_COUNT);
+    if (!h->h_sc) AMG_HIP(hipHostMalloc(reinterpret_cast<void **>(&h->h_sc), SC_COUNT * sizeof(double)));
+    AMG_HIP(hipStreamSynchronize(s));
+}
+
+// ---------------------------------------------------------------- batched FGMRES
+// Per-system norms of a merged level-0 vector (host result).
+static void seg_norms(amg_ctx *h, const double *v, DevBuf<double> &partial, DevBuf<double> &hb, int kmax,
+                      std::vector<double> &out) {
+    const ChunkView t = h->b_chunks.view();
+    launch_seg_multidot(v, 0, 1, v, t, partial.p, h->stream);
+    launch_seg_reduce(partial.p, t.n, 1, h->nsys, h->b_c0.p, h->b_c1.p, h->b_c2.p, h->b_c3.p, hb.p, kmax, h->stream);
+    std::vector<double> tmp(static_cast<size_t>(h->nsys) * kmax);
+    AMG_HIP(hipMemcpyAsync(tmp.data(), hb.p, tmp.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    AMG_HIP(hipStreamSynchronize(h->stream));
+    out.resize(h->nsys);
+    for (int i = 0; i < h->nsys; ++i) out[i] = std::sqrt(tmp[static_cast<size_t>(i) * kmax]);
+}
+
+// Right-preconditioned FGMRES(m) with classical Gram-Schmidt twice, one
+// Krylov process per system, advanced in lockstep: every launch serves all
+// systems; a system that has converged stops taking Arnoldi steps (its
+// columns are left out of its update) while the others continue.
+int solve_fgmres_batched(amg_ctx *h, const double *b, double *x, double tol, int maxit, amg_result *res) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const int ns = h->nsys;
+    const int64_t n = h->n_dof;
+    const int m = std::max(1, h->prm.restart);
+    const int kmax = m + 1;
+    if (h->gm_m != m) {
+        h->gm_V.alloc(static_cast<size_t>(m + 1) * n);
+        h->gm_Z.alloc(static_cast<size_t>(m) * n);
+        h->gm_m = m;
+    }
+    const ChunkView t = h->b_chunks.view();
+    DevBuf<double> partial(static_cast<size_t>(kmax) * std::max(1, t.n)), hb(static_cast<size_t>(ns) * kmax),
+        coef(ns), ycoef(static_cast<size_t>(ns) * m);
+    DevBuf<int> cnt(ns);
+    double *V = h->gm_V.p, *Z = h->gm_Z.p;
+    std::vector<double> H(static_cast<size_t>(ns) * (m + 1) * m), cs(static_cast<size_t>(ns) * m),
+        sn(static_cast<size_t>(ns) * m), g(static_cast<size_t>(ns) * (m + 1)), hcol(static_cast<size_t>(ns) * kmax),
+        hp(static_cast<size_t>(ns) * kmax);
+    std::vector<double> beta, r0, hn;
+    std::vector<int> status(ns, AMG_NOT_CONVERGED), iters(ns, 0), jcnt(ns, 0);
+    std::vector<char> active(ns, 0), running(ns, 0);
+    std::vector<double> hc(ns);
+    system_residual(h, b, x, V);
+    seg_norms(h, V, partial, hb, kmax, r0);
+    beta = r0;
+    for (int i = 0; i < ns; ++i) {
+        if (!(r0[i] == r0[i])) status[i] = AMG_DIVERGED;
+        else if (r0[i] == 0.0) status[i] = AMG_OK;
+        else active[i] = 1;
+    }
+    auto any = [&](const std::vector<char> &v) { return std::any_of(v.begin(), v.end(), [](char c) { return c != 0; }); };
+    int it = 0;
+    while (any(active) && it < maxit) {
+        for (int i = 0; i < ns; ++i) hc[i] = active[i] && beta[i] > 0.0 ? 1.0 / beta[i] : 0.0;
+        AMG_HIP(hipMemcpyAsync(coef.p, hc.data(), ns * sizeof(double), hipMemcpyHostToDevice, h->stream));
+        launch_seg_scale(V, V, coef.p, t, h->stream);
+        std::fill(g.begin(), g.end(), 0.0);
+        for (int i = 0; i < ns; ++i) {
+            g[static_cast<size_t>(i) * (m + 1)] = active[i] ? beta[i] : 0.0;
+            running[i] = active[i];
+            jcnt[i] = 0;
+        }
+        for (int j = 0; j < m && any(running) && it < maxit; ++j) {
+            double *vj = V + static_cast<int64_t>(j) * n, *w = V + static_cast<int64_t>(j + 1) * n;
+            double *zj = Z + static_cast<int64_t>(j) * n;
+            precondition_any(h, vj, zj);
+            system_matvec(h, zj, w);
+            std::fill(hcol.begin(), hcol.end(), 0.0);
+            for (int pass = 0; pass < 2; ++pass) {
+                launch_seg_multidot(V, n, j + 1, w, t, partial.p, h->stream);
+                launch_seg_reduce(partial.p, t.n, j + 1, ns, h->b_c0.p, h->b_c1.p, h->b_c2.p, h->b_c3.p, hb.p, kmax,
+                                  h->stream);
+                launch_seg_multi_axpy(V, n, j + 1, hb.p, kmax, w, t, h->stream);
+                AMG_HIP(hipMemcpyAsync(hp.data(), hb.p, hp.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+                AMG_HIP(hipStreamSynchronize(h->stream));
+                for (int i = 0; i < ns; ++i)
+                    for (int q = 0; q <= j; ++q) hcol[static_cast<size_t>(i) * kmax + q] += hp[static_cast<size_t>(i) * kmax + q];
+            }
+            seg_norms(h, w, partial, hb, kmax, hn);
+            for (int i = 0; i < ns; ++i) hc[i] = hn[i] > 0.0 ? 1.0 / hn[i] : 0.0;
+            AMG_HIP(hipMemcpyAsync(coef.p, hc.data(), ns * sizeof(double), hipMemcpyHostToDevice, h->stream));
+            launch_seg_scale(w, w, coef.p, t, h->stream);
+            for (int i = 0; i < ns; ++i) {
+                if (!running[i]) continue;
+                double *hcl = &hcol[static_cast<size_t>(i) * kmax];
+                double *csi = &cs[static_cast<size_t>(i) * m], *sni = &sn[static_cast<size_t>(i) * m];
+                double *gi = &g[static_cast<size_t>(i) * (m + 1)];
+                double *Hi = &H[static_cast<size_t>(i) * (m + 1) * m];
+                hcl[j + 1] = hn[i];
+                for (int q = 0; q < j; ++q) {
+                    const double tq = csi[q] * hcl[q] + sni[q] * hcl[q + 1];
+                    hcl[q + 1] = -sni[q] * hcl[q] + csi[q] * hcl[q + 1];
+                    hcl[q] = tq;
+                }
+                const double den = std::hypot(hcl[j], hcl[j + 1]);
+                csi[j] = den > 0.0 ? hcl[j] / den : 1.0;
+                sni[j] = den > 0.0 ? hcl[j + 1] / den : 0.0;
+                hcl[j] = den;
+                gi[j + 1] = -sni[j] * gi[j];
+                gi[j] = csi[j] * gi[j];
+                for (int q = 0; q <= j; ++q) Hi[static_cast<size_t>(q) * m + j] = hcl[q];
+                ++iters[i];
+                jcnt[i] = j + 1;
+                const double est = std::fabs(gi[j + 1]) / r0[i];
+                if (!(est == est) || est > 1e3) {
+                    status[i] = AMG_DIVERGED;
+                    running[i] = 0;
+                    active[i] = 0;
+                } else if (est <= tol || hn[i] == 0.0) {
+                    running[i] = 0;
+                }
+            }
+            ++it;
+        }
+        // x_i += Z y_i with y_i = R_i^{-1} g_i over the system's own columns
+        std::vector<double> Y(static_cast<size_t>(ns) * m, 0.0);
+        for (int i = 0; i < ns; ++i) {
+            const int ji = jcnt[i];
+            const double *Hi = &H[static_cast<size_t>(i) * (m + 1) * m];
+            const double *gi = &g[static_cast<size_t>(i) * (m + 1)];
+            double *yi = &Y[static_cast<size_t>(i) * m];
+            for (int q = ji - 1; q >= 0; --q) {
+                double sv = gi[q];
+                for (int k = q + 1; k < ji; ++k) sv -= Hi[static_cast<size_t>(q) * m + k] * yi[k];
+                yi[q] = Hi[static_cast<size_t>(q) * m + q] != 0.0 ? sv / Hi[static_cast<size_t>(q) * m + q] : 0.0;
+            }
+        }
+        AMG_HIP(hipMemcpyAsync(ycoef.p, Y.data(), Y.size() * sizeof(double), hipMemcpyHostToDevice, h->stream));
+        AMG_HIP(hipMemcpyAsync(cnt.p, jcnt.data(), ns * sizeof(int), hipMemcpyHostToDevice, h->stream));
+        launch_seg_multi_add(Z, n, ycoef.p, m, cnt.p, x, t, h->stream);
+        system_residual(h, b, x, V);
+        seg_norms(h, V, partial, hb, kmax, beta);
+        for (int i = 0; i < ns; ++i)
+            if (active[i] && beta[i] / r0[i] <= tol) {
+                status[i] = AMG_OK;
+                active[i] = 0;
+            }
+    }
+    system_residual(h, b, x, h->kw.p);
+    std::vector<double> fin;
+    seg_norms(h, h->kw.p, partial, hb, kmax, fin);
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    int worst = AMG_OK;
+    for (int j = 0; j < ns; ++j) {
+        const double rel = r0[j] > 0.0 ? fin[j] / r0[j] : 0.0;
+        int st = status[j];
+        if (st == AMG_OK && !(rel == rel)) st = AMG_DIVERGED;
+        if (res) {
+            amg_result &o = res[h->b_order[j]];
+            o.iters = iters[j];
+            o.status = st;
+            o.relres = rel;
+            o.solve_ms = ms;
+        }
+        worst = std::max(worst, st);
+    }
+    profile_collect(h);
+    return worst;
+}
+
+}  // namespace amgp2

@@ -7,6 +7,7 @@
 
 #include "common.h"
 #include "host_setup.h"
+#include "batch.h"
 #include "kernels.h"
 #include "learn.h"
 #include "mixed.h"
@@ -129,6 +130,30 @@ struct Level {
     int64_t vlen() const { return 3 * static_cast<int64_t>(n) + n_pres; }
 };
 
+// Chunk table of a batch vector (see ChunkView); dst: second start per chunk
+// for copies between layouts.
+struct ChunkTable {
+    int n = 0;
+    DevBuf<int64_t> start, dst;
+    DevBuf<int> len, seg;
+    void build(const std::vector<int64_t> &st, const std::vector<int> &ln, const std::vector<int> &sg,
+               const std::vector<int64_t> &ds, hipStream_t s) {
+        n = static_cast<int>(st.size());
+        start.upload(st, s);
+        len.upload(ln, s);
+        seg.upload(sg, s);
+        if (!ds.empty()) dst.upload(ds, s);
+    }
+    ChunkView view() const {
+        ChunkView v;
+        v.n = n;
+        v.start = start.p;
+        v.len = len.p;
+        v.seg = seg.p;
+        return v;
+    }
+};
+
 struct ProfStat {
     int64_t launches = 0;
     double ms = 0.0, bytes = 0.0;
@@ -166,6 +191,16 @@ struct amg_ctx {
     // flexible GMRES workspace: V ((m+1) x n), Z (m x n), device scalars
     amgp2::DevBuf<double> gm_V, gm_Z, gm_h, gm_y;
     int gm_m = 0;
+    // batch of independent saddle systems merged level by level (nsys > 0):
+    // merged position q holds caller system b_order[q]; systems are ordered
+    // by decreasing depth so that those still coarsening on a level lead it
+    int nsys = 0;
+    std::vector<int> b_order;
+    std::vector<int64_t> b_uoff, b_poff, b_nu, b_np;  // per merged position, level-0 vector
+    amgp2::ChunkTable b_chunks;                       // level-0 vector, by system
+    amgp2::DevBuf<int> b_c0, b_c1, b_c2, b_c3;        // chunk runs of each system
+    amgp2::ChunkTable b_in, b_out;                    // caller layout <-> merged layout
+    amgp2::DevBuf<double> b_b, b_x;                   // merged-layout right-hand side / iterate
     // Krylov workspace
     amgp2::DevBuf<double> kr, kz, kp, kq, kw;
     amgp2::DevBuf<double> partial, sc;
@@ -206,6 +241,9 @@ void system_residual(amg_ctx *h, const double *b, const double *x, double *r);
 int solve_fgmres(amg_ctx *h, const double *b, double *x, double tol, int maxit, amg_result *res);
 int solve_stationary_saddle(amg_ctx *h, const double *b, double *x, double tol, int maxit, amg_result *res);
 void precondition_any(amg_ctx *h, const double *r, double *z);
+// batches
+void build_batch(amg_ctx *h, int nsys, const amg_system *sys);
+int solve_fgmres_batched(amg_ctx *h, const double *b, double *x, double tol, int maxit, amg_result *res);
 void saddle_apply(amg_ctx *h, int l, const double *x, double *y);
 void saddle_smooth(amg_ctx *h, int l, const double *b, double *x);
 void vcycle(amg_ctx *h, int l, const double *b, double *x);

@@ -93,22 +93,23 @@ void launch_blk(int br, int bc, int op, int G, const BlkArgs &a, hipStream_t s) 
     else throw Error(AMG_EINVAL, "block kernel: unsupported block shape");
 }
 
-__global__ void k_sgs_u(int64_t n, const double *dinv, const double *r, double damping, double *t, double *u) {
+__global__ void k_sgs_u(int64_t n, int64_t ld, const double *dinv, const double *r, double damping, double *t,
+                        double *u) {
     const int64_t q = static_cast<int64_t>(blockIdx.x) * SB + threadIdx.x;
     if (q >= 3 * n) return;
     const int64_t i = q / 3;
     const int c = static_cast<int>(q % 3);
-    const double d = dinv[(3 * c) * n + i] * r[3 * i] + dinv[(3 * c + 1) * n + i] * r[3 * i + 1] +
-                     dinv[(3 * c + 2) * n + i] * r[3 * i + 2];
+    const double d = dinv[(3 * c) * ld + i] * r[3 * i] + dinv[(3 * c + 1) * ld + i] * r[3 * i + 1] +
+                     dinv[(3 * c + 2) * ld + i] * r[3 * i + 2];
     const double v = damping * d;
     t[q] = v;
     u[q] += v;
 }
 
-void launch_sgs_u(int64_t n, const double *dinv, const double *r, double damping, double *t, double *u,
+void launch_sgs_u(int64_t n, int64_t ld, const double *dinv, const double *r, double damping, double *t, double *u,
                   hipStream_t s) {
     if (n <= 0) return;
-    k_sgs_u<<<ceil_div(3 * n, SB), SB, 0, s>>>(n, dinv, r, damping, t, u);
+    k_sgs_u<<<ceil_div(3 * n, SB), SB, 0, s>>>(n, ld, dinv, r, damping, t, u);
     AMG_CHECK_LAUNCH();
 }
 

@@ -33,8 +33,9 @@ struct BlkArgs {
 // br, bc in {1, 3}; G lanes per row
 void launch_blk(int br, int bc, int op, int G, const BlkArgs &a, hipStream_t s);
 
-// sGS velocity step: t_i = damping * D_i^{-1} r_i; u_i += t_i (3x3 blocks)
-void launch_sgs_u(int64_t n, const double *dinv, const double *r, double damping, double *t, double *u,
+// sGS velocity step on the first n nodes: t_i = damping * D_i^{-1} r_i;
+// u_i += t_i (3x3 blocks, dinv planes of stride ld >= n)
+void launch_sgs_u(int64_t n, int64_t ld, const double *dinv, const double *r, double damping, double *t, double *u,
                   hipStream_t s);
 // sGS pressure scaling 1 / (damping * sum_k b_k^T D_{col k}^{-1} b_k + C_pp)
 void launch_sgs_scale(int np, const int *brow, const int *bcol, const double *bval, int64_t bnnz,

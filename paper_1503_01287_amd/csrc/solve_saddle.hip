@@ -132,7 +132,7 @@ static void sgs_step(amg_ctx *h, int l, const double *b, double *x, bool x_zero)
         saddle_residual_rows(h, l, b, x, L.r.p, L.nA, L.npA);
         r = L.r.p;
     }
-    launch_sgs_u(L.nA, L.dinv.p, r, h->prm.sgs_damping, L.t.p, x, h->stream);
+    launch_sgs_u(L.nA, L.n, L.dinv.p, r, h->prm.sgs_damping, L.t.p, x, h->stream);
     BlkArgs bb = blk(L.B);
     bb.nrows = L.npA;
     bb.x = L.t.p;

@@ -54,6 +54,30 @@ def _dev_ptr(t, n: int, name: str):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _marshal(system: LinearSystem, keep: list) -> "C.AmgSystem":
+    """amg_system over host copies of the arrays (kept alive in `keep`)."""
+    def arr(a, dtype, ctype):
+        if a is None:
+            return None
+        a = np.ascontiguousarray(a, dtype=dtype)
+        keep.append(a)
+        return C._ptr(a, ctype)
+
+    s = C.AmgSystem()
+    s.n_lin, s.n_quad, s.n_pres, s.bs = system.n_lin, system.n_quad, system.n_pres, system.bs
+    s.A_rowptr = arr(system.A_rowptr, np.int32, ctypes.c_int32)
+    s.A_col = arr(system.A_col, np.int32, ctypes.c_int32)
+    s.A_val = arr(system.A_val, np.float64, ctypes.c_double)
+    s.B_rowptr = arr(system.B_rowptr, np.int32, ctypes.c_int32)
+    s.B_col = arr(system.B_col, np.int32, ctypes.c_int32)
+    s.B_val = arr(system.B_val, np.float64, ctypes.c_double)
+    s.C_rowptr = arr(system.C_rowptr, np.int32, ctypes.c_int32)
+    s.C_col = arr(system.C_col, np.int32, ctypes.c_int32)
+    s.C_val = arr(system.C_val, np.float64, ctypes.c_double)
+    s.pressure_kernel = 1 if system.pressure_kernel else 0
+    return s
+
+
 class AMGSolver:
     """amg_setup on construction; amg_solve / amg_precondition / ... on call."""
 
@@ -88,26 +112,7 @@ class AMGSolver:
         self.params = p
         self.system = system
         keep = []
-
-        def arr(a, dtype, ctype):
-            if a is None:
-                return None
-            a = np.ascontiguousarray(a, dtype=dtype)
-            keep.append(a)
-            return C._ptr(a, ctype)
-
-        s = C.AmgSystem()
-        s.n_lin, s.n_quad, s.n_pres, s.bs = system.n_lin, system.n_quad, system.n_pres, system.bs
-        s.A_rowptr = arr(system.A_rowptr, np.int32, ctypes.c_int32)
-        s.A_col = arr(system.A_col, np.int32, ctypes.c_int32)
-        s.A_val = arr(system.A_val, np.float64, ctypes.c_double)
-        s.B_rowptr = arr(system.B_rowptr, np.int32, ctypes.c_int32)
-        s.B_col = arr(system.B_col, np.int32, ctypes.c_int32)
-        s.B_val = arr(system.B_val, np.float64, ctypes.c_double)
-        s.C_rowptr = arr(system.C_rowptr, np.int32, ctypes.c_int32)
-        s.C_col = arr(system.C_col, np.int32, ctypes.c_int32)
-        s.C_val = arr(system.C_val, np.float64, ctypes.c_double)
-        s.pressure_kernel = 1 if system.pressure_kernel else 0
+        s = _marshal(system, keep)
         self._stream = stream
         h = ctypes.c_void_p()
         C.check(L.amg_setup(ctypes.byref(s), ctypes.byref(p), _stream_handle(stream), ctypes.byref(h)),
@@ -212,3 +217,79 @@ class AMGSolver:
             self.close()
         except Exception:
             pass
+
+
+class BatchedSolver:
+    """amg_setup_batched over several saddle point systems; vectors are the
+    systems' [u; p] one after another, in the order given."""
+
+    def __init__(self, systems, smoother: str = "BS-1-1", cycles: int = 1, nu: int = 1,
+                 coarse_max: int = 300, max_levels: int = 10, sgs_omega: float = 0.125,
+                 sgs_damping: float = 0.5, restart: int = 100, stream=None):
+        L = C.lib()
+        p = C.default_params()
+        sm = parse_smoother(smoother)
+        p.smoother = C.SMOOTH[sm["smoother"]]
+        p.pre, p.post = sm["pre"], sm["post"]
+        p.sgs_omega, p.sgs_damping = sgs_omega, sgs_damping
+        p.cycles, p.nu = cycles, nu
+        p.coarse_max, p.max_levels = coarse_max, max_levels
+        p.krylov = C.KRYLOV["FGMRES"]
+        p.restart = restart
+        self.params = p
+        self.systems = list(systems)
+        keep = []
+        arr = (C.AmgSystem * len(self.systems))()
+        for i, sysm in enumerate(self.systems):
+            arr[i] = _marshal(sysm, keep)
+        self._stream = stream
+        h = ctypes.c_void_p()
+        C.check(L.amg_setup_batched(len(self.systems), arr, ctypes.byref(p), _stream_handle(stream),
+                                    ctypes.byref(h)), "amg_setup_batched")
+        self.h = h
+        self.sizes = [s.dofs for s in self.systems]
+        self.n = int(sum(self.sizes))
+
+    def solve(self, b, x, tol: float = 1e-8, maxit: int = 500) -> list:
+        res = (C.AmgResult * len(self.systems))()
+        code = C.lib().amg_solve_batched(self.h, _dev_ptr(b, self.n, "b"), _dev_ptr(x, self.n, "x"), float(tol),
+                                         int(maxit), _stream_handle(self._stream), res)
+        C.check(code, "amg_solve_batched")
+        return [SolveResult(r.iters, r.status, r.relres, r.solve_ms) for r in res]
+
+    def offsets(self):
+        """(velocity offsets, pressure offsets) of every system in the merged level-0 vector."""
+        u = np.zeros(len(self.systems), dtype=np.int64)
+        q = np.zeros(len(self.systems), dtype=np.int64)
+        C.check(C.lib().amg_batch_offsets(self.h, u.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                          q.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))), "amg_batch_offsets")
+        return u, q
+
+    def precondition(self, r, z) -> None:
+        """One preconditioner application in the merged layout."""
+        C.check(C.lib().amg_precondition(self.h, _dev_ptr(r, self.n, "r"), _dev_ptr(z, self.n, "z"),
+                                         _stream_handle(self._stream)), "amg_precondition")
+
+    @property
+    def num_levels(self) -> int:
+        return C.check(C.lib().amg_num_levels(self.h), "amg_num_levels")
+
+    def level_info(self, level: int):
+        info = C.AmgLevelInfo()
+        C.check(C.lib().amg_get_level_info(self.h, level, ctypes.byref(info)), "amg_get_level_info")
+        return info
+
+    def profile(self, mode: int = 1) -> None:
+        C.check(C.lib().amg_profile_enable(self.h, int(mode)), "amg_profile_enable")
+
+    def close(self) -> None:
+        if getattr(self, "h", None):
+            C.lib().amg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
