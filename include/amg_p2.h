@@ -149,6 +149,10 @@ typedef struct {
                              that is not finite or not inside (0.2, 1.2)
                              falls back to omega / level_omega. Only read
                              during amg_setup.                               */
+    int32_t graph;        /* 1 (default): each preconditioner application is
+                             recorded once into a HIP graph and replayed
+                             (same kernels, same order, same results); 0:
+                             launched one by one. Profiling runs unrecorded. */
 } amg_params;
 
 typedef struct {

@@ -47,7 +47,7 @@ class AmgParams(ctypes.Structure):
         ("restart", ctypes.c_int32), ("precision", ctypes.c_int32),
         ("n_level_omega", ctypes.c_int32), ("level_omega", _f64p),
         ("fuse_coarse", ctypes.c_int32), ("autotune", ctypes.c_int32),
-        ("omega_model", ctypes.c_void_p),
+        ("omega_model", ctypes.c_void_p), ("graph", ctypes.c_int32),
     ]
 
 

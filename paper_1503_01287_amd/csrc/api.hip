@@ -14,6 +14,7 @@ void set_last_error(const std::string &msg) { g_last_error = msg; }
 using namespace amgp2;
 
 amg_ctx::~amg_ctx() {
+    for (auto &g : graphs) (void)hipGraphExecDestroy(g.exec);
     for (auto &pe : pending) {
         (void)hipEventDestroy(pe.a);
         (void)hipEventDestroy(pe.b);
@@ -62,6 +63,7 @@ void amg_default_params(amg_params *p) {
     p->fuse_coarse = 1;
     p->autotune = 1;
     p->omega_model = nullptr;
+    p->graph = 1;
 }
 
 int amg_setup(const amg_system *sys, const amg_params *params, amg_stream stream, amg_handle *out) {
@@ -447,6 +449,9 @@ int amg_set_level_omega(amg_handle h, int32_t n, const double *omega) {
         for (int i = 0; i < n; ++i)
             AMG_REQUIRE(std::isfinite(omega[i]), AMG_EINVAL, "amg_set_level_omega: weight not finite");
         h->level_omega.assign(omega, omega + n);
+        // recorded preconditioners hold the old weights
+        for (auto &g : h->graphs) (void)hipGraphExecDestroy(g.exec);
+        h->graphs.clear();
         setup_tail(h);
         refresh_tail_f32(h);
         return AMG_OK;

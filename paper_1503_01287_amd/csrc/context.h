@@ -201,6 +201,15 @@ struct amg_ctx {
     amgp2::DevBuf<int> b_c0, b_c1, b_c2, b_c3;        // chunk runs of each system
     amgp2::ChunkTable b_in, b_out;                    // caller layout <-> merged layout
     amgp2::DevBuf<double> b_b, b_x;                   // merged-layout right-hand side / iterate
+    // recorded preconditioner applications (HIP graphs) and staging vectors
+    struct GraphEntry {
+        const double *r;
+        double *z;
+        bool filled;
+        hipGraphExec_t exec;
+    };
+    std::vector<GraphEntry> graphs;
+    amgp2::DevBuf<double> g_in, g_out;
     // Krylov workspace
     amgp2::DevBuf<double> kr, kz, kp, kq, kw;
     amgp2::DevBuf<double> partial, sc;
@@ -241,6 +250,7 @@ void system_residual(amg_ctx *h, const double *b, const double *x, double *r);
 int solve_fgmres(amg_ctx *h, const double *b, double *x, double tol, int maxit, amg_result *res);
 int solve_stationary_saddle(amg_ctx *h, const double *b, double *x, double tol, int maxit, amg_result *res);
 void precondition_any(amg_ctx *h, const double *r, double *z);
+void precondition_staged(amg_ctx *h, const double *r, double *z);
 // batches
 void build_batch(amg_ctx *h, int nsys, const amg_system *sys);
 int solve_fgmres_batched(amg_ctx *h, const double *b, double *x, double tol, int maxit, amg_result *res);

@@ -237,13 +237,86 @@ void vcycle(amg_ctx *h, int l, const double *b, double *x) { cycle(h, l, b, x, t
 // z = M^{-1} r: `cycles` successive applications of Algorithm 1 on the
 // finest level, the first from z = 0, each further one from the current z.
 // z_filled: z already holds zeros.
-static void precondition_impl(amg_ctx *h, const double *r, double *z, bool z_filled) {
+static void precondition_eager(amg_ctx *h, const double *r, double *z, bool z_filled) {
+    if (h->saddle) {
+        saddle_precondition(h, r, z);
+        return;
+    }
     if (h->mixed) {
         precondition_mp(h, r, z);
         return;
     }
     const int cyc = std::max(1, h->prm.cycles);
     for (int k = 0; k < cyc; ++k) cycle(h, 0, r, z, k == 0, k == 0 && z_filled);
+}
+
+// The preconditioner's launches recorded once into a HIP graph per (r, z)
+// pair and replayed: one launch call instead of hundreds. The recording
+// runs on a stream of the library's own (a capture cannot run on the legacy
+// default stream) and contains kernels only: no host synchronisation, no
+// memset nodes, no event records (profiling runs eagerly).
+static hipGraphExec_t graph_for(amg_ctx *h, const double *r, double *z, bool z_filled) {
+    for (const auto &g : h->graphs)
+        if (g.r == r && g.z == z && g.filled == z_filled) return g.exec;
+    if (h->graphs.size() >= 8) return nullptr;
+    hipStream_t cs = nullptr;
+    AMG_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    // the capture stream must see everything ordered before it on the caller's stream
+    hipEvent_t ev;
+    AMG_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    AMG_HIP(hipEventRecord(ev, h->stream));
+    AMG_HIP(hipStreamWaitEvent(cs, ev, 0));
+    const hipStream_t saved = h->stream;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    h->stream = cs;
+    AMG_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+    try {
+        precondition_eager(h, r, z, z_filled);
+    } catch (...) {
+        (void)hipStreamEndCapture(cs, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        h->stream = saved;
+        (void)hipStreamDestroy(cs);
+        (void)hipEventDestroy(ev);
+        throw;
+    }
+    h->stream = saved;
+    AMG_HIP(hipStreamEndCapture(cs, &graph));
+    AMG_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    AMG_HIP(hipGraphDestroy(graph));
+    AMG_HIP(hipStreamSynchronize(cs));
+    AMG_HIP(hipStreamDestroy(cs));
+    AMG_HIP(hipEventDestroy(ev));
+    h->graphs.push_back({r, z, z_filled, exec});
+    return exec;
+}
+
+// z = M^{-1} r for pointers that stay the same from call to call
+static void precondition_impl(amg_ctx *h, const double *r, double *z, bool z_filled) {
+    if (h->prm.graph && !h->prof) {
+        if (hipGraphExec_t g = graph_for(h, r, z, z_filled)) {
+            AMG_HIP(hipGraphLaunch(g, h->stream));
+            return;
+        }
+    }
+    precondition_eager(h, r, z, z_filled);
+}
+
+// z = M^{-1} r for pointers that change from call to call (the flexible
+// GMRES basis): through staging vectors so that one recording serves all
+void precondition_staged(amg_ctx *h, const double *r, double *z) {
+    if (!h->prm.graph || h->prof) {
+        precondition_eager(h, r, z, false);
+        return;
+    }
+    if (h->g_in.n != static_cast<size_t>(h->n_dof)) {
+        h->g_in.alloc(h->n_dof);
+        h->g_out.alloc(h->n_dof);
+    }
+    launch_copy(h->g_in.p, r, h->n_dof, h->stream);
+    precondition_impl(h, h->g_in.p, h->g_out.p, false);
+    launch_copy(z, h->g_out.p, h->n_dof, h->stream);
 }
 
 void precondition(amg_ctx *h, const double *r, double *z) { precondition_impl(h, r, z, false); }

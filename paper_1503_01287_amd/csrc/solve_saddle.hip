@@ -327,12 +327,7 @@ void system_residual(amg_ctx *h, const double *b, const double *x, double *r) {
     }
 }
 
-void precondition_any(amg_ctx *h, const double *r, double *z) {
-    if (h->saddle)
-        saddle_precondition(h, r, z);
-    else
-        precondition(h, r, z);
-}
+void precondition_any(amg_ctx *h, const double *r, double *z) { precondition_staged(h, r, z); }
 
 // ---------------------------------------------------------------- FGMRES
 static double norm2(amg_ctx *h, const double *v) {

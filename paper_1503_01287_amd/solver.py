@@ -86,7 +86,7 @@ class AMGSolver:
                  max_levels: int = 10, separate: bool = True, level_omega=None,
                  sgs_omega: float = 0.125, sgs_damping: float = 0.5, restart: int = 100,
                  omega: float | None = None, fuse_coarse: bool = True, autotune: bool = True,
-                 omega_model=None, stream=None):
+                 omega_model=None, graph: bool = True, stream=None):
         L = C.lib()
         p = C.default_params()
         sm = parse_smoother(smoother)
@@ -104,6 +104,7 @@ class AMGSolver:
         p.autotune = 1 if autotune else 0
         if omega_model is not None:
             p.omega_model = omega_model.h
+        p.graph = 1 if graph else 0
         self._omega_buf = None
         if level_omega is not None:
             self._omega_buf = np.ascontiguousarray(level_omega, dtype=np.float64)
@@ -225,7 +226,7 @@ class BatchedSolver:
 
     def __init__(self, systems, smoother: str = "BS-1-1", cycles: int = 1, nu: int = 1,
                  coarse_max: int = 300, max_levels: int = 10, sgs_omega: float = 0.125,
-                 sgs_damping: float = 0.5, restart: int = 100, stream=None):
+                 sgs_damping: float = 0.5, restart: int = 100, graph: bool = True, stream=None):
         L = C.lib()
         p = C.default_params()
         sm = parse_smoother(smoother)
@@ -236,6 +237,7 @@ class BatchedSolver:
         p.coarse_max, p.max_levels = coarse_max, max_levels
         p.krylov = C.KRYLOV["FGMRES"]
         p.restart = restart
+        p.graph = 1 if graph else 0
         self.params = p
         self.systems = list(systems)
         keep = []
@@ -281,6 +283,14 @@ class BatchedSolver:
 
     def profile(self, mode: int = 1) -> None:
         C.check(C.lib().amg_profile_enable(self.h, int(mode)), "amg_profile_enable")
+
+    def profile_read(self, cls: str) -> dict:
+        n = ctypes.c_int64()
+        ms = ctypes.c_double()
+        by = ctypes.c_double()
+        C.check(C.lib().amg_profile_read(self.h, cls.encode(), ctypes.byref(n), ctypes.byref(ms),
+                                         ctypes.byref(by)), "amg_profile_read")
+        return dict(launches=n.value, ms=ms.value, bytes=by.value)
 
     def close(self) -> None:
         if getattr(self, "h", None):
