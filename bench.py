@@ -209,7 +209,7 @@ def main() -> int:
         for l in range(solver.num_levels):
             i = solver.level_info(l)
             levels.append(dict(nodes=i.n_lin + i.n_quad, pressure=i.n_pres, nnz=int(i.nnz_A), colors=int(i.n_colors),
-                               lanes=[int(i.lanes_A), int(i.lanes_gs)], fused=bool(i.fused),
+                               lanes=[int(i.lanes_A), int(i.lanes_gs)], gs_xcd=int(i.gs_xcd), fused=bool(i.fused),
                                omega=round(float(i.omega), 4)))
         print(f"# {precision}/{krylov} setup {setup_ms:.0f} ms, levels {levels}", file=sys.stderr, flush=True)
         for _ in range(args.warmup):

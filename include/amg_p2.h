@@ -180,6 +180,8 @@ typedef struct {
                                       hierarchy of this level's Schur
                                       complement (0 if not built)             */
     int64_t nnz_S;                 /* entries of that Schur complement S_l   */
+    int32_t gs_xcd;                /* 1 if the colour sweeps give each XCD one
+                                      contiguous eighth of a colour's rows    */
 } amg_level_info;
 
 /* Fill *p with the defaults listed above. */

@@ -262,8 +262,10 @@ static void autotune_level(amg_ctx *h, Level &L) {
         }
     }
     if (!L.cptr.empty()) {
-        // a whole forward sweep, colour by colour, as the smoother runs it
+        // a whole forward sweep, colour by colour, as the smoother runs it,
+        // with round-robin or per-XCD contiguous workgroup placement
         best = 1e30f;
+        for (int xcd = 0; xcd < 2; ++xcd)
         for (int G : cand) {
             auto sweep = [&] {
                 for (size_t c = 0; c + 1 < L.cptr.size(); ++c) {
@@ -280,6 +282,7 @@ static void autotune_level(amg_ctx *h, Level &L) {
                     a.y = L.t.p;
                     a.dinv = L.dinv.p;
                     a.dinv_n = L.n;
+                    a.xcd_chunks = xcd;
                     launch_row(L.mode, OP_GS, G, a, s);
                 }
             };
@@ -287,6 +290,7 @@ static void autotune_level(amg_ctx *h, Level &L) {
             if (ms < best) {
                 best = ms;
                 L.Gg = G;
+                L.gs_xcd = xcd;
             }
         }
     }

@@ -38,7 +38,8 @@ __device__ __forceinline__ float ld(const void *p, int64_t idx) {
 
 template <int MODE, int G, int OP, int KIND>
 __global__ void __launch_bounds__(MBLOCK) k_row_mp(const RowArgsMP a) {
-    const int64_t t = static_cast<int64_t>(blockIdx.x) * MBLOCK + threadIdx.x;
+    const int64_t blk = a.xcd_chunks ? xcd_chunk_block() : static_cast<int64_t>(blockIdx.x);
+    const int64_t t = blk * MBLOCK + threadIdx.x;
     const int g = static_cast<int>(t / G);
     const int lane = static_cast<int>(t % G);
     const bool active = g < a.nrows;
@@ -108,8 +109,9 @@ __global__ void __launch_bounds__(MBLOCK) k_row_mp(const RowArgsMP a) {
 
 template <int MODE, int G, int KIND>
 static void launch_mp_g(int op, const RowArgsMP &a, hipStream_t s) {
-    const int nb = ceil_div(static_cast<int64_t>(a.nrows) * G, MBLOCK);
+    int nb = ceil_div(static_cast<int64_t>(a.nrows) * G, MBLOCK);
     if (nb == 0) return;
+    if (a.xcd_chunks) nb = (nb + 7) / 8 * 8;
     switch (op) {
         case OP_SPMV: k_row_mp<MODE, G, OP_SPMV, KIND><<<nb, MBLOCK, 0, s>>>(a); break;
         case OP_SPMV_ADD: k_row_mp<MODE, G, OP_SPMV_ADD, KIND><<<nb, MBLOCK, 0, s>>>(a); break;

@@ -42,9 +42,11 @@ template <int MODE, int G, int OP>
 __global__ void __launch_bounds__(BLOCK) k_row(const RowArgs a) {
     // Workgroups are dispatched round-robin over the 8 XCDs, so consecutive
     // row blocks run on different XCDs at the same time and the whole chip
-    // streams through one region of the matrix. (Remapping ids to give each
-    // XCD a contiguous range measured 1.9x slower on the finest level.)
-    const int64_t t = static_cast<int64_t>(blockIdx.x) * BLOCK + threadIdx.x;
+    // streams through one region of the matrix. Contiguous ranges per XCD
+    // (xcd_chunks) are chosen by the setup-time tuner where they pay: they
+    // keep each XCD's gathers of x inside its own L2.
+    const int64_t blk = a.xcd_chunks ? xcd_chunk_block() : static_cast<int64_t>(blockIdx.x);
+    const int64_t t = blk * BLOCK + threadIdx.x;
     const int g = static_cast<int>(t / G);
     const int lane = static_cast<int>(t % G);
     const bool active = g < a.nrows;
@@ -142,8 +144,12 @@ int row_blocks(int nrows, int G) { return ceil_div(static_cast<int64_t>(nrows) *
 
 template <int MODE, int G>
 static void launch_row_g(RowOp op, const RowArgs &a, hipStream_t s) {
-    const int nb = row_blocks(a.nrows, G);
+    int nb = row_blocks(a.nrows, G);
     if (nb == 0) return;
+    if (a.xcd_chunks) {
+        AMG_REQUIRE(op != OP_SPMV_DOT, AMG_EINVAL, "row kernel: XCD chunks with block partials");
+        nb = (nb + 7) / 8 * 8;
+    }
     switch (op) {
         case OP_SPMV: k_row<MODE, G, OP_SPMV><<<nb, BLOCK, 0, s>>>(a); break;
         case OP_SPMV_ADD: k_row<MODE, G, OP_SPMV_ADD><<<nb, BLOCK, 0, s>>>(a); break;

@@ -39,6 +39,7 @@ struct RowArgs {
     double omega = 1.0;
     double *partial = nullptr;      // per-block partial sums (SPMV_DOT)
     double *zero_out = nullptr;     // if set: zero_out_i = 0 for every row i written
+    int xcd_chunks = 0;             // 1: each XCD takes one contiguous eighth of the rows
 };
 
 // mode: 3 = 3x3 blocks; 1 = scalar entries applied to 3-component vectors.
@@ -47,6 +48,14 @@ void launch_row(int mode, RowOp op, int G, const RowArgs &a, hipStream_t s);
 
 // Number of blocks the row kernel uses (size of the partial-sum buffer).
 int row_blocks(int nrows, int G);
+
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup w runs on
+// XCD w mod 8). With a grid padded to a multiple of 8, this maps the
+// workgroups of XCD k to the k-th contiguous eighth of the logical blocks, so
+// that each XCD's L2 holds the vector entries of one region of the mesh.
+__device__ __forceinline__ int64_t xcd_chunk_block() {
+    return static_cast<int64_t>(blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+}
 
 // ---------------------------------------------------------------- vectors
 void launch_fill(double *x, double v, int64_t n, hipStream_t s);

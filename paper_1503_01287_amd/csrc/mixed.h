@@ -27,6 +27,7 @@ struct RowArgsMP {
     int64_t dinv_n = 0;
     float omega = 1.f;
     float *zero_out = nullptr;
+    int xcd_chunks = 0;             // as RowArgs::xcd_chunks
 };
 
 // Same operations as launch_row (OP_SPMV, OP_SPMV_ADD, OP_RESID, OP_JACOBI,

@@ -144,6 +144,7 @@ static void gs_sweep(amg_ctx *h, int l, const double *b, double *x, bool forward
         a.y = x;
         a.dinv = L.dinv.p;
         a.dinv_n = L.n;
+        a.xcd_chunks = L.gs_xcd;
         // matrix rows of this colour + row pointer, row id, b_i, x_i read and
         // write, inverted diagonal block
         const double bytes = static_cast<double>(L.colour_nnz[c]) * (L.Ag.np * 8.0 + 4.0) +

@@ -144,6 +144,7 @@ static void gs_mp(amg_ctx *h, int l, const float *b, float *x, bool forward, boo
         a.y = x;
         a.dinv = L.mp.dinv.p;
         a.dinv_n = L.n;
+        a.xcd_chunks = L.gs_xcd;
         ProfScope ps(h, tag("gs", l), mat_bytes(L, L.colour_nnz[c], a.nrows) + a.nrows * (4.0 + 12.0 + 24.0 + nb * 4.0));
         launch_row_mp(L.mode, OP_GS, L.Gg, L.mp.kind, a, h->stream);
     }
