@@ -38,7 +38,7 @@ WORKLOADS = {
                                 smoother="sGS-1-1", saddle=True),
     "stokes-batch-64": dict(desc="64 lid-driven Stokes cavities (Taylor-Hood, mirrored Kuhn split), n^3 cubes with "
                                  "n ~ U{8..20}, lid speed ~ U[0.5, 2], mu=0.5, one merged hierarchy",
-                            smoother="BS-1-1", saddle=True, batch=True),
+                            smoother="BS-1-1", saddle=True, batch=True, precision="FP32"),
 }
 
 
@@ -157,8 +157,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the event-timed pass")
     ap.add_argument("--precision", default="MIXED", choices=["MIXED", "FP32", "FP64"],
-                    help="cycle arithmetic of the timed solve of an SPD workload (FP64 outer loop always); "
-                         "the FP64 PCG solve is timed beside it for comparison. Saddle workloads run FP64.")
+                    help="cycle arithmetic of the timed solve (FP64 outer loop always; the Stokes batch "
+                         "uses FP32 unless FP64 is asked for); the plain FP64 solve is timed beside it")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -171,7 +171,7 @@ def main() -> int:
 
     wl = WORKLOADS[args.workload]
     saddle, batch = wl.get("saddle", False), wl.get("batch", False)
-    precision = "FP64" if saddle else args.precision
+    precision = wl.get("precision", args.precision) if args.precision != "FP64" else "FP64"
     t0 = time.perf_counter()
     sysm = build_system(args.workload)
     t_asm = time.perf_counter() - t0
@@ -185,7 +185,7 @@ def main() -> int:
 
     def make(precision: str, krylov: str, with_model: bool):
         if batch:
-            return amg.BatchedSolver(sysm.systems, smoother=wl["smoother"])
+            return amg.BatchedSolver(sysm.systems, smoother=wl["smoother"], precision=precision)
         kw = {"omega_model": model} if (with_model and model is not None) else {}
         return amg.AMGSolver(sysm, smoother=wl["smoother"], krylov=krylov, precision=precision, **kw)
 
@@ -266,8 +266,8 @@ def main() -> int:
         return out
 
     if saddle:
-        prim = run_variant("FP64", "FGMRES", not args.no_profile)
-        comp = None
+        prim = run_variant(precision, "FGMRES", not args.no_profile)
+        comp = run_variant("FP64", "FGMRES", False) if precision != "FP64" else None
     else:
         primary_kry = "PCG" if precision == "FP64" else "FCG"
         prim = run_variant(precision, primary_kry, not args.no_profile, with_model=use_model)
@@ -277,7 +277,7 @@ def main() -> int:
     if batch:
         t_all, its = 0.0, []
         for s_ in sysm.systems:
-            single = amg.AMGSolver(s_, smoother=wl["smoother"], krylov="FGMRES")
+            single = amg.AMGSolver(s_, smoother=wl["smoother"], krylov="FGMRES", precision=precision)
             bb = torch.from_numpy(s_.rhs).to(dev)
             xx = torch.zeros_like(bb)
             single.solve(bb, xx, tol=args.tol, maxit=1000)
@@ -291,7 +291,8 @@ def main() -> int:
             single.close()
         unbatched = {"ms_per_step": round(t_all * 1e3, 2), "value": round(sysm.dofs / t_all, 1),
                      "iterations_max": max(its), "iterations_min": min(its),
-                     "note": "the same systems, one amg_solve after another (warm, FGMRES, same smoother)"}
+                     "note": "the same systems, one amg_solve after another (warm, FGMRES, same smoother "
+                             "and precision)"}
         print(f"# unbatched: {t_all * 1e3:.1f} ms for all systems", file=sys.stderr, flush=True)
 
     # reference solution for the error of each variant: FP64 to 1e-12 (untimed)
@@ -339,11 +340,8 @@ def main() -> int:
               file=sys.stderr, flush=True)
 
     kry = prim["krylov"]
-    if saddle:
-        dtype = "f64"
-    else:
-        dtype = "f64" if precision == "FP64" else (
-            "f32 cycle, f64 outer" if precision == "FP32" else "f32/bf16 cycle, f64 outer")
+    dtype = "f64" if precision == "FP64" else (
+        "f32 cycle, f64 outer" if precision == "FP32" else "f32/bf16 cycle, f64 outer")
     out = {
         "metric": "DOF-solves/s to 1e-8 rel. residual (mixed/learned vs plain FP64); V-cycle HBM GB/s",
         "value": round(value, 1),

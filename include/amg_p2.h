@@ -77,6 +77,10 @@ typedef void *amg_stream; /* hipStream_t */
                             Krylov loop, its dots and the coarsest solve FP64.
                             Use a flexible outer method (FCG or FGMRES).      */
 #define AMG_PREC_FP32 2  /* as AMG_PREC_MIXED with every operator in FP32    */
+/* Saddle point systems: the same modes apply to A; B, B^T, C, the transfers,
+ * the smoothers' scalings and the Braess-Sarazin Schur hierarchies are FP32
+ * in both reduced modes; the explicit inverses of the systems that end on a
+ * level stay FP64 (FP64 accumulation). Requires AMG_KRYLOV_FGMRES. */
 
 /*
  * The linear system (Section 2.4). All pointers are HOST pointers; the
@@ -240,7 +244,8 @@ int amg_get_level_colors(amg_handle h, int32_t level, int32_t *colors);
  * ending on it are solved by their explicit inverses), and every kernel of a
  * V-cycle serves the whole batch. The outer method is flexible GMRES with
  * per-system inner products, Hessenberg matrices and convergence tests.
- * Saddle point systems only (sGS or Braess-Sarazin smoother, FGMRES, FP64).
+ * Saddle point systems only (sGS or Braess-Sarazin smoother, FGMRES; any
+ * precision mode).
  */
 int amg_setup_batched(int32_t nsys, const amg_system *systems, const amg_params *params, amg_stream stream,
                       amg_handle *out);

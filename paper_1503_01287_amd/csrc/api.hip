@@ -78,8 +78,8 @@ int amg_setup(const amg_system *sys, const amg_params *params, amg_stream stream
                         "amg_setup: saddle point systems need the sGS or Braess-Sarazin smoother");
             AMG_REQUIRE(p.krylov == AMG_KRYLOV_FGMRES || p.krylov == AMG_KRYLOV_NONE, AMG_EINVAL,
                         "amg_setup: saddle point systems need FGMRES or the stand-alone iteration");
-            AMG_REQUIRE(p.precision == AMG_PREC_FP64, AMG_EUNSUPPORTED,
-                        "amg_setup: saddle point systems run in FP64");
+            AMG_REQUIRE(p.precision == AMG_PREC_FP64 || p.krylov == AMG_KRYLOV_FGMRES, AMG_EINVAL,
+                        "amg_setup: a reduced-precision saddle cycle needs the flexible GMRES outer loop");
         } else {
             AMG_REQUIRE(p.smoother == AMG_SMOOTH_JA || p.smoother == AMG_SMOOTH_GS, AMG_EINVAL,
                         "amg_setup: SPD systems need the JA or GS smoother");
@@ -115,7 +115,8 @@ static void check_params(const amg_params &p, bool saddle) {
                     "amg_setup: saddle point systems need the sGS or Braess-Sarazin smoother");
         AMG_REQUIRE(p.krylov == AMG_KRYLOV_FGMRES || p.krylov == AMG_KRYLOV_NONE, AMG_EINVAL,
                     "amg_setup: saddle point systems need FGMRES or the stand-alone iteration");
-        AMG_REQUIRE(p.precision == AMG_PREC_FP64, AMG_EUNSUPPORTED, "amg_setup: saddle point systems run in FP64");
+        AMG_REQUIRE(p.precision == AMG_PREC_FP64 || p.krylov == AMG_KRYLOV_FGMRES, AMG_EINVAL,
+                    "amg_setup: a reduced-precision saddle cycle needs the flexible GMRES outer loop");
     }
     AMG_REQUIRE(p.krylov != AMG_KRYLOV_FGMRES || p.restart >= 1, AMG_EINVAL, "amg_setup: restart < 1");
     AMG_REQUIRE(p.pre >= 0 && p.post >= 0 && p.cycles >= 1 && p.nu >= 1 && p.nu <= 2, AMG_EINVAL,

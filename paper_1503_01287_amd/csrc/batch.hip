@@ -111,6 +111,7 @@ void build_batch(amg_ctx *h, int nsys, const amg_system *sys) {
         inst[i]->prm = p;
         inst[i]->prm.autotune = 0;
         inst[i]->prm.omega_model = nullptr;
+        inst[i]->prm.precision = AMG_PREC_FP64;  // the merged hierarchy is converted once
         inst[i]->stream = s;
         build_hierarchy(inst[i].get(), &sys[i]);
         depth[i] = static_cast<int>(inst[i]->lv.size()) - 1;
@@ -357,6 +358,10 @@ void build_batch(amg_ctx *h, int nsys, const amg_system *sys) {
     h->lv = std::move(merged);
     h->saddle = true;
     h->pinned = -1;
+    if (p.precision != AMG_PREC_FP64) {
+        build_mixed(h);
+        build_saddle_mp(h);
+    }
     h->n_dof = static_cast<int>(h->lv[0].vlen());
     const size_t nd = static_cast<size_t>(h->n_dof);
     h->b_b.alloc(nd);

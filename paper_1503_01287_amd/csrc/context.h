@@ -34,6 +34,8 @@ struct LevelMP {
     DevBuf<float> dinv;            // FP32 inverted diagonal blocks
     DevBuf<float> pval, rval;      // FP32 transfer weights
     DevBuf<float> x, b, r, t;      // FP32 work vectors
+    // saddle levels: FP32 planes of B, B^T, C, H, H^T and the smoothers' scalings
+    DevBuf<float> sB, sBt, sC, sH, sHt, sgs, ahat;
     const void *aval() const { return kind == VAL_F32 ? static_cast<const void *>(a32.p) : a16.p; }
     const void *agval() const { return kind == VAL_F32 ? static_cast<const void *>(ag32.p) : ag16.p; }
     int vbytes() const { return kind == VAL_F32 ? 4 : 2; }
@@ -83,6 +85,7 @@ struct SchurLevel {
     std::vector<int> cptr;       // rows of colour c: rowid[cptr[c] .. cptr[c+1])
     DevBuf<int> rowid;
     DevBuf<double> x, b, r;
+    DevBuf<float> s32, dinv32, x32, b32, r32;  // reduced-precision cycle
     int G = 8;
 };
 
@@ -234,6 +237,7 @@ namespace amgp2 {
 
 void build_hierarchy(amg_ctx *h, const amg_system *sys);
 void build_mixed(amg_ctx *h);
+void build_saddle_mp(amg_ctx *h);
 void precondition_mp(amg_ctx *h, const double *r, double *z);
 // saddle point path
 void saddle_setup_level(amg_ctx *h, Level &L);

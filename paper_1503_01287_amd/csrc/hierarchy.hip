@@ -714,6 +714,9 @@ void build_hierarchy(amg_ctx *h, const amg_system *sys) {
     if (!h->saddle) {
         setup_tail(h);
         build_mixed(h);
+    } else if (p.precision != AMG_PREC_FP64) {
+        build_mixed(h);
+        build_saddle_mp(h);
     }
     h->n_dof = static_cast<int>(h->lv[0].vlen());
     const size_t nd = static_cast<size_t>(h->n_dof);

@@ -8,27 +8,27 @@ namespace amgp2 {
 
 constexpr int SB = 256;
 
-template <int G>
-__device__ __forceinline__ double gsum(double v) {
+template <int G, typename T>
+__device__ __forceinline__ T gsum(T v) {
 #pragma unroll
     for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
     return v;
 }
 
-template <int BR, int BC, int G, int OP>
-__global__ void __launch_bounds__(SB) k_blk(const BlkArgs a) {
+template <typename T, int BR, int BC, int G, int OP>
+__global__ void __launch_bounds__(SB) k_blk(const BlkArgsT<T> a) {
     const int64_t t = static_cast<int64_t>(blockIdx.x) * SB + threadIdx.x;
     const int i = static_cast<int>(t / G);
     const int lane = static_cast<int>(t % G);
     const bool active = i < a.nrows;
-    double s[BR];
+    T s[BR];
 #pragma unroll
-    for (int r = 0; r < BR; ++r) s[r] = 0.0;
+    for (int r = 0; r < BR; ++r) s[r] = T(0);
     if (active) {
         const int64_t nz = a.nnz;
         for (int k = a.rowptr[i] + lane; k < a.rowptr[i + 1]; k += G) {
             const int j = a.col[k];
-            double xv[BC];
+            T xv[BC];
 #pragma unroll
             for (int c = 0; c < BC; ++c) xv[c] = a.x[BC * j + c];
 #pragma unroll
@@ -41,7 +41,7 @@ __global__ void __launch_bounds__(SB) k_blk(const BlkArgs a) {
     for (int r = 0; r < BR; ++r) s[r] = gsum<G>(s[r]);
     if (!active || lane >= BR) return;
     const int r = lane;
-    double sv = s[0];
+    T sv = s[0];
 #pragma unroll
     for (int q = 1; q < BR; ++q)
         if (r == q) sv = s[q];
@@ -53,18 +53,18 @@ __global__ void __launch_bounds__(SB) k_blk(const BlkArgs a) {
     else a.y[o] += a.omega * a.dscale[i] * (sv - a.b[o]);
 }
 
-template <int BR, int BC, int G>
-static void launch_blk_g(int op, const BlkArgs &a, hipStream_t s) {
+template <typename T, int BR, int BC, int G>
+static void launch_blk_g(int op, const BlkArgsT<T> &a, hipStream_t s) {
     const int nb = ceil_div(static_cast<int64_t>(a.nrows) * G, SB);
     if (nb == 0) return;
     switch (op) {
-        case BLK_SPMV: k_blk<BR, BC, G, BLK_SPMV><<<nb, SB, 0, s>>>(a); break;
-        case BLK_ADD: k_blk<BR, BC, G, BLK_ADD><<<nb, SB, 0, s>>>(a); break;
-        case BLK_SUB: k_blk<BR, BC, G, BLK_SUB><<<nb, SB, 0, s>>>(a); break;
-        case BLK_RESID: k_blk<BR, BC, G, BLK_RESID><<<nb, SB, 0, s>>>(a); break;
+        case BLK_SPMV: k_blk<T, BR, BC, G, BLK_SPMV><<<nb, SB, 0, s>>>(a); break;
+        case BLK_ADD: k_blk<T, BR, BC, G, BLK_ADD><<<nb, SB, 0, s>>>(a); break;
+        case BLK_SUB: k_blk<T, BR, BC, G, BLK_SUB><<<nb, SB, 0, s>>>(a); break;
+        case BLK_RESID: k_blk<T, BR, BC, G, BLK_RESID><<<nb, SB, 0, s>>>(a); break;
         case BLK_SGS_P:
             if constexpr (BR == 1) {
-                k_blk<BR, BC, G, BLK_SGS_P><<<nb, SB, 0, s>>>(a);
+                k_blk<T, BR, BC, G, BLK_SGS_P><<<nb, SB, 0, s>>>(a);
                 break;
             }
             [[fallthrough]];
@@ -73,45 +73,52 @@ static void launch_blk_g(int op, const BlkArgs &a, hipStream_t s) {
     AMG_CHECK_LAUNCH();
 }
 
-template <int BR, int BC>
-static void launch_blk_m(int op, int G, const BlkArgs &a, hipStream_t s) {
+template <typename T, int BR, int BC>
+static void launch_blk_m(int op, int G, const BlkArgsT<T> &a, hipStream_t s) {
     switch (G) {
-        case 4: launch_blk_g<BR, BC, 4>(op, a, s); break;
-        case 8: launch_blk_g<BR, BC, 8>(op, a, s); break;
-        case 16: launch_blk_g<BR, BC, 16>(op, a, s); break;
-        case 32: launch_blk_g<BR, BC, 32>(op, a, s); break;
-        case 64: launch_blk_g<BR, BC, 64>(op, a, s); break;
+        case 4: launch_blk_g<T, BR, BC, 4>(op, a, s); break;
+        case 8: launch_blk_g<T, BR, BC, 8>(op, a, s); break;
+        case 16: launch_blk_g<T, BR, BC, 16>(op, a, s); break;
+        case 32: launch_blk_g<T, BR, BC, 32>(op, a, s); break;
+        case 64: launch_blk_g<T, BR, BC, 64>(op, a, s); break;
         default: throw Error(AMG_EINVAL, "block kernel: unsupported group size");
     }
 }
 
-void launch_blk(int br, int bc, int op, int G, const BlkArgs &a, hipStream_t s) {
-    if (br == 1 && bc == 3) launch_blk_m<1, 3>(op, G, a, s);
-    else if (br == 3 && bc == 1) launch_blk_m<3, 1>(op, G, a, s);
-    else if (br == 1 && bc == 1) launch_blk_m<1, 1>(op, G, a, s);
-    else if (br == 3 && bc == 3) launch_blk_m<3, 3>(op, G, a, s);
+template <typename T>
+void launch_blk(int br, int bc, int op, int G, const BlkArgsT<T> &a, hipStream_t s) {
+    if (br == 1 && bc == 3) launch_blk_m<T, 1, 3>(op, G, a, s);
+    else if (br == 3 && bc == 1) launch_blk_m<T, 3, 1>(op, G, a, s);
+    else if (br == 1 && bc == 1) launch_blk_m<T, 1, 1>(op, G, a, s);
+    else if (br == 3 && bc == 3) launch_blk_m<T, 3, 3>(op, G, a, s);
     else throw Error(AMG_EINVAL, "block kernel: unsupported block shape");
 }
+template void launch_blk<double>(int, int, int, int, const BlkArgsT<double> &, hipStream_t);
+template void launch_blk<float>(int, int, int, int, const BlkArgsT<float> &, hipStream_t);
 
-__global__ void k_sgs_u(int64_t n, int64_t ld, const double *dinv, const double *r, double damping, double *t,
-                        double *u) {
+template <typename T>
+__global__ void k_sgs_u(int64_t n, int64_t ld, const T *dinv, const T *r, T damping, T *t, T *u) {
     const int64_t q = static_cast<int64_t>(blockIdx.x) * SB + threadIdx.x;
     if (q >= 3 * n) return;
     const int64_t i = q / 3;
     const int c = static_cast<int>(q % 3);
-    const double d = dinv[(3 * c) * ld + i] * r[3 * i] + dinv[(3 * c + 1) * ld + i] * r[3 * i + 1] +
-                     dinv[(3 * c + 2) * ld + i] * r[3 * i + 2];
-    const double v = damping * d;
+    const T d = dinv[(3 * c) * ld + i] * r[3 * i] + dinv[(3 * c + 1) * ld + i] * r[3 * i + 1] +
+                dinv[(3 * c + 2) * ld + i] * r[3 * i + 2];
+    const T v = damping * d;
     t[q] = v;
     u[q] += v;
 }
 
-void launch_sgs_u(int64_t n, int64_t ld, const double *dinv, const double *r, double damping, double *t, double *u,
-                  hipStream_t s) {
+template <typename T>
+void launch_sgs_u(int64_t n, int64_t ld, const T *dinv, const T *r, T damping, T *t, T *u, hipStream_t s) {
     if (n <= 0) return;
-    k_sgs_u<<<ceil_div(3 * n, SB), SB, 0, s>>>(n, ld, dinv, r, damping, t, u);
+    k_sgs_u<T><<<ceil_div(3 * n, SB), SB, 0, s>>>(n, ld, dinv, r, damping, t, u);
     AMG_CHECK_LAUNCH();
 }
+template void launch_sgs_u<double>(int64_t, int64_t, const double *, const double *, double, double *, double *,
+                                   hipStream_t);
+template void launch_sgs_u<float>(int64_t, int64_t, const float *, const float *, float, float *, float *,
+                                  hipStream_t);
 
 __global__ void k_sgs_scale(int np, const int *brow, const int *bcol, const double *bval, int64_t bnnz,
                             const double *dinv, int64_t nv, double damping, const int *crow, const int *ccol,
@@ -146,7 +153,8 @@ void launch_sgs_scale(int np, const int *brow, const int *bcol, const double *bv
     AMG_CHECK_LAUNCH();
 }
 
-__global__ void k_scale(int64_t n, const double *d, const double *x, double *y) {
+template <typename T>
+__global__ void k_scale(int64_t n, const T *d, const T *x, T *y) {
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * SB + threadIdx.x; i < n;
          i += static_cast<int64_t>(gridDim.x) * SB)
         y[i] = d[i] * x[i];
@@ -163,11 +171,14 @@ static int grid_s(int64_t n) {
     return static_cast<int>(nb < 1 ? 1 : nb);
 }
 
-void launch_scale(int64_t n, const double *d, const double *x, double *y, hipStream_t s) {
+template <typename T>
+void launch_scale(int64_t n, const T *d, const T *x, T *y, hipStream_t s) {
     if (n <= 0) return;
-    k_scale<<<grid_s(n), SB, 0, s>>>(n, d, x, y);
+    k_scale<T><<<grid_s(n), SB, 0, s>>>(n, d, x, y);
     AMG_CHECK_LAUNCH();
 }
+template void launch_scale<double>(int64_t, const double *, const double *, double *, hipStream_t);
+template void launch_scale<float>(int64_t, const float *, const float *, float *, hipStream_t);
 void launch_scale_diff(int64_t n, const double *d, const double *x, const double *z, double *y, hipStream_t s) {
     if (n <= 0) return;
     k_scale_diff<<<grid_s(n), SB, 0, s>>>(n, d, x, z, y);
@@ -251,15 +262,15 @@ void launch_schur_numeric(int np, const int *brow, const int *bcol, const double
     AMG_CHECK_LAUNCH();
 }
 
-template <int G>
-__global__ void __launch_bounds__(SB) k_scalar_gs(int nrows, const int *rowptr, const int *col, const double *val,
-                                                  const int *rowid, const double *dinv, const double *b, double *x) {
+template <typename T, int G>
+__global__ void __launch_bounds__(SB) k_scalar_gs(int nrows, const int *rowptr, const int *col, const T *val,
+                                                  const int *rowid, const T *dinv, const T *b, T *x) {
     const int64_t t = static_cast<int64_t>(blockIdx.x) * SB + threadIdx.x;
     const int g = static_cast<int>(t / G);
     const int lane = static_cast<int>(t % G);
     const bool active = g < nrows;
     const int i = active ? rowid[g] : 0;
-    double s = 0.0;
+    T s = T(0);
     if (active)
         for (int k = rowptr[i] + lane; k < rowptr[i + 1]; k += G) {
             const int j = col[k];
@@ -270,36 +281,58 @@ __global__ void __launch_bounds__(SB) k_scalar_gs(int nrows, const int *rowptr, 
     x[i] = (b[i] - s) * dinv[i];
 }
 
-void launch_scalar_gs(int nrows, const int *rowptr, const int *col, const double *val, const int *rowid,
-                      const double *dinv, const double *b, double *x, int G, hipStream_t s) {
+template <typename T>
+void launch_scalar_gs(int nrows, const int *rowptr, const int *col, const T *val, const int *rowid, const T *dinv,
+                      const T *b, T *x, int G, hipStream_t s) {
     if (nrows <= 0) return;
     const int nb = ceil_div(static_cast<int64_t>(nrows) * G, SB);
     switch (G) {
-        case 4: k_scalar_gs<4><<<nb, SB, 0, s>>>(nrows, rowptr, col, val, rowid, dinv, b, x); break;
-        case 8: k_scalar_gs<8><<<nb, SB, 0, s>>>(nrows, rowptr, col, val, rowid, dinv, b, x); break;
-        case 16: k_scalar_gs<16><<<nb, SB, 0, s>>>(nrows, rowptr, col, val, rowid, dinv, b, x); break;
-        case 32: k_scalar_gs<32><<<nb, SB, 0, s>>>(nrows, rowptr, col, val, rowid, dinv, b, x); break;
-        default: k_scalar_gs<64><<<nb, SB, 0, s>>>(nrows, rowptr, col, val, rowid, dinv, b, x); break;
+        case 4: k_scalar_gs<T, 4><<<nb, SB, 0, s>>>(nrows, rowptr, col, val, rowid, dinv, b, x); break;
+        case 8: k_scalar_gs<T, 8><<<nb, SB, 0, s>>>(nrows, rowptr, col, val, rowid, dinv, b, x); break;
+        case 16: k_scalar_gs<T, 16><<<nb, SB, 0, s>>>(nrows, rowptr, col, val, rowid, dinv, b, x); break;
+        case 32: k_scalar_gs<T, 32><<<nb, SB, 0, s>>>(nrows, rowptr, col, val, rowid, dinv, b, x); break;
+        default: k_scalar_gs<T, 64><<<nb, SB, 0, s>>>(nrows, rowptr, col, val, rowid, dinv, b, x); break;
     }
     AMG_CHECK_LAUNCH();
 }
+template void launch_scalar_gs<double>(int, const int *, const int *, const double *, const int *, const double *,
+                                       const double *, double *, int, hipStream_t);
+template void launch_scalar_gs<float>(int, const int *, const int *, const float *, const int *, const float *,
+                                      const float *, float *, int, hipStream_t);
 
-__global__ void k_add_scaled(int64_t n, const double *d, const double *w, double *u) {
+template <typename T>
+__global__ void k_add_scaled(int64_t n, const T *d, const T *w, T *u) {
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * SB + threadIdx.x; i < n;
          i += static_cast<int64_t>(gridDim.x) * SB)
         u[i] += d[i] * w[i];
 }
 
-void launch_add_scaled(int64_t n, const double *d, const double *w, double *u, hipStream_t s) {
+template <typename T>
+void launch_add_scaled(int64_t n, const T *d, const T *w, T *u, hipStream_t s) {
     if (n <= 0) return;
-    k_add_scaled<<<grid_s(n), SB, 0, s>>>(n, d, w, u);
+    k_add_scaled<T><<<grid_s(n), SB, 0, s>>>(n, d, w, u);
+    AMG_CHECK_LAUNCH();
+}
+template void launch_add_scaled<double>(int64_t, const double *, const double *, double *, hipStream_t);
+template void launch_add_scaled<float>(int64_t, const float *, const float *, float *, hipStream_t);
+
+__global__ void k_axpby_f(float *y, const float *x, float a, float b, int64_t n) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * SB + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * SB)
+        y[i] = a * x[i] + b * y[i];
+}
+
+void launch_axpby_f(float *y, const float *x, float a, float b, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    k_axpby_f<<<grid_s(n), SB, 0, s>>>(y, x, a, b, n);
     AMG_CHECK_LAUNCH();
 }
 
 // ---------------------------------------------------------------- dense segments
-// one wavefront per output row over all segments; lanes stride the columns
-__global__ void __launch_bounds__(SB) k_dense_segs(const DenseSegView d, const double *xu, const double *xp,
-                                                   double *yu, double *yp) {
+// one wavefront per output row over all segments; lanes stride the columns;
+// FP64 inverse and accumulation whatever the vector type
+template <typename T>
+__global__ void __launch_bounds__(SB) k_dense_segs(const DenseSegView d, const T *xu, const T *xp, T *yu, T *yp) {
     const int r = blockIdx.x * (SB / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (r >= d.rows) return;
@@ -313,24 +346,28 @@ __global__ void __launch_bounds__(SB) k_dense_segs(const DenseSegView d, const d
     const int m = d.rstart[sg + 1] - d.rstart[sg];
     const int i = r - d.rstart[sg];
     const int nu = d.nu[sg];
-    const double *xus = xu + d.uoff[sg], *xps = xp + d.poff[sg];
+    const T *xus = xu + d.uoff[sg], *xps = xp + d.poff[sg];
     const double *row = d.inv + d.moff[sg] + static_cast<int64_t>(i) * m;
     double acc = 0.0;
-    for (int j = lane; j < m; j += 64) acc += row[j] * (j < nu ? xus[j] : xps[j - nu]);
+    for (int j = lane; j < m; j += 64) acc += row[j] * static_cast<double>(j < nu ? xus[j] : xps[j - nu]);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
     if (lane == 0) {
-        if (i < nu) yu[d.uoff[sg] + i] = acc;
-        else yp[d.poff[sg] + i - nu] = acc;
+        if (i < nu) yu[d.uoff[sg] + i] = static_cast<T>(acc);
+        else yp[d.poff[sg] + i - nu] = static_cast<T>(acc);
     }
 }
 
-void launch_dense_segs(const DenseSegView &d, const double *xu, const double *xp, double *yu, double *yp,
-                       hipStream_t s) {
+template <typename T>
+void launch_dense_segs(const DenseSegView &d, const T *xu, const T *xp, T *yu, T *yp, hipStream_t s) {
     if (d.count <= 0 || d.rows <= 0) return;
-    k_dense_segs<<<ceil_div(d.rows, SB / 64), SB, 0, s>>>(d, xu, xp, yu, yp);
+    k_dense_segs<T><<<ceil_div(d.rows, SB / 64), SB, 0, s>>>(d, xu, xp, yu, yp);
     AMG_CHECK_LAUNCH();
 }
+template void launch_dense_segs<double>(const DenseSegView &, const double *, const double *, double *, double *,
+                                        hipStream_t);
+template void launch_dense_segs<float>(const DenseSegView &, const float *, const float *, float *, float *,
+                                       hipStream_t);
 
 // ---------------------------------------------------------------- FGMRES
 constexpr int MD_BLOCKS = 256;

@@ -18,31 +18,38 @@ enum BlkOp : int {
     BLK_SGS_P = 4,  // (1x3 rows of B) y_p += omega * dscale_p * (s - b_p)
 };
 
-struct BlkArgs {
+// T = double (FP64 path) or float (reduced-precision cycle: FP32 values,
+// vectors and accumulation)
+template <typename T>
+struct BlkArgsT {
     int nrows = 0;
     const int *rowptr = nullptr, *col = nullptr;
-    const double *val = nullptr;   // planes: br*bc
+    const T *val = nullptr;   // planes: br*bc
     int64_t nnz = 0;
-    const double *x = nullptr;     // bc components per column node
-    const double *b = nullptr;     // br components per row
-    double *y = nullptr;
-    const double *dscale = nullptr;
-    double omega = 1.0;
+    const T *x = nullptr;     // bc components per column node
+    const T *b = nullptr;     // br components per row
+    T *y = nullptr;
+    const T *dscale = nullptr;
+    T omega = 1;
 };
+using BlkArgs = BlkArgsT<double>;
+using BlkArgsF = BlkArgsT<float>;
 
 // br, bc in {1, 3}; G lanes per row
-void launch_blk(int br, int bc, int op, int G, const BlkArgs &a, hipStream_t s);
+template <typename T>
+void launch_blk(int br, int bc, int op, int G, const BlkArgsT<T> &a, hipStream_t s);
 
 // sGS velocity step on the first n nodes: t_i = damping * D_i^{-1} r_i;
 // u_i += t_i (3x3 blocks, dinv planes of stride ld >= n)
-void launch_sgs_u(int64_t n, int64_t ld, const double *dinv, const double *r, double damping, double *t, double *u,
-                  hipStream_t s);
+template <typename T>
+void launch_sgs_u(int64_t n, int64_t ld, const T *dinv, const T *r, T damping, T *t, T *u, hipStream_t s);
 // sGS pressure scaling 1 / (damping * sum_k b_k^T D_{col k}^{-1} b_k + C_pp)
 void launch_sgs_scale(int np, const int *brow, const int *bcol, const double *bval, int64_t bnnz,
                       const double *dinv, int64_t nv, double damping, const int *crow, const int *ccol,
                       const double *cval, int64_t cnnz, double *out, hipStream_t s);
-// y_i = d_i * x_i (elementwise, n doubles) / y_i = d_i * (x_i - z_i)
-void launch_scale(int64_t n, const double *d, const double *x, double *y, hipStream_t s);
+// y_i = d_i * x_i (elementwise) / y_i = d_i * (x_i - z_i)
+template <typename T>
+void launch_scale(int64_t n, const T *d, const T *x, T *y, hipStream_t s);
 void launch_scale_diff(int64_t n, const double *d, const double *x, const double *z, double *y, hipStream_t s);
 // 1 / (2 a_ii) for every velocity unknown (Braess-Sarazin's A_hat = 2 diag(A))
 void launch_bs_diag(int n, const int *rowptr, const int *col, const double *val, int64_t nnz, double *out,
@@ -57,10 +64,14 @@ void launch_schur_numeric(int np, const int *brow, const int *bcol, const double
                           double *sval, hipStream_t s);
 // scalar Gauss-Seidel update of the rows rowid[0..nrows) of one colour of
 // S (natural row order): x_i = dinv_i (b_i - sum_{j != i} S_ij x_j)
-void launch_scalar_gs(int nrows, const int *rowptr, const int *col, const double *val, const int *rowid,
-                      const double *dinv, const double *b, double *x, int G, hipStream_t s);
+template <typename T>
+void launch_scalar_gs(int nrows, const int *rowptr, const int *col, const T *val, const int *rowid, const T *dinv,
+                      const T *b, T *x, int G, hipStream_t s);
 // u += d .* w
-void launch_add_scaled(int64_t n, const double *d, const double *w, double *u, hipStream_t s);
+template <typename T>
+void launch_add_scaled(int64_t n, const T *d, const T *w, T *u, hipStream_t s);
+// y = a x + b y
+void launch_axpby_f(float *y, const float *x, float a, float b, int64_t n, hipStream_t s);
 
 // Explicit inverses of the systems that end on a level ("dense segments"):
 // segment s is an m_s x m_s row-major inverse at inv + moff[s] acting on the
@@ -72,9 +83,10 @@ struct DenseSegView {
     const int *rstart = nullptr, *uoff = nullptr, *nu = nullptr, *poff = nullptr;
     const double *inv = nullptr;
 };
-// y = M_s x on every segment (x and y: u parts xu/yu, p parts xp/yp)
-void launch_dense_segs(const DenseSegView &d, const double *xu, const double *xp, double *yu, double *yp,
-                       hipStream_t s);
+// y = M_s x on every segment (x and y: u parts xu/yu, p parts xp/yp); the
+// inverses stay FP64 and so does the accumulation, also for FP32 vectors
+template <typename T>
+void launch_dense_segs(const DenseSegView &d, const T *xu, const T *xp, T *yu, T *yp, hipStream_t s);
 
 // FGMRES inner products: h[i] = <V_i, w> for i < k (V_i = V + i * ld) as
 // block partials partial[i * nb + block]; returns nb

@@ -6,6 +6,7 @@
 // the coarsest solve stays the FP64 explicit inverse. The coarse end that is
 // assembled as one operator (from level dense_start down) is applied from an
 // FP32 copy of that FP64-assembled operator.
+#include <algorithm>
 #include <cmath>
 
 #include "context.h"
@@ -20,7 +21,7 @@ void build_mixed(amg_ctx *h) {
     for (size_t l = 0; l < h->lv.size(); ++l) {
         Level &L = h->lv[l];
         LevelMP &M = L.mp;
-        const size_t nv = 3 * static_cast<size_t>(L.n);
+        const size_t nv = static_cast<size_t>(L.vlen());
         M.x.alloc(nv);
         M.b.alloc(nv);
         M.r.alloc(nv);
@@ -54,6 +55,38 @@ void build_mixed(amg_ctx *h) {
         launch_to_f32(L.R.val.p, M.rval.p, L.R.nnz, s);
     }
     refresh_tail_f32(h);
+}
+
+// FP32 copies of the saddle blocks, transfers and smoother scalings, and of
+// the Braess-Sarazin Schur hierarchies (after build_mixed)
+void build_saddle_mp(amg_ctx *h) {
+    hipStream_t s = h->stream;
+    auto conv = [&](DevBuf<float> &dst, const DevBuf<double> &src) {
+        dst.alloc(std::max<size_t>(1, src.n));
+        if (src.n) launch_to_f32(src.p, dst.p, static_cast<int64_t>(src.n), s);
+    };
+    for (Level &L : h->lv) {
+        LevelMP &M = L.mp;
+        conv(M.sB, L.B.val);
+        conv(M.sBt, L.Bt.val);
+        if (L.C.nnz > 0) conv(M.sC, L.C.val);
+        if (L.H.nnz > 0) {
+            conv(M.sH, L.H.val);
+            conv(M.sHt, L.Ht.val);
+        }
+        if (L.sgs_scale.n) conv(M.sgs, L.sgs_scale);
+        if (L.bs_ahat.n) conv(M.ahat, L.bs_ahat);
+        if (L.nA > 0 && M.dinv.n == 0) conv(M.dinv, L.dinv);
+        for (SchurLevel &q : L.schur.lv) {
+            conv(q.s32, q.S.val);
+            if (q.dinv.n) conv(q.dinv32, q.dinv);
+            const size_t m = std::max<size_t>(1, q.S.nrows);
+            q.x32.alloc(m);
+            q.b32.alloc(m);
+            q.r32.alloc(m);
+        }
+    }
+    AMG_HIP(hipStreamSynchronize(s));
 }
 
 void refresh_tail_f32(amg_ctx *h) {

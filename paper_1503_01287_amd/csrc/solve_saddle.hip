@@ -44,47 +44,183 @@ void saddle_setup_level(amg_ctx *h, Level &L) {
     AMG_HIP(hipStreamSynchronize(s));
 }
 
+// ---------------------------------------------------------------- precision views
+// The cycle below runs on FP64 data (T = double) or on the FP32 copies of the
+// reduced-precision cycle (T = float); SV<T> gives the level's arrays of each.
+template <typename T>
+struct SV;
+template <>
+struct SV<double> {
+    static double *x(Level &L) { return L.x.p; }
+    static double *b(Level &L) { return L.b.p; }
+    static double *r(Level &L) { return L.r.p; }
+    static double *t(Level &L) { return L.t.p; }
+    static const double *B(const Level &L) { return L.B.val.p; }
+    static const double *Bt(const Level &L) { return L.Bt.val.p; }
+    static const double *C(const Level &L) { return L.C.val.p; }
+    static const double *H(const Level &L) { return L.H.val.p; }
+    static const double *Ht(const Level &L) { return L.Ht.val.p; }
+    static const double *dinv(const Level &L) { return L.dinv.p; }
+    static const double *sgs(const Level &L) { return L.sgs_scale.p; }
+    static const double *ahat(const Level &L) { return L.bs_ahat.p; }
+    static const double *S(const SchurLevel &q) { return q.S.val.p; }
+    static const double *sdinv(const SchurLevel &q) { return q.dinv.p; }
+    static double *sx(SchurLevel &q) { return q.x.p; }
+    static double *sb(SchurLevel &q) { return q.b.p; }
+    static double *sr(SchurLevel &q) { return q.r.p; }
+};
+template <>
+struct SV<float> {
+    static float *x(Level &L) { return L.mp.x.p; }
+    static float *b(Level &L) { return L.mp.b.p; }
+    static float *r(Level &L) { return L.mp.r.p; }
+    static float *t(Level &L) { return L.mp.t.p; }
+    static const float *B(const Level &L) { return L.mp.sB.p; }
+    static const float *Bt(const Level &L) { return L.mp.sBt.p; }
+    static const float *C(const Level &L) { return L.mp.sC.p; }
+    static const float *H(const Level &L) { return L.mp.sH.p; }
+    static const float *Ht(const Level &L) { return L.mp.sHt.p; }
+    static const float *dinv(const Level &L) { return L.mp.dinv.p; }
+    static const float *sgs(const Level &L) { return L.mp.sgs.p; }
+    static const float *ahat(const Level &L) { return L.mp.ahat.p; }
+    static const float *S(const SchurLevel &q) { return q.s32.p; }
+    static const float *sdinv(const SchurLevel &q) { return q.dinv32.p; }
+    static float *sx(SchurLevel &q) { return q.x32.p; }
+    static float *sb(SchurLevel &q) { return q.b32.p; }
+    static float *sr(SchurLevel &q) { return q.r32.p; }
+};
+
+template <typename T>
+static BlkArgsT<T> blkT(const DMat &m, const T *val) {
+    BlkArgsT<T> a;
+    a.nrows = m.nrows;
+    a.rowptr = m.rowptr.p;
+    a.col = m.col.p;
+    a.val = val;
+    a.nnz = m.nnz;
+    return a;
+}
+
+static void fillv(double *x, int64_t n, hipStream_t s) { launch_fill(x, 0.0, n, s); }
+static void fillv(float *x, int64_t n, hipStream_t s) { launch_fill_f32(x, 0.f, n, s); }
+static void copyv(double *d, const double *x, int64_t n, hipStream_t s) { launch_copy(d, x, n, s); }
+static void copyv(float *d, const float *x, int64_t n, hipStream_t s) { launch_copy_f32(d, x, n, s); }
+static void axpbyv(double *y, const double *x, double a, double b, int64_t n, hipStream_t s) {
+    launch_axpby(y, x, a, b, n, s);
+}
+static void axpbyv(float *y, const float *x, float a, float b, int64_t n, hipStream_t s) {
+    launch_axpby_f(y, x, a, b, n, s);
+}
+
+// r_u = f - A u on the first nrows velocity nodes (3x3 blocks)
+static void a_resid(amg_ctx *h, int l, const double *b, const double *x, double *r, int nrows) {
+    Level &L = h->lv[l];
+    RowArgs a;
+    a.nrows = nrows;
+    a.rowptr = L.A.rowptr.p;
+    a.col = L.A.col.p;
+    a.val = L.A.val.p;
+    a.nnz = L.A.nnz;
+    a.x = x;
+    a.b = b;
+    a.y = r;
+    ProfScope ps(h, tag("resid", l), static_cast<double>(L.A.nnz) * 76.0 + L.n * 76.0);
+    launch_row(3, OP_RESID, L.G, a, h->stream);
+}
+static void a_resid(amg_ctx *h, int l, const float *b, const float *x, float *r, int nrows) {
+    Level &L = h->lv[l];
+    RowArgsMP a;
+    a.nrows = nrows;
+    a.rowptr = L.A.rowptr.p;
+    a.col = L.A.col.p;
+    a.val = L.mp.aval();
+    a.rscale = L.mp.scale.p;
+    a.nnz = L.A.nnz;
+    a.x = x;
+    a.b = b;
+    a.y = r;
+    ProfScope ps(h, tag("resid", l), static_cast<double>(L.A.nnz) * (9.0 * L.mp.vbytes() + 4.0) + L.n * 40.0);
+    launch_row_mp(3, OP_RESID, L.G, L.mp.kind, a, h->stream);
+}
+// velocity restriction (R = P^T, scalar per component) into the next level
+static void restrict_u(amg_ctx *h, int l, const double *r, double *bc) {
+    Level &L = h->lv[l];
+    RowArgs a;
+    a.nrows = L.R.nrows;
+    a.rowptr = L.R.rowptr.p;
+    a.col = L.R.col.p;
+    a.val = L.R.val.p;
+    a.nnz = L.R.nnz;
+    a.x = r;
+    a.y = bc;
+    launch_row(1, OP_SPMV, L.Gr, a, h->stream);
+}
+static void restrict_u(amg_ctx *h, int l, const float *r, float *bc) {
+    Level &L = h->lv[l];
+    RowArgsMP a;
+    a.nrows = L.R.nrows;
+    a.rowptr = L.R.rowptr.p;
+    a.col = L.R.col.p;
+    a.val = L.mp.rval.p;
+    a.nnz = L.R.nnz;
+    a.x = r;
+    a.y = bc;
+    launch_row_mp(1, OP_SPMV, L.Gr, VAL_F32, a, h->stream);
+}
+static void prolong_u(amg_ctx *h, int l, const double *xc, double *x) {
+    Level &L = h->lv[l];
+    RowArgs a;
+    a.nrows = L.P.nrows;
+    a.rowptr = L.P.rowptr.p;
+    a.col = L.P.col.p;
+    a.val = L.P.val.p;
+    a.nnz = L.P.nnz;
+    a.x = xc;
+    a.y = x;
+    launch_row(1, OP_SPMV_ADD, L.Gp, a, h->stream);
+}
+static void prolong_u(amg_ctx *h, int l, const float *xc, float *x) {
+    Level &L = h->lv[l];
+    RowArgsMP a;
+    a.nrows = L.P.nrows;
+    a.rowptr = L.P.rowptr.p;
+    a.col = L.P.col.p;
+    a.val = L.mp.pval.p;
+    a.nnz = L.P.nnz;
+    a.x = xc;
+    a.y = x;
+    launch_row_mp(1, OP_SPMV_ADD, L.Gp, VAL_F32, a, h->stream);
+}
+
 // r = [f - A u - B^T p ; g - B u + C p] on level l for the first nrows_u
 // velocity nodes and nrows_p pressure nodes (r and b are full level vectors)
-static void saddle_residual_rows(amg_ctx *h, int l, const double *b, const double *x, double *r, int nrows_u,
-                                 int nrows_p) {
+template <typename T>
+static void saddle_residual_rows(amg_ctx *h, int l, const T *b, const T *x, T *r, int nrows_u, int nrows_p) {
     Level &L = h->lv[l];
     const int64_t nu = 3 * static_cast<int64_t>(L.n);
-    {
-        RowArgs a;
-        a.nrows = nrows_u;
-        a.rowptr = L.A.rowptr.p;
-        a.col = L.A.col.p;
-        a.val = L.A.val.p;
-        a.nnz = L.A.nnz;
-        a.x = x;
-        a.b = b;
-        a.y = r;
-        ProfScope ps(h, tag("resid", l), static_cast<double>(L.A.nnz) * 76.0 + L.n * 76.0);
-        launch_row(3, OP_RESID, L.G, a, h->stream);
-    }
-    BlkArgs bt = blk(L.Bt);
+    a_resid(h, l, b, x, r, nrows_u);
+    BlkArgsT<T> bt = blkT<T>(L.Bt, SV<T>::Bt(L));
     bt.nrows = nrows_u;
     bt.x = x + nu;
     bt.y = r;
-    launch_blk(3, 1, BLK_SUB, L.Gbt, bt, h->stream);
-    BlkArgs bb = blk(L.B);
+    launch_blk<T>(3, 1, BLK_SUB, L.Gbt, bt, h->stream);
+    BlkArgsT<T> bb = blkT<T>(L.B, SV<T>::B(L));
     bb.nrows = nrows_p;
     bb.x = x;
     bb.b = b + nu;
     bb.y = r + nu;
-    launch_blk(1, 3, BLK_RESID, L.Gb, bb, h->stream);
+    launch_blk<T>(1, 3, BLK_RESID, L.Gb, bb, h->stream);
     if (L.C.nnz > 0) {
-        BlkArgs cc = blk(L.C);
+        BlkArgsT<T> cc = blkT<T>(L.C, SV<T>::C(L));
         cc.nrows = nrows_p;
         cc.x = x + nu;
         cc.y = r + nu;
-        launch_blk(1, 1, BLK_ADD, L.Gc, cc, h->stream);
+        launch_blk<T>(1, 1, BLK_ADD, L.Gc, cc, h->stream);
     }
 }
 
 static void saddle_residual(amg_ctx *h, int l, const double *b, const double *x, double *r) {
-    saddle_residual_rows(h, l, b, x, r, h->lv[l].n, h->lv[l].n_pres);
+    saddle_residual_rows<double>(h, l, b, x, r, h->lv[l].n, h->lv[l].n_pres);
 }
 
 // y = K_l x
@@ -124,23 +260,24 @@ void saddle_apply(amg_ctx *h, int l, const double *x, double *y) {
 // diag(B M_A^{-1} B^T + C)): du = M_A^{-1} r_u, dp = omega S_d^{-1}(B du - r_p),
 // on the smoothed rows of the level. x_zero: the iterate is zero, so the
 // residual is the right-hand side.
-static void sgs_step(amg_ctx *h, int l, const double *b, double *x, bool x_zero) {
+template <typename T>
+static void sgs_step(amg_ctx *h, int l, const T *b, T *x, bool x_zero) {
     Level &L = h->lv[l];
     const int64_t nu = 3 * static_cast<int64_t>(L.n);
-    const double *r = b;
+    const T *r = b;
     if (!x_zero) {
-        saddle_residual_rows(h, l, b, x, L.r.p, L.nA, L.npA);
-        r = L.r.p;
+        saddle_residual_rows<T>(h, l, b, x, SV<T>::r(L), L.nA, L.npA);
+        r = SV<T>::r(L);
     }
-    launch_sgs_u(L.nA, L.n, L.dinv.p, r, h->prm.sgs_damping, L.t.p, x, h->stream);
-    BlkArgs bb = blk(L.B);
+    launch_sgs_u<T>(L.nA, L.n, SV<T>::dinv(L), r, static_cast<T>(h->prm.sgs_damping), SV<T>::t(L), x, h->stream);
+    BlkArgsT<T> bb = blkT<T>(L.B, SV<T>::B(L));
     bb.nrows = L.npA;
-    bb.x = L.t.p;
+    bb.x = SV<T>::t(L);
     bb.b = r + nu;
     bb.y = x + nu;
-    bb.dscale = L.sgs_scale.p;
-    bb.omega = h->prm.sgs_omega;
-    launch_blk(1, 3, BLK_SGS_P, L.Gb, bb, h->stream);
+    bb.dscale = SV<T>::sgs(L);
+    bb.omega = static_cast<T>(h->prm.sgs_omega);
+    launch_blk<T>(1, 3, BLK_SGS_P, L.Gb, bb, h->stream);
 }
 
 // Scalar V(1,1) cycle on level k of the Schur hierarchy of saddle level l,
@@ -148,37 +285,39 @@ static void sgs_step(amg_ctx *h, int l, const double *b, double *x, bool x_zero)
 // (forward before the coarse correction, backward after it), restriction
 // with H^T and prolongation with H of saddle level l + k; rows that end on
 // this level are solved by their explicit inverses.
-static void schur_vcycle(amg_ctx *h, int l, int k, const double *b, double *x) {
+template <typename T>
+static void schur_vcycle(amg_ctx *h, int l, int k, const T *b, T *x) {
     SchurHier &sh = h->lv[l].schur;
     SchurLevel &q = sh.lv[k];
     hipStream_t s = h->stream;
-    if (q.dseg.count > 0) launch_dense_segs(q.dseg.view(), nullptr, b, nullptr, x, s);
+    if (q.dseg.count > 0)
+        launch_dense_segs<T>(q.dseg.view(), static_cast<const T *>(nullptr), b, static_cast<T *>(nullptr), x, s);
     if (q.nA == 0) return;
     const int nc = static_cast<int>(q.cptr.size()) - 1;
-    launch_fill(x, 0.0, q.nA, s);
+    fillv(x, q.nA, s);
     for (int c = 0; c < nc; ++c)
-        launch_scalar_gs(q.cptr[c + 1] - q.cptr[c], q.S.rowptr.p, q.S.col.p, q.S.val.p, q.rowid.p + q.cptr[c],
-                         q.dinv.p, b, x, q.G, s);
-    BlkArgs ra = blk(q.S);
+        launch_scalar_gs<T>(q.cptr[c + 1] - q.cptr[c], q.S.rowptr.p, q.S.col.p, SV<T>::S(q), q.rowid.p + q.cptr[c],
+                            SV<T>::sdinv(q), b, x, q.G, s);
+    BlkArgsT<T> ra = blkT<T>(q.S, SV<T>::S(q));
     ra.nrows = q.nA;
     ra.x = x;
     ra.b = b;
-    ra.y = q.r.p;
-    launch_blk(1, 1, BLK_RESID, q.G, ra, s);
+    ra.y = SV<T>::sr(q);
+    launch_blk<T>(1, 1, BLK_RESID, q.G, ra, s);
     const Level &V = h->lv[l + k];
     SchurLevel &n = sh.lv[k + 1];
-    BlkArgs ht = blk(V.Ht);
-    ht.x = q.r.p;
-    ht.y = n.b.p;
-    launch_blk(1, 1, BLK_SPMV, V.Ght, ht, s);
-    schur_vcycle(h, l, k + 1, n.b.p, n.x.p);
-    BlkArgs hh = blk(V.H);
-    hh.x = n.x.p;
+    BlkArgsT<T> ht = blkT<T>(V.Ht, SV<T>::Ht(V));
+    ht.x = SV<T>::sr(q);
+    ht.y = SV<T>::sb(n);
+    launch_blk<T>(1, 1, BLK_SPMV, V.Ght, ht, s);
+    schur_vcycle<T>(h, l, k + 1, SV<T>::sb(n), SV<T>::sx(n));
+    BlkArgsT<T> hh = blkT<T>(V.H, SV<T>::H(V));
+    hh.x = SV<T>::sx(n);
     hh.y = x;
-    launch_blk(1, 1, BLK_ADD, V.Gh, hh, s);
+    launch_blk<T>(1, 1, BLK_ADD, V.Gh, hh, s);
     for (int c = nc - 1; c >= 0; --c)
-        launch_scalar_gs(q.cptr[c + 1] - q.cptr[c], q.S.rowptr.p, q.S.col.p, q.S.val.p, q.rowid.p + q.cptr[c],
-                         q.dinv.p, b, x, q.G, s);
+        launch_scalar_gs<T>(q.cptr[c + 1] - q.cptr[c], q.S.rowptr.p, q.S.col.p, SV<T>::S(q), q.rowid.p + q.cptr[c],
+                            SV<T>::sdinv(q), b, x, q.G, s);
 }
 
 // One Braess-Sarazin step (Section 3.3): K_hat = [[A_hat, B^T], [B, B A_hat^{-1} B^T - S_hat]]
@@ -187,100 +326,98 @@ static void schur_vcycle(amg_ctx *h, int l, int k, const double *b, double *x) {
 // S_hat dp = B A_hat^{-1} r_u - r_p, du = A_hat^{-1}(r_u - B^T dp).
 // The cycle is linear and odd, so it is run on -(B A_hat^{-1} r_u - r_p)
 // and returns -dp exactly (negation commutes with every rounding).
-static void bs_step(amg_ctx *h, int l, const double *b, double *x, bool x_zero) {
+template <typename T>
+static void bs_step(amg_ctx *h, int l, const T *b, T *x, bool x_zero) {
     Level &L = h->lv[l];
     hipStream_t s = h->stream;
     const int64_t nu = 3 * static_cast<int64_t>(L.n);
+    T *r = SV<T>::r(L);
     if (x_zero)
-        launch_copy(L.r.p, b, L.vlen(), s);
+        copyv(r, b, L.vlen(), s);
     else
-        saddle_residual_rows(h, l, b, x, L.r.p, L.nA, L.npA);
-    launch_scale(3 * static_cast<int64_t>(L.nA), L.bs_ahat.p, L.r.p, L.t.p, s);
+        saddle_residual_rows<T>(h, l, b, x, r, L.nA, L.npA);
+    launch_scale<T>(3 * static_cast<int64_t>(L.nA), SV<T>::ahat(L), r, SV<T>::t(L), s);
     SchurLevel &q0 = L.schur.lv[0];
-    BlkArgs bb = blk(L.B);
+    BlkArgsT<T> bb = blkT<T>(L.B, SV<T>::B(L));
     bb.nrows = L.npA;
-    bb.x = L.t.p;
-    bb.b = L.r.p + nu;
-    bb.y = q0.b.p;
-    launch_blk(1, 3, BLK_RESID, L.Gb, bb, s);
-    schur_vcycle(h, l, 0, q0.b.p, q0.x.p);
-    launch_axpby(x + nu, q0.x.p, -1.0, 1.0, L.npA, s);
-    BlkArgs bt = blk(L.Bt);
+    bb.x = SV<T>::t(L);
+    bb.b = r + nu;
+    bb.y = SV<T>::sb(q0);
+    launch_blk<T>(1, 3, BLK_RESID, L.Gb, bb, s);
+    schur_vcycle<T>(h, l, 0, SV<T>::sb(q0), SV<T>::sx(q0));
+    axpbyv(x + nu, SV<T>::sx(q0), T(-1), T(1), L.npA, s);
+    BlkArgsT<T> bt = blkT<T>(L.Bt, SV<T>::Bt(L));
     bt.nrows = L.nA;
-    bt.x = q0.x.p;
-    bt.y = L.r.p;
-    launch_blk(3, 1, BLK_ADD, L.Gbt, bt, s);
-    launch_add_scaled(3 * static_cast<int64_t>(L.nA), L.bs_ahat.p, L.r.p, x, s);
+    bt.x = SV<T>::sx(q0);
+    bt.y = r;
+    launch_blk<T>(3, 1, BLK_ADD, L.Gbt, bt, s);
+    launch_add_scaled<T>(3 * static_cast<int64_t>(L.nA), SV<T>::ahat(L), r, x, s);
 }
 
-static void saddle_step(amg_ctx *h, int l, const double *b, double *x, bool x_zero) {
+template <typename T>
+static void saddle_step(amg_ctx *h, int l, const T *b, T *x, bool x_zero) {
     if (h->prm.smoother == AMG_SMOOTH_BS)
-        bs_step(h, l, b, x, x_zero);
+        bs_step<T>(h, l, b, x, x_zero);
     else
-        sgs_step(h, l, b, x, x_zero);
+        sgs_step<T>(h, l, b, x, x_zero);
 }
 
 // Algorithm 1 on saddle level l: systems that end on this level take their
 // explicit inverse; the others are smoothed, restricted with P^T = diag(I, J, H)^T,
 // corrected from level l + 1 and smoothed again.
-static void saddle_cycle(amg_ctx *h, int l, const double *b, double *x, bool x_zero) {
+template <typename T>
+static void saddle_cycle(amg_ctx *h, int l, const T *b, T *x, bool x_zero) {
     Level &L = h->lv[l];
     const int64_t nu = 3 * static_cast<int64_t>(L.n);
     if (L.dseg.count > 0) {
         ProfScope ps(h, "coarse", L.dseg.bytes);
-        launch_dense_segs(L.dseg.view(), b, b + nu, x, x + nu, h->stream);
+        launch_dense_segs<T>(L.dseg.view(), b, b + nu, x, x + nu, h->stream);
     }
     if (L.nA == 0) return;
     const amg_params &p = h->prm;
     if (x_zero) {
-        launch_fill(x, 0.0, 3 * static_cast<int64_t>(L.nA), h->stream);
-        launch_fill(x + nu, 0.0, L.npA, h->stream);
+        fillv(x, 3 * static_cast<int64_t>(L.nA), h->stream);
+        fillv(x + nu, L.npA, h->stream);
     }
-    for (int k = 0; k < p.pre; ++k) saddle_step(h, l, b, x, x_zero && k == 0);
-    saddle_residual_rows(h, l, b, x, L.r.p, L.nA, L.npA);
+    for (int k = 0; k < p.pre; ++k) saddle_step<T>(h, l, b, x, x_zero && k == 0);
+    saddle_residual_rows<T>(h, l, b, x, SV<T>::r(L), L.nA, L.npA);
     Level &C = h->lv[l + 1];
     const int64_t ncu = 3 * static_cast<int64_t>(C.n);
+    restrict_u(h, l, SV<T>::r(L), SV<T>::b(C));
     {
-        RowArgs a;
-        a.nrows = L.R.nrows;
-        a.rowptr = L.R.rowptr.p;
-        a.col = L.R.col.p;
-        a.val = L.R.val.p;
-        a.nnz = L.R.nnz;
-        a.x = L.r.p;
-        a.y = C.b.p;
-        launch_row(1, OP_SPMV, L.Gr, a, h->stream);
-        BlkArgs ht = blk(L.Ht);
-        ht.x = L.r.p + nu;
-        ht.y = C.b.p + ncu;
-        launch_blk(1, 1, BLK_SPMV, L.Ght, ht, h->stream);
+        BlkArgsT<T> ht = blkT<T>(L.Ht, SV<T>::Ht(L));
+        ht.x = SV<T>::r(L) + nu;
+        ht.y = SV<T>::b(C) + ncu;
+        launch_blk<T>(1, 1, BLK_SPMV, L.Ght, ht, h->stream);
     }
     const int nu_rec = C.nA > 0 ? std::max(1, p.nu) : 1;
-    for (int k = 0; k < nu_rec; ++k) saddle_cycle(h, l + 1, C.b.p, C.x.p, k == 0);
+    for (int k = 0; k < nu_rec; ++k) saddle_cycle<T>(h, l + 1, SV<T>::b(C), SV<T>::x(C), k == 0);
+    prolong_u(h, l, SV<T>::x(C), x);
     {
-        RowArgs a;
-        a.nrows = L.P.nrows;
-        a.rowptr = L.P.rowptr.p;
-        a.col = L.P.col.p;
-        a.val = L.P.val.p;
-        a.nnz = L.P.nnz;
-        a.x = C.x.p;
-        a.y = x;
-        launch_row(1, OP_SPMV_ADD, L.Gp, a, h->stream);
-        BlkArgs hh = blk(L.H);
-        hh.x = C.x.p + ncu;
+        BlkArgsT<T> hh = blkT<T>(L.H, SV<T>::H(L));
+        hh.x = SV<T>::x(C) + ncu;
         hh.y = x + nu;
-        launch_blk(1, 1, BLK_ADD, L.Gh, hh, h->stream);
+        launch_blk<T>(1, 1, BLK_ADD, L.Gh, hh, h->stream);
     }
-    for (int k = 0; k < p.post; ++k) saddle_step(h, l, b, x, false);
+    for (int k = 0; k < p.post; ++k) saddle_step<T>(h, l, b, x, false);
 }
 
+// z = M^{-1} r (FP64 vectors). The reduced-precision cycle converts r to
+// FP32 on the finest level and z back to FP64; the outer FGMRES stays FP64.
 void saddle_precondition(amg_ctx *h, const double *r, double *z) {
     const int cyc = std::max(1, h->prm.cycles);
-    for (int k = 0; k < cyc; ++k) saddle_cycle(h, 0, r, z, k == 0);
+    if (h->mixed) {
+        Level &L0 = h->lv[0];
+        const int64_t n = L0.vlen();
+        launch_to_f32(r, L0.mp.b.p, n, h->stream);
+        for (int k = 0; k < cyc; ++k) saddle_cycle<float>(h, 0, L0.mp.b.p, L0.mp.x.p, k == 0);
+        launch_to_f64(L0.mp.x.p, z, n, h->stream);
+        return;
+    }
+    for (int k = 0; k < cyc; ++k) saddle_cycle<double>(h, 0, r, z, k == 0);
 }
 
-void saddle_smooth(amg_ctx *h, int l, const double *b, double *x) { saddle_step(h, l, b, x, false); }
+void saddle_smooth(amg_ctx *h, int l, const double *b, double *x) { saddle_step<double>(h, l, b, x, false); }
 
 static double norm2(amg_ctx *h, const double *v);
 
