@@ -108,6 +108,7 @@ def cpu_baseline(name: str, iters_full: int, tol: float, budget_s: float = 20.0)
         scale_dofs = sum(3 * (2 * m + 1) ** 3 + (m + 1) ** 3 for m, _ in cfg)
     else:
         o, sm = workloads.laplace(4), "GS-1-1"
+    print(f"# cpu baseline: oracle system assembled ({o.A.nrows} nodes)", file=sys.stderr, flush=True)
     if saddle:
         h = oamg.setup(o.A, o.nlin, o.nquad, B=o.B, C=o.C, singular=o.singular)
         if sm.startswith("BS"):
@@ -125,6 +126,7 @@ def cpu_baseline(name: str, iters_full: int, tol: float, budget_s: float = 20.0)
         run = lambda k: krylov.pcg(mv, pc, o.b.ravel(), tol=0.0, maxit=k)
         dofs = 3 * o.A.nrows
         method = "PCG"
+    print(f"# cpu baseline: oracle hierarchy built ({len(h.levels)} levels)", file=sys.stderr, flush=True)
     # a short first run measures the cost of one iteration, then a run sized to the budget
     t0 = time.perf_counter()
     run(1)
