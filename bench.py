@@ -25,6 +25,24 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "elasticity-32_gs-L0_traffic.md")
+
+
+def measured_traffic(workload: str, precision: str, kernel_class: str, lanes: int):
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 --pmc summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), if it
+    covers this kernel and launch shape; else None."""
+    if workload != "elasticity-32" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if not line.startswith("traffic:"):
+                continue
+            kv = dict(t.split("=", 1) for t in line.split()[1:])
+            if (kv.get("class") == kernel_class and kv.get("precision") == precision
+                    and int(kv.get("lanes", -1)) == lanes):
+                return int(kv["bytes_per_launch"])
+    return None
 
 WORKLOADS = {
     "elasticity-32": dict(desc="linear elasticity, pure displacement, unit cube 32^3 cubes x 6 Kuhn tets, "
@@ -249,8 +267,10 @@ def main() -> int:
                 per_launch_bytes = st["bytes"] / st["launches"]
                 per_launch_ms = st["ms"] / st["launches"]
                 achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
+                lanes = levels[0]["lanes"][1] if dom.startswith("gs.") else levels[0]["lanes"][0]
+                traffic = measured_traffic(args.workload, precision, dom, lanes)
                 out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                                   "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                                   "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                                    "kernel": dom, "launches_per_step": st["launches"] // args.steps,
                                    "bytes_per_launch": per_launch_bytes,
                                    "mean_launch_us": round(per_launch_ms * 1e3, 2),

@@ -244,8 +244,23 @@ static void autotune_level(amg_ctx *h, Level &L) {
         }
         return best_ms;
     };
-    float best = 1e30f;
-    for (int G : cand) {
+    // Candidates are timed against the heuristic's choice, which another
+    // candidate replaces only when it is at least 3% faster: timing noise
+    // then does not flip the choice from one setup to the next.
+    auto pick = [&](int G0, auto &&time_of) {
+        int bestG = G0;
+        float best = time_of(G0);
+        for (int G : cand) {
+            if (G == G0) continue;
+            const float ms = time_of(G);
+            if (ms < 0.97f * best) {
+                best = ms;
+                bestG = G;
+            }
+        }
+        return std::make_pair(bestG, best);
+    };
+    L.G = pick(L.G, [&](int G) {
         RowArgs a;
         a.nrows = L.n;
         a.rowptr = L.A.rowptr.p;
@@ -255,19 +270,13 @@ static void autotune_level(amg_ctx *h, Level &L) {
         a.x = L.x.p;
         a.b = L.b.p;
         a.y = L.r.p;
-        const float ms = time_it([&] { launch_row(L.mode, OP_RESID, G, a, s); });
-        if (ms < best) {
-            best = ms;
-            L.G = G;
-        }
-    }
+        return time_it([&] { launch_row(L.mode, OP_RESID, G, a, s); });
+    }).first;
     if (!L.cptr.empty()) {
         // a whole forward sweep, colour by colour, as the smoother runs it,
         // with round-robin or per-XCD contiguous workgroup placement
-        best = 1e30f;
-        for (int xcd = 0; xcd < 2; ++xcd)
-        for (int G : cand) {
-            auto sweep = [&] {
+        auto sweep_time = [&](int G, int xcd) {
+            return time_it([&] {
                 for (size_t c = 0; c + 1 < L.cptr.size(); ++c) {
                     if (L.cptr[c + 1] == L.cptr[c]) continue;
                     RowArgs a;
@@ -285,13 +294,15 @@ static void autotune_level(amg_ctx *h, Level &L) {
                     a.xcd_chunks = xcd;
                     launch_row(L.mode, OP_GS, G, a, s);
                 }
-            };
-            const float ms = time_it(sweep);
-            if (ms < best) {
-                best = ms;
-                L.Gg = G;
-                L.gs_xcd = xcd;
-            }
+            });
+        };
+        const auto rr = pick(L.Gg, [&](int G) { return sweep_time(G, 0); });
+        const auto xc = pick(rr.first, [&](int G) { return sweep_time(G, 1); });
+        L.Gg = rr.first;
+        L.gs_xcd = 0;
+        if (xc.second < 0.97f * rr.second) {
+            L.Gg = xc.first;
+            L.gs_xcd = 1;
         }
     }
     AMG_HIP(hipEventDestroy(e0));
