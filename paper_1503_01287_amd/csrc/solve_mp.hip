@@ -13,6 +13,89 @@
 
 namespace amgp2 {
 
+// The reduced-precision kernels read half (FP32) or a quarter (BF16) of the
+// bytes per entry, so their best lanes per row can differ from the FP64
+// kernels': time them on their own, starting from the FP64 choice and
+// switching only for a 3% gain.
+static void autotune_mp(amg_ctx *h, Level &L) {
+    hipStream_t s = h->stream;
+    LevelMP &M = L.mp;
+    const int cand[] = {8, 16, 32, 64};
+    const int64_t nv = 3 * static_cast<int64_t>(L.n);
+    launch_fill_f32(M.x.p, 0.f, nv, s);
+    launch_fill_f32(M.b.p, 1.f, nv, s);
+    launch_fill_f32(M.t.p, 0.f, nv, s);
+    hipEvent_t e0, e1;
+    AMG_HIP(hipEventCreate(&e0));
+    AMG_HIP(hipEventCreate(&e1));
+    auto time_it = [&](auto &&launch) {
+        launch();
+        launch();
+        float best_ms = 1e30f;
+        for (int r = 0; r < 7; ++r) {
+            AMG_HIP(hipEventRecord(e0, s));
+            launch();
+            AMG_HIP(hipEventRecord(e1, s));
+            AMG_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            AMG_HIP(hipEventElapsedTime(&ms, e0, e1));
+            best_ms = std::min(best_ms, ms);
+        }
+        return best_ms;
+    };
+    auto pick = [&](int G0, auto &&time_of) {
+        int bestG = G0;
+        float best = time_of(G0);
+        for (int G : cand) {
+            if (G == G0) continue;
+            const float ms = time_of(G);
+            if (ms < 0.97f * best) {
+                best = ms;
+                bestG = G;
+            }
+        }
+        return bestG;
+    };
+    M.G = pick(M.G, [&](int G) {
+        RowArgsMP a;
+        a.nrows = L.n;
+        a.rowptr = L.A.rowptr.p;
+        a.col = L.A.col.p;
+        a.val = M.aval();
+        a.rscale = M.scale.p;
+        a.nnz = L.A.nnz;
+        a.x = M.x.p;
+        a.b = M.b.p;
+        a.y = M.r.p;
+        return time_it([&] { launch_row_mp(L.mode, OP_RESID, G, M.kind, a, s); });
+    });
+    if (!L.cptr.empty())
+        M.Gg = pick(M.Gg, [&](int G) {
+            return time_it([&] {
+                for (size_t c = 0; c + 1 < L.cptr.size(); ++c) {
+                    if (L.cptr[c + 1] == L.cptr[c]) continue;
+                    RowArgsMP a;
+                    a.nrows = L.cptr[c + 1] - L.cptr[c];
+                    a.rowptr = L.Ag.rowptr.p + L.cptr[c];
+                    a.col = L.Ag.col.p;
+                    a.val = M.agval();
+                    a.rscale = M.scale.p;
+                    a.nnz = L.Ag.nnz;
+                    a.rowid = L.g_rowid.p + L.cptr[c];
+                    a.x = M.t.p;
+                    a.b = M.b.p;
+                    a.y = M.t.p;
+                    a.dinv = M.dinv.p;
+                    a.dinv_n = L.n;
+                    a.xcd_chunks = L.gs_xcd;
+                    launch_row_mp(L.mode, OP_GS, G, M.kind, a, s);
+                }
+            });
+        });
+    AMG_HIP(hipEventDestroy(e0));
+    AMG_HIP(hipEventDestroy(e1));
+}
+
 void build_mixed(amg_ctx *h) {
     hipStream_t s = h->stream;
     const int prec = h->prm.precision;
@@ -53,6 +136,9 @@ void build_mixed(amg_ctx *h) {
         launch_to_f32(L.P.val.p, M.pval.p, L.P.nnz, s);
         M.rval.alloc(L.R.nnz);
         launch_to_f32(L.R.val.p, M.rval.p, L.R.nnz, s);
+        M.G = L.G;
+        M.Gg = L.Gg;
+        if (h->prm.autotune) autotune_mp(h, L);
     }
     refresh_tail_f32(h);
 }
@@ -124,7 +210,7 @@ static void residual_mp(amg_ctx *h, int l, const float *b, const float *x, float
     a.b = b;
     a.y = r;
     ProfScope ps(h, tag("resid", l), mat_bytes(L, L.A.nnz, L.n) + 3.0 * L.n * 12.0);
-    launch_row_mp(L.mode, OP_RESID, L.G, L.mp.kind, a, h->stream);
+    launch_row_mp(L.mode, OP_RESID, L.mp.G, L.mp.kind, a, h->stream);
 }
 
 static void jacobi_mp(amg_ctx *h, int l, const float *b, float *x, bool zero) {
@@ -146,7 +232,7 @@ static void jacobi_mp(amg_ctx *h, int l, const float *b, float *x, bool zero) {
     a.omega = om;
     {
         ProfScope ps(h, tag("jacobi", l), mat_bytes(L, L.A.nnz, L.n) + 3.0 * L.n * 12.0 + nb * 4.0 * L.n);
-        launch_row_mp(L.mode, OP_JACOBI, L.G, L.mp.kind, a, h->stream);
+        launch_row_mp(L.mode, OP_JACOBI, L.mp.G, L.mp.kind, a, h->stream);
     }
     launch_copy_f32(x, L.mp.t.p, 3 * static_cast<int64_t>(L.n), h->stream);
 }
@@ -179,7 +265,7 @@ static void gs_mp(amg_ctx *h, int l, const float *b, float *x, bool forward, boo
         a.dinv_n = L.n;
         a.xcd_chunks = L.gs_xcd;
         ProfScope ps(h, tag("gs", l), mat_bytes(L, L.colour_nnz[c], a.nrows) + a.nrows * (4.0 + 12.0 + 24.0 + nb * 4.0));
-        launch_row_mp(L.mode, OP_GS, L.Gg, L.mp.kind, a, h->stream);
+        launch_row_mp(L.mode, OP_GS, L.mp.Gg, L.mp.kind, a, h->stream);
     }
 }
 

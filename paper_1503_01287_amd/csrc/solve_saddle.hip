@@ -140,7 +140,7 @@ static void a_resid(amg_ctx *h, int l, const float *b, const float *x, float *r,
     a.b = b;
     a.y = r;
     ProfScope ps(h, tag("resid", l), static_cast<double>(L.A.nnz) * (9.0 * L.mp.vbytes() + 4.0) + L.n * 40.0);
-    launch_row_mp(3, OP_RESID, L.G, L.mp.kind, a, h->stream);
+    launch_row_mp(3, OP_RESID, L.mp.G, L.mp.kind, a, h->stream);
 }
 // velocity restriction (R = P^T, scalar per component) into the next level
 static void restrict_u(amg_ctx *h, int l, const double *r, double *bc) {
