@@ -27,8 +27,8 @@ to a cited work that it does not reproduce):
 
 Section 3.1 (Algorithm 1, the basic AMG iteration) is ``cycle``; Section 3.3's
 smoothers are ``jacobi``, ``gauss_seidel`` (block, lexicographic or by
-colours), ``sgs_step`` (segregated Gauss-Seidel / Uzawa) and ``bs_step``
-(Braess-Sarazin). Parity unpinned: the exact iteration counts of the paper's
+colours), ``sgs_step`` (segregated Gauss-Seidel / Uzawa), ``bs_step``
+(Braess-Sarazin) and ``vanka_step`` (multiplicative Vanka). Parity unpinned: the exact iteration counts of the paper's
 tables (they depend on unstated details); the Braess-Sarazin inner Schur
 cycle and the sGS pressure scaling follow the readings in their docstrings.
 """
@@ -139,6 +139,7 @@ class Level:
     order_bwd: np.ndarray | None = None
     schur: "Hierarchy | None" = None     # Braess-Sarazin: scalar AMG on C + B (2D)^-1 B^T
     sgs_diag: np.ndarray | None = None   # sGS pressure scaling diag(B M_A^-1 B^T + C)
+    vanka: "VankaPatches | None" = None  # multiplicative Vanka patches and their order
 
     @property
     def n(self) -> int:
@@ -263,12 +264,14 @@ class Smoother:
     @staticmethod
     def parse(name: str) -> "Smoother":
         parts = name.split("-")
-        kind = {"JA": "JA", "GS": "GS", "sGS": "SGS", "BS": "BS", "Braess": "BS"}[parts[0]]
+        kind = {"JA": "JA", "GS": "GS", "sGS": "SGS", "BS": "BS", "Braess": "BS", "Vanka": "VANKA"}[parts[0]]
         if parts[0] == "Braess":
             parts = ["BS"] + parts[2:]
         s = Smoother(kind, int(parts[1]), int(parts[2]))
-        if kind == "JA" and len(parts) > 3:
+        if kind in ("JA", "VANKA") and len(parts) > 3:
             s.omega = float(parts[3])
+        elif kind == "VANKA":
+            s.omega = VANKA_OMEGA
         return s
 
     def level_omega(self, l: int) -> float:
@@ -345,6 +348,68 @@ def bs_step(lev: Level, sm: Smoother, f, g, u, p):
     dp = scalar_vcycle(lev.schur, 0, rs, np.zeros_like(rs))
     du = ahat_inv * (ru - lev.B.transpose().matvec(dp.reshape(-1, 1)))
     return u + du, p + dp
+
+
+# --------------------------------------------------------------------------
+# multiplicative Vanka (Section 3.3)
+# --------------------------------------------------------------------------
+VANKA_OMEGA = 0.8   # damping of the local corrections (the paper gives no value; reading R15)
+
+
+@dataclass
+class VankaPatches:
+    nodes: list            # velocity nodes of patch i (sorted)
+    dofs: list             # saddle-vector indices: 3 * node + c for every node, then the pressure
+    order: np.ndarray      # processing order: by colour, then index
+    colors: np.ndarray
+    K: sp.csr_matrix       # the level's saddle matrix [[A, B^T], [B, -C]]
+
+
+def saddle_matrix(lev: Level) -> sp.csr_matrix:
+    Bs = lev.B.scipy()
+    C = lev.C.scipy() if lev.C is not None else sp.csr_matrix((lev.npres, lev.npres))
+    return sp.bmat([[lev.A.scipy(), Bs.T], [Bs, -C]], format="csr")
+
+
+def vanka_patches(lev: Level) -> VankaPatches:
+    """Patch i holds pressure DOF i and every velocity DOF of the nodes coupled
+    to it through B (the structural pattern of B_ll and B_lq). Two patches may
+    be processed at the same time when they share no velocity node, A couples
+    none of their nodes and C does not couple their pressures: then the
+    multiplicative sweep in (colour, index) order equals the sequential sweep
+    in that order. Colours: greedy first-fit in index order on that conflict
+    graph (reading R19)."""
+    npres, n = lev.npres, lev.n
+    nodes = [lev.B.indices[lev.B.indptr[i]:lev.B.indptr[i + 1]].copy() for i in range(npres)]
+    N = sp.csr_matrix((np.ones(lev.B.nnz), lev.B.indices, lev.B.indptr), shape=(npres, n))
+    conf = (N @ lev.A.pattern() @ N.T).tocsr()
+    if lev.C is not None:
+        conf = (conf + lev.C.pattern()).tocsr()
+    conf.sort_indices()
+    colors = cloops.greedy_colour(conf.indptr, conf.indices)
+    order = np.lexsort((np.arange(npres), colors))
+    nv = 3 * n
+    dofs = [np.concatenate([(3 * nd[:, None] + np.arange(3)[None, :]).ravel(), [nv + i]]) for i, nd in enumerate(nodes)]
+    return VankaPatches(nodes, dofs, order, colors, saddle_matrix(lev))
+
+
+def vanka_step(lev: Level, sm: Smoother, f, g, u, p):
+    """One multiplicative Vanka sweep: for every patch in order, the local
+    system (the saddle matrix restricted to the patch) is solved for the
+    current residual on the patch, and omega times the correction is added."""
+    if lev.vanka is None:
+        lev.vanka = vanka_patches(lev)
+    V = lev.vanka
+    x = np.concatenate([np.asarray(u, dtype=np.float64).ravel(), np.asarray(p, dtype=np.float64)])
+    b = np.concatenate([np.asarray(f, dtype=np.float64).ravel(), np.asarray(g, dtype=np.float64)])
+    K = V.K
+    for i in V.order:
+        idx = V.dofs[i]
+        r = b[idx] - K[idx] @ x
+        Ki = K[idx][:, idx].toarray()
+        x[idx] += sm.omega * np.linalg.solve(Ki, r)
+    nv = 3 * lev.n
+    return x[:nv].reshape(-1, 3), x[nv:]
 
 
 # --------------------------------------------------------------------------
@@ -444,9 +509,9 @@ def cycle(h: Hierarchy, l: int, sm: Smoother, b: np.ndarray, x: np.ndarray, nu: 
 
 
 def saddle_cycle(h: Hierarchy, l: int, sm: Smoother, f, g, u, p, nu: int = 1):
-    """Algorithm 1 for the saddle hierarchy with the sGS or BS smoother."""
+    """Algorithm 1 for the saddle hierarchy with the sGS, BS or Vanka smoother."""
     lev = h.levels[l]
-    step = sgs_step if sm.kind == "SGS" else bs_step
+    step = {"SGS": sgs_step, "BS": bs_step, "VANKA": vanka_step}[sm.kind]
     for _ in range(sm.pre):
         u, p = step(lev, sm, f, g, u, p)
     ru, rp = saddle_residual(lev, f, g, u, p)
