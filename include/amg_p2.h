@@ -63,6 +63,11 @@ typedef void *amg_stream; /* hipStream_t */
 #define AMG_SMOOTH_GS 1  /* block Gauss-Seidel by colours ("GS-m-m")        */
 #define AMG_SMOOTH_SGS 2 /* segregated Gauss-Seidel / Uzawa ("sGS-m-m")     */
 #define AMG_SMOOTH_BS 3  /* Braess-Sarazin ("Braess-Sarazin-m-m")           */
+#define AMG_SMOOTH_VANKA 4 /* multiplicative Vanka ("Vanka-m-m"), FP64, not
+                              in batches: one patch per pressure DOF with the
+                              velocity nodes of its row of B; local saddle
+                              matrices inverted at setup; patches processed
+                              colour by colour                                */
 
 /* ---- outer iterations ------------------------------------------------ */
 #define AMG_KRYLOV_PCG 0    /* preconditioned CG, FP64 (SPD)                 */
@@ -157,6 +162,7 @@ typedef struct {
                              recorded once into a HIP graph and replayed
                              (same kernels, same order, same results); 0:
                              launched one by one. Profiling runs unrecorded. */
+    double vanka_omega;   /* Vanka damping of the local corrections (0.8)  */
 } amg_params;
 
 typedef struct {

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libamgp2.so")
 # status codes and options (mirrors amg_p2.h)
 AMG_OK, AMG_NOT_CONVERGED, AMG_BREAKDOWN, AMG_DIVERGED = 0, 1, 2, 3
 AMG_EINVAL, AMG_EHIP, AMG_ENOMEM, AMG_EUNSUPPORTED = -1, -2, -3, -4
-SMOOTH = {"JA": 0, "GS": 1, "SGS": 2, "BS": 3}
+SMOOTH = {"JA": 0, "GS": 1, "SGS": 2, "BS": 3, "VANKA": 4}
 KRYLOV = {"PCG": 0, "FCG": 1, "FGMRES": 2, "NONE": 3}
 PREC = {"FP64": 0, "MIXED": 1, "FP32": 2}
 
@@ -47,7 +47,7 @@ class AmgParams(ctypes.Structure):
         ("restart", ctypes.c_int32), ("precision", ctypes.c_int32),
         ("n_level_omega", ctypes.c_int32), ("level_omega", _f64p),
         ("fuse_coarse", ctypes.c_int32), ("autotune", ctypes.c_int32),
-        ("omega_model", ctypes.c_void_p), ("graph", ctypes.c_int32),
+        ("omega_model", ctypes.c_void_p), ("graph", ctypes.c_int32), ("vanka_omega", ctypes.c_double),
     ]
 
 

@@ -64,6 +64,7 @@ void amg_default_params(amg_params *p) {
     p->autotune = 1;
     p->omega_model = nullptr;
     p->graph = 1;
+    p->vanka_omega = 0.8;
 }
 
 int amg_setup(const amg_system *sys, const amg_params *params, amg_stream stream, amg_handle *out) {
@@ -74,8 +75,11 @@ int amg_setup(const amg_system *sys, const amg_params *params, amg_stream stream
         const amg_params &p = *params;
         AMG_REQUIRE(sys != nullptr, AMG_EINVAL, "amg_setup: null system");
         if (sys->n_pres > 0) {
-            AMG_REQUIRE(p.smoother == AMG_SMOOTH_SGS || p.smoother == AMG_SMOOTH_BS, AMG_EINVAL,
-                        "amg_setup: saddle point systems need the sGS or Braess-Sarazin smoother");
+            AMG_REQUIRE(p.smoother == AMG_SMOOTH_SGS || p.smoother == AMG_SMOOTH_BS ||
+                            p.smoother == AMG_SMOOTH_VANKA,
+                        AMG_EINVAL, "amg_setup: saddle point systems need the sGS, Braess-Sarazin or Vanka smoother");
+            AMG_REQUIRE(p.smoother != AMG_SMOOTH_VANKA || p.precision == AMG_PREC_FP64, AMG_EUNSUPPORTED,
+                        "amg_setup: the Vanka smoother runs in FP64");
             AMG_REQUIRE(p.krylov == AMG_KRYLOV_FGMRES || p.krylov == AMG_KRYLOV_NONE, AMG_EINVAL,
                         "amg_setup: saddle point systems need FGMRES or the stand-alone iteration");
             AMG_REQUIRE(p.precision == AMG_PREC_FP64 || p.krylov == AMG_KRYLOV_FGMRES, AMG_EINVAL,
@@ -132,6 +136,8 @@ int amg_setup_batched(int32_t nsys, const amg_system *systems, const amg_params 
         const amg_params &p = *params;
         check_params(p, true);
         AMG_REQUIRE(p.krylov == AMG_KRYLOV_FGMRES, AMG_EINVAL, "amg_setup_batched: batches run FGMRES");
+        AMG_REQUIRE(p.smoother != AMG_SMOOTH_VANKA, AMG_EUNSUPPORTED,
+                    "amg_setup_batched: batches run the sGS or Braess-Sarazin smoother");
         AMG_REQUIRE(!p.omega_model, AMG_EINVAL, "amg_setup_batched: omega_model is for JA on SPD systems");
         auto *h = new amg_ctx();
         h->prm = p;

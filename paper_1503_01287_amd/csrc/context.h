@@ -13,6 +13,7 @@
 #include "mixed.h"
 #include "saddle.h"
 #include "tail.h"
+#include "vanka.h"
 
 namespace amgp2 {
 
@@ -98,6 +99,17 @@ struct SchurHier {
     int m = 0;
 };
 
+// Multiplicative Vanka data of a saddle level: patch node lists, the patches
+// ordered by colour (rows order[cptr[c] .. cptr[c+1]) of colour c) and the
+// patches' inverted local matrices.
+struct VankaData {
+    int npatch = 0, max_nodes = 0;
+    DevBuf<int> pptr, pnode, order;
+    DevBuf<int64_t> moff;
+    DevBuf<double> inv;
+    std::vector<int> cptr;
+};
+
 struct Level {
     int n_lin = 0, n_quad = 0, n = 0, n_pres = 0;
     int mode = 3;             // 3: 3x3 blocks; 1: scalar operator applied per component
@@ -131,6 +143,7 @@ struct Level {
     int nA = 0, npA = 0;
     DenseSegs dseg;
     SchurHier schur;          // BS: scalar hierarchy of this level's Schur complement
+    VankaData vanka;          // multiplicative Vanka patches
     int Gb = 16, Gbt = 16, Gc = 8, Gh = 4, Ght = 8;
     int64_t vlen() const { return 3 * static_cast<int64_t>(n) + n_pres; }
 };
@@ -243,6 +256,8 @@ void precondition_mp(amg_ctx *h, const double *r, double *z);
 // saddle point path
 void saddle_setup_level(amg_ctx *h, Level &L);
 void setup_schur(amg_ctx *h, int l);
+void setup_vanka(amg_ctx *h, int l);
+VankaView vanka_view(Level &L);
 // JA damping per level from the network of prm.omega_model (fallback: prm.omega)
 void predict_level_omega(amg_ctx *h);
 double jacobi_omega(const amg_ctx *h, int l);

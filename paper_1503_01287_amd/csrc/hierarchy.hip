@@ -584,6 +584,116 @@ void setup_schur(amg_ctx *h, int l) {
     AMG_HIP(hipStreamSynchronize(s));
 }
 
+VankaView vanka_view(Level &L) {
+    VankaView v;
+    v.npatch = L.vanka.npatch;
+    v.pptr = L.vanka.pptr.p;
+    v.pnode = L.vanka.pnode.p;
+    v.moff = L.vanka.moff.p;
+    v.inv = L.vanka.inv.p;
+    v.n = L.n;
+    v.arow = L.A.rowptr.p;
+    v.acol = L.A.col.p;
+    v.aval = L.A.val.p;
+    v.annz = L.A.nnz;
+    v.brow = L.B.rowptr.p;
+    v.bcol = L.B.col.p;
+    v.bval = L.B.val.p;
+    v.bnnz = L.B.nnz;
+    v.btrow = L.Bt.rowptr.p;
+    v.btcol = L.Bt.col.p;
+    v.btval = L.Bt.val.p;
+    v.btnnz = L.Bt.nnz;
+    if (L.C.nnz > 0) {
+        v.crow = L.C.rowptr.p;
+        v.ccol = L.C.col.p;
+        v.cval = L.C.val.p;
+    }
+    return v;
+}
+
+// Multiplicative Vanka on saddle level l (Section 3.3): patch i = pressure
+// DOF i and the velocity nodes of B's row i (structural pattern, sorted).
+// Patches i and j conflict when A couples a node of one to a node of the
+// other (A's pattern holds the diagonal, so shared nodes count) or when C
+// couples their pressures; greedy first-fit colouring in index order of the
+// conflict graph gives the processing order (colour, then index). The local
+// matrices are assembled and inverted on the GPU.
+void setup_vanka(amg_ctx *h, int l) {
+    hipStream_t s = h->stream;
+    Level &L = h->lv[l];
+    VankaData &V = L.vanka;
+    HostCSR bp = download_pattern(L.B, s);
+    const int np = L.n_pres;
+    V.npatch = np;
+    V.max_nodes = 0;
+    for (int i = 0; i < np; ++i) {
+        std::sort(bp.col.begin() + bp.rowptr[i], bp.col.begin() + bp.rowptr[i + 1]);
+        V.max_nodes = std::max(V.max_nodes, bp.rowptr[i + 1] - bp.rowptr[i]);
+    }
+    const HostCSR node_patch = transpose(bp);  // patches containing each node
+    HostCSR cp;
+    if (L.C.nnz > 0) cp = download_pattern(L.C, s);
+    HostCSR conf;
+    conf.nrows = conf.ncols = np;
+    conf.rowptr.assign(np + 1, 0);
+    std::vector<int> mark_node(L.n, -1), mark_patch(np, -1);
+    for (int i = 0; i < np; ++i) {
+        for (int k = bp.rowptr[i]; k < bp.rowptr[i + 1]; ++k) {
+            const int u = bp.col[k];
+            for (int q = L.hpat.rowptr[u]; q < L.hpat.rowptr[u + 1]; ++q) {
+                const int w = L.hpat.col[q];
+                if (mark_node[w] == i) continue;
+                mark_node[w] = i;
+                for (int t = node_patch.rowptr[w]; t < node_patch.rowptr[w + 1]; ++t) {
+                    const int j = node_patch.col[t];
+                    if (mark_patch[j] != i) {
+                        mark_patch[j] = i;
+                        conf.col.push_back(j);
+                    }
+                }
+            }
+        }
+        if (L.C.nnz > 0)
+            for (int k = cp.rowptr[i]; k < cp.rowptr[i + 1]; ++k) {
+                const int j = cp.col[k];
+                if (mark_patch[j] != i) {
+                    mark_patch[j] = i;
+                    conf.col.push_back(j);
+                }
+            }
+        conf.rowptr[i + 1] = static_cast<int>(conf.col.size());
+    }
+    std::vector<int> colour;
+    const int nc = greedy_colouring(conf, colour);
+    V.cptr.assign(nc + 1, 0);
+    for (int i = 0; i < np; ++i) ++V.cptr[colour[i] + 1];
+    std::partial_sum(V.cptr.begin(), V.cptr.end(), V.cptr.begin());
+    std::vector<int> order(std::max(1, np)), next(V.cptr.begin(), V.cptr.end() - 1);
+    for (int i = 0; i < np; ++i) order[next[colour[i]]++] = i;
+    std::vector<int64_t> moff(std::max(1, np), 0);
+    int64_t total = 0;
+    for (int i = 0; i < np; ++i) {
+        moff[i] = total;
+        const int64_t m = 3 * static_cast<int64_t>(bp.rowptr[i + 1] - bp.rowptr[i]) + 1;
+        total += m * m;
+    }
+    AMG_REQUIRE(total * 8 <= (int64_t(96) << 30), AMG_ENOMEM,
+                "amg_setup: the Vanka patch inverses would exceed 96 GiB");
+    V.pptr.upload(bp.rowptr, s);
+    V.pnode.upload(bp.col, s);
+    V.order.upload(order, s);
+    V.moff.upload(moff, s);
+    V.inv.alloc(static_cast<size_t>(std::max<int64_t>(1, total)));
+    const VankaView view = vanka_view(L);
+    launch_vanka_assemble(view, V.max_nodes, s);
+    DevBuf<int> flag(1);
+    flag.zero(s);
+    launch_vanka_invert(view, 3 * V.max_nodes + 1, flag.p, s);
+    AMG_REQUIRE(flag.download(s)[0] == 0, AMG_EINVAL, "amg_setup: singular Vanka patch matrix");
+    AMG_HIP(hipStreamSynchronize(s));
+}
+
 double jacobi_omega(const amg_ctx *h, int l) {
     if (h->level_omega.empty()) return h->prm.omega;
     return h->level_omega[std::min<size_t>(l, h->level_omega.size() - 1)];
@@ -722,6 +832,8 @@ void build_hierarchy(amg_ctx *h, const amg_system *sys) {
     setup_coarsest(h, h->lv.back());
     if (h->saddle && p.smoother == AMG_SMOOTH_BS)
         for (int l = 0; l + 1 < static_cast<int>(h->lv.size()); ++l) setup_schur(h, l);
+    if (h->saddle && p.smoother == AMG_SMOOTH_VANKA)
+        for (int l = 0; l + 1 < static_cast<int>(h->lv.size()); ++l) setup_vanka(h, l);
     if (!h->saddle) {
         setup_tail(h);
         build_mixed(h);

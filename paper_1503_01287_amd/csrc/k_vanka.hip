@@ -1,0 +1,223 @@
+// Multiplicative Vanka kernels (see vanka.h): local-matrix assembly, batched
+// Gauss-Jordan inversion and the coloured patch update. One workgroup per
+// patch; local DOF a < 3 n_P is component a % 3 of node a / 3 of the patch,
+// a = 3 n_P is the patch's pressure.
+#include "common.h"
+#include "vanka.h"
+
+namespace amgp2 {
+
+constexpr int VB = 256;
+
+// position of column c in the sorted row [b, e) of idx, or -1
+__device__ __forceinline__ int find_col(const int *idx, int b, int e, int c) {
+    int lo = b, hi = e - 1;
+    while (lo <= hi) {
+        const int mid = (lo + hi) >> 1;
+        const int v = idx[mid];
+        if (v == c) return mid;
+        if (v < c) lo = mid + 1;
+        else hi = mid - 1;
+    }
+    return -1;
+}
+
+__global__ void __launch_bounds__(VB) k_vanka_assemble(const VankaView v) {
+    extern __shared__ int nodes[];
+    const int i = blockIdx.x;
+    const int p0 = v.pptr[i], nn = v.pptr[i + 1] - p0;
+    for (int k = threadIdx.x; k < nn; k += VB) nodes[k] = v.pnode[p0 + k];
+    __syncthreads();
+    const int m = 3 * nn + 1;
+    double *M = v.inv + v.moff[i];
+    for (int64_t e = threadIdx.x; e < static_cast<int64_t>(m) * m; e += VB) {
+        const int a = static_cast<int>(e % m), bcol = static_cast<int>(e / m);  // column-major
+        double val = 0.0;
+        const bool ap = a == 3 * nn, bp = bcol == 3 * nn;
+        if (!ap && !bp) {
+            const int ua = nodes[a / 3], ub = nodes[bcol / 3];
+            const int q = find_col(v.acol, v.arow[ua], v.arow[ua + 1], ub);
+            if (q >= 0) val = v.aval[static_cast<int64_t>((a % 3) * 3 + bcol % 3) * v.annz + q];
+        } else if (!ap && bp) {  // B^T(u_a, i)[c_a]
+            const int ua = nodes[a / 3];
+            const int q = find_col(v.btcol, v.btrow[ua], v.btrow[ua + 1], i);
+            if (q >= 0) val = v.btval[static_cast<int64_t>(a % 3) * v.btnnz + q];
+        } else if (ap && !bp) {  // B(i, u_b)[c_b] = B^T(u_b, i)[c_b]
+            const int ub = nodes[bcol / 3];
+            const int q = find_col(v.btcol, v.btrow[ub], v.btrow[ub + 1], i);
+            if (q >= 0) val = v.btval[static_cast<int64_t>(bcol % 3) * v.btnnz + q];
+        } else if (v.crow) {     // -C(i, i)
+            const int q = find_col(v.ccol, v.crow[i], v.crow[i + 1], i);
+            if (q >= 0) val = -v.cval[q];
+        }
+        M[e] = val;
+    }
+}
+
+void launch_vanka_assemble(const VankaView &v, int max_nodes, hipStream_t s) {
+    if (v.npatch <= 0) return;
+    k_vanka_assemble<<<v.npatch, VB, max_nodes * sizeof(int), s>>>(v);
+    AMG_CHECK_LAUNCH();
+}
+
+// In-place Gauss-Jordan inversion with partial (row) pivoting of one
+// column-major m x m matrix per workgroup; row swaps are undone as column
+// swaps at the end.
+__global__ void __launch_bounds__(VB) k_vanka_invert(const VankaView v, int *flag) {
+    extern __shared__ unsigned char smem[];
+    __shared__ double rv[VB];
+    __shared__ int ri[VB];
+    const int i = blockIdx.x;
+    const int m = 3 * (v.pptr[i + 1] - v.pptr[i]) + 1;
+    double *f = reinterpret_cast<double *>(smem);
+    int *perm = reinterpret_cast<int *>(f + m);
+    double *M = v.inv + v.moff[i];
+    auto E = [&](int r, int c) -> double & { return M[static_cast<int64_t>(c) * m + r]; };
+    for (int k = 0; k < m; ++k) {
+        double best = -1.0;
+        int bi = k;
+        for (int r = k + threadIdx.x; r < m; r += VB) {
+            const double a = fabs(E(r, k));
+            if (a > best) {
+                best = a;
+                bi = r;
+            }
+        }
+        rv[threadIdx.x] = best;
+        ri[threadIdx.x] = bi;
+        __syncthreads();
+        for (int o = VB / 2; o > 0; o >>= 1) {
+            if (threadIdx.x < o) {
+                const double b2 = rv[threadIdx.x + o];
+                const int i2 = ri[threadIdx.x + o];
+                if (b2 > rv[threadIdx.x] || (b2 == rv[threadIdx.x] && i2 < ri[threadIdx.x])) {
+                    rv[threadIdx.x] = b2;
+                    ri[threadIdx.x] = i2;
+                }
+            }
+            __syncthreads();
+        }
+        const int piv = ri[0];
+        const bool zero = rv[0] == 0.0;
+        __syncthreads();
+        if (zero) {
+            if (threadIdx.x == 0) atomicOr(flag, 1);
+            return;  // uniform across the workgroup
+        }
+        if (threadIdx.x == 0) perm[k] = piv;
+        if (piv != k)
+            for (int c = threadIdx.x; c < m; c += VB) {
+                const double t = E(k, c);
+                E(k, c) = E(piv, c);
+                E(piv, c) = t;
+            }
+        __syncthreads();
+        const double p = E(k, k);
+        for (int r = threadIdx.x; r < m; r += VB) f[r] = E(r, k);
+        __syncthreads();
+        for (int r = threadIdx.x; r < m; r += VB) E(r, k) = r == k ? 1.0 : 0.0;
+        __syncthreads();
+        for (int c = threadIdx.x; c < m; c += VB) E(k, c) /= p;
+        __syncthreads();
+        for (int64_t e = threadIdx.x; e < static_cast<int64_t>(m) * m; e += VB) {
+            const int r = static_cast<int>(e % m), c = static_cast<int>(e / m);
+            if (r != k) E(r, c) -= f[r] * E(k, c);
+        }
+        __syncthreads();
+    }
+    for (int k = m - 1; k >= 0; --k) {
+        const int q = perm[k];
+        if (q != k)
+            for (int r = threadIdx.x; r < m; r += VB) {
+                const double t = E(r, k);
+                E(r, k) = E(r, q);
+                E(r, q) = t;
+            }
+        __syncthreads();
+    }
+}
+
+void launch_vanka_invert(const VankaView &v, int max_m, int *flag, hipStream_t s) {
+    if (v.npatch <= 0) return;
+    k_vanka_invert<<<v.npatch, VB, static_cast<size_t>(max_m) * (sizeof(double) + sizeof(int)), s>>>(v, flag);
+    AMG_CHECK_LAUNCH();
+}
+
+// One colour of the multiplicative sweep: residual on the patch (wavefront
+// per node, lanes over the node's A and B^T rows), correction with the
+// patch's inverse, update in place.
+__global__ void __launch_bounds__(VB) k_vanka_colour(const VankaView v, const int *order, const double *b,
+                                                     double *x, double omega) {
+    extern __shared__ unsigned char smem[];
+    const int i = order[blockIdx.x];
+    const int p0 = v.pptr[i], nn = v.pptr[i + 1] - p0;
+    const int m = 3 * nn + 1;
+    double *r = reinterpret_cast<double *>(smem);
+    int *nodes = reinterpret_cast<int *>(r + m);
+    for (int k = threadIdx.x; k < nn; k += VB) nodes[k] = v.pnode[p0 + k];
+    __syncthreads();
+    const int64_t nu = 3 * static_cast<int64_t>(v.n);
+    const double *p = x + nu;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int k = wave; k <= nn; k += VB / 64) {
+        if (k < nn) {
+            const int u = nodes[k];
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+            for (int q = v.arow[u] + lane; q < v.arow[u + 1]; q += 64) {
+                const int j = v.acol[q];
+                const double x0 = x[3 * j], x1 = x[3 * j + 1], x2 = x[3 * j + 2];
+                s0 += v.aval[0 * v.annz + q] * x0 + v.aval[1 * v.annz + q] * x1 + v.aval[2 * v.annz + q] * x2;
+                s1 += v.aval[3 * v.annz + q] * x0 + v.aval[4 * v.annz + q] * x1 + v.aval[5 * v.annz + q] * x2;
+                s2 += v.aval[6 * v.annz + q] * x0 + v.aval[7 * v.annz + q] * x1 + v.aval[8 * v.annz + q] * x2;
+            }
+            for (int q = v.btrow[u] + lane; q < v.btrow[u + 1]; q += 64) {
+                const double pq = p[v.btcol[q]];
+                s0 += v.btval[q] * pq;
+                s1 += v.btval[v.btnnz + q] * pq;
+                s2 += v.btval[2 * v.btnnz + q] * pq;
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                s0 += __shfl_xor(s0, o, 64);
+                s1 += __shfl_xor(s1, o, 64);
+                s2 += __shfl_xor(s2, o, 64);
+            }
+            if (lane == 0) {
+                r[3 * k] = b[3 * u] - s0;
+                r[3 * k + 1] = b[3 * u + 1] - s1;
+                r[3 * k + 2] = b[3 * u + 2] - s2;
+            }
+        } else {
+            // pressure row: g_i - B_i u + C_i p
+            double s = 0.0;
+            for (int q = v.brow[i] + lane; q < v.brow[i + 1]; q += 64) {
+                const int j = v.bcol[q];
+                s += v.bval[q] * x[3 * j] + v.bval[v.bnnz + q] * x[3 * j + 1] + v.bval[2 * v.bnnz + q] * x[3 * j + 2];
+            }
+            if (v.crow)
+                for (int q = v.crow[i] + lane; q < v.crow[i + 1]; q += 64) s -= v.cval[q] * p[v.ccol[q]];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+            if (lane == 0) r[3 * nn] = b[nu + i] - s;
+        }
+    }
+    __syncthreads();
+    const double *M = v.inv + v.moff[i];
+    for (int a = threadIdx.x; a < m; a += VB) {
+        double d = 0.0;
+        for (int c = 0; c < m; ++c) d += M[static_cast<int64_t>(c) * m + a] * r[c];
+        d *= omega;
+        if (a < 3 * nn) x[3 * static_cast<int64_t>(nodes[a / 3]) + a % 3] += d;
+        else x[nu + i] += d;
+    }
+}
+
+void launch_vanka_colour(const VankaView &v, const int *order, int count, int max_nodes, const double *b,
+                         double *x, double omega, hipStream_t s) {
+    if (count <= 0) return;
+    const size_t lds = static_cast<size_t>(3 * max_nodes + 1) * sizeof(double) + max_nodes * sizeof(int);
+    k_vanka_colour<<<count, VB, lds, s>>>(v, order, b, x, omega);
+    AMG_CHECK_LAUNCH();
+}
+
+}  // namespace amgp2

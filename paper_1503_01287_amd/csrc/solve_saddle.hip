@@ -354,10 +354,28 @@ static void bs_step(amg_ctx *h, int l, const T *b, T *x, bool x_zero) {
     launch_add_scaled<T>(3 * static_cast<int64_t>(L.nA), SV<T>::ahat(L), r, x, s);
 }
 
+// One multiplicative Vanka sweep (Section 3.3): the patches colour by
+// colour, each x_P += omega K_P^{-1} (b - K x)_P with the residual of the
+// current iterate (FP64 only).
+static void vanka_step(amg_ctx *h, int l, const double *b, double *x) {
+    Level &L = h->lv[l];
+    const VankaView v = vanka_view(L);
+    const int nc = static_cast<int>(L.vanka.cptr.size()) - 1;
+    ProfScope ps(h, tag("vanka", l), 0.0);
+    for (int c = 0; c < nc; ++c)
+        launch_vanka_colour(v, L.vanka.order.p + L.vanka.cptr[c], L.vanka.cptr[c + 1] - L.vanka.cptr[c],
+                            L.vanka.max_nodes, b, x, h->prm.vanka_omega, h->stream);
+}
+static void vanka_step(amg_ctx *, int, const float *, float *) {
+    throw Error(AMG_EUNSUPPORTED, "the Vanka smoother runs in FP64");
+}
+
 template <typename T>
 static void saddle_step(amg_ctx *h, int l, const T *b, T *x, bool x_zero) {
     if (h->prm.smoother == AMG_SMOOTH_BS)
         bs_step<T>(h, l, b, x, x_zero);
+    else if (h->prm.smoother == AMG_SMOOTH_VANKA)
+        vanka_step(h, l, b, x);
     else
         sgs_step<T>(h, l, b, x, x_zero);
 }

@@ -16,14 +16,17 @@ from .problems import LinearSystem
 
 def parse_smoother(name: str) -> dict:
     """The paper's smoother names: 'JA-1-1-0.5', 'GS-2-2', 'sGS-1-1',
-    'Braess-Sarazin-1-1' (alias 'BS-1-1')."""
+    'Braess-Sarazin-1-1' (alias 'BS-1-1'), 'Vanka-1-1' (optionally with its
+    damping, 'Vanka-1-1-0.8')."""
     parts = name.split("-")
     if parts[0] == "Braess":
         parts = ["BS"] + parts[2:]
-    kind = {"JA": "JA", "GS": "GS", "sGS": "SGS", "SGS": "SGS", "BS": "BS"}[parts[0]]
+    kind = {"JA": "JA", "GS": "GS", "sGS": "SGS", "SGS": "SGS", "BS": "BS", "Vanka": "VANKA"}[parts[0]]
     out = dict(smoother=kind, pre=int(parts[1]), post=int(parts[2]))
     if kind == "JA" and len(parts) > 3:
         out["omega"] = float(parts[3])
+    if kind == "VANKA" and len(parts) > 3:
+        out["vanka_omega"] = float(parts[3])
     return out
 
 
@@ -94,6 +97,8 @@ class AMGSolver:
         p.pre, p.post = sm["pre"], sm["post"]
         p.omega = omega if omega is not None else sm.get("omega", 0.5)
         p.sgs_omega, p.sgs_damping = sgs_omega, sgs_damping
+        if "vanka_omega" in sm:
+            p.vanka_omega = sm["vanka_omega"]
         p.cycles, p.nu = cycles, nu
         p.coarse_max, p.max_levels = coarse_max, max_levels
         p.separate = 1 if separate else 0
