@@ -108,6 +108,13 @@ struct VankaData {
     DevBuf<int64_t> moff;
     DevBuf<double> inv;
     std::vector<int> cptr;
+    // two-kernel path for large patches (chosen at setup): residual buffer,
+    // per-colour prefix of the apply's 64-row tiles, tiles per colour
+    bool split = false;
+    DevBuf<int64_t> roff;
+    DevBuf<double> rbuf;
+    DevBuf<int> tpre;
+    std::vector<int> ntiles;
 };
 
 struct Level {

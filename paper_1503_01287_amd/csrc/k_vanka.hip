@@ -143,44 +143,53 @@ void launch_vanka_invert(const VankaView &v, int max_m, int *flag, hipStream_t s
     AMG_CHECK_LAUNCH();
 }
 
-// One colour of the multiplicative sweep: residual on the patch (wavefront
-// per node, lanes over the node's A and B^T rows), correction with the
-// patch's inverse, update in place.
-__global__ void __launch_bounds__(VB) k_vanka_colour(const VankaView v, const int *order, const double *b,
-                                                     double *x, double omega) {
+// One colour of the multiplicative sweep, 1,024 threads per patch (a colour
+// holds only a few hundred patches, so each needs many waves in flight):
+// residual on the patch (VG lanes per node row, 64 rows at a time, over the
+// node's A and B^T rows), correction with the patch's inverse (row tiles of
+// 64 VR rows, the 16 wavefronts spread over tiles and column groups, partial
+// sums added in LDS in a fixed order), update in place.
+constexpr int VG = 16;
+constexpr int VR = 4;     // rows per lane and pass in the apply
+constexpr int VCB = 1024; // threads per patch: the ~m / 3 node rows of a patch at once
+constexpr int VNW = VCB / 64;
+
+__global__ void __launch_bounds__(VCB) k_vanka_colour(const VankaView v, const int *order, const double *b,
+                                                      double *x, double omega) {
     extern __shared__ unsigned char smem[];
     const int i = order[blockIdx.x];
     const int p0 = v.pptr[i], nn = v.pptr[i + 1] - p0;
     const int m = 3 * nn + 1;
     double *r = reinterpret_cast<double *>(smem);
-    int *nodes = reinterpret_cast<int *>(r + m);
-    for (int k = threadIdx.x; k < nn; k += VB) nodes[k] = v.pnode[p0 + k];
+    double *part = r + m;                       // NG x m partial products (NG m <= m + 64 VR VNW)
+    int *nodes = reinterpret_cast<int *>(part + m + 64 * VR * VNW);
+    for (int k = threadIdx.x; k < nn; k += VCB) nodes[k] = v.pnode[p0 + k];
     __syncthreads();
     const int64_t nu = 3 * static_cast<int64_t>(v.n);
     const double *p = x + nu;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int k = wave; k <= nn; k += VB / 64) {
+    const int grp = threadIdx.x / VG, lane = threadIdx.x % VG;
+    for (int k = grp; k <= nn; k += VCB / VG) {
         if (k < nn) {
             const int u = nodes[k];
             double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-            for (int q = v.arow[u] + lane; q < v.arow[u + 1]; q += 64) {
+            for (int q = v.arow[u] + lane; q < v.arow[u + 1]; q += VG) {
                 const int j = v.acol[q];
                 const double x0 = x[3 * j], x1 = x[3 * j + 1], x2 = x[3 * j + 2];
                 s0 += v.aval[0 * v.annz + q] * x0 + v.aval[1 * v.annz + q] * x1 + v.aval[2 * v.annz + q] * x2;
                 s1 += v.aval[3 * v.annz + q] * x0 + v.aval[4 * v.annz + q] * x1 + v.aval[5 * v.annz + q] * x2;
                 s2 += v.aval[6 * v.annz + q] * x0 + v.aval[7 * v.annz + q] * x1 + v.aval[8 * v.annz + q] * x2;
             }
-            for (int q = v.btrow[u] + lane; q < v.btrow[u + 1]; q += 64) {
+            for (int q = v.btrow[u] + lane; q < v.btrow[u + 1]; q += VG) {
                 const double pq = p[v.btcol[q]];
                 s0 += v.btval[q] * pq;
                 s1 += v.btval[v.btnnz + q] * pq;
                 s2 += v.btval[2 * v.btnnz + q] * pq;
             }
 #pragma unroll
-            for (int o = 32; o > 0; o >>= 1) {
-                s0 += __shfl_xor(s0, o, 64);
-                s1 += __shfl_xor(s1, o, 64);
-                s2 += __shfl_xor(s2, o, 64);
+            for (int o = VG / 2; o > 0; o >>= 1) {
+                s0 += __shfl_xor(s0, o, VG);
+                s1 += __shfl_xor(s1, o, VG);
+                s2 += __shfl_xor(s2, o, VG);
             }
             if (lane == 0) {
                 r[3 * k] = b[3 * u] - s0;
@@ -190,23 +199,52 @@ __global__ void __launch_bounds__(VB) k_vanka_colour(const VankaView v, const in
         } else {
             // pressure row: g_i - B_i u + C_i p
             double s = 0.0;
-            for (int q = v.brow[i] + lane; q < v.brow[i + 1]; q += 64) {
+            for (int q = v.brow[i] + lane; q < v.brow[i + 1]; q += VG) {
                 const int j = v.bcol[q];
                 s += v.bval[q] * x[3 * j] + v.bval[v.bnnz + q] * x[3 * j + 1] + v.bval[2 * v.bnnz + q] * x[3 * j + 2];
             }
             if (v.crow)
-                for (int q = v.crow[i] + lane; q < v.crow[i + 1]; q += 64) s -= v.cval[q] * p[v.ccol[q]];
+                for (int q = v.crow[i] + lane; q < v.crow[i + 1]; q += VG) s -= v.cval[q] * p[v.ccol[q]];
 #pragma unroll
-            for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+            for (int o = VG / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, VG);
             if (lane == 0) r[3 * nn] = b[nu + i] - s;
         }
     }
     __syncthreads();
     const double *M = v.inv + v.moff[i];
-    for (int a = threadIdx.x; a < m; a += VB) {
-        double d = 0.0;
-        for (int c = 0; c < m; ++c) d += M[static_cast<int64_t>(c) * m + a] * r[c];
-        d *= omega;
+    const int wave = threadIdx.x >> 6, wl = threadIdx.x & 63;
+    // RT tiles of 64 * VR rows; the waves of a tile split the columns into NG groups
+    const int RT = (m + 64 * VR - 1) / (64 * VR);
+    const int NG = RT >= VNW ? 1 : VNW / RT;
+    const int grpc = wave % NG;
+    const int c0 = grpc * m / NG, c1 = (grpc + 1) * m / NG;
+    for (int tile = wave / NG; tile < RT; tile += VNW / NG) {
+        const int a0 = tile * 64 * VR;
+        double acc[VR];
+#pragma unroll
+        for (int t = 0; t < VR; ++t) acc[t] = 0.0;
+        for (int c = c0; c < c1; ++c) {
+            const double rc = r[c];
+            const double *col = M + static_cast<int64_t>(c) * m;
+#pragma unroll
+            for (int t = 0; t < VR; ++t) {
+                const int a = a0 + wl + 64 * t;
+                if (a < m) acc[t] += col[a] * rc;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < VR; ++t) {
+            const int a = a0 + wl + 64 * t;
+            if (a < m) part[grpc * m + a] = acc[t];
+        }
+    }
+    __syncthreads();
+    for (int a = threadIdx.x; a < m; a += VCB) {
+        double sum = 0.0;
+        const int RT = (m + 64 * VR - 1) / (64 * VR);
+        const int NG = RT >= VNW ? 1 : VNW / RT;
+        for (int g = 0; g < NG; ++g) sum += part[g * m + a];
+        const double d = omega * sum;
         if (a < 3 * nn) x[3 * static_cast<int64_t>(nodes[a / 3]) + a % 3] += d;
         else x[nu + i] += d;
     }
@@ -215,8 +253,108 @@ __global__ void __launch_bounds__(VB) k_vanka_colour(const VankaView v, const in
 void launch_vanka_colour(const VankaView &v, const int *order, int count, int max_nodes, const double *b,
                          double *x, double omega, hipStream_t s) {
     if (count <= 0) return;
-    const size_t lds = static_cast<size_t>(3 * max_nodes + 1) * sizeof(double) + max_nodes * sizeof(int);
-    k_vanka_colour<<<count, VB, lds, s>>>(v, order, b, x, omega);
+    const int max_m = 3 * max_nodes + 1;
+    const size_t lds = static_cast<size_t>(2 * max_m + 64 * VR * VNW) * sizeof(double) + max_nodes * sizeof(int);
+    k_vanka_colour<<<count, VCB, lds, s>>>(v, order, b, x, omega);
+    AMG_CHECK_LAUNCH();
+}
+
+// Residual of every patch of a colour into rbuf (same arithmetic as the
+// fused kernel's first phase).
+__global__ void __launch_bounds__(VCB) k_vanka_resid(const VankaView v, const int *order, const int64_t *roff,
+                                                     double *rbuf, const double *b, const double *x) {
+    extern __shared__ int snodes[];
+    const int i = order[blockIdx.x];
+    const int p0 = v.pptr[i], nn = v.pptr[i + 1] - p0;
+    for (int k = threadIdx.x; k < nn; k += VCB) snodes[k] = v.pnode[p0 + k];
+    __syncthreads();
+    double *r = rbuf + roff[i];
+    const int64_t nu = 3 * static_cast<int64_t>(v.n);
+    const double *p = x + nu;
+    const int grp = threadIdx.x / VG, lane = threadIdx.x % VG;
+    for (int k = grp; k <= nn; k += VCB / VG) {
+        if (k < nn) {
+            const int u = snodes[k];
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+            for (int q = v.arow[u] + lane; q < v.arow[u + 1]; q += VG) {
+                const int j = v.acol[q];
+                const double x0 = x[3 * j], x1 = x[3 * j + 1], x2 = x[3 * j + 2];
+                s0 += v.aval[0 * v.annz + q] * x0 + v.aval[1 * v.annz + q] * x1 + v.aval[2 * v.annz + q] * x2;
+                s1 += v.aval[3 * v.annz + q] * x0 + v.aval[4 * v.annz + q] * x1 + v.aval[5 * v.annz + q] * x2;
+                s2 += v.aval[6 * v.annz + q] * x0 + v.aval[7 * v.annz + q] * x1 + v.aval[8 * v.annz + q] * x2;
+            }
+            for (int q = v.btrow[u] + lane; q < v.btrow[u + 1]; q += VG) {
+                const double pq = p[v.btcol[q]];
+                s0 += v.btval[q] * pq;
+                s1 += v.btval[v.btnnz + q] * pq;
+                s2 += v.btval[2 * v.btnnz + q] * pq;
+            }
+#pragma unroll
+            for (int o = VG / 2; o > 0; o >>= 1) {
+                s0 += __shfl_xor(s0, o, VG);
+                s1 += __shfl_xor(s1, o, VG);
+                s2 += __shfl_xor(s2, o, VG);
+            }
+            if (lane == 0) {
+                r[3 * k] = b[3 * u] - s0;
+                r[3 * k + 1] = b[3 * u + 1] - s1;
+                r[3 * k + 2] = b[3 * u + 2] - s2;
+            }
+        } else {
+            double s = 0.0;
+            for (int q = v.brow[i] + lane; q < v.brow[i + 1]; q += VG) {
+                const int j = v.bcol[q];
+                s += v.bval[q] * x[3 * j] + v.bval[v.bnnz + q] * x[3 * j + 1] + v.bval[2 * v.bnnz + q] * x[3 * j + 2];
+            }
+            if (v.crow)
+                for (int q = v.crow[i] + lane; q < v.crow[i + 1]; q += VG) s -= v.cval[q] * p[v.ccol[q]];
+#pragma unroll
+            for (int o = VG / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, VG);
+            if (lane == 0) r[3 * nn] = b[nu + i] - s;
+        }
+    }
+}
+
+// 64 rows of one patch's correction per workgroup: lane = row, the 4
+// wavefronts take a quarter of the columns each, partial sums added in LDS.
+__global__ void __launch_bounds__(VB) k_vanka_apply(const VankaView v, const int *order, const int *tpre,
+                                                    int count, const int64_t *roff, const double *rbuf,
+                                                    double *x, double omega) {
+    __shared__ double part[4][64];
+    int lo = 0, hi = count - 1;
+    const int t = blockIdx.x;
+    while (lo < hi) {  // last patch whose first tile is <= t
+        const int mid = (lo + hi + 1) >> 1;
+        if (tpre[mid] <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    const int i = order[lo];
+    const int p0 = v.pptr[i], nn = v.pptr[i + 1] - p0;
+    const int m = 3 * nn + 1;
+    const int a = (t - tpre[lo]) * 64 + (threadIdx.x & 63);
+    const int wave = threadIdx.x >> 6;
+    const double *r = rbuf + roff[i];
+    const double *M = v.inv + v.moff[i];
+    const int c0 = wave * m / 4, c1 = (wave + 1) * m / 4;
+    double acc = 0.0;
+    if (a < m)
+        for (int c = c0; c < c1; ++c) acc += M[static_cast<int64_t>(c) * m + a] * r[c];
+    part[wave][threadIdx.x & 63] = acc;
+    __syncthreads();
+    if (wave != 0 || a >= m) return;
+    const int l = threadIdx.x;
+    const double d = omega * (((part[0][l] + part[1][l]) + part[2][l]) + part[3][l]);
+    if (a < 3 * nn) x[3 * static_cast<int64_t>(v.pnode[p0 + a / 3]) + a % 3] += d;
+    else x[3 * static_cast<int64_t>(v.n) + i] += d;
+}
+
+void launch_vanka_colour_split(const VankaView &v, const int *order, const int *tpre, int count, int ntiles,
+                               int max_nodes, const int64_t *roff, double *rbuf, const double *b, double *x,
+                               double omega, hipStream_t s) {
+    if (count <= 0) return;
+    k_vanka_resid<<<count, VCB, max_nodes * sizeof(int), s>>>(v, order, roff, rbuf, b, x);
+    AMG_CHECK_LAUNCH();
+    k_vanka_apply<<<ntiles, VB, 0, s>>>(v, order, tpre, count, roff, rbuf, x, omega);
     AMG_CHECK_LAUNCH();
 }
 

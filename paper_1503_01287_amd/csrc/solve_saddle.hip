@@ -362,9 +362,15 @@ static void vanka_step(amg_ctx *h, int l, const double *b, double *x) {
     const VankaView v = vanka_view(L);
     const int nc = static_cast<int>(L.vanka.cptr.size()) - 1;
     ProfScope ps(h, tag("vanka", l), 0.0);
-    for (int c = 0; c < nc; ++c)
-        launch_vanka_colour(v, L.vanka.order.p + L.vanka.cptr[c], L.vanka.cptr[c + 1] - L.vanka.cptr[c],
-                            L.vanka.max_nodes, b, x, h->prm.vanka_omega, h->stream);
+    VankaData &V = L.vanka;
+    for (int c = 0; c < nc; ++c) {
+        const int cnt = V.cptr[c + 1] - V.cptr[c];
+        if (V.split)
+            launch_vanka_colour_split(v, V.order.p + V.cptr[c], V.tpre.p + V.cptr[c], cnt, V.ntiles[c], V.max_nodes,
+                                      V.roff.p, V.rbuf.p, b, x, h->prm.vanka_omega, h->stream);
+        else
+            launch_vanka_colour(v, V.order.p + V.cptr[c], cnt, V.max_nodes, b, x, h->prm.vanka_omega, h->stream);
+    }
 }
 static void vanka_step(amg_ctx *, int, const float *, float *) {
     throw Error(AMG_EUNSUPPORTED, "the Vanka smoother runs in FP64");

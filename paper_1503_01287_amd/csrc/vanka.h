@@ -39,5 +39,12 @@ void launch_vanka_invert(const VankaView &v, int max_m, int *flag, hipStream_t s
 // one colour: the patches order[0 .. count); x = [u (3n); p]
 void launch_vanka_colour(const VankaView &v, const int *order, int count, int max_nodes, const double *b,
                          double *x, double omega, hipStream_t s);
+// the same colour in two kernels, for large patches: the patches' residuals
+// into rbuf (patch i at rbuf + roff[i]), then the corrections with
+// ceil(m_i / 64) workgroups per patch (tpre: prefix of those counts over the
+// colour's patches, ntiles their total)
+void launch_vanka_colour_split(const VankaView &v, const int *order, const int *tpre, int count, int ntiles,
+                               int max_nodes, const int64_t *roff, double *rbuf, const double *b, double *x,
+                               double omega, hipStream_t s);
 
 }  // namespace amgp2

@@ -58,9 +58,12 @@ def _mv(o):
     return mv
 
 
-def test_vanka_sweep(case):
+@pytest.mark.parametrize("autotune", [True, False])
+def test_vanka_sweep(case, autotune):
+    """Every level; without the tuner, patches above 256 unknowns take the
+    two-kernel path and the others the fused one."""
     name, hs, o, h = case
-    s = amg.AMGSolver(hs, smoother="Vanka-1-1", krylov="FGMRES")
+    s = amg.AMGSolver(hs, smoother="Vanka-1-1", krylov="FGMRES", autotune=autotune)
     sm = oamg.Smoother.parse("Vanka-1-1")
     rng = np.random.default_rng(51)
     for l in range(len(h.levels) - 1):
