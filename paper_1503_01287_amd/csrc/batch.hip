@@ -112,6 +112,7 @@ void build_batch(amg_ctx *h, int nsys, const amg_system *sys) {
         inst[i]->prm.autotune = 0;
         inst[i]->prm.omega_model = nullptr;
         inst[i]->prm.precision = AMG_PREC_FP64;  // the merged hierarchy is converted once
+        inst[i]->batch_member = true;            // explicit Schur tails are assembled once, merged
         inst[i]->stream = s;
         build_hierarchy(inst[i].get(), &sys[i]);
         depth[i] = static_cast<int>(inst[i]->lv.size()) - 1;
@@ -279,6 +280,8 @@ void build_batch(amg_ctx *h, int nsys, const amg_system *sys) {
                     for (size_t j = 0; j < R.size(); ++j)
                         if (depth[R[j]] == l + k) copy_segment(Q.dseg, kk++, inst[R[j]]->lv[l].schur.lv[k].dseg, s);
                 }
+                Q.blk_off = off;
+                Q.blk_rows = rows;
                 Q.G = lanes_of(Q.S.nnz, Q.S.nrows);
                 Q.x.alloc(std::max(1, tot));
                 Q.b.alloc(std::max(1, tot));
@@ -358,6 +361,9 @@ void build_batch(amg_ctx *h, int nsys, const amg_system *sys) {
     h->lv = std::move(merged);
     h->saddle = true;
     h->pinned = -1;
+    if (bs)
+        for (int l = 0; l + 1 < static_cast<int>(h->lv.size()); ++l)
+            if (!h->lv[l].schur.lv.empty()) setup_schur_dense(h, l);
     if (p.precision != AMG_PREC_FP64) {
         build_mixed(h);
         build_saddle_mp(h);

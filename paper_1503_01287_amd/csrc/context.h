@@ -83,6 +83,7 @@ struct SchurLevel {
     DMat S;
     int nA = 0;                  // leading rows that are smoothed (the rest: dseg)
     DenseSegs dseg;
+    std::vector<int> blk_off, blk_rows;  // the systems' row ranges (one block outside batches)
     DevBuf<double> dinv;         // 1 / S_ii
     std::vector<int> cptr;       // rows of colour c: rowid[cptr[c] .. cptr[c+1])
     DevBuf<int> rowid;
@@ -97,6 +98,10 @@ struct SchurHier {
     std::vector<SchurLevel> lv;
     DevBuf<double> inv;
     int m = 0;
+    // the cycle from Schur level dense_from down, assembled per system as an
+    // explicit operator (one GEMV instead of the colour sweeps); -1: none
+    int dense_from = -1;
+    DenseSegs tdense;
 };
 
 // Multiplicative Vanka data of a saddle level: patch node lists, the patches
@@ -220,6 +225,7 @@ struct amg_ctx {
     // merged position q holds caller system b_order[q]; systems are ordered
     // by decreasing depth so that those still coarsening on a level lead it
     int nsys = 0;
+    bool batch_member = false;  // a system's own hierarchy, built to be merged into a batch
     std::vector<int> b_order;
     std::vector<int64_t> b_uoff, b_poff, b_nu, b_np;  // per merged position, level-0 vector
     amgp2::ChunkTable b_chunks;                       // level-0 vector, by system
@@ -264,6 +270,7 @@ void precondition_mp(amg_ctx *h, const double *r, double *z);
 void saddle_setup_level(amg_ctx *h, Level &L);
 void setup_schur(amg_ctx *h, int l);
 void setup_vanka(amg_ctx *h, int l);
+void setup_schur_dense(amg_ctx *h, int l);
 VankaView vanka_view(Level &L);
 // JA damping per level from the network of prm.omega_model (fallback: prm.omega)
 void predict_level_omega(amg_ctx *h);

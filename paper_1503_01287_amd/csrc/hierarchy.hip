@@ -576,6 +576,10 @@ void setup_schur(amg_ctx *h, int l) {
     sh.m = m;
     sh.inv.upload(M, s);
     for (size_t k = 0; k + 1 < sh.lv.size(); ++k) sh.lv[k].nA = sh.lv[k].S.nrows;
+    for (SchurLevel &q : sh.lv) {
+        q.blk_off.assign(1, 0);
+        q.blk_rows.assign(1, q.S.nrows);
+    }
     c.nA = 0;
     c.dseg = DenseSegs();
     c.dseg.add(m, 0, 0, 0);
@@ -895,7 +899,10 @@ void build_hierarchy(amg_ctx *h, const amg_system *sys) {
     }
     setup_coarsest(h, h->lv.back());
     if (h->saddle && p.smoother == AMG_SMOOTH_BS)
-        for (int l = 0; l + 1 < static_cast<int>(h->lv.size()); ++l) setup_schur(h, l);
+        for (int l = 0; l + 1 < static_cast<int>(h->lv.size()); ++l) {
+            setup_schur(h, l);
+            if (!h->batch_member) setup_schur_dense(h, l);
+        }
     if (h->saddle && p.smoother == AMG_SMOOTH_VANKA)
         for (int l = 0; l + 1 < static_cast<int>(h->lv.size()); ++l) setup_vanka(h, l);
     if (!h->saddle) {

@@ -369,6 +369,33 @@ template void launch_dense_segs<double>(const DenseSegView &, const double *, co
 template void launch_dense_segs<float>(const DenseSegView &, const float *, const float *, float *, float *,
                                        hipStream_t);
 
+// one thread per segment
+__global__ void k_segment_units(const DenseSegView d, int j, double *x) {
+    const int sg = blockIdx.x * SB + threadIdx.x;
+    if (sg >= d.count) return;
+    if (j < d.rstart[sg + 1] - d.rstart[sg]) x[d.poff[sg] + j] = 1.0;
+}
+
+void launch_segment_units(const DenseSegView &d, int j, double *x, hipStream_t s) {
+    if (d.count <= 0) return;
+    k_segment_units<<<ceil_div(d.count, SB), SB, 0, s>>>(d, j, x);
+    AMG_CHECK_LAUNCH();
+}
+
+// one workgroup per segment
+__global__ void k_segment_store_column(const DenseSegView d, int j, const double *x, double *inv) {
+    const int sg = blockIdx.x;
+    const int m = d.rstart[sg + 1] - d.rstart[sg];
+    if (j >= m) return;
+    for (int i = threadIdx.x; i < m; i += SB) inv[d.moff[sg] + static_cast<int64_t>(i) * m + j] = x[d.poff[sg] + i];
+}
+
+void launch_segment_store_column(const DenseSegView &d, int j, const double *x, double *inv, hipStream_t s) {
+    if (d.count <= 0) return;
+    k_segment_store_column<<<d.count, SB, 0, s>>>(d, j, x, inv);
+    AMG_CHECK_LAUNCH();
+}
+
 // ---------------------------------------------------------------- FGMRES
 constexpr int MD_BLOCKS = 256;
 

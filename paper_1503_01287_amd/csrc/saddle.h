@@ -88,6 +88,11 @@ struct DenseSegView {
 template <typename T>
 void launch_dense_segs(const DenseSegView &d, const T *xu, const T *xp, T *yu, T *yp, hipStream_t s);
 
+// x = sum over segments s with m_s > j of the unit vector at poff[s] + j
+void launch_segment_units(const DenseSegView &d, int j, double *x, hipStream_t s);
+// column j of every segment's matrix (row-major) from x: M_s[i][j] = x[poff[s] + i]
+void launch_segment_store_column(const DenseSegView &d, int j, const double *x, double *inv, hipStream_t s);
+
 // FGMRES inner products: h[i] = <V_i, w> for i < k (V_i = V + i * ld) as
 // block partials partial[i * nb + block]; returns nb
 int launch_multidot(const double *V, int64_t ld, int k, const double *w, int64_t n, double *partial,

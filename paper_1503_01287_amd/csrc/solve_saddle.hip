@@ -3,6 +3,7 @@
 // Braess-Sarazin smoother of Section 3.3, the saddle Galerkin hierarchy K_{l+1} = P^T K_l P
 // with P = diag(I, J, H), and right-preconditioned flexible GMRES (the
 // paper's outer method for these systems, Section 4.4).
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 
@@ -290,6 +291,10 @@ static void schur_vcycle(amg_ctx *h, int l, int k, const T *b, T *x) {
     SchurHier &sh = h->lv[l].schur;
     SchurLevel &q = sh.lv[k];
     hipStream_t s = h->stream;
+    if (k == sh.dense_from) {
+        launch_dense_segs<T>(sh.tdense.view(), static_cast<const T *>(nullptr), b, static_cast<T *>(nullptr), x, s);
+        return;
+    }
     if (q.dseg.count > 0)
         launch_dense_segs<T>(q.dseg.view(), static_cast<const T *>(nullptr), b, static_cast<T *>(nullptr), x, s);
     if (q.nA == 0) return;
@@ -318,6 +323,51 @@ static void schur_vcycle(amg_ctx *h, int l, int k, const T *b, T *x) {
     for (int c = nc - 1; c >= 0; --c)
         launch_scalar_gs<T>(q.cptr[c + 1] - q.cptr[c], q.S.rowptr.p, q.S.col.p, SV<T>::S(q), q.rowid.p + q.cptr[c],
                             SV<T>::sdinv(q), b, x, q.G, s);
+}
+
+// The Schur cycle of saddle level l from Schur level k down is a fixed linear
+// map of its right-hand side (zero initial guess), block diagonal over the
+// systems of a batch. From the first level k >= 1 (k >= 0 below the finest
+// saddle level) whose systems all have at most SCHUR_DENSE_MAX rows, it is
+// assembled once, column by column from unit right-hand sides (one per
+// system at a time), and applied as one segmented GEMV: the same map as the
+// colour sweeps it replaces, up to rounding order.
+constexpr int SCHUR_DENSE_MAX = 1500;
+
+void setup_schur_dense(amg_ctx *h, int l) {
+    SchurHier &sh = h->lv[l].schur;
+    const int K = static_cast<int>(sh.lv.size()) - 1;  // the last level is already explicit
+    int k0 = -1;
+    for (int k = (l == 0 ? 1 : 0); k < K; ++k) {
+        const auto &rows = sh.lv[k].blk_rows;
+        if (!rows.empty() && *std::max_element(rows.begin(), rows.end()) <= SCHUR_DENSE_MAX) {
+            k0 = k;
+            break;
+        }
+    }
+    if (k0 < 0) return;
+    SchurLevel &q = sh.lv[k0];
+    hipStream_t s = h->stream;
+    sh.dense_from = -1;
+    sh.tdense = DenseSegs();
+    int mmax = 0;
+    for (size_t b = 0; b < q.blk_rows.size(); ++b) {
+        if (q.blk_rows[b] == 0) continue;
+        sh.tdense.add(q.blk_rows[b], 0, 0, q.blk_off[b]);
+        mmax = std::max(mmax, q.blk_rows[b]);
+    }
+    sh.tdense.finalize(s);
+    const DenseSegView v = sh.tdense.view();
+    const int n = std::max(1, q.S.nrows);
+    DevBuf<double> unit(n), col(n);
+    for (int j = 0; j < mmax; ++j) {
+        launch_fill(unit.p, 0.0, n, s);
+        launch_segment_units(v, j, unit.p, s);
+        schur_vcycle<double>(h, l, k0, unit.p, col.p);
+        launch_segment_store_column(v, j, col.p, sh.tdense.inv.p, s);
+    }
+    AMG_HIP(hipStreamSynchronize(s));
+    sh.dense_from = k0;
 }
 
 // One Braess-Sarazin step (Section 3.3): K_hat = [[A_hat, B^T], [B, B A_hat^{-1} B^T - S_hat]]
