@@ -29,6 +29,12 @@ void launch_seg_reduce(const double *partial, int n, int k, int nsys, const int 
 // w -= sum_{j<k} h[seg * kmax + j] V_j
 void launch_seg_multi_axpy(const double *V, int64_t ld, int k, const double *h, int kmax, double *w,
                            const ChunkView &t, hipStream_t s);
+// the same, then w /= hn per system with hn = sqrt(h[k] - sum_{j<k} h[j]^2)
+// (the new norm by Pythagoras when h[k] = <w, w> and the V_j are
+// orthonormal), stored in h[seg * kmax + k + 1] (needs k + 2 <= kmax); a
+// system with hn == 0 keeps its w unscaled
+void launch_seg_multi_axpy_normalize(const double *V, int64_t ld, int k, double *h, int kmax, double *w,
+                                     const ChunkView &t, int nsys, hipStream_t s);
 // y = coef[seg] * x
 void launch_seg_scale(const double *x, double *y, const double *coef, const ChunkView &t, hipStream_t s);
 // x += sum_{j < cnt[seg]} y[seg * kmax + j] Z_j

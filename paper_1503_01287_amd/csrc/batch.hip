@@ -413,20 +413,25 @@ int solve_fgmres_batched(amg_ctx *h, const double *b, double *x, double tol, int
         h->gm_m = m;
     }
     const ChunkView t = h->b_chunks.view();
-    DevBuf<double> partial(static_cast<size_t>(kmax) * std::max(1, t.n)), hb(static_cast<size_t>(ns) * kmax),
+    // hb: first-pass coefficients (stride kmax), then hb2: second-pass
+    // coefficients, <w1, w1> and the new norm (stride kmax2)
+    const int kmax2 = m + 2;
+    DevBuf<double> partial(static_cast<size_t>(kmax) * std::max(1, t.n)), hb(static_cast<size_t>(ns) * (kmax + kmax2)),
         coef(ns), ycoef(static_cast<size_t>(ns) * m);
     DevBuf<int> cnt(ns);
-    double *V = h->gm_V.p, *Z = h->gm_Z.p;
+    double *V = h->gm_V.p, *Z = h->gm_Z.p, *hb2 = hb.p + static_cast<size_t>(ns) * kmax;
     std::vector<double> H(static_cast<size_t>(ns) * (m + 1) * m), cs(static_cast<size_t>(ns) * m),
         sn(static_cast<size_t>(ns) * m), g(static_cast<size_t>(ns) * (m + 1)), hcol(static_cast<size_t>(ns) * kmax),
-        hp(static_cast<size_t>(ns) * kmax);
+        hp(static_cast<size_t>(ns) * (kmax + kmax2));
     std::vector<double> beta, r0, hn;
     std::vector<int> status(ns, AMG_NOT_CONVERGED), iters(ns, 0), jcnt(ns, 0);
     std::vector<char> active(ns, 0), running(ns, 0);
     std::vector<double> hc(ns);
+    std::vector<char> fix(ns, 0);
     system_residual(h, b, x, V);
     seg_norms(h, V, partial, hb, kmax, r0);
     beta = r0;
+    hn.assign(ns, 0.0);
     for (int i = 0; i < ns; ++i) {
         if (!(r0[i] == r0[i])) status[i] = AMG_DIVERGED;
         else if (r0[i] == 0.0) status[i] = AMG_OK;
@@ -449,21 +454,44 @@ int solve_fgmres_batched(amg_ctx *h, const double *b, double *x, double tol, int
             double *zj = Z + static_cast<int64_t>(j) * n;
             precondition_any(h, vj, zj);
             system_matvec(h, zj, w);
-            std::fill(hcol.begin(), hcol.end(), 0.0);
-            for (int pass = 0; pass < 2; ++pass) {
-                launch_seg_multidot(V, n, j + 1, w, t, partial.p, h->stream);
-                launch_seg_reduce(partial.p, t.n, j + 1, ns, h->b_c0.p, h->b_c1.p, h->b_c2.p, h->b_c3.p, hb.p, kmax,
-                                  h->stream);
-                launch_seg_multi_axpy(V, n, j + 1, hb.p, kmax, w, t, h->stream);
-                AMG_HIP(hipMemcpyAsync(hp.data(), hb.p, hp.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-                AMG_HIP(hipStreamSynchronize(h->stream));
-                for (int i = 0; i < ns; ++i)
-                    for (int q = 0; q <= j; ++q) hcol[static_cast<size_t>(i) * kmax + q] += hp[static_cast<size_t>(i) * kmax + q];
+            // classical Gram-Schmidt, twice, with one host synchronisation:
+            // the second pass also returns <w1_i, w1_i> (w is basis slot
+            // j + 1), the new norms follow by Pythagoras and the last update
+            // normalises every system's w on the device
+            launch_seg_multidot(V, n, j + 1, w, t, partial.p, h->stream);
+            launch_seg_reduce(partial.p, t.n, j + 1, ns, h->b_c0.p, h->b_c1.p, h->b_c2.p, h->b_c3.p, hb.p, kmax,
+                              h->stream);
+            launch_seg_multi_axpy(V, n, j + 1, hb.p, kmax, w, t, h->stream);
+            launch_seg_multidot(V, n, j + 2, w, t, partial.p, h->stream);
+            launch_seg_reduce(partial.p, t.n, j + 2, ns, h->b_c0.p, h->b_c1.p, h->b_c2.p, h->b_c3.p, hb2, kmax2,
+                              h->stream);
+            launch_seg_multi_axpy_normalize(V, n, j + 1, hb2, kmax2, w, t, ns, h->stream);
+            AMG_HIP(hipMemcpyAsync(hp.data(), hb.p, hp.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+            AMG_HIP(hipStreamSynchronize(h->stream));
+            const double *hp2 = hp.data() + static_cast<size_t>(ns) * kmax;
+            bool remeasure = false;
+            for (int i = 0; i < ns; ++i) {
+                for (int q = 0; q <= j; ++q)
+                    hcol[static_cast<size_t>(i) * kmax + q] =
+                        hp[static_cast<size_t>(i) * kmax + q] + hp2[static_cast<size_t>(i) * kmax2 + q];
+                hn[i] = hp2[static_cast<size_t>(i) * kmax2 + j + 2];
+                // Pythagoras loses digits when the second pass removed a
+                // large part of w1: measure that system's norm instead
+                fix[i] = running[i] && hn[i] * hn[i] < 1e-4 * hp2[static_cast<size_t>(i) * kmax2 + j + 1];
+                remeasure |= fix[i] != 0;
             }
-            seg_norms(h, w, partial, hb, kmax, hn);
-            for (int i = 0; i < ns; ++i) hc[i] = hn[i] > 0.0 ? 1.0 / hn[i] : 0.0;
-            AMG_HIP(hipMemcpyAsync(coef.p, hc.data(), ns * sizeof(double), hipMemcpyHostToDevice, h->stream));
-            launch_seg_scale(w, w, coef.p, t, h->stream);
+            if (remeasure) {
+                std::vector<double> a;
+                seg_norms(h, w, partial, hb, kmax, a);
+                for (int i = 0; i < ns; ++i) {
+                    hc[i] = 1.0;
+                    if (!fix[i]) continue;
+                    if (a[i] > 0.0) hc[i] = 1.0 / a[i];
+                    hn[i] = hn[i] > 0.0 ? hn[i] * a[i] : a[i];
+                }
+                AMG_HIP(hipMemcpyAsync(coef.p, hc.data(), ns * sizeof(double), hipMemcpyHostToDevice, h->stream));
+                launch_seg_scale(w, w, coef.p, t, h->stream);
+            }
             for (int i = 0; i < ns; ++i) {
                 if (!running[i]) continue;
                 double *hcl = &hcol[static_cast<size_t>(i) * kmax];

@@ -219,7 +219,7 @@ struct amg_ctx {
     bool saddle = false;
     int pinned = -1;                  // coarsest unknown pinned to zero (pressure kernel), -1 none
     // flexible GMRES workspace: V ((m+1) x n), Z (m x n), device scalars
-    amgp2::DevBuf<double> gm_V, gm_Z, gm_h, gm_y;
+    amgp2::DevBuf<double> gm_V, gm_Z, gm_h, gm_y, gm_part;
     int gm_m = 0;
     // batch of independent saddle systems merged level by level (nsys > 0):
     // merged position q holds caller system b_order[q]; systems are ordered

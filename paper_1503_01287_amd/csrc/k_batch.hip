@@ -75,25 +75,49 @@ void launch_seg_reduce(const double *partial, int n, int k, int nsys, const int 
 }
 
 __global__ void __launch_bounds__(CB) k_seg_multi_axpy(const double *V, int64_t ld, int k, const double *h,
-                                                       int kmax, double *w, const ChunkView t) {
+                                                       int kmax, double *w, const ChunkView t, int scaled) {
     const int c = blockIdx.x;
     const int64_t s0 = t.start[c];
     const int len = t.len[c];
     const double *hs = h + static_cast<int64_t>(t.seg[c]) * kmax;
+    double inv = 1.0;
+    if (scaled) {
+        const double hn = hs[k + 1];
+        inv = hn > 0.0 ? 1.0 / hn : 1.0;
+    }
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
         const int i = threadIdx.x + e * CB;
         if (i >= len) continue;
         double a = w[s0 + i];
         for (int j = 0; j < k; ++j) a -= hs[j] * V[j * ld + s0 + i];
-        w[s0 + i] = a;
+        w[s0 + i] = a * inv;
     }
 }
 
 void launch_seg_multi_axpy(const double *V, int64_t ld, int k, const double *h, int kmax, double *w,
                            const ChunkView &t, hipStream_t s) {
     if (t.n <= 0 || k <= 0) return;
-    k_seg_multi_axpy<<<t.n, CB, 0, s>>>(V, ld, k, h, kmax, w, t);
+    k_seg_multi_axpy<<<t.n, CB, 0, s>>>(V, ld, k, h, kmax, w, t, 0);
+    AMG_CHECK_LAUNCH();
+}
+
+// one thread per system: hn = sqrt(h[k] - sum_{j<k} h[j]^2) into h[k + 1]
+__global__ void k_seg_pythagoras(double *h, int k, int kmax, int nsys) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nsys) return;
+    double *hs = h + static_cast<int64_t>(i) * kmax;
+    double hsq = hs[k];
+    for (int j = 0; j < k; ++j) hsq -= hs[j] * hs[j];
+    hs[k + 1] = sqrt(fmax(hsq, 0.0));
+}
+
+void launch_seg_multi_axpy_normalize(const double *V, int64_t ld, int k, double *h, int kmax, double *w,
+                                     const ChunkView &t, int nsys, hipStream_t s) {
+    if (t.n <= 0 || nsys <= 0) return;
+    k_seg_pythagoras<<<ceil_div(nsys, CB), CB, 0, s>>>(h, k, kmax, nsys);
+    AMG_CHECK_LAUNCH();
+    k_seg_multi_axpy<<<t.n, CB, 0, s>>>(V, ld, k, h, kmax, w, t, 1);
     AMG_CHECK_LAUNCH();
 }
 

@@ -1,6 +1,8 @@
 // Saddle-point kernels (see saddle.h). Like the velocity row kernels these
 // are bandwidth bound: B holds 1x3 blocks (28 bytes per entry in FP64), C
 // scalars (12 bytes); the vectors they gather are small.
+#include <algorithm>
+
 #include "common.h"
 #include "saddle.h"
 
@@ -397,33 +399,56 @@ void launch_segment_store_column(const DenseSegView &d, int j, const double *x, 
 }
 
 // ---------------------------------------------------------------- FGMRES
-constexpr int MD_BLOCKS = 256;
+// Workgroup (c, g) dots the chunk c of w (MD_CHUNK entries, held in
+// registers) with the same chunk of the basis vectors g * MD_VEC ..
+// g * MD_VEC + MD_VEC - 1: one pass over w per group instead of one per
+// vector, and one block reduction for the whole group.
+constexpr int MD_PER = 2;
+constexpr int MD_CHUNK = MD_PER * SB;
+constexpr int MD_VEC = 8;
 
-__global__ void __launch_bounds__(SB) k_multidot(const double *V, int64_t ld, const double *w, int64_t n,
+__global__ void __launch_bounds__(SB) k_multidot(const double *V, int64_t ld, int k, const double *w, int64_t n,
                                                  double *partial) {
-    // blockIdx.y = vector index, blockIdx.x = chunk
-    const double *v = V + static_cast<int64_t>(blockIdx.y) * ld;
-    double acc = 0.0;
-    for (int64_t t = static_cast<int64_t>(blockIdx.x) * SB + threadIdx.x; t < n;
-         t += static_cast<int64_t>(gridDim.x) * SB)
-        acc += v[t] * w[t];
-    __shared__ double red[SB / 64];
-    acc = gsum<64>(acc);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __shared__ double red[MD_VEC][SB / 64];
+    const int64_t s0 = static_cast<int64_t>(blockIdx.x) * MD_CHUNK;
+    const int j0 = blockIdx.y * MD_VEC;
+    const int nv = min(MD_VEC, k - j0);
+    double wv[MD_PER];
+#pragma unroll
+    for (int e = 0; e < MD_PER; ++e) {
+        const int64_t t = s0 + threadIdx.x + e * SB;
+        wv[e] = t < n ? w[t] : 0.0;
+    }
+    double acc[MD_VEC];
+#pragma unroll
+    for (int q = 0; q < MD_VEC; ++q) {
+        acc[q] = 0.0;
+        if (q < nv) {
+            const double *v = V + (j0 + q) * ld;
+#pragma unroll
+            for (int e = 0; e < MD_PER; ++e) {
+                const int64_t t = s0 + threadIdx.x + e * SB;
+                if (t < n) acc[q] += v[t] * wv[e];
+            }
+        }
+        acc[q] = gsum<64>(acc[q]);
+        if ((threadIdx.x & 63) == 0) red[q][threadIdx.x >> 6] = acc[q];
+    }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < nv) {
         double s = 0.0;
-        for (int q = 0; q < SB / 64; ++q) s += red[q];
-        partial[static_cast<int64_t>(blockIdx.y) * gridDim.x + blockIdx.x] = s;
+        for (int q = 0; q < SB / 64; ++q) s += red[threadIdx.x][q];
+        partial[static_cast<int64_t>(j0 + threadIdx.x) * gridDim.x + blockIdx.x] = s;
     }
 }
+
+int multidot_blocks(int64_t n) { return static_cast<int>(std::max<int64_t>(1, (n + MD_CHUNK - 1) / MD_CHUNK)); }
 
 int launch_multidot(const double *V, int64_t ld, int k, const double *w, int64_t n, double *partial,
                     hipStream_t s) {
     if (k <= 0) return 0;
-    int nb = static_cast<int>(std::min<int64_t>(MD_BLOCKS, (n + SB - 1) / SB));
-    nb = nb < 1 ? 1 : nb;
-    k_multidot<<<dim3(nb, k), SB, 0, s>>>(V, ld, w, n, partial);
+    const int nb = multidot_blocks(n);
+    k_multidot<<<dim3(nb, ceil_div(k, MD_VEC)), SB, 0, s>>>(V, ld, k, w, n, partial);
     AMG_CHECK_LAUNCH();
     return nb;
 }
@@ -445,18 +470,37 @@ void launch_multidot_reduce(const double *partial, int nb, int k, double *h, hip
     AMG_CHECK_LAUNCH();
 }
 
-__global__ void k_multi_axpy(const double *V, int64_t ld, int k, const double *h, double *w, int64_t n) {
+// w -= V h; with `scaled`, the result is also divided by
+// hn = sqrt(h[k] - sum_i h[i]^2), the norm of the new w when w was already
+// orthogonal to the V_i up to a second Gram-Schmidt pass and h[k] = <w, w>
+// (Pythagoras); hn is written to h[k + 1].
+__global__ void k_multi_axpy(const double *V, int64_t ld, int k, double *h, double *w, int64_t n, int scaled) {
+    double inv = 1.0;
+    if (scaled) {
+        double hsq = h[k];
+        for (int i = 0; i < k; ++i) hsq -= h[i] * h[i];
+        const double hn = sqrt(fmax(hsq, 0.0));
+        inv = hn > 0.0 ? 1.0 / hn : 1.0;
+        if (blockIdx.x == 0 && threadIdx.x == 0) h[k + 1] = hn;
+    }
     for (int64_t t = static_cast<int64_t>(blockIdx.x) * SB + threadIdx.x; t < n;
          t += static_cast<int64_t>(gridDim.x) * SB) {
         double s = 0.0;
         for (int i = 0; i < k; ++i) s += h[i] * V[static_cast<int64_t>(i) * ld + t];
-        w[t] -= s;
+        w[t] = (w[t] - s) * inv;
     }
 }
 
 void launch_multi_axpy(const double *V, int64_t ld, int k, const double *h, double *w, int64_t n, hipStream_t s) {
     if (k <= 0 || n <= 0) return;
-    k_multi_axpy<<<grid_s(n), SB, 0, s>>>(V, ld, k, h, w, n);
+    k_multi_axpy<<<grid_s(n), SB, 0, s>>>(V, ld, k, const_cast<double *>(h), w, n, 0);
+    AMG_CHECK_LAUNCH();
+}
+
+void launch_multi_axpy_normalize(const double *V, int64_t ld, int k, double *h, double *w, int64_t n,
+                                 hipStream_t s) {
+    if (n <= 0) return;
+    k_multi_axpy<<<grid_s(n), SB, 0, s>>>(V, ld, k, h, w, n, 1);
     AMG_CHECK_LAUNCH();
 }
 

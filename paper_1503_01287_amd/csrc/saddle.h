@@ -94,14 +94,21 @@ void launch_segment_units(const DenseSegView &d, int j, double *x, hipStream_t s
 void launch_segment_store_column(const DenseSegView &d, int j, const double *x, double *inv, hipStream_t s);
 
 // FGMRES inner products: h[i] = <V_i, w> for i < k (V_i = V + i * ld) as
-// block partials partial[i * nb + block]; returns nb
+// block partials partial[i * nb + block] (nb = multidot_blocks(n), the
+// buffer holds k * nb values); returns nb
 int launch_multidot(const double *V, int64_t ld, int k, const double *w, int64_t n, double *partial,
                     hipStream_t s);
+int multidot_blocks(int64_t n);
 // h[i] = sum of partial[i * nb ...] for i < k
 void launch_multidot_reduce(const double *partial, int nb, int k, double *h, hipStream_t s);
 // w -= sum_i h[i] V_i
 void launch_multi_axpy(const double *V, int64_t ld, int k, const double *h, double *w, int64_t n,
                        hipStream_t s);
+// the same, then w /= hn with hn = sqrt(h[k] - sum_{i<k} h[i]^2) (the new
+// norm by Pythagoras when h[k] = <w, w> and the V_i are orthonormal); hn is
+// stored in h[k + 1]; w is left unscaled when hn == 0
+void launch_multi_axpy_normalize(const double *V, int64_t ld, int k, double *h, double *w, int64_t n,
+                                 hipStream_t s);
 // x += sum_i y[i] Z_i  (y on the device)
 void launch_multi_add(const double *Z, int64_t ld, int k, const double *y, double *x, int64_t n,
                       hipStream_t s);

@@ -561,10 +561,12 @@ int solve_fgmres(amg_ctx *h, const double *b, double *x, double tol, int maxit, 
         h->gm_Z.alloc(static_cast<size_t>(m) * n);
         h->gm_h.alloc(static_cast<size_t>(2 * (m + 2)));
         h->gm_y.alloc(static_cast<size_t>(m + 1));
+        h->gm_part.alloc(static_cast<size_t>(m + 2) * multidot_blocks(n));
         h->gm_m = m;
     }
     double *V = h->gm_V.p, *Z = h->gm_Z.p;
-    std::vector<double> H(static_cast<size_t>(m + 1) * m), cs(m), sn(m), g(m + 1), hcol(m + 2);
+    std::vector<double> H(static_cast<size_t>(m + 1) * m), cs(m), sn(m), g(m + 1), hcol(m + 2),
+        hbuf(static_cast<size_t>(2 * (m + 2)));
     system_residual(h, b, x, V);
     const double r0 = norm2(h, V);
     auto finish = [&](int it, int status) {
@@ -599,26 +601,36 @@ int solve_fgmres(amg_ctx *h, const double *b, double *x, double tol, int maxit, 
             double *zj = Z + static_cast<int64_t>(j) * n;
             precondition_any(h, vj, zj);
             system_matvec(h, zj, w);
-            // classical Gram-Schmidt, twice
-            std::fill(hcol.begin(), hcol.end(), 0.0);
-            for (int pass = 0; pass < 2; ++pass) {
-                const int nb = launch_multidot(V, n, j + 1, w, n, h->partial.p, h->stream);
-                launch_multidot_reduce(h->partial.p, nb, j + 1, h->gm_h.p, h->stream);
-                launch_multi_axpy(V, n, j + 1, h->gm_h.p, w, n, h->stream);
-                std::vector<double> hp(j + 1);
-                AMG_HIP(hipMemcpyAsync(hp.data(), h->gm_h.p, (j + 1) * sizeof(double), hipMemcpyDeviceToHost,
-                                       h->stream));
-                AMG_HIP(hipStreamSynchronize(h->stream));
-                for (int i = 0; i <= j; ++i) hcol[i] += hp[i];
+            // classical Gram-Schmidt, twice, with one host synchronisation:
+            // the second pass also returns <w1, w1> (w is basis slot j + 1),
+            // the new norm follows by Pythagoras and the last update
+            // normalises w on the device
+            double *h1 = h->gm_h.p, *h2 = h->gm_h.p + (m + 2);
+            int nb = launch_multidot(V, n, j + 1, w, n, h->gm_part.p, h->stream);
+            launch_multidot_reduce(h->gm_part.p, nb, j + 1, h1, h->stream);
+            launch_multi_axpy(V, n, j + 1, h1, w, n, h->stream);
+            nb = launch_multidot(V, n, j + 2, w, n, h->gm_part.p, h->stream);
+            launch_multidot_reduce(h->gm_part.p, nb, j + 2, h2, h->stream);
+            launch_multi_axpy_normalize(V, n, j + 1, h2, w, n, h->stream);
+            AMG_HIP(hipMemcpyAsync(hbuf.data(), h->gm_h.p, hbuf.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                   h->stream));
+            AMG_HIP(hipStreamSynchronize(h->stream));
+            for (int i = 0; i <= j; ++i) hcol[i] = hbuf[i] + hbuf[m + 2 + i];
+            double hn = hbuf[m + 2 + j + 2];
+            const double w1sq = hbuf[m + 2 + j + 1];
+            if (hn * hn < 1e-4 * w1sq) {
+                // the second pass removed a large part of w: Pythagoras has
+                // lost digits, measure the norm (w = w2 / hn, or w2 if hn = 0)
+                const double a = norm2(h, w);
+                if (a > 0.0) {
+                    h->h_sc[SC_TMP] = a;
+                    AMG_HIP(hipMemcpyAsync(h->sc.p + SC_TMP, &h->h_sc[SC_TMP], sizeof(double),
+                                           hipMemcpyHostToDevice, h->stream));
+                    launch_scale_by_inverse(w, w, n, h->sc.p, SC_TMP, h->stream);
+                }
+                hn = hn > 0.0 ? hn * a : a;
             }
-            const double hn = norm2(h, w);
             hcol[j + 1] = hn;
-            if (hn > 0.0) {
-                h->h_sc[SC_TMP] = hn;
-                AMG_HIP(hipMemcpyAsync(h->sc.p + SC_TMP, &h->h_sc[SC_TMP], sizeof(double), hipMemcpyHostToDevice,
-                                       h->stream));
-                launch_scale_by_inverse(w, w, n, h->sc.p, SC_TMP, h->stream);
-            }
             for (int i = 0; i < j; ++i) {
                 const double t = cs[i] * hcol[i] + sn[i] * hcol[i + 1];
                 hcol[i + 1] = -sn[i] * hcol[i] + cs[i] * hcol[i + 1];
