@@ -43,7 +43,46 @@ __global__ void __launch_bounds__(MBLOCK) k_row_mp(const RowArgsMP a) {
     const int g = static_cast<int>(t / G);
     const int lane = static_cast<int>(t % G);
     const bool active = g < a.nrows;
+    constexpr bool NEEDS_B = OP == OP_RESID || OP == OP_JACOBI || OP == OP_GS;
+    constexpr bool NEEDS_D = OP == OP_JACOBI || OP == OP_GS;
+    constexpr bool NEEDS_OWN = OP == OP_SPMV_ADD || OP == OP_JACOBI || OP == OP_GS;
+    // Row-local operands of the epilogue (right-hand side, inverted diagonal
+    // block, own entry, BF16 row scales) are loaded before the row's matrix
+    // entries so that their latency overlaps the row instead of following
+    // the group reduction.
     const int i = active ? (a.rowid ? a.rowid[g] : g) : 0;
+    const bool ep = active && lane < 3;
+    const int c = ep ? lane : 0;
+    float b0 = 0.f, b1 = 0.f, b2 = 0.f, d0 = 0.f, d1 = 0.f, d2 = 0.f, own = 0.f;
+    float q0 = 1.f, q1 = 1.f, q2 = 1.f;
+    if (ep) {
+        if constexpr (NEEDS_B) {
+            b0 = a.b[3 * i];
+            b1 = a.b[3 * i + 1];
+            b2 = a.b[3 * i + 2];
+        }
+        if constexpr (NEEDS_D) {
+            if constexpr (MODE == 3) {
+                const float *D = a.dinv + i;
+                const int64_t dn = a.dinv_n;
+                d0 = D[(3 * c) * dn];
+                d1 = D[(3 * c + 1) * dn];
+                d2 = D[(3 * c + 2) * dn];
+            } else {
+                d0 = a.dinv[i];
+            }
+        }
+        if constexpr (NEEDS_OWN) own = OP == OP_JACOBI ? a.x[3 * i + c] : a.y[3 * i + c];
+        if constexpr (KIND == VAL_BF16) {
+            if constexpr (MODE == 3) {
+                q0 = a.rscale[3 * i];
+                q1 = a.rscale[3 * i + 1];
+                q2 = a.rscale[3 * i + 2];
+            } else {
+                q0 = q1 = q2 = a.rscale[i];
+            }
+        }
+    }
     float s0 = 0.f, s1 = 0.f, s2 = 0.f;
     if (active) {
         const int beg = a.rowptr[g], end = a.rowptr[g + 1];
@@ -68,42 +107,31 @@ __global__ void __launch_bounds__(MBLOCK) k_row_mp(const RowArgsMP a) {
     s0 = group_sum_f<G>(s0);
     s1 = group_sum_f<G>(s1);
     s2 = group_sum_f<G>(s2);
-    if (!active || lane >= 3) return;
+    if (!ep) return;
     if constexpr (KIND == VAL_BF16) {
-        if constexpr (MODE == 3) {
-            s0 *= a.rscale[3 * i];
-            s1 *= a.rscale[3 * i + 1];
-            s2 *= a.rscale[3 * i + 2];
-        } else {
-            const float sc = a.rscale[i];
-            s0 *= sc;
-            s1 *= sc;
-            s2 *= sc;
-        }
+        s0 *= q0;
+        s1 *= q1;
+        s2 *= q2;
     }
-    const int c = lane;
     const float sc = c == 0 ? s0 : (c == 1 ? s1 : s2);
     if (a.zero_out) a.zero_out[3 * i + c] = 0.f;
     if constexpr (OP == OP_SPMV) {
         a.y[3 * i + c] = sc;
     } else if constexpr (OP == OP_SPMV_ADD) {
-        a.y[3 * i + c] += sc;
+        a.y[3 * i + c] = own + sc;
     } else if constexpr (OP == OP_RESID) {
-        a.y[3 * i + c] = a.b[3 * i + c] - sc;
+        a.y[3 * i + c] = (c == 0 ? b0 : (c == 1 ? b1 : b2)) - sc;
     } else {
-        const float r0 = a.b[3 * i] - s0, r1 = a.b[3 * i + 1] - s1, r2 = a.b[3 * i + 2] - s2;
+        const float r0 = b0 - s0, r1 = b1 - s1, r2 = b2 - s2;
         float d;
-        if constexpr (MODE == 3) {
-            const float *D = a.dinv + i;
-            const int64_t dn = a.dinv_n;
-            d = D[(3 * c) * dn] * r0 + D[(3 * c + 1) * dn] * r1 + D[(3 * c + 2) * dn] * r2;
-        } else {
-            d = a.dinv[i] * (c == 0 ? r0 : (c == 1 ? r1 : r2));
-        }
-        if constexpr (OP == OP_JACOBI)
-            a.y[3 * i + c] = a.x[3 * i + c] + a.omega * d;
+        if constexpr (MODE == 3)
+            d = d0 * r0 + d1 * r1 + d2 * r2;
         else
-            a.y[3 * i + c] += d;
+            d = d0 * (c == 0 ? r0 : (c == 1 ? r1 : r2));
+        if constexpr (OP == OP_JACOBI)
+            a.y[3 * i + c] = own + a.omega * d;
+        else  // OP_GS: in place (a.y aliases a.x)
+            a.y[3 * i + c] = own + d;
     }
 }
 
