@@ -28,7 +28,7 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "elasticity-32_gs-L0_traffic.md")
 
 
-def measured_traffic(workload: str, precision: str, kernel_class: str, lanes: int):
+def measured_traffic(workload: str, precision: str, kernel_class: str, lanes: int, pair: int):
     """HBM bytes per launch of the dominant kernel from the committed
     rocprofv3 --pmc summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), if it
     covers this kernel and launch shape; else None."""
@@ -40,7 +40,7 @@ def measured_traffic(workload: str, precision: str, kernel_class: str, lanes: in
                 continue
             kv = dict(t.split("=", 1) for t in line.split()[1:])
             if (kv.get("class") == kernel_class and kv.get("precision") == precision
-                    and int(kv.get("lanes", -1)) == lanes):
+                    and int(kv.get("lanes", -1)) == lanes and int(kv.get("pair", 0)) == pair):
                 return int(kv["bytes_per_launch"])
     return None
 
@@ -229,7 +229,8 @@ def main() -> int:
         for l in range(solver.num_levels):
             i = solver.level_info(l)
             levels.append(dict(nodes=i.n_lin + i.n_quad, pressure=i.n_pres, nnz=int(i.nnz_A), colors=int(i.n_colors),
-                               lanes=[int(i.lanes_A), int(i.lanes_gs)], gs_xcd=int(i.gs_xcd), fused=bool(i.fused),
+                               lanes=[int(i.lanes_A), int(i.lanes_gs)], pair=[int(i.pair_A), int(i.pair_gs)],
+                               gs_xcd=int(i.gs_xcd), fused=bool(i.fused),
                                omega=round(float(i.omega), 4)))
         print(f"# {precision}/{krylov} setup {setup_ms:.0f} ms, levels {levels}", file=sys.stderr, flush=True)
         for _ in range(args.warmup):
@@ -267,8 +268,9 @@ def main() -> int:
                 per_launch_bytes = st["bytes"] / st["launches"]
                 per_launch_ms = st["ms"] / st["launches"]
                 achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
-                lanes = levels[0]["lanes"][1] if dom.startswith("gs.") else levels[0]["lanes"][0]
-                traffic = measured_traffic(args.workload, precision, dom, lanes)
+                which = 1 if dom.startswith("gs.") else 0
+                traffic = measured_traffic(args.workload, precision, dom, levels[0]["lanes"][which],
+                                           levels[0]["pair"][which])
                 out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                                    "kernel": dom, "launches_per_step": st["launches"] // args.steps,

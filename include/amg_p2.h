@@ -182,7 +182,9 @@ typedef struct {
     int32_t n_colors;              /* Gauss-Seidel colours (0 if not built)    */
     int32_t is_coarsest;
     int32_t lanes_A, lanes_gs;     /* lanes per row chosen for the level's
-                                      natural-order and colour-sweep kernels  */
+                                      natural-order and colour-sweep kernels
+                                      (of the reduced-precision copies when
+                                      precision is not FP64)                 */
     int32_t fused;                 /* 1 if a V-cycle reaching this level runs
                                       it inside the fused coarse kernel       */
     double omega;                  /* JA damping used on this level          */
@@ -192,6 +194,8 @@ typedef struct {
     int64_t nnz_S;                 /* entries of that Schur complement S_l   */
     int32_t gs_xcd;                /* 1 if the colour sweeps give each XCD one
                                       contiguous eighth of a colour's rows    */
+    int32_t pair_A, pair_gs;       /* 1 if those kernels take two entries per
+                                      lane and loop trip (reduced precision)  */
 } amg_level_info;
 
 /* Fill *p with the defaults listed above. */

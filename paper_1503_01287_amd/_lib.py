@@ -65,7 +65,7 @@ class AmgLevelInfo(ctypes.Structure):
         ("n_colors", ctypes.c_int32), ("is_coarsest", ctypes.c_int32),
         ("lanes_A", ctypes.c_int32), ("lanes_gs", ctypes.c_int32), ("fused", ctypes.c_int32),
         ("omega", ctypes.c_double), ("schur_levels", ctypes.c_int32), ("nnz_S", ctypes.c_int64),
-        ("gs_xcd", ctypes.c_int32),
+        ("gs_xcd", ctypes.c_int32), ("pair_A", ctypes.c_int32), ("pair_gs", ctypes.c_int32),
     ]
 
 

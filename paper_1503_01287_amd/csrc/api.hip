@@ -271,8 +271,10 @@ int amg_get_level_info(amg_handle h, int32_t level, amg_level_info *info) {
         info->nnz_P = L.coarsest ? 0 : L.P.nnz;
         info->n_colors = L.cptr.empty() ? 0 : static_cast<int>(L.cptr.size()) - 1;
         info->is_coarsest = L.coarsest ? 1 : 0;
-        info->lanes_A = L.G;
-        info->lanes_gs = L.Gg;
+        info->lanes_A = h->mixed ? L.mp.G : L.G;
+        info->lanes_gs = h->mixed ? L.mp.Gg : L.Gg;
+        info->pair_A = h->mixed ? L.mp.pair : 0;
+        info->pair_gs = h->mixed ? L.mp.pairg : 0;
         const int fs = h->tail_start >= 0 ? h->tail_start : h->dense_start;
         info->fused = (fs >= 0 && level >= fs) ? 1 : 0;
         info->schur_levels = static_cast<int>(L.schur.lv.size());

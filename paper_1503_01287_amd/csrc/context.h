@@ -30,6 +30,7 @@ struct DMat {
 struct LevelMP {
     int kind = VAL_F32;            // value kind of A and its grouped copy
     int G = 16, Gg = 16;           // lanes per row of the reduced-precision A / grouped-A kernels
+    int pair = 0, pairg = 0;       // their loop form (two entries per trip), chosen by the tuner
     DevBuf<float> a32, ag32;       // FP32 planes
     DevBuf<uint16_t> a16, ag16;    // BF16 planes (values / row scale)
     DevBuf<float> scale;           // BF16: scale of every scalar row

@@ -36,7 +36,24 @@ __device__ __forceinline__ float ld(const void *p, int64_t idx) {
         return bf16_to_f32(static_cast<const uint16_t *>(p)[idx]);
 }
 
-template <int MODE, int G, int OP, int KIND>
+// s += A_k x_j for entry k (a 3x3 block of nine planes, or a scalar that
+// multiplies every component)
+template <int MODE, int KIND>
+__device__ __forceinline__ void acc_entry(const void *val, int64_t nz, int k, float x0, float x1, float x2,
+                                          float &s0, float &s1, float &s2) {
+    if constexpr (MODE == 3) {
+        s0 += ld<KIND>(val, k) * x0 + ld<KIND>(val, nz + k) * x1 + ld<KIND>(val, 2 * nz + k) * x2;
+        s1 += ld<KIND>(val, 3 * nz + k) * x0 + ld<KIND>(val, 4 * nz + k) * x1 + ld<KIND>(val, 5 * nz + k) * x2;
+        s2 += ld<KIND>(val, 6 * nz + k) * x0 + ld<KIND>(val, 7 * nz + k) * x1 + ld<KIND>(val, 8 * nz + k) * x2;
+    } else {
+        const float v = ld<KIND>(val, k);
+        s0 += v * x0;
+        s1 += v * x1;
+        s2 += v * x2;
+    }
+}
+
+template <int MODE, int G, int OP, int KIND, bool PAIR>
 __global__ void __launch_bounds__(MBLOCK) k_row_mp(const RowArgsMP a) {
     const int64_t blk = a.xcd_chunks ? xcd_chunk_block() : static_cast<int64_t>(blockIdx.x);
     const int64_t t = blk * MBLOCK + threadIdx.x;
@@ -87,21 +104,22 @@ __global__ void __launch_bounds__(MBLOCK) k_row_mp(const RowArgsMP a) {
     if (active) {
         const int beg = a.rowptr[g], end = a.rowptr[g + 1];
         const int64_t nz = a.nnz;
-        for (int k = beg + lane; k < end; k += G) {
+        int k = beg + lane;
+        if constexpr (PAIR) {
+            // two entries per trip: both column indices, then both gathers
+            // of x, are in flight together (long rows on few lanes)
+            for (; k + G < end; k += 2 * G) {
+                const int j = a.col[k], jb = a.col[k + G];
+                const float x0 = a.x[3 * j], x1 = a.x[3 * j + 1], x2 = a.x[3 * j + 2];
+                const float y0 = a.x[3 * jb], y1 = a.x[3 * jb + 1], y2 = a.x[3 * jb + 2];
+                acc_entry<MODE, KIND>(a.val, nz, k, x0, x1, x2, s0, s1, s2);
+                acc_entry<MODE, KIND>(a.val, nz, k + G, y0, y1, y2, s0, s1, s2);
+            }
+        }
+        for (; k < end; k += G) {
             const int j = a.col[k];
             const float x0 = a.x[3 * j], x1 = a.x[3 * j + 1], x2 = a.x[3 * j + 2];
-            if constexpr (MODE == 3) {
-                s0 += ld<KIND>(a.val, k) * x0 + ld<KIND>(a.val, nz + k) * x1 + ld<KIND>(a.val, 2 * nz + k) * x2;
-                s1 += ld<KIND>(a.val, 3 * nz + k) * x0 + ld<KIND>(a.val, 4 * nz + k) * x1 +
-                      ld<KIND>(a.val, 5 * nz + k) * x2;
-                s2 += ld<KIND>(a.val, 6 * nz + k) * x0 + ld<KIND>(a.val, 7 * nz + k) * x1 +
-                      ld<KIND>(a.val, 8 * nz + k) * x2;
-            } else {
-                const float v = ld<KIND>(a.val, k);
-                s0 += v * x0;
-                s1 += v * x1;
-                s2 += v * x2;
-            }
+            acc_entry<MODE, KIND>(a.val, nz, k, x0, x1, x2, s0, s1, s2);
         }
     }
     s0 = group_sum_f<G>(s0);
@@ -140,12 +158,22 @@ static void launch_mp_g(int op, const RowArgsMP &a, hipStream_t s) {
     int nb = ceil_div(static_cast<int64_t>(a.nrows) * G, MBLOCK);
     if (nb == 0) return;
     if (a.xcd_chunks) nb = (nb + 7) / 8 * 8;
+    const bool pair = a.pair != 0;
     switch (op) {
-        case OP_SPMV: k_row_mp<MODE, G, OP_SPMV, KIND><<<nb, MBLOCK, 0, s>>>(a); break;
-        case OP_SPMV_ADD: k_row_mp<MODE, G, OP_SPMV_ADD, KIND><<<nb, MBLOCK, 0, s>>>(a); break;
-        case OP_RESID: k_row_mp<MODE, G, OP_RESID, KIND><<<nb, MBLOCK, 0, s>>>(a); break;
-        case OP_JACOBI: k_row_mp<MODE, G, OP_JACOBI, KIND><<<nb, MBLOCK, 0, s>>>(a); break;
-        case OP_GS: k_row_mp<MODE, G, OP_GS, KIND><<<nb, MBLOCK, 0, s>>>(a); break;
+        case OP_SPMV: k_row_mp<MODE, G, OP_SPMV, KIND, false><<<nb, MBLOCK, 0, s>>>(a); break;
+        case OP_SPMV_ADD: k_row_mp<MODE, G, OP_SPMV_ADD, KIND, false><<<nb, MBLOCK, 0, s>>>(a); break;
+        case OP_RESID:
+            if (pair) k_row_mp<MODE, G, OP_RESID, KIND, true><<<nb, MBLOCK, 0, s>>>(a);
+            else k_row_mp<MODE, G, OP_RESID, KIND, false><<<nb, MBLOCK, 0, s>>>(a);
+            break;
+        case OP_JACOBI:
+            if (pair) k_row_mp<MODE, G, OP_JACOBI, KIND, true><<<nb, MBLOCK, 0, s>>>(a);
+            else k_row_mp<MODE, G, OP_JACOBI, KIND, false><<<nb, MBLOCK, 0, s>>>(a);
+            break;
+        case OP_GS:
+            if (pair) k_row_mp<MODE, G, OP_GS, KIND, true><<<nb, MBLOCK, 0, s>>>(a);
+            else k_row_mp<MODE, G, OP_GS, KIND, false><<<nb, MBLOCK, 0, s>>>(a);
+            break;
         default: throw Error(AMG_EINVAL, "mixed row kernel: unsupported operation");
     }
     AMG_CHECK_LAUNCH();

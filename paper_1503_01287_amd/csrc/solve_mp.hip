@@ -43,20 +43,25 @@ static void autotune_mp(amg_ctx *h, Level &L) {
         }
         return best_ms;
     };
-    auto pick = [&](int G0, auto &&time_of) {
-        int bestG = G0;
-        float best = time_of(G0);
-        for (int G : cand) {
-            if (G == G0) continue;
-            const float ms = time_of(G);
-            if (ms < 0.97f * best) {
-                best = ms;
-                bestG = G;
+    // (lanes, loop form) pairs; the heuristic lane count in the plain form is
+    // kept unless another choice is at least 3% faster
+    auto pick = [&](int G0, int &pair_out, auto &&time_of) {
+        int bestG = G0, bestP = 0;
+        float best = time_of(G0, 0);
+        for (int P = 0; P < 2; ++P)
+            for (int G : cand) {
+                if (G == G0 && P == 0) continue;
+                const float ms = time_of(G, P);
+                if (ms < 0.97f * best) {
+                    best = ms;
+                    bestG = G;
+                    bestP = P;
+                }
             }
-        }
+        pair_out = bestP;
         return bestG;
     };
-    M.G = pick(M.G, [&](int G) {
+    M.G = pick(M.G, M.pair, [&](int G, int P) {
         RowArgsMP a;
         a.nrows = L.n;
         a.rowptr = L.A.rowptr.p;
@@ -67,10 +72,11 @@ static void autotune_mp(amg_ctx *h, Level &L) {
         a.x = M.x.p;
         a.b = M.b.p;
         a.y = M.r.p;
+        a.pair = P;
         return time_it([&] { launch_row_mp(L.mode, OP_RESID, G, M.kind, a, s); });
     });
     if (!L.cptr.empty())
-        M.Gg = pick(M.Gg, [&](int G) {
+        M.Gg = pick(M.Gg, M.pairg, [&](int G, int P) {
             return time_it([&] {
                 for (size_t c = 0; c + 1 < L.cptr.size(); ++c) {
                     if (L.cptr[c + 1] == L.cptr[c]) continue;
@@ -88,6 +94,7 @@ static void autotune_mp(amg_ctx *h, Level &L) {
                     a.dinv = M.dinv.p;
                     a.dinv_n = L.n;
                     a.xcd_chunks = L.gs_xcd;
+                    a.pair = P;
                     launch_row_mp(L.mode, OP_GS, G, M.kind, a, s);
                 }
             });
@@ -195,6 +202,7 @@ static RowArgsMP args_natural(Level &L) {
     a.val = L.mp.aval();
     a.rscale = L.mp.scale.p;
     a.nnz = L.A.nnz;
+    a.pair = L.mp.pair;
     return a;
 }
 
@@ -264,6 +272,7 @@ static void gs_mp(amg_ctx *h, int l, const float *b, float *x, bool forward, boo
         a.dinv = L.mp.dinv.p;
         a.dinv_n = L.n;
         a.xcd_chunks = L.gs_xcd;
+        a.pair = L.mp.pairg;
         ProfScope ps(h, tag("gs", l), mat_bytes(L, L.colour_nnz[c], a.nrows) + a.nrows * (4.0 + 12.0 + 24.0 + nb * 4.0));
         launch_row_mp(L.mode, OP_GS, L.mp.Gg, L.mp.kind, a, h->stream);
     }

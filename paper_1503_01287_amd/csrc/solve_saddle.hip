@@ -140,6 +140,7 @@ static void a_resid(amg_ctx *h, int l, const float *b, const float *x, float *r,
     a.x = x;
     a.b = b;
     a.y = r;
+    a.pair = L.mp.pair;
     ProfScope ps(h, tag("resid", l), static_cast<double>(L.A.nnz) * (9.0 * L.mp.vbytes() + 4.0) + L.n * 40.0);
     launch_row_mp(3, OP_RESID, L.mp.G, L.mp.kind, a, h->stream);
 }
