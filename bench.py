@@ -28,7 +28,7 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "elasticity-32_gs-L0_traffic.md")
 
 
-def measured_traffic(workload: str, precision: str, kernel_class: str, lanes: int, pair: int):
+def measured_traffic(workload: str, precision: str, kernel_class: str, lanes: int, pair: int, xcd: int):
     """HBM bytes per launch of the dominant kernel from the committed
     rocprofv3 --pmc summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), if it
     covers this kernel and launch shape; else None."""
@@ -40,7 +40,8 @@ def measured_traffic(workload: str, precision: str, kernel_class: str, lanes: in
                 continue
             kv = dict(t.split("=", 1) for t in line.split()[1:])
             if (kv.get("class") == kernel_class and kv.get("precision") == precision
-                    and int(kv.get("lanes", -1)) == lanes and int(kv.get("pair", 0)) == pair):
+                    and int(kv.get("lanes", -1)) == lanes and int(kv.get("pair", 0)) == pair
+                    and int(kv.get("xcd", 0)) == xcd):
                 return int(kv["bytes_per_launch"])
     return None
 
@@ -270,7 +271,7 @@ def main() -> int:
                 achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
                 which = 1 if dom.startswith("gs.") else 0
                 traffic = measured_traffic(args.workload, precision, dom, levels[0]["lanes"][which],
-                                           levels[0]["pair"][which])
+                                           levels[0]["pair"][which], levels[0]["gs_xcd"] if which else 0)
                 out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                                    "kernel": dom, "launches_per_step": st["launches"] // args.steps,

@@ -279,7 +279,7 @@ int amg_get_level_info(amg_handle h, int32_t level, amg_level_info *info) {
         info->fused = (fs >= 0 && level >= fs) ? 1 : 0;
         info->schur_levels = static_cast<int>(L.schur.lv.size());
         info->omega = jacobi_omega(h, level);
-        info->gs_xcd = L.gs_xcd;
+        info->gs_xcd = h->mixed ? L.mp.xcd : L.gs_xcd;
         info->nnz_S = L.schur.lv.empty() ? 0 : L.schur.lv[0].S.nnz;
         return AMG_OK;
     });

@@ -31,6 +31,7 @@ struct LevelMP {
     int kind = VAL_F32;            // value kind of A and its grouped copy
     int G = 16, Gg = 16;           // lanes per row of the reduced-precision A / grouped-A kernels
     int pair = 0, pairg = 0;       // their loop form (two entries per trip), chosen by the tuner
+    int xcd = 0;                   // per-XCD contiguous rows in the colour sweeps (as Level::gs_xcd)
     DevBuf<float> a32, ag32;       // FP32 planes
     DevBuf<uint16_t> a16, ag16;    // BF16 planes (values / row scale)
     DevBuf<float> scale;           // BF16: scale of every scalar row
@@ -278,6 +279,8 @@ void predict_level_omega(amg_ctx *h);
 double jacobi_omega(const amg_ctx *h, int l);
 // (re)build the fused coarse end of the SPD V-cycle from the current weights
 void setup_tail(amg_ctx *h);
+// lanes per row for a row kernel from the mean entries per row (4..64)
+int lanes_for(int64_t nnz, int nrows);
 // FP32 copy of the assembled coarse-end operator (reduced-precision cycle)
 void refresh_tail_f32(amg_ctx *h);
 void saddle_precondition(amg_ctx *h, const double *r, double *z);

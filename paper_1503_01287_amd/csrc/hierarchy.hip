@@ -130,7 +130,7 @@ static DMat spgemm(const DMat &X, const DMat &Y, bool search_y, hipStream_t s) {
 
 // Lanes per row for a row kernel: the smallest power of two (4..64) not
 // below the mean entries per row.
-static int lanes_for(int64_t nnz, int nrows) {
+int lanes_for(int64_t nnz, int nrows) {
     const double avg = nrows > 0 ? static_cast<double>(nnz) / nrows : 1.0;
     int G = 4;
     while (G < 64 && G < avg) G *= 2;
@@ -245,7 +245,7 @@ static void autotune_level(amg_ctx *h, Level &L) {
         return best_ms;
     };
     // Candidates are timed against the heuristic's choice, which another
-    // candidate replaces only when it is at least 3% faster: timing noise
+    // candidate replaces only when it is at least 5% faster: timing noise
     // then does not flip the choice from one setup to the next.
     auto pick = [&](int G0, auto &&time_of) {
         int bestG = G0;
@@ -253,7 +253,7 @@ static void autotune_level(amg_ctx *h, Level &L) {
         for (int G : cand) {
             if (G == G0) continue;
             const float ms = time_of(G);
-            if (ms < 0.97f * best) {
+            if (ms < 0.95f * best) {
                 best = ms;
                 bestG = G;
             }
@@ -300,7 +300,7 @@ static void autotune_level(amg_ctx *h, Level &L) {
         const auto xc = pick(rr.first, [&](int G) { return sweep_time(G, 1); });
         L.Gg = rr.first;
         L.gs_xcd = 0;
-        if (xc.second < 0.97f * rr.second) {
+        if (xc.second < 0.95f * rr.second) {
             L.Gg = xc.first;
             L.gs_xcd = 1;
         }

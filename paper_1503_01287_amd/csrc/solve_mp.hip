@@ -44,7 +44,7 @@ static void autotune_mp(amg_ctx *h, Level &L) {
         return best_ms;
     };
     // (lanes, loop form) pairs; the heuristic lane count in the plain form is
-    // kept unless another choice is at least 3% faster
+    // kept unless another choice is at least 5% faster
     auto pick = [&](int G0, int &pair_out, auto &&time_of) {
         int bestG = G0, bestP = 0;
         float best = time_of(G0, 0);
@@ -52,7 +52,7 @@ static void autotune_mp(amg_ctx *h, Level &L) {
             for (int G : cand) {
                 if (G == G0 && P == 0) continue;
                 const float ms = time_of(G, P);
-                if (ms < 0.97f * best) {
+                if (ms < 0.95f * best) {
                     best = ms;
                     bestG = G;
                     bestP = P;
@@ -75,8 +75,10 @@ static void autotune_mp(amg_ctx *h, Level &L) {
         a.pair = P;
         return time_it([&] { launch_row_mp(L.mode, OP_RESID, G, M.kind, a, s); });
     });
-    if (!L.cptr.empty())
-        M.Gg = pick(M.Gg, M.pairg, [&](int G, int P) {
+    if (!L.cptr.empty()) {
+        // a whole forward sweep, colour by colour, as the smoother runs it;
+        // then per-XCD contiguous rows for the chosen kernel
+        auto sweep_time = [&](int G, int P, int xcd) {
             return time_it([&] {
                 for (size_t c = 0; c + 1 < L.cptr.size(); ++c) {
                     if (L.cptr[c + 1] == L.cptr[c]) continue;
@@ -93,12 +95,15 @@ static void autotune_mp(amg_ctx *h, Level &L) {
                     a.y = M.t.p;
                     a.dinv = M.dinv.p;
                     a.dinv_n = L.n;
-                    a.xcd_chunks = L.gs_xcd;
+                    a.xcd_chunks = xcd;
                     a.pair = P;
                     launch_row_mp(L.mode, OP_GS, G, M.kind, a, s);
                 }
             });
-        });
+        };
+        M.Gg = pick(M.Gg, M.pairg, [&](int G, int P) { return sweep_time(G, P, 0); });
+        M.xcd = sweep_time(M.Gg, M.pairg, 1) < 0.95f * sweep_time(M.Gg, M.pairg, 0) ? 1 : 0;
+    }
     AMG_HIP(hipEventDestroy(e0));
     AMG_HIP(hipEventDestroy(e1));
 }
@@ -143,8 +148,10 @@ void build_mixed(amg_ctx *h) {
         launch_to_f32(L.P.val.p, M.pval.p, L.P.nnz, s);
         M.rval.alloc(L.R.nnz);
         launch_to_f32(L.R.val.p, M.rval.p, L.R.nnz, s);
-        M.G = L.G;
-        M.Gg = L.Gg;
+        // the tuner starts from the heuristic lane count, not from the FP64
+        // kernels' tuned choice, so that its result does not inherit their
+        // timing noise
+        M.G = M.Gg = lanes_for(L.A.nnz, L.n);
         if (h->prm.autotune) autotune_mp(h, L);
     }
     refresh_tail_f32(h);
@@ -271,7 +278,7 @@ static void gs_mp(amg_ctx *h, int l, const float *b, float *x, bool forward, boo
         a.y = x;
         a.dinv = L.mp.dinv.p;
         a.dinv_n = L.n;
-        a.xcd_chunks = L.gs_xcd;
+        a.xcd_chunks = L.mp.xcd;
         a.pair = L.mp.pairg;
         ProfScope ps(h, tag("gs", l), mat_bytes(L, L.colour_nnz[c], a.nrows) + a.nrows * (4.0 + 12.0 + 24.0 + nb * 4.0));
         launch_row_mp(L.mode, OP_GS, L.mp.Gg, L.mp.kind, a, h->stream);

@@ -42,6 +42,9 @@ def main() -> int:
     prec = "FP64" if saddle else args.precision
     kry = "FGMRES" if saddle else ("PCG" if prec == "FP64" else "FCG")
     s = AMGSolver(sysm, krylov=kry, precision=prec, **kw)
+    i0 = s.level_info(0)
+    print(f"level 0: lanes {i0.lanes_A}/{i0.lanes_gs}, two entries per trip {i0.pair_A}/{i0.pair_gs}, "
+          f"per-XCD rows {i0.gs_xcd}", file=sys.stderr, flush=True)
     b = torch.from_numpy(sysm.rhs).to(dev)
     x = torch.zeros_like(b)
     for _ in range(args.solves):
