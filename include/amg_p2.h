@@ -146,7 +146,8 @@ typedef struct {
     const double *level_omega;    /* host, n_level_omega values (copied)   */
     int32_t fuse_coarse;  /* 1 (default): the coarse end of a V-cycle runs as
                              one kernel (an explicit operator assembled at
-                             setup, or a single-workgroup kernel); 0: one
+                             setup, one per system for saddle systems and
+                             batches, or a single-workgroup kernel); 0: one
                              launch per operation. Same arithmetic, up to
                              rounding order.                                  */
     int32_t autotune;     /* 1 (default): time the row kernels' lanes-per-row

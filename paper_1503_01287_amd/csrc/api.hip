@@ -275,7 +275,9 @@ int amg_get_level_info(amg_handle h, int32_t level, amg_level_info *info) {
         info->lanes_gs = h->mixed ? L.mp.Gg : L.Gg;
         info->pair_A = h->mixed ? L.mp.pair : 0;
         info->pair_gs = h->mixed ? L.mp.pairg : 0;
-        const int fs = h->tail_start >= 0 ? h->tail_start : h->dense_start;
+        const int fs = h->tail_start >= 0 ? h->tail_start
+                       : h->dense_start >= 0 ? h->dense_start
+                                             : h->saddle_tail_from;
         info->fused = (fs >= 0 && level >= fs) ? 1 : 0;
         info->schur_levels = static_cast<int>(L.schur.lv.size());
         info->omega = jacobi_omega(h, level);

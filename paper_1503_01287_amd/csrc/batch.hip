@@ -148,6 +148,10 @@ void build_batch(amg_ctx *h, int nsys, const amg_system *sys) {
             }
         }
         M.coarsest = M.nA == 0;
+        M.sys_noff = noff;
+        M.sys_n = nrow;
+        M.sys_poff = poff;
+        M.sys_np = prow;
         std::vector<const DMat *> pa, pb, pbt, pc;
         bool anyc = false;
         for (int i : P) {
@@ -368,6 +372,7 @@ void build_batch(amg_ctx *h, int nsys, const amg_system *sys) {
         build_mixed(h);
         build_saddle_mp(h);
     }
+    setup_saddle_tail(h);
     h->n_dof = static_cast<int>(h->lv[0].vlen());
     const size_t nd = static_cast<size_t>(h->n_dof);
     h->b_b.alloc(nd);

@@ -156,6 +156,9 @@ struct Level {
     // whose hierarchy continues below); the others are solved by dseg
     int nA = 0, npA = 0;
     DenseSegs dseg;
+    // the systems on this level (one outside batches), in vector order:
+    // first node, nodes, first pressure, pressures
+    std::vector<int> sys_noff, sys_n, sys_poff, sys_np;
     SchurHier schur;          // BS: scalar hierarchy of this level's Schur complement
     VankaData vanka;          // multiplicative Vanka patches
     int Gb = 16, Gbt = 16, Gc = 8, Gh = 4, Ght = 8;
@@ -219,6 +222,10 @@ struct amg_ctx {
     amgp2::DevBuf<float> tail_dense32;
     // saddle point system
     bool saddle = false;
+    // the saddle V-cycle from level saddle_tail_from (>= 1) down, entered
+    // from a zero guess, as one explicit map per system (-1: none)
+    int saddle_tail_from = -1;
+    amgp2::DenseSegs saddle_tail;
     int pinned = -1;                  // coarsest unknown pinned to zero (pressure kernel), -1 none
     // flexible GMRES workspace: V ((m+1) x n), Z (m x n), device scalars
     amgp2::DevBuf<double> gm_V, gm_Z, gm_h, gm_y, gm_part;
@@ -273,6 +280,7 @@ void saddle_setup_level(amg_ctx *h, Level &L);
 void setup_schur(amg_ctx *h, int l);
 void setup_vanka(amg_ctx *h, int l);
 void setup_schur_dense(amg_ctx *h, int l);
+void setup_saddle_tail(amg_ctx *h);
 VankaView vanka_view(Level &L);
 // JA damping per level from the network of prm.omega_model (fallback: prm.omega)
 void predict_level_omega(amg_ctx *h);

@@ -912,6 +912,7 @@ void build_hierarchy(amg_ctx *h, const amg_system *sys) {
         build_mixed(h);
         build_saddle_mp(h);
     }
+    if (h->saddle && !h->batch_member) setup_saddle_tail(h);
     h->n_dof = static_cast<int>(h->lv[0].vlen());
     const size_t nd = static_cast<size_t>(h->n_dof);
     h->kr.alloc(nd);

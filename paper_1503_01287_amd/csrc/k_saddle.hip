@@ -372,29 +372,36 @@ template void launch_dense_segs<float>(const DenseSegView &, const float *, cons
                                        hipStream_t);
 
 // one thread per segment
-__global__ void k_segment_units(const DenseSegView d, int j, double *x) {
+__global__ void k_segment_units(const DenseSegView d, int j, double *xu, double *xp) {
     const int sg = blockIdx.x * SB + threadIdx.x;
     if (sg >= d.count) return;
-    if (j < d.rstart[sg + 1] - d.rstart[sg]) x[d.poff[sg] + j] = 1.0;
+    if (j >= d.rstart[sg + 1] - d.rstart[sg]) return;
+    const int nu = d.nu[sg];
+    if (j < nu) xu[d.uoff[sg] + j] = 1.0;
+    else xp[d.poff[sg] + j - nu] = 1.0;
 }
 
-void launch_segment_units(const DenseSegView &d, int j, double *x, hipStream_t s) {
+void launch_segment_units(const DenseSegView &d, int j, double *xu, double *xp, hipStream_t s) {
     if (d.count <= 0) return;
-    k_segment_units<<<ceil_div(d.count, SB), SB, 0, s>>>(d, j, x);
+    k_segment_units<<<ceil_div(d.count, SB), SB, 0, s>>>(d, j, xu, xp);
     AMG_CHECK_LAUNCH();
 }
 
 // one workgroup per segment
-__global__ void k_segment_store_column(const DenseSegView d, int j, const double *x, double *inv) {
+__global__ void k_segment_store_column(const DenseSegView d, int j, const double *xu, const double *xp,
+                                       double *inv) {
     const int sg = blockIdx.x;
     const int m = d.rstart[sg + 1] - d.rstart[sg];
     if (j >= m) return;
-    for (int i = threadIdx.x; i < m; i += SB) inv[d.moff[sg] + static_cast<int64_t>(i) * m + j] = x[d.poff[sg] + i];
+    const int nu = d.nu[sg];
+    for (int i = threadIdx.x; i < m; i += SB)
+        inv[d.moff[sg] + static_cast<int64_t>(i) * m + j] = i < nu ? xu[d.uoff[sg] + i] : xp[d.poff[sg] + i - nu];
 }
 
-void launch_segment_store_column(const DenseSegView &d, int j, const double *x, double *inv, hipStream_t s) {
+void launch_segment_store_column(const DenseSegView &d, int j, const double *xu, const double *xp, double *inv,
+                                 hipStream_t s) {
     if (d.count <= 0) return;
-    k_segment_store_column<<<d.count, SB, 0, s>>>(d, j, x, inv);
+    k_segment_store_column<<<d.count, SB, 0, s>>>(d, j, xu, xp, inv);
     AMG_CHECK_LAUNCH();
 }
 

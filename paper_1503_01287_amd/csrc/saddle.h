@@ -88,10 +88,13 @@ struct DenseSegView {
 template <typename T>
 void launch_dense_segs(const DenseSegView &d, const T *xu, const T *xp, T *yu, T *yp, hipStream_t s);
 
-// x = sum over segments s with m_s > j of the unit vector at poff[s] + j
-void launch_segment_units(const DenseSegView &d, int j, double *x, hipStream_t s);
-// column j of every segment's matrix (row-major) from x: M_s[i][j] = x[poff[s] + i]
-void launch_segment_store_column(const DenseSegView &d, int j, const double *x, double *inv, hipStream_t s);
+// x = sum over segments s with m_s > j of the unit vector of the segment's
+// row j: xu[uoff[s] + j] for j < nu[s], else xp[poff[s] + j - nu[s]]
+void launch_segment_units(const DenseSegView &d, int j, double *xu, double *xp, hipStream_t s);
+// column j of every segment's matrix (row-major) from x, rows read as in
+// launch_segment_units: M_s[i][j] = x(row i of segment s)
+void launch_segment_store_column(const DenseSegView &d, int j, const double *xu, const double *xp, double *inv,
+                                 hipStream_t s);
 
 // FGMRES inner products: h[i] = <V_i, w> for i < k (V_i = V + i * ld) as
 // block partials partial[i * nb + block] (nb = multidot_blocks(n), the
