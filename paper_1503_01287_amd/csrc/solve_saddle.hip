@@ -504,57 +504,38 @@ void saddle_smooth(amg_ctx *h, int l, const double *b, double *x) { saddle_step<
 // diagonal over the systems of a batch (the smoothers, transfers and coarse
 // solves are linear; Vanka's and Braess-Sarazin's inner solves included).
 // From the first level d >= 1 on which every system has at most
-// SADDLE_TAIL_MAX rows it is assembled once, column by column from unit
+// SADDLE_TAIL_MAX rows, the GEMV would beat the cycle and the assembly fits
+// the setup budget, it is assembled once, column by column from unit
 // right-hand sides (one per system at a time) through the FP64 cycle, and
 // applied as one segmented GEMV: the same map as the launches it replaces,
-// up to rounding order, where it measures faster than those launches. Visits
+// up to rounding order, kept where it measures faster than those launches. Visits
 // of level d from a nonzero guess (the second recursion of a W-cycle) still
 // run the cycle itself. Called after the reduced-precision copies exist.
 constexpr int SADDLE_TAIL_MAX = 5000;
 constexpr double SADDLE_TAIL_BYTES_MAX = 2.0e9;
+constexpr double SADDLE_TAIL_SETUP_MS = 2000.0;
 
 void setup_saddle_tail(amg_ctx *h) {
     h->saddle_tail_from = -1;
     h->saddle_tail = DenseSegs();
     if (!h->saddle || !h->prm.fuse_coarse) return;
     const int last = static_cast<int>(h->lv.size()) - 1;
-    int d = -1;
-    for (int l = 1; l < last; ++l) {
-        Level &L = h->lv[l];
-        if (L.sys_n.empty()) {
-            L.sys_noff.assign(1, 0);
-            L.sys_n.assign(1, L.n);
-            L.sys_poff.assign(1, 0);
-            L.sys_np.assign(1, L.n_pres);
-        }
-        if (L.nA == 0) break;  // every system ends here: already one explicit solve
-        bool fits = true;
-        double bytes = 0.0;
-        for (size_t j = 0; j < L.sys_n.size(); ++j) {
-            const double m = 3.0 * L.sys_n[j] + L.sys_np[j];
-            fits &= m <= SADDLE_TAIL_MAX;
-            bytes += 8.0 * m * m;
-        }
-        if (fits && bytes <= SADDLE_TAIL_BYTES_MAX) {
-            d = l;
-            break;
-        }
-    }
-    if (d < 0) return;
-    Level &L = h->lv[d];
     hipStream_t s = h->stream;
-    // one cycle from level d, in the precision the solves use, from a zero guess
-    const int64_t nv = std::max<int64_t>(1, L.vlen()), nu = 3 * static_cast<int64_t>(L.n);
     hipEvent_t e0, e1;
     AMG_HIP(hipEventCreate(&e0));
     AMG_HIP(hipEventCreate(&e1));
-    auto time_cycle = [&]() {
-        if (h->mixed) launch_fill_f32(L.mp.b.p, 1.f, nv, s);
+    // one cycle from level d from a zero guess, FP64 or in the precision the
+    // solves use
+    auto time_cycle = [&](int d, bool fp64) {
+        Level &L = h->lv[d];
+        const int64_t nv = std::max<int64_t>(1, L.vlen());
+        const bool mp = h->mixed && !fp64;
+        if (mp) launch_fill_f32(L.mp.b.p, 1.f, nv, s);
         else launch_fill(L.b.p, 1.0, nv, s);
         float best = 1e30f;
         for (int r = 0; r < 4; ++r) {
             AMG_HIP(hipEventRecord(e0, s));
-            if (h->mixed) saddle_cycle<float>(h, d, L.mp.b.p, L.mp.x.p, true);
+            if (mp) saddle_cycle<float>(h, d, L.mp.b.p, L.mp.x.p, true);
             else saddle_cycle<double>(h, d, L.b.p, L.x.p, true);
             AMG_HIP(hipEventRecord(e1, s));
             AMG_HIP(hipEventSynchronize(e1));
@@ -564,45 +545,57 @@ void setup_saddle_tail(amg_ctx *h) {
         }
         return best;
     };
-    const float sparse_ms = time_cycle();
-    DenseSegs &T = h->saddle_tail;
-    int mmax = 0;
-    for (size_t j = 0; j < L.sys_n.size(); ++j) {
-        const int m = 3 * L.sys_n[j] + L.sys_np[j];
-        if (m == 0) continue;
-        T.add(m, 3 * L.sys_noff[j], 3 * L.sys_n[j], L.sys_poff[j]);
-        mmax = std::max(mmax, m);
+    for (int d = 1; d < last; ++d) {
+        Level &L = h->lv[d];
+        if (L.sys_n.empty()) {
+            L.sys_noff.assign(1, 0);
+            L.sys_n.assign(1, L.n);
+            L.sys_poff.assign(1, 0);
+            L.sys_np.assign(1, L.n_pres);
+        }
+        if (L.nA == 0) break;  // every system ends here: already one explicit solve
+        int mmax = 0;
+        double bytes = 0.0;
+        for (size_t j = 0; j < L.sys_n.size(); ++j) {
+            const int m = 3 * L.sys_n[j] + L.sys_np[j];
+            mmax = std::max(mmax, m);
+            bytes += 8.0 * m * static_cast<double>(m);
+        }
+        if (mmax > SADDLE_TAIL_MAX || bytes > SADDLE_TAIL_BYTES_MAX) continue;
+        // the GEMV streams the maps at no more than about 5 TB/s: assemble
+        // them only where that already beats the launches they would
+        // replace, and where the assembly (one FP64 cycle per column) stays
+        // within SADDLE_TAIL_SETUP_MS; otherwise try a coarser level
+        const float sparse_ms = time_cycle(d, false);
+        if (bytes / 5.0e9 >= 0.9 * sparse_ms) continue;
+        const float asm_ms = h->mixed ? time_cycle(d, true) : sparse_ms;
+        if (static_cast<double>(mmax) * asm_ms > SADDLE_TAIL_SETUP_MS) continue;
+        DenseSegs &T = h->saddle_tail;
+        for (size_t j = 0; j < L.sys_n.size(); ++j) {
+            const int m = 3 * L.sys_n[j] + L.sys_np[j];
+            if (m > 0) T.add(m, 3 * L.sys_noff[j], 3 * L.sys_n[j], L.sys_poff[j]);
+        }
+        T.finalize(s);
+        const DenseSegView v = T.view();
+        const int64_t nv = std::max<int64_t>(1, L.vlen()), nu = 3 * static_cast<int64_t>(L.n);
+        DevBuf<double> unit(nv), col(nv);
+        for (int j = 0; j < mmax; ++j) {
+            launch_fill(unit.p, 0.0, nv, s);
+            launch_segment_units(v, j, unit.p, unit.p + nu, s);
+            saddle_cycle<double>(h, d, unit.p, col.p, true);
+            launch_segment_store_column(v, j, col.p, col.p + nu, T.inv.p, s);
+        }
+        AMG_HIP(hipStreamSynchronize(s));
+        h->saddle_tail_from = d;
+        const float dense_ms = time_cycle(d, false);
+        if (!(dense_ms < 0.95f * sparse_ms)) {
+            h->saddle_tail_from = -1;
+            T = DenseSegs();
+        }
+        break;
     }
-    double bytes = 0.0;
-    for (int m : T.h_m) bytes += 8.0 * m * m;
-    // the GEMV streams the maps at no more than about 5 TB/s: assemble them
-    // only where that already beats the launches they would replace
-    if (bytes / 5.0e9 >= 0.9 * sparse_ms) {
-        T = DenseSegs();
-        AMG_HIP(hipEventDestroy(e0));
-        AMG_HIP(hipEventDestroy(e1));
-        return;
-    }
-    T.finalize(s);
-    const DenseSegView v = T.view();
-    DevBuf<double> unit(nv), col(nv);
-    for (int j = 0; j < mmax; ++j) {
-        launch_fill(unit.p, 0.0, nv, s);
-        launch_segment_units(v, j, unit.p, unit.p + nu, s);
-        saddle_cycle<double>(h, d, unit.p, col.p, true);
-        launch_segment_store_column(v, j, col.p, col.p + nu, T.inv.p, s);
-    }
-    AMG_HIP(hipStreamSynchronize(s));
-    h->saddle_tail_from = d;
-    const float dense_ms = time_cycle();
     AMG_HIP(hipEventDestroy(e0));
     AMG_HIP(hipEventDestroy(e1));
-    if (!(dense_ms < 0.95f * sparse_ms)) {
-        h->saddle_tail_from = -1;
-        T = DenseSegs();
-        return;
-    }
-    h->saddle_tail_from = d;
 }
 
 

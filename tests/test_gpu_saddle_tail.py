@@ -38,10 +38,15 @@ def _rel(a, b):
 @pytest.mark.parametrize("smoother,precision,tol", [
     ("sGS-1-1", "FP64", 1e-11), ("BS-1-1", "FP64", 1e-11), ("Vanka-1-1", "FP64", 1e-11),
     ("sGS-2-2", "FP64", 1e-11), ("sGS-1-1", "MIXED", 2e-4), ("BS-1-1", "FP32", 2e-4)])
-@pytest.mark.parametrize("make", [lambda: amg.problems.mixed_elasticity(8),
-                                  lambda: amg.problems.stokes_cavity(6, 1.1)], ids=["mixed8", "cavity6"])
-def test_tail_is_the_cycle(make, smoother, precision, tol):
-    sysm = make()
+@pytest.mark.parametrize("kind", ["mixed", "cavity"])
+def test_tail_is_the_cycle(kind, smoother, precision, tol):
+    # Vanka's cycle is the costliest to assemble (one cycle per column):
+    # smaller systems keep its assembly inside the setup budget
+    small = smoother.startswith("Vanka")
+    if kind == "mixed":
+        sysm = amg.problems.mixed_elasticity(5 if small else 8)
+    else:
+        sysm = amg.problems.stokes_cavity(4 if small else 6, 1.1)
     kw = dict(smoother=smoother, krylov="FGMRES", precision=precision)
     fused = amg.AMGSolver(sysm, fuse_coarse=True, **kw)
     plain = amg.AMGSolver(sysm, fuse_coarse=False, **kw)
