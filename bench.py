@@ -177,6 +177,9 @@ def main() -> int:
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the event-timed pass")
+    ap.add_argument("--only-timed", action="store_true",
+                    help="for profiler runs: only the timed variant (no FP64 or unbatched comparison, no "
+                         "reference solve, so no error figures)")
     ap.add_argument("--precision", default="MIXED", choices=["MIXED", "FP32", "FP64"],
                     help="cycle arithmetic of the timed solve (FP64 outer loop always; the Stokes batch "
                          "uses FP32 unless FP64 is asked for); the plain FP64 solve is timed beside it")
@@ -290,16 +293,17 @@ def main() -> int:
         solver.close()
         return out
 
+    full = not args.only_timed
     if saddle:
         prim = run_variant(precision, "FGMRES", not args.no_profile)
-        comp = run_variant("FP64", "FGMRES", False) if precision != "FP64" else None
+        comp = run_variant("FP64", "FGMRES", False) if precision != "FP64" and full else None
     else:
         primary_kry = "PCG" if precision == "FP64" else "FCG"
         prim = run_variant(precision, primary_kry, not args.no_profile, with_model=use_model)
-        comp = run_variant("FP64", "PCG", False) if (precision != "FP64" or use_model) else None
+        comp = run_variant("FP64", "PCG", False) if (precision != "FP64" or use_model) and full else None
     # the same systems solved one after another (batch only), once
     unbatched = None
-    if batch:
+    if batch and full:
         t_all, its = 0.0, []
         for s_ in sysm.systems:
             single = amg.AMGSolver(s_, smoother=wl["smoother"], krylov="FGMRES", precision=precision)
@@ -321,36 +325,39 @@ def main() -> int:
         print(f"# unbatched: {t_all * 1e3:.1f} ms for all systems", file=sys.stderr, flush=True)
 
     # reference solution for the error of each variant: FP64 to 1e-12 (untimed)
-    ref_solver = make("FP64", "FGMRES" if saddle else "PCG", False)
-    solve_once(ref_solver, 1e-12)
-    ref = x.clone()
-    ref_res = solve_once(ref_solver, 1e-12)
-    ref_solver.close()
-    ref_iters = ref_res[1]
+    ref_iters = None
+    prim["error_vs_fp64_reference"] = None
+    if full:
+        ref_solver = make("FP64", "FGMRES" if saddle else "PCG", False)
+        solve_once(ref_solver, 1e-12)
+        ref = x.clone()
+        ref_res = solve_once(ref_solver, 1e-12)
+        ref_solver.close()
+        ref_iters = ref_res[1]
 
-    def centred(v):
-        """Pressure of systems with constants in the pressure kernel taken with zero mean."""
-        if not saddle:
+        def centred(v):
+            """Pressure of systems with constants in the pressure kernel taken with zero mean."""
+            if not saddle:
+                return v
+            v = v.clone()
+            systems = sysm.systems if batch else [sysm]
+            o = 0
+            for s_ in systems:
+                if s_.pressure_kernel:
+                    nu = 3 * s_.nodes
+                    p_ = v[o + nu:o + s_.dofs]
+                    p_ -= p_.mean()
+                o += s_.dofs
             return v
-        v = v.clone()
-        systems = sysm.systems if batch else [sysm]
-        o = 0
-        for s_ in systems:
-            if s_.pressure_kernel:
-                nu = 3 * s_.nodes
-                p_ = v[o + nu:o + s_.dofs]
-                p_ -= p_.mean()
-            o += s_.dofs
-        return v
 
-    refc = centred(ref)
+        refc = centred(ref)
 
-    def err(v):
-        return float(torch.linalg.norm(centred(v["solution"]) - refc) / torch.linalg.norm(refc))
+        def err(v):
+            return float(torch.linalg.norm(centred(v["solution"]) - refc) / torch.linalg.norm(refc))
 
-    prim["error_vs_fp64_reference"] = err(prim)
-    if comp:
-        comp["error_vs_fp64_reference"] = err(comp)
+        prim["error_vs_fp64_reference"] = err(prim)
+        if comp:
+            comp["error_vs_fp64_reference"] = err(comp)
     ms, value, iters = prim["ms_per_step"], prim["value"], prim["iterations"]
     roofline = prim.get("roofline")
     vcycle = prim.get("vcycle_bandwidth")

@@ -55,6 +55,7 @@ struct DenseSegs {
     DevBuf<int64_t> moff;
     DevBuf<int> rstart, uoff, nu, poff;
     DevBuf<double> inv;
+    DevBuf<float> inv32;  // FP32 copy for FP32 cycles (assembled maps only)
     double bytes = 0.0;  // matrix bytes read per application
     void add(int m, int uoff_, int nu_, int poff_) {
         h_moff.push_back(h_moff.empty() ? 0 : h_moff.back() + static_cast<int64_t>(h_m.back()) * h_m.back());
@@ -64,6 +65,7 @@ struct DenseSegs {
         h_poff.push_back(poff_);
     }
     void finalize(hipStream_t s);  // upload the tables, allocate inv
+    void make_f32(hipStream_t s);  // inv32 from inv (FP32 cycles then read it)
     DenseSegView view() const {
         DenseSegView v;
         v.count = count;
@@ -74,6 +76,7 @@ struct DenseSegs {
         v.nu = nu.p;
         v.poff = poff.p;
         v.inv = inv.p;
+        v.inv32 = inv32.n ? inv32.p : nullptr;
         return v;
     }
 };

@@ -28,6 +28,12 @@ void DenseSegs::finalize(hipStream_t s) {
     inv.alloc(count ? static_cast<size_t>(h_moff.back() + static_cast<int64_t>(h_m.back()) * h_m.back()) : 0);
 }
 
+void DenseSegs::make_f32(hipStream_t s) {
+    inv32.alloc(inv.n);
+    if (inv.n) launch_to_f32(inv.p, inv32.p, static_cast<int64_t>(inv.n), s);
+    bytes *= 0.5;
+}
+
 static void upload_pattern(DMat &m, const HostCSR &h, hipStream_t s) {
     m.nrows = h.nrows;
     m.ncols = h.ncols;

@@ -2,6 +2,7 @@
 // are bandwidth bound: B holds 1x3 blocks (28 bytes per entry in FP64), C
 // scalars (12 bytes); the vectors they gather are small.
 #include <algorithm>
+#include <type_traits>
 
 #include "common.h"
 #include "saddle.h"
@@ -333,8 +334,9 @@ void launch_axpby_f(float *y, const float *x, float a, float b, int64_t n, hipSt
 // ---------------------------------------------------------------- dense segments
 // one wavefront per output row over all segments; lanes stride the columns;
 // FP64 inverse and accumulation whatever the vector type
-template <typename T>
-__global__ void __launch_bounds__(SB) k_dense_segs(const DenseSegView d, const T *xu, const T *xp, T *yu, T *yp) {
+template <typename T, typename M>
+__global__ void __launch_bounds__(SB) k_dense_segs(const DenseSegView d, const M *mat, const T *xu, const T *xp,
+                                                   T *yu, T *yp) {
     const int r = blockIdx.x * (SB / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (r >= d.rows) return;
@@ -349,9 +351,19 @@ __global__ void __launch_bounds__(SB) k_dense_segs(const DenseSegView d, const T
     const int i = r - d.rstart[sg];
     const int nu = d.nu[sg];
     const T *xus = xu + d.uoff[sg], *xps = xp + d.poff[sg];
-    const double *row = d.inv + d.moff[sg] + static_cast<int64_t>(i) * m;
+    const M *row = mat + d.moff[sg] + static_cast<int64_t>(i) * m;
     double acc = 0.0;
-    for (int j = lane; j < m; j += 64) acc += row[j] * static_cast<double>(j < nu ? xus[j] : xps[j - nu]);
+    // four entries per lane and trip keep four row loads in flight
+    int j = lane;
+    for (; j + 192 < m; j += 256) {
+        const double a0 = row[j], a1 = row[j + 64], a2 = row[j + 128], a3 = row[j + 192];
+        const int j1 = j + 64, j2 = j + 128, j3 = j + 192;
+        acc += a0 * static_cast<double>(j < nu ? xus[j] : xps[j - nu]);
+        acc += a1 * static_cast<double>(j1 < nu ? xus[j1] : xps[j1 - nu]);
+        acc += a2 * static_cast<double>(j2 < nu ? xus[j2] : xps[j2 - nu]);
+        acc += a3 * static_cast<double>(j3 < nu ? xus[j3] : xps[j3 - nu]);
+    }
+    for (; j < m; j += 64) acc += static_cast<double>(row[j]) * static_cast<double>(j < nu ? xus[j] : xps[j - nu]);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
     if (lane == 0) {
@@ -363,7 +375,11 @@ __global__ void __launch_bounds__(SB) k_dense_segs(const DenseSegView d, const T
 template <typename T>
 void launch_dense_segs(const DenseSegView &d, const T *xu, const T *xp, T *yu, T *yp, hipStream_t s) {
     if (d.count <= 0 || d.rows <= 0) return;
-    k_dense_segs<T><<<ceil_div(d.rows, SB / 64), SB, 0, s>>>(d, xu, xp, yu, yp);
+    const int nb = ceil_div(d.rows, SB / 64);
+    if (std::is_same<T, float>::value && d.inv32)
+        k_dense_segs<T, float><<<nb, SB, 0, s>>>(d, d.inv32, xu, xp, yu, yp);
+    else
+        k_dense_segs<T, double><<<nb, SB, 0, s>>>(d, d.inv, xu, xp, yu, yp);
     AMG_CHECK_LAUNCH();
 }
 template void launch_dense_segs<double>(const DenseSegView &, const double *, const double *, double *, double *,

@@ -82,9 +82,11 @@ struct DenseSegView {
     const int64_t *moff = nullptr;
     const int *rstart = nullptr, *uoff = nullptr, *nu = nullptr, *poff = nullptr;
     const double *inv = nullptr;
+    const float *inv32 = nullptr;  // FP32 copy of inv, or null
 };
 // y = M_s x on every segment (x and y: u parts xu/yu, p parts xp/yp); the
-// inverses stay FP64 and so does the accumulation, also for FP32 vectors
+// accumulation is FP64; FP32 vectors use the FP32 copy of the matrices when
+// there is one (assembled coarse-end maps), else the FP64 matrices
 template <typename T>
 void launch_dense_segs(const DenseSegView &d, const T *xu, const T *xp, T *yu, T *yp, hipStream_t s);
 

@@ -177,6 +177,8 @@ void build_saddle_mp(amg_ctx *h) {
         if (L.sgs_scale.n) conv(M.sgs, L.sgs_scale);
         if (L.bs_ahat.n) conv(M.ahat, L.bs_ahat);
         if (L.nA > 0 && M.dinv.n == 0) conv(M.dinv, L.dinv);
+        // assembled Schur coarse ends: FP32 copies for the FP32 cycle
+        if (L.schur.dense_from >= 0 && L.schur.tdense.inv32.n == 0) L.schur.tdense.make_f32(s);
         for (SchurLevel &q : L.schur.lv) {
             conv(q.s32, q.S.val);
             if (q.dinv.n) conv(q.dinv32, q.dinv);

@@ -567,7 +567,8 @@ void setup_saddle_tail(amg_ctx *h) {
         // replace, and where the assembly (one FP64 cycle per column) stays
         // within SADDLE_TAIL_SETUP_MS; otherwise try a coarser level
         const float sparse_ms = time_cycle(d, false);
-        if (bytes / 5.0e9 >= 0.9 * sparse_ms) continue;
+        const double gemv_bytes = h->mixed ? 0.5 * bytes : bytes;  // FP32 copy in FP32 cycles
+        if (gemv_bytes / 5.0e9 >= 0.9 * sparse_ms) continue;
         const float asm_ms = h->mixed ? time_cycle(d, true) : sparse_ms;
         if (static_cast<double>(mmax) * asm_ms > SADDLE_TAIL_SETUP_MS) continue;
         DenseSegs &T = h->saddle_tail;
@@ -585,6 +586,7 @@ void setup_saddle_tail(amg_ctx *h) {
             saddle_cycle<double>(h, d, unit.p, col.p, true);
             launch_segment_store_column(v, j, col.p, col.p + nu, T.inv.p, s);
         }
+        if (h->mixed) T.make_f32(s);  // the FP32 cycle reads an FP32 copy
         AMG_HIP(hipStreamSynchronize(s));
         h->saddle_tail_from = d;
         const float dense_ms = time_cycle(d, false);
