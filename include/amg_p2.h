@@ -196,7 +196,7 @@ typedef struct {
     int32_t gs_xcd;                /* 1 if the colour sweeps give each XCD one
                                       contiguous eighth of a colour's rows    */
     int32_t pair_A, pair_gs;       /* 1 if those kernels take two entries per
-                                      lane and loop trip (reduced precision)  */
+                                      lane and loop trip                      */
 } amg_level_info;
 
 /* Fill *p with the defaults listed above. */

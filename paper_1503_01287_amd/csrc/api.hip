@@ -273,8 +273,8 @@ int amg_get_level_info(amg_handle h, int32_t level, amg_level_info *info) {
         info->is_coarsest = L.coarsest ? 1 : 0;
         info->lanes_A = h->mixed ? L.mp.G : L.G;
         info->lanes_gs = h->mixed ? L.mp.Gg : L.Gg;
-        info->pair_A = h->mixed ? L.mp.pair : 0;
-        info->pair_gs = h->mixed ? L.mp.pairg : 0;
+        info->pair_A = h->mixed ? L.mp.pair : L.pair;
+        info->pair_gs = h->mixed ? L.mp.pairg : L.pairg;
         const int fs = h->tail_start >= 0 ? h->tail_start
                        : h->dense_start >= 0 ? h->dense_start
                                              : h->saddle_tail_from;

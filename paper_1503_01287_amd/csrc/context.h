@@ -148,6 +148,7 @@ struct Level {
     DevBuf<double> x, b, r, t;
     int G = 16, Gg = 16, Gp = 4, Gr = 8;  // lanes per row: A, grouped A, P, R
     int gs_xcd = 0;           // colour sweeps with one contiguous eighth of the rows per XCD
+    int pair = 0, pairg = 0;  // two entries per lane and trip (natural-order / colour kernels)
     LevelMP mp;               // mixed-precision copy (AMG_PREC_MIXED / FP32)
     // saddle point levels (n_pres > 0); vectors are [u (3n); p (n_pres)]
     DMat B, Bt, C;            // B: n_pres x n (1x3), Bt: n x n_pres (3x1), C: n_pres^2 (may be empty)

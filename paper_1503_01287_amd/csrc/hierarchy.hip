@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <numeric>
+#include <tuple>
 
 #include "context.h"
 
@@ -254,19 +255,21 @@ static void autotune_level(amg_ctx *h, Level &L) {
     // candidate replaces only when it is at least 5% faster: timing noise
     // then does not flip the choice from one setup to the next.
     auto pick = [&](int G0, auto &&time_of) {
-        int bestG = G0;
-        float best = time_of(G0);
-        for (int G : cand) {
-            if (G == G0) continue;
-            const float ms = time_of(G);
-            if (ms < 0.95f * best) {
-                best = ms;
-                bestG = G;
+        int bestG = G0, bestP = 0;
+        float best = time_of(G0, 0);
+        for (int P = 0; P < 2; ++P)
+            for (int G : cand) {
+                if (G == G0 && P == 0) continue;
+                const float ms = time_of(G, P);
+                if (ms < 0.95f * best) {
+                    best = ms;
+                    bestG = G;
+                    bestP = P;
+                }
             }
-        }
-        return std::make_pair(bestG, best);
+        return std::make_tuple(bestG, bestP, best);
     };
-    L.G = pick(L.G, [&](int G) {
+    std::tie(L.G, L.pair, std::ignore) = pick(L.G, [&](int G, int P) {
         RowArgs a;
         a.nrows = L.n;
         a.rowptr = L.A.rowptr.p;
@@ -276,12 +279,13 @@ static void autotune_level(amg_ctx *h, Level &L) {
         a.x = L.x.p;
         a.b = L.b.p;
         a.y = L.r.p;
+        a.pair = P;
         return time_it([&] { launch_row(L.mode, OP_RESID, G, a, s); });
-    }).first;
+    });
     if (!L.cptr.empty()) {
         // a whole forward sweep, colour by colour, as the smoother runs it,
         // with round-robin or per-XCD contiguous workgroup placement
-        auto sweep_time = [&](int G, int xcd) {
+        auto sweep_time = [&](int G, int P, int xcd) {
             return time_it([&] {
                 for (size_t c = 0; c + 1 < L.cptr.size(); ++c) {
                     if (L.cptr[c + 1] == L.cptr[c]) continue;
@@ -298,18 +302,14 @@ static void autotune_level(amg_ctx *h, Level &L) {
                     a.dinv = L.dinv.p;
                     a.dinv_n = L.n;
                     a.xcd_chunks = xcd;
+                    a.pair = P;
                     launch_row(L.mode, OP_GS, G, a, s);
                 }
             });
         };
-        const auto rr = pick(L.Gg, [&](int G) { return sweep_time(G, 0); });
-        const auto xc = pick(rr.first, [&](int G) { return sweep_time(G, 1); });
-        L.Gg = rr.first;
-        L.gs_xcd = 0;
-        if (xc.second < 0.95f * rr.second) {
-            L.Gg = xc.first;
-            L.gs_xcd = 1;
-        }
+        float rr_ms = 0.f;
+        std::tie(L.Gg, L.pairg, rr_ms) = pick(L.Gg, [&](int G, int P) { return sweep_time(G, P, 0); });
+        L.gs_xcd = sweep_time(L.Gg, L.pairg, 1) < 0.95f * rr_ms ? 1 : 0;
     }
     AMG_HIP(hipEventDestroy(e0));
     AMG_HIP(hipEventDestroy(e1));

@@ -38,7 +38,25 @@ __device__ __forceinline__ double block_sum(double v) {
     return t;
 }
 
-template <int MODE, int G, int OP>
+// s += A_k x_j for entry k (a 3x3 block of nine planes, or a scalar that
+// multiplies every component)
+template <int MODE>
+__device__ __forceinline__ void acc_entry(const double *val, int64_t nz, int k, double x0, double x1, double x2,
+                                          double &s0, double &s1, double &s2) {
+    if constexpr (MODE == 3) {
+        const double *v = val + k;
+        s0 += v[0] * x0 + v[nz] * x1 + v[2 * nz] * x2;
+        s1 += v[3 * nz] * x0 + v[4 * nz] * x1 + v[5 * nz] * x2;
+        s2 += v[6 * nz] * x0 + v[7 * nz] * x1 + v[8 * nz] * x2;
+    } else {
+        const double v = val[k];
+        s0 += v * x0;
+        s1 += v * x1;
+        s2 += v * x2;
+    }
+}
+
+template <int MODE, int G, int OP, bool PAIR>
 __global__ void __launch_bounds__(BLOCK) k_row(const RowArgs a) {
     // Workgroups are dispatched round-robin over the 8 XCDs, so consecutive
     // row blocks run on different XCDs at the same time and the whole chip
@@ -82,22 +100,23 @@ __global__ void __launch_bounds__(BLOCK) k_row(const RowArgs a) {
     if (active) {
         const int beg = a.rowptr[g], end = a.rowptr[g + 1];
         const int64_t nz = a.nnz;
-        // (a two-entries-per-trip variant measured slower on gfx950: the
-        // extra registers cost more occupancy than the overlap gained)
-        for (int k = beg + lane; k < end; k += G) {
+        int k = beg + lane;
+        if constexpr (PAIR) {
+            // two entries per trip: both column indices, then both gathers
+            // of x, in flight together (long rows on few lanes; the tuner
+            // picks this form only where it measures faster)
+            for (; k + G < end; k += 2 * G) {
+                const int j = a.col[k], jb = a.col[k + G];
+                const double x0 = a.x[3 * j], x1 = a.x[3 * j + 1], x2 = a.x[3 * j + 2];
+                const double y0 = a.x[3 * jb], y1 = a.x[3 * jb + 1], y2 = a.x[3 * jb + 2];
+                acc_entry<MODE>(a.val, nz, k, x0, x1, x2, s0, s1, s2);
+                acc_entry<MODE>(a.val, nz, k + G, y0, y1, y2, s0, s1, s2);
+            }
+        }
+        for (; k < end; k += G) {
             const int j = a.col[k];
             const double x0 = a.x[3 * j], x1 = a.x[3 * j + 1], x2 = a.x[3 * j + 2];
-            if constexpr (MODE == 3) {
-                const double *v = a.val + k;
-                s0 += v[0] * x0 + v[nz] * x1 + v[2 * nz] * x2;
-                s1 += v[3 * nz] * x0 + v[4 * nz] * x1 + v[5 * nz] * x2;
-                s2 += v[6 * nz] * x0 + v[7 * nz] * x1 + v[8 * nz] * x2;
-            } else {
-                const double v = a.val[k];
-                s0 += v * x0;
-                s1 += v * x1;
-                s2 += v * x2;
-            }
+            acc_entry<MODE>(a.val, nz, k, x0, x1, x2, s0, s1, s2);
         }
     }
     s0 = group_sum<G>(s0);
@@ -150,14 +169,21 @@ static void launch_row_g(RowOp op, const RowArgs &a, hipStream_t s) {
         AMG_REQUIRE(op != OP_SPMV_DOT, AMG_EINVAL, "row kernel: XCD chunks with block partials");
         nb = (nb + 7) / 8 * 8;
     }
+    const bool pair = a.pair != 0;
+#define AMG_ROW_CASE(OPC)                                                       \
+    case OPC:                                                                   \
+        if (pair) k_row<MODE, G, OPC, true><<<nb, BLOCK, 0, s>>>(a);             \
+        else k_row<MODE, G, OPC, false><<<nb, BLOCK, 0, s>>>(a);                 \
+        break;
     switch (op) {
-        case OP_SPMV: k_row<MODE, G, OP_SPMV><<<nb, BLOCK, 0, s>>>(a); break;
-        case OP_SPMV_ADD: k_row<MODE, G, OP_SPMV_ADD><<<nb, BLOCK, 0, s>>>(a); break;
-        case OP_RESID: k_row<MODE, G, OP_RESID><<<nb, BLOCK, 0, s>>>(a); break;
-        case OP_JACOBI: k_row<MODE, G, OP_JACOBI><<<nb, BLOCK, 0, s>>>(a); break;
-        case OP_GS: k_row<MODE, G, OP_GS><<<nb, BLOCK, 0, s>>>(a); break;
-        case OP_SPMV_DOT: k_row<MODE, G, OP_SPMV_DOT><<<nb, BLOCK, 0, s>>>(a); break;
+        AMG_ROW_CASE(OP_SPMV)
+        case OP_SPMV_ADD: k_row<MODE, G, OP_SPMV_ADD, false><<<nb, BLOCK, 0, s>>>(a); break;
+        AMG_ROW_CASE(OP_RESID)
+        AMG_ROW_CASE(OP_JACOBI)
+        AMG_ROW_CASE(OP_GS)
+        AMG_ROW_CASE(OP_SPMV_DOT)
     }
+#undef AMG_ROW_CASE
     AMG_CHECK_LAUNCH();
 }
 

@@ -126,6 +126,7 @@ static void a_resid(amg_ctx *h, int l, const double *b, const double *x, double 
     a.b = b;
     a.y = r;
     ProfScope ps(h, tag("resid", l), static_cast<double>(L.A.nnz) * 76.0 + L.n * 76.0);
+    a.pair = L.pair;
     launch_row(3, OP_RESID, L.G, a, h->stream);
 }
 static void a_resid(amg_ctx *h, int l, const float *b, const float *x, float *r, int nrows) {
@@ -239,6 +240,7 @@ void saddle_apply(amg_ctx *h, int l, const double *x, double *y) {
         a.x = x;
         a.y = y;
         ProfScope ps(h, tag("spmv", l), static_cast<double>(L.A.nnz) * 76.0 + L.n * 52.0);
+        a.pair = L.pair;
         launch_row(3, OP_SPMV, L.G, a, h->stream);
     }
     BlkArgs bt = blk(L.Bt);
