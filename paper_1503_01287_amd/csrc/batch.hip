@@ -308,6 +308,10 @@ void build_batch(amg_ctx *h, int nsys, const amg_system *sys) {
         M.t.alloc(nv);
     }
     AMG_HIP(hipStreamSynchronize(s));
+    // the merged levels' kernels see other shapes than the systems' own
+    if (p.autotune)
+        for (Level &M : merged)
+            if (M.nA > 0) autotune_level(h, M);
 
     // level-0 layout of every system, chunk tables
     h->nsys = nsys;

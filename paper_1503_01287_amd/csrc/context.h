@@ -293,6 +293,8 @@ double jacobi_omega(const amg_ctx *h, int l);
 void setup_tail(amg_ctx *h);
 // lanes per row for a row kernel from the mean entries per row (4..64)
 int lanes_for(int64_t nnz, int nrows);
+// setup-time tuner of a level's FP64 kernels (lanes, loop form, XCD placement)
+void autotune_level(amg_ctx *h, Level &L);
 // FP32 copy of the assembled coarse-end operator (reduced-precision cycle)
 void refresh_tail_f32(amg_ctx *h);
 void saddle_precondition(amg_ctx *h, const double *r, double *z);

@@ -9,6 +9,7 @@
 #include <tuple>
 
 #include "context.h"
+#include "saddle.h"
 
 namespace amgp2 {
 
@@ -226,7 +227,7 @@ static void setup_smoother(amg_ctx *h, Level &L) {
 // Autotuner: lanes per row for the level's row kernels, measured with HIP
 // events on the level's own operators (residual on the natural rows, one
 // Gauss-Seidel launch on the largest colour). Runs on scratch vectors.
-static void autotune_level(amg_ctx *h, Level &L) {
+void autotune_level(amg_ctx *h, Level &L) {
     hipStream_t s = h->stream;
     const int cand[] = {8, 16, 32, 64};
     hipEvent_t e0, e1;
@@ -310,6 +311,46 @@ static void autotune_level(amg_ctx *h, Level &L) {
         float rr_ms = 0.f;
         std::tie(L.Gg, L.pairg, rr_ms) = pick(L.Gg, [&](int G, int P) { return sweep_time(G, P, 0); });
         L.gs_xcd = sweep_time(L.Gg, L.pairg, 1) < 0.95f * rr_ms ? 1 : 0;
+    }
+    if (L.n_pres > 0 && L.B.nnz > 0) {
+        // saddle levels: lanes of the B (1x3, pressure rows) and B^T (3x1,
+        // velocity rows) kernels, same rule (heuristic kept unless >= 5% slower)
+        const int64_t nu = 3 * static_cast<int64_t>(L.n);
+        launch_fill(L.x.p, 0.0, L.vlen(), s);
+        launch_fill(L.b.p, 1.0, L.vlen(), s);
+        const int gcand[] = {4, 8, 16, 32, 64};
+        auto pick_g = [&](int G0, auto &&time_of) {
+            int bestG = G0;
+            float best = time_of(G0);
+            for (int G : gcand) {
+                if (G == G0) continue;
+                const float ms = time_of(G);
+                if (ms < 0.95f * best) {
+                    best = ms;
+                    bestG = G;
+                }
+            }
+            return bestG;
+        };
+        BlkArgs bb;
+        bb.nrows = L.B.nrows;
+        bb.rowptr = L.B.rowptr.p;
+        bb.col = L.B.col.p;
+        bb.val = L.B.val.p;
+        bb.nnz = L.B.nnz;
+        bb.x = L.x.p;
+        bb.b = L.b.p + nu;
+        bb.y = L.r.p + nu;
+        L.Gb = pick_g(L.Gb, [&](int G) { return time_it([&] { launch_blk<double>(1, 3, BLK_RESID, G, bb, s); }); });
+        BlkArgs bt;
+        bt.nrows = L.Bt.nrows;
+        bt.rowptr = L.Bt.rowptr.p;
+        bt.col = L.Bt.col.p;
+        bt.val = L.Bt.val.p;
+        bt.nnz = L.Bt.nnz;
+        bt.x = L.x.p + nu;
+        bt.y = L.r.p;
+        L.Gbt = pick_g(L.Gbt, [&](int G) { return time_it([&] { launch_blk<double>(3, 1, BLK_ADD, G, bt, s); }); });
     }
     AMG_HIP(hipEventDestroy(e0));
     AMG_HIP(hipEventDestroy(e1));

@@ -24,12 +24,23 @@ __global__ void __launch_bounds__(SB) k_blk(const BlkArgsT<T> a) {
     const int i = static_cast<int>(t / G);
     const int lane = static_cast<int>(t % G);
     const bool active = i < a.nrows;
+    // the epilogue's row-local operands are loaded before the row's entries
+    // so that their latency overlaps the row
+    const bool ep = active && lane < BR;
+    const int64_t o = static_cast<int64_t>(BR) * i + (ep ? lane : 0);
+    T bo = T(0), yo = T(0), ds = T(0);
+    if (ep) {
+        if constexpr (OP == BLK_RESID || OP == BLK_SGS_P) bo = a.b[o];
+        if constexpr (OP == BLK_ADD || OP == BLK_SUB || OP == BLK_SGS_P) yo = a.y[o];
+        if constexpr (OP == BLK_SGS_P) ds = a.dscale[i];
+    }
     T s[BR];
 #pragma unroll
     for (int r = 0; r < BR; ++r) s[r] = T(0);
     if (active) {
         const int64_t nz = a.nnz;
-        for (int k = a.rowptr[i] + lane; k < a.rowptr[i + 1]; k += G) {
+        const int beg = a.rowptr[i], end = a.rowptr[i + 1];
+        for (int k = beg + lane; k < end; k += G) {
             const int j = a.col[k];
             T xv[BC];
 #pragma unroll
@@ -42,18 +53,17 @@ __global__ void __launch_bounds__(SB) k_blk(const BlkArgsT<T> a) {
     }
 #pragma unroll
     for (int r = 0; r < BR; ++r) s[r] = gsum<G>(s[r]);
-    if (!active || lane >= BR) return;
+    if (!ep) return;
     const int r = lane;
     T sv = s[0];
 #pragma unroll
     for (int q = 1; q < BR; ++q)
         if (r == q) sv = s[q];
-    const int64_t o = static_cast<int64_t>(BR) * i + r;
     if constexpr (OP == BLK_SPMV) a.y[o] = sv;
-    else if constexpr (OP == BLK_ADD) a.y[o] += sv;
-    else if constexpr (OP == BLK_SUB) a.y[o] -= sv;
-    else if constexpr (OP == BLK_RESID) a.y[o] = a.b[o] - sv;
-    else a.y[o] += a.omega * a.dscale[i] * (sv - a.b[o]);
+    else if constexpr (OP == BLK_ADD) a.y[o] = yo + sv;
+    else if constexpr (OP == BLK_SUB) a.y[o] = yo - sv;
+    else if constexpr (OP == BLK_RESID) a.y[o] = bo - sv;
+    else a.y[o] = yo + a.omega * ds * (sv - bo);
 }
 
 template <typename T, int BR, int BC, int G>
