@@ -276,6 +276,7 @@ void build_batch(amg_ctx *h, int nsys, const amg_system *sys) {
                 }
                 if (order_rows.empty()) order_rows.push_back(0);
                 Q.rowid.upload(order_rows, s);
+                group_schur_rows(Q, s);
                 for (size_t j = 0; j < R.size(); ++j)
                     if (depth[R[j]] == l + k) Q.dseg.add(rows[j], 0, 0, off[j]);
                 if (!Q.dseg.h_m.empty()) {

@@ -92,8 +92,9 @@ struct SchurLevel {
     DevBuf<double> dinv;         // 1 / S_ii
     std::vector<int> cptr;       // rows of colour c: rowid[cptr[c] .. cptr[c+1])
     DevBuf<int> rowid;
+    DMat Sg;                     // the smoothed rows of S in the order rowid (colour sweeps)
     DevBuf<double> x, b, r;
-    DevBuf<float> s32, dinv32, x32, b32, r32;  // reduced-precision cycle
+    DevBuf<float> s32, sg32, dinv32, x32, b32, r32;  // reduced-precision cycle
     int G = 8;
 };
 
@@ -295,6 +296,8 @@ void setup_tail(amg_ctx *h);
 int lanes_for(int64_t nnz, int nrows);
 // setup-time tuner of a level's FP64 kernels (lanes, loop form, XCD placement)
 void autotune_level(amg_ctx *h, Level &L);
+// q.Sg from q.S, q.rowid and q.cptr
+void group_schur_rows(SchurLevel &q, hipStream_t s);
 // FP32 copy of the assembled coarse-end operator (reduced-precision cycle)
 void refresh_tail_f32(amg_ctx *h);
 void saddle_precondition(amg_ctx *h, const double *r, double *z);

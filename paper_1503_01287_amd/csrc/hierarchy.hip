@@ -227,6 +227,28 @@ static void setup_smoother(amg_ctx *h, Level &L) {
 // Autotuner: lanes per row for the level's row kernels, measured with HIP
 // events on the level's own operators (residual on the natural rows, one
 // Gauss-Seidel launch on the largest colour). Runs on scratch vectors.
+// Copy of a Schur level's smoothed rows grouped by colour (rows in the order
+// rowid), so that a colour sweep reads its rows' pointers by position,
+// together with the row ids, instead of after them.
+void group_schur_rows(SchurLevel &q, hipStream_t s) {
+    const int m = q.cptr.empty() ? 0 : q.cptr.back();
+    q.Sg = DMat();
+    q.Sg.np = 1;
+    q.Sg.nrows = m;
+    q.Sg.ncols = q.S.ncols;
+    if (m == 0) return;
+    const std::vector<int> rp = q.S.rowptr.download(s), order = q.rowid.download(s);
+    std::vector<int> grp(m + 1, 0);
+    for (int g = 0; g < m; ++g) grp[g + 1] = grp[g] + rp[order[g] + 1] - rp[order[g]];
+    q.Sg.nnz = grp[m];
+    q.Sg.rowptr.upload(grp, s);
+    q.Sg.col.alloc(std::max<int64_t>(1, q.Sg.nnz));
+    q.Sg.val.alloc(std::max<int64_t>(1, q.Sg.nnz));
+    launch_gather_rows(1, m, q.rowid.p, q.S.rowptr.p, q.S.col.p, q.S.val.p, q.S.nnz, q.Sg.rowptr.p, q.Sg.col.p,
+                       q.Sg.val.p, s);
+    AMG_HIP(hipStreamSynchronize(s));
+}
+
 void autotune_level(amg_ctx *h, Level &L) {
     hipStream_t s = h->stream;
     const int cand[] = {8, 16, 32, 64};
@@ -595,6 +617,7 @@ void setup_schur(amg_ctx *h, int l) {
         std::vector<int> order(std::max(1, n)), next(q.cptr.begin(), q.cptr.end() - 1);
         for (int i = 0; i < n; ++i) order[next[colour[i]]++] = i;
         q.rowid.upload(order, s);
+        group_schur_rows(q, s);
         q.dinv.alloc(std::max(1, n));
         DevBuf<int> flag(1);
         flag.zero(s);

@@ -278,20 +278,31 @@ void launch_schur_numeric(int np, const int *brow, const int *bcol, const double
 template <typename T, int G>
 __global__ void __launch_bounds__(SB) k_scalar_gs(int nrows, const int *rowptr, const int *col, const T *val,
                                                   const int *rowid, const T *dinv, const T *b, T *x) {
+    // rows of one colour grouped (row g of the launch: entries rowptr[g] ..
+    // rowptr[g+1], node rowid[g]); the row pointers and the row id load
+    // together, the right-hand side and diagonal with the row's entries
     const int64_t t = static_cast<int64_t>(blockIdx.x) * SB + threadIdx.x;
     const int g = static_cast<int>(t / G);
     const int lane = static_cast<int>(t % G);
     const bool active = g < nrows;
-    const int i = active ? rowid[g] : 0;
-    T s = T(0);
-    if (active)
-        for (int k = rowptr[i] + lane; k < rowptr[i + 1]; k += G) {
-            const int j = col[k];
-            if (j != i) s += val[k] * x[j];
+    T s = T(0), bi = T(0), di = T(0);
+    int i = 0;
+    if (active) {
+        i = rowid[g];
+        const int beg = rowptr[g], end = rowptr[g + 1];
+        if (lane == 0) {
+            bi = b[i];
+            di = dinv[i];
         }
+        for (int k = beg + lane; k < end; k += G) {
+            const int j = col[k];
+            const T v = val[k], xj = x[j];
+            s += j != i ? v * xj : T(0);
+        }
+    }
     s = gsum<G>(s);
     if (!active || lane != 0) return;
-    x[i] = (b[i] - s) * dinv[i];
+    x[i] = (bi - s) * di;
 }
 
 template <typename T>

@@ -62,8 +62,9 @@ void launch_schur_numeric(int np, const int *brow, const int *bcol, const double
                           const int *btrow, const int *btcol, const double *btval, int64_t btnnz, const double *d,
                           const int *crow, const int *ccol, const double *cval, const int *srow, const int *scol,
                           double *sval, hipStream_t s);
-// scalar Gauss-Seidel update of the rows rowid[0..nrows) of one colour of
-// S (natural row order): x_i = dinv_i (b_i - sum_{j != i} S_ij x_j)
+// scalar Gauss-Seidel update of the rows of one colour of S, grouped: row g
+// (g < nrows) has entries rowptr[g] .. rowptr[g+1] of col/val and node
+// i = rowid[g]: x_i = dinv_i (b_i - sum_{j != i} S_ij x_j)
 template <typename T>
 void launch_scalar_gs(int nrows, const int *rowptr, const int *col, const T *val, const int *rowid, const T *dinv,
                       const T *b, T *x, int G, hipStream_t s);

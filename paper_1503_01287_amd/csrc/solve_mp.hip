@@ -181,6 +181,7 @@ void build_saddle_mp(amg_ctx *h) {
         if (L.schur.dense_from >= 0 && L.schur.tdense.inv32.n == 0) L.schur.tdense.make_f32(s);
         for (SchurLevel &q : L.schur.lv) {
             conv(q.s32, q.S.val);
+            if (q.Sg.nnz > 0) conv(q.sg32, q.Sg.val);
             if (q.dinv.n) conv(q.dinv32, q.dinv);
             const size_t m = std::max<size_t>(1, q.S.nrows);
             q.x32.alloc(m);

@@ -65,6 +65,7 @@ struct SV<double> {
     static const double *sgs(const Level &L) { return L.sgs_scale.p; }
     static const double *ahat(const Level &L) { return L.bs_ahat.p; }
     static const double *S(const SchurLevel &q) { return q.S.val.p; }
+    static const double *Sg(const SchurLevel &q) { return q.Sg.val.p; }
     static const double *sdinv(const SchurLevel &q) { return q.dinv.p; }
     static double *sx(SchurLevel &q) { return q.x.p; }
     static double *sb(SchurLevel &q) { return q.b.p; }
@@ -85,6 +86,7 @@ struct SV<float> {
     static const float *sgs(const Level &L) { return L.mp.sgs.p; }
     static const float *ahat(const Level &L) { return L.mp.ahat.p; }
     static const float *S(const SchurLevel &q) { return q.s32.p; }
+    static const float *Sg(const SchurLevel &q) { return q.sg32.p; }
     static const float *sdinv(const SchurLevel &q) { return q.dinv32.p; }
     static float *sx(SchurLevel &q) { return q.x32.p; }
     static float *sb(SchurLevel &q) { return q.b32.p; }
@@ -304,8 +306,8 @@ static void schur_vcycle(amg_ctx *h, int l, int k, const T *b, T *x) {
     const int nc = static_cast<int>(q.cptr.size()) - 1;
     fillv(x, q.nA, s);
     for (int c = 0; c < nc; ++c)
-        launch_scalar_gs<T>(q.cptr[c + 1] - q.cptr[c], q.S.rowptr.p, q.S.col.p, SV<T>::S(q), q.rowid.p + q.cptr[c],
-                            SV<T>::sdinv(q), b, x, q.G, s);
+        launch_scalar_gs<T>(q.cptr[c + 1] - q.cptr[c], q.Sg.rowptr.p + q.cptr[c], q.Sg.col.p, SV<T>::Sg(q),
+                            q.rowid.p + q.cptr[c], SV<T>::sdinv(q), b, x, q.G, s);
     BlkArgsT<T> ra = blkT<T>(q.S, SV<T>::S(q));
     ra.nrows = q.nA;
     ra.x = x;
@@ -324,8 +326,8 @@ static void schur_vcycle(amg_ctx *h, int l, int k, const T *b, T *x) {
     hh.y = x;
     launch_blk<T>(1, 1, BLK_ADD, V.Gh, hh, s);
     for (int c = nc - 1; c >= 0; --c)
-        launch_scalar_gs<T>(q.cptr[c + 1] - q.cptr[c], q.S.rowptr.p, q.S.col.p, SV<T>::S(q), q.rowid.p + q.cptr[c],
-                            SV<T>::sdinv(q), b, x, q.G, s);
+        launch_scalar_gs<T>(q.cptr[c + 1] - q.cptr[c], q.Sg.rowptr.p + q.cptr[c], q.Sg.col.p, SV<T>::Sg(q),
+                            q.rowid.p + q.cptr[c], SV<T>::sdinv(q), b, x, q.G, s);
 }
 
 // The Schur cycle of saddle level l from Schur level k down is a fixed linear
