@@ -388,6 +388,7 @@ void build_batch(amg_ctx *h, int nsys, const amg_system *sys) {
     h->kq.alloc(nd);
     h->kw.alloc(nd);
     h->partial.alloc(static_cast<size_t>(std::max(1024 * 128, row_blocks(h->lv[0].n, 64))));
+    h->tune_flush.release();
     h->sc.alloc(SC_COUNT);
     if (!h->h_sc) AMG_HIP(hipHostMalloc(reinterpret_cast<void **>(&h->h_sc), SC_COUNT * sizeof(double)));
     AMG_HIP(hipStreamSynchronize(s));

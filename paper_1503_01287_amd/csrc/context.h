@@ -225,6 +225,9 @@ struct amg_ctx {
     // reduced-precision cycle (precision != AMG_PREC_FP64)
     bool mixed = false;
     amgp2::DevBuf<float> tail_dense32;
+    // setup-time tuners: a buffer larger than the 256 MB Infinity Cache,
+    // written before every timed repetition (released after setup)
+    amgp2::DevBuf<double> tune_flush;
     // saddle point system
     bool saddle = false;
     // the saddle V-cycle from level saddle_tail_from (>= 1) down, entered
@@ -296,6 +299,10 @@ void setup_tail(amg_ctx *h);
 int lanes_for(int64_t nnz, int nrows);
 // setup-time tuner of a level's FP64 kernels (lanes, loop form, XCD placement)
 void autotune_level(amg_ctx *h, Level &L);
+// evict the GPU caches before a tuner's timed run: inside a cycle a level's
+// operator is read after the finer levels' passes have replaced it in the
+// caches, so the tuners time kernels on cold data
+void evict_caches(amg_ctx *h);
 // q.Sg from q.S, q.rowid and q.cptr
 void group_schur_rows(SchurLevel &q, hipStream_t s);
 // FP32 copy of the assembled coarse-end operator (reduced-precision cycle)

@@ -227,6 +227,12 @@ static void setup_smoother(amg_ctx *h, Level &L) {
 // Autotuner: lanes per row for the level's row kernels, measured with HIP
 // events on the level's own operators (residual on the natural rows, one
 // Gauss-Seidel launch on the largest colour). Runs on scratch vectors.
+void evict_caches(amg_ctx *h) {
+    constexpr size_t n = (512u << 20) / sizeof(double);
+    if (h->tune_flush.n != n) h->tune_flush.alloc(n);
+    launch_fill(h->tune_flush.p, 0.0, static_cast<int64_t>(n), h->stream);
+}
+
 // Copy of a Schur level's smoothed rows grouped by colour (rows in the order
 // rowid), so that a colour sweep reads its rows' pointers by position,
 // together with the row ids, instead of after them.
@@ -264,6 +270,7 @@ void autotune_level(amg_ctx *h, Level &L) {
         launch();
         float best_ms = 1e30f;
         for (int r = 0; r < 7; ++r) {
+            evict_caches(h);
             AMG_HIP(hipEventRecord(e0, s));
             launch();
             AMG_HIP(hipEventRecord(e1, s));
@@ -991,6 +998,7 @@ void build_hierarchy(amg_ctx *h, const amg_system *sys) {
     h->kq.alloc(nd);
     h->kw.alloc(nd);
     h->partial.alloc(static_cast<size_t>(std::max(1024 * 128, row_blocks(h->lv[0].n, 64))));
+    h->tune_flush.release();
     h->sc.alloc(SC_COUNT);
     if (!h->h_sc) AMG_HIP(hipHostMalloc(reinterpret_cast<void **>(&h->h_sc), SC_COUNT * sizeof(double)));
     AMG_HIP(hipStreamSynchronize(s));

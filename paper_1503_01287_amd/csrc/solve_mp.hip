@@ -33,6 +33,7 @@ static void autotune_mp(amg_ctx *h, Level &L) {
         launch();
         float best_ms = 1e30f;
         for (int r = 0; r < 7; ++r) {
+            evict_caches(h);
             AMG_HIP(hipEventRecord(e0, s));
             launch();
             AMG_HIP(hipEventRecord(e1, s));

@@ -538,6 +538,7 @@ void setup_saddle_tail(amg_ctx *h) {
         else launch_fill(L.b.p, 1.0, nv, s);
         float best = 1e30f;
         for (int r = 0; r < 4; ++r) {
+            evict_caches(h);
             AMG_HIP(hipEventRecord(e0, s));
             if (mp) saddle_cycle<float>(h, d, L.mp.b.p, L.mp.x.p, true);
             else saddle_cycle<double>(h, d, L.b.p, L.x.p, true);
