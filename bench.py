@@ -25,25 +25,30 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "elasticity-32_gs-L0_traffic.md")
+PROFILES = os.path.join(ROOT, "profiles")
 
 
 def measured_traffic(workload: str, precision: str, kernel_class: str, lanes: int, pair: int, xcd: int):
-    """HBM bytes per launch of the dominant kernel from the committed
-    rocprofv3 --pmc summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), if it
-    covers this kernel and launch shape; else None."""
-    if workload != "elasticity-32" or not os.path.exists(TRAFFIC_FILE):
+    """HBM bytes per launch of the dominant kernel from a committed rocprofv3
+    --pmc summary of this workload (profiles/<workload>_*_traffic.md:
+    FETCH_SIZE + WRITE_SIZE, copy-calibrated), if one covers this kernel
+    class, precision and launch shape; else None."""
+    if not os.path.isdir(PROFILES):
         return None
-    with open(TRAFFIC_FILE) as f:
-        for line in f:
-            if not line.startswith("traffic:"):
-                continue
-            kv = dict(t.split("=", 1) for t in line.split()[1:])
-            if (kv.get("class") == kernel_class and kv.get("precision") == precision
-                    and int(kv.get("lanes", -1)) == lanes and int(kv.get("pair", 0)) == pair
-                    and int(kv.get("xcd", 0)) == xcd):
-                return int(kv["bytes_per_launch"])
+    for name in sorted(os.listdir(PROFILES)):
+        if not (name.startswith(workload + "_") and name.endswith("_traffic.md")):
+            continue
+        with open(os.path.join(PROFILES, name)) as f:
+            for line in f:
+                if not line.startswith("traffic:"):
+                    continue
+                kv = dict(t.split("=", 1) for t in line.split()[1:])
+                if (kv.get("class") == kernel_class and kv.get("precision") == precision
+                        and int(kv.get("lanes", -1)) == lanes and int(kv.get("pair", 0)) == pair
+                        and int(kv.get("xcd", 0)) == xcd):
+                    return int(kv["bytes_per_launch"])
     return None
+
 
 WORKLOADS = {
     "elasticity-32": dict(desc="linear elasticity, pure displacement, unit cube 32^3 cubes x 6 Kuhn tets, "
@@ -234,6 +239,7 @@ def main() -> int:
             i = solver.level_info(l)
             levels.append(dict(nodes=i.n_lin + i.n_quad, pressure=i.n_pres, nnz=int(i.nnz_A), colors=int(i.n_colors),
                                lanes=[int(i.lanes_A), int(i.lanes_gs)], pair=[int(i.pair_A), int(i.pair_gs)],
+                               fp64=[int(i.lanes64_A), int(i.pair64_A)],
                                gs_xcd=int(i.gs_xcd), fused=bool(i.fused),
                                omega=round(float(i.omega), 4)))
         print(f"# {precision}/{krylov} setup {setup_ms:.0f} ms, levels {levels}", file=sys.stderr, flush=True)
@@ -272,9 +278,15 @@ def main() -> int:
                 per_launch_bytes = st["bytes"] / st["launches"]
                 per_launch_ms = st["ms"] / st["launches"]
                 achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
-                which = 1 if dom.startswith("gs.") else 0
-                traffic = measured_traffic(args.workload, precision, dom, levels[0]["lanes"][which],
-                                           levels[0]["pair"][which], levels[0]["gs_xcd"] if which else 0)
+                # the outer operator is the FP64 kernel; the cycle's kernels
+                # are the reduced-precision copies unless the cycle is FP64
+                if dom.startswith("spmv."):
+                    lanes, pair, xcd = levels[0]["fp64"][0], levels[0]["fp64"][1], 0
+                else:
+                    which = 1 if dom.startswith("gs.") else 0
+                    lanes, pair = levels[0]["lanes"][which], levels[0]["pair"][which]
+                    xcd = levels[0]["gs_xcd"] if which else 0
+                traffic = measured_traffic(args.workload, precision, dom, lanes, pair, xcd)
                 out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                                    "kernel": dom, "launches_per_step": st["launches"] // args.steps,

@@ -197,6 +197,10 @@ typedef struct {
                                       contiguous eighth of a colour's rows    */
     int32_t pair_A, pair_gs;       /* 1 if those kernels take two entries per
                                       lane and loop trip                      */
+    int32_t lanes64_A, pair64_A;   /* the FP64 natural-order kernels' lanes
+                                      and loop form (the outer Krylov
+                                      operator also in reduced-precision
+                                      solves)                                 */
 } amg_level_info;
 
 /* Fill *p with the defaults listed above. */

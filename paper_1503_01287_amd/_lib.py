@@ -66,6 +66,7 @@ class AmgLevelInfo(ctypes.Structure):
         ("lanes_A", ctypes.c_int32), ("lanes_gs", ctypes.c_int32), ("fused", ctypes.c_int32),
         ("omega", ctypes.c_double), ("schur_levels", ctypes.c_int32), ("nnz_S", ctypes.c_int64),
         ("gs_xcd", ctypes.c_int32), ("pair_A", ctypes.c_int32), ("pair_gs", ctypes.c_int32),
+        ("lanes64_A", ctypes.c_int32), ("pair64_A", ctypes.c_int32),
     ]
 
 

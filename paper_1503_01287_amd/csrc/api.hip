@@ -275,6 +275,8 @@ int amg_get_level_info(amg_handle h, int32_t level, amg_level_info *info) {
         info->lanes_gs = h->mixed ? L.mp.Gg : L.Gg;
         info->pair_A = h->mixed ? L.mp.pair : L.pair;
         info->pair_gs = h->mixed ? L.mp.pairg : L.pairg;
+        info->lanes64_A = L.G;
+        info->pair64_A = L.pair;
         const int fs = h->tail_start >= 0 ? h->tail_start
                        : h->dense_start >= 0 ? h->dense_start
                                              : h->saddle_tail_from;
