@@ -164,6 +164,14 @@ typedef struct {
                              (same kernels, same order, same results); 0:
                              launched one by one. Profiling runs unrecorded. */
     double vanka_omega;   /* Vanka damping of the local corrections (0.8)  */
+    int32_t gs_post;      /* direction of the post-smoothing Gauss-Seidel
+                             sweeps (SPD systems): 0 (default) backward under
+                             a Krylov method - a symmetric cycle, which CG
+                             needs - and forward in the stand-alone solver,
+                             the form the stand-alone tables of Section 4
+                             follow; 1 always backward; 2 always forward.
+                             A forward post-smoother runs the coarse end
+                             level by level (no assembled coarse end).      */
 } amg_params;
 
 typedef struct {

@@ -260,6 +260,11 @@ class Smoother:
     sgs_omega: float = 0.125      # sGS pressure parameter (Section 4.4)
     sgs_damping: float = 0.5      # sGS M_A = damped block Jacobi with damping 0.5
     omegas: tuple | None = None   # per-level JA damping (overrides omega)
+    # post-smoothing GS sweeps forward like the pre-smoothing ones. Reading of
+    # Section 4: under CG the cycle must be symmetric (forward pre, backward
+    # post), while the stand-alone solver tables follow same-direction sweeps
+    # (with backward post-sweeps they would need about 2.5x the iterations)
+    post_forward: bool = False
 
     @staticmethod
     def parse(name: str) -> "Smoother":
@@ -287,7 +292,7 @@ def smooth_spd(h: Hierarchy, l: int, sm: Smoother, b, x, pre: bool):
         if sm.kind == "JA":
             x = jacobi(lev, b, x, sm.level_omega(l))
         elif sm.kind == "GS":
-            x = gauss_seidel(lev, b, x, forward=pre)
+            x = gauss_seidel(lev, b, x, forward=pre or sm.post_forward)
         else:
             raise ValueError(sm.kind)
     return x

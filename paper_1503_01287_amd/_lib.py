@@ -48,6 +48,7 @@ class AmgParams(ctypes.Structure):
         ("n_level_omega", ctypes.c_int32), ("level_omega", _f64p),
         ("fuse_coarse", ctypes.c_int32), ("autotune", ctypes.c_int32),
         ("omega_model", ctypes.c_void_p), ("graph", ctypes.c_int32), ("vanka_omega", ctypes.c_double),
+        ("gs_post", ctypes.c_int32),
     ]
 
 

@@ -65,6 +65,7 @@ void amg_default_params(amg_params *p) {
     p->omega_model = nullptr;
     p->graph = 1;
     p->vanka_omega = 0.8;
+    p->gs_post = 0;
 }
 
 int amg_setup(const amg_system *sys, const amg_params *params, amg_stream stream, amg_handle *out) {
@@ -95,8 +96,10 @@ int amg_setup(const amg_system *sys, const amg_params *params, amg_stream stream
                     "amg_setup: invalid smoothing/cycle counts");
         AMG_REQUIRE(p.precision == AMG_PREC_FP64 || p.precision == AMG_PREC_MIXED || p.precision == AMG_PREC_FP32,
                     AMG_EINVAL, "amg_setup: unknown precision mode");
+        AMG_REQUIRE(p.gs_post >= 0 && p.gs_post <= 2, AMG_EINVAL, "amg_setup: gs_post must be 0, 1 or 2");
         auto *h = new amg_ctx();
         h->prm = p;
+        h->post_forward = p.gs_post == 2 || (p.gs_post == 0 && p.krylov == AMG_KRYLOV_NONE);
         h->prm.level_omega = nullptr;
         if (p.n_level_omega > 0 && p.level_omega)
             h->level_omega.assign(p.level_omega, p.level_omega + p.n_level_omega);
@@ -125,6 +128,7 @@ static void check_params(const amg_params &p, bool saddle) {
     AMG_REQUIRE(p.krylov != AMG_KRYLOV_FGMRES || p.restart >= 1, AMG_EINVAL, "amg_setup: restart < 1");
     AMG_REQUIRE(p.pre >= 0 && p.post >= 0 && p.cycles >= 1 && p.nu >= 1 && p.nu <= 2, AMG_EINVAL,
                 "amg_setup: invalid smoothing/cycle counts");
+    AMG_REQUIRE(p.gs_post >= 0 && p.gs_post <= 2, AMG_EINVAL, "amg_setup: gs_post must be 0, 1 or 2");
 }
 
 int amg_setup_batched(int32_t nsys, const amg_system *systems, const amg_params *params, amg_stream stream,
@@ -234,9 +238,12 @@ int amg_smooth(amg_handle h, int32_t level, const double *b, double *x, int32_t 
         AMG_REQUIRE(level >= 0 && level < static_cast<int>(h->lv.size()) - 1, AMG_EINVAL,
                     "amg_smooth: level has no smoother (coarsest or out of range)");
         h->stream = static_cast<hipStream_t>(stream);
-        // one step: temporarily force a single pre/post step
+        // one step: temporarily force a single pre/post step, in the
+        // direction asked for (colours ascending or descending)
         amg_params save = h->prm;
+        const bool save_post = h->post_forward;
         h->prm.pre = h->prm.post = 1;
+        h->post_forward = false;
         try {
             if (h->saddle)
                 saddle_smooth(h, level, b, x);
@@ -244,9 +251,11 @@ int amg_smooth(amg_handle h, int32_t level, const double *b, double *x, int32_t 
                 smooth(h, level, b, x, forward != 0, false, false);
         } catch (...) {
             h->prm = save;
+            h->post_forward = save_post;
             throw;
         }
         h->prm = save;
+        h->post_forward = save_post;
         AMG_HIP(hipStreamSynchronize(h->stream));
         profile_collect(h);
         return AMG_OK;

@@ -222,6 +222,9 @@ struct amg_ctx {
     int dense_start = -1;
     amgp2::DevBuf<double> tail_dense;
     int tail_m = 0, tail_nc = 1;
+    // post-smoothing Gauss-Seidel sweeps forward (the stand-alone form, see
+    // amg_params::gs_post) instead of backward (the symmetric cycle)
+    bool post_forward = false;
     // reduced-precision cycle (precision != AMG_PREC_FP64)
     bool mixed = false;
     amgp2::DevBuf<float> tail_dense32;

@@ -525,7 +525,8 @@ void setup_tail(amg_ctx *h) {
     h->tail_m = 0;
     h->tail_dense.release();
     const amg_params &p = h->prm;
-    if (!p.fuse_coarse || p.nu != 1) return;
+    // (both forms implement the symmetric cycle: forward pre-, backward post-smoothing)
+    if (!p.fuse_coarse || p.nu != 1 || h->post_forward) return;
     if (p.smoother != AMG_SMOOTH_JA && p.smoother != AMG_SMOOTH_GS) return;
     const int L = static_cast<int>(h->lv.size()) - 1;
     if (L == 0) return;

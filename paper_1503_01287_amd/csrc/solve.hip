@@ -169,7 +169,7 @@ void smooth(amg_ctx *h, int l, const double *b, double *x, bool pre, bool zero_i
         if (p.smoother == AMG_SMOOTH_JA)
             jacobi_step(h, l, b, x, zero_init && k == 0);
         else
-            gs_sweep(h, l, b, x, pre, pre && zero_init && k == 0);
+            gs_sweep(h, l, b, x, pre || h->post_forward, pre && zero_init && k == 0);
     }
 }
 

@@ -299,7 +299,7 @@ static void smooth_mp(amg_ctx *h, int l, const float *b, float *x, bool pre, boo
         if (p.smoother == AMG_SMOOTH_JA)
             jacobi_mp(h, l, b, x, zero_init && k == 0);
         else
-            gs_mp(h, l, b, x, pre, pre && zero_init && k == 0);
+            gs_mp(h, l, b, x, pre || h->post_forward, pre && zero_init && k == 0);
     }
 }
 

@@ -89,10 +89,11 @@ class AMGSolver:
                  max_levels: int = 10, separate: bool = True, level_omega=None,
                  sgs_omega: float = 0.125, sgs_damping: float = 0.5, restart: int = 100,
                  omega: float | None = None, fuse_coarse: bool = True, autotune: bool = True,
-                 omega_model=None, graph: bool = True, stream=None):
+                 omega_model=None, graph: bool = True, gs_post: str = "auto", stream=None):
         L = C.lib()
         p = C.default_params()
         sm = parse_smoother(smoother)
+        p.gs_post = {"auto": 0, "backward": 1, "forward": 2}[gs_post]
         p.smoother = C.SMOOTH[sm["smoother"]]
         p.pre, p.post = sm["pre"], sm["post"]
         p.omega = omega if omega is not None else sm.get("omega", 0.5)

@@ -137,14 +137,35 @@ def test_multiple_cycles_and_w_cycle(case, cycles, nu):
     assert rel(host(z), prec(r).ravel()) < 1e-11, (name, cycles, nu)
 
 
-@pytest.mark.parametrize("smoother,kry,fuse", [("GS-1-1", "PCG", True), ("GS-1-1", "PCG", False),
-                                               ("JA-1-1-0.5", "PCG", True), ("GS-1-1", "FCG", True),
-                                               ("GS-1-1", "NONE", True)])
-def test_solve_matches_oracle(case, smoother, kry, fuse):
+@pytest.mark.parametrize("fuse", [True, False])
+@pytest.mark.parametrize("precision,tol", [("FP64", 1e-11), ("FP32", 2e-5)])
+def test_vcycle_forward_post_smoothing(case, precision, tol, fuse):
+    """gs_post='forward': the post-smoothing sweeps run forward like the
+    pre-smoothing ones (the stand-alone form), level by level."""
     name, hsys, o = case
-    # the stand-alone iteration contracts by ~0.95 per cycle on elasticity
+    s = amg.AMGSolver(hsys, smoother="GS-1-1", gs_post="forward", precision=precision, krylov="FCG",
+                      fuse_coarse=fuse)
+    assert not any(s.level_info(l).fused for l in range(s.num_levels))
+    h = _oracle_hierarchy(o)
+    sm = oamg.Smoother.parse("GS-1-1")
+    sm.post_forward = True
+    prec = oamg.preconditioner(h, sm)
+    r = np.random.default_rng(15).standard_normal(hsys.dofs)
+    z = torch.zeros(hsys.dofs, dtype=torch.float64, device=DEV)
+    s.precondition(dev(r), z)
+    assert rel(host(z), prec(r).ravel()) < tol, (name, precision, rel(host(z), prec(r).ravel()))
+
+
+@pytest.mark.parametrize("smoother,kry,fuse,post", [("GS-1-1", "PCG", True, "auto"), ("GS-1-1", "PCG", False, "auto"),
+                                                    ("JA-1-1-0.5", "PCG", True, "auto"),
+                                                    ("GS-1-1", "FCG", True, "auto"),
+                                                    ("GS-1-1", "NONE", True, "auto"),
+                                                    ("GS-1-1", "NONE", True, "backward")])
+def test_solve_matches_oracle(case, smoother, kry, fuse, post):
+    name, hsys, o = case
+    # the symmetric stand-alone iteration contracts by ~0.95 per cycle on elasticity
     tol = 1e-10 if kry != "NONE" else 1e-8
-    s = amg.AMGSolver(hsys, smoother=smoother, krylov=kry, fuse_coarse=fuse)
+    s = amg.AMGSolver(hsys, smoother=smoother, krylov=kry, fuse_coarse=fuse, gs_post=post)
     b = dev(hsys.rhs)
     x = torch.zeros_like(b)
     res = s.solve(b, x, tol=tol, maxit=1000)
@@ -157,14 +178,17 @@ def test_solve_matches_oracle(case, smoother, kry, fuse):
     elif kry == "FCG":
         ref = krylov.fcg(mv, lambda r: prec(r).ravel(), o.b.ravel(), tol=tol)
     else:
-        ref = _stationary(o, h, smoother, tol)
+        # the stand-alone solver sweeps forward after the coarse correction
+        # too unless told otherwise
+        ref = _stationary(o, h, smoother, tol, post_forward=post == "auto")
     assert abs(res.iters - ref.iters) <= 1, (name, res.iters, ref.iters)
     xs = host(x)
     assert np.linalg.norm(xs - ref.x) / np.linalg.norm(ref.x) < 1e-8
 
 
-def _stationary(o, h, smoother, tol):
+def _stationary(o, h, smoother, tol, post_forward=False):
     sm = oamg.Smoother.parse(smoother)
+    sm.post_forward = post_forward
     b = o.b
     x = np.zeros_like(b)
     r0 = np.linalg.norm(b)
