@@ -300,6 +300,13 @@ def paper_spd(n: int, kind: str, lam: float = 1.73e6, mu: float = 1.15e6) -> SPD
     return SPDSystem(mesh, A, b, lift, dmask)
 
 
+def paper_mixed(n: int, lam: float = 1.73e6, mu: float = 1.15e6) -> "SaddleSystem":
+    """Section 4.4: the mixed form of the elasticity problem on Section 4.1's data."""
+    mesh = kuhn_mesh(n)
+    mask_v, func = paper_cube_bc(mesh)
+    return saddle_system(mesh, mu, 1.0 / lam, mask_v, func)
+
+
 def saddle_system(mesh: Mesh, mu: float, lam_inv: float, mask_v: np.ndarray, func,
                   load: np.ndarray | None = None, closed: bool = False) -> SaddleSystem:
     """[[A, B^T], [B, -C]] for mixed elasticity (lam_inv = 1/lambda) or Stokes (0)."""

@@ -1,10 +1,13 @@
-"""The paper's SPD iteration tables (Section 4, vector Laplacian and
-elasticity in pure displacement form, meshes L1-L4 = 4^3 ... 32^3 cubes)
-rerun on the GPU: stand-alone AMG and AMG-preconditioned CG, V-cycle (nu = 1)
-and W-cycle (nu = 2), smoothers JA-1-1-0.5, JA-2-2-0.5, GS-1-1, GS-2-2, FP64,
-the paper's boundary data (u = 0 on z = 0, u = (0, 0, 1) on z = 1) and its
-stopping rule (relative residual 1e-11). The paper's counts are printed
-beside ours; '-' marks a run that does not converge (within MAXIT).
+"""The paper's iteration tables (Section 4, meshes L1-L4 = 4^3 ... 32^3
+cubes, its boundary data u = 0 on z = 0, u = (0, 0, 1) on z = 1, FP64)
+rerun on the GPU. SPD (vector Laplacian, elasticity in pure displacement
+form; relative residual 1e-11): stand-alone AMG and AMG-preconditioned CG,
+V-cycle (nu = 1) and W-cycle (nu = 2), smoothers JA-1-1-0.5, JA-2-2-0.5,
+GS-1-1, GS-2-2. Mixed elasticity (Section 4.4; relative residual 1e-9 of the
+whole residual): stand-alone AMG with sGS-k-k and Braess-Sarazin-k-k, and
+GMRES with one or two V-cycles of sGS-1-1, Braess-Sarazin-1-1 and
+Vanka-1-1 (flexible GMRES here). The paper's counts are printed beside ours;
+'-' marks a run that does not converge (within MAXIT).
 
     python -m paper_1503_01287_amd.paper_tables [--levels 1 2 3 4] [--out table.md]
 """
@@ -48,39 +51,69 @@ PAPER = {
 }
 
 
+# mixed elasticity: (table label, Krylov method, V-cycles per preconditioner, smoother, counts at L1..L4)
+PAPER_MIXED = [
+    ("tab:amgelasamguzawanotay", "NONE", 1, "sGS-1-1", [107, 104, 99, 93]),
+    ("tab:amgelasamguzawanotay", "NONE", 1, "sGS-2-2", [54, 53, 53, 59]),
+    ("tab:amgelasgmresuzawanotay", "FGMRES", 1, "sGS-1-1", [14, 18, 19, 21]),
+    ("tab:amgelasgmresuzawanotay", "FGMRES", 2, "sGS-1-1", [12, 15, 15, 15]),
+    ("tab:amgelasamgBS", "NONE", 1, "BS-1-1", [135, 133, 125, 117]),
+    ("tab:amgelasamgBS", "NONE", 1, "BS-2-2", [71, 70, 66, 62]),
+    ("tab:amgelasgmresBS", "FGMRES", 1, "BS-1-1", [27, 27, 27, 27]),
+    ("tab:amgelasgmresBS", "FGMRES", 2, "BS-1-1", [18, 19, 19, 19]),
+    ("tab:amgelasgmresvanka", "FGMRES", 1, "Vanka-1-1", [60, 45, 49, 69]),
+    ("tab:amgelasgmresvanka", "FGMRES", 2, "Vanka-1-1", [42, 30, 32, 45]),
+]
+
+
+def _run(systems, kind, l, dev, tol, **kw):
+    import torch
+    from . import problems, AMGSolver
+    key = (kind, l)
+    if key not in systems:
+        systems[key] = problems.paper_cube(SIZES[l], kind)
+    sysm = systems[key]
+    s = AMGSolver(sysm, **kw)
+    b = torch.from_numpy(sysm.rhs).to(dev)
+    x = torch.zeros_like(b)
+    t0 = time.perf_counter()
+    r = s.solve(b, x, tol=tol, maxit=MAXIT)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0)
+    s.close()
+    return sysm, (str(r.iters) if r.converged else "-"), ms
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--levels", type=int, nargs="+", default=[1, 2, 3, 4])
     ap.add_argument("--out", default=None)
+    ap.add_argument("--only", choices=["spd", "mixed"], default=None)
     args = ap.parse_args()
     import torch
-    from . import problems, AMGSolver
     dev = torch.device("cuda:0")
     systems = {}
     lines = ["| table | smoother | " + " | ".join(f"L{l} (ours / paper)" for l in args.levels) + " |",
              "|---|---|" + "---|" * len(args.levels)]
-    for (label, kind, kry, nu), rows in PAPER.items():
+    for (label, kind, kry, nu), rows in (PAPER.items() if args.only != "mixed" else []):
         for sm in SMOOTHERS:
             cells = []
             for l in args.levels:
-                key = (kind, l)
-                if key not in systems:
-                    systems[key] = problems.paper_cube(SIZES[l], kind)
-                sysm = systems[key]
-                s = AMGSolver(sysm, smoother=sm, krylov=kry, nu=nu)
-                b = torch.from_numpy(sysm.rhs).to(dev)
-                x = torch.zeros_like(b)
-                t0 = time.perf_counter()
-                r = s.solve(b, x, tol=1e-11, maxit=MAXIT)
-                torch.cuda.synchronize()
-                ms = 1e3 * (time.perf_counter() - t0)
-                s.close()
-                ours = str(r.iters) if r.converged else "-"
+                sysm, ours, ms = _run(systems, kind, l, dev, 1e-11, smoother=sm, krylov=kry, nu=nu)
                 ref = rows[sm][l - 1]
                 cells.append(f"{ours} / {'-' if ref is None else ref}")
                 print(f"{label} {sm} L{l} ({sysm.dofs} DOF): {ours} iterations ({ms:.0f} ms), paper "
                       f"{'-' if ref is None else ref}", file=sys.stderr, flush=True)
             lines.append(f"| {label} | {sm} | " + " | ".join(cells) + " |")
+    for label, kry, cyc, sm, ref in (PAPER_MIXED if args.only != "spd" else []):
+        cells = []
+        for l in args.levels:
+            sysm, ours, ms = _run(systems, "mixed", l, dev, 1e-9, smoother=sm, krylov=kry, cycles=cyc)
+            cells.append(f"{ours} / {ref[l - 1]}")
+            print(f"{label} {sm} {cyc} V L{l} ({sysm.dofs} DOF): {ours} iterations ({ms:.0f} ms), paper "
+                  f"{ref[l - 1]}", file=sys.stderr, flush=True)
+        name = sm if kry == "NONE" else f"{sm}, {cyc} V-cycle{'s' if cyc > 1 else ''}"
+        lines.append(f"| {label} | {name} | " + " | ".join(cells) + " |")
     text = "\n".join(lines) + "\n"
     print(text)
     if args.out:

@@ -381,7 +381,9 @@ def stokes_cavity(n: int, speed: float, mu: float = 0.5) -> LinearSystem:
 
 
 def paper_cube(n: int, kind: str = "laplace", lam: float = 1.73e6, mu: float = 1.15e6) -> LinearSystem:
-    """Section 4.1's data: u = 0 on z = 0, u = (0, 0, 1) on z = 1."""
+    """Section 4.1's data: u = 0 on z = 0, u = (0, 0, 1) on z = 1, zero
+    Neumann data elsewhere; kind "laplace", "elastic" or "mixed" (the mixed
+    displacement-pressure form of Section 4.4, C = (1/lambda) mass)."""
     mesh = cube_mesh(n)
     z = mesh.xyz[:, 2]
     vmask = (z == 0.0) | (z == 1.0)
@@ -390,5 +392,7 @@ def paper_cube(n: int, kind: str = "laplace", lam: float = 1.73e6, mu: float = 1
         out = np.zeros((X.shape[0], 3))
         out[X[:, 2] == 1.0, 2] = 1.0
         return out
+    if kind == "mixed":
+        return _saddle(f"paper-mixed-{n}", mesh, mu, 1.0 / lam, vmask, g, None, False)
     return _spd(f"paper-{kind}-{n}", mesh, "laplace" if kind == "laplace" else "elastic", lam, mu,
                 vmask, g, None, kind == "laplace")

@@ -78,6 +78,20 @@ def test_harness_paper_cube_matches_oracle():
     assert np.abs(h.rhs - o.b.ravel()).max() < 1e-14
 
 
+def test_harness_paper_mixed_matches_oracle():
+    """Section 4.4's mixed system: quadrature assembly (harness) vs closed
+    form (oracle), blocks and right-hand side."""
+    h = amg.problems.paper_cube(3, "mixed")
+    o = fem.paper_mixed(3)
+    assert h.n_pres == o.B.nrows and h.dofs == 3 * o.A.nrows + o.B.nrows
+    assert np.array_equal(h.A_col, o.A.indices) and np.array_equal(h.B_col, o.B.indices)
+    assert np.abs(h.A_val.reshape(-1, 3, 3) - o.A.vals).max() <= 1e-14 * np.abs(o.A.vals).max()
+    assert np.abs(h.B_val.reshape(-1, 1, 3) - o.B.vals.reshape(-1, 1, 3)).max() <= 1e-14 * np.abs(o.B.vals).max()
+    assert np.abs(h.C_val - o.C.vals.ravel()).max() <= 1e-14 * np.abs(o.C.vals).max()
+    rhs = np.concatenate([o.f.ravel(), o.g])
+    assert np.abs(h.rhs - rhs).max() <= 1e-14 * np.abs(rhs).max()
+
+
 def test_sizes_match_paper_table():
     h = amg.problems.elasticity(8)
     assert h.dofs == 14739

@@ -241,6 +241,27 @@ def test_standalone_counts_paper_bc(golden):
     assert sym > 2 * its[0], (sym, its)
 
 
+def test_mixed_bs_gmres_count_paper_bc(golden):
+    """Section 4.4 (mixed elasticity on the paper's data, L1): GMRES with one
+    Braess-Sarazin-1-1 V-cycle per iteration needs the paper's count within 5
+    (soft; the inner Schur-complement cycle is a reading)."""
+    paper = {r[0]: [int(v) for v in r[1:5]] for r in golden("paper_iterations.txt")}
+    o = fem.paper_mixed(4)
+    assert 3 * o.A.nrows + o.B.nrows == 2312   # saddle DOF at L1 (mesh table)
+    h = amg.setup(o.A, o.nlin, o.nquad, B=o.B, C=o.C, singular=o.singular)
+    amg.prepare_bs(h)
+    Bt = o.B.transpose()
+    nv = 3 * o.A.nrows
+
+    def mv(z):
+        u, p = z[:nv].reshape(-1, 3), z[nv:]
+        return np.concatenate([o.A.matvec(u).ravel() + Bt.matvec(p.reshape(-1, 1)).ravel(),
+                               o.B.matvec(u)[:, 0] - o.C.matvec(p.reshape(-1, 1))[:, 0]])
+    r = krylov.fgmres(mv, amg.preconditioner(h, amg.Smoother.parse("BS-1-1")),
+                      np.concatenate([o.f.ravel(), o.g]), tol=1e-9)
+    assert abs(r.iters - paper["mixed_gmres_BS_1V"][0]) <= 5, r.iters
+
+
 # ---------------------------------------------------------------- Krylov
 def test_pcg_exact_preconditioner_one_iteration():
     s = workloads.laplace(2)
