@@ -6,7 +6,9 @@ V-cycle (nu = 1) and W-cycle (nu = 2), smoothers JA-1-1-0.5, JA-2-2-0.5,
 GS-1-1, GS-2-2. Mixed elasticity (Section 4.4; relative residual 1e-9 of the
 whole residual): stand-alone AMG with sGS-k-k and Braess-Sarazin-k-k, and
 GMRES with one or two V-cycles of sGS-1-1, Braess-Sarazin-1-1 and
-Vanka-1-1 (flexible GMRES here). The paper's counts are printed beside ours;
+Vanka-1-1 (flexible GMRES here). Non-separating coarsening (the black-box
+comparison of Section 4.2, vector Laplacian, two W-cycles per iteration).
+The paper's counts are printed beside ours;
 '-' marks a run that does not converge (within MAXIT).
 
     python -m paper_1503_01287_amd.paper_tables [--levels 1 2 3 4] [--out table.md]
@@ -66,6 +68,15 @@ PAPER_MIXED = [
 ]
 
 
+# non-separating ("black-box") coarsening, vector Laplacian, 2 W-cycles per
+# iteration with one smoothing step each way (smoother read as GS-1-1);
+# None = the paper's "> 200"
+PAPER_NONSEP = [
+    ("tab:nonsepamg", "NONE", [90, 158, None, None]),
+    ("tab:nonsepamg", "PCG", [22, 25, 36, 64]),
+]
+
+
 def _run(systems, kind, l, dev, tol, **kw):
     import torch
     from . import problems, AMGSolver
@@ -88,14 +99,14 @@ def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--levels", type=int, nargs="+", default=[1, 2, 3, 4])
     ap.add_argument("--out", default=None)
-    ap.add_argument("--only", choices=["spd", "mixed"], default=None)
+    ap.add_argument("--only", choices=["spd", "mixed", "nonsep"], default=None)
     args = ap.parse_args()
     import torch
     dev = torch.device("cuda:0")
     systems = {}
     lines = ["| table | smoother | " + " | ".join(f"L{l} (ours / paper)" for l in args.levels) + " |",
              "|---|---|" + "---|" * len(args.levels)]
-    for (label, kind, kry, nu), rows in (PAPER.items() if args.only != "mixed" else []):
+    for (label, kind, kry, nu), rows in (PAPER.items() if args.only in (None, "spd") else []):
         for sm in SMOOTHERS:
             cells = []
             for l in args.levels:
@@ -105,7 +116,7 @@ def main() -> int:
                 print(f"{label} {sm} L{l} ({sysm.dofs} DOF): {ours} iterations ({ms:.0f} ms), paper "
                       f"{'-' if ref is None else ref}", file=sys.stderr, flush=True)
             lines.append(f"| {label} | {sm} | " + " | ".join(cells) + " |")
-    for label, kry, cyc, sm, ref in (PAPER_MIXED if args.only != "spd" else []):
+    for label, kry, cyc, sm, ref in (PAPER_MIXED if args.only in (None, "mixed") else []):
         cells = []
         for l in args.levels:
             sysm, ours, ms = _run(systems, "mixed", l, dev, 1e-9, smoother=sm, krylov=kry, cycles=cyc)
@@ -114,6 +125,17 @@ def main() -> int:
                   f"{ref[l - 1]}", file=sys.stderr, flush=True)
         name = sm if kry == "NONE" else f"{sm}, {cyc} V-cycle{'s' if cyc > 1 else ''}"
         lines.append(f"| {label} | {name} | " + " | ".join(cells) + " |")
+    for label, kry, ref in (PAPER_NONSEP if args.only in (None, "nonsep") else []):
+        cells = []
+        for l in args.levels:
+            sysm, ours, ms = _run(systems, "laplace", l, dev, 1e-11, smoother="GS-1-1", krylov=kry, nu=2,
+                                  cycles=2, separate=False)
+            r = "> 200" if ref[l - 1] is None else ref[l - 1]
+            cells.append(f"{ours} / {r}")
+            print(f"{label} {kry} L{l} ({sysm.dofs} DOF): {ours} iterations ({ms:.0f} ms), paper {r}",
+                  file=sys.stderr, flush=True)
+        lines.append(f"| {label} | non-separating, {'AMG' if kry == 'NONE' else 'PCG'}, 2 W-cycles | "
+                     + " | ".join(cells) + " |")
     text = "\n".join(lines) + "\n"
     print(text)
     if args.out:
