@@ -227,7 +227,8 @@ struct amg_ctx {
     bool post_forward = false;
     // reduced-precision cycle (precision != AMG_PREC_FP64)
     bool mixed = false;
-    amgp2::DevBuf<float> tail_dense32;
+    amgp2::DevBuf<float> tail_dense32;     // FP32 cycles
+    amgp2::DevBuf<uint16_t> tail_dense16;  // FP32/BF16 cycles (coarse levels in BF16)
     // setup-time tuners: a buffer larger than the 256 MB Infinity Cache,
     // written before every timed repetition (released after setup)
     amgp2::DevBuf<double> tune_flush;

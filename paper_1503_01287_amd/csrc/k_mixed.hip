@@ -3,6 +3,8 @@
 // conversions that build those copies. A 3x3 block costs 40 bytes in FP32
 // and 22 bytes in BF16 (76 in FP64), so the bandwidth-bound passes move
 // 1.9x / 3.5x fewer bytes.
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 #include "mixed.h"
@@ -362,15 +364,20 @@ void launch_diag_solve_mp(int mode, int nrows, const int *rowid, const float *di
     AMG_CHECK_LAUNCH();
 }
 
-__global__ void __launch_bounds__(MBLOCK) k_dense_gemv_f32(const float *M, int m, int nc, const float *X, float *Y) {
+// y = M x for a dense m x m operator applied to nc components, one
+// wavefront per row, four row loads in flight per lane; M in FP32 or BF16,
+// FP32 accumulation
+template <int KIND>
+__global__ void __launch_bounds__(MBLOCK) k_dense_gemv_mp(const void *M, int m, int nc, const float *X, float *Y) {
     const int row = blockIdx.x * (MBLOCK / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (row >= m) return;
     float a0 = 0.f, a1 = 0.f, a2 = 0.f;
-    const float *Mr = M + static_cast<int64_t>(row) * m;
+    const int64_t base = static_cast<int64_t>(row) * m;
     int j = lane;
     for (; j + 192 < m; j += 256) {
-        const float v0 = Mr[j], v1 = Mr[j + 64], v2 = Mr[j + 128], v3 = Mr[j + 192];
+        const float v0 = ld<KIND>(M, base + j), v1 = ld<KIND>(M, base + j + 64), v2 = ld<KIND>(M, base + j + 128),
+                    v3 = ld<KIND>(M, base + j + 192);
         if (nc == 1) {
             a0 += v0 * X[j] + v1 * X[j + 64] + v2 * X[j + 128] + v3 * X[j + 192];
         } else {
@@ -380,7 +387,7 @@ __global__ void __launch_bounds__(MBLOCK) k_dense_gemv_f32(const float *M, int m
         }
     }
     for (; j < m; j += 64) {
-        const float v = Mr[j];
+        const float v = ld<KIND>(M, base + j);
         a0 += v * X[j * nc];
         if (nc > 1) {
             a1 += v * X[j * nc + 1];
@@ -395,7 +402,26 @@ __global__ void __launch_bounds__(MBLOCK) k_dense_gemv_f32(const float *M, int m
 
 void launch_dense_gemv_f32(const float *M, int m, int nc, const float *X, float *Y, hipStream_t s) {
     if (m <= 0) return;
-    k_dense_gemv_f32<<<ceil_div(m, MBLOCK / 64), MBLOCK, 0, s>>>(M, m, nc, X, Y);
+    k_dense_gemv_mp<VAL_F32><<<ceil_div(m, MBLOCK / 64), MBLOCK, 0, s>>>(M, m, nc, X, Y);
+    AMG_CHECK_LAUNCH();
+}
+
+void launch_dense_gemv_bf16(const uint16_t *M, int m, int nc, const float *X, float *Y, hipStream_t s) {
+    if (m <= 0) return;
+    k_dense_gemv_mp<VAL_BF16><<<ceil_div(m, MBLOCK / 64), MBLOCK, 0, s>>>(M, m, nc, X, Y);
+    AMG_CHECK_LAUNCH();
+}
+
+__global__ void k_to_bf16(const double *src, uint16_t *dst, int64_t n) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * MBLOCK + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * MBLOCK)
+        dst[i] = f32_to_bf16(static_cast<float>(src[i]));
+}
+
+void launch_to_bf16(const double *src, uint16_t *dst, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    const int64_t nb = std::min<int64_t>(4096, (n + MBLOCK - 1) / MBLOCK);
+    k_to_bf16<<<static_cast<int>(nb), MBLOCK, 0, s>>>(src, dst, n);
     AMG_CHECK_LAUNCH();
 }
 

@@ -55,5 +55,8 @@ void launch_diag_solve_mp(int mode, int nrows, const int *rowid, const float *di
                           float *x, hipStream_t s);
 // Y = M X with an FP32 dense matrix (m x m), nc components
 void launch_dense_gemv_f32(const float *M, int m, int nc, const float *X, float *Y, hipStream_t s);
+void launch_dense_gemv_bf16(const uint16_t *M, int m, int nc, const float *X, float *Y, hipStream_t s);
+// BF16 (round to nearest even) copy of FP64 values
+void launch_to_bf16(const double *src, uint16_t *dst, int64_t n, hipStream_t s);
 
 }  // namespace amgp2

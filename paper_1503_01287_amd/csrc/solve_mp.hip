@@ -195,10 +195,18 @@ void build_saddle_mp(amg_ctx *h) {
 
 void refresh_tail_f32(amg_ctx *h) {
     h->tail_dense32.release();
+    h->tail_dense16.release();
     if (h->mixed && h->tail_m > 0) {
+        // the coarse end below the finest level, in the coarse levels' value
+        // type: BF16 in the FP32/BF16 cycle, FP32 in the FP32 cycle
         const int64_t mm = static_cast<int64_t>(h->tail_m) * h->tail_m;
-        h->tail_dense32.alloc(mm);
-        launch_to_f32(h->tail_dense.p, h->tail_dense32.p, mm, h->stream);
+        if (h->prm.precision == AMG_PREC_MIXED) {
+            h->tail_dense16.alloc(mm);
+            launch_to_bf16(h->tail_dense.p, h->tail_dense16.p, mm, h->stream);
+        } else {
+            h->tail_dense32.alloc(mm);
+            launch_to_f32(h->tail_dense.p, h->tail_dense32.p, mm, h->stream);
+        }
     }
     AMG_HIP(hipStreamSynchronize(h->stream));
 }
@@ -322,8 +330,12 @@ static void cycle_mp(amg_ctx *h, int l, const float *b, float *x, bool x_zero, b
         return;
     }
     if (l == h->dense_start && x_zero) {
-        ProfScope ps(h, "dense_tail", static_cast<double>(h->tail_m) * h->tail_m * 4.0);
-        launch_dense_gemv_f32(h->tail_dense32.p, h->tail_m, h->tail_nc, b, x, h->stream);
+        const bool bf = h->tail_dense16.n > 0;
+        ProfScope ps(h, "dense_tail", static_cast<double>(h->tail_m) * h->tail_m * (bf ? 2.0 : 4.0));
+        if (bf)
+            launch_dense_gemv_bf16(h->tail_dense16.p, h->tail_m, h->tail_nc, b, x, h->stream);
+        else
+            launch_dense_gemv_f32(h->tail_dense32.p, h->tail_m, h->tail_nc, b, x, h->stream);
         return;
     }
     smooth_mp(h, l, b, x, true, x_zero, filled);
