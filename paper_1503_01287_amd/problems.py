@@ -319,6 +319,26 @@ def laplace_rhs(sysm: LinearSystem, workload: int, i: int) -> np.ndarray:
     return np.ascontiguousarray(_eliminate(rowptr, col, full, np.zeros_like(lift), lift, mask, False).ravel())
 
 
+def laplace_rhs_many(sysm: LinearSystem, workload: int, ids) -> list:
+    """laplace_rhs for several Dirichlet data sets, the operator assembled
+    once: with A = A_s (x) I_3 and zero load, the eliminated right-hand side
+    is -A_s g on the free rows (g the lifting, nonzero on Dirichlet nodes
+    only) and 0 on the Dirichlet rows."""
+    import scipy.sparse as sps
+    mesh = cube_mesh(sysm.n)
+    rowptr, col, val = velocity_operator(mesh, "laplace", scalar=True)
+    N = mesh.nv + mesh.ne
+    A = sps.csr_matrix((np.asarray(val).ravel(), col, rowptr), shape=(N, N))
+    out = []
+    for i in ids:
+        data = synth.trig_dirichlet(workload, i)
+        lift, mask = _dirichlet(mesh, mesh.xyz[:, 0] == 0.0, lambda X, d=data: d(X[:, 1], X[:, 2]))
+        rhs = -(A @ lift)
+        rhs[mask] = 0.0
+        out.append(np.ascontiguousarray(rhs.ravel()))
+    return out
+
+
 def elasticity(n: int, i: int = 0, E: float = 1.0, nu: float = 0.3,
                workload: int = synth.ELASTICITY) -> LinearSystem:
     """Pure-displacement elasticity, clamped x = 0, random traction on x = 1."""

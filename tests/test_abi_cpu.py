@@ -72,6 +72,22 @@ def test_harness_matches_oracle_assembly(n):
     assert np.abs(he.rhs - oe.b.ravel()).max() <= 1e-14 * np.abs(oe.b).max()
 
 
+def test_laplace_rhs_many_matches_assembly():
+    """The right-hand sides of several Dirichlet data sets from one operator
+    equal those of separate assemblies, and data set 0 equals the oracle's."""
+    import synth
+    n = 4
+    h = amg.problems.laplace(n, workload=synth.LAPLACE_LARGE, i=0)
+    many = amg.problems.laplace_rhs_many(h, synth.LAPLACE_LARGE, [0, 1, 2])
+    o = workloads.laplace(n, workload=synth.LAPLACE_LARGE, i=0)
+    scale = max(1.0, np.abs(o.b).max())
+    assert np.abs(many[0] - o.b.ravel()).max() <= 1e-13 * scale
+    for i in (1, 2):
+        ref = amg.problems.laplace(n, workload=synth.LAPLACE_LARGE, i=i).rhs
+        assert np.abs(many[i] - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max())
+        assert np.abs(many[i] - many[0]).max() > 1e-3 * scale   # distinct data sets
+
+
 def test_harness_paper_cube_matches_oracle():
     h = amg.problems.paper_cube(3, "laplace")
     o = fem.paper_spd(3, "laplace")
