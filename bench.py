@@ -249,7 +249,7 @@ def main() -> int:
         levels = []
         for l in range(solver.num_levels):
             i = solver.level_info(l)
-            levels.append(dict(nodes=i.n_lin + i.n_quad, pressure=i.n_pres, nnz=int(i.nnz_A), colors=int(i.n_colors),
+            levels.append(dict(nodes=i.n_lin + i.n_quad, pressure=i.n_pres, nnz=int(i.nnz_A), kept=int(i.kept_A), colors=int(i.n_colors),
                                lanes=[int(i.lanes_A), int(i.lanes_gs)], pair=[int(i.pair_A), int(i.pair_gs)],
                                fp64=[int(i.lanes64_A), int(i.pair64_A)],
                                gs_xcd=int(i.gs_xcd), fused=bool(i.fused),

@@ -184,7 +184,9 @@ typedef struct {
 typedef struct {
     int32_t n_lin, n_quad, n_pres; /* nodes on the level                      */
     int32_t bs;                    /* 3 or 1                                   */
-    int64_t nnz_A, nnz_B, nnz_C;   /* stored entries (blocks)                  */
+    int64_t nnz_A, nnz_B, nnz_C;   /* entries (blocks) of the structural
+                                      pattern, as amg_get_level_matrix
+                                      returns them                            */
     int64_t nnz_P;                 /* entries of the scalar prolongation to
                                       this level from the next coarser one
                                       (0 on the coarsest level)               */
@@ -209,6 +211,12 @@ typedef struct {
                                       and loop form (the outer Krylov
                                       operator also in reduced-precision
                                       solves)                                 */
+    int64_t kept_A, kept_B;        /* entries the smoothers and solve kernels
+                                      stream: the structural ones less the
+                                      numerically zero off-diagonal blocks,
+                                      dropped once the setup's pattern-based
+                                      steps are done (Dirichlet couplings,
+                                      couplings that vanish on the mesh)     */
 } amg_level_info;
 
 /* Fill *p with the defaults listed above. */

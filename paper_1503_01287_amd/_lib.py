@@ -68,6 +68,7 @@ class AmgLevelInfo(ctypes.Structure):
         ("omega", ctypes.c_double), ("schur_levels", ctypes.c_int32), ("nnz_S", ctypes.c_int64),
         ("gs_xcd", ctypes.c_int32), ("pair_A", ctypes.c_int32), ("pair_gs", ctypes.c_int32),
         ("lanes64_A", ctypes.c_int32), ("pair64_A", ctypes.c_int32),
+        ("kept_A", ctypes.c_int64), ("kept_B", ctypes.c_int64),
     ]
 
 

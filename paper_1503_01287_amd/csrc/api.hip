@@ -274,8 +274,10 @@ int amg_get_level_info(amg_handle h, int32_t level, amg_level_info *info) {
         info->n_quad = L.n_quad;
         info->n_pres = L.n_pres;
         info->bs = L.mode;
-        info->nnz_A = L.A.nnz;
-        info->nnz_B = L.B.nnz;
+        info->nnz_A = L.pattern_nnz_A();
+        info->nnz_B = L.pattern_nnz_B();
+        info->kept_A = L.A.nnz;
+        info->kept_B = L.B.nnz;
         info->nnz_C = L.C.nnz;
         info->nnz_P = L.coarsest ? 0 : L.P.nnz;
         info->n_colors = L.cptr.empty() ? 0 : static_cast<int>(L.cptr.size()) - 1;
@@ -304,8 +306,8 @@ int amg_get_level_matrix(amg_handle h, int32_t level, int32_t which, int32_t *ro
         AMG_REQUIRE(level >= 0 && level < static_cast<int>(h->lv.size()), AMG_EINVAL, "bad level");
         const Level &L = h->lv[level];
         const DMat *m = nullptr;
-        if (which == 0) m = &L.A;
-        if (which == 1 && L.B.nnz > 0) m = &L.B;
+        if (which == 0) m = L.A_pat.nnz > 0 ? &L.A_pat : &L.A;
+        if (which == 1 && L.B.nnz > 0) m = L.B_pat.nnz > 0 ? &L.B_pat : &L.B;
         if (which == 2 && L.C.nnz > 0) m = &L.C;
         if (which == 3) {
             AMG_REQUIRE(!L.coarsest, AMG_EINVAL, "coarsest level has no prolongation");
@@ -486,7 +488,8 @@ int amg_level_features(amg_handle h, int32_t level, double *features) {
         AMG_REQUIRE(h && features, AMG_EINVAL, "amg_level_features: null argument");
         AMG_REQUIRE(level >= 0 && level < static_cast<int>(h->lv.size()), AMG_EINVAL, "bad level");
         const Level &L = h->lv[level];
-        row_features(L.mode, L.n, L.A.rowptr.p, L.A.col.p, L.A.val.p, L.A.nnz, level, features, h->stream);
+        const DMat &A = L.A_pat.nnz > 0 ? L.A_pat : L.A;  // features are defined on the structural rows
+        row_features(L.mode, L.n, A.rowptr.p, A.col.p, A.val.p, A.nnz, level, features, h->stream);
         return AMG_OK;
     });
 }

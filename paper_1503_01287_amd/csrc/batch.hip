@@ -140,6 +140,8 @@ void build_batch(amg_ctx *h, int nsys, const amg_system *sys) {
             prow[j] = V.n_pres;
             M.n += V.n;
             M.n_pres += V.n_pres;
+            M.nnz_pat_A += V.pattern_nnz_A();
+            M.nnz_pat_B += V.pattern_nnz_B();
             M.n_lin += V.n_lin;
             M.n_quad += V.n_quad;
             if (depth[P[j]] > l) {

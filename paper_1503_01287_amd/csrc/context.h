@@ -153,6 +153,13 @@ struct Level {
     LevelMP mp;               // mixed-precision copy (AMG_PREC_MIXED / FP32)
     // saddle point levels (n_pres > 0); vectors are [u (3n); p (n_pres)]
     DMat B, Bt, C;            // B: n_pres x n (1x3), Bt: n x n_pres (3x1), C: n_pres^2 (may be empty)
+    // structural A and B where their numerically zero blocks were dropped
+    // from A and B after setup (empty otherwise): export and row features;
+    // a merged batch level keeps only the members' structural counts
+    DMat A_pat, B_pat;
+    int64_t nnz_pat_A = 0, nnz_pat_B = 0;
+    int64_t pattern_nnz_A() const { return A_pat.nnz > 0 ? A_pat.nnz : nnz_pat_A > 0 ? nnz_pat_A : A.nnz; }
+    int64_t pattern_nnz_B() const { return B_pat.nnz > 0 ? B_pat.nnz : nnz_pat_B > 0 ? nnz_pat_B : B.nnz; }
     DMat H, Ht;               // pressure prolongation to this level and its transpose
     DevBuf<double> sgs_scale; // sGS: 1 / diag(B M_A^{-1} B^T + C)
     DevBuf<double> bs_ahat;   // BS: 1 / (2 a_ii) per velocity unknown

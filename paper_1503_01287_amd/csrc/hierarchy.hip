@@ -138,6 +138,32 @@ static DMat spgemm(const DMat &X, const DMat &Y, bool search_y, hipStream_t s) {
 
 // Lanes per row for a row kernel: the smallest power of two (4..64) not
 // below the mean entries per row.
+// The operator without its numerically zero entries (all planes zero, the
+// diagonal of a square operator always kept): on these meshes the Dirichlet
+// couplings removed by the symmetric elimination and couplings that vanish
+// on the Kuhn split. False, with out untouched, when there are none.
+static bool drop_zero_entries(const DMat &m, bool square, DMat &out, hipStream_t s) {
+    if (m.nnz == 0 || m.nrows == 0) return false;
+    DevBuf<int> cnt(static_cast<size_t>(m.nrows));
+    launch_count_kept(m.np, m.nrows, square, m.rowptr.p, m.col.p, m.val.p, m.nnz, cnt.p, s);
+    const std::vector<int> c = cnt.download(s);
+    std::vector<int> rp(static_cast<size_t>(m.nrows) + 1, 0);
+    for (int i = 0; i < m.nrows; ++i) rp[i + 1] = rp[i] + c[i];
+    if (rp.back() == m.nnz) return false;
+    out = DMat();
+    out.nrows = m.nrows;
+    out.ncols = m.ncols;
+    out.np = m.np;
+    out.nnz = rp.back();
+    out.rowptr.upload(rp, s);
+    out.col.alloc(static_cast<size_t>(std::max<int64_t>(1, out.nnz)));
+    out.val.alloc(static_cast<size_t>(std::max<int64_t>(1, out.nnz * out.np)));
+    launch_compact_rows(m.np, m.nrows, square, m.rowptr.p, m.col.p, m.val.p, m.nnz, out.rowptr.p, out.col.p,
+                        out.val.p, out.nnz, s);
+    AMG_HIP(hipStreamSynchronize(s));
+    return true;
+}
+
 int lanes_for(int64_t nnz, int nrows) {
     const double avg = nrows > 0 ? static_cast<double>(nnz) / nrows : 1.0;
     int G = 4;
@@ -204,8 +230,9 @@ static void setup_smoother(amg_ctx *h, Level &L) {
     std::partial_sum(L.cptr.begin(), L.cptr.end(), L.cptr.begin());
     std::vector<int> grp(L.n + 1, 0);
     L.colour_nnz.assign(ncol, 0);
+    const std::vector<int> arp = L.A.rowptr.download(s);  // stored rows (zero blocks dropped)
     for (int g = 0; g < L.n; ++g) {
-        const int len = L.hpat.rowptr[order[g] + 1] - L.hpat.rowptr[order[g]];
+        const int len = arp[order[g] + 1] - arp[order[g]];
         grp[g + 1] = grp[g] + len;
         L.colour_nnz[L.colour[order[g]]] += len;
     }
@@ -963,6 +990,18 @@ void build_hierarchy(amg_ctx *h, const amg_system *sys) {
         L.npA = L.coarsest ? 0 : L.n_pres;
     }
     if (p.omega_model && p.smoother == AMG_SMOOTH_JA && !h->saddle) predict_level_omega(h);
+    // Coarsening, the Galerkin products and the row features above used the
+    // structural patterns. From here on every level keeps A without its
+    // numerically zero blocks: the smoother setup, the tuners, the
+    // reduced-precision copies and the solve-phase kernels stream that
+    // (the same operator, fewer bytes); the structural A stays for export.
+    for (Level &L : h->lv) {
+        DMat c;
+        if (drop_zero_entries(L.A, true, c, s)) {
+            L.A_pat = std::move(L.A);
+            L.A = std::move(c);
+        }
+    }
     for (Level &L : h->lv) {
         const size_t nv = static_cast<size_t>(L.vlen());
         L.x.alloc(nv);
@@ -983,6 +1022,17 @@ void build_hierarchy(amg_ctx *h, const amg_system *sys) {
         }
     if (h->saddle && p.smoother == AMG_SMOOTH_VANKA)
         for (int l = 0; l + 1 < static_cast<int>(h->lv.size()); ++l) setup_vanka(h, l);
+    // B and B^T likewise, once the Schur complements and the Vanka patches
+    // (defined on B's structural pattern) are built
+    if (h->saddle)
+        for (Level &L : h->lv) {
+            DMat c;
+            if (drop_zero_entries(L.B, false, c, s)) {
+                L.B_pat = std::move(L.B);
+                L.B = std::move(c);
+            }
+            if (drop_zero_entries(L.Bt, false, c, s)) L.Bt = std::move(c);
+        }
     if (!h->saddle) {
         setup_tail(h);
         build_mixed(h);

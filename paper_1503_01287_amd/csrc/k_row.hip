@@ -508,4 +508,65 @@ void launch_gather_rows(int np, int nrows, const int *order, const int *rowptr, 
     AMG_CHECK_LAUNCH();
 }
 
+// Entry k of row i is kept when it is the diagonal of a square operator or
+// one of its np planes is nonzero.
+__device__ inline bool kept_entry(int np, const double *val, int64_t nnz, int64_t k, bool diag) {
+    if (diag) return true;
+    for (int p = 0; p < np; ++p)
+        if (val[p * nnz + k] != 0.0) return true;
+    return false;
+}
+
+// One wavefront per row: the row's kept entries.
+__global__ void k_count_kept(int np, int nrows, int square, const int *rowptr, const int *col, const double *val,
+                             int64_t nnz, int *count) {
+    const int i = blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (i >= nrows) return;
+    int c = 0;
+    for (int k = rowptr[i] + lane; k < rowptr[i + 1]; k += 64)
+        c += kept_entry(np, val, nnz, k, square && col[k] == i) ? 1 : 0;
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+    if (lane == 0) count[i] = c;
+}
+
+// One wavefront per row: the kept entries in their order, placed by a
+// prefix count over the wavefront's ballot.
+__global__ void k_compact_rows(int np, int nrows, int square, const int *rowptr, const int *col, const double *val,
+                               int64_t nnz, const int *c_rowptr, int *c_col, double *c_val, int64_t c_nnz) {
+    const int i = blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (i >= nrows) return;
+    int dst = c_rowptr[i];
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    for (int k0 = rowptr[i]; k0 < rowptr[i + 1]; k0 += 64) {
+        const int k = k0 + lane;
+        const bool keep = k < rowptr[i + 1] && kept_entry(np, val, nnz, k, square && col[k] == i);
+        const uint64_t mask = __ballot(keep);
+        if (keep) {
+            const int64_t d = dst + __popcll(mask & below);
+            c_col[d] = col[k];
+            for (int p = 0; p < np; ++p) c_val[p * c_nnz + d] = val[p * nnz + k];
+        }
+        dst += __popcll(mask);
+    }
+}
+
+void launch_count_kept(int np, int nrows, bool square, const int *rowptr, const int *col, const double *val,
+                       int64_t nnz, int *count, hipStream_t s) {
+    if (nrows <= 0) return;
+    k_count_kept<<<ceil_div(nrows, BLOCK / 64), BLOCK, 0, s>>>(np, nrows, square ? 1 : 0, rowptr, col, val, nnz,
+                                                                count);
+    AMG_CHECK_LAUNCH();
+}
+
+void launch_compact_rows(int np, int nrows, bool square, const int *rowptr, const int *col, const double *val,
+                         int64_t nnz, const int *c_rowptr, int *c_col, double *c_val, int64_t c_nnz,
+                         hipStream_t s) {
+    if (nrows <= 0) return;
+    k_compact_rows<<<ceil_div(nrows, BLOCK / 64), BLOCK, 0, s>>>(np, nrows, square ? 1 : 0, rowptr, col, val, nnz,
+                                                                  c_rowptr, c_col, c_val, c_nnz);
+    AMG_CHECK_LAUNCH();
+}
+
 }  // namespace amgp2

@@ -108,6 +108,15 @@ void launch_gather_rows(int np, int nrows, const int *order, const int *rowptr, 
                         const double *val, int64_t nnz, const int *g_rowptr, int *g_col,
                         double *g_val, hipStream_t s);
 
+// Dropping numerically zero entries (all planes zero; the diagonal of a
+// square operator is always kept): count per row, then the kept entries in
+// their order into (c_rowptr, c_col, c_val) with c_nnz entries.
+void launch_count_kept(int np, int nrows, bool square, const int *rowptr, const int *col, const double *val,
+                       int64_t nnz, int *count, hipStream_t s);
+void launch_compact_rows(int np, int nrows, bool square, const int *rowptr, const int *col, const double *val,
+                         int64_t nnz, const int *c_rowptr, int *c_col, double *c_val, int64_t c_nnz,
+                         hipStream_t s);
+
 // Galerkin SpGEMM C = X Y on node patterns (setup's hot loop).
 // Symbolic phases use a hash set in LDS per wavefront; numeric phases let
 // each lane own one output entry and sum its products in a fixed order, so

@@ -156,3 +156,39 @@ def test_saddle_stationary_iteration():
     x = torch.zeros_like(b)
     res = s.solve(b, x, tol=1e-6, maxit=2000)
     assert res.converged, res
+
+
+@pytest.mark.parametrize("smoother", ["sGS-1-1", "BS-1-1"])
+def test_zero_blocks_dropped_after_setup(smoother):
+    """After the pattern-based setup the solve kernels stream A and B without
+    their numerically zero blocks (here the cavity's Dirichlet couplings): on
+    every level the kept counts equal the nonzero blocks (plus A's diagonal)
+    of the exported structural operators, those still equal the oracle's,
+    and the operator and one cycle still equal the oracle's."""
+    hs, o = amg.problems.stokes_cavity(5, 1.1), workloads.stokes(5, 1.1)
+    s = amg.AMGSolver(hs, smoother=smoother, krylov="FGMRES")
+    h = _oh(o)
+    dropped = 0
+    for l, lev in enumerate(h.levels):
+        info = s.level_info(l)
+        rp, col, val = s.level_matrix(l, "A")
+        assert np.array_equal(rp, lev.A.indptr) and np.array_equal(col, lev.A.indices)
+        rows = np.repeat(np.arange(len(rp) - 1), np.diff(rp))
+        keep = (np.abs(val).max(axis=1) > 0) | (col == rows)
+        assert info.kept_A == keep.sum() and info.nnz_A == len(col), l
+        _, _, bval = s.level_matrix(l, "B")
+        assert info.kept_B == (np.abs(bval).max(axis=1) > 0).sum() and info.nnz_B == len(bval), l
+        dropped += info.nnz_A - info.kept_A
+    assert dropped > 0
+    rng = np.random.default_rng(22)
+    z = rng.standard_normal(hs.dofs)
+    y = torch.zeros(hs.dofs, dtype=torch.float64, device=DEV)
+    s.apply(0, dev(z), y)
+    assert rel(host(y), _mv(o)(z)) < 1e-13
+    if smoother.startswith("BS"):
+        oamg.prepare_bs(h)
+    prec = oamg.preconditioner(h, oamg.Smoother.parse(smoother))
+    zc = torch.zeros(hs.dofs, dtype=torch.float64, device=DEV)
+    s.precondition(dev(z), zc)
+    assert rel(host(zc), prec(z)) < 1e-10
+    s.close()
