@@ -22,19 +22,23 @@ struct ChunkView {
 // partial[j * n + c] = <V_j, w> over chunk c, j < k (V_j = V + j * ld)
 void launch_seg_multidot(const double *V, int64_t ld, int k, const double *w, const ChunkView &t, double *partial,
                          hipStream_t s);
+// the same for the chunks of the systems s with want[s] != 0 only
+void launch_seg_multidot_masked(const double *V, int64_t ld, int k, const double *w, const ChunkView &t,
+                                const int *want, double *partial, hipStream_t s);
+// two right-hand sides in one pass over the basis: partial[(r * k + j) * n
+// + c] holds <V_j, a> (r = 0) and <V_j, b> (r = 1) over chunk c
+void launch_seg_multidot2(const double *V, int64_t ld, int k, const double *a, const double *b, const ChunkView &t,
+                          double *partial, hipStream_t s);
 // h[i * kmax + j] = sum of partial[j * n + c] over the chunks c of system i:
 // [c0[i], c1[i]) then [c2[i], c3[i]) in order
 void launch_seg_reduce(const double *partial, int n, int k, int nsys, const int *c0, const int *c1, const int *c2,
                        const int *c3, double *h, int kmax, hipStream_t s);
-// w -= sum_{j<k} h[seg * kmax + j] V_j
-void launch_seg_multi_axpy(const double *V, int64_t ld, int k, const double *h, int kmax, double *w,
-                           const ChunkView &t, hipStream_t s);
-// the same, then w /= hn per system with hn = sqrt(h[k] - sum_{j<k} h[j]^2)
-// (the new norm by Pythagoras when h[k] = <w, w> and the V_j are
-// orthonormal), stored in h[seg * kmax + k + 1] (needs k + 2 <= kmax); a
-// system with hn == 0 keeps its w unscaled
-void launch_seg_multi_axpy_normalize(const double *V, int64_t ld, int k, double *h, int kmax, double *w,
-                                     const ChunkView &t, int nsys, hipStream_t s);
+// Delayed reorthogonalisation step of every system on basis slots j
+// (pending vector) and j + 1 (new vector), as launch_dcgs2_update, with
+// system s's dots of launch_multidot2 over V_0..V_{j+1} at h + s * stride
+// (2 (j + 2) values) and its gamma, d, eta written after them
+void launch_seg_dcgs2_update(double *V, int64_t ld, int j, double *h, int stride, const ChunkView &t, bool reorth,
+                             hipStream_t s);
 // y = coef[seg] * x
 void launch_seg_scale(const double *x, double *y, const double *coef, const ChunkView &t, hipStream_t s);
 // x += sum_{j < cnt[seg]} y[seg * kmax + j] Z_j

@@ -410,133 +410,166 @@ static void seg_norms(amg_ctx *h, const double *v, DevBuf<double> &partial, DevB
     for (int i = 0; i < h->nsys; ++i) out[i] = std::sqrt(tmp[static_cast<size_t>(i) * kmax]);
 }
 
-// Right-preconditioned FGMRES(m) with classical Gram-Schmidt twice, one
-// Krylov process per system, advanced in lockstep: every launch serves all
-// systems; a system that has converged stops taking Arnoldi steps (its
-// columns are left out of its update) while the others continue.
+// Right-preconditioned FGMRES(m), one Krylov process per system, advanced in
+// lockstep: every launch serves all systems; a system that has converged
+// stops taking Arnoldi steps (its columns are left out of its update) while
+// the others continue. Orthogonalisation as in solve_fgmres (classical
+// Gram-Schmidt with delayed reorthogonalisation, one pass of dots and one
+// update per step, Hessenberg columns completed one step late or, when a
+// system's provisional estimate meets the tolerance or the cycle ends, by one
+// more pass over that system's chunks of the basis).
 int solve_fgmres_batched(amg_ctx *h, const double *b, double *x, double tol, int maxit, amg_result *res) {
     const auto t0 = std::chrono::steady_clock::now();
     const int ns = h->nsys;
     const int64_t n = h->n_dof;
     const int m = std::max(1, h->prm.restart);
-    const int kmax = m + 1;
     if (h->gm_m != m) {
         h->gm_V.alloc(static_cast<size_t>(m + 1) * n);
         h->gm_Z.alloc(static_cast<size_t>(m) * n);
         h->gm_m = m;
     }
     const ChunkView t = h->b_chunks.view();
-    // hb: first-pass coefficients (stride kmax), then hb2: second-pass
-    // coefficients, <w1, w1> and the new norm (stride kmax2)
-    const int kmax2 = m + 2;
-    DevBuf<double> partial(static_cast<size_t>(kmax) * std::max(1, t.n)), hb(static_cast<size_t>(ns) * (kmax + kmax2)),
-        coef(ns), ycoef(static_cast<size_t>(ns) * m);
-    DevBuf<int> cnt(ns);
-    double *V = h->gm_V.p, *Z = h->gm_Z.p, *hb2 = hb.p + static_cast<size_t>(ns) * kmax;
-    std::vector<double> H(static_cast<size_t>(ns) * (m + 1) * m), cs(static_cast<size_t>(ns) * m),
-        sn(static_cast<size_t>(ns) * m), g(static_cast<size_t>(ns) * (m + 1)), hcol(static_cast<size_t>(ns) * kmax),
-        hp(static_cast<size_t>(ns) * (kmax + kmax2));
-    std::vector<double> beta, r0, hn;
-    std::vector<int> status(ns, AMG_NOT_CONVERGED), iters(ns, 0), jcnt(ns, 0);
-    std::vector<char> active(ns, 0), running(ns, 0);
+    // per system: the dots of a step (2 (m + 2)), then gamma, d, eta
+    const int stride = 2 * (m + 2) + 4;
+    DevBuf<double> partial(static_cast<size_t>(2 * (m + 2)) * std::max(1, t.n)),
+        hb(static_cast<size_t>(ns) * stride), coef(ns), ycoef(static_cast<size_t>(ns) * m);
+    DevBuf<int> cnt(ns), want(ns);
+    double *V = h->gm_V.p, *Z = h->gm_Z.p;
+    // per system: H rotated columns (row-major q * m + c), Hr raw columns
+    // (column c at c * (m + 1)), rotations, g, pending scales eta
+    const size_t hsz = static_cast<size_t>(m + 1) * m;
+    std::vector<double> H(ns * hsz), Hr(ns * hsz), cs(static_cast<size_t>(ns) * m), sn(static_cast<size_t>(ns) * m),
+        g(static_cast<size_t>(ns) * (m + 1)), eta(static_cast<size_t>(ns) * (m + 1), 1.0), hcol(m + 2),
+        hp(static_cast<size_t>(ns) * stride);
+    std::vector<double> beta, r0;
+    std::vector<int> status(ns, AMG_NOT_CONVERGED), iters(ns, 0), jcnt(ns, 0), wanth(ns, 0);
+    std::vector<char> active(ns, 0), running(ns, 0), done(static_cast<size_t>(ns) * m, 0);
     std::vector<double> hc(ns);
-    std::vector<char> fix(ns, 0);
     system_residual(h, b, x, V);
-    seg_norms(h, V, partial, hb, kmax, r0);
+    seg_norms(h, V, partial, hb, stride, r0);
     beta = r0;
-    hn.assign(ns, 0.0);
     for (int i = 0; i < ns; ++i) {
         if (!(r0[i] == r0[i])) status[i] = AMG_DIVERGED;
         else if (r0[i] == 0.0) status[i] = AMG_OK;
         else active[i] = 1;
     }
     auto any = [&](const std::vector<char> &v) { return std::any_of(v.begin(), v.end(), [](char c) { return c != 0; }); };
+    // system i: rotations 0..c-1 on raw column c, rotation c, g; returns the
+    // residual estimate after c + 1 columns (commit) or only that estimate
+    auto rotate = [&](int i, int c, bool commit) {
+        const double *raw = &Hr[i * hsz + static_cast<size_t>(c) * (m + 1)];
+        double *csi = &cs[static_cast<size_t>(i) * m], *sni = &sn[static_cast<size_t>(i) * m];
+        double *gi = &g[static_cast<size_t>(i) * (m + 1)];
+        for (int q = 0; q <= c + 1; ++q) hcol[q] = raw[q];
+        for (int q = 0; q < c; ++q) {
+            const double tq = csi[q] * hcol[q] + sni[q] * hcol[q + 1];
+            hcol[q + 1] = -sni[q] * hcol[q] + csi[q] * hcol[q + 1];
+            hcol[q] = tq;
+        }
+        const double den = std::hypot(hcol[c], hcol[c + 1]);
+        if (!commit) return den > 0.0 ? std::fabs(hcol[c + 1] / den * gi[c]) / r0[i] : 0.0;
+        csi[c] = den > 0.0 ? hcol[c] / den : 1.0;
+        sni[c] = den > 0.0 ? hcol[c + 1] / den : 0.0;
+        hcol[c] = den;
+        gi[c + 1] = -sni[c] * gi[c];
+        gi[c] = csi[c] * gi[c];
+        double *Hi = &H[i * hsz];
+        for (int q = 0; q <= c; ++q) Hi[static_cast<size_t>(q) * m + c] = hcol[q];
+        return std::fabs(gi[c + 1]) / r0[i];
+    };
+    // a completed column's test: false when system i stops taking steps
+    auto judge = [&](int i, double est, bool breakdown) {
+        if (!(est == est) || est > 1e3) {
+            status[i] = AMG_DIVERGED;
+            running[i] = 0;
+            active[i] = 0;
+            return false;
+        }
+        if (est <= tol || breakdown) {
+            running[i] = 0;
+            return false;
+        }
+        return true;
+    };
     int it = 0;
     while (any(active) && it < maxit) {
         for (int i = 0; i < ns; ++i) hc[i] = active[i] && beta[i] > 0.0 ? 1.0 / beta[i] : 0.0;
         AMG_HIP(hipMemcpyAsync(coef.p, hc.data(), ns * sizeof(double), hipMemcpyHostToDevice, h->stream));
         launch_seg_scale(V, V, coef.p, t, h->stream);
         std::fill(g.begin(), g.end(), 0.0);
+        std::fill(done.begin(), done.end(), 0);
         for (int i = 0; i < ns; ++i) {
             g[static_cast<size_t>(i) * (m + 1)] = active[i] ? beta[i] : 0.0;
             running[i] = active[i];
             jcnt[i] = 0;
         }
-        for (int j = 0; j < m && any(running) && it < maxit; ++j) {
+        for (int j = 0; j < m && any(running) && it < maxit; ++j, ++it) {
             double *vj = V + static_cast<int64_t>(j) * n, *w = V + static_cast<int64_t>(j + 1) * n;
             double *zj = Z + static_cast<int64_t>(j) * n;
             precondition_any(h, vj, zj);
             system_matvec(h, zj, w);
-            // classical Gram-Schmidt, twice, with one host synchronisation:
-            // the second pass also returns <w1_i, w1_i> (w is basis slot
-            // j + 1), the new norms follow by Pythagoras and the last update
-            // normalises every system's w on the device
-            launch_seg_multidot(V, n, j + 1, w, t, partial.p, h->stream);
-            launch_seg_reduce(partial.p, t.n, j + 1, ns, h->b_c0.p, h->b_c1.p, h->b_c2.p, h->b_c3.p, hb.p, kmax,
+            const int k = j + 2;
+            launch_seg_multidot2(V, n, k, vj, w, t, partial.p, h->stream);
+            launch_seg_reduce(partial.p, t.n, 2 * k, ns, h->b_c0.p, h->b_c1.p, h->b_c2.p, h->b_c3.p, hb.p, stride,
                               h->stream);
-            launch_seg_multi_axpy(V, n, j + 1, hb.p, kmax, w, t, h->stream);
-            launch_seg_multidot(V, n, j + 2, w, t, partial.p, h->stream);
-            launch_seg_reduce(partial.p, t.n, j + 2, ns, h->b_c0.p, h->b_c1.p, h->b_c2.p, h->b_c3.p, hb2, kmax2,
-                              h->stream);
-            launch_seg_multi_axpy_normalize(V, n, j + 1, hb2, kmax2, w, t, ns, h->stream);
+            launch_seg_dcgs2_update(V, n, j, hb.p, stride, t, j > 0, h->stream);
             AMG_HIP(hipMemcpyAsync(hp.data(), hb.p, hp.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream));
             AMG_HIP(hipStreamSynchronize(h->stream));
-            const double *hp2 = hp.data() + static_cast<size_t>(ns) * kmax;
-            bool remeasure = false;
+            const bool last = j + 1 == m || it + 1 >= maxit;
+            bool cleanup = false;
             for (int i = 0; i < ns; ++i) {
-                for (int q = 0; q <= j; ++q)
-                    hcol[static_cast<size_t>(i) * kmax + q] =
-                        hp[static_cast<size_t>(i) * kmax + q] + hp2[static_cast<size_t>(i) * kmax2 + q];
-                hn[i] = hp2[static_cast<size_t>(i) * kmax2 + j + 2];
-                // Pythagoras loses digits when the second pass removed a
-                // large part of w1: measure that system's norm instead
-                fix[i] = running[i] && hn[i] * hn[i] < 1e-4 * hp2[static_cast<size_t>(i) * kmax2 + j + 1];
-                remeasure |= fix[i] != 0;
-            }
-            if (remeasure) {
-                std::vector<double> a;
-                seg_norms(h, w, partial, hb, kmax, a);
-                for (int i = 0; i < ns; ++i) {
-                    hc[i] = 1.0;
-                    if (!fix[i]) continue;
-                    if (a[i] > 0.0) hc[i] = 1.0 / a[i];
-                    hn[i] = hn[i] > 0.0 ? hn[i] * a[i] : a[i];
-                }
-                AMG_HIP(hipMemcpyAsync(coef.p, hc.data(), ns * sizeof(double), hipMemcpyHostToDevice, h->stream));
-                launch_seg_scale(w, w, coef.p, t, h->stream);
-            }
-            for (int i = 0; i < ns; ++i) {
+                wanth[i] = 0;
                 if (!running[i]) continue;
-                double *hcl = &hcol[static_cast<size_t>(i) * kmax];
-                double *csi = &cs[static_cast<size_t>(i) * m], *sni = &sn[static_cast<size_t>(i) * m];
-                double *gi = &g[static_cast<size_t>(i) * (m + 1)];
-                double *Hi = &H[static_cast<size_t>(i) * (m + 1) * m];
-                hcl[j + 1] = hn[i];
-                for (int q = 0; q < j; ++q) {
-                    const double tq = csi[q] * hcl[q] + sni[q] * hcl[q + 1];
-                    hcl[q + 1] = -sni[q] * hcl[q] + csi[q] * hcl[q + 1];
-                    hcl[q] = tq;
+                const double *hi = &hp[static_cast<size_t>(i) * stride];
+                const double *dA = hi, *dB = hi + k;
+                const double gam = hi[2 * k], d = hi[2 * k + 1], et = hi[2 * k + 2];
+                double *ei = &eta[static_cast<size_t>(i) * (m + 1)];
+                char *di = &done[static_cast<size_t>(i) * m];
+                if (j > 0 && !di[j - 1]) {
+                    // u_j = V s + gamma v_j completes column j - 1
+                    double *c1 = &Hr[i * hsz + static_cast<size_t>(j - 1) * (m + 1)];
+                    for (int q = 0; q < j; ++q) c1[q] += ei[j] * dA[q];
+                    c1[j] = ei[j] * gam;
+                    di[j - 1] = 1;
+                    jcnt[i] = j;
+                    if (!judge(i, rotate(i, j - 1, true), gam == 0.0)) continue;
                 }
-                const double den = std::hypot(hcl[j], hcl[j + 1]);
-                csi[j] = den > 0.0 ? hcl[j] / den : 1.0;
-                sni[j] = den > 0.0 ? hcl[j + 1] / den : 0.0;
-                hcl[j] = den;
-                gi[j + 1] = -sni[j] * gi[j];
-                gi[j] = csi[j] * gi[j];
-                for (int q = 0; q <= j; ++q) Hi[static_cast<size_t>(q) * m + j] = hcl[q];
-                ++iters[i];
-                jcnt[i] = j + 1;
-                const double est = std::fabs(gi[j + 1]) / r0[i];
-                if (!(est == est) || est > 1e3) {
-                    status[i] = AMG_DIVERGED;
-                    running[i] = 0;
-                    active[i] = 0;
-                } else if (est <= tol || hn[i] == 0.0) {
-                    running[i] = 0;
+                double *cj = &Hr[i * hsz + static_cast<size_t>(j) * (m + 1)];
+                for (int q = 0; q < j; ++q) cj[q] = dB[q];
+                cj[j] = d;
+                cj[j + 1] = et;
+                ei[j + 1] = et;
+                wanth[i] = last || et == 0.0 || rotate(i, j, false) <= tol;
+                cleanup |= wanth[i] != 0;
+            }
+            if (cleanup) {
+                // complete column j of the flagged systems: V_{0..j} . u_{j+1}, |u_{j+1}|^2
+                AMG_HIP(hipMemcpyAsync(want.p, wanth.data(), ns * sizeof(int), hipMemcpyHostToDevice, h->stream));
+                launch_seg_multidot_masked(V, n, k, w, t, want.p, partial.p, h->stream);
+                launch_seg_reduce(partial.p, t.n, k, ns, h->b_c0.p, h->b_c1.p, h->b_c2.p, h->b_c3.p, hb.p, stride,
+                                  h->stream);
+                AMG_HIP(hipMemcpyAsync(hp.data(), hb.p, hp.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                       h->stream));
+                AMG_HIP(hipStreamSynchronize(h->stream));
+                for (int i = 0; i < ns; ++i) {
+                    if (!wanth[i]) continue;
+                    const double *si = &hp[static_cast<size_t>(i) * stride];
+                    const double et = eta[static_cast<size_t>(i) * (m + 1) + j + 1];
+                    double *cj = &Hr[i * hsz + static_cast<size_t>(j) * (m + 1)];
+                    double ss = 0.0;
+                    for (int q = 0; q <= j; ++q) {
+                        ss += si[q] * si[q];
+                        cj[q] += et * si[q];
+                    }
+                    const double g2 = si[j + 1] - ss;
+                    cj[j + 1] = et * (g2 > 0.0 ? std::sqrt(g2) : 0.0);
+                    done[static_cast<size_t>(i) * m + j] = 1;
+                    jcnt[i] = j + 1;
+                    judge(i, rotate(i, j, true), cj[j + 1] == 0.0);
                 }
             }
-            ++it;
         }
+        for (int i = 0; i < ns; ++i) iters[i] += jcnt[i];
         // x_i += Z y_i with y_i = R_i^{-1} g_i over the system's own columns
         std::vector<double> Y(static_cast<size_t>(ns) * m, 0.0);
         for (int i = 0; i < ns; ++i) {
@@ -554,7 +587,7 @@ int solve_fgmres_batched(amg_ctx *h, const double *b, double *x, double tol, int
         AMG_HIP(hipMemcpyAsync(cnt.p, jcnt.data(), ns * sizeof(int), hipMemcpyHostToDevice, h->stream));
         launch_seg_multi_add(Z, n, ycoef.p, m, cnt.p, x, t, h->stream);
         system_residual(h, b, x, V);
-        seg_norms(h, V, partial, hb, kmax, beta);
+        seg_norms(h, V, partial, hb, stride, beta);
         for (int i = 0; i < ns; ++i)
             if (active[i] && beta[i] / r0[i] <= tol) {
                 status[i] = AMG_OK;
@@ -563,7 +596,7 @@ int solve_fgmres_batched(amg_ctx *h, const double *b, double *x, double tol, int
     }
     system_residual(h, b, x, h->kw.p);
     std::vector<double> fin;
-    seg_norms(h, h->kw.p, partial, hb, kmax, fin);
+    seg_norms(h, h->kw.p, partial, hb, stride, fin);
     const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     int worst = AMG_OK;
     for (int j = 0; j < ns; ++j) {

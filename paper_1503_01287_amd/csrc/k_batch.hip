@@ -21,35 +21,146 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
     return t;
 }
 
-__global__ void __launch_bounds__(CB) k_seg_multidot(const double *V, int64_t ld, int k, const double *w,
-                                                     const ChunkView t, double *partial) {
-    __shared__ double red[CB / 64];
+// Workgroup (c, g) dots chunk c of the NR right-hand sides (held in
+// registers) with the same chunk of basis vectors g * SMD_VEC ..
+// g * SMD_VEC + SMD_VEC - 1: every basis chunk is read once for all
+// right-hand sides and one block reduction serves the whole group. Right-
+// hand side r's dot with vector j goes to partial[(r * k + j) * n_chunks + c].
+// With `want`, chunks of systems s with want[s] == 0 are skipped (their
+// partial entries are left as they were).
+constexpr int SMD_VEC = 8;
+
+template <int NR>
+__global__ void __launch_bounds__(CB) k_seg_multidot(const double *V, int64_t ld, int k, const double *w0,
+                                                     const double *w1, const ChunkView t, const int *want,
+                                                     double *partial) {
+    __shared__ double red[NR * SMD_VEC][CB / 64];
     const int c = blockIdx.x;
+    if (want && !want[t.seg[c]]) return;
     const int64_t s0 = t.start[c];
     const int len = t.len[c];
-    double wv[PER];
+    const int j0 = blockIdx.y * SMD_VEC;
+    const int nv = min(SMD_VEC, k - j0);
+    double wv[NR][PER];
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
         const int i = threadIdx.x + e * CB;
-        wv[e] = i < len ? w[s0 + i] : 0.0;
+        wv[0][e] = i < len ? w0[s0 + i] : 0.0;
+        if (NR == 2) wv[NR - 1][e] = i < len ? w1[s0 + i] : 0.0;
     }
-    for (int j = 0; j < k; ++j) {
-        const double *v = V + j * ld + s0;
-        double a = 0.0;
 #pragma unroll
-        for (int e = 0; e < PER; ++e) {
-            const int i = threadIdx.x + e * CB;
-            if (i < len) a += v[i] * wv[e];
+    for (int q = 0; q < SMD_VEC; ++q) {
+        double acc[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) acc[r] = 0.0;
+        if (q < nv) {
+            const double *v = V + (j0 + q) * ld + s0;
+#pragma unroll
+            for (int e = 0; e < PER; ++e) {
+                const int i = threadIdx.x + e * CB;
+                if (i < len) {
+                    const double vi = v[i];
+#pragma unroll
+                    for (int r = 0; r < NR; ++r) acc[r] += vi * wv[r][e];
+                }
+            }
         }
-        a = block_sum(a, red);
-        if (threadIdx.x == 0) partial[static_cast<int64_t>(j) * t.n + c] = a;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            double a = acc[r];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+            if ((threadIdx.x & 63) == 0) red[r * SMD_VEC + q][threadIdx.x >> 6] = a;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < NR * nv) {
+        const int r = threadIdx.x / nv, q = threadIdx.x % nv;
+        double a = 0.0;
+        for (int w = 0; w < CB / 64; ++w) a += red[r * SMD_VEC + q][w];
+        partial[(static_cast<int64_t>(r) * k + j0 + q) * t.n + c] = a;
     }
 }
 
 void launch_seg_multidot(const double *V, int64_t ld, int k, const double *w, const ChunkView &t, double *partial,
                          hipStream_t s) {
+    launch_seg_multidot_masked(V, ld, k, w, t, nullptr, partial, s);
+}
+
+void launch_seg_multidot_masked(const double *V, int64_t ld, int k, const double *w, const ChunkView &t,
+                                const int *want, double *partial, hipStream_t s) {
     if (t.n <= 0 || k <= 0) return;
-    k_seg_multidot<<<t.n, CB, 0, s>>>(V, ld, k, w, t, partial);
+    k_seg_multidot<1><<<dim3(t.n, ceil_div(k, SMD_VEC)), CB, 0, s>>>(V, ld, k, w, w, t, want, partial);
+    AMG_CHECK_LAUNCH();
+}
+
+void launch_seg_multidot2(const double *V, int64_t ld, int k, const double *a, const double *b, const ChunkView &t,
+                          double *partial, hipStream_t s) {
+    if (t.n <= 0 || k <= 0) return;
+    k_seg_multidot<2><<<dim3(t.n, ceil_div(k, SMD_VEC)), CB, 0, s>>>(V, ld, k, a, b, t, nullptr, partial);
+    AMG_CHECK_LAUNCH();
+}
+
+// The delayed-reorthogonalisation step of every system (see
+// launch_seg_dcgs2_update): chunk c takes its system's dots from
+// h + seg * stride.
+__global__ void __launch_bounds__(CB) k_seg_dcgs2_update(double *V, int64_t ld, int j, double *h, int stride,
+                                                         const ChunkView t, int reorth) {
+    const int c = blockIdx.x;
+    const int64_t s0 = t.start[c];
+    const int len = t.len[c];
+    double *hs = h + static_cast<int64_t>(t.seg[c]) * stride;
+    const int k = j + 2;
+    const double *dA = hs, *dB = hs + k;
+    double ss = 0.0, sc = 0.0, cc = 0.0;
+    for (int q = 0; q < j; ++q) {
+        if (reorth) {
+            ss += dA[q] * dA[q];
+            sc += dA[q] * dB[q];
+        }
+        cc += dB[q] * dB[q];
+    }
+    double gam = 1.0;
+    if (reorth) {
+        const double g2 = dA[j] - ss;
+        gam = g2 > 0.0 ? sqrt(g2) : 0.0;
+    }
+    const double gs = gam > 0.0 ? gam : 1.0;
+    const double d = reorth ? (dB[j] - sc) / gs : dB[j];
+    const double omega = dB[j + 1];
+    const double eta = sqrt(fmax(omega - cc - d * d, 1e-4 * omega));
+    const double ig = 1.0 / gs, ie = eta > 0.0 ? 1.0 / eta : 1.0;
+    double *vj = V + static_cast<int64_t>(j) * ld + s0, *w = V + static_cast<int64_t>(j + 1) * ld + s0;
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+        const int i = threadIdx.x + e * CB;
+        if (i >= len) continue;
+        double as = 0.0, ac = 0.0;
+        for (int q = 0; q < j; ++q) {
+            const double v = V[q * ld + s0 + i];
+            if (reorth) as += dA[q] * v;
+            ac += dB[q] * v;
+        }
+        double u = vj[i];
+        if (reorth) {
+            u = (u - as) * ig;
+            vj[i] = u;
+        }
+        w[i] = (w[i] - ac - d * u) * ie;
+    }
+    // every chunk of the system writes the same three values; the dots
+    // read above lie below them
+    if (threadIdx.x == 0) {
+        hs[2 * k] = gam;
+        hs[2 * k + 1] = d;
+        hs[2 * k + 2] = eta;
+    }
+}
+
+void launch_seg_dcgs2_update(double *V, int64_t ld, int j, double *h, int stride, const ChunkView &t, bool reorth,
+                             hipStream_t s) {
+    if (t.n <= 0) return;
+    k_seg_dcgs2_update<<<t.n, CB, 0, s>>>(V, ld, j, h, stride, t, reorth ? 1 : 0);
     AMG_CHECK_LAUNCH();
 }
 
@@ -71,53 +182,6 @@ void launch_seg_reduce(const double *partial, int n, int k, int nsys, const int 
                        const int *c3, double *h, int kmax, hipStream_t s) {
     if (nsys <= 0 || k <= 0) return;
     k_seg_reduce<<<nsys * k, CB, 0, s>>>(partial, n, k, c0, c1, c2, c3, h, kmax);
-    AMG_CHECK_LAUNCH();
-}
-
-__global__ void __launch_bounds__(CB) k_seg_multi_axpy(const double *V, int64_t ld, int k, const double *h,
-                                                       int kmax, double *w, const ChunkView t, int scaled) {
-    const int c = blockIdx.x;
-    const int64_t s0 = t.start[c];
-    const int len = t.len[c];
-    const double *hs = h + static_cast<int64_t>(t.seg[c]) * kmax;
-    double inv = 1.0;
-    if (scaled) {
-        const double hn = hs[k + 1];
-        inv = hn > 0.0 ? 1.0 / hn : 1.0;
-    }
-#pragma unroll
-    for (int e = 0; e < PER; ++e) {
-        const int i = threadIdx.x + e * CB;
-        if (i >= len) continue;
-        double a = w[s0 + i];
-        for (int j = 0; j < k; ++j) a -= hs[j] * V[j * ld + s0 + i];
-        w[s0 + i] = a * inv;
-    }
-}
-
-void launch_seg_multi_axpy(const double *V, int64_t ld, int k, const double *h, int kmax, double *w,
-                           const ChunkView &t, hipStream_t s) {
-    if (t.n <= 0 || k <= 0) return;
-    k_seg_multi_axpy<<<t.n, CB, 0, s>>>(V, ld, k, h, kmax, w, t, 0);
-    AMG_CHECK_LAUNCH();
-}
-
-// one thread per system: hn = sqrt(h[k] - sum_{j<k} h[j]^2) into h[k + 1]
-__global__ void k_seg_pythagoras(double *h, int k, int kmax, int nsys) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nsys) return;
-    double *hs = h + static_cast<int64_t>(i) * kmax;
-    double hsq = hs[k];
-    for (int j = 0; j < k; ++j) hsq -= hs[j] * hs[j];
-    hs[k + 1] = sqrt(fmax(hsq, 0.0));
-}
-
-void launch_seg_multi_axpy_normalize(const double *V, int64_t ld, int k, double *h, int kmax, double *w,
-                                     const ChunkView &t, int nsys, hipStream_t s) {
-    if (t.n <= 0 || nsys <= 0) return;
-    k_seg_pythagoras<<<ceil_div(nsys, CB), CB, 0, s>>>(h, k, kmax, nsys);
-    AMG_CHECK_LAUNCH();
-    k_seg_multi_axpy<<<t.n, CB, 0, s>>>(V, ld, k, h, kmax, w, t, 1);
     AMG_CHECK_LAUNCH();
 }
 

@@ -443,46 +443,59 @@ void launch_segment_store_column(const DenseSegView &d, int j, const double *xu,
 }
 
 // ---------------------------------------------------------------- FGMRES
-// Workgroup (c, g) dots the chunk c of w (MD_CHUNK entries, held in
-// registers) with the same chunk of the basis vectors g * MD_VEC ..
-// g * MD_VEC + MD_VEC - 1: one pass over w per group instead of one per
-// vector, and one block reduction for the whole group.
+// Workgroup (c, g) dots the chunk c of the NR right-hand sides (MD_CHUNK
+// entries each, held in registers) with the same chunk of the basis vectors
+// g * MD_VEC .. g * MD_VEC + MD_VEC - 1: one pass over the right-hand sides
+// per group instead of one per vector, every basis chunk read once for all
+// right-hand sides, and one block reduction for the whole group. Right-hand
+// side r's dot with vector q goes to partial[(r * k + q) * nb + c].
 constexpr int MD_PER = 2;
 constexpr int MD_CHUNK = MD_PER * SB;
 constexpr int MD_VEC = 8;
 
-__global__ void __launch_bounds__(SB) k_multidot(const double *V, int64_t ld, int k, const double *w, int64_t n,
-                                                 double *partial) {
-    __shared__ double red[MD_VEC][SB / 64];
+template <int NR>
+__global__ void __launch_bounds__(SB) k_multidot(const double *V, int64_t ld, int k, const double *w0,
+                                                 const double *w1, int64_t n, double *partial) {
+    __shared__ double red[NR * MD_VEC][SB / 64];
     const int64_t s0 = static_cast<int64_t>(blockIdx.x) * MD_CHUNK;
     const int j0 = blockIdx.y * MD_VEC;
     const int nv = min(MD_VEC, k - j0);
-    double wv[MD_PER];
+    double wv[NR][MD_PER];
 #pragma unroll
     for (int e = 0; e < MD_PER; ++e) {
         const int64_t t = s0 + threadIdx.x + e * SB;
-        wv[e] = t < n ? w[t] : 0.0;
+        wv[0][e] = t < n ? w0[t] : 0.0;
+        if (NR == 2) wv[NR - 1][e] = t < n ? w1[t] : 0.0;
     }
-    double acc[MD_VEC];
 #pragma unroll
     for (int q = 0; q < MD_VEC; ++q) {
-        acc[q] = 0.0;
+        double acc[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) acc[r] = 0.0;
         if (q < nv) {
             const double *v = V + (j0 + q) * ld;
 #pragma unroll
             for (int e = 0; e < MD_PER; ++e) {
                 const int64_t t = s0 + threadIdx.x + e * SB;
-                if (t < n) acc[q] += v[t] * wv[e];
+                if (t < n) {
+                    const double vt = v[t];
+#pragma unroll
+                    for (int r = 0; r < NR; ++r) acc[r] += vt * wv[r][e];
+                }
             }
         }
-        acc[q] = gsum<64>(acc[q]);
-        if ((threadIdx.x & 63) == 0) red[q][threadIdx.x >> 6] = acc[q];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const double a = gsum<64>(acc[r]);
+            if ((threadIdx.x & 63) == 0) red[r * MD_VEC + q][threadIdx.x >> 6] = a;
+        }
     }
     __syncthreads();
-    if (threadIdx.x < nv) {
+    if (threadIdx.x < NR * nv) {
+        const int r = threadIdx.x / nv, q = threadIdx.x % nv;
         double s = 0.0;
-        for (int q = 0; q < SB / 64; ++q) s += red[threadIdx.x][q];
-        partial[static_cast<int64_t>(j0 + threadIdx.x) * gridDim.x + blockIdx.x] = s;
+        for (int b = 0; b < SB / 64; ++b) s += red[r * MD_VEC + q][b];
+        partial[(static_cast<int64_t>(r) * k + j0 + q) * gridDim.x + blockIdx.x] = s;
     }
 }
 
@@ -492,7 +505,16 @@ int launch_multidot(const double *V, int64_t ld, int k, const double *w, int64_t
                     hipStream_t s) {
     if (k <= 0) return 0;
     const int nb = multidot_blocks(n);
-    k_multidot<<<dim3(nb, ceil_div(k, MD_VEC)), SB, 0, s>>>(V, ld, k, w, n, partial);
+    k_multidot<1><<<dim3(nb, ceil_div(k, MD_VEC)), SB, 0, s>>>(V, ld, k, w, w, n, partial);
+    AMG_CHECK_LAUNCH();
+    return nb;
+}
+
+int launch_multidot2(const double *V, int64_t ld, int k, const double *a, const double *b, int64_t n,
+                     double *partial, hipStream_t s) {
+    if (k <= 0) return 0;
+    const int nb = multidot_blocks(n);
+    k_multidot<2><<<dim3(nb, ceil_div(k, MD_VEC)), SB, 0, s>>>(V, ld, k, a, b, n, partial);
     AMG_CHECK_LAUNCH();
     return nb;
 }
@@ -514,37 +536,66 @@ void launch_multidot_reduce(const double *partial, int nb, int k, double *h, hip
     AMG_CHECK_LAUNCH();
 }
 
-// w -= V h; with `scaled`, the result is also divided by
-// hn = sqrt(h[k] - sum_i h[i]^2), the norm of the new w when w was already
-// orthogonal to the V_i up to a second Gram-Schmidt pass and h[k] = <w, w>
-// (Pythagoras); hn is written to h[k + 1].
-__global__ void k_multi_axpy(const double *V, int64_t ld, int k, double *h, double *w, int64_t n, int scaled) {
-    double inv = 1.0;
-    if (scaled) {
-        double hsq = h[k];
-        for (int i = 0; i < k; ++i) hsq -= h[i] * h[i];
-        const double hn = sqrt(fmax(hsq, 0.0));
-        inv = hn > 0.0 ? 1.0 / hn : 1.0;
-        if (blockIdx.x == 0 && threadIdx.x == 0) h[k + 1] = hn;
+// One step of classical Gram-Schmidt with delayed reorthogonalisation.
+// Basis slot j holds the pending vector u (orthogonalised once against
+// V_0..V_{j-1}), slot j + 1 the new vector w. With k = j + 2, h[0..k) are
+// the dots V_i . u and h[k..2k) the dots V_i . w (i <= j + 1). The update
+// finishes u: v_j = (u - sum_{i<j} s_i V_i) / gamma, s_i = V_i . u,
+// gamma^2 = u . u - |s|^2 (skipped when reorth is 0: v_j is final already),
+// and orthogonalises w once against V_0..V_{j-1}, v_j:
+// w' = w - sum_{i<j} c_i V_i - d v_j with c_i = V_i . w,
+// d = v_j . w = (u . w - s . c) / gamma, then scales it by
+// eta = sqrt(w . w - |c|^2 - d^2) (Pythagoras; any positive scale serves,
+// as the next step measures the new pending vector exactly, so a
+// cancelled estimate falls back to 1e-2 |w|). gamma, d and eta are written
+// to h[2k], h[2k + 1], h[2k + 2].
+__global__ void k_dcgs2_update(double *V, int64_t ld, int j, double *h, int64_t n, int reorth) {
+    const int k = j + 2;
+    const double *dA = h, *dB = h + k;
+    double ss = 0.0, sc = 0.0, cc = 0.0;
+    for (int i = 0; i < j; ++i) {
+        if (reorth) {
+            ss += dA[i] * dA[i];
+            sc += dA[i] * dB[i];
+        }
+        cc += dB[i] * dB[i];
     }
+    double gam = 1.0;
+    if (reorth) {
+        const double g2 = dA[j] - ss;
+        gam = g2 > 0.0 ? sqrt(g2) : 0.0;
+    }
+    const double gs = gam > 0.0 ? gam : 1.0;
+    const double d = reorth ? (dB[j] - sc) / gs : dB[j];
+    const double omega = dB[j + 1];
+    const double eta = sqrt(fmax(omega - cc - d * d, 1e-4 * omega));
+    const double ig = 1.0 / gs, ie = eta > 0.0 ? 1.0 / eta : 1.0;
+    double *vj = V + static_cast<int64_t>(j) * ld, *w = V + static_cast<int64_t>(j + 1) * ld;
     for (int64_t t = static_cast<int64_t>(blockIdx.x) * SB + threadIdx.x; t < n;
          t += static_cast<int64_t>(gridDim.x) * SB) {
-        double s = 0.0;
-        for (int i = 0; i < k; ++i) s += h[i] * V[static_cast<int64_t>(i) * ld + t];
-        w[t] = (w[t] - s) * inv;
+        double as = 0.0, ac = 0.0;
+        for (int i = 0; i < j; ++i) {
+            const double v = V[static_cast<int64_t>(i) * ld + t];
+            if (reorth) as += dA[i] * v;
+            ac += dB[i] * v;
+        }
+        double u = vj[t];
+        if (reorth) {
+            u = (u - as) * ig;
+            vj[t] = u;
+        }
+        w[t] = (w[t] - ac - d * u) * ie;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        h[2 * k] = gam;
+        h[2 * k + 1] = d;
+        h[2 * k + 2] = eta;
     }
 }
 
-void launch_multi_axpy(const double *V, int64_t ld, int k, const double *h, double *w, int64_t n, hipStream_t s) {
-    if (k <= 0 || n <= 0) return;
-    k_multi_axpy<<<grid_s(n), SB, 0, s>>>(V, ld, k, const_cast<double *>(h), w, n, 0);
-    AMG_CHECK_LAUNCH();
-}
-
-void launch_multi_axpy_normalize(const double *V, int64_t ld, int k, double *h, double *w, int64_t n,
-                                 hipStream_t s) {
+void launch_dcgs2_update(double *V, int64_t ld, int j, double *h, int64_t n, bool reorth, hipStream_t s) {
     if (n <= 0) return;
-    k_multi_axpy<<<grid_s(n), SB, 0, s>>>(V, ld, k, h, w, n, 1);
+    k_dcgs2_update<<<grid_s(n), SB, 0, s>>>(V, ld, j, h, n, reorth ? 1 : 0);
     AMG_CHECK_LAUNCH();
 }
 

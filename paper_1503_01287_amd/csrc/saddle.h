@@ -105,16 +105,18 @@ void launch_segment_store_column(const DenseSegView &d, int j, const double *xu,
 int launch_multidot(const double *V, int64_t ld, int k, const double *w, int64_t n, double *partial,
                     hipStream_t s);
 int multidot_blocks(int64_t n);
+// the same for two right-hand sides in one pass over the basis:
+// partial[(r * k + i) * nb + block] holds <V_i, a> (r = 0) and <V_i, b>
+// (r = 1); the buffer holds 2 k nb values
+int launch_multidot2(const double *V, int64_t ld, int k, const double *a, const double *b, int64_t n,
+                     double *partial, hipStream_t s);
 // h[i] = sum of partial[i * nb ...] for i < k
 void launch_multidot_reduce(const double *partial, int nb, int k, double *h, hipStream_t s);
-// w -= sum_i h[i] V_i
-void launch_multi_axpy(const double *V, int64_t ld, int k, const double *h, double *w, int64_t n,
-                       hipStream_t s);
-// the same, then w /= hn with hn = sqrt(h[k] - sum_{i<k} h[i]^2) (the new
-// norm by Pythagoras when h[k] = <w, w> and the V_i are orthonormal); hn is
-// stored in h[k + 1]; w is left unscaled when hn == 0
-void launch_multi_axpy_normalize(const double *V, int64_t ld, int k, double *h, double *w, int64_t n,
-                                 hipStream_t s);
+// Delayed reorthogonalisation step on basis slots j (pending vector) and
+// j + 1 (new vector) from the reduced dots h[0 .. 2(j + 2)) of
+// launch_multidot2(V, ld, j + 2, V_j, V_{j+1}); writes gamma, d, eta to
+// h[2(j + 2) ..] (see k_dcgs2_update)
+void launch_dcgs2_update(double *V, int64_t ld, int j, double *h, int64_t n, bool reorth, hipStream_t s);
 // x += sum_i y[i] Z_i  (y on the device)
 void launch_multi_add(const double *Z, int64_t ld, int k, const double *y, double *x, int64_t n,
                       hipStream_t s);

@@ -662,9 +662,21 @@ static double norm2(amg_ctx *h, const double *v) {
     return std::sqrt(h->h_sc[SC_TMP]);
 }
 
-// Right-preconditioned flexible GMRES(m) with classical Gram-Schmidt applied
-// twice (two batched passes over the basis per iteration); the Hessenberg
-// matrix and its Givens rotations live on the host (m <= a few hundred).
+// Right-preconditioned flexible GMRES(m); the Hessenberg matrix and its
+// Givens rotations live on the host (m <= a few hundred). Classical
+// Gram-Schmidt with delayed reorthogonalisation (DCGS2: Swirydowicz,
+// Langou, Ananthan, Yang and Thomas, Numer. Linear Algebra Appl. 2021):
+// step j preconditions the pending vector u_j (orthogonalised once), and one
+// pass over the basis takes the dots of V_0..V_{j+1} with u_j and with the
+// new w = A z_j, after which one update finishes v_j (the second pass) and
+// orthogonalises w once. Two passes over the basis per step instead of the
+// four of CGS2, one host synchronisation. Column j - 1 of the Hessenberg
+// matrix is complete at step j (u_j = V s + gamma v_j adds eta_j s to it and
+// makes its subdiagonal eta_j gamma); the residual estimate of column j is
+// taken provisionally with its pending subdiagonal eta_{j+1}, and when that
+// meets the tolerance (or the cycle ends) one more pass over the basis
+// completes the column before the exact test. FGMRES allows any z_j: the
+// relation A Z = V H holds column by column with z_j = M^{-1} u_j.
 int solve_fgmres(amg_ctx *h, const double *b, double *x, double tol, int maxit, amg_result *res) {
     const auto t0 = std::chrono::steady_clock::now();
     const int64_t n = h->n_dof;
@@ -672,14 +684,17 @@ int solve_fgmres(amg_ctx *h, const double *b, double *x, double tol, int maxit, 
     if (h->gm_m != m) {
         h->gm_V.alloc(static_cast<size_t>(m + 1) * n);
         h->gm_Z.alloc(static_cast<size_t>(m) * n);
-        h->gm_h.alloc(static_cast<size_t>(2 * (m + 2)));
+        h->gm_h.alloc(static_cast<size_t>(2 * (m + 2) + 4));
         h->gm_y.alloc(static_cast<size_t>(m + 1));
-        h->gm_part.alloc(static_cast<size_t>(m + 2) * multidot_blocks(n));
+        h->gm_part.alloc(static_cast<size_t>(2 * (m + 2)) * multidot_blocks(n));
         h->gm_m = m;
     }
     double *V = h->gm_V.p, *Z = h->gm_Z.p;
-    std::vector<double> H(static_cast<size_t>(m + 1) * m), cs(m), sn(m), g(m + 1), hcol(m + 2),
-        hbuf(static_cast<size_t>(2 * (m + 2)));
+    // H: rotated (upper triangular) columns, row-major i * m + j; Hr: the
+    // raw Hessenberg columns (column j at j * (m + 1))
+    std::vector<double> H(static_cast<size_t>(m + 1) * m), Hr(static_cast<size_t>(m + 1) * m), cs(m), sn(m),
+        g(m + 1), hcol(m + 2), hbuf(static_cast<size_t>(2 * (m + 2) + 4)), eta(m + 1, 1.0);
+    std::vector<char> done_col(m, 0);
     system_residual(h, b, x, V);
     const double r0 = norm2(h, V);
     auto finish = [&](int it, int status) {
@@ -700,76 +715,109 @@ int solve_fgmres(amg_ctx *h, const double *b, double *x, double tol, int maxit, 
     int it = 0;
     double beta = r0;
     int status = AMG_NOT_CONVERGED;
+    // rotations 0..c-1 applied to raw column c, rotation c formed, g updated;
+    // returns the residual estimate after c + 1 columns
+    auto rotate = [&](int c) {
+        const double *raw = Hr.data() + static_cast<size_t>(c) * (m + 1);
+        for (int i = 0; i <= c + 1; ++i) hcol[i] = raw[i];
+        for (int i = 0; i < c; ++i) {
+            const double t = cs[i] * hcol[i] + sn[i] * hcol[i + 1];
+            hcol[i + 1] = -sn[i] * hcol[i] + cs[i] * hcol[i + 1];
+            hcol[i] = t;
+        }
+        const double den = std::hypot(hcol[c], hcol[c + 1]);
+        cs[c] = den > 0.0 ? hcol[c] / den : 1.0;
+        sn[c] = den > 0.0 ? hcol[c + 1] / den : 0.0;
+        hcol[c] = den;
+        g[c + 1] = -sn[c] * g[c];
+        g[c] = cs[c] * g[c];
+        for (int i = 0; i <= c; ++i) H[static_cast<size_t>(i) * m + c] = hcol[i];
+        return std::fabs(g[c + 1]) / r0;
+    };
+    // the same estimate without changing the rotations (provisional column)
+    auto estimate = [&](int c) {
+        const double *raw = Hr.data() + static_cast<size_t>(c) * (m + 1);
+        for (int i = 0; i <= c + 1; ++i) hcol[i] = raw[i];
+        for (int i = 0; i < c; ++i) {
+            const double t = cs[i] * hcol[i] + sn[i] * hcol[i + 1];
+            hcol[i + 1] = -sn[i] * hcol[i] + cs[i] * hcol[i + 1];
+            hcol[i] = t;
+        }
+        const double den = std::hypot(hcol[c], hcol[c + 1]);
+        return den > 0.0 ? std::fabs(hcol[c + 1] / den * g[c]) / r0 : 0.0;
+    };
     while (it < maxit) {
         // V_0 = r / beta (r is in V_0 already)
         h->h_sc[SC_TMP] = beta;
         AMG_HIP(hipMemcpyAsync(h->sc.p + SC_TMP, &h->h_sc[SC_TMP], sizeof(double), hipMemcpyHostToDevice, h->stream));
         launch_scale_by_inverse(V, V, n, h->sc.p, SC_TMP, h->stream);
         std::fill(g.begin(), g.end(), 0.0);
+        std::fill(done_col.begin(), done_col.end(), 0);
         g[0] = beta;
-        int j = 0;
-        bool done = false;
-        for (; j < m && it < maxit; ++j) {
+        int nc = 0;  // complete, rotated columns
+        bool stop = false;
+        double *hd = h->gm_h.p;
+        for (int j = 0; j < m && it + j < maxit && !stop; ++j) {
             double *vj = V + static_cast<int64_t>(j) * n, *w = V + static_cast<int64_t>(j + 1) * n;
             double *zj = Z + static_cast<int64_t>(j) * n;
             precondition_any(h, vj, zj);
             system_matvec(h, zj, w);
-            // classical Gram-Schmidt, twice, with one host synchronisation:
-            // the second pass also returns <w1, w1> (w is basis slot j + 1),
-            // the new norm follows by Pythagoras and the last update
-            // normalises w on the device
-            double *h1 = h->gm_h.p, *h2 = h->gm_h.p + (m + 2);
-            int nb = launch_multidot(V, n, j + 1, w, n, h->gm_part.p, h->stream);
-            launch_multidot_reduce(h->gm_part.p, nb, j + 1, h1, h->stream);
-            launch_multi_axpy(V, n, j + 1, h1, w, n, h->stream);
-            nb = launch_multidot(V, n, j + 2, w, n, h->gm_part.p, h->stream);
-            launch_multidot_reduce(h->gm_part.p, nb, j + 2, h2, h->stream);
-            launch_multi_axpy_normalize(V, n, j + 1, h2, w, n, h->stream);
-            AMG_HIP(hipMemcpyAsync(hbuf.data(), h->gm_h.p, hbuf.size() * sizeof(double), hipMemcpyDeviceToHost,
+            const int k = j + 2;
+            int nb = launch_multidot2(V, n, k, vj, w, n, h->gm_part.p, h->stream);
+            launch_multidot_reduce(h->gm_part.p, nb, 2 * k, hd, h->stream);
+            launch_dcgs2_update(V, n, j, hd, n, j > 0, h->stream);
+            AMG_HIP(hipMemcpyAsync(hbuf.data(), hd, (2 * k + 3) * sizeof(double), hipMemcpyDeviceToHost,
                                    h->stream));
             AMG_HIP(hipStreamSynchronize(h->stream));
-            for (int i = 0; i <= j; ++i) hcol[i] = hbuf[i] + hbuf[m + 2 + i];
-            double hn = hbuf[m + 2 + j + 2];
-            const double w1sq = hbuf[m + 2 + j + 1];
-            if (hn * hn < 1e-4 * w1sq) {
-                // the second pass removed a large part of w: Pythagoras has
-                // lost digits, measure the norm (w = w2 / hn, or w2 if hn = 0)
-                const double a = norm2(h, w);
-                if (a > 0.0) {
-                    h->h_sc[SC_TMP] = a;
-                    AMG_HIP(hipMemcpyAsync(h->sc.p + SC_TMP, &h->h_sc[SC_TMP], sizeof(double),
-                                           hipMemcpyHostToDevice, h->stream));
-                    launch_scale_by_inverse(w, w, n, h->sc.p, SC_TMP, h->stream);
+            const double *dA = hbuf.data(), *dB = hbuf.data() + k;
+            const double gam = hbuf[2 * k], d = hbuf[2 * k + 1], et = hbuf[2 * k + 2];
+            double est = 0.0;
+            if (j > 0 && !done_col[j - 1]) {
+                // u_j = V s + gamma v_j completes column j - 1
+                double *c1 = Hr.data() + static_cast<size_t>(j - 1) * (m + 1);
+                for (int i = 0; i < j; ++i) c1[i] += eta[j] * dA[i];
+                c1[j] = eta[j] * gam;
+                done_col[j - 1] = 1;
+                est = rotate(j - 1);
+                nc = j;
+                if (!(est == est) || est > 1e3) {
+                    status = AMG_DIVERGED;
+                    break;
                 }
-                hn = hn > 0.0 ? hn * a : a;
+                if (est <= tol || gam == 0.0) break;  // column j is not used
             }
-            hcol[j + 1] = hn;
-            for (int i = 0; i < j; ++i) {
-                const double t = cs[i] * hcol[i] + sn[i] * hcol[i + 1];
-                hcol[i + 1] = -sn[i] * hcol[i] + cs[i] * hcol[i + 1];
-                hcol[i] = t;
-            }
-            const double den = std::hypot(hcol[j], hcol[j + 1]);
-            cs[j] = den > 0.0 ? hcol[j] / den : 1.0;
-            sn[j] = den > 0.0 ? hcol[j + 1] / den : 0.0;
-            hcol[j] = den;
-            g[j + 1] = -sn[j] * g[j];
-            g[j] = cs[j] * g[j];
-            for (int i = 0; i <= j; ++i) H[static_cast<size_t>(i) * m + j] = hcol[i];
-            ++it;
-            const double est = std::fabs(g[j + 1]) / r0;
-            if (!(est == est) || est > 1e3) {
-                status = AMG_DIVERGED;
-                done = true;
-                ++j;
-                break;
-            }
-            if (est <= tol || hn == 0.0) {
-                done = true;
-                ++j;
-                break;
+            // column j with its pending subdiagonal
+            double *cj = Hr.data() + static_cast<size_t>(j) * (m + 1);
+            for (int i = 0; i < j; ++i) cj[i] = dB[i];
+            cj[j] = d;
+            cj[j + 1] = et;
+            eta[j + 1] = et;
+            const bool last = j + 1 == m || it + j + 1 >= maxit;
+            if (last || et == 0.0 || estimate(j) <= tol) {
+                // complete column j now: s = V_{0..j} . u_{j+1}, |u_{j+1}|^2
+                nb = launch_multidot(V, n, k, w, n, h->gm_part.p, h->stream);
+                launch_multidot_reduce(h->gm_part.p, nb, k, hd, h->stream);
+                AMG_HIP(hipMemcpyAsync(hbuf.data(), hd, k * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+                AMG_HIP(hipStreamSynchronize(h->stream));
+                double ss = 0.0;
+                for (int i = 0; i <= j; ++i) {
+                    ss += hbuf[i] * hbuf[i];
+                    cj[i] += et * hbuf[i];
+                }
+                const double g2 = hbuf[j + 1] - ss;
+                cj[j + 1] = et * (g2 > 0.0 ? std::sqrt(g2) : 0.0);
+                done_col[j] = 1;
+                est = rotate(j);
+                nc = j + 1;
+                if (!(est == est) || est > 1e3) {
+                    status = AMG_DIVERGED;
+                    break;
+                }
+                stop = est <= tol || cj[j + 1] == 0.0;
             }
         }
+        it += nc;
+        const int j = nc;
         // y = R^{-1} g, x += Z y
         std::vector<double> y(j, 0.0);
         for (int i = j - 1; i >= 0; --i) {
@@ -788,7 +836,7 @@ int solve_fgmres(amg_ctx *h, const double *b, double *x, double tol, int maxit, 
             status = AMG_OK;
             break;
         }
-        (void)done;
+        if (nc == 0) break;  // no progress possible (breakdown on the first column)
     }
     return finish(it, status);
 }
