@@ -104,8 +104,9 @@ void launch_seg_multidot2(const double *V, int64_t ld, int k, const double *a, c
 // The delayed-reorthogonalisation step of every system (see
 // launch_seg_dcgs2_update): chunk c takes its system's dots from
 // h + seg * stride.
+template <bool REORTH>
 __global__ void __launch_bounds__(CB) k_seg_dcgs2_update(double *V, int64_t ld, int j, double *h, int stride,
-                                                         const ChunkView t, int reorth) {
+                                                         const ChunkView t) {
     const int c = blockIdx.x;
     const int64_t s0 = t.start[c];
     const int len = t.len[c];
@@ -114,39 +115,51 @@ __global__ void __launch_bounds__(CB) k_seg_dcgs2_update(double *V, int64_t ld, 
     const double *dA = hs, *dB = hs + k;
     double ss = 0.0, sc = 0.0, cc = 0.0;
     for (int q = 0; q < j; ++q) {
-        if (reorth) {
+        if (REORTH) {
             ss += dA[q] * dA[q];
             sc += dA[q] * dB[q];
         }
         cc += dB[q] * dB[q];
     }
     double gam = 1.0;
-    if (reorth) {
+    if (REORTH) {
         const double g2 = dA[j] - ss;
         gam = g2 > 0.0 ? sqrt(g2) : 0.0;
     }
     const double gs = gam > 0.0 ? gam : 1.0;
-    const double d = reorth ? (dB[j] - sc) / gs : dB[j];
+    const double d = REORTH ? (dB[j] - sc) / gs : dB[j];
     const double omega = dB[j + 1];
     const double eta = sqrt(fmax(omega - cc - d * d, 1e-4 * omega));
     const double ig = 1.0 / gs, ie = eta > 0.0 ? 1.0 / eta : 1.0;
+    // basis vectors outer, the thread's PER entries inner: PER independent
+    // loads in flight per vector
+    double as[PER], ac[PER];
+#pragma unroll
+    for (int e = 0; e < PER; ++e) as[e] = ac[e] = 0.0;
+    for (int q = 0; q < j; ++q) {
+        const double sq = REORTH ? dA[q] : 0.0, cq = dB[q];
+        const double *v = V + q * ld + s0;
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            const int i = threadIdx.x + e * CB;
+            if (i < len) {
+                const double vi = v[i];
+                if (REORTH) as[e] += sq * vi;
+                ac[e] += cq * vi;
+            }
+        }
+    }
     double *vj = V + static_cast<int64_t>(j) * ld + s0, *w = V + static_cast<int64_t>(j + 1) * ld + s0;
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
         const int i = threadIdx.x + e * CB;
         if (i >= len) continue;
-        double as = 0.0, ac = 0.0;
-        for (int q = 0; q < j; ++q) {
-            const double v = V[q * ld + s0 + i];
-            if (reorth) as += dA[q] * v;
-            ac += dB[q] * v;
-        }
         double u = vj[i];
-        if (reorth) {
-            u = (u - as) * ig;
+        if (REORTH) {
+            u = (u - as[e]) * ig;
             vj[i] = u;
         }
-        w[i] = (w[i] - ac - d * u) * ie;
+        w[i] = (w[i] - ac[e] - d * u) * ie;
     }
     // every chunk of the system writes the same three values; the dots
     // read above lie below them
@@ -160,7 +173,10 @@ __global__ void __launch_bounds__(CB) k_seg_dcgs2_update(double *V, int64_t ld, 
 void launch_seg_dcgs2_update(double *V, int64_t ld, int j, double *h, int stride, const ChunkView &t, bool reorth,
                              hipStream_t s) {
     if (t.n <= 0) return;
-    k_seg_dcgs2_update<<<t.n, CB, 0, s>>>(V, ld, j, h, stride, t, reorth ? 1 : 0);
+    if (reorth)
+        k_seg_dcgs2_update<true><<<t.n, CB, 0, s>>>(V, ld, j, h, stride, t);
+    else
+        k_seg_dcgs2_update<false><<<t.n, CB, 0, s>>>(V, ld, j, h, stride, t);
     AMG_CHECK_LAUNCH();
 }
 

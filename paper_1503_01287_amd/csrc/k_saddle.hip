@@ -449,7 +449,7 @@ void launch_segment_store_column(const DenseSegView &d, int j, const double *xu,
 // per group instead of one per vector, every basis chunk read once for all
 // right-hand sides, and one block reduction for the whole group. Right-hand
 // side r's dot with vector q goes to partial[(r * k + q) * nb + c].
-constexpr int MD_PER = 2;
+constexpr int MD_PER = 4;
 constexpr int MD_CHUNK = MD_PER * SB;
 constexpr int MD_VEC = 8;
 
@@ -549,24 +549,25 @@ void launch_multidot_reduce(const double *partial, int nb, int k, double *h, hip
 // as the next step measures the new pending vector exactly, so a
 // cancelled estimate falls back to 1e-2 |w|). gamma, d and eta are written
 // to h[2k], h[2k + 1], h[2k + 2].
-__global__ void k_dcgs2_update(double *V, int64_t ld, int j, double *h, int64_t n, int reorth) {
+template <bool REORTH>
+__global__ void __launch_bounds__(SB) k_dcgs2_update(double *V, int64_t ld, int j, double *h, int64_t n) {
     const int k = j + 2;
     const double *dA = h, *dB = h + k;
     double ss = 0.0, sc = 0.0, cc = 0.0;
     for (int i = 0; i < j; ++i) {
-        if (reorth) {
+        if (REORTH) {
             ss += dA[i] * dA[i];
             sc += dA[i] * dB[i];
         }
         cc += dB[i] * dB[i];
     }
     double gam = 1.0;
-    if (reorth) {
+    if (REORTH) {
         const double g2 = dA[j] - ss;
         gam = g2 > 0.0 ? sqrt(g2) : 0.0;
     }
     const double gs = gam > 0.0 ? gam : 1.0;
-    const double d = reorth ? (dB[j] - sc) / gs : dB[j];
+    const double d = REORTH ? (dB[j] - sc) / gs : dB[j];
     const double omega = dB[j + 1];
     const double eta = sqrt(fmax(omega - cc - d * d, 1e-4 * omega));
     const double ig = 1.0 / gs, ie = eta > 0.0 ? 1.0 / eta : 1.0;
@@ -574,13 +575,14 @@ __global__ void k_dcgs2_update(double *V, int64_t ld, int j, double *h, int64_t 
     for (int64_t t = static_cast<int64_t>(blockIdx.x) * SB + threadIdx.x; t < n;
          t += static_cast<int64_t>(gridDim.x) * SB) {
         double as = 0.0, ac = 0.0;
+#pragma unroll 8
         for (int i = 0; i < j; ++i) {
             const double v = V[static_cast<int64_t>(i) * ld + t];
-            if (reorth) as += dA[i] * v;
+            if (REORTH) as += dA[i] * v;
             ac += dB[i] * v;
         }
         double u = vj[t];
-        if (reorth) {
+        if (REORTH) {
             u = (u - as) * ig;
             vj[t] = u;
         }
@@ -595,7 +597,10 @@ __global__ void k_dcgs2_update(double *V, int64_t ld, int j, double *h, int64_t 
 
 void launch_dcgs2_update(double *V, int64_t ld, int j, double *h, int64_t n, bool reorth, hipStream_t s) {
     if (n <= 0) return;
-    k_dcgs2_update<<<grid_s(n), SB, 0, s>>>(V, ld, j, h, n, reorth ? 1 : 0);
+    if (reorth)
+        k_dcgs2_update<true><<<grid_s(n), SB, 0, s>>>(V, ld, j, h, n);
+    else
+        k_dcgs2_update<false><<<grid_s(n), SB, 0, s>>>(V, ld, j, h, n);
     AMG_CHECK_LAUNCH();
 }
 
