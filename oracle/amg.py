@@ -29,8 +29,9 @@ Section 3.1 (Algorithm 1, the basic AMG iteration) is ``cycle``; Section 3.3's
 smoothers are ``jacobi``, ``gauss_seidel`` (block, lexicographic or by
 colours), ``sgs_step`` (segregated Gauss-Seidel / Uzawa), ``bs_step``
 (Braess-Sarazin) and ``vanka_step`` (multiplicative Vanka). Parity unpinned: the exact iteration counts of the paper's
-tables (they depend on unstated details); the Braess-Sarazin inner Schur
-cycle and the sGS pressure scaling follow the readings in their docstrings.
+tables (they depend on unstated details). The Braess-Sarazin inner Schur
+cycle and the sGS pressure scaling follow the readings in their docstrings;
+both are pinned to their dense definitions.
 """
 from __future__ import annotations
 
@@ -343,8 +344,9 @@ def bs_step(lev: Level, sm: Smoother, f, g, u, p):
     A_hat = 2 D with D the (scalar) diagonal of A. Solving K_hat [du; dp] = r:
     S_hat dp = B A_hat^{-1} r_u - r_p, du = A_hat^{-1} (r_u - B^T dp), where
     S_hat^{-1} is one V(1,1) Gauss-Seidel cycle of the scalar AMG hierarchy of
-    S = C + B A_hat^{-1} B^T (zero initial guess). Parity unpinned beyond the
-    dense block formula it is checked against.
+    S = C + B A_hat^{-1} B^T (zero initial guess). Pinned against the dense
+    block formula, and the inner cycle against its dense two-grid definition
+    (triangular solves for the coloured sweeps, exact coarsest solve).
     """
     ru, rp = saddle_residual(lev, f, g, u, p)
     ahat_inv = 1.0 / (2.0 * np.einsum("nii->ni", lev.A.diag_blocks()))

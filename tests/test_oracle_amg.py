@@ -399,6 +399,62 @@ def test_bs_step_dense_formula():
     assert np.abs(S - (C + B @ np.linalg.solve(Ahat, B.T))).max() < 1e-14 * np.abs(S).max()
 
 
+def _dense_scalar_cycle(levels, pinned, k):
+    """Matrix of the scalar V(1,1) cycle from Schur level k, written with dense
+    linear algebra: a forward Gauss-Seidel sweep from x = 0 in the order pi is
+    the lower triangular solve of the permuted matrix, the backward sweep (the
+    reverse order) adds the upper triangular solve of the residual, the
+    transfers are H^T and H, and the coarsest level is solved exactly (with
+    its last row and column replaced by the identity and the last right-hand
+    side entry dropped when the constant pressure is in the kernel)."""
+    S = levels[k].S.dense()
+    n = S.shape[0]
+    if k == len(levels) - 1:
+        Sd = S.copy()
+        if not pinned:
+            return np.linalg.inv(Sd)
+        Sd[-1, :] = 0.0
+        Sd[:, -1] = 0.0
+        Sd[-1, -1] = 1.0
+        keep = np.eye(n)
+        keep[-1, -1] = 0.0
+        return np.linalg.solve(Sd, keep)
+    pi = levels[k].order_fwd
+    Pm = np.eye(n)[pi]                       # (Pm x)[i] = x[pi[i]]
+    Sp = Pm @ S @ Pm.T
+    Gf = Pm.T @ np.linalg.inv(np.tril(Sp)) @ Pm
+    Gb = Pm.T @ np.linalg.inv(np.triu(Sp)) @ Pm
+    H = levels[k].H.toarray()
+    Mc = _dense_scalar_cycle(levels, pinned, k + 1)
+    Id = np.eye(n)
+    x1 = Gf
+    x2 = x1 + H @ Mc @ H.T @ (Id - S @ x1)
+    return x2 + Gb @ (Id - S @ x2)
+
+
+@pytest.mark.parametrize("which", ["mixed", "cavity"])
+def test_schur_inner_cycle_is_dense_two_grid(which):
+    """The Braess-Sarazin inner cycle (one scalar V(1,1) Gauss-Seidel cycle
+    on S = C + B (2D)^{-1} B^T) against its dense definition, on a Schur
+    hierarchy of at least two levels; with C present it is a symmetric
+    operator (backward sweep after the coarse correction)."""
+    if which == "mixed":
+        s = workloads.mixed_elasticity(2)
+    else:
+        s = workloads.stokes(3, 1.1)
+    h = _saddle_hierarchy(s, coarse_max=100)
+    amg.prepare_bs(h)
+    levels, _, pinned = h.levels[0].schur
+    assert len(levels) >= 2 and pinned == (which == "cavity")
+    n = levels[0].S.nrows
+    got = _dense_operator(lambda e: amg.scalar_vcycle(h.levels[0].schur, 0, e, np.zeros(n)), n)
+    want = _dense_scalar_cycle(levels, pinned, 0)
+    assert np.abs(got - want).max() < 1e-10 * np.abs(want).max()
+    if not pinned:
+        assert np.abs(got - got.T).max() < 1e-10 * np.abs(got).max()
+        assert np.linalg.eigvalsh(0.5 * (got + got.T)).min() > 0.0
+
+
 def _saddle_matvec(s):
     A, B = s.A, s.B
     Bt = B.transpose()
