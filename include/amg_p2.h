@@ -151,7 +151,13 @@ typedef struct {
                              launch per operation. Same arithmetic, up to
                              rounding order.                                  */
     int32_t autotune;     /* 1 (default): time the row kernels' lanes-per-row
-                             choices on each level at setup; 0: heuristic.   */
+                             choices on each level at setup, and time the
+                             saddle coarse-end candidates (fuse_coarse);
+                             0: no setup choice depends on timing (heuristic
+                             launch shapes, no assembled saddle coarse end),
+                             so two setups of the same input give the same
+                             bits. Solves on one hierarchy always repeat
+                             bit for bit (fixed summation orders).           */
     amg_mlp_handle omega_model; /* JA only, SPD only, NULL (default) = off:
                              the damping of every non-coarsest level is the
                              network's prediction from that level's row

@@ -522,7 +522,8 @@ constexpr double SADDLE_TAIL_SETUP_MS = 2000.0;
 void setup_saddle_tail(amg_ctx *h) {
     h->saddle_tail_from = -1;
     h->saddle_tail = DenseSegs();
-    if (!h->saddle || !h->prm.fuse_coarse) return;
+    // the choice below is timed: without the tuner, setups stay timing-free
+    if (!h->saddle || !h->prm.fuse_coarse || !h->prm.autotune) return;
     const int last = static_cast<int>(h->lv.size()) - 1;
     hipStream_t s = h->stream;
     hipEvent_t e0, e1;

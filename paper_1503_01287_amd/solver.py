@@ -233,7 +233,7 @@ class BatchedSolver:
     def __init__(self, systems, smoother: str = "BS-1-1", cycles: int = 1, nu: int = 1,
                  coarse_max: int = 300, max_levels: int = 10, sgs_omega: float = 0.125,
                  sgs_damping: float = 0.5, restart: int = 100, graph: bool = True, precision: str = "FP64",
-                 fuse_coarse: bool = True, stream=None):
+                 fuse_coarse: bool = True, autotune: bool = True, stream=None):
         L = C.lib()
         p = C.default_params()
         sm = parse_smoother(smoother)
@@ -247,6 +247,7 @@ class BatchedSolver:
         p.graph = 1 if graph else 0
         p.precision = C.PREC[precision]
         p.fuse_coarse = 1 if fuse_coarse else 0
+        p.autotune = 1 if autotune else 0
         self.params = p
         self.systems = list(systems)
         keep = []
