@@ -16,12 +16,15 @@ ProfScope::ProfScope(amg_ctx *hh, const std::string &cls, double bytes) : h(hh),
     amg_ctx::Pending pe;
     pe.cls = cls;
     pe.bytes = bytes;
+    // timing-only events: no system-scope fence (its L2 writeback and
+    // invalidate would lengthen the interval and slow the next kernel);
+    // profile_collect synchronises the stream before reading them
     for (hipEvent_t *e : {&pe.a, &pe.b}) {
         if (!h->event_pool.empty()) {
             *e = h->event_pool.back();
             h->event_pool.pop_back();
         } else {
-            AMG_HIP(hipEventCreate(e));
+            AMG_HIP(hipEventCreateWithFlags(e, hipEventDisableSystemFence));
         }
     }
     AMG_HIP(hipEventRecord(pe.a, h->stream));
