@@ -17,6 +17,9 @@ It shares no code with the GPU path. Modules:
               coarse operators, smoothers and Algorithm 1 (Section 3).
 * ``krylov``  PCG, flexible CG and flexible GMRES drivers.
 * ``mlp``     FP64 reference of the damping-weight network (gradient checks).
+* ``reduced`` the cycle on operators rounded as a reduced-precision
+              preconditioner stores them (FP32 finest, BF16 with row
+              scales below), computed in FP64.
 * ``loops.c`` the inherently sequential loops (greedy independent set,
               greedy colouring, Gauss-Seidel sweeps) in plain C.
 

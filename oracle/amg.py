@@ -266,6 +266,9 @@ class Smoother:
     # post), while the stand-alone solver tables follow same-direction sweeps
     # (with backward post-sweeps they would need about 2.5x the iterations)
     post_forward: bool = False
+    # sGS (2,2) block: -omega^{-1} diag(B M_A^{-1} B^T + C) (reading R14) when
+    # True, the literal -omega^{-1} I of Section 3.3 when False
+    sgs_scaled: bool = True
 
     @staticmethod
     def parse(name: str) -> "Smoother":
@@ -325,16 +328,20 @@ def sgs_step(lev: Level, sm: Smoother, f, g, u, p):
 
     Reading: the paper writes the (2,2) block as -omega^{-1} I with
     omega = 0.125; taken literally the pressure update does not scale with the
-    mesh (B ~ h^2, so B M_A^{-1} B^T ~ h^3) and FGMRES stagnates. The block is
-    read as -omega^{-1} S_d with S_d = diag(B M_A^{-1} B^T + C), omega = 0.125.
+    mesh (B ~ h^2, so B M_A^{-1} B^T ~ h^3) and FGMRES needs several times
+    the paper's iterations. The block is read as -omega^{-1} S_d with
+    S_d = diag(B M_A^{-1} B^T + C), omega = 0.125; ``sm.sgs_scaled = False``
+    gives the literal form.
     Solving K_hat [du; dp] = [r_u; r_p]: du = M_A^{-1} r_u,
     dp = omega S_d^{-1} (B du - r_p).
     """
-    if lev.sgs_diag is None:
-        lev.sgs_diag = sgs_pressure_diag(lev, sm.sgs_damping)
     ru, rp = saddle_residual(lev, f, g, u, p)
     du = sm.sgs_damping * np.einsum("nij,nj->ni", lev.dinv, ru)
-    dp = sm.sgs_omega * (lev.B.matvec(du)[:, 0] - rp) / lev.sgs_diag
+    dp = sm.sgs_omega * (lev.B.matvec(du)[:, 0] - rp)
+    if sm.sgs_scaled:
+        if lev.sgs_diag is None:
+            lev.sgs_diag = sgs_pressure_diag(lev, sm.sgs_damping)
+        dp = dp / lev.sgs_diag
     return u + du, p + dp
 
 
@@ -500,7 +507,8 @@ def prepare_bs(h: Hierarchy) -> None:
 # Algorithm 1
 # --------------------------------------------------------------------------
 def cycle(h: Hierarchy, l: int, sm: Smoother, b: np.ndarray, x: np.ndarray, nu: int = 1) -> np.ndarray:
-    """Algorithm 1 for an SPD hierarchy: AMG(K_l, x_l, b_l) with nu recursive calls."""
+    """Algorithm 1 for an SPD hierarchy: AMG(K_l, x_l, b_l) with nu recursive
+    calls (pinned for nu = 1 and 2 by the dense recursive error operator)."""
     lev = h.levels[l]
     x = smooth_spd(h, l, sm, b, x, pre=True)
     r = b - lev.A.matvec(x)
@@ -516,7 +524,8 @@ def cycle(h: Hierarchy, l: int, sm: Smoother, b: np.ndarray, x: np.ndarray, nu: 
 
 
 def saddle_cycle(h: Hierarchy, l: int, sm: Smoother, f, g, u, p, nu: int = 1):
-    """Algorithm 1 for the saddle hierarchy with the sGS, BS or Vanka smoother."""
+    """Algorithm 1 for the saddle hierarchy with the sGS, BS or Vanka smoother
+    (pinned by the dense error operator S (I - P K_c^{-1} P^T K) S)."""
     lev = h.levels[l]
     step = {"SGS": sgs_step, "BS": bs_step, "VANKA": vanka_step}[sm.kind]
     for _ in range(sm.pre):
@@ -541,7 +550,8 @@ def saddle_cycle(h: Hierarchy, l: int, sm: Smoother, f, g, u, p, nu: int = 1):
 
 
 def preconditioner(h: Hierarchy, sm: Smoother, cycles: int = 1, nu: int = 1):
-    """z = M^{-1} r: ``cycles`` successive applications of Algorithm 1 from zero."""
+    """z = M^{-1} r: ``cycles`` successive applications of Algorithm 1 from zero
+    (reading R17; two cycles square the error operator of one)."""
     if not h.saddle:
         def apply(r):
             r = np.asarray(r).reshape(-1, 3)

@@ -41,6 +41,8 @@ def lib():
         L.oracle_block_gs.restype = None
         L.oracle_scalar_gs.argtypes = [i64, p, p, p, p, p, p]
         L.oracle_scalar_gs.restype = None
+        L.oracle_block_gs_update.argtypes = [i64, p, p, p, p, p, p, p]
+        L.oracle_block_gs_update.restype = None
         _lib = L
     return _lib
 
@@ -78,6 +80,18 @@ def block_gs(order, indptr, indices, vals, dinv, b, x) -> None:
     bb = np.ascontiguousarray(b, dtype=np.float64)
     assert x.flags.c_contiguous and x.dtype == np.float64
     lib().oracle_block_gs(o.shape[0], _p(o), _p(ip), _p(ix), _p(v), _p(d), _p(bb), _p(x))
+
+
+def block_gs_update(order, indptr, indices, vals, dinv, b, x) -> None:
+    """In-place block Gauss-Seidel sweep in correction form (x modified)."""
+    o = np.ascontiguousarray(order, dtype=np.int64)
+    ip = np.ascontiguousarray(indptr, dtype=np.int64)
+    ix = np.ascontiguousarray(indices, dtype=np.int64)
+    v = np.ascontiguousarray(vals, dtype=np.float64)
+    d = np.ascontiguousarray(dinv, dtype=np.float64)
+    bb = np.ascontiguousarray(b, dtype=np.float64)
+    assert x.flags.c_contiguous and x.dtype == np.float64
+    lib().oracle_block_gs_update(o.shape[0], _p(o), _p(ip), _p(ix), _p(v), _p(d), _p(bb), _p(x))
 
 
 def scalar_gs(order, indptr, indices, vals, b, x) -> None:

@@ -99,3 +99,29 @@ void oracle_scalar_gs(int64_t m, const int64_t *order, const int64_t *indptr, co
         x[i] = s / d;
     }
 }
+
+/* One block Gauss-Seidel sweep in correction form, nodes visited in
+ * order[0..m):  x_i <- x_i + D_i^{-1} ( b_i - sum_j A_ij x_j )  (j = i included).
+ * With D_i = A_ii this is the sweep above; the reduced-precision reading of
+ * the cycle uses it with the rounded operator A and D_i^{-1} inverted from
+ * the unrounded diagonal blocks. */
+void oracle_block_gs_update(int64_t m, const int64_t *order, const int64_t *indptr, const int64_t *indices,
+                            const double *vals, const double *dinv, const double *b, double *x)
+{
+    for (int64_t q = 0; q < m; ++q) {
+        int64_t i = order[q];
+        double s0 = b[3 * i], s1 = b[3 * i + 1], s2 = b[3 * i + 2];
+        for (int64_t k = indptr[i]; k < indptr[i + 1]; ++k) {
+            int64_t j = indices[k];
+            const double *a = vals + 9 * k;
+            double x0 = x[3 * j], x1 = x[3 * j + 1], x2 = x[3 * j + 2];
+            s0 -= a[0] * x0 + a[1] * x1 + a[2] * x2;
+            s1 -= a[3] * x0 + a[4] * x1 + a[5] * x2;
+            s2 -= a[6] * x0 + a[7] * x1 + a[8] * x2;
+        }
+        const double *d = dinv + 9 * i;
+        x[3 * i] += d[0] * s0 + d[1] * s1 + d[2] * s2;
+        x[3 * i + 1] += d[3] * s0 + d[4] * s1 + d[5] * s2;
+        x[3 * i + 2] += d[6] * s0 + d[7] * s1 + d[8] * s2;
+    }
+}

@@ -96,6 +96,44 @@ def test_colouring_valid():
         assert not np.any(lev.colors[rows[off]] == lev.colors[lev.A.indices[off]])
 
 
+def _first_fit_python(ip, ix):
+    """Reading R19 written out: visit nodes in index order, give each the
+    smallest colour no already coloured neighbour holds (self loops ignored)."""
+    n = len(ip) - 1
+    col = [-1] * n
+    for i in range(n):
+        used = {col[j] for j in ix[ip[i]:ip[i + 1]] if j != i and col[j] >= 0}
+        c = 0
+        while c in used:
+            c += 1
+        col[i] = c
+    return np.array(col)
+
+
+def test_colouring_is_first_fit_in_index_order():
+    """The C colouring equals a pure-Python first-fit in index order, bit for
+    bit, on every level of an elasticity hierarchy, a Laplacian and graphs
+    with more than 64 colours (the C loop grows its mark array there)."""
+    s = workloads.elasticity(4)
+    h = amg.setup(s.A, s.nlin, s.nquad)
+    graphs = [(lev.A.indptr, lev.A.indices) for lev in h.levels]
+    sl = workloads.laplace(3)
+    graphs.append((sl.A.indptr, sl.A.indices))
+    rng = np.random.default_rng(8)
+    for n, p in ((150, 1.0), (300, 0.5), (400, 0.05)):
+        dense = np.triu(rng.random((n, n)) < p, 1)
+        G = sp.csr_matrix(dense | dense.T)
+        G.sort_indices()
+        graphs.append((G.indptr.astype(np.int64), G.indices.astype(np.int64)))
+    ncols = []
+    for ip, ix in graphs:
+        want = _first_fit_python(ip, ix)
+        got = cloops.greedy_colour(ip, ix)
+        assert np.array_equal(got, want)
+        ncols.append(int(want.max()) + 1)
+    assert max(ncols) > 128      # the complete graph on 150 nodes needs 150
+
+
 # ---------------------------------------------------------------- smoothers
 def _blocks_dense(lev):
     A = lev.A.dense()
