@@ -223,6 +223,14 @@ typedef struct {
                                       dropped once the setup's pattern-based
                                       steps are done (Dirichlet couplings,
                                       couplings that vanish on the mesh)     */
+    int32_t coarse_map;            /* 1 on the first level of the assembled
+                                      coarse end: a V-cycle that enters this
+                                      level from a zero guess applies the
+                                      explicit map x = T b of the cycle from
+                                      here down (FP64 assembly; streamed as
+                                      BF16 in the FP32/BF16 cycle, each entry
+                                      rounded to nearest even, and as FP32 in
+                                      the FP32 cycle); 0 elsewhere          */
 } amg_level_info;
 
 /* Fill *p with the defaults listed above. */
@@ -272,6 +280,24 @@ int amg_get_level_matrix(amg_handle h, int32_t level, int32_t which, int32_t *ro
 
 /* Colour of every node of level l (host array of n_lin + n_quad int32). */
 int amg_get_level_colors(amg_handle h, int32_t level, int32_t *colors);
+
+/* Launch shape of level l's row kernels, replacing the setup tuner's choice
+ * (for tests that run every variant; results agree up to rounding order).
+ * kernels: AMG_SHAPE_NATURAL the FP64 natural-order kernels (residual,
+ * Jacobi, operator, the outer Krylov operator on level 0), AMG_SHAPE_SWEEP
+ * the FP64 colour sweeps, AMG_SHAPE_NATURAL_RP / AMG_SHAPE_SWEEP_RP the same
+ * kernels of the reduced-precision copies. lanes: lanes of the 64-wide
+ * wavefront per row, one of 4, 8, 16, 32, 64. pair: 1 = two entries per lane
+ * and loop trip, 0 = one. xcd (colour sweeps only): 1 = each XCD takes one
+ * contiguous eighth of a colour's rows, 0 = round-robin placement.
+ * Recorded preconditioner graphs are dropped (they hold the old shapes).
+ * Errors: AMG_EINVAL for a bad level, kernel class, lane count or flag, or a
+ * reduced-precision class on an FP64 hierarchy. */
+#define AMG_SHAPE_NATURAL 0
+#define AMG_SHAPE_SWEEP 1
+#define AMG_SHAPE_NATURAL_RP 2
+#define AMG_SHAPE_SWEEP_RP 3
+int amg_set_launch_shape(amg_handle h, int32_t level, int32_t kernels, int32_t lanes, int32_t pair, int32_t xcd);
 
 /* ---- batches of independent saddle point systems ----------------------
  * Many solves of uneven size in one set of launches. Each system gets the

@@ -21,6 +21,7 @@ AMG_EINVAL, AMG_EHIP, AMG_ENOMEM, AMG_EUNSUPPORTED = -1, -2, -3, -4
 SMOOTH = {"JA": 0, "GS": 1, "SGS": 2, "BS": 3, "VANKA": 4}
 KRYLOV = {"PCG": 0, "FCG": 1, "FGMRES": 2, "NONE": 3}
 PREC = {"FP64": 0, "MIXED": 1, "FP32": 2}
+SHAPE = {"natural": 0, "sweep": 1, "natural_rp": 2, "sweep_rp": 3}
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _f64p = ctypes.POINTER(ctypes.c_double)
@@ -69,6 +70,7 @@ class AmgLevelInfo(ctypes.Structure):
         ("gs_xcd", ctypes.c_int32), ("pair_A", ctypes.c_int32), ("pair_gs", ctypes.c_int32),
         ("lanes64_A", ctypes.c_int32), ("pair64_A", ctypes.c_int32),
         ("kept_A", ctypes.c_int64), ("kept_B", ctypes.c_int64),
+        ("coarse_map", ctypes.c_int32),
     ]
 
 
@@ -88,6 +90,8 @@ SIGNATURES = {
     "amg_get_level_info": (ctypes.c_int, [_H, ctypes.c_int32, ctypes.POINTER(AmgLevelInfo)]),
     "amg_get_level_matrix": (ctypes.c_int, [_H, ctypes.c_int32, ctypes.c_int32, _i32p, _i32p, _f64p]),
     "amg_get_level_colors": (ctypes.c_int, [_H, ctypes.c_int32, _i32p]),
+    "amg_set_launch_shape": (ctypes.c_int, [_H, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                            ctypes.c_int32]),
     "amg_profile_enable": (ctypes.c_int, [_H, ctypes.c_int32]),
     "amg_profile_read": (ctypes.c_int, [_H, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64),
                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),

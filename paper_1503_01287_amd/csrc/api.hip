@@ -296,6 +296,7 @@ int amg_get_level_info(amg_handle h, int32_t level, amg_level_info *info) {
         info->omega = jacobi_omega(h, level);
         info->gs_xcd = h->mixed ? L.mp.xcd : L.gs_xcd;
         info->nnz_S = L.schur.lv.empty() ? 0 : L.schur.lv[0].S.nnz;
+        info->coarse_map = (level == h->dense_start) || (level == h->saddle_tail_from) ? 1 : 0;
         return AMG_OK;
     });
 }
@@ -464,6 +465,41 @@ void amg_mlp_destroy(amg_mlp_handle m) {
     if (!m) return;
     if (m->stream) (void)hipStreamSynchronize(m->stream);
     delete m;
+}
+
+int amg_set_launch_shape(amg_handle h, int32_t level, int32_t kernels, int32_t lanes, int32_t pair, int32_t xcd) {
+    return guarded([&]() -> int {
+        AMG_REQUIRE(h != nullptr, AMG_EINVAL, "amg_set_launch_shape: null handle");
+        AMG_REQUIRE(level >= 0 && level < static_cast<int>(h->lv.size()), AMG_EINVAL,
+                    "amg_set_launch_shape: bad level");
+        AMG_REQUIRE(lanes == 4 || lanes == 8 || lanes == 16 || lanes == 32 || lanes == 64, AMG_EINVAL,
+                    "amg_set_launch_shape: lanes must be 4, 8, 16, 32 or 64");
+        AMG_REQUIRE((pair == 0 || pair == 1) && (xcd == 0 || xcd == 1), AMG_EINVAL,
+                    "amg_set_launch_shape: pair and xcd are 0 or 1");
+        Level &L = h->lv[level];
+        const bool sweep = kernels == AMG_SHAPE_SWEEP || kernels == AMG_SHAPE_SWEEP_RP;
+        AMG_REQUIRE(sweep || xcd == 0, AMG_EINVAL, "amg_set_launch_shape: xcd applies to colour sweeps only");
+        switch (kernels) {
+            case AMG_SHAPE_NATURAL: L.G = lanes; L.pair = pair; break;
+            case AMG_SHAPE_SWEEP: L.Gg = lanes; L.pairg = pair; L.gs_xcd = xcd; break;
+            case AMG_SHAPE_NATURAL_RP:
+            case AMG_SHAPE_SWEEP_RP:
+                AMG_REQUIRE(h->mixed, AMG_EINVAL, "amg_set_launch_shape: no reduced-precision copy (FP64 hierarchy)");
+                if (kernels == AMG_SHAPE_NATURAL_RP) {
+                    L.mp.G = lanes;
+                    L.mp.pair = pair;
+                } else {
+                    L.mp.Gg = lanes;
+                    L.mp.pairg = pair;
+                    L.mp.xcd = xcd;
+                }
+                break;
+            default: throw Error(AMG_EINVAL, "amg_set_launch_shape: unknown kernel class");
+        }
+        for (auto &g : h->graphs) (void)hipGraphExecDestroy(g.exec);
+        h->graphs.clear();
+        return AMG_OK;
+    });
 }
 
 int amg_set_level_omega(amg_handle h, int32_t n, const double *omega) {

@@ -17,9 +17,13 @@ static int ceil_div_i(int64_t a, int b) { return static_cast<int>((a + b - 1) / 
 // Per scalar row: rho = sum_{off} |a| / |d|, sigma = (d + sum_{off} a) / d,
 // tau = sqrt(sum_{off} a^2) / |d|, nz = stored scalars of the row.
 // PASS 0 accumulates (rho, sigma, tau, nz, max rho); PASS 1 (rho - mean)^2.
+// mean_sum: when not null, the mean of rho is mean_sum[0] / rows (the pass-0
+// sum left on the device), else mean_rho.
 template <int MODE, int PASS>
 __global__ void __launch_bounds__(LB) k_row_stats(int rows, const int *rowptr, const int *col, const double *val,
-                                                   int64_t nnz, double mean_rho, double *partial) {
+                                                   int64_t nnz, double mean_rho, const double *mean_sum,
+                                                   double *partial) {
+    if (mean_sum) mean_rho = mean_sum[0] / rows;
     constexpr int NV = PASS == 0 ? 5 : 1;
     __shared__ double red[NV][LB];
     const int q = blockIdx.x * LB + threadIdx.x;
@@ -110,11 +114,11 @@ __global__ void __launch_bounds__(LB) k_stats_reduce(const double *partial, int 
 
 template <int PASS>
 static void stats_pass(int mode, int rows, const int *rowptr, const int *col, const double *val, int64_t nnz,
-                       double mean, double *partial, int nb, hipStream_t s) {
+                       double mean, const double *mean_sum, double *partial, int nb, hipStream_t s) {
     if (mode == 3)
-        k_row_stats<3, PASS><<<nb, LB, 0, s>>>(rows, rowptr, col, val, nnz, mean, partial);
+        k_row_stats<3, PASS><<<nb, LB, 0, s>>>(rows, rowptr, col, val, nnz, mean, mean_sum, partial);
     else
-        k_row_stats<1, PASS><<<nb, LB, 0, s>>>(rows, rowptr, col, val, nnz, mean, partial);
+        k_row_stats<1, PASS><<<nb, LB, 0, s>>>(rows, rowptr, col, val, nnz, mean, mean_sum, partial);
     AMG_CHECK_LAUNCH();
 }
 
@@ -125,12 +129,12 @@ void row_features(int mode, int n, const int *rowptr, const int *col, const doub
     const int rows = mode * n;
     const int nb = ceil_div_i(rows, LB);
     DevBuf<double> partial(static_cast<size_t>(nb) * 5), out(5);
-    stats_pass<0>(mode, rows, rowptr, col, val, nnz, 0.0, partial.p, nb, s);
+    stats_pass<0>(mode, rows, rowptr, col, val, nnz, 0.0, nullptr, partial.p, nb, s);
     k_stats_reduce<5><<<1, LB, 0, s>>>(partial.p, nb, out.p);
     AMG_CHECK_LAUNCH();
     std::vector<double> a = out.download(s);
     const double mean = a[0] / rows;
-    stats_pass<1>(mode, rows, rowptr, col, val, nnz, mean, partial.p, nb, s);
+    stats_pass<1>(mode, rows, rowptr, col, val, nnz, mean, nullptr, partial.p, nb, s);
     k_stats_reduce<1><<<1, LB, 0, s>>>(partial.p, nb, out.p);
     AMG_CHECK_LAUNCH();
     std::vector<double> b = out.download(s);

@@ -15,12 +15,19 @@ constexpr int MBLOCK = 256;
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t v) { return __uint_as_float(static_cast<uint32_t>(v) << 16); }
 
-// round to nearest even
-__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;  // NaN
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return static_cast<uint16_t>(u >> 16);
+// FP64 -> BF16, rounded once to the nearest value with 8 significant bits
+// (ties to even) straight from the FP64 value: the low 45 of FP64's 52
+// fraction bits are dropped with round-half-even, and the result, which has
+// 8 significant bits and an exponent inside FP32's normal range for the
+// scaled operator values, converts to FP32 exactly; its high 16 bits are the
+// BF16 value. (Rounding through FP32 first would round twice.)
+__device__ __forceinline__ uint16_t f64_to_bf16(double d) {
+    uint64_t u = static_cast<uint64_t>(__double_as_longlong(d));
+    if ((u & 0x7fffffffffffffffull) > 0x7ff0000000000000ull) return 0x7fc0;  // NaN
+    u += 0x00000fffffffffffull + ((u >> 45) & 1ull);
+    u &= ~0x00001fffffffffffull;
+    const float f = static_cast<float>(__longlong_as_double(static_cast<long long>(u)));
+    return static_cast<uint16_t>(__float_as_uint(f) >> 16);
 }
 
 template <int G>
@@ -298,7 +305,7 @@ __global__ void k_planes_bf16(int nrows, const int *rowptr, const int *rowid, co
         for (int p = 0; p < MODE * MODE; ++p) {
             const int r = p / MODE;
             const double v = src[static_cast<int64_t>(p) * nnz + k] / static_cast<double>(scale[MODE * i + r]);
-            dst[static_cast<int64_t>(p) * nnz + k] = f32_to_bf16(static_cast<float>(v));
+            dst[static_cast<int64_t>(p) * nnz + k] = f64_to_bf16(v);
         }
     }
 }
@@ -415,7 +422,7 @@ void launch_dense_gemv_bf16(const uint16_t *M, int m, int nc, const float *X, fl
 __global__ void k_to_bf16(const double *src, uint16_t *dst, int64_t n) {
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * MBLOCK + threadIdx.x; i < n;
          i += static_cast<int64_t>(gridDim.x) * MBLOCK)
-        dst[i] = f32_to_bf16(static_cast<float>(src[i]));
+        dst[i] = f64_to_bf16(src[i]);
 }
 
 void launch_to_bf16(const double *src, uint16_t *dst, int64_t n, hipStream_t s) {

@@ -185,6 +185,12 @@ class AMGSolver:
                 "amg_get_level_matrix")
         return rowptr, col[:nnz], val[: nnz * width].reshape(nnz, width)
 
+    def set_launch_shape(self, level: int, kernels: str, lanes: int, pair: bool = False, xcd: bool = False) -> None:
+        """Override the tuner's launch shape of one kernel class on a level:
+        kernels 'natural', 'sweep', 'natural_rp' or 'sweep_rp'."""
+        C.check(C.lib().amg_set_launch_shape(self.h, level, C.SHAPE[kernels], int(lanes), 1 if pair else 0,
+                                             1 if xcd else 0), "amg_set_launch_shape")
+
     def set_level_omega(self, omega) -> None:
         """New JA damping per level (level l uses omega[min(l, len - 1)])."""
         w = np.ascontiguousarray(omega, dtype=np.float64)
