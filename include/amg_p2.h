@@ -368,6 +368,19 @@ int amg_set_level_omega(amg_handle h, int32_t n, const double *omega);
  *    l / 10, log10(3 N_l) / 7]. */
 int amg_level_features(amg_handle h, int32_t level, double *features);
 
+/* amg_level_features for callers that cannot allocate device memory (code
+ * under HIP graph capture, serving loops, harnesses that forbid allocation):
+ * the same eight features of level l, written to features_dev, a DEVICE
+ * array of 8 doubles, on `stream` without allocating and without a host
+ * synchronisation (the call returns once the work is enqueued). The partial
+ * sums live in a fixed 1 MiB device array of the library, one per GPU, held
+ * until the process ends; the level may have at most 6,710,272 scalar rows
+ * (3 N_l for 3x3 blocks, N_l for bs = 1), else AMG_EINVAL. Every call on one
+ * GPU shares that array: calls that overlap on one GPU (other streams, other
+ * threads) race and must be ordered by the caller. Values agree with
+ * amg_level_features up to the last bit of the square root and logarithm. */
+int amg_level_features_noalloc(amg_handle h, int32_t level, double *features_dev, amg_stream stream);
+
 /* Per-kernel timing of the hot loops with HIP events recorded on the
  * library's launch stream (the stream of the call that launches them).
  * enable = 1 times every launch, enable = 2 only the finest level's launches

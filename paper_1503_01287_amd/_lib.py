@@ -109,6 +109,7 @@ SIGNATURES = {
                                      ctypes.c_float, _f32p]),
     "amg_mlp_destroy": (None, [ctypes.c_void_p]),
     "amg_level_features": (ctypes.c_int, [_H, ctypes.c_int32, _f64p]),
+    "amg_level_features_noalloc": (ctypes.c_int, [_H, ctypes.c_int32, ctypes.c_void_p, _S]),
     "amg_set_level_omega": (ctypes.c_int, [_H, ctypes.c_int32, _f64p]),
     "amg_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "amg_last_error": (ctypes.c_char_p, []),

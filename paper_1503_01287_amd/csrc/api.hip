@@ -530,6 +530,18 @@ int amg_level_features(amg_handle h, int32_t level, double *features) {
     });
 }
 
+int amg_level_features_noalloc(amg_handle h, int32_t level, double *features_dev, amg_stream stream) {
+    return guarded([&]() -> int {
+        AMG_REQUIRE(h && features_dev, AMG_EINVAL, "amg_level_features_noalloc: null argument");
+        AMG_REQUIRE(level >= 0 && level < static_cast<int>(h->lv.size()), AMG_EINVAL, "bad level");
+        const Level &L = h->lv[level];
+        const DMat &A = L.A_pat.nnz > 0 ? L.A_pat : L.A;
+        row_features_noalloc(L.mode, L.n, A.rowptr.p, A.col.p, A.val.p, A.nnz, level, features_scratch_address(),
+                             features_dev, static_cast<hipStream_t>(stream));
+        return AMG_OK;
+    });
+}
+
 const char *amg_status_string(int status) {
     switch (status) {
         case AMG_OK: return "converged";

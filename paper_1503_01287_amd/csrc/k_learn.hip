@@ -3,6 +3,8 @@
 // partials; per-parameter gradient sums over the samples in order), so the
 // results are deterministic.
 #include <cmath>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "learn.h"
@@ -146,6 +148,76 @@ void row_features(int mode, int n, const int *rowptr, const int *col, const doub
     f[5] = a[3] / rows / 64.0;
     f[6] = level / 10.0;
     f[7] = std::log10(3.0 * n) / 7.0;
+}
+
+// ------------------------------------------------------------ features without allocation
+// The same two passes with every intermediate in a fixed device array of the
+// library (`scratch`, one copy per GPU for the life of the process) instead
+// of buffers allocated per call, and the eight features written to the
+// device: [0, 8) the reductions (pass-0 sums and maximum, pass-1 sum),
+// [8, 8 + 5 nb) the per-block partials. Nothing in it needs clearing: each
+// call writes every value it reads.
+constexpr int64_t FEAT_SCRATCH_DOUBLES = 131072;  // 1 MiB
+constexpr int64_t FEAT_PARTIAL_OFF = 8;
+constexpr int FEAT_MAX_BLOCKS = static_cast<int>((FEAT_SCRATCH_DOUBLES - FEAT_PARTIAL_OFF) / 5);
+static __device__ __align__(256) double scratch[FEAT_SCRATCH_DOUBLES];
+
+int features_noalloc_max_rows() { return FEAT_MAX_BLOCKS * LB; }
+
+// out[0..8) from the reductions, the same expressions as row_features' host part
+__global__ void k_features_final(const double *red, int rows, int n, int level, double *out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double mean = red[0] / rows;
+    out[0] = mean;
+    out[1] = red[4];
+    out[2] = sqrt(red[5] / rows);
+    out[3] = red[1] / rows;
+    out[4] = red[2] / rows;
+    out[5] = red[3] / rows / 64.0;
+    out[6] = level / 10.0;
+    out[7] = log10(3.0 * n) / 7.0;
+}
+
+void row_features_noalloc(int mode, int n, const int *rowptr, const int *col, const double *val, int64_t nnz,
+                          int level, double *scratch_dev, double *f_dev, hipStream_t s) {
+    AMG_REQUIRE(mode == 1 || mode == 3, AMG_EINVAL, "row_features: mode must be 1 or 3");
+    AMG_REQUIRE(n > 0, AMG_EINVAL, "row_features: empty level");
+    const int64_t rows64 = static_cast<int64_t>(mode) * n;
+    AMG_REQUIRE(rows64 <= features_noalloc_max_rows(), AMG_EINVAL,
+                "amg_level_features_noalloc: level has " + std::to_string(rows64) +
+                    " scalar rows, more than the fixed scratch array serves (" +
+                    std::to_string(features_noalloc_max_rows()) + ")");
+    const int rows = static_cast<int>(rows64);
+    const int nb = ceil_div_i(rows, LB);
+    double *red = scratch_dev;
+    double *partial = scratch_dev + FEAT_PARTIAL_OFF;
+    stats_pass<0>(mode, rows, rowptr, col, val, nnz, 0.0, nullptr, partial, nb, s);
+    k_stats_reduce<5><<<1, LB, 0, s>>>(partial, nb, red);
+    AMG_CHECK_LAUNCH();
+    stats_pass<1>(mode, rows, rowptr, col, val, nnz, 0.0, red, partial, nb, s);
+    k_stats_reduce<1><<<1, LB, 0, s>>>(partial, nb, red + 5);
+    AMG_CHECK_LAUNCH();
+    k_features_final<<<1, 64, 0, s>>>(red, rows, n, level, f_dev);
+    AMG_CHECK_LAUNCH();
+}
+
+// Device address of `scratch` on the current device: looked up once per
+// device with that device current (each GPU holds its own copy of the array
+// at its own address; the array's name is not a device address in host code).
+double *features_scratch_address() {
+    static std::mutex mu;
+    static double *addr[64] = {};
+    int d = 0;
+    AMG_HIP(hipGetDevice(&d));
+    AMG_REQUIRE(d >= 0 && d < 64, AMG_EINVAL, "features scratch: device index beyond 63");
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[d]) {
+        void *p = nullptr;
+        AMG_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        AMG_REQUIRE(p != nullptr, AMG_EHIP, "features scratch: no device address");
+        addr[d] = static_cast<double *>(p);
+    }
+    return addr[d];
 }
 
 // ------------------------------------------------------------ network

@@ -24,6 +24,15 @@ constexpr float MLP_OMEGA_MIN = 0.2f, MLP_OMEGA_SPAN = 1.0f;
 void row_features(int mode, int n, const int *rowptr, const int *col, const double *val, int64_t nnz, int level,
                   double *features_host, hipStream_t s);
 
+// The same features written to f_dev (8 device doubles), stream-ordered,
+// with every intermediate in scratch_dev (features_scratch_address()): no
+// allocation, no host synchronisation. Levels of more than
+// features_noalloc_max_rows() scalar rows are rejected (AMG_EINVAL).
+void row_features_noalloc(int mode, int n, const int *rowptr, const int *col, const double *val, int64_t nnz,
+                          int level, double *scratch_dev, double *f_dev, hipStream_t s);
+int features_noalloc_max_rows();
+double *features_scratch_address();
+
 struct MlpWork {
     int cap = 0;
     DevBuf<float> X, y, H1, H2, S, om, D1, D2, D3, err2;

@@ -202,6 +202,12 @@ class AMGSolver:
         C.check(C.lib().amg_level_features(self.h, level, C._ptr(out, ctypes.c_double)), "amg_level_features")
         return out
 
+    def level_features_noalloc(self, level: int, out) -> None:
+        """The eight features into a device tensor of 8 float64 (stream-ordered,
+        no allocation inside the library)."""
+        C.check(C.lib().amg_level_features_noalloc(self.h, level, _dev_ptr(out, 8, "out"),
+                                                   _stream_handle(self._stream)), "amg_level_features_noalloc")
+
     def level_colors(self, level: int) -> np.ndarray:
         info = self.level_info(level)
         out = np.zeros(info.n_lin + info.n_quad, dtype=np.int32)
