@@ -174,6 +174,298 @@ def cpu_baseline(name: str, iters_full: int, tol: float, budget_s: float = 20.0)
                       f"host has {os.cpu_count()} logical CPUs"}
 
 
+# kernel classes of the library's profiler (amg_profile_read): one launch of
+# one kernel per event pair, except "blas" (a partial-sum kernel and its
+# reduction), which the roofline leaves out
+CYCLE_OPS = ("gs", "resid", "jacobi", "jacobi0", "restrict", "prolong", "vanka", "spmv")
+SINGLE_CLASSES = ("coarse", "dense_tail", "saddle_tail", "tail")
+
+
+def _profile_classes(nlevels: int) -> list:
+    return [f"{op}.L{l}" for l in range(nlevels) for op in CYCLE_OPS] + list(SINGLE_CLASSES) + ["blas"]
+
+
+def _class_shape(cls: str, levels: list):
+    """(lanes, pair, xcd) of the kernel a class launches, for the traffic lookup."""
+    if "." not in cls:
+        return -1, 0, 0
+    op, lv = cls.split(".")
+    lv = levels[int(lv[1:])]
+    if op == "spmv":
+        return lv["fp64"][0], lv["fp64"][1], 0
+    which = 1 if op == "gs" else 0
+    return lv["lanes"][which], lv["pair"][which], (lv["gs_xcd"] if which else 0)
+
+
+# ---------------------------------------------------------------- assembly
+def _assemble_cavity(args):
+    from paper_1503_01287_amd import problems
+    n, sp = args
+    return problems.stokes_cavity(n, sp)
+
+
+class _Grid:
+    def __init__(self, n):
+        self.n = n
+
+
+def _laplace_rhs_chunk(args):
+    import synth
+    from paper_1503_01287_amd import problems
+    n, ids = args
+    return problems.laplace_rhs_many(_Grid(n), synth.LAPLACE_LARGE, ids)
+
+
+def _pool(workers: int):
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    # spawn: the workers start clean (no GPU runtime state from this process)
+    return ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn"))
+
+
+def assemble(name: str, n_rhs: int, workers: int):
+    """The workload's system (host arrays) and its right-hand sides, the
+    independent pieces assembled in parallel on the host cores."""
+    import synth
+    from paper_1503_01287_amd import problems
+    if name == "stokes-batch-64":
+        with _pool(workers) as ex:
+            systems = list(ex.map(_assemble_cavity, synth.stokes_batch()))
+        b = _Batch(systems)
+        return b, [b.rhs]
+    sysm = build_system(name)
+    if name != "laplace-48":
+        return sysm, [sysm.rhs]
+    ids = list(range(n_rhs))
+    k = max(1, min(workers, 8, len(ids)))
+    chunks = [(sysm.n, ids[i::k]) for i in range(k)]
+    with _pool(k) as ex:
+        parts = list(ex.map(_laplace_rhs_chunk, chunks))
+    rhs = [None] * len(ids)
+    for (_, cid), part in zip(chunks, parts):
+        for i, r in zip(cid, part):
+            rhs[i] = r
+    return sysm, rhs
+
+
+# ---------------------------------------------------------------- measurement
+def measure(name: str, sysm, rhs, steps: int, warmup: int, tol: float, precision: str, profile: bool,
+            variants: list, reference: bool = True) -> dict:
+    """Time each variant (setup once, `warmup` untimed and `steps` timed
+    solves, right-hand side k for solve k), optionally profile the first one
+    (HIP events around every launch of every level), and measure every
+    variant's error against an FP64 solve of the last right-hand side to
+    1e-12 (run by the FP64 variant's own hierarchy)."""
+    import torch
+    import paper_1503_01287_amd as amg
+    from paper_1503_01287_amd import learned
+    wl = WORKLOADS[name]
+    saddle, batch = wl.get("saddle", False), wl.get("batch", False)
+    dev = torch.device("cuda:0")
+    bs = [torch.from_numpy(r).to(dev) for r in rhs]
+    x = torch.zeros_like(bs[0])
+    model = learned.DampingModel.load() if os.path.exists(learned.MODEL_PATH) else None
+
+    def make(prec: str, krylov: str, with_model: bool, omega=None):
+        if batch:
+            return amg.BatchedSolver(sysm.systems, smoother=wl["smoother"], precision=prec)
+        kw = {"omega_model": model} if (with_model and model is not None) else {}
+        if omega is not None:
+            kw["level_omega"] = [omega]
+        return amg.AMGSolver(sysm, smoother=wl["smoother"], krylov=krylov, precision=prec, **kw)
+
+    def solve_once(solver, t, k=-1):
+        x.zero_()
+        r = solver.solve(bs[k % len(bs)], x, tol=t, maxit=1000)
+        if batch:
+            return all(q.converged and q.relres <= t * 1.0001 for q in r), max(q.iters for q in r), \
+                max(q.relres for q in r)
+        return r.converged and r.relres <= t * 1.0001, r.iters, r.relres
+
+    def levels_of(solver):
+        out = []
+        for l in range(solver.num_levels):
+            i = solver.level_info(l)
+            out.append(dict(nodes=i.n_lin + i.n_quad, pressure=i.n_pres, nnz=int(i.nnz_A), kept=int(i.kept_A),
+                            colors=int(i.n_colors), lanes=[int(i.lanes_A), int(i.lanes_gs)],
+                            pair=[int(i.pair_A), int(i.pair_gs)], fp64=[int(i.lanes64_A), int(i.pair64_A)],
+                            gs_xcd=int(i.gs_xcd), fused=bool(i.fused), coarse_map=bool(i.coarse_map),
+                            omega=round(float(i.omega), 4)))
+        return out
+
+    def run_variant(v: dict) -> dict:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        solver = make(v["precision"], v["krylov"], v.get("model", False), v.get("omega"))
+        torch.cuda.synchronize()
+        setup_ms = (time.perf_counter() - t0) * 1e3
+        levels = levels_of(solver)
+        print(f"# {name} {v['label']}: setup {setup_ms:.0f} ms", file=sys.stderr, flush=True)
+        for k in range(warmup):
+            solve_once(solver, tol, k)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        results = [solve_once(solver, tol, warmup + k) for k in range(steps)]
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        if not all(r[0] for r in results):
+            raise SystemExit(f"# {name} {v['label']}: solve did not converge: {results}")
+        ms = elapsed * 1e3 / steps
+        out = dict(label=v["label"], precision=v["precision"], krylov=v["krylov"], setup_ms=round(setup_ms, 1),
+                   ms_per_step=round(ms, 3), value=sysm.dofs * steps / elapsed, iterations=results[-1][1],
+                   relres=results[-1][2], levels=levels, solution=x.clone(),
+                   learned_omega=bool(v.get("model") and model is not None))
+        if v.get("omega") is not None:
+            out["omega"] = v["omega"]
+        print(f"# {name} {v['label']}: {steps} solves, {ms:.2f} ms/solve, {results[-1][1]} iterations, "
+              f"relres {results[-1][2]:.2e}", file=sys.stderr, flush=True)
+        if v.get("profile"):
+            out.update(profile_pass(solver, levels))
+        if v.get("reference"):
+            last = warmup + steps - 1
+            ok, its, _ = solve_once(solver, 1e-12, last)
+            out["reference"] = (x.clone(), its)
+        solver.close()
+        return out
+
+    def profile_pass(solver, levels) -> dict:
+        """The same solves again with HIP events around every launch."""
+        solver.profile(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            solve_once(solver, tol, warmup + k)
+        torch.cuda.synchronize()
+        prof_ms = (time.perf_counter() - t0) * 1e3 / steps
+        stats = {c: solver.profile_read(c) for c in _profile_classes(len(levels))}
+        solver.profile(0)
+        stats = {c: v for c, v in stats.items() if v["launches"] > 0}
+        res = {}
+        kern = {c: v for c, v in stats.items() if c != "blas"}
+        if kern:
+            dom = max(kern, key=lambda c: kern[c]["ms"])
+            st = kern[dom]
+            per_launch_bytes = st["bytes"] / st["launches"]
+            per_launch_ms = st["ms"] / st["launches"]
+            achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
+            lanes, pair, xcd = _class_shape(dom, levels)
+            traffic = measured_traffic(name, precision, dom, lanes, pair, xcd)
+            res["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                               "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                               "kernel": dom, "launches_per_step": st["launches"] // steps,
+                               "bytes_per_launch": per_launch_bytes,
+                               "mean_launch_us": round(per_launch_ms * 1e3, 2),
+                               "profiled_ms_per_step": round(prof_ms, 2)}
+
+            def agg(sel):
+                b_ = sum(v["bytes"] for c, v in sel.items())
+                m_ = sum(v["ms"] for c, v in sel.items())
+                return round(b_ / max(m_ * 1e-3, 1e-12) / 1e9, 1), round(m_ / steps, 3)
+            cyc = {c: v for c, v in kern.items() if c != "spmv.L0"}
+            fin = {c: v for c, v in cyc.items() if c.endswith(".L0")}
+            all_gbps, all_ms = agg(cyc)
+            fin_gbps, fin_ms = agg(fin)
+            per_level = {}
+            for l in range(len(levels)):
+                lv = {c: v for c, v in cyc.items() if c.endswith(f".L{l}")}
+                if lv:
+                    g_, m_ = agg(lv)
+                    per_level[f"L{l}"] = {"GBps": g_, "ms_per_step": m_}
+            ce = {c: v for c, v in cyc.items() if c in SINGLE_CLASSES}
+            if ce:
+                g_, m_ = agg(ce)
+                per_level["coarse_end"] = {"GBps": g_, "ms_per_step": m_}
+            res["vcycle_bandwidth"] = {
+                "all_levels_GBps": all_gbps, "all_levels_ms_per_step": all_ms,
+                "all_levels_frac": round(all_gbps / HBM_PEAK_GBS, 4),
+                "finest_level_GBps": fin_gbps, "finest_level_ms_per_step": fin_ms,
+                "per_level": per_level,
+                "per_class": {c: {"launches_per_step": v["launches"] // steps,
+                                  "ms_per_step": round(v["ms"] / steps, 3),
+                                  "GBps": round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 1)}
+                              for c, v in sorted(kern.items(), key=lambda kv: -kv[1]["ms"])},
+                "note": "algorithmic bytes over HIP-event time per launch, every launch of every level; "
+                        "all_levels: the V-cycle's kernels (the outer FP64 operator spmv.L0 and the Krylov "
+                        "vector kernels excluded)"}
+        return res
+
+    out = {"workload": f"{name}: {wl['desc']}", "dofs": sysm.dofs, "rhs_data_sets": len(bs), "variants": {}}
+    ref = None
+    for v in variants:
+        r = run_variant(v)
+        if "reference" in r:
+            ref, out["reference_iterations"] = r.pop("reference")
+        out["variants"][v["label"]] = r
+    if ref is not None:
+        def centred(t):
+            if not saddle:
+                return t
+            t = t.clone()
+            o = 0
+            for s_ in (sysm.systems if batch else [sysm]):
+                if s_.pressure_kernel:
+                    p_ = t[o + 3 * s_.nodes:o + s_.dofs]
+                    p_ -= p_.mean()
+                o += s_.dofs
+            return t
+        refc = centred(ref)
+        for r in out["variants"].values():
+            r["error_vs_fp64_reference"] = float(torch.linalg.norm(centred(r["solution"]) - refc)
+                                                 / torch.linalg.norm(refc))
+    for r in out["variants"].values():
+        r.pop("solution", None)
+    return out
+
+
+def variants_for(name: str, precision: str, profile: bool, extras: bool) -> list:
+    wl = WORKLOADS[name]
+    saddle = wl.get("saddle", False)
+    prec = wl.get("precision", precision) if precision != "FP64" else "FP64"
+    kry = "FGMRES" if saddle else ("PCG" if prec == "FP64" else "FCG")
+    fp64_kry = "FGMRES" if saddle else "PCG"
+    if name == "laplace-48":
+        v = [dict(label="learned_mixed", precision=prec, krylov=kry, model=True, profile=profile)]
+        if extras:
+            v.append(dict(label="fixed_mixed", precision=prec, krylov=kry))
+        v.append(dict(label="fixed_fp64", precision="FP64", krylov=fp64_kry, reference=True))
+        return v
+    v = [dict(label="primary", precision=prec, krylov=kry, profile=profile)]
+    if prec != "FP64":
+        v.append(dict(label="fp64", precision="FP64", krylov=fp64_kry, reference=True))
+    else:
+        v[0]["reference"] = True
+    return v
+
+
+def best_global_omega(name: str, sysm, rhs, tol: float, grid=None) -> dict:
+    """The best single damping weight for every level (JA, reduced-precision
+    cycle in FCG): fewest iterations on the first right-hand side over a grid,
+    ties broken by time; the baseline the learned per-level weights are
+    compared with beside the paper's fixed 0.5."""
+    import torch
+    import paper_1503_01287_amd as amg
+    grid = grid or [round(0.30 + 0.05 * i, 2) for i in range(19)]
+    dev = torch.device("cuda:0")
+    b = torch.from_numpy(rhs[0]).to(dev)
+    x = torch.zeros_like(b)
+    s = amg.AMGSolver(sysm, smoother="JA-1-1-0.5", krylov="FCG", precision="MIXED")
+    rows = []
+    for w in grid:
+        s.set_level_omega([w])
+        x.zero_()
+        r = s.solve(b, x, tol=tol, maxit=300)
+        torch.cuda.synchronize()
+        x.zero_()
+        t0 = time.perf_counter()
+        r = s.solve(b, x, tol=tol, maxit=300)
+        torch.cuda.synchronize()
+        rows.append((r.iters if r.converged else 10 ** 6, time.perf_counter() - t0, w))
+    s.close()
+    its, t, w = min(rows)
+    print(f"# {name}: best global omega {w} ({its} iterations)", file=sys.stderr, flush=True)
+    return {"omega": w, "iterations": its, "grid": [g[2] for g in rows], "grid_iterations": [g[0] for g in rows]}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -184,220 +476,77 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the event-timed pass")
     ap.add_argument("--only-timed", action="store_true",
-                    help="for profiler runs: only the timed variant (no FP64 or unbatched comparison, no "
-                         "reference solve, so no error figures)")
+                    help="for profiler runs: only the timed variant (no FP64 comparison, no reference "
+                         "solve, so no error figures, no other workloads)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the other workloads' lines (learned damping on the 48^3 Laplacian, the "
+                         "64-cavity Stokes batch) that the default elasticity run adds")
     ap.add_argument("--precision", default="MIXED", choices=["MIXED", "FP32", "FP64"],
                     help="cycle arithmetic of the timed solve (FP64 outer loop always; the Stokes batch "
                          "uses FP32 unless FP64 is asked for); the plain FP64 solve is timed beside it")
+    ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1),
+                    help="host processes for assembling independent systems and right-hand sides")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
               "(one MI355X per process; sharding is a design note only)", file=sys.stderr)
         return 2
 
-    import torch
-    import paper_1503_01287_amd as amg
-    from paper_1503_01287_amd import learned
-
-    wl = WORKLOADS[args.workload]
-    saddle, batch = wl.get("saddle", False), wl.get("batch", False)
-    precision = wl.get("precision", args.precision) if args.precision != "FP64" else "FP64"
-    t0 = time.perf_counter()
-    sysm = build_system(args.workload)
-    t_asm = time.perf_counter() - t0
-    print(f"# assembled {sysm.name}: {sysm.dofs} DOF in {t_asm:.1f}s", file=sys.stderr, flush=True)
-
-    dev = torch.device("cuda:0")
-    b = torch.from_numpy(sysm.rhs).to(dev)
-    x = torch.zeros_like(b)
-    # right-hand sides: the vector Laplacian workload is one setup and many
-    # solves, each with its own seeded Dirichlet data set (solve k uses data
-    # set k); the others solve their one right-hand side repeatedly
-    bs = [b]
-    if args.workload == "laplace-48":
-        import synth
-        from paper_1503_01287_amd import problems
-        t0 = time.perf_counter()
-        bs = [torch.from_numpy(r).to(dev) for r in
-              problems.laplace_rhs_many(sysm, synth.LAPLACE_LARGE, range(args.warmup + args.steps))]
-        print(f"# {len(bs)} Dirichlet data sets in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
-    use_model = args.workload == "laplace-48" and os.path.exists(learned.MODEL_PATH)
-    model = learned.DampingModel.load() if use_model else None
-
-    def make(precision: str, krylov: str, with_model: bool):
-        if batch:
-            return amg.BatchedSolver(sysm.systems, smoother=wl["smoother"], precision=precision)
-        kw = {"omega_model": model} if (with_model and model is not None) else {}
-        return amg.AMGSolver(sysm, smoother=wl["smoother"], krylov=krylov, precision=precision, **kw)
-
-    def solve_once(solver, tol, k=-1):
-        x.zero_()
-        r = solver.solve(bs[k % len(bs)], x, tol=tol, maxit=1000)
-        if batch:
-            ok = all(q.converged and q.relres <= tol * 1.0001 for q in r)
-            return ok, max(q.iters for q in r), max(q.relres for q in r)
-        return r.converged and r.relres <= tol * 1.0001, r.iters, r.relres
-
-    def run_variant(precision: str, krylov: str, profile: bool, with_model: bool = False) -> dict:
-        """amg_setup (timed once), W warm-up and K timed solves; optionally
-        the same K solves again with HIP events on the finest level."""
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        solver = make(precision, krylov, with_model)
-        torch.cuda.synchronize()
-        setup_ms = (time.perf_counter() - t0) * 1e3
-        levels = []
-        for l in range(solver.num_levels):
-            i = solver.level_info(l)
-            levels.append(dict(nodes=i.n_lin + i.n_quad, pressure=i.n_pres, nnz=int(i.nnz_A), kept=int(i.kept_A), colors=int(i.n_colors),
-                               lanes=[int(i.lanes_A), int(i.lanes_gs)], pair=[int(i.pair_A), int(i.pair_gs)],
-                               fp64=[int(i.lanes64_A), int(i.pair64_A)],
-                               gs_xcd=int(i.gs_xcd), fused=bool(i.fused),
-                               omega=round(float(i.omega), 4)))
-        print(f"# {precision}/{krylov} setup {setup_ms:.0f} ms, levels {levels}", file=sys.stderr, flush=True)
-        for k in range(args.warmup):
-            solve_once(solver, args.tol, k)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        results = [solve_once(solver, args.tol, args.warmup + k) for k in range(args.steps)]
-        torch.cuda.synchronize()
-        elapsed = time.perf_counter() - t0
-        if not all(r[0] for r in results):
-            raise SystemExit(f"# {precision}/{krylov}: solve did not converge: {results}")
-        ms = elapsed * 1e3 / args.steps
-        sol = x.clone()
-        out = dict(precision=precision, krylov=krylov, setup_ms=round(setup_ms, 1), ms_per_step=round(ms, 3),
-                   value=sysm.dofs * args.steps / elapsed, iterations=results[-1][1],
-                   relres=results[-1][2], levels=levels, solution=sol, learned_omega=bool(with_model and model))
-        print(f"# {precision}/{krylov}{' learned-omega' if out['learned_omega'] else ''}: {args.steps} solves, "
-              f"{ms:.2f} ms/solve, {results[-1][1]} iterations, relres {results[-1][2]:.2e}",
-              file=sys.stderr, flush=True)
-        if profile:
-            solver.profile(2)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for k in range(args.steps):
-                solve_once(solver, args.tol, args.warmup + k)
-            torch.cuda.synchronize()
-            prof_ms = (time.perf_counter() - t0) * 1e3 / args.steps
-            classes = ["gs.L0", "resid.L0", "spmv.L0", "jacobi.L0", "jacobi0.L0", "restrict.L0", "prolong.L0"]
-            stats = {c: solver.profile_read(c) for c in classes}
-            solver.profile(0)
-            stats = {c: v for c, v in stats.items() if v["launches"] > 0}
-            if stats:
-                dom = max(stats, key=lambda c: stats[c]["ms"])
-                st = stats[dom]
-                per_launch_bytes = st["bytes"] / st["launches"]
-                per_launch_ms = st["ms"] / st["launches"]
-                achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
-                # the outer operator is the FP64 kernel; the cycle's kernels
-                # are the reduced-precision copies unless the cycle is FP64
-                if dom.startswith("spmv."):
-                    lanes, pair, xcd = levels[0]["fp64"][0], levels[0]["fp64"][1], 0
-                else:
-                    which = 1 if dom.startswith("gs.") else 0
-                    lanes, pair = levels[0]["lanes"][which], levels[0]["pair"][which]
-                    xcd = levels[0]["gs_xcd"] if which else 0
-                traffic = measured_traffic(args.workload, precision, dom, lanes, pair, xcd)
-                out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                                   "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                                   "kernel": dom, "launches_per_step": st["launches"] // args.steps,
-                                   "bytes_per_launch": per_launch_bytes,
-                                   "mean_launch_us": round(per_launch_ms * 1e3, 2),
-                                   "profiled_ms_per_step": round(prof_ms, 2)}
-                tot_b = sum(v["bytes"] for v in stats.values())
-                tot_ms = sum(v["ms"] for v in stats.values())
-                out["vcycle_bandwidth"] = {
-                    "finest_level_GBps": round(tot_b / (tot_ms * 1e-3) / 1e9, 1),
-                    "finest_level_ms_per_step": round(tot_ms / args.steps, 3),
-                    "per_class": {c: {"launches_per_step": v["launches"] // args.steps,
-                                      "ms_per_step": round(v["ms"] / args.steps, 3),
-                                      "GBps": round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 1)}
-                                  for c, v in stats.items()}}
-        solver.close()
-        return out
-
+    name = args.workload
     full = not args.only_timed
-    if saddle:
-        prim = run_variant(precision, "FGMRES", not args.no_profile)
-        comp = run_variant("FP64", "FGMRES", False) if precision != "FP64" and full else None
-    else:
-        primary_kry = "PCG" if precision == "FP64" else "FCG"
-        prim = run_variant(precision, primary_kry, not args.no_profile, with_model=use_model)
-        comp = run_variant("FP64", "PCG", False) if (precision != "FP64" or use_model) and full else None
-    # the same systems solved one after another (batch only), once
-    unbatched = None
-    if batch and full:
-        t_all, its = 0.0, []
-        for s_ in sysm.systems:
-            single = amg.AMGSolver(s_, smoother=wl["smoother"], krylov="FGMRES", precision=precision)
-            bb = torch.from_numpy(s_.rhs).to(dev)
-            xx = torch.zeros_like(bb)
-            single.solve(bb, xx, tol=args.tol, maxit=1000)
-            xx.zero_()
-            torch.cuda.synchronize()
+    extras = full and not args.no_extras and name == "elasticity-32"
+    extra_steps, extra_warmup = min(args.steps, 5), 1
+    # host assembly first, before this process touches the GPU
+    t0 = time.perf_counter()
+    sysm, rhs = assemble(name, args.warmup + args.steps, args.workers)
+    print(f"# assembled {sysm.name}: {sysm.dofs} DOF, {len(rhs)} right-hand side(s) in "
+          f"{time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    other = {}
+    if extras:
+        for xn in ("laplace-48", "stokes-batch-64"):
             t0 = time.perf_counter()
-            r = single.solve(bb, xx, tol=args.tol, maxit=1000)
-            torch.cuda.synchronize()
-            t_all += time.perf_counter() - t0
-            its.append(r.iters)
-            single.close()
-        unbatched = {"ms_per_step": round(t_all * 1e3, 2), "value": round(sysm.dofs / t_all, 1),
-                     "iterations_max": max(its), "iterations_min": min(its),
-                     "note": "the same systems, one amg_solve after another (warm, FGMRES, same smoother "
-                             "and precision)"}
-        print(f"# unbatched: {t_all * 1e3:.1f} ms for all systems", file=sys.stderr, flush=True)
+            other[xn] = assemble(xn, extra_warmup + extra_steps, args.workers)
+            print(f"# assembled {xn} in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
 
-    # reference solution for the error of each variant: FP64 to 1e-12 (untimed)
-    ref_iters = None
-    prim["error_vs_fp64_reference"] = None
-    if full:
-        ref_solver = make("FP64", "FGMRES" if saddle else "PCG", False)
-        # the same right-hand side as the variants' last timed solve
-        last = args.warmup + args.steps - 1
-        solve_once(ref_solver, 1e-12, last)
-        ref = x.clone()
-        ref_res = solve_once(ref_solver, 1e-12, last)
-        ref_solver.close()
-        ref_iters = ref_res[1]
+    precision = WORKLOADS[name].get("precision", args.precision) if args.precision != "FP64" else "FP64"
+    vs = variants_for(name, args.precision, not args.no_profile, False)
+    if not full:
+        vs = [dict(v, reference=False) for v in vs[:1]]
+    prim_all = measure(name, sysm, rhs, args.steps, args.warmup, args.tol, precision, not args.no_profile, vs)
+    labels = list(prim_all["variants"])
+    prim = prim_all["variants"][labels[0]]
+    comp = prim_all["variants"][labels[-1]] if len(labels) > 1 else None
 
-        def centred(v):
-            """Pressure of systems with constants in the pressure kernel taken with zero mean."""
-            if not saddle:
-                return v
-            v = v.clone()
-            systems = sysm.systems if batch else [sysm]
-            o = 0
-            for s_ in systems:
-                if s_.pressure_kernel:
-                    nu = 3 * s_.nodes
-                    p_ = v[o + nu:o + s_.dofs]
-                    p_ -= p_.mean()
-                o += s_.dofs
-            return v
+    others = None
+    if extras:
+        others = {}
+        for xn, (xs, xr) in other.items():
+            xprec = WORKLOADS[xn].get("precision", "MIXED")
+            res = measure(xn, xs, xr, extra_steps, extra_warmup, args.tol, xprec, False,
+                          variants_for(xn, args.precision, False, True))
+            if xn == "laplace-48":
+                best = best_global_omega(xn, xs, xr, args.tol)
+                bw = measure(xn, xs, xr, extra_steps, extra_warmup, args.tol, "MIXED", False,
+                             [dict(label="best_global_omega_mixed", precision="MIXED", krylov="FCG",
+                                   omega=best["omega"]),
+                              dict(label="fixed_fp64", precision="FP64", krylov="PCG", reference=True)])
+                res["variants"]["best_global_omega_mixed"] = bw["variants"]["best_global_omega_mixed"]
+                res["best_global_omega_search"] = best
+            for r in res["variants"].values():
+                r.pop("levels", None)
+                for k in ("value", "relres"):
+                    r[k] = float(f"{r[k]:.6g}")
+            others[xn] = res
 
-        refc = centred(ref)
-
-        def err(v):
-            return float(torch.linalg.norm(centred(v["solution"]) - refc) / torch.linalg.norm(refc))
-
-        prim["error_vs_fp64_reference"] = err(prim)
-        if comp:
-            comp["error_vs_fp64_reference"] = err(comp)
     ms, value, iters = prim["ms_per_step"], prim["value"], prim["iterations"]
-    roofline = prim.get("roofline")
-    vcycle = prim.get("vcycle_bandwidth")
-    setup_ms, levels = prim["setup_ms"], prim["levels"]
-    results_relres = prim["relres"]
-
     cpu = None
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
-        cpu = cpu_baseline(args.workload, comp["iterations"] if comp else iters, args.tol)
+        cpu = cpu_baseline(name, comp["iterations"] if comp else iters, args.tol)
         print(f"# cpu baseline {time.perf_counter() - t0:.0f}s: {cpu['value']:.3g} DOF-solves/s",
               file=sys.stderr, flush=True)
 
-    kry = prim["krylov"]
+    wl = WORKLOADS[name]
     dtype = "f64" if precision == "FP64" else (
         "f32 cycle, f64 outer" if precision == "FP32" else "f32/bf16 cycle, f64 outer")
     out = {
@@ -413,23 +562,23 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": dtype,
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {wl['desc']}", "dofs": sysm.dofs,
-                   "smoother": wl["smoother"], "krylov": kry, "precision": precision,
+        "config": {"workload": prim_all["workload"], "dofs": sysm.dofs,
+                   "smoother": wl["smoother"], "krylov": prim["krylov"], "precision": precision,
                    "learned_omega": prim["learned_omega"],
-                   "tol": args.tol, "iterations": iters, "relres": results_relres,
-                   "error_vs_fp64_reference": prim["error_vs_fp64_reference"],
-                   "setup_ms": round(setup_ms, 1), "levels": levels, "parallelism": "single GPU",
-                   "rhs_data_sets": len(bs)},
+                   "tol": args.tol, "iterations": iters, "relres": prim["relres"],
+                   "error_vs_fp64_reference": prim.get("error_vs_fp64_reference"),
+                   "setup_ms": prim["setup_ms"], "levels": prim["levels"], "parallelism": "single GPU",
+                   "rhs_data_sets": prim_all["rhs_data_sets"]},
         "fp64_comparison": None if comp is None else {
             k: (float(f"{v:.6g}") if isinstance(v, float) else v) for k, v in comp.items()
             if k in ("precision", "krylov", "ms_per_step", "value", "iterations", "relres", "setup_ms",
-                     "error_vs_fp64_reference")},
-        "unbatched_comparison": unbatched,
-        "reference": {"krylov": "FGMRES" if saddle else "PCG", "precision": "FP64", "tol": 1e-12,
-                      "iterations": ref_iters},
-        "roofline": roofline,
-        "vcycle_bandwidth": vcycle,
+                     "error_vs_fp64_reference", "learned_omega")},
+        "reference": {"krylov": "FGMRES" if wl.get("saddle") else "PCG", "precision": "FP64", "tol": 1e-12,
+                      "iterations": prim_all.get("reference_iterations")},
+        "roofline": prim.get("roofline"),
+        "vcycle_bandwidth": prim.get("vcycle_bandwidth"),
         "cpu_baseline": cpu,
+        "other_workloads": others,
     }
     print(json.dumps(out))
     return 0

@@ -26,7 +26,7 @@ import scipy.sparse as sps  # noqa: E402
 
 import paper_1503_01287_amd as amg  # noqa: E402
 import synth  # noqa: E402
-from oracle import amg as oamg, workloads  # noqa: E402
+from oracle import amg as oamg, krylov, reduced, workloads  # noqa: E402
 
 DEV = torch.device("cuda:0")
 TOL = 1e-8
@@ -105,8 +105,8 @@ def true_relres(mv, b, x):
     return np.linalg.norm(b - mv(x)) / np.linalg.norm(b)
 
 
-def fp64_solution(hs, smoother, krylov, b):
-    ref = amg.AMGSolver(hs, smoother=smoother, krylov=krylov)
+def fp64_solution(hs, smoother, kry, b):
+    ref = amg.AMGSolver(hs, smoother=smoother, krylov=kry)
     x = torch.zeros_like(b)
     r = ref.solve(b, x, tol=1e-12, maxit=1000)
     ref.close()
@@ -168,6 +168,42 @@ def test_elasticity32_reduced_fcg(elast):
     assert rel2(xs, fp64_solution(hs, "GS-1-1", "PCG", b)) < ERR
 
 
+@SLOW
+def test_elasticity32_reduced_cycle_vs_oracle_reading(elast):
+    """The FP32/BF16 cycle launch by launch (no assembled coarse end) against
+    the oracle's reduced-precision reading of the same cycle at full size
+    (the assembled coarse end is compared at small sizes, where the oracle
+    assembles its map in seconds)."""
+    hs, o, h = elast
+    s = amg.AMGSolver(hs, smoother="GS-1-1", krylov="FCG", precision="MIXED", fuse_coarse=False)
+    r = np.random.default_rng(76).standard_normal(hs.dofs)
+    z = torch.zeros(hs.dofs, dtype=torch.float64, device=DEV)
+    s.precondition(dev(r), z)
+    s.close()
+    want = reduced.reduced_preconditioner(h, oamg.Smoother.parse("GS-1-1"), "MIXED")(r).ravel()
+    assert relmax(host(z), want) < 1e-5
+
+
+@SLOW
+def test_elasticity32_solutions_vs_oracle_solution(elast):
+    """The method's target at full size: the timed solve (FP32/BF16 cycle in
+    FP64 FCG to 1e-8) within 1e-7 of the oracle's own FP64 solution (its
+    AMG-PCG to 1e-12), and the GPU's FP64 PCG solution to 1e-12 within 1e-9."""
+    hs, o, h = elast
+    prec = oamg.preconditioner(h, oamg.Smoother.parse("GS-1-1"))
+    ref = krylov.pcg(lambda v: o.A.matvec(v).ravel(), lambda r: prec(r).ravel(), o.b.ravel(), tol=1e-12,
+                     maxit=300)
+    assert ref.converged and ref.relres <= 1.01e-12, ref.relres
+    b = dev(hs.rhs)
+    for precision, kry, tol, bound in (("MIXED", "FCG", TOL, ERR), ("FP64", "PCG", 1e-12, 1e-9)):
+        s = amg.AMGSolver(hs, smoother="GS-1-1", krylov=kry, precision=precision)
+        x = torch.zeros_like(b)
+        res = s.solve(b, x, tol=tol, maxit=300)
+        s.close()
+        assert res.converged, (precision, res)
+        assert rel2(host(x), ref.x) < bound, (precision, rel2(host(x), ref.x))
+
+
 # ---------------------------------------------------------------- mixed elasticity 24^3
 @pytest.fixture(scope="module")
 def mixed():
@@ -209,6 +245,25 @@ def test_mixed24_reduced_fgmres(mixed):
     rhs = np.concatenate([o.f.ravel(), o.g])
     assert true_relres(oracle_mv(o), rhs, xs) <= TOL * 1.01
     assert rel2(xs, fp64_solution(hs, "sGS-1-1", "FGMRES", b)) < ERR
+
+
+@SLOW
+def test_mixed24_solution_vs_oracle_solution(mixed):
+    """The timed solve (FP32/BF16 sGS cycle in FP64 FGMRES to 1e-8) within
+    1e-7 of the oracle's own FP64 solution (its FGMRES with the FP64 sGS
+    cycle to 1e-12)."""
+    hs, o, h = mixed
+    prec = oamg.preconditioner(h, oamg.Smoother.parse("sGS-1-1"))
+    rhs = np.concatenate([o.f.ravel(), o.g])
+    ref = krylov.fgmres(oracle_mv(o), prec, rhs, tol=1e-12, maxit=400, restart=200)
+    assert ref.converged, ref.relres
+    s = amg.AMGSolver(hs, smoother="sGS-1-1", krylov="FGMRES", precision="MIXED")
+    b = dev(hs.rhs)
+    x = torch.zeros_like(b)
+    res = s.solve(b, x, tol=TOL, maxit=1000)
+    s.close()
+    assert res.converged, res
+    assert rel2(host(x), ref.x) < ERR, rel2(host(x), ref.x)
 
 
 # ---------------------------------------------------------------- vector Laplacian 48^3
@@ -313,3 +368,17 @@ def test_stokes_batch_fp32_fgmres(cavities):
         sl = slice(off[i], off[i + 1])
         assert true_relres(harness_mv(s), s.rhs, out["FP32"][sl]) <= TOL * 1.01, i
         assert rel2(centre(out["FP32"][sl], s), centre(out["FP64"][sl], s)) < ERR, i
+    # the smallest and the largest cavity against the oracle's own FP64
+    # solution of that cavity alone (its FGMRES with the BS-1-1 cycle to 1e-12)
+    ns = [n for n, _ in cfg]
+    for i in sorted({ns.index(min(ns)), ns.index(max(ns))}):
+        n, sp = cfg[i]
+        o = workloads.stokes(n, sp)
+        h = oamg.setup(o.A, o.nlin, o.nquad, B=o.B, C=o.C, singular=o.singular)
+        oamg.prepare_bs(h)
+        prec = oamg.preconditioner(h, oamg.Smoother.parse("BS-1-1"))
+        ref = krylov.fgmres(oracle_mv(o), prec, np.concatenate([o.f.ravel(), o.g]), tol=1e-12, maxit=400,
+                            restart=200)
+        assert ref.converged, (i, n, ref.relres)
+        sl = slice(off[i], off[i + 1])
+        assert rel2(centre(out["FP32"][sl], systems[i]), centre(ref.x, systems[i])) < ERR, (i, n)
