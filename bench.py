@@ -444,11 +444,14 @@ def best_global_omega(name: str, sysm, rhs, tol: float, grid=None) -> dict:
     compared with beside the paper's fixed 0.5."""
     import torch
     import paper_1503_01287_amd as amg
-    grid = grid or [round(0.30 + 0.05 * i, 2) for i in range(19)]
     dev = torch.device("cuda:0")
     b = torch.from_numpy(rhs[0]).to(dev)
     x = torch.zeros_like(b)
     s = amg.AMGSolver(sysm, smoother="JA-1-1-0.5", krylov="FCG", precision="MIXED")
+    # up to the smallest level bound 0.95 * 2 / lambda_max(D^-1 A_l): beyond
+    # it the cycle need not be positive definite
+    top = min(s.level_info(l).omega_max for l in range(s.num_levels - 1))
+    grid = grid or [round(0.30 + 0.05 * i, 2) for i in range(40) if 0.30 + 0.05 * i <= top + 1e-9]
     rows = []
     for w in grid:
         s.set_level_omega([w])

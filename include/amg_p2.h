@@ -163,7 +163,15 @@ typedef struct {
                              network's prediction from that level's row
                              features (amg_level_features); a prediction
                              that is not finite or not inside (0.2, 1.2)
-                             falls back to omega / level_omega. Only read
+                             falls back to omega / level_omega, and a
+                             learned weight above the level's bound
+                             0.95 * 2 / lambda_max(D^{-1} A_l) is lowered to
+                             it (amg_level_info.omega_max). The FP64
+                             residual judges the weights: an amg_solve that
+                             breaks down, diverges or misses the tolerance
+                             is repeated from its initial guess with the
+                             fixed weights, which then stay (iterations and
+                             time of both attempts are reported). Only read
                              during amg_setup.                               */
     int32_t graph;        /* 1 (default): each preconditioner application is
                              recorded once into a HIP graph and replayed
@@ -231,6 +239,20 @@ typedef struct {
                                       BF16 in the FP32/BF16 cycle, each entry
                                       rounded to nearest even, and as FP32 in
                                       the FP32 cycle); 0 elsewhere          */
+    int32_t learned;               /* 1 while the JA weights are the damping
+                                      network's (0 after a fallback or
+                                      amg_set_level_omega)                   */
+    double omega_max;              /* JA smoother (SPD): the bound learned
+                                      weights are kept under,
+                                      0.95 * 2 / lambda_max(D^{-1} A_l) with
+                                      lambda_max estimated by 100 power
+                                      iterations (a symmetric V-cycle with
+                                      damped block Jacobi is positive
+                                      definite only for omega below
+                                      2 / lambda_max); fixed weights are not
+                                      changed; 0 for other smoothers          */
+    int32_t omega_fallbacks;       /* solves repeated with the fixed weights
+                                      because the learned ones failed        */
 } amg_level_info;
 
 /* Fill *p with the defaults listed above. */

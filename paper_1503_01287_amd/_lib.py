@@ -70,7 +70,8 @@ class AmgLevelInfo(ctypes.Structure):
         ("gs_xcd", ctypes.c_int32), ("pair_A", ctypes.c_int32), ("pair_gs", ctypes.c_int32),
         ("lanes64_A", ctypes.c_int32), ("pair64_A", ctypes.c_int32),
         ("kept_A", ctypes.c_int64), ("kept_B", ctypes.c_int64),
-        ("coarse_map", ctypes.c_int32),
+        ("coarse_map", ctypes.c_int32), ("learned", ctypes.c_int32), ("omega_max", ctypes.c_double),
+        ("omega_fallbacks", ctypes.c_int32),
     ]
 
 

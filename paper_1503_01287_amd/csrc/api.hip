@@ -194,15 +194,43 @@ int amg_solve(amg_handle h, const double *b, double *x, double tol, int32_t maxi
         AMG_REQUIRE(h->nsys == 0, AMG_EINVAL, "amg_solve: batch handle (use amg_solve_batched)");
         AMG_REQUIRE(tol > 0.0 && maxit >= 0, AMG_EINVAL, "amg_solve: tol must be > 0, maxit >= 0");
         h->stream = static_cast<hipStream_t>(stream);
-        switch (h->prm.krylov) {
-            case AMG_KRYLOV_PCG: return solve_pcg(h, b, x, tol, maxit, res);
-            case AMG_KRYLOV_FCG: return solve_fcg(h, b, x, tol, maxit, res);
-            case AMG_KRYLOV_NONE:
-                return h->saddle ? solve_stationary_saddle(h, b, x, tol, maxit, res)
-                                 : solve_stationary(h, b, x, tol, maxit, res);
-            case AMG_KRYLOV_FGMRES: return solve_fgmres(h, b, x, tol, maxit, res);
-            default: throw Error(AMG_EINVAL, "amg_solve: unknown Krylov method");
+        auto run = [&](amg_result *r) -> int {
+            switch (h->prm.krylov) {
+                case AMG_KRYLOV_PCG: return solve_pcg(h, b, x, tol, maxit, r);
+                case AMG_KRYLOV_FCG: return solve_fcg(h, b, x, tol, maxit, r);
+                case AMG_KRYLOV_NONE:
+                    return h->saddle ? solve_stationary_saddle(h, b, x, tol, maxit, r)
+                                     : solve_stationary(h, b, x, tol, maxit, r);
+                case AMG_KRYLOV_FGMRES: return solve_fgmres(h, b, x, tol, maxit, r);
+                default: throw Error(AMG_EINVAL, "amg_solve: unknown Krylov method");
+            }
+        };
+        if (!h->learned) return run(res);
+        // learned damping: the FP64 residual judges the weights; a solve that
+        // breaks down, diverges or misses the tolerance is repeated from the
+        // same initial guess with the caller's fixed weights, which stay
+        amg_result first{};
+        if (h->x0_save.n != static_cast<size_t>(h->n_dof)) h->x0_save.alloc(h->n_dof);
+        launch_copy(h->x0_save.p, x, h->n_dof, h->stream);
+        const int st = run(&first);
+        if (st == AMG_OK) {
+            if (res) *res = first;
+            return st;
         }
+        h->level_omega = h->fixed_omega;
+        h->learned = false;
+        h->omega_fallbacks += 1;
+        for (auto &g : h->graphs) (void)hipGraphExecDestroy(g.exec);
+        h->graphs.clear();
+        setup_tail(h);
+        refresh_tail_f32(h);
+        launch_copy(x, h->x0_save.p, h->n_dof, h->stream);
+        amg_result second{};
+        const int st2 = run(&second);
+        second.iters += first.iters;
+        second.solve_ms += first.solve_ms;
+        if (res) *res = second;
+        return st2;
     });
 }
 
@@ -297,6 +325,9 @@ int amg_get_level_info(amg_handle h, int32_t level, amg_level_info *info) {
         info->gs_xcd = h->mixed ? L.mp.xcd : L.gs_xcd;
         info->nnz_S = L.schur.lv.empty() ? 0 : L.schur.lv[0].S.nnz;
         info->coarse_map = (level == h->dense_start) || (level == h->saddle_tail_from) ? 1 : 0;
+        info->learned = h->learned ? 1 : 0;
+        info->omega_max = level < static_cast<int>(h->omega_cap.size()) ? h->omega_cap[level] : 0.0;
+        info->omega_fallbacks = h->omega_fallbacks;
         return AMG_OK;
     });
 }
@@ -412,6 +443,7 @@ static void mlp_upload(amg_mlp *m, const float *X, const float *y, int n) {
     AMG_HIP(hipMemcpyAsync(m->w.X.p, X, static_cast<size_t>(n) * MLP_NF * sizeof(float), hipMemcpyHostToDevice,
                            m->stream));
     if (y) AMG_HIP(hipMemcpyAsync(m->w.y.p, y, static_cast<size_t>(n) * sizeof(float), hipMemcpyHostToDevice, m->stream));
+    AMG_HIP(hipStreamSynchronize(m->stream));  // the caller may free X and y on return
 }
 
 int amg_mlp_forward(amg_mlp_handle m, const float *X, int32_t n, float *omega) {
@@ -510,6 +542,7 @@ int amg_set_level_omega(amg_handle h, int32_t n, const double *omega) {
         for (int i = 0; i < n; ++i)
             AMG_REQUIRE(std::isfinite(omega[i]), AMG_EINVAL, "amg_set_level_omega: weight not finite");
         h->level_omega.assign(omega, omega + n);
+        h->learned = false;  // the caller's weights from now on
         // recorded preconditioners hold the old weights
         for (auto &g : h->graphs) (void)hipGraphExecDestroy(g.exec);
         h->graphs.clear();

@@ -64,9 +64,15 @@ struct DevBuf {
         p = nullptr;
         n = 0;
     }
+    // Host to device, complete on return: the source is often a temporary
+    // the caller frees right away, and an asynchronous copy from pageable
+    // memory may read its source after the call has returned.
     void upload(const T *h, size_t count, hipStream_t s) {
         if (count != n) alloc(count);
-        if (count) AMG_HIP(hipMemcpyAsync(p, h, count * sizeof(T), hipMemcpyHostToDevice, s));
+        if (count) {
+            AMG_HIP(hipMemcpyAsync(p, h, count * sizeof(T), hipMemcpyHostToDevice, s));
+            AMG_HIP(hipStreamSynchronize(s));
+        }
     }
     void upload(const std::vector<T> &v, hipStream_t s) { upload(v.data(), v.size(), s); }
     std::vector<T> download(hipStream_t s) const {

@@ -213,6 +213,15 @@ struct amg_ctx_impl;
 struct amg_ctx {
     amg_params prm{};
     std::vector<double> level_omega;
+    // learned damping: the network's weights are in use (set at setup); the
+    // caller's fixed weights they replaced (fallback), and each level's
+    // bound OMEGA_CAP_FACTOR * 2 / lambda_max(D^{-1} A_l) (JA hierarchies)
+    // the learned weights are kept under
+    bool learned = false;
+    std::vector<double> fixed_omega;
+    std::vector<double> omega_cap;
+    int omega_fallbacks = 0;       // solves that fell back to the fixed weights
+    amgp2::DevBuf<double> x0_save; // initial guess of a learned-weight solve
     hipStream_t stream = nullptr;
     std::vector<amgp2::Level> lv;
     // coarsest level: explicit dense inverse
@@ -303,6 +312,15 @@ void setup_saddle_tail(amg_ctx *h);
 VankaView vanka_view(Level &L);
 // JA damping per level from the network of prm.omega_model (fallback: prm.omega)
 void predict_level_omega(amg_ctx *h);
+// every JA level's bound OMEGA_CAP_FACTOR * 2 / lambda_max(D^{-1} A_l), and
+// learned weights lowered to it: a symmetric V-cycle with damped block Jacobi
+// is positive definite only for weights below 2 / lambda_max; the estimate
+// (a Rayleigh quotient after 100 power iterations) approaches lambda_max from
+// below, hence the margin
+constexpr double OMEGA_CAP_FACTOR = 0.95;
+void cap_learned_omega(amg_ctx *h);
+// estimate of lambda_max(D^{-1} A_l) by power iteration (FP64, on the device)
+double lambda_max_dinv_a(amg_ctx *h, Level &L);
 double jacobi_omega(const amg_ctx *h, int l);
 // (re)build the fused coarse end of the SPD V-cycle from the current weights
 void setup_tail(amg_ctx *h);

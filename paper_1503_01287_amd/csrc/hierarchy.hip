@@ -468,6 +468,7 @@ static void setup_coarsest(amg_ctx *h, Level &L) {
             L.dseg.add(m, 0, nu, 0);
             L.dseg.finalize(s);
             AMG_HIP(hipMemcpyAsync(L.dseg.inv.p, M.data(), M.size() * sizeof(double), hipMemcpyHostToDevice, s));
+            AMG_HIP(hipStreamSynchronize(s));  // M is a local
         }
     } else {
         const int m = L.n;
@@ -895,12 +896,66 @@ void predict_level_omega(amg_ctx *h) {
     AMG_HIP(hipMemcpyAsync(om.data(), m->w.om.p, L * sizeof(float), hipMemcpyDeviceToHost, s));
     AMG_HIP(hipStreamSynchronize(s));
     std::vector<double> w(L + 1);
+    bool used = false;
     for (int l = 0; l < L; ++l) {
         const double o = om[l];
-        w[l] = (std::isfinite(o) && o > MLP_OMEGA_MIN && o < MLP_OMEGA_MIN + MLP_OMEGA_SPAN) ? o : jacobi_omega(h, l);
+        const bool ok = std::isfinite(o) && o > MLP_OMEGA_MIN && o < MLP_OMEGA_MIN + MLP_OMEGA_SPAN;
+        w[l] = ok ? o : jacobi_omega(h, l);
+        used = used || ok;
     }
     w[L] = w[L - 1];
+    h->fixed_omega = h->level_omega;
     h->level_omega = std::move(w);
+    h->learned = used;
+}
+
+// Power iteration on D^{-1} A_l from a fixed pseudo-random start: the
+// Rayleigh quotient (A v, D^{-1} A v) / (v, A v) of the generalised problem
+// A v = lambda D v (a lower bound of lambda_max that converges to it).
+double lambda_max_dinv_a(amg_ctx *h, Level &L) {
+    hipStream_t s = h->stream;
+    const int64_t nv = 3 * static_cast<int64_t>(L.n);
+    DevBuf<double> v(nv), y(nv), w(nv), partial(static_cast<size_t>(dot_blocks(nv))), sc(4);
+    launch_fill_hash(v.p, nv, 0x5eed, s);
+    auto dot = [&](const double *a, const double *b) {
+        const int nb = launch_dot_partial(a, b, nv, partial.p, s);
+        launch_reduce(partial.p, nb, sc.p, 0, s);
+        double r = 0.0;
+        AMG_HIP(hipMemcpyAsync(&r, sc.p, sizeof(double), hipMemcpyDeviceToHost, s));
+        AMG_HIP(hipStreamSynchronize(s));
+        return r;
+    };
+    RowArgs a;
+    a.nrows = L.n;
+    a.rowptr = L.A.rowptr.p;
+    a.col = L.A.col.p;
+    a.val = L.A.val.p;
+    a.nnz = L.A.nnz;
+    double lam = 0.0;
+    for (int it = 0; it < 100; ++it) {
+        a.x = v.p;
+        a.y = y.p;
+        launch_row(L.mode, OP_SPMV, L.G, a, s);                 // y = A v
+        launch_jacobi_zero(L.mode, L.n, L.dinv.p, y.p, 1.0, w.p, s);  // w = D^{-1} A v
+        const double vav = dot(v.p, y.p), ydy = dot(y.p, w.p), ww = dot(w.p, w.p);
+        if (!(vav > 0.0) || !(ww > 0.0)) break;
+        lam = ydy / vav;
+        launch_axpby(v.p, w.p, 1.0 / std::sqrt(ww), 0.0, nv, s);   // v = w / |w|
+    }
+    return lam;
+}
+
+void cap_learned_omega(amg_ctx *h) {
+    const int L = static_cast<int>(h->lv.size()) - 1;
+    h->omega_cap.assign(L + 1, 0.0);
+    for (int l = 0; l < L; ++l) {
+        const double lam = lambda_max_dinv_a(h, h->lv[l]);
+        h->omega_cap[l] = lam > 0.0 ? OMEGA_CAP_FACTOR * 2.0 / lam : 0.0;
+    }
+    if (!h->learned) return;
+    for (int l = 0; l < L; ++l)
+        if (h->omega_cap[l] > 0.0 && h->level_omega[l] > h->omega_cap[l]) h->level_omega[l] = h->omega_cap[l];
+    h->level_omega[L] = h->level_omega[L - 1];
 }
 
 void build_hierarchy(amg_ctx *h, const amg_system *sys) {
@@ -1016,6 +1071,7 @@ void build_hierarchy(amg_ctx *h, const amg_system *sys) {
         }
     }
     setup_coarsest(h, h->lv.back());
+    if (!h->saddle && p.smoother == AMG_SMOOTH_JA) cap_learned_omega(h);
     if (h->saddle && p.smoother == AMG_SMOOTH_BS)
         for (int l = 0; l + 1 < static_cast<int>(h->lv.size()); ++l) {
             setup_schur(h, l);

@@ -213,10 +213,31 @@ __global__ void k_fill(double *x, double v, int64_t n) {
         x[i] = v;
 }
 
+// x_i = a value in [-1, 1) from a hash of (i, seed): a fixed start vector
+// with components along every eigenvector (power iterations)
+__global__ void k_fill_hash(double *x, int64_t n, uint32_t seed) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * BLOCK + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * BLOCK) {
+        uint32_t h = static_cast<uint32_t>(i) * 0x9e3779b1u ^ seed;
+        h ^= h >> 16;
+        h *= 0x85ebca6bu;
+        h ^= h >> 13;
+        h *= 0xc2b2ae35u;
+        h ^= h >> 16;
+        x[i] = static_cast<double>(h) * (2.0 / 4294967296.0) - 1.0;
+    }
+}
+
 static int grid_for(int64_t n) {
     int64_t nb = (n + BLOCK - 1) / BLOCK;
     if (nb > 4096) nb = 4096;
     return static_cast<int>(nb < 1 ? 1 : nb);
+}
+
+void launch_fill_hash(double *x, int64_t n, uint32_t seed, hipStream_t s) {
+    if (n <= 0) return;
+    k_fill_hash<<<grid_for(n), BLOCK, 0, s>>>(x, n, seed);
+    AMG_CHECK_LAUNCH();
 }
 
 void launch_fill(double *x, double v, int64_t n, hipStream_t s) {

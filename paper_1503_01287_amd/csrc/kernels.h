@@ -60,6 +60,7 @@ __device__ __forceinline__ int64_t xcd_chunk_block() {
 
 // ---------------------------------------------------------------- vectors
 void launch_fill(double *x, double v, int64_t n, hipStream_t s);
+void launch_fill_hash(double *x, int64_t n, uint32_t seed, hipStream_t s);
 void launch_copy(double *dst, const double *src, int64_t n, hipStream_t s);
 // x_i = D_i^{-1} b_i for the nodes rowid[0..nrows) (first colour of a
 // Gauss-Seidel sweep from x = 0); dinv planes of stride n

@@ -7,9 +7,12 @@ n in [16, 32], trigonometric Dirichlet data) and each non-coarsest level l,
 the damping of level l is swept over a grid with the other levels at their
 current best, and the mean convergence factor of JA-1-1 V-cycle PCG (the
 geometric mean residual reduction per iteration to 1e-8) is recorded. The
-target for level l is the minimiser of a parabola through the best grid
-point and its neighbours. The network then regresses target weights on the
-level's row features.
+grid runs from 0.3 to 1.8 and stops at the level's bound
+0.95 * 2 / lambda_max(D^{-1} A_l) (amg_level_info.omega_max), above which
+the symmetric cycle need not be positive definite. The target for level l
+is the minimiser of a parabola through the best grid point and its
+neighbours, kept under the bound. The network then regresses target
+weights on the level's row features.
 """
 from __future__ import annotations
 
@@ -90,7 +93,7 @@ class DampingModel:
 
 
 # ---------------------------------------------------------------- training data
-OMEGA_GRID = np.round(np.arange(0.3, 1.151, 0.05), 4)
+OMEGA_GRID = np.round(np.arange(0.3, 1.801, 0.05), 4)
 
 
 def _rate(res) -> float:
@@ -108,7 +111,8 @@ def sweep_targets(system, rhs_list, omega_grid=OMEGA_GRID, rounds: int = 2, log=
     s = AMGSolver(system, smoother="JA-1-1-0.5", krylov="PCG")
     L = s.num_levels - 1
     feats = np.array([s.level_features(l) for l in range(L)])
-    omega = np.full(L + 1, 0.5)
+    caps = np.array([s.level_info(l).omega_max for l in range(L)])
+    omega = np.minimum(np.full(L + 1, 0.5), np.append(caps, caps[-1]))
     solves = 0
 
     def score(om):
@@ -124,8 +128,9 @@ def sweep_targets(system, rhs_list, omega_grid=OMEGA_GRID, rounds: int = 2, log=
 
     for _ in range(rounds):
         for l in range(L):
+            grid = np.array([w for w in omega_grid if w <= caps[l]] or [caps[l]])
             vals = []
-            for w in omega_grid:
+            for w in grid:
                 om = omega.copy()
                 om[l] = w
                 if l == L - 1:
@@ -133,13 +138,14 @@ def sweep_targets(system, rhs_list, omega_grid=OMEGA_GRID, rounds: int = 2, log=
                 vals.append(score(om))
             vals = np.array(vals)
             k = int(np.argmin(vals))
-            best = float(omega_grid[k])
-            if 0 < k < len(omega_grid) - 1:
+            best = float(grid[k])
+            if 0 < k < len(grid) - 1:
                 y0, y1, y2 = vals[k - 1], vals[k], vals[k + 1]
                 den = y0 - 2 * y1 + y2
                 if den > 0:
-                    h = omega_grid[1] - omega_grid[0]
-                    best = float(omega_grid[k] + 0.5 * h * (y0 - y2) / den)
+                    h = grid[1] - grid[0]
+                    best = float(grid[k] + 0.5 * h * (y0 - y2) / den)
+            best = min(best, float(caps[l]))
             omega[l] = best
             if l == L - 1:
                 omega[L] = best
