@@ -181,6 +181,27 @@ CYCLE_OPS = ("gs", "resid", "jacobi", "jacobi0", "restrict", "prolong", "vanka",
 SINGLE_CLASSES = ("coarse", "dense_tail", "saddle_tail", "tail")
 
 
+SETUP_PHASES = ("upload", "coarsen", "galerkin", "omega_network", "drop_zeros", "smoother", "autotune", "coarsest",
+                "omega_bound", "schur", "schur_map", "vanka", "coarse_map", "reduced_copies", "saddle_map", "merge")
+
+
+def setup_breakdown(solver) -> dict:
+    """Wall ms per setup phase (the library records them at every setup) and
+    the Galerkin numeric kernels' rate."""
+    out = {}
+    for ph in SETUP_PHASES:
+        r = solver.profile_read("setup." + ph)
+        if r["launches"]:
+            out[ph] = round(r["ms"], 1)
+    g = solver.profile_read("setup.spgemm_numeric")
+    if g["launches"]:
+        gbps = g["bytes"] / max(g["ms"] * 1e-3, 1e-12) / 1e9
+        out["spgemm_numeric"] = {"launches": g["launches"], "ms": round(g["ms"], 2),
+                                 "algorithmic_bytes": int(g["bytes"]), "GBps": round(gbps, 1),
+                                 "frac": round(gbps / HBM_PEAK_GBS, 4)}
+    return out
+
+
 def _profile_classes(nlevels: int) -> list:
     return [f"{op}.L{l}" for l in range(nlevels) for op in CYCLE_OPS] + list(SINGLE_CLASSES) + ["blas"]
 
@@ -300,7 +321,8 @@ def measure(name: str, sysm, rhs, steps: int, warmup: int, tol: float, precision
         torch.cuda.synchronize()
         setup_ms = (time.perf_counter() - t0) * 1e3
         levels = levels_of(solver)
-        print(f"# {name} {v['label']}: setup {setup_ms:.0f} ms", file=sys.stderr, flush=True)
+        phases = setup_breakdown(solver)
+        print(f"# {name} {v['label']}: setup {setup_ms:.0f} ms {phases}", file=sys.stderr, flush=True)
         for k in range(warmup):
             solve_once(solver, tol, k)
         torch.cuda.synchronize()
@@ -312,6 +334,7 @@ def measure(name: str, sysm, rhs, steps: int, warmup: int, tol: float, precision
             raise SystemExit(f"# {name} {v['label']}: solve did not converge: {results}")
         ms = elapsed * 1e3 / steps
         out = dict(label=v["label"], precision=v["precision"], krylov=v["krylov"], setup_ms=round(setup_ms, 1),
+                   setup_phases_ms=phases,
                    ms_per_step=round(ms, 3), value=sysm.dofs * steps / elapsed, iterations=results[-1][1],
                    relres=results[-1][2], levels=levels, solution=x.clone(),
                    learned_omega=bool(v.get("model") and model is not None))
@@ -570,7 +593,8 @@ def main() -> int:
                    "learned_omega": prim["learned_omega"],
                    "tol": args.tol, "iterations": iters, "relres": prim["relres"],
                    "error_vs_fp64_reference": prim.get("error_vs_fp64_reference"),
-                   "setup_ms": prim["setup_ms"], "levels": prim["levels"], "parallelism": "single GPU",
+                   "setup_ms": prim["setup_ms"], "setup_phases_ms": prim["setup_phases_ms"],
+                   "levels": prim["levels"], "parallelism": "single GPU",
                    "rhs_data_sets": prim_all["rhs_data_sets"]},
         "fp64_comparison": None if comp is None else {
             k: (float(f"{v:.6g}") if isinstance(v, float) else v) for k, v in comp.items()

@@ -411,7 +411,17 @@ int amg_profile_enable(amg_handle h, int32_t enable);
 /* Kernel classes "<op>.L<level>" with op one of spmv, gs, jacobi, jacobi0,
  * resid, restrict, prolong; plus "coarse" and "blas". Returns launches,
  * total ms and algorithmic bytes (bytes the operation must move at least:
- * every stored entry and index once, every vector once). */
+ * every stored entry and index once, every vector once).
+ * Setup phases are always recorded (never cleared): "setup.<phase>" with
+ * phase one of upload, coarsen (graphs, independent sets, interpolation;
+ * host), galerkin (the Galerkin products), omega_network, drop_zeros,
+ * smoother (diagonal inverses, colouring, colour-grouped copies, saddle
+ * scalings), autotune, coarsest (dense inverse), omega_bound, schur,
+ * schur_map, vanka, coarse_map, reduced_copies, saddle_map, merge (batches;
+ * a batch also sums its systems' own phases): calls and wall ms.
+ * "setup.spgemm_numeric": the Galerkin numeric kernels' HIP-event ms and
+ * algorithmic bytes (both factors and the product's pattern read once, its
+ * values written once). */
 int amg_profile_read(amg_handle h, const char *kernel_class, int64_t *launches, double *total_ms,
                      double *bytes);
 

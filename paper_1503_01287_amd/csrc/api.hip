@@ -384,7 +384,8 @@ int amg_profile_read(amg_handle h, const char *cls, int64_t *launches, double *t
         AMG_REQUIRE(h && cls && launches && total_ms && bytes, AMG_EINVAL, "amg_profile_read: null argument");
         profile_collect(h);
         auto it = h->stats.find(cls);
-        if (it == h->stats.end()) {
+        if (it == h->stats.end()) it = h->setup_stats.find(cls);
+        if (it == h->setup_stats.end()) {
             *launches = 0;
             *total_ms = 0.0;
             *bytes = 0.0;

@@ -116,7 +116,15 @@ void build_batch(amg_ctx *h, int nsys, const amg_system *sys) {
         inst[i]->stream = s;
         build_hierarchy(inst[i].get(), &sys[i]);
         depth[i] = static_cast<int>(inst[i]->lv.size()) - 1;
+        // the systems' own setup phases, summed
+        for (const auto &kv : inst[i]->setup_stats) {
+            ProfStat &st = h->setup_stats[kv.first];
+            st.launches += kv.second.launches;
+            st.ms += kv.second.ms;
+            st.bytes += kv.second.bytes;
+        }
     }
+    auto ph_merge = std::make_unique<SetupPhase>(h, "merge");
     std::vector<int> order(nsys);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return depth[a] > depth[b]; });
@@ -311,10 +319,13 @@ void build_batch(amg_ctx *h, int nsys, const amg_system *sys) {
         M.t.alloc(nv);
     }
     AMG_HIP(hipStreamSynchronize(s));
+    ph_merge.reset();
     // the merged levels' kernels see other shapes than the systems' own
-    if (p.autotune)
+    if (p.autotune) {
+        SetupPhase ph(h, "autotune");
         for (Level &M : merged)
             if (M.nA > 0) autotune_level(h, M);
+    }
 
     // level-0 layout of every system, chunk tables
     h->nsys = nsys;
@@ -372,14 +383,20 @@ void build_batch(amg_ctx *h, int nsys, const amg_system *sys) {
     h->lv = std::move(merged);
     h->saddle = true;
     h->pinned = -1;
-    if (bs)
+    if (bs) {
+        SetupPhase ph(h, "schur_map");
         for (int l = 0; l + 1 < static_cast<int>(h->lv.size()); ++l)
             if (!h->lv[l].schur.lv.empty()) setup_schur_dense(h, l);
+    }
     if (p.precision != AMG_PREC_FP64) {
+        SetupPhase ph(h, "reduced_copies");
         build_mixed(h);
         build_saddle_mp(h);
     }
-    setup_saddle_tail(h);
+    {
+        SetupPhase ph(h, "saddle_map");
+        setup_saddle_tail(h);
+    }
     h->n_dof = static_cast<int>(h->lv[0].vlen());
     const size_t nd = static_cast<size_t>(h->n_dof);
     h->b_b.alloc(nd);

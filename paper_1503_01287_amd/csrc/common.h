@@ -39,6 +39,11 @@ void set_last_error(const std::string &msg);
         if (!(cond)) throw ::amgp2::Error(code, msg); \
     } while (0)
 
+// Host to device copy, complete on return. Large copies go through two
+// pinned staging halves, the host copy of one chunk overlapping the DMA of
+// the previous one; small ones copy from the source directly.
+void copy_h2d(void *dst, const void *src, size_t bytes, hipStream_t s);
+
 // Owning device allocation.
 template <typename T>
 struct DevBuf {
@@ -69,10 +74,7 @@ struct DevBuf {
     // memory may read its source after the call has returned.
     void upload(const T *h, size_t count, hipStream_t s) {
         if (count != n) alloc(count);
-        if (count) {
-            AMG_HIP(hipMemcpyAsync(p, h, count * sizeof(T), hipMemcpyHostToDevice, s));
-            AMG_HIP(hipStreamSynchronize(s));
-        }
+        if (count) copy_h2d(p, h, count * sizeof(T), s);
     }
     void upload(const std::vector<T> &v, hipStream_t s) { upload(v.data(), v.size(), s); }
     std::vector<T> download(hipStream_t s) const {

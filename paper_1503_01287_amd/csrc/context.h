@@ -1,6 +1,7 @@
 // The hierarchy held by an amg_handle and the routines that build and run it.
 #pragma once
 
+#include <chrono>
 #include <map>
 #include <string>
 #include <vector>
@@ -294,6 +295,10 @@ struct amg_ctx {
     std::vector<Pending> pending;
     std::vector<hipEvent_t> event_pool;
     std::map<std::string, amgp2::ProfStat> stats;
+    // setup phases (always recorded, never cleared): "setup.<phase>" with
+    // host wall time per phase; the Galerkin numeric kernels also with their
+    // HIP-event time and algorithmic bytes ("setup.spgemm_numeric")
+    std::map<std::string, amgp2::ProfStat> setup_stats;
     ~amg_ctx();
 };
 
@@ -356,6 +361,21 @@ int solve_pcg(amg_ctx *h, const double *b, double *x, double tol, int maxit, amg
 int solve_fcg(amg_ctx *h, const double *b, double *x, double tol, int maxit, amg_result *res);
 int solve_stationary(amg_ctx *h, const double *b, double *x, double tol, int maxit, amg_result *res);
 double true_relres(amg_ctx *h, const double *b, const double *x, double r0norm);
+
+// Wall time of a setup phase (the stream synchronised at the end) added to
+// h->setup_stats["setup." + name].
+struct SetupPhase {
+    amg_ctx *h;
+    std::string name;
+    std::chrono::steady_clock::time_point t0;
+    SetupPhase(amg_ctx *hh, const char *n) : h(hh), name(std::string("setup.") + n), t0(std::chrono::steady_clock::now()) {}
+    ~SetupPhase() {
+        (void)hipStreamSynchronize(h->stream);
+        ProfStat &st = h->setup_stats[name];
+        st.launches += 1;
+        st.ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+};
 
 // profiling helpers (no-ops unless enabled)
 struct ProfScope {

@@ -8,6 +8,8 @@
 #include <numeric>
 #include <tuple>
 
+#include <memory>
+
 #include "context.h"
 #include "saddle.h"
 
@@ -60,11 +62,12 @@ static void upload_blocks(DMat &m, int nrows, int ncols, const int32_t *rowptr, 
     m.np = np;
     m.rowptr.upload(rowptr, nrows + 1, s);
     m.col.upload(col, static_cast<size_t>(m.nnz), s);
-    std::vector<double> planes(static_cast<size_t>(np) * m.nnz);
-    for (int64_t k = 0; k < m.nnz; ++k)
-        for (int p = 0; p < np; ++p) planes[static_cast<size_t>(p) * m.nnz + k] = val[k * np + p];
-    m.val.upload(planes, s);
-    AMG_HIP(hipStreamSynchronize(s));  // `planes` goes out of scope
+    // the caller's blocks as they are, then into planes on the device
+    DevBuf<double> aos;
+    aos.upload(val, static_cast<size_t>(np) * m.nnz, s);
+    m.val.alloc(std::max<size_t>(1, static_cast<size_t>(np) * m.nnz));
+    launch_aos_to_planes(aos.p, np, m.nnz, m.val.p, s);
+    AMG_HIP(hipStreamSynchronize(s));
 }
 
 // B^T of a host 1x3-block matrix (nrows x ncols) as 3x1 blocks (3 planes).
@@ -104,7 +107,8 @@ static HostCSR download_pattern(const DMat &m, hipStream_t s) {
 // C = X Y, one of X / Y scalar (np = 1), the other with np planes.
 // search_y: Y's rows are long (binary search in them); otherwise Y is a
 // prolongation with a few entries per row (linear scan).
-static DMat spgemm(const DMat &X, const DMat &Y, bool search_y, hipStream_t s) {
+static DMat spgemm(amg_ctx *h, const DMat &X, const DMat &Y, bool search_y) {
+    hipStream_t s = h->stream;
     AMG_REQUIRE(X.ncols == Y.nrows, AMG_EINVAL, "spgemm: shape mismatch");
     AMG_REQUIRE(X.np == 1 || Y.np == 1, AMG_EINVAL, "spgemm: one factor must be scalar");
     DMat C;
@@ -126,13 +130,37 @@ static DMat spgemm(const DMat &X, const DMat &Y, bool search_y, hipStream_t s) {
     launch_spgemm_fill(C.nrows, X.rowptr.p, X.col.p, Y.rowptr.p, Y.col.p, C.rowptr.p, C.col.p, s);
     C.val.alloc(std::max<int64_t>(1, C.nnz * C.np));
     AMG_REQUIRE(search_y ? X.np == 1 : Y.np == 1, AMG_EINVAL, "spgemm: factor layout");
-    if (!search_y)
-        launch_spgemm_numeric_bx(X.np, C.nrows, X.rowptr.p, X.col.p, X.val.p, X.nnz, Y.rowptr.p, Y.col.p,
-                                 Y.val.p, C.rowptr.p, C.col.p, C.val.p, C.nnz, s);
-    else
-        launch_spgemm_numeric_by(Y.np, C.nrows, X.rowptr.p, X.col.p, X.val.p, Y.rowptr.p, Y.col.p,
-                                 Y.val.p, Y.nnz, C.rowptr.p, C.col.p, C.val.p, C.nnz, s);
-    AMG_HIP(hipStreamSynchronize(s));
+    hipEvent_t e0, e1;
+    AMG_HIP(hipEventCreate(&e0));
+    AMG_HIP(hipEventCreate(&e1));
+    flag.zero(s);
+    AMG_HIP(hipEventRecord(e0, s));
+    launch_spgemm_numeric_lds(search_y, C.np, C.nrows, X.rowptr.p, X.col.p, X.val.p, X.nnz, Y.rowptr.p, Y.col.p,
+                              Y.val.p, Y.nnz, C.rowptr.p, C.col.p, C.val.p, C.nnz, flag.p, s);
+    AMG_HIP(hipEventRecord(e1, s));
+    AMG_HIP(hipEventSynchronize(e1));
+    if (flag.download(s)[0] != 0) {
+        // a factor row beyond the LDS staging: the unstaged kernels (same sums)
+        if (!search_y)
+            launch_spgemm_numeric_bx(X.np, C.nrows, X.rowptr.p, X.col.p, X.val.p, X.nnz, Y.rowptr.p, Y.col.p,
+                                     Y.val.p, C.rowptr.p, C.col.p, C.val.p, C.nnz, s);
+        else
+            launch_spgemm_numeric_by(Y.np, C.nrows, X.rowptr.p, X.col.p, X.val.p, Y.rowptr.p, Y.col.p,
+                                     Y.val.p, Y.nnz, C.rowptr.p, C.col.p, C.val.p, C.nnz, s);
+        AMG_HIP(hipEventRecord(e1, s));
+        AMG_HIP(hipEventSynchronize(e1));
+    }
+    float ms = 0.f;
+    AMG_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    // algorithmic bytes: both factors and the product's pattern read once,
+    // the product's values written once
+    ProfStat &st = h->setup_stats["setup.spgemm_numeric"];
+    st.launches += 1;
+    st.ms += ms;
+    st.bytes += static_cast<double>(X.nnz) * (X.np * 8.0 + 4.0) + static_cast<double>(Y.nnz) * (Y.np * 8.0 + 4.0) +
+                static_cast<double>(C.nnz) * (C.np * 8.0 + 4.0) + 4.0 * (X.nrows + Y.nrows + C.nrows);
     return C;
 }
 
@@ -633,9 +661,9 @@ void setup_schur(amg_ctx *h, int l) {
     const int last = static_cast<int>(h->lv.size()) - 1;
     for (int k = l; k < last; ++k) {
         const Level &V = h->lv[k];
-        DMat SH = spgemm(sh.lv.back().S, V.H, false, s);
+        DMat SH = spgemm(h, sh.lv.back().S, V.H, false);
         SchurLevel nx;
-        nx.S = spgemm(V.Ht, SH, true, s);
+        nx.S = spgemm(h, V.Ht, SH, true);
         sh.lv.push_back(std::move(nx));
     }
     for (size_t k = 0; k < sh.lv.size(); ++k) {
@@ -967,6 +995,7 @@ void build_hierarchy(amg_ctx *h, const amg_system *sys) {
     h->lv.clear();
     h->lv.emplace_back();
     {
+        SetupPhase ph(h, "upload");
         Level &L0 = h->lv.back();
         L0.n_lin = sys->n_lin;
         L0.n_quad = sys->n_quad;
@@ -991,6 +1020,7 @@ void build_hierarchy(amg_ctx *h, const amg_system *sys) {
         if (L.vlen() <= p.coarse_max || static_cast<int>(h->lv.size()) >= max_levels) break;
         HostCSR P, Hp;
         int ncl = 0, ncq = 0;
+        auto ph_c = std::make_unique<SetupPhase>(h, "coarsen");
         if (p.separate) {
             HostCSR gl = subgraph(L.hpat, 0, L.n_lin), gq = subgraph(L.hpat, L.n_lin, L.n);
             HostCSR pl = averaging_interpolation(gl, greedy_independent_set(gl));
@@ -1012,8 +1042,10 @@ void build_hierarchy(amg_ctx *h, const amg_system *sys) {
         L.hP = std::move(P);
         L.Gp = lanes_for(L.P.nnz, L.P.nrows);
         L.Gr = lanes_for(L.R.nnz, L.R.nrows);
-        DMat AP = spgemm(L.A, L.P, false, s);
-        DMat Ac = spgemm(L.R, AP, true, s);
+        ph_c.reset();
+        SetupPhase ph_g(h, "galerkin");
+        DMat AP = spgemm(h, L.A, L.P, false);
+        DMat Ac = spgemm(h, L.R, AP, true);
         Level next;
         next.n_lin = ncl;
         next.n_quad = ncq;
@@ -1028,13 +1060,13 @@ void build_hierarchy(amg_ctx *h, const amg_system *sys) {
             upload_scalar(L.Ht, transpose(Hp), s);
             L.Gh = lanes_for(L.H.nnz, L.H.nrows);
             L.Ght = lanes_for(L.Ht.nnz, L.Ht.nrows);
-            DMat BP = spgemm(L.B, L.P, false, s);
-            next.B = spgemm(L.Ht, BP, true, s);
-            DMat BtH = spgemm(L.Bt, L.H, false, s);
-            next.Bt = spgemm(L.R, BtH, true, s);
+            DMat BP = spgemm(h, L.B, L.P, false);
+            next.B = spgemm(h, L.Ht, BP, true);
+            DMat BtH = spgemm(h, L.Bt, L.H, false);
+            next.Bt = spgemm(h, L.R, BtH, true);
             if (L.C.nnz > 0) {
-                DMat CH = spgemm(L.C, L.H, false, s);
-                next.C = spgemm(L.Ht, CH, true, s);
+                DMat CH = spgemm(h, L.C, L.H, false);
+                next.C = spgemm(h, L.Ht, CH, true);
             }
             next.n_pres = ncl;
         }
@@ -1045,17 +1077,23 @@ void build_hierarchy(amg_ctx *h, const amg_system *sys) {
         L.nA = L.coarsest ? 0 : L.n;
         L.npA = L.coarsest ? 0 : L.n_pres;
     }
-    if (p.omega_model && p.smoother == AMG_SMOOTH_JA && !h->saddle) predict_level_omega(h);
+    if (p.omega_model && p.smoother == AMG_SMOOTH_JA && !h->saddle) {
+        SetupPhase ph(h, "omega_network");
+        predict_level_omega(h);
+    }
     // Coarsening, the Galerkin products and the row features above used the
     // structural patterns. From here on every level keeps A without its
     // numerically zero blocks: the smoother setup, the tuners, the
     // reduced-precision copies and the solve-phase kernels stream that
     // (the same operator, fewer bytes); the structural A stays for export.
-    for (Level &L : h->lv) {
-        DMat c;
-        if (drop_zero_entries(L.A, true, c, s)) {
-            L.A_pat = std::move(L.A);
-            L.A = std::move(c);
+    {
+        SetupPhase ph(h, "drop_zeros");
+        for (Level &L : h->lv) {
+            DMat c;
+            if (drop_zero_entries(L.A, true, c, s)) {
+                L.A_pat = std::move(L.A);
+                L.A = std::move(c);
+            }
         }
     }
     for (Level &L : h->lv) {
@@ -1065,20 +1103,41 @@ void build_hierarchy(amg_ctx *h, const amg_system *sys) {
         L.r.alloc(nv);
         L.t.alloc(nv);
         if (!L.coarsest) {
-            setup_smoother(h, L);
-            if (h->saddle) saddle_setup_level(h, L);
-            if (p.autotune) autotune_level(h, L);
+            {
+                SetupPhase ph(h, "smoother");
+                setup_smoother(h, L);
+                if (h->saddle) saddle_setup_level(h, L);
+            }
+            if (p.autotune) {
+                SetupPhase ph(h, "autotune");
+                autotune_level(h, L);
+            }
         }
     }
-    setup_coarsest(h, h->lv.back());
-    if (!h->saddle && p.smoother == AMG_SMOOTH_JA) cap_learned_omega(h);
+    {
+        SetupPhase ph(h, "coarsest");
+        setup_coarsest(h, h->lv.back());
+    }
+    if (!h->saddle && p.smoother == AMG_SMOOTH_JA) {
+        SetupPhase ph(h, "omega_bound");
+        cap_learned_omega(h);
+    }
     if (h->saddle && p.smoother == AMG_SMOOTH_BS)
         for (int l = 0; l + 1 < static_cast<int>(h->lv.size()); ++l) {
-            setup_schur(h, l);
-            if (!h->batch_member) setup_schur_dense(h, l);
+            {
+                SetupPhase ph(h, "schur");
+                setup_schur(h, l);
+            }
+            if (!h->batch_member) {
+                SetupPhase ph(h, "schur_map");
+                setup_schur_dense(h, l);
+            }
         }
     if (h->saddle && p.smoother == AMG_SMOOTH_VANKA)
-        for (int l = 0; l + 1 < static_cast<int>(h->lv.size()); ++l) setup_vanka(h, l);
+        for (int l = 0; l + 1 < static_cast<int>(h->lv.size()); ++l) {
+            SetupPhase ph(h, "vanka");
+            setup_vanka(h, l);
+        }
     // B and B^T likewise, once the Schur complements and the Vanka patches
     // (defined on B's structural pattern) are built
     if (h->saddle)
@@ -1091,13 +1150,21 @@ void build_hierarchy(amg_ctx *h, const amg_system *sys) {
             if (drop_zero_entries(L.Bt, false, c, s)) L.Bt = std::move(c);
         }
     if (!h->saddle) {
-        setup_tail(h);
+        {
+            SetupPhase ph(h, "coarse_map");
+            setup_tail(h);
+        }
+        SetupPhase ph(h, "reduced_copies");
         build_mixed(h);
     } else if (p.precision != AMG_PREC_FP64) {
+        SetupPhase ph(h, "reduced_copies");
         build_mixed(h);
         build_saddle_mp(h);
     }
-    if (h->saddle && !h->batch_member) setup_saddle_tail(h);
+    if (h->saddle && !h->batch_member) {
+        SetupPhase ph(h, "saddle_map");
+        setup_saddle_tail(h);
+    }
     h->n_dof = static_cast<int>(h->lv[0].vlen());
     const size_t nd = static_cast<size_t>(h->n_dof);
     h->kr.alloc(nd);

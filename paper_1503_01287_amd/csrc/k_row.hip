@@ -8,6 +8,9 @@
 // entries t, t+G, ..., so each plane load of the group is one contiguous
 // segment, and the 3 partial sums are reduced across the group with
 // cross-lane shuffles.
+#include <cstring>
+#include <mutex>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -250,6 +253,53 @@ __global__ void k_copy(double *d, const double *src, int64_t n) {
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * BLOCK + threadIdx.x; i < n;
          i += static_cast<int64_t>(gridDim.x) * BLOCK)
         d[i] = src[i];
+}
+
+void copy_h2d(void *dst, const void *src, size_t bytes, hipStream_t s) {
+    constexpr size_t SMALL = 1u << 18, CHUNK = 8u << 20;
+    if (bytes == 0) return;
+    if (bytes <= SMALL) {
+        AMG_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
+        AMG_HIP(hipStreamSynchronize(s));
+        return;
+    }
+    static std::mutex mu;
+    static char *pin[2] = {nullptr, nullptr};
+    static hipEvent_t done[2];
+    std::lock_guard<std::mutex> lock(mu);
+    if (!pin[0])
+        for (int i = 0; i < 2; ++i) {
+            AMG_HIP(hipHostMalloc(reinterpret_cast<void **>(&pin[i]), CHUNK, hipHostMallocPortable));
+            AMG_HIP(hipEventCreateWithFlags(&done[i], hipEventDisableTiming));
+        }
+    const char *from = static_cast<const char *>(src);
+    char *to = static_cast<char *>(dst);
+    int half = 0;
+    for (size_t off = 0; off < bytes; off += CHUNK, half ^= 1) {
+        const size_t nb = std::min(CHUNK, bytes - off);
+        AMG_HIP(hipEventSynchronize(done[half]));  // this half's previous DMA has finished
+        std::memcpy(pin[half], from + off, nb);
+        AMG_HIP(hipMemcpyAsync(to + off, pin[half], nb, hipMemcpyHostToDevice, s));
+        AMG_HIP(hipEventRecord(done[half], s));
+    }
+    AMG_HIP(hipStreamSynchronize(s));
+}
+
+// planes[p * nnz + k] = aos[k * np + p]
+__global__ void k_aos_to_planes(const double *aos, int np, int64_t nnz, double *planes) {
+    const int64_t total = nnz * np;
+    for (int64_t t = static_cast<int64_t>(blockIdx.x) * BLOCK + threadIdx.x; t < total;
+         t += static_cast<int64_t>(gridDim.x) * BLOCK) {
+        const int64_t k = t / np;
+        const int p = static_cast<int>(t - k * np);
+        planes[p * nnz + k] = aos[t];
+    }
+}
+
+void launch_aos_to_planes(const double *aos, int np, int64_t nnz, double *planes, hipStream_t s) {
+    if (nnz <= 0) return;
+    k_aos_to_planes<<<grid_for(nnz * np), BLOCK, 0, s>>>(aos, np, nnz, planes);
+    AMG_CHECK_LAUNCH();
 }
 
 void launch_copy(double *dst, const double *src, int64_t n, hipStream_t s) {

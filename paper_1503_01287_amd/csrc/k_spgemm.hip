@@ -192,6 +192,216 @@ __global__ void __launch_bounds__(SBLOCK) k_spgemm_num_by(int nrows, const int *
     }
 }
 
+// ---------------------------------------------------------------- numeric, LDS-staged
+// The same sums in the same order as the kernels above, with the dependent
+// loads taken out of each lane's inner loop: one wavefront per output row
+// stages a chunk of the row's products in LDS (all lanes load in parallel,
+// an in-wave prefix sum places them), then every lane scans the staged
+// list for the output entries it owns. Each output is still summed over
+// k ascending (and, for X Y with Y scalar, over Y's row in order), so the
+// result is bit-for-bit the one-lane-per-entry kernels'.
+constexpr int NCAP = 1024;  // staged products per wavefront
+constexpr int NT = 4;       // output entries per lane kept in registers (256 per row per pass)
+
+// wavefront inclusive prefix sum
+__device__ __forceinline__ int wave_incl_scan(int v, int lane) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int u = __shfl_up(v, o, 64);
+        if (lane >= o) v += u;
+    }
+    return v;
+}
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// C = X Y, X in planes (np), Y scalar (an interpolation: few entries per row)
+template <int NP>
+__global__ void __launch_bounds__(SBLOCK) k_spgemm_num_bx_lds(int nrows, const int *xr, const int *xc,
+                                                              const double *xv, int64_t xnnz, const int *yr,
+                                                              const int *yc, const double *yv, const int *cr,
+                                                              const int *cc, double *cv, int64_t cnnz,
+                                                              int *overflow) {
+    __shared__ int s_col[WAVES][NCAP];
+    __shared__ int s_k[WAVES][NCAP];
+    __shared__ double s_w[WAVES][NCAP];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int row = blockIdx.x * WAVES + w;
+    if (row >= nrows) return;  // whole wavefronts leave; only wave-level syncs below
+    const int xb = xr[row], xe = xr[row + 1];
+    for (int q0 = cr[row]; q0 < cr[row + 1]; q0 += 64 * NT) {
+        int J[NT];
+        double acc[NT][NP];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int q = q0 + lane + 64 * t;
+            J[t] = q < cr[row + 1] ? cc[q] : -1;
+#pragma unroll
+            for (int p = 0; p < NP; ++p) acc[t][p] = 0.0;
+        }
+        for (int k0 = xb; k0 < xe;) {
+            const int k = k0 + lane;
+            int yb = 0, cnt = 0;
+            if (k < xe) {
+                const int j = xc[k];
+                yb = yr[j];
+                cnt = yr[j + 1] - yb;
+            }
+            const int incl = wave_incl_scan(cnt, lane);
+            // the leading lanes whose products fit (incl grows with the lane)
+            const unsigned long long fit = __ballot(k < xe && incl <= NCAP);
+            const int take = __popcll(fit);
+            if (take == 0) {  // one Y row alone exceeds the staging capacity
+                if (lane == 0) atomicOr(overflow, 1);
+                return;
+            }
+            const int total = __shfl(incl, take - 1, 64);
+            if (lane < take)
+                for (int m = 0, e = incl - cnt; m < cnt; ++m, ++e) {
+                    s_col[w][e] = yc[yb + m];
+                    s_w[w][e] = yv[yb + m];
+                    s_k[w][e] = k;
+                }
+            wave_sync();
+            for (int e = 0; e < total; ++e) {
+                const int col = s_col[w][e];
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+                    if (col == J[t]) {
+                        const double wgt = s_w[w][e];
+                        const int kk = s_k[w][e];
+#pragma unroll
+                        for (int p = 0; p < NP; ++p) acc[t][p] += wgt * xv[p * xnnz + kk];
+                    }
+            }
+            wave_sync();
+            k0 += take;
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int q = q0 + lane + 64 * t;
+            if (q < cr[row + 1])
+#pragma unroll
+                for (int p = 0; p < NP; ++p) cv[p * cnnz + q] = acc[t][p];
+        }
+    }
+}
+
+// C = X Y, X scalar, Y in planes (np) with sorted rows: the column lists of
+// the Y rows a chunk of X's row touches are staged, and each lane finds its
+// output column in them by binary search in LDS
+template <int NP>
+__global__ void __launch_bounds__(SBLOCK) k_spgemm_num_by_lds(int nrows, const int *xr, const int *xc,
+                                                              const double *xv, const int *yr, const int *yc,
+                                                              const double *yv, int64_t ynnz, const int *cr,
+                                                              const int *cc, double *cv, int64_t cnnz,
+                                                              int *overflow) {
+    __shared__ int s_col[WAVES][2 * NCAP];
+    __shared__ int s_beg[WAVES][64], s_cnt[WAVES][64], s_yb[WAVES][64];
+    __shared__ double s_x[WAVES][64];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int row = blockIdx.x * WAVES + w;
+    if (row >= nrows) return;
+    const int xb = xr[row], xe = xr[row + 1];
+    for (int q0 = cr[row]; q0 < cr[row + 1]; q0 += 64 * NT) {
+        int J[NT];
+        double acc[NT][NP];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int q = q0 + lane + 64 * t;
+            J[t] = q < cr[row + 1] ? cc[q] : -1;
+#pragma unroll
+            for (int p = 0; p < NP; ++p) acc[t][p] = 0.0;
+        }
+        for (int k0 = xb; k0 < xe;) {
+            const int k = k0 + lane;
+            int yb = 0, cnt = 0;
+            double xk = 0.0;
+            if (k < xe) {
+                const int i = xc[k];
+                xk = xv[k];
+                yb = yr[i];
+                cnt = yr[i + 1] - yb;
+            }
+            const int incl = wave_incl_scan(cnt, lane);
+            const unsigned long long fit = __ballot(k < xe && incl <= 2 * NCAP);
+            const int take = __popcll(fit);
+            if (take == 0) {
+                if (lane == 0) atomicOr(overflow, 1);
+                return;
+            }
+            if (lane < take) {
+                const int e0 = incl - cnt;
+                s_beg[w][lane] = e0;
+                s_cnt[w][lane] = cnt;
+                s_yb[w][lane] = yb;
+                s_x[w][lane] = xk;
+                for (int m = 0; m < cnt; ++m) s_col[w][e0 + m] = yc[yb + m];
+            }
+            wave_sync();
+            for (int u = 0; u < take; ++u) {
+                const int beg = s_beg[w][u], n = s_cnt[w][u];
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    if (J[t] < 0) continue;
+                    int lo = 0, hi = n - 1;
+                    while (lo <= hi) {
+                        const int mid = (lo + hi) >> 1;
+                        const int c = s_col[w][beg + mid];
+                        if (c == J[t]) {
+                            const double wgt = s_x[w][u];
+                            const int64_t m = s_yb[w][u] + mid;
+#pragma unroll
+                            for (int p = 0; p < NP; ++p) acc[t][p] += wgt * yv[p * ynnz + m];
+                            break;
+                        }
+                        if (c < J[t])
+                            lo = mid + 1;
+                        else
+                            hi = mid - 1;
+                    }
+                }
+            }
+            wave_sync();
+            k0 += take;
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int q = q0 + lane + 64 * t;
+            if (q < cr[row + 1])
+#pragma unroll
+                for (int p = 0; p < NP; ++p) cv[p * cnnz + q] = acc[t][p];
+        }
+    }
+}
+
+bool launch_spgemm_numeric_lds(bool by, int np, int nrows, const int *xr, const int *xc, const double *xv,
+                               int64_t xnnz, const int *yr, const int *yc, const double *yv, int64_t ynnz,
+                               const int *cr, const int *cc, double *cv, int64_t cnnz, int *overflow,
+                               hipStream_t s) {
+    if (nrows <= 0) return true;
+    const int nb = ceil_div(nrows, WAVES);
+#define AMG_NUM(NPV)                                                                                         \
+    if (by)                                                                                                \
+        k_spgemm_num_by_lds<NPV><<<nb, SBLOCK, 0, s>>>(nrows, xr, xc, xv, yr, yc, yv, ynnz, cr, cc, cv, cnnz, \
+                                                      overflow);                                           \
+    else                                                                                                   \
+        k_spgemm_num_bx_lds<NPV><<<nb, SBLOCK, 0, s>>>(nrows, xr, xc, xv, xnnz, yr, yc, yv, cr, cc, cv, cnnz, \
+                                                      overflow);
+    switch (np) {
+        case 1: AMG_NUM(1) break;
+        case 3: AMG_NUM(3) break;
+        case 9: AMG_NUM(9) break;
+        default: throw Error(AMG_EINVAL, "spgemm: unsupported block shape");
+    }
+#undef AMG_NUM
+    AMG_CHECK_LAUNCH();
+    return true;
+}
+
 void launch_spgemm_numeric_bx(int np, int nrows, const int *xr, const int *xc, const double *xv,
                               int64_t xnnz, const int *yr, const int *yc, const double *yv, const int *cr,
                               const int *cc, double *cv, int64_t cnnz, hipStream_t s) {

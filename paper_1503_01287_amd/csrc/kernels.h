@@ -62,6 +62,8 @@ __device__ __forceinline__ int64_t xcd_chunk_block() {
 void launch_fill(double *x, double v, int64_t n, hipStream_t s);
 void launch_fill_hash(double *x, int64_t n, uint32_t seed, hipStream_t s);
 void launch_copy(double *dst, const double *src, int64_t n, hipStream_t s);
+// planes[p * nnz + k] = aos[k * np + p] (blocks stored entry by entry -> planes)
+void launch_aos_to_planes(const double *aos, int np, int64_t nnz, double *planes, hipStream_t s);
 // x_i = D_i^{-1} b_i for the nodes rowid[0..nrows) (first colour of a
 // Gauss-Seidel sweep from x = 0); dinv planes of stride n
 void launch_diag_solve(int mode, int nrows, const int *rowid, const double *dinv, int64_t n, const double *b,
@@ -131,6 +133,13 @@ void launch_spgemm_fill(int nrows, const int *xr, const int *xc, const int *yr, 
 void launch_spgemm_numeric_bx(int np, int nrows, const int *xr, const int *xc, const double *xv,
                               int64_t xnnz, const int *yr, const int *yc, const double *yv,
                               const int *cr, const int *cc, double *cv, int64_t cnnz, hipStream_t s);
+// LDS-staged numeric phase, same sums in the same order (by: X scalar and Y
+// in planes, else X in planes and Y scalar); *overflow (device) is set when
+// a Y row alone exceeds the staging capacity: then run the kernels above
+bool launch_spgemm_numeric_lds(bool by, int np, int nrows, const int *xr, const int *xc, const double *xv,
+                               int64_t xnnz, const int *yr, const int *yc, const double *yv, int64_t ynnz,
+                               const int *cr, const int *cc, double *cv, int64_t cnnz, int *overflow,
+                               hipStream_t s);
 // X is scalar, Y has np planes (Y rows sorted)
 void launch_spgemm_numeric_by(int np, int nrows, const int *xr, const int *xc, const double *xv,
                               const int *yr, const int *yc, const double *yv, int64_t ynnz,

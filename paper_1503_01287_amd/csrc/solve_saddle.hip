@@ -341,6 +341,7 @@ constexpr int SCHUR_DENSE_MAX = 1500;
 
 void setup_schur_dense(amg_ctx *h, int l) {
     SchurHier &sh = h->lv[l].schur;
+    if (!h->prm.fuse_coarse) return;  // launch by launch (amg_params::fuse_coarse = 0)
     const int K = static_cast<int>(sh.lv.size()) - 1;  // the last level is already explicit
     int k0 = -1;
     for (int k = (l == 0 ? 1 : 0); k < K; ++k) {

@@ -40,6 +40,10 @@ def main() -> int:
                     help="default: MIXED, FP32 for the Stokes batch")
     ap.add_argument("--solves", type=int, default=1)
     ap.add_argument("--copy-mib", type=int, default=256)
+    ap.add_argument("--fuse-coarse", type=int, default=1, choices=[0, 1],
+                    help="0: no assembled coarse-end maps (the 64-cavity batch's map assembly issues"
+                         " some 10^5-10^6 small dispatches, which the counter profiler does not survive;"
+                         " the finest-level kernels and operators are the same)")
     args = ap.parse_args()
 
     import torch
@@ -51,7 +55,7 @@ def main() -> int:
     prec = args.precision or ("FP32" if wl == "stokes-batch-64" else "MIXED")
     if wl == "stokes-batch-64":
         systems = [problems.stokes_cavity(n, sp) for n, sp in synth.stokes_batch()]
-        s = BatchedSolver(systems, smoother="BS-1-1", precision=prec)
+        s = BatchedSolver(systems, smoother="BS-1-1", precision=prec, fuse_coarse=bool(args.fuse_coarse))
         rhs = __import__("numpy").concatenate([q.rhs for q in systems])
         kry = "FGMRES"
     else:
@@ -66,7 +70,7 @@ def main() -> int:
             sysm, kw["smoother"] = problems.mixed_elasticity(24), "sGS-1-1"
         saddle = sysm.n_pres > 0
         kry = "FGMRES" if saddle else ("PCG" if prec == "FP64" else "FCG")
-        s = AMGSolver(sysm, krylov=kry, precision=prec, **kw)
+        s = AMGSolver(sysm, krylov=kry, precision=prec, fuse_coarse=bool(args.fuse_coarse), **kw)
         rhs = sysm.rhs
     i0 = s.level_info(0)
     print(f"level 0: lanes {i0.lanes_A}/{i0.lanes_gs}, two entries per trip {i0.pair_A}/{i0.pair_gs}, "
