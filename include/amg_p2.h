@@ -274,6 +274,24 @@ int amg_setup(const amg_system *sys, const amg_params *params, amg_stream stream
 int amg_solve(amg_handle h, const double *b, double *x, double tol, int32_t maxit,
               amg_stream stream, amg_result *res);
 
+/* Several right-hand sides on one SPD hierarchy (PCG or FCG, any precision,
+ * JA or GS): K x_r = b_r for r < nrhs, 1 <= nrhs <= 8. Every operator,
+ * transfer and coarse-end pass of the V-cycle and of the outer operator reads
+ * its matrix once for all right-hand sides (blocks of 2, 4 or 8; a block
+ * beyond nrhs carries zero right-hand sides, which take no iterations);
+ * each right-hand side keeps its own Krylov scalars, stopping test
+ * (||b_r - K x_r|| <= tol ||b_r - K x_r,0||) and iteration count, and one
+ * that has converged keeps its iterate while the others continue. The
+ * arithmetic per right-hand side is amg_solve's up to the order of the
+ * floating-point sums; the learned-damping fallback of amg_solve is not
+ * applied here. B, X: DEVICE arrays of nrhs vectors one after another (each
+ * laid out as amg_solve's b, x); X holds the initial guesses on entry.
+ * results: HOST array of nrhs (solve_ms is the whole call's). Returns the
+ * worst status. Errors: AMG_EINVAL for a saddle point system or batch
+ * handle, another outer method, nrhs outside 1..8. */
+int amg_solve_multi(amg_handle h, int32_t nrhs, const double *B, double *X, double tol, int32_t maxit,
+                    amg_stream stream, amg_result *results);
+
 /* z = M^{-1} r: `cycles` applications of Algorithm 1 from a zero initial
  * guess on the finest level (the preconditioner used inside amg_solve).
  * r, z: device pointers, same layout as amg_solve's b and x. FP64 in and

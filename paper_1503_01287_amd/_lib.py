@@ -84,6 +84,8 @@ SIGNATURES = {
                                  ctypes.POINTER(_H)]),
     "amg_solve": (ctypes.c_int, [_H, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_int32, _S,
                                  ctypes.POINTER(AmgResult)]),
+    "amg_solve_multi": (ctypes.c_int, [_H, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                       ctypes.c_int32, _S, ctypes.POINTER(AmgResult)]),
     "amg_precondition": (ctypes.c_int, [_H, ctypes.c_void_p, ctypes.c_void_p, _S]),
     "amg_apply": (ctypes.c_int, [_H, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, _S]),
     "amg_smooth": (ctypes.c_int, [_H, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, _S]),

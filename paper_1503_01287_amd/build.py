@@ -17,7 +17,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libamgp2.so")
 OBJDIR = os.path.join(ROOT, "_build", "obj")
 
-SOURCES = ["k_row.hip", "k_spgemm.hip", "k_tail.hip", "k_mixed.hip", "solve_mp.hip", "k_saddle.hip", "solve_saddle.hip", "k_learn.hip", "k_vanka.hip", "k_batch.hip", "batch.hip", "hierarchy.hip", "solve.hip", "api.hip", "host_setup.cpp"]
+SOURCES = ["k_row.hip", "k_spgemm.hip", "k_tail.hip", "k_mixed.hip", "solve_mp.hip", "k_saddle.hip", "solve_saddle.hip", "k_learn.hip", "k_vanka.hip", "k_batch.hip", "batch.hip", "k_multi.hip", "solve_multi.hip", "hierarchy.hip", "solve.hip", "api.hip", "host_setup.cpp"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -234,6 +234,16 @@ int amg_solve(amg_handle h, const double *b, double *x, double tol, int32_t maxi
     });
 }
 
+int amg_solve_multi(amg_handle h, int32_t nrhs, const double *B, double *X, double tol, int32_t maxit,
+                    amg_stream stream, amg_result *results) {
+    return guarded([&]() -> int {
+        AMG_REQUIRE(h && B && X, AMG_EINVAL, "amg_solve_multi: null argument");
+        AMG_REQUIRE(tol > 0.0 && maxit >= 0, AMG_EINVAL, "amg_solve_multi: tol must be > 0, maxit >= 0");
+        h->stream = static_cast<hipStream_t>(stream);
+        return solve_multi(h, nrhs, B, X, tol, maxit, results);
+    });
+}
+
 int amg_precondition(amg_handle h, const double *r, double *z, amg_stream stream) {
     return guarded([&]() -> int {
         AMG_REQUIRE(h && r && z, AMG_EINVAL, "amg_precondition: null argument");

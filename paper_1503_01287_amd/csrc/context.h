@@ -202,6 +202,30 @@ struct ChunkTable {
     }
 };
 
+// Work of amg_solve_multi (blocks of K right-hand sides), kept between calls
+// with the same K: per-level block vectors (FP64 or FP32 cycle), the outer
+// Krylov blocks, dot partials and pinned slots for per-column coefficients.
+struct MultiLevelWork {
+    DevBuf<double> x, b, r, t;
+    DevBuf<float> x32, b32, r32, t32;
+};
+
+struct MultiWork {
+    static constexpr int SLOTS = 16;
+    int K = 0;
+    std::vector<MultiLevelWork> lv;
+    DevBuf<double> B, X, R, Z, P, Q, partial, dots, coef;
+    double *h_coef = nullptr, *h_dots = nullptr;
+    int used = 0;
+    MultiWork() = default;
+    MultiWork(const MultiWork &) = delete;
+    MultiWork &operator=(const MultiWork &) = delete;
+    ~MultiWork() {
+        if (h_coef) (void)hipHostFree(h_coef);
+        if (h_dots) (void)hipHostFree(h_dots);
+    }
+};
+
 struct ProfStat {
     int64_t launches = 0;
     double ms = 0.0, bytes = 0.0;
@@ -281,6 +305,7 @@ struct amg_ctx {
     amgp2::DevBuf<double> g_in, g_out;
     // Krylov workspace
     amgp2::DevBuf<double> kr, kz, kp, kq, kw;
+    amgp2::MultiWork multi;  // amg_solve_multi
     amgp2::DevBuf<double> partial, sc;
     double *h_sc = nullptr;  // pinned host copy of the scalars
     int n_dof = 0;           // length of a solve vector
@@ -360,6 +385,8 @@ void smooth(amg_ctx *h, int l, const double *b, double *x, bool pre, bool zero_i
 int solve_pcg(amg_ctx *h, const double *b, double *x, double tol, int maxit, amg_result *res);
 int solve_fcg(amg_ctx *h, const double *b, double *x, double tol, int maxit, amg_result *res);
 int solve_stationary(amg_ctx *h, const double *b, double *x, double tol, int maxit, amg_result *res);
+// K right-hand sides at once (SPD, PCG or FCG); B, X: nrhs vectors one after another
+int solve_multi(amg_ctx *h, int nrhs, const double *B, double *X, double tol, int maxit, amg_result *res);
 double true_relres(amg_ctx *h, const double *b, const double *x, double r0norm);
 
 // Wall time of a setup phase (the stream synchronised at the end) added to
