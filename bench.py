@@ -440,6 +440,65 @@ def measure(name: str, sysm, rhs, steps: int, warmup: int, tol: float, precision
     return out
 
 
+def measure_blocks(name: str, sysm, rhs, K: int, precision: str, krylov: str, with_model: bool, tol: float,
+                   passes: int = 1) -> dict:
+    """Every right-hand side of `rhs` solved in blocks of K by amg_solve_multi
+    (one setup; one untimed warm-up block, then `passes` timed passes over all
+    blocks); DOF-solves/s over the timed blocks, and each block's first
+    right-hand side against an FP64 solve to 1e-12 of it alone."""
+    import numpy as np
+    import torch
+    import paper_1503_01287_amd as amg
+    from paper_1503_01287_amd import learned
+    wl = WORKLOADS[name]
+    dev = torch.device("cuda:0")
+    model = learned.DampingModel.load() if (with_model and os.path.exists(learned.MODEL_PATH)) else None
+    kw = {"omega_model": model} if model is not None else {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s = amg.AMGSolver(sysm, smoother=wl["smoother"], krylov=krylov, precision=precision, **kw)
+    torch.cuda.synchronize()
+    setup_ms = (time.perf_counter() - t0) * 1e3
+    blocks = [torch.from_numpy(np.ascontiguousarray(np.stack(rhs[i:i + K]))).to(dev) for i in range(0, len(rhs), K)]
+    X = torch.zeros_like(blocks[0])
+    s.solve_multi(blocks[0], X, tol=tol, maxit=1000)
+    iters, rel, sols = [], [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(passes):
+        sols = []
+        for Bk in blocks:
+            Xk = torch.zeros_like(Bk)
+            res = s.solve_multi(Bk, Xk, tol=tol, maxit=1000)
+            if not all(r.converged and r.relres <= tol * 1.0001 for r in res):
+                raise SystemExit(f"# {name} block solve did not converge: {res}")
+            iters += [r.iters for r in res]
+            rel += [r.relres for r in res]
+            sols.append(Xk[0].clone())
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    s.close()
+    nsolves = passes * len(rhs)
+    # error of each block's first right-hand side against an FP64 solve of it
+    ref = amg.AMGSolver(sysm, smoother=wl["smoother"], krylov="PCG", precision="FP64")
+    errs = []
+    for Bk, xk in zip(blocks, sols):
+        xr = torch.zeros_like(Bk[0])
+        ref.solve(Bk[0].contiguous(), xr, tol=1e-12, maxit=1000)
+        errs.append(float(torch.linalg.norm(xk - xr) / torch.linalg.norm(xr)))
+    ref.close()
+    out = {"rhs_per_block": K, "rhs": len(rhs), "blocks": len(blocks), "precision": precision, "krylov": krylov,
+           "learned_omega": model is not None, "setup_ms": round(setup_ms, 1),
+           "ms_per_block": round(elapsed * 1e3 / (passes * len(blocks)), 3),
+           "ms_per_rhs": round(elapsed * 1e3 / nsolves, 3),
+           "value": float(f"{sysm.dofs * nsolves / elapsed:.6g}"),
+           "iterations_max": max(iters), "iterations_min": min(iters), "relres_max": max(rel),
+           "error_vs_fp64_reference_max": max(errs)}
+    print(f"# {name} blocks of {K}: {out['ms_per_rhs']:.2f} ms per right-hand side, iterations "
+          f"{min(iters)}-{max(iters)}", file=sys.stderr, flush=True)
+    return out
+
+
 def variants_for(name: str, precision: str, profile: bool, extras: bool) -> list:
     wl = WORKLOADS[name]
     saddle = wl.get("saddle", False)
@@ -512,6 +571,10 @@ def main() -> int:
                          "uses FP32 unless FP64 is asked for); the plain FP64 solve is timed beside it")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1),
                     help="host processes for assembling independent systems and right-hand sides")
+    ap.add_argument("--rhs-block", type=int, default=0,
+                    help="laplace-48: solve --rhs-count Dirichlet data sets in blocks of this many right-hand "
+                         "sides (amg_solve_multi); one step = one block")
+    ap.add_argument("--rhs-count", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -519,6 +582,8 @@ def main() -> int:
         return 2
 
     name = args.workload
+    if args.rhs_block:
+        return block_main(args)
     full = not args.only_timed
     extras = full and not args.no_extras and name == "elasticity-32"
     extra_steps, extra_warmup = min(args.steps, 5), 1
@@ -528,10 +593,16 @@ def main() -> int:
     print(f"# assembled {sysm.name}: {sysm.dofs} DOF, {len(rhs)} right-hand side(s) in "
           f"{time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
     other = {}
+    other_block_rhs = []
     if extras:
         for xn in ("laplace-48", "stokes-batch-64"):
             t0 = time.perf_counter()
-            other[xn] = assemble(xn, extra_warmup + extra_steps, args.workers)
+            # the Laplacian: the single-solve data sets, then 10 more (16 in all, two blocks of 8)
+            other[xn] = assemble(xn, extra_warmup + extra_steps + (10 if xn == "laplace-48" else 0), args.workers)
+            if xn == "laplace-48":
+                xs_, xr_ = other[xn]
+                other_block_rhs = xr_[extra_warmup + extra_steps:]
+                other[xn] = (xs_, xr_[:extra_warmup + extra_steps])
             print(f"# assembled {xn} in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
 
     precision = WORKLOADS[name].get("precision", args.precision) if args.precision != "FP64" else "FP64"
@@ -558,6 +629,8 @@ def main() -> int:
                               dict(label="fixed_fp64", precision="FP64", krylov="PCG", reference=True)])
                 res["variants"]["best_global_omega_mixed"] = bw["variants"]["best_global_omega_mixed"]
                 res["best_global_omega_search"] = best
+                res["blocks_of_rhs"] = measure_blocks(xn, xs, xr + other_block_rhs, 8, "MIXED", "FCG", True,
+                                                      args.tol)
             for r in res["variants"].values():
                 r.pop("levels", None)
                 for k in ("value", "relres"):
@@ -606,6 +679,33 @@ def main() -> int:
         "vcycle_bandwidth": prim.get("vcycle_bandwidth"),
         "cpu_baseline": cpu,
         "other_workloads": others,
+    }
+    print(json.dumps(out))
+    return 0
+
+
+def block_main(args) -> int:
+    """--rhs-block K: every Dirichlet data set of the 48^3 Laplacian workload
+    in blocks of K right-hand sides; one JSON line like main()'s, one step =
+    one block of K solves, value = DOF-solves/s of the timed blocks."""
+    if args.workload != "laplace-48":
+        raise SystemExit("--rhs-block applies to the laplace-48 workload")
+    K = args.rhs_block
+    t0 = time.perf_counter()
+    sysm, rhs = assemble("laplace-48", args.rhs_count, args.workers)
+    print(f"# assembled {sysm.name}: {args.rhs_count} data sets in {time.perf_counter() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    learned_ = measure_blocks("laplace-48", sysm, rhs, K, "MIXED", "FCG", True, args.tol)
+    fixed64 = measure_blocks("laplace-48", sysm, rhs, K, "FP64", "PCG", False, args.tol)
+    out = {
+        "metric": "DOF-solves/s to 1e-8 rel. residual (mixed/learned vs plain FP64); V-cycle HBM GB/s",
+        "value": learned_["value"], "unit": "DOF-solves/s", "n_gpus": 1, "steps": learned_["blocks"],
+        "warmup": 1, "ms_per_step": learned_["ms_per_block"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32/bf16 cycle, f64 outer", "data": "synthetic",
+        "config": {"workload": f"laplace-48: {WORKLOADS['laplace-48']['desc']}", "dofs": sysm.dofs,
+                   "rhs_data_sets": args.rhs_count, "rhs_per_block": K, "smoother": "JA-1-1",
+                   "learned_omega": learned_["learned_omega"], "tol": args.tol},
+        "learned_mixed_blocks": learned_, "fixed_fp64_blocks": fixed64,
     }
     print(json.dumps(out))
     return 0

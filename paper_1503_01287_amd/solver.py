@@ -301,18 +301,6 @@ class BatchedSolver:
                                           q.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))), "amg_batch_offsets")
         return u, q
 
-    def solve_multi(self, B, X, tol: float = 1e-8, maxit: int = 500) -> list:
-        """amg_solve_multi: B, X are (k, n) contiguous float64 CUDA tensors
-        (k <= 8 right-hand sides); returns one SolveResult per row."""
-        k = B.shape[0] if B.dim() == 2 else 0
-        if B.dim() != 2 or X.shape != B.shape or B.shape[1] != self.n:
-            raise ValueError(f"expected (k, {self.n}) tensors")
-        res = (C.AmgResult * k)()
-        code = C.lib().amg_solve_multi(self.h, k, _dev_ptr(B, k * self.n, "B"), _dev_ptr(X, k * self.n, "X"),
-                                       float(tol), int(maxit), _stream_handle(self._stream), res)
-        C.check(code, "amg_solve_multi")
-        return [SolveResult(r.iters, r.status, r.relres, r.solve_ms) for r in res]
-
     def precondition(self, r, z) -> None:
         """One preconditioner application in the merged layout."""
         C.check(C.lib().amg_precondition(self.h, _dev_ptr(r, self.n, "r"), _dev_ptr(z, self.n, "z"),
