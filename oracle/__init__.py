@@ -22,6 +22,10 @@ It shares no code with the GPU path. Modules:
               scales below), computed in FP64.
 * ``loops.c`` the inherently sequential loops (greedy independent set,
               greedy colouring, Gauss-Seidel sweeps) in plain C.
+* ``threaded`` (with ``omp_loops.c``) the order-independent loops (block and
+              transfer products, Gauss-Seidel within a colour, Jacobi) on
+              every host core, for timing the oracle there; the results
+              equal the sequential ones (bit for bit for the sweeps).
 
 Functions whose result has no independent pin say "parity unpinned" in their
 docstring.
