@@ -88,8 +88,8 @@ typedef void *amg_stream; /* hipStream_t */
  * level stay FP64 (FP64 accumulation). Requires AMG_KRYLOV_FGMRES. */
 
 /*
- * The linear system (Section 2.4). All pointers are HOST pointers; the
- * library copies the data to the device.
+ * The linear system (Section 2.4). The pointers are host pointers, or device
+ * pointers under memory = AMG_MEM_DEVICE; the library copies the data.
  *
  * A (velocity/displacement block): square over N = n_lin + n_quad nodes, CSR
  *   over nodes with sorted column indices and every diagonal entry present.
@@ -108,6 +108,15 @@ typedef void *amg_stream; /* hipStream_t */
  * pressure_kernel: 1 when constant pressures lie in the kernel (velocity
  *   Dirichlet data on the whole boundary, C = 0); the coarsest solve then
  *   pins its last pressure unknown.
+ * memory: where the nine arrays live. AMG_MEM_HOST (0, the default of a
+ *   zero-initialised struct): host memory. AMG_MEM_DEVICE (1): device memory
+ *   of the current device (hipMalloc'd or managed); the setup reads them in
+ *   stream order on its stream (work the caller queued on that stream before
+ *   the call is complete first) and copies them to the host for its
+ *   host-side passes (coarse/fine splits, colouring, checks) before
+ *   uploading its own copy, so the caller may free or overwrite them once the
+ *   setup has returned. A pointer that is not device memory under
+ *   AMG_MEM_DEVICE is rejected with AMG_EINVAL.
  */
 typedef struct {
     int32_t n_lin, n_quad, n_pres;
@@ -119,7 +128,11 @@ typedef struct {
     const int32_t *C_rowptr, *C_col;
     const double *C_val;
     int32_t pressure_kernel;
+    int32_t memory; /* AMG_MEM_HOST or AMG_MEM_DEVICE */
 } amg_system;
+
+#define AMG_MEM_HOST 0
+#define AMG_MEM_DEVICE 1
 
 /*
  * Parameters. amg_default_params fills the paper's defaults: GS-1-1, JA damping

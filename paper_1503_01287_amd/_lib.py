@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libamgp2.so")
 # status codes and options (mirrors amg_p2.h)
 AMG_OK, AMG_NOT_CONVERGED, AMG_BREAKDOWN, AMG_DIVERGED = 0, 1, 2, 3
 AMG_EINVAL, AMG_EHIP, AMG_ENOMEM, AMG_EUNSUPPORTED = -1, -2, -3, -4
+AMG_MEM_HOST, AMG_MEM_DEVICE = 0, 1
 SMOOTH = {"JA": 0, "GS": 1, "SGS": 2, "BS": 3, "VANKA": 4}
 KRYLOV = {"PCG": 0, "FCG": 1, "FGMRES": 2, "NONE": 3}
 PREC = {"FP64": 0, "MIXED": 1, "FP32": 2}
@@ -35,7 +36,7 @@ class AmgSystem(ctypes.Structure):
         ("A_rowptr", _i32p), ("A_col", _i32p), ("A_val", _f64p),
         ("B_rowptr", _i32p), ("B_col", _i32p), ("B_val", _f64p),
         ("C_rowptr", _i32p), ("C_col", _i32p), ("C_val", _f64p),
-        ("pressure_kernel", ctypes.c_int32),
+        ("pressure_kernel", ctypes.c_int32), ("memory", ctypes.c_int32),
     ]
 
 

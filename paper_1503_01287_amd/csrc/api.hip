@@ -23,6 +23,73 @@ amg_ctx::~amg_ctx() {
     if (h_sc) (void)hipHostFree(h_sc);
 }
 
+// A system given in device memory (amg_system::memory == AMG_MEM_DEVICE),
+// copied to host vectors in stream order; sys then points at them.
+struct StagedSystem {
+    std::vector<int32_t> arp, acol, brp, bcol, crp, ccol;
+    std::vector<double> aval, bval, cval;
+    amg_system sys{};
+};
+
+static void require_device(const void *p, const char *name) {
+    hipPointerAttribute_t at{};
+    const hipError_t e = hipPointerGetAttributes(&at, p);
+    if (e != hipSuccess) (void)hipGetLastError();
+    AMG_REQUIRE(e == hipSuccess && (at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged), AMG_EINVAL,
+                std::string("amg_setup: ") + name + " is not device memory (memory = AMG_MEM_DEVICE)");
+}
+
+template <typename T>
+static void fetch(std::vector<T> &dst, const T *src, int64_t n, const char *name, hipStream_t s) {
+    dst.resize(static_cast<size_t>(std::max<int64_t>(n, 0)));
+    if (n <= 0) return;
+    require_device(src, name);
+    AMG_HIP(hipMemcpyAsync(dst.data(), src, static_cast<size_t>(n) * sizeof(T), hipMemcpyDeviceToHost, s));
+}
+
+static void stage_system(const amg_system &in, hipStream_t s, StagedSystem &out) {
+    out.sys = in;
+    out.sys.memory = AMG_MEM_HOST;
+    const int64_t n = static_cast<int64_t>(in.n_lin) + in.n_quad;
+    AMG_REQUIRE(n > 0 && in.n_lin >= 0 && in.n_quad >= 0 && in.n_pres >= 0 && (in.bs == 1 || in.bs == 3),
+                AMG_EINVAL, "amg_setup: invalid sizes");
+    AMG_REQUIRE(in.A_rowptr && in.A_col && in.A_val, AMG_EINVAL, "amg_setup: A is missing");
+    // row pointers first: their last entries give the array lengths
+    fetch(out.arp, in.A_rowptr, n + 1, "A_rowptr", s);
+    const bool has_b = in.n_pres > 0 && in.B_rowptr && in.B_col && in.B_val;
+    const bool has_c = in.n_pres > 0 && in.C_rowptr && in.C_col && in.C_val;
+    if (has_b) fetch(out.brp, in.B_rowptr, static_cast<int64_t>(in.n_pres) + 1, "B_rowptr", s);
+    if (has_c) fetch(out.crp, in.C_rowptr, static_cast<int64_t>(in.n_pres) + 1, "C_rowptr", s);
+    AMG_HIP(hipStreamSynchronize(s));
+    const int64_t na = out.arp[n], nb = has_b ? out.brp[in.n_pres] : 0, nc = has_c ? out.crp[in.n_pres] : 0;
+    AMG_REQUIRE(na >= 0 && nb >= 0 && nc >= 0, AMG_EINVAL, "amg_setup: negative entry count in a row pointer");
+    fetch(out.acol, in.A_col, na, "A_col", s);
+    fetch(out.aval, in.A_val, na * in.bs * in.bs, "A_val", s);
+    if (has_b) {
+        fetch(out.bcol, in.B_col, nb, "B_col", s);
+        fetch(out.bval, in.B_val, 3 * nb, "B_val", s);
+    }
+    if (has_c) {
+        fetch(out.ccol, in.C_col, nc, "C_col", s);
+        fetch(out.cval, in.C_val, nc, "C_val", s);
+    }
+    AMG_HIP(hipStreamSynchronize(s));
+    // a zero-length array still needs a non-null host pointer for the checks
+    for (auto *v : {&out.acol, &out.bcol, &out.ccol})
+        if (v->empty()) v->push_back(0);
+    for (auto *v : {&out.aval, &out.bval, &out.cval})
+        if (v->empty()) v->push_back(0.0);
+    out.sys.A_rowptr = out.arp.data();
+    out.sys.A_col = out.acol.data();
+    out.sys.A_val = out.aval.data();
+    out.sys.B_rowptr = has_b ? out.brp.data() : nullptr;
+    out.sys.B_col = has_b ? out.bcol.data() : nullptr;
+    out.sys.B_val = has_b ? out.bval.data() : nullptr;
+    out.sys.C_rowptr = has_c ? out.crp.data() : nullptr;
+    out.sys.C_col = has_c ? out.ccol.data() : nullptr;
+    out.sys.C_val = has_c ? out.cval.data() : nullptr;
+}
+
 template <typename F>
 static int guarded(F &&f) {
     try {
@@ -75,6 +142,13 @@ int amg_setup(const amg_system *sys, const amg_params *params, amg_stream stream
         AMG_REQUIRE(params != nullptr, AMG_EINVAL, "amg_setup: null params");
         const amg_params &p = *params;
         AMG_REQUIRE(sys != nullptr, AMG_EINVAL, "amg_setup: null system");
+        AMG_REQUIRE(sys->memory == AMG_MEM_HOST || sys->memory == AMG_MEM_DEVICE, AMG_EINVAL,
+                    "amg_setup: memory must be AMG_MEM_HOST or AMG_MEM_DEVICE");
+        StagedSystem staged;
+        if (sys->memory == AMG_MEM_DEVICE) {
+            stage_system(*sys, static_cast<hipStream_t>(stream), staged);
+            sys = &staged.sys;
+        }
         if (sys->n_pres > 0) {
             AMG_REQUIRE(p.smoother == AMG_SMOOTH_SGS || p.smoother == AMG_SMOOTH_BS ||
                             p.smoother == AMG_SMOOTH_VANKA,
@@ -143,13 +217,24 @@ int amg_setup_batched(int32_t nsys, const amg_system *systems, const amg_params 
         AMG_REQUIRE(p.smoother != AMG_SMOOTH_VANKA, AMG_EUNSUPPORTED,
                     "amg_setup_batched: batches run the sGS or Braess-Sarazin smoother");
         AMG_REQUIRE(!p.omega_model, AMG_EINVAL, "amg_setup_batched: omega_model is for JA on SPD systems");
+        std::vector<StagedSystem> staged;
+        std::vector<amg_system> host_sys(systems, systems + nsys);
+        for (int i = 0; i < nsys; ++i) {
+            AMG_REQUIRE(systems[i].memory == AMG_MEM_HOST || systems[i].memory == AMG_MEM_DEVICE, AMG_EINVAL,
+                        "amg_setup_batched: memory must be AMG_MEM_HOST or AMG_MEM_DEVICE");
+            if (systems[i].memory == AMG_MEM_DEVICE) {
+                if (staged.empty()) staged.resize(nsys);
+                stage_system(systems[i], static_cast<hipStream_t>(stream), staged[i]);
+                host_sys[i] = staged[i].sys;
+            }
+        }
         auto *h = new amg_ctx();
         h->prm = p;
         h->prm.level_omega = nullptr;
         h->prm.n_level_omega = 0;
         h->stream = static_cast<hipStream_t>(stream);
         try {
-            build_batch(h, nsys, systems);
+            build_batch(h, nsys, host_sys.data());
         } catch (...) {
             delete h;
             throw;

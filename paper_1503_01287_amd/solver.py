@@ -57,12 +57,19 @@ def _dev_ptr(t, n: int, name: str):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def _marshal(system: LinearSystem, keep: list) -> "C.AmgSystem":
-    """amg_system over host copies of the arrays (kept alive in `keep`)."""
+def _marshal(system: LinearSystem, keep: list, device: bool = False) -> "C.AmgSystem":
+    """amg_system over host copies of the arrays, or over device copies
+    (CUDA tensors, memory = AMG_MEM_DEVICE) when `device`; the copies are
+    kept alive in `keep`."""
     def arr(a, dtype, ctype):
         if a is None:
             return None
         a = np.ascontiguousarray(a, dtype=dtype)
+        if device:
+            import torch
+            t = torch.from_numpy(a).to("cuda")
+            keep.append(t)
+            return ctypes.cast(ctypes.c_void_p(t.data_ptr()), ctypes.POINTER(ctype))
         keep.append(a)
         return C._ptr(a, ctype)
 
@@ -78,6 +85,7 @@ def _marshal(system: LinearSystem, keep: list) -> "C.AmgSystem":
     s.C_col = arr(system.C_col, np.int32, ctypes.c_int32)
     s.C_val = arr(system.C_val, np.float64, ctypes.c_double)
     s.pressure_kernel = 1 if system.pressure_kernel else 0
+    s.memory = 1 if device else 0
     return s
 
 
@@ -89,7 +97,8 @@ class AMGSolver:
                  max_levels: int = 10, separate: bool = True, level_omega=None,
                  sgs_omega: float = 0.125, sgs_damping: float = 0.5, restart: int = 100,
                  omega: float | None = None, fuse_coarse: bool = True, autotune: bool = True,
-                 omega_model=None, graph: bool = True, gs_post: str = "auto", stream=None):
+                 omega_model=None, graph: bool = True, gs_post: str = "auto", stream=None,
+                 device_system: bool = False):
         L = C.lib()
         p = C.default_params()
         sm = parse_smoother(smoother)
@@ -119,7 +128,10 @@ class AMGSolver:
         self.params = p
         self.system = system
         keep = []
-        s = _marshal(system, keep)
+        s = _marshal(system, keep, device=device_system)
+        if device_system:
+            import torch
+            (torch.cuda.current_stream() if stream is None else stream).synchronize()
         self._stream = stream
         h = ctypes.c_void_p()
         C.check(L.amg_setup(ctypes.byref(s), ctypes.byref(p), _stream_handle(stream), ctypes.byref(h)),
@@ -257,7 +269,7 @@ class BatchedSolver:
     def __init__(self, systems, smoother: str = "BS-1-1", cycles: int = 1, nu: int = 1,
                  coarse_max: int = 300, max_levels: int = 10, sgs_omega: float = 0.125,
                  sgs_damping: float = 0.5, restart: int = 100, graph: bool = True, precision: str = "FP64",
-                 fuse_coarse: bool = True, autotune: bool = True, stream=None):
+                 fuse_coarse: bool = True, autotune: bool = True, stream=None, device_system: bool = False):
         L = C.lib()
         p = C.default_params()
         sm = parse_smoother(smoother)
@@ -277,7 +289,10 @@ class BatchedSolver:
         keep = []
         arr = (C.AmgSystem * len(self.systems))()
         for i, sysm in enumerate(self.systems):
-            arr[i] = _marshal(sysm, keep)
+            arr[i] = _marshal(sysm, keep, device=device_system)
+        if device_system:
+            import torch
+            torch.cuda.synchronize()
         self._stream = stream
         h = ctypes.c_void_p()
         C.check(L.amg_setup_batched(len(self.systems), arr, ctypes.byref(p), _stream_handle(stream),
