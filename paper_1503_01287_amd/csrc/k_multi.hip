@@ -32,102 +32,177 @@ __device__ __forceinline__ T gsum(T v) {
     return v;
 }
 
-// One group of G lanes per row; lane t walks entries t, t + G, ... and keeps
-// 3 x K partial sums; after the group reduction every lane holds the row's
-// sums, and lane t writes the outputs (c, r) with c K + r = t (mod G).
-template <int MODE, int G, int OP, int VK, int K>
+// One group of G = E K lanes per row. Lane (e, r) = (lane / K, lane % K)
+// walks the row's entries e, e + E, ... for right-hand side r, U entries per
+// trip (their column indices, then their values and gathers, in flight
+// together; entries past the row's end are skipped): the K lanes of one
+// entry slot read its column index and values at the same addresses and the
+// 3 K contiguous values of x at that column together (x at column j,
+// component c, right-hand side r sits at (3 j + c) K + r). The 3 sums of
+// every lane are reduced over the E slots in a fixed butterfly order, and the
+// slot-0 lanes write their right-hand side's 3 outputs of the row.
+template <int MODE, int E, int U, int OP, int VK, int K>
 __global__ void __launch_bounds__(TB) k_mrow(const MRowArgs a) {
     using T = vec_t<VK>;
+    constexpr int G = E * K;
+    static_assert(G <= 64 && (64 % G) == 0, "a row group stays inside one wavefront");
     const int64_t t = static_cast<int64_t>(blockIdx.x) * TB + threadIdx.x;
     const int g = static_cast<int>(t / G), lane = static_cast<int>(t % G);
     if (g >= a.nrows) return;  // whole groups leave together (G divides 64)
+    const int e = lane / K, r = lane % K;
     const int i = a.rowid ? a.rowid[g] : g;
     const T *x = static_cast<const T *>(a.x);
-    T s[3][K];
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int r = 0; r < K; ++r) s[c][r] = T(0);
-    const int beg = a.rowptr[g], end = a.rowptr[g + 1];
-    const int64_t nz = a.nnz;
-    for (int k = beg + lane; k < end; k += G) {
-        const int j = a.col[k];
-        const T *xj = x + static_cast<int64_t>(3) * j * K;
-        T xv[3][K];
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-#pragma unroll
-            for (int r = 0; r < K; ++r) xv[c][r] = xj[c * K + r];
-        if constexpr (MODE == 3) {
-#pragma unroll
-            for (int rr = 0; rr < 3; ++rr)
-#pragma unroll
-                for (int cc = 0; cc < 3; ++cc) {
-                    const T v = ldv<VK>(a.val, (3 * rr + cc) * nz + k);
-#pragma unroll
-                    for (int r = 0; r < K; ++r) s[rr][r] += v * xv[cc][r];
-                }
-        } else {
-            const T v = ldv<VK>(a.val, k);
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-#pragma unroll
-                for (int r = 0; r < K; ++r) s[c][r] += v * xv[c][r];
-        }
-    }
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int r = 0; r < K; ++r) s[c][r] = gsum<G>(s[c][r]);
-    if constexpr (VK == MK_BF16) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const float q = MODE == 3 ? a.rscale[3 * i + c] : a.rscale[i];
-#pragma unroll
-            for (int r = 0; r < K; ++r) s[c][r] *= q;
-        }
-    }
     const T *b = static_cast<const T *>(a.b);
     T *y = static_cast<T *>(a.y);
     const T *D = static_cast<const T *>(a.dinv);
-    const int64_t base = static_cast<int64_t>(3) * i * K;
+    const int64_t o0 = static_cast<int64_t>(3) * i * K + r;  // output (i, 0, r); (i, c, r) at o0 + c K
+    constexpr bool NEEDS_B = OP == M_RESID || OP == M_JACOBI || OP == M_GS;
+    constexpr bool NEEDS_D = OP == M_JACOBI || OP == M_GS;
+    // the epilogue's row operands, loaded before the row's entries so that
+    // their latency overlaps the row
+    T b0 = T(0), b1 = T(0), b2 = T(0), w0 = T(0), w1 = T(0), w2 = T(0);
+    T dm[MODE == 3 ? 9 : 1];
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
+    for (int q = 0; q < (MODE == 3 ? 9 : 1); ++q) dm[q] = T(0);
+    float q0 = 1.f, q1 = 1.f, q2 = 1.f;
+    if (e == 0) {
+        if constexpr (NEEDS_B) {
+            b0 = b[o0];
+            b1 = b[o0 + K];
+            b2 = b[o0 + 2 * K];
+        }
+        if constexpr (NEEDS_D) {
+            if constexpr (MODE == 3) {
 #pragma unroll
-        for (int r = 0; r < K; ++r) {
-            if ((c * K + r) % G != lane) continue;
-            const int64_t o = base + c * K + r;
-            if (a.zero_out) static_cast<T *>(a.zero_out)[o] = T(0);
-            if constexpr (OP == M_SPMV) {
-                y[o] = s[c][r];
-            } else if constexpr (OP == M_SPMV_ADD) {
-                y[o] = y[o] + s[c][r];
-            } else if constexpr (OP == M_RESID) {
-                y[o] = b[o] - s[c][r];
+                for (int q = 0; q < 9; ++q) dm[q] = D[q * a.dinv_n + i];
             } else {
-                T d;
-                if constexpr (MODE == 3) {
-                    const T r0 = b[base + r] - s[0][r], r1 = b[base + K + r] - s[1][r],
-                            r2 = b[base + 2 * K + r] - s[2][r];
-                    d = D[(3 * c) * a.dinv_n + i] * r0 + D[(3 * c + 1) * a.dinv_n + i] * r1 +
-                        D[(3 * c + 2) * a.dinv_n + i] * r2;
-                } else {
-                    d = D[i] * (b[o] - s[c][r]);
-                }
-                if constexpr (OP == M_JACOBI)
-                    y[o] = x[o] + static_cast<T>(a.omega) * d;
-                else  // M_GS, in place
-                    y[o] = y[o] + d;
+                dm[0] = D[i];
             }
         }
+        if constexpr (OP == M_SPMV_ADD || OP == M_GS || OP == M_JACOBI) {
+            const T *own = OP == M_JACOBI ? x : y;
+            w0 = own[o0];
+            w1 = own[o0 + K];
+            w2 = own[o0 + 2 * K];
+        }
+        if constexpr (VK == MK_BF16) {
+            if constexpr (MODE == 3) {
+                q0 = a.rscale[3 * i];
+                q1 = a.rscale[3 * i + 1];
+                q2 = a.rscale[3 * i + 2];
+            } else {
+                q0 = q1 = q2 = a.rscale[i];
+            }
+        }
+    }
+    T s0 = T(0), s1 = T(0), s2 = T(0);
+    const int beg = a.rowptr[g], end = a.rowptr[g + 1];
+    const int64_t nz = a.nnz;
+    constexpr int NV = MODE == 3 ? 9 : 1;
+    for (int k = beg + e; k < end; k += U * E) {
+        int j[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) j[u] = k + u * E < end ? a.col[k + u * E] : -1;
+        T v[U][NV], xv[U][3];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (j[u] >= 0) {
+#pragma unroll
+                for (int q = 0; q < NV; ++q) v[u][q] = ldv<VK>(a.val, q * nz + k + u * E);
+                const T *xj = x + static_cast<int64_t>(3) * j[u] * K + r;
+                xv[u][0] = xj[0];
+                xv[u][1] = xj[K];
+                xv[u][2] = xj[2 * K];
+            } else {
+#pragma unroll
+                for (int q = 0; q < NV; ++q) v[u][q] = T(0);
+                xv[u][0] = xv[u][1] = xv[u][2] = T(0);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if constexpr (MODE == 3) {
+                s0 += v[u][0] * xv[u][0] + v[u][1] * xv[u][1] + v[u][2] * xv[u][2];
+                s1 += v[u][3] * xv[u][0] + v[u][4] * xv[u][1] + v[u][5] * xv[u][2];
+                s2 += v[u][6] * xv[u][0] + v[u][7] * xv[u][1] + v[u][8] * xv[u][2];
+            } else {
+                s0 += v[u][0] * xv[u][0];
+                s1 += v[u][0] * xv[u][1];
+                s2 += v[u][0] * xv[u][2];
+            }
+        }
+    }
+    // over the entry slots: lanes of one right-hand side differ by multiples of K
+#pragma unroll
+    for (int o = G / 2; o >= K; o >>= 1) {
+        s0 += __shfl_xor(s0, o, G);
+        s1 += __shfl_xor(s1, o, G);
+        s2 += __shfl_xor(s2, o, G);
+    }
+    if (e != 0) return;
+    if constexpr (VK == MK_BF16) {
+        s0 *= q0;
+        s1 *= q1;
+        s2 *= q2;
+    }
+    if (a.zero_out) {
+        T *z = static_cast<T *>(a.zero_out);
+        z[o0] = T(0);
+        z[o0 + K] = T(0);
+        z[o0 + 2 * K] = T(0);
+    }
+    T y0, y1, y2;
+    if constexpr (OP == M_SPMV) {
+        y0 = s0;
+        y1 = s1;
+        y2 = s2;
+    } else if constexpr (OP == M_SPMV_ADD) {
+        y0 = w0 + s0;
+        y1 = w1 + s1;
+        y2 = w2 + s2;
+    } else if constexpr (OP == M_RESID) {
+        y0 = b0 - s0;
+        y1 = b1 - s1;
+        y2 = b2 - s2;
+    } else {
+        const T r0 = b0 - s0, r1 = b1 - s1, r2 = b2 - s2;
+        T d0, d1, d2;
+        if constexpr (MODE == 3) {
+            d0 = dm[0] * r0 + dm[1] * r1 + dm[2] * r2;
+            d1 = dm[3] * r0 + dm[4] * r1 + dm[5] * r2;
+            d2 = dm[6] * r0 + dm[7] * r1 + dm[8] * r2;
+        } else {
+            d0 = dm[0] * r0;
+            d1 = dm[0] * r1;
+            d2 = dm[0] * r2;
+        }
+        if constexpr (OP == M_JACOBI) {
+            const T om = static_cast<T>(a.omega);
+            y0 = w0 + om * d0;
+            y1 = w1 + om * d1;
+            y2 = w2 + om * d2;
+        } else {  // M_GS, in place
+            y0 = w0 + d0;
+            y1 = w1 + d1;
+            y2 = w2 + d2;
+        }
+    }
+    y[o0] = y0;
+    y[o0 + K] = y1;
+    y[o0 + 2 * K] = y2;
 }
 
+// 16 lanes per row (E = 16 / K entry slots), 4 entries per slot and trip for
+// scalar entries, 2 for 3x3 blocks: the fastest of the shapes measured on
+// the 48^3 Laplacian's finest operator with 8 right-hand sides (E in 1..16,
+// U in 1..8; 2- and 4-wide vector gathers per lane and per-XCD row chunks
+// were slower)
 template <int MODE, int OP, int VK, int K>
 static void mrow_launch(const MRowArgs &a, hipStream_t s) {
-    constexpr int G = MODE == 3 ? 16 : 8;
+    constexpr int G = 16, E = G / K, U = MODE == 3 ? 2 : 4;
     const int nb = ceil_div(static_cast<int64_t>(a.nrows) * G, TB);
     if (nb == 0) return;
-    k_mrow<MODE, G, OP, VK, K><<<nb, TB, 0, s>>>(a);
+    k_mrow<MODE, E, U, OP, VK, K><<<nb, TB, 0, s>>>(a);
 }
 
 template <int MODE, int VK, int K>
@@ -318,13 +393,23 @@ __global__ void __launch_bounds__(TB) k_mdot(DotPtrs q, int64_t nd, double *part
     }
 }
 
-// out[o] = sum of partial[blk][o] over blk in order
-__global__ void k_mdot_reduce(const double *partial, int nb, int no, double *out) {
-    const int o = blockIdx.x * 64 + threadIdx.x;
-    if (o >= no) return;
+// out[o] = sum of partial[blk][o] over the nb blocks: one workgroup per
+// output; thread u sums blocks u, u + TB, ... in order, then a fixed-order
+// tree over the workgroup
+__global__ void __launch_bounds__(TB) k_mdot_reduce(const double *partial, int nb, int no, double *out) {
+    __shared__ double red[TB / 64];
+    const int o = blockIdx.x;
     double v = 0.0;
-    for (int b = 0; b < nb; ++b) v += partial[static_cast<int64_t>(b) * no + o];
-    out[o] = v;
+    for (int b = threadIdx.x; b < nb; b += TB) v += partial[static_cast<int64_t>(b) * no + o];
+    v = gsum<64>(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double w = 0.0;
+#pragma unroll
+        for (int u = 0; u < TB / 64; ++u) w += red[u];
+        out[o] = w;
+    }
 }
 
 template <int NP>
@@ -353,7 +438,7 @@ void launch_mdot(int np, int K, int64_t nd, const double *const *a, const double
     }
     AMG_CHECK_LAUNCH();
     const int no = np * K;
-    k_mdot_reduce<<<ceil_div(no, 64), 64, 0, s>>>(partial, nb, no, out);
+    k_mdot_reduce<<<no, TB, 0, s>>>(partial, nb, no, out);
     AMG_CHECK_LAUNCH();
 }
 
