@@ -28,7 +28,7 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
 PROFILES = os.path.join(ROOT, "profiles")
 
 
-def measured_traffic(workload: str, precision: str, kernel_class: str, lanes: int, pair: int, xcd: int):
+def measured_traffic(workload: str, precision: str, kernel_class: str, lanes: int, trip: int, xcd: int):
     """HBM bytes per launch of the dominant kernel from a committed rocprofv3
     --pmc summary of this workload (profiles/<workload>_*_traffic.md:
     FETCH_SIZE + WRITE_SIZE, copy-calibrated), if one covers this kernel
@@ -44,7 +44,7 @@ def measured_traffic(workload: str, precision: str, kernel_class: str, lanes: in
                     continue
                 kv = dict(t.split("=", 1) for t in line.split()[1:])
                 if (kv.get("class") == kernel_class and kv.get("precision") == precision
-                        and int(kv.get("lanes", -1)) == lanes and int(kv.get("pair", 0)) == pair
+                        and int(kv.get("lanes", -1)) == lanes and int(kv.get("trip", 0)) == trip
                         and int(kv.get("xcd", 0)) == xcd):
                     return int(kv["bytes_per_launch"])
     return None
@@ -233,7 +233,7 @@ def _profile_classes(nlevels: int) -> list:
 
 
 def _class_shape(cls: str, levels: list):
-    """(lanes, pair, xcd) of the kernel a class launches, for the traffic lookup."""
+    """(lanes, entries per trip, xcd) of the kernel a class launches, for the traffic lookup."""
     if "." not in cls:
         return -1, 0, 0
     op, lv = cls.split(".")
@@ -241,7 +241,7 @@ def _class_shape(cls: str, levels: list):
     if op == "spmv":
         return lv["fp64"][0], lv["fp64"][1], 0
     which = 1 if op == "gs" else 0
-    return lv["lanes"][which], lv["pair"][which], (lv["gs_xcd"] if which else 0)
+    return lv["lanes"][which], lv["trip"][which], (lv["gs_xcd"] if which else 0)
 
 
 # ---------------------------------------------------------------- assembly
@@ -335,7 +335,7 @@ def measure(name: str, sysm, rhs, steps: int, warmup: int, tol: float, precision
             i = solver.level_info(l)
             out.append(dict(nodes=i.n_lin + i.n_quad, pressure=i.n_pres, nnz=int(i.nnz_A), kept=int(i.kept_A),
                             colors=int(i.n_colors), lanes=[int(i.lanes_A), int(i.lanes_gs)],
-                            pair=[int(i.pair_A), int(i.pair_gs)], fp64=[int(i.lanes64_A), int(i.pair64_A)],
+                            trip=[int(i.trip_A), int(i.trip_gs)], fp64=[int(i.lanes64_A), int(i.trip64_A)],
                             gs_xcd=int(i.gs_xcd), fused=bool(i.fused), coarse_map=bool(i.coarse_map),
                             omega=round(float(i.omega), 4)))
         return out
@@ -397,8 +397,8 @@ def measure(name: str, sysm, rhs, steps: int, warmup: int, tol: float, precision
             per_launch_bytes = st["bytes"] / st["launches"]
             per_launch_ms = st["ms"] / st["launches"]
             achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
-            lanes, pair, xcd = _class_shape(dom, levels)
-            traffic = measured_traffic(name, precision, dom, lanes, pair, xcd)
+            lanes, trip, xcd = _class_shape(dom, levels)
+            traffic = measured_traffic(name, precision, dom, lanes, trip, xcd)
             res["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                                "kernel": dom, "launches_per_step": st["launches"] // steps,

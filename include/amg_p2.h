@@ -232,10 +232,10 @@ typedef struct {
     int64_t nnz_S;                 /* entries of that Schur complement S_l   */
     int32_t gs_xcd;                /* 1 if the colour sweeps give each XCD one
                                       contiguous eighth of a colour's rows    */
-    int32_t pair_A, pair_gs;       /* 1 if those kernels take two entries per
-                                      lane and loop trip                      */
-    int32_t lanes64_A, pair64_A;   /* the FP64 natural-order kernels' lanes
-                                      and loop form (the outer Krylov
+    int32_t trip_A, trip_gs;       /* entries per lane and loop trip of those
+                                      kernels: 1, 2 or 4                      */
+    int32_t lanes64_A, trip64_A;   /* the FP64 natural-order kernels' lanes
+                                      and entries per trip (the outer Krylov
                                       operator also in reduced-precision
                                       solves)                                 */
     int64_t kept_A, kept_B;        /* entries the smoothers and solve kernels
@@ -340,17 +340,19 @@ int amg_get_level_colors(amg_handle h, int32_t level, int32_t *colors);
  * Jacobi, operator, the outer Krylov operator on level 0), AMG_SHAPE_SWEEP
  * the FP64 colour sweeps, AMG_SHAPE_NATURAL_RP / AMG_SHAPE_SWEEP_RP the same
  * kernels of the reduced-precision copies. lanes: lanes of the 64-wide
- * wavefront per row, one of 4, 8, 16, 32, 64. pair: 1 = two entries per lane
- * and loop trip, 0 = one. xcd (colour sweeps only): 1 = each XCD takes one
+ * wavefront per row, one of 4, 8, 16, 32, 64. trip: entries per lane and
+ * loop trip, 1, 2 or 4 (a lane's entries of one trip have their loads in
+ * flight together; the sums do not depend on it; the prolongation kernels
+ * always take 1). xcd (colour sweeps only): 1 = each XCD takes one
  * contiguous eighth of a colour's rows, 0 = round-robin placement.
  * Recorded preconditioner graphs are dropped (they hold the old shapes).
- * Errors: AMG_EINVAL for a bad level, kernel class, lane count or flag, or a
+ * Errors: AMG_EINVAL for a bad level, kernel class, lane count, trip or flag, or a
  * reduced-precision class on an FP64 hierarchy. */
 #define AMG_SHAPE_NATURAL 0
 #define AMG_SHAPE_SWEEP 1
 #define AMG_SHAPE_NATURAL_RP 2
 #define AMG_SHAPE_SWEEP_RP 3
-int amg_set_launch_shape(amg_handle h, int32_t level, int32_t kernels, int32_t lanes, int32_t pair, int32_t xcd);
+int amg_set_launch_shape(amg_handle h, int32_t level, int32_t kernels, int32_t lanes, int32_t trip, int32_t xcd);
 
 /* ---- batches of independent saddle point systems ----------------------
  * Many solves of uneven size in one set of launches. Each system gets the

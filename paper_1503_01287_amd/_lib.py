@@ -68,8 +68,8 @@ class AmgLevelInfo(ctypes.Structure):
         ("n_colors", ctypes.c_int32), ("is_coarsest", ctypes.c_int32),
         ("lanes_A", ctypes.c_int32), ("lanes_gs", ctypes.c_int32), ("fused", ctypes.c_int32),
         ("omega", ctypes.c_double), ("schur_levels", ctypes.c_int32), ("nnz_S", ctypes.c_int64),
-        ("gs_xcd", ctypes.c_int32), ("pair_A", ctypes.c_int32), ("pair_gs", ctypes.c_int32),
-        ("lanes64_A", ctypes.c_int32), ("pair64_A", ctypes.c_int32),
+        ("gs_xcd", ctypes.c_int32), ("trip_A", ctypes.c_int32), ("trip_gs", ctypes.c_int32),
+        ("lanes64_A", ctypes.c_int32), ("trip64_A", ctypes.c_int32),
         ("kept_A", ctypes.c_int64), ("kept_B", ctypes.c_int64),
         ("coarse_map", ctypes.c_int32), ("learned", ctypes.c_int32), ("omega_max", ctypes.c_double),
         ("omega_fallbacks", ctypes.c_int32),

@@ -407,10 +407,10 @@ int amg_get_level_info(amg_handle h, int32_t level, amg_level_info *info) {
         info->is_coarsest = L.coarsest ? 1 : 0;
         info->lanes_A = h->mixed ? L.mp.G : L.G;
         info->lanes_gs = h->mixed ? L.mp.Gg : L.Gg;
-        info->pair_A = h->mixed ? L.mp.pair : L.pair;
-        info->pair_gs = h->mixed ? L.mp.pairg : L.pairg;
+        info->trip_A = h->mixed ? L.mp.trip : L.trip;
+        info->trip_gs = h->mixed ? L.mp.tripg : L.tripg;
         info->lanes64_A = L.G;
-        info->pair64_A = L.pair;
+        info->trip64_A = L.trip;
         const int fs = h->tail_start >= 0 ? h->tail_start
                        : h->dense_start >= 0 ? h->dense_start
                                              : h->saddle_tail_from;
@@ -595,30 +595,30 @@ void amg_mlp_destroy(amg_mlp_handle m) {
     delete m;
 }
 
-int amg_set_launch_shape(amg_handle h, int32_t level, int32_t kernels, int32_t lanes, int32_t pair, int32_t xcd) {
+int amg_set_launch_shape(amg_handle h, int32_t level, int32_t kernels, int32_t lanes, int32_t trip, int32_t xcd) {
     return guarded([&]() -> int {
         AMG_REQUIRE(h != nullptr, AMG_EINVAL, "amg_set_launch_shape: null handle");
         AMG_REQUIRE(level >= 0 && level < static_cast<int>(h->lv.size()), AMG_EINVAL,
                     "amg_set_launch_shape: bad level");
         AMG_REQUIRE(lanes == 4 || lanes == 8 || lanes == 16 || lanes == 32 || lanes == 64, AMG_EINVAL,
                     "amg_set_launch_shape: lanes must be 4, 8, 16, 32 or 64");
-        AMG_REQUIRE((pair == 0 || pair == 1) && (xcd == 0 || xcd == 1), AMG_EINVAL,
-                    "amg_set_launch_shape: pair and xcd are 0 or 1");
+        AMG_REQUIRE(trip == 1 || trip == 2 || trip == 4, AMG_EINVAL, "amg_set_launch_shape: trip must be 1, 2 or 4");
+        AMG_REQUIRE(xcd == 0 || xcd == 1, AMG_EINVAL, "amg_set_launch_shape: xcd is 0 or 1");
         Level &L = h->lv[level];
         const bool sweep = kernels == AMG_SHAPE_SWEEP || kernels == AMG_SHAPE_SWEEP_RP;
         AMG_REQUIRE(sweep || xcd == 0, AMG_EINVAL, "amg_set_launch_shape: xcd applies to colour sweeps only");
         switch (kernels) {
-            case AMG_SHAPE_NATURAL: L.G = lanes; L.pair = pair; break;
-            case AMG_SHAPE_SWEEP: L.Gg = lanes; L.pairg = pair; L.gs_xcd = xcd; break;
+            case AMG_SHAPE_NATURAL: L.G = lanes; L.trip = trip; break;
+            case AMG_SHAPE_SWEEP: L.Gg = lanes; L.tripg = trip; L.gs_xcd = xcd; break;
             case AMG_SHAPE_NATURAL_RP:
             case AMG_SHAPE_SWEEP_RP:
                 AMG_REQUIRE(h->mixed, AMG_EINVAL, "amg_set_launch_shape: no reduced-precision copy (FP64 hierarchy)");
                 if (kernels == AMG_SHAPE_NATURAL_RP) {
                     L.mp.G = lanes;
-                    L.mp.pair = pair;
+                    L.mp.trip = trip;
                 } else {
                     L.mp.Gg = lanes;
-                    L.mp.pairg = pair;
+                    L.mp.tripg = trip;
                     L.mp.xcd = xcd;
                 }
                 break;

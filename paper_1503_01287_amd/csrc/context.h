@@ -31,7 +31,7 @@ struct DMat {
 struct LevelMP {
     int kind = VAL_F32;            // value kind of A and its grouped copy
     int G = 16, Gg = 16;           // lanes per row of the reduced-precision A / grouped-A kernels
-    int pair = 0, pairg = 0;       // their loop form (two entries per trip), chosen by the tuner
+    int trip = 1, tripg = 1;       // their entries per lane and loop trip (1, 2, 4), chosen by the tuner
     int xcd = 0;                   // per-XCD contiguous rows in the colour sweeps (as Level::gs_xcd)
     DevBuf<float> a32, ag32;       // FP32 planes
     DevBuf<uint16_t> a16, ag16;    // BF16 planes (values / row scale)
@@ -150,7 +150,7 @@ struct Level {
     DevBuf<double> x, b, r, t;
     int G = 16, Gg = 16, Gp = 4, Gr = 8;  // lanes per row: A, grouped A, P, R
     int gs_xcd = 0;           // colour sweeps with one contiguous eighth of the rows per XCD
-    int pair = 0, pairg = 0;  // two entries per lane and trip (natural-order / colour kernels)
+    int trip = 1, tripg = 1;  // entries per lane and loop trip, 1, 2 or 4 (natural-order / colour kernels)
     LevelMP mp;               // mixed-precision copy (AMG_PREC_MIXED / FP32)
     // saddle point levels (n_pres > 0); vectors are [u (3n); p (n_pres)]
     DMat B, Bt, C;            // B: n_pres x n (1x3), Bt: n x n_pres (3x1), C: n_pres^2 (may be empty)

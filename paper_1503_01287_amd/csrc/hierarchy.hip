@@ -336,26 +336,29 @@ void autotune_level(amg_ctx *h, Level &L) {
         }
         return best_ms;
     };
-    // Candidates are timed against the heuristic's choice, which another
-    // candidate replaces only when it is at least 5% faster (10% for the
-    // two-entries-per-trip form, whose gain on these rows sits near 5%):
-    // timing noise then does not flip the choice from one setup to the next.
+    // Candidates (lanes G, entries per lane and trip T) are timed against
+    // the heuristic's choice (T = 1), which another candidate replaces only
+    // when it is at least 5% faster (10% for T > 1, whose gain on some rows
+    // sits near 5%): timing noise then does not flip the choice from one
+    // setup to the next. T > 1 is tried only where a trip of the row group
+    // (G T entries) is at most twice the mean row.
+    const double avg_row = static_cast<double>(L.A.nnz) / std::max(1, L.n);
     auto pick = [&](int G0, auto &&time_of) {
-        int bestG = G0, bestP = 0;
-        float best = time_of(G0, 0);
-        for (int P = 0; P < 2; ++P)
+        int bestG = G0, bestT = 1;
+        float best = time_of(G0, 1);
+        for (int T : {1, 2, 4})
             for (int G : cand) {
-                if (G == G0 && P == 0) continue;
-                const float ms = time_of(G, P);
-                if (ms < (P ? 0.90f : 0.95f) * best) {
+                if ((G == G0 && T == 1) || (T > 1 && G * T > 2.0 * avg_row)) continue;
+                const float ms = time_of(G, T);
+                if (ms < (T > 1 ? 0.90f : 0.95f) * best) {
                     best = ms;
                     bestG = G;
-                    bestP = P;
+                    bestT = T;
                 }
             }
-        return std::make_tuple(bestG, bestP, best);
+        return std::make_tuple(bestG, bestT, best);
     };
-    std::tie(L.G, L.pair, std::ignore) = pick(L.G, [&](int G, int P) {
+    std::tie(L.G, L.trip, std::ignore) = pick(L.G, [&](int G, int P) {
         RowArgs a;
         a.nrows = L.n;
         a.rowptr = L.A.rowptr.p;
@@ -365,7 +368,7 @@ void autotune_level(amg_ctx *h, Level &L) {
         a.x = L.x.p;
         a.b = L.b.p;
         a.y = L.r.p;
-        a.pair = P;
+        a.trip = P;
         return time_it([&] { launch_row(L.mode, OP_RESID, G, a, s); });
     });
     if (!L.cptr.empty()) {
@@ -388,14 +391,14 @@ void autotune_level(amg_ctx *h, Level &L) {
                     a.dinv = L.dinv.p;
                     a.dinv_n = L.n;
                     a.xcd_chunks = xcd;
-                    a.pair = P;
+                    a.trip = P;
                     launch_row(L.mode, OP_GS, G, a, s);
                 }
             });
         };
         float rr_ms = 0.f;
-        std::tie(L.Gg, L.pairg, rr_ms) = pick(L.Gg, [&](int G, int P) { return sweep_time(G, P, 0); });
-        L.gs_xcd = sweep_time(L.Gg, L.pairg, 1) < 0.95f * rr_ms ? 1 : 0;
+        std::tie(L.Gg, L.tripg, rr_ms) = pick(L.Gg, [&](int G, int P) { return sweep_time(G, P, 0); });
+        L.gs_xcd = sweep_time(L.Gg, L.tripg, 1) < 0.95f * rr_ms ? 1 : 0;
     }
     if (L.n_pres > 0 && L.B.nnz > 0) {
         // saddle levels: lanes of the B (1x3, pressure rows) and B^T (3x1,

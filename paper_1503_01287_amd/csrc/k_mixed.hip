@@ -62,7 +62,8 @@ __device__ __forceinline__ void acc_entry(const void *val, int64_t nz, int k, fl
     }
 }
 
-template <int MODE, int G, int OP, int KIND, bool PAIR>
+// U entries per lane and loop trip as in k_row (the same result for every U)
+template <int MODE, int G, int OP, int KIND, int U>
 __global__ void __launch_bounds__(MBLOCK) k_row_mp(const RowArgsMP a) {
     const int64_t blk = a.xcd_chunks ? xcd_chunk_block() : static_cast<int64_t>(blockIdx.x);
     const int64_t t = blk * MBLOCK + threadIdx.x;
@@ -113,22 +114,34 @@ __global__ void __launch_bounds__(MBLOCK) k_row_mp(const RowArgsMP a) {
     if (active) {
         const int beg = a.rowptr[g], end = a.rowptr[g + 1];
         const int64_t nz = a.nnz;
-        int k = beg + lane;
-        if constexpr (PAIR) {
-            // two entries per trip: both column indices, then both gathers
-            // of x, are in flight together (long rows on few lanes)
-            for (; k + G < end; k += 2 * G) {
-                const int j = a.col[k], jb = a.col[k + G];
+        if constexpr (U == 1) {
+            for (int k = beg + lane; k < end; k += G) {
+                const int j = a.col[k];
                 const float x0 = a.x[3 * j], x1 = a.x[3 * j + 1], x2 = a.x[3 * j + 2];
-                const float y0 = a.x[3 * jb], y1 = a.x[3 * jb + 1], y2 = a.x[3 * jb + 2];
                 acc_entry<MODE, KIND>(a.val, nz, k, x0, x1, x2, s0, s1, s2);
-                acc_entry<MODE, KIND>(a.val, nz, k + G, y0, y1, y2, s0, s1, s2);
             }
-        }
-        for (; k < end; k += G) {
-            const int j = a.col[k];
-            const float x0 = a.x[3 * j], x1 = a.x[3 * j + 1], x2 = a.x[3 * j + 2];
-            acc_entry<MODE, KIND>(a.val, nz, k, x0, x1, x2, s0, s1, s2);
+        } else {
+            for (int k = beg + lane; k < end; k += U * G) {
+                int j[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) j[u] = k + u * G < end ? a.col[k + u * G] : -1;
+                float xv[U][3];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int jj = j[u] >= 0 ? j[u] : 0;
+                    if (j[u] >= 0) {
+                        xv[u][0] = a.x[3 * jj];
+                        xv[u][1] = a.x[3 * jj + 1];
+                        xv[u][2] = a.x[3 * jj + 2];
+                    } else {
+                        xv[u][0] = xv[u][1] = xv[u][2] = 0.f;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (j[u] >= 0)
+                        acc_entry<MODE, KIND>(a.val, nz, k + u * G, xv[u][0], xv[u][1], xv[u][2], s0, s1, s2);
+            }
         }
     }
     s0 = group_sum_f<G>(s0);
@@ -167,24 +180,23 @@ static void launch_mp_g(int op, const RowArgsMP &a, hipStream_t s) {
     int nb = ceil_div(static_cast<int64_t>(a.nrows) * G, MBLOCK);
     if (nb == 0) return;
     if (a.xcd_chunks) nb = (nb + 7) / 8 * 8;
-    const bool pair = a.pair != 0;
+    AMG_REQUIRE(a.trip == 1 || a.trip == 2 || a.trip == 4, AMG_EINVAL,
+                "mixed row kernel: 1, 2 or 4 entries per trip");
+#define AMG_MP_CASE(OPC)                                                             \
+    case OPC:                                                                        \
+        if (a.trip == 4) k_row_mp<MODE, G, OPC, KIND, 4><<<nb, MBLOCK, 0, s>>>(a);   \
+        else if (a.trip == 2) k_row_mp<MODE, G, OPC, KIND, 2><<<nb, MBLOCK, 0, s>>>(a); \
+        else k_row_mp<MODE, G, OPC, KIND, 1><<<nb, MBLOCK, 0, s>>>(a);               \
+        break;
     switch (op) {
-        case OP_SPMV: k_row_mp<MODE, G, OP_SPMV, KIND, false><<<nb, MBLOCK, 0, s>>>(a); break;
-        case OP_SPMV_ADD: k_row_mp<MODE, G, OP_SPMV_ADD, KIND, false><<<nb, MBLOCK, 0, s>>>(a); break;
-        case OP_RESID:
-            if (pair) k_row_mp<MODE, G, OP_RESID, KIND, true><<<nb, MBLOCK, 0, s>>>(a);
-            else k_row_mp<MODE, G, OP_RESID, KIND, false><<<nb, MBLOCK, 0, s>>>(a);
-            break;
-        case OP_JACOBI:
-            if (pair) k_row_mp<MODE, G, OP_JACOBI, KIND, true><<<nb, MBLOCK, 0, s>>>(a);
-            else k_row_mp<MODE, G, OP_JACOBI, KIND, false><<<nb, MBLOCK, 0, s>>>(a);
-            break;
-        case OP_GS:
-            if (pair) k_row_mp<MODE, G, OP_GS, KIND, true><<<nb, MBLOCK, 0, s>>>(a);
-            else k_row_mp<MODE, G, OP_GS, KIND, false><<<nb, MBLOCK, 0, s>>>(a);
-            break;
+        case OP_SPMV: k_row_mp<MODE, G, OP_SPMV, KIND, 1><<<nb, MBLOCK, 0, s>>>(a); break;
+        case OP_SPMV_ADD: k_row_mp<MODE, G, OP_SPMV_ADD, KIND, 1><<<nb, MBLOCK, 0, s>>>(a); break;
+        AMG_MP_CASE(OP_RESID)
+        AMG_MP_CASE(OP_JACOBI)
+        AMG_MP_CASE(OP_GS)
         default: throw Error(AMG_EINVAL, "mixed row kernel: unsupported operation");
     }
+#undef AMG_MP_CASE
     AMG_CHECK_LAUNCH();
 }
 

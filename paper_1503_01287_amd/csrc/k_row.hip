@@ -59,7 +59,11 @@ __device__ __forceinline__ void acc_entry(const double *val, int64_t nz, int k, 
     }
 }
 
-template <int MODE, int G, int OP, bool PAIR>
+// U entries per lane and loop trip (1, 2 or 4): the trip's column indices,
+// then its gathers of x and its values, are in flight together; entries past
+// the row's end are skipped. Each lane still adds its entries in increasing
+// order, so the result does not depend on U.
+template <int MODE, int G, int OP, int U>
 __global__ void __launch_bounds__(BLOCK) k_row(const RowArgs a) {
     // Workgroups are dispatched round-robin over the 8 XCDs, so consecutive
     // row blocks run on different XCDs at the same time and the whole chip
@@ -103,23 +107,33 @@ __global__ void __launch_bounds__(BLOCK) k_row(const RowArgs a) {
     if (active) {
         const int beg = a.rowptr[g], end = a.rowptr[g + 1];
         const int64_t nz = a.nnz;
-        int k = beg + lane;
-        if constexpr (PAIR) {
-            // two entries per trip: both column indices, then both gathers
-            // of x, in flight together (long rows on few lanes; the tuner
-            // picks this form only where it measures faster)
-            for (; k + G < end; k += 2 * G) {
-                const int j = a.col[k], jb = a.col[k + G];
+        if constexpr (U == 1) {
+            for (int k = beg + lane; k < end; k += G) {
+                const int j = a.col[k];
                 const double x0 = a.x[3 * j], x1 = a.x[3 * j + 1], x2 = a.x[3 * j + 2];
-                const double y0 = a.x[3 * jb], y1 = a.x[3 * jb + 1], y2 = a.x[3 * jb + 2];
                 acc_entry<MODE>(a.val, nz, k, x0, x1, x2, s0, s1, s2);
-                acc_entry<MODE>(a.val, nz, k + G, y0, y1, y2, s0, s1, s2);
             }
-        }
-        for (; k < end; k += G) {
-            const int j = a.col[k];
-            const double x0 = a.x[3 * j], x1 = a.x[3 * j + 1], x2 = a.x[3 * j + 2];
-            acc_entry<MODE>(a.val, nz, k, x0, x1, x2, s0, s1, s2);
+        } else {
+            for (int k = beg + lane; k < end; k += U * G) {
+                int j[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) j[u] = k + u * G < end ? a.col[k + u * G] : -1;
+                double xv[U][3];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int jj = j[u] >= 0 ? j[u] : 0;
+                    if (j[u] >= 0) {
+                        xv[u][0] = a.x[3 * jj];
+                        xv[u][1] = a.x[3 * jj + 1];
+                        xv[u][2] = a.x[3 * jj + 2];
+                    } else {
+                        xv[u][0] = xv[u][1] = xv[u][2] = 0.0;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (j[u] >= 0) acc_entry<MODE>(a.val, nz, k + u * G, xv[u][0], xv[u][1], xv[u][2], s0, s1, s2);
+            }
         }
     }
     s0 = group_sum<G>(s0);
@@ -172,15 +186,16 @@ static void launch_row_g(RowOp op, const RowArgs &a, hipStream_t s) {
         AMG_REQUIRE(op != OP_SPMV_DOT, AMG_EINVAL, "row kernel: XCD chunks with block partials");
         nb = (nb + 7) / 8 * 8;
     }
-    const bool pair = a.pair != 0;
+    AMG_REQUIRE(a.trip == 1 || a.trip == 2 || a.trip == 4, AMG_EINVAL, "row kernel: 1, 2 or 4 entries per trip");
 #define AMG_ROW_CASE(OPC)                                                       \
     case OPC:                                                                   \
-        if (pair) k_row<MODE, G, OPC, true><<<nb, BLOCK, 0, s>>>(a);             \
-        else k_row<MODE, G, OPC, false><<<nb, BLOCK, 0, s>>>(a);                 \
+        if (a.trip == 4) k_row<MODE, G, OPC, 4><<<nb, BLOCK, 0, s>>>(a);         \
+        else if (a.trip == 2) k_row<MODE, G, OPC, 2><<<nb, BLOCK, 0, s>>>(a);    \
+        else k_row<MODE, G, OPC, 1><<<nb, BLOCK, 0, s>>>(a);                     \
         break;
     switch (op) {
         AMG_ROW_CASE(OP_SPMV)
-        case OP_SPMV_ADD: k_row<MODE, G, OP_SPMV_ADD, false><<<nb, BLOCK, 0, s>>>(a); break;
+        case OP_SPMV_ADD: k_row<MODE, G, OP_SPMV_ADD, 1><<<nb, BLOCK, 0, s>>>(a); break;
         AMG_ROW_CASE(OP_RESID)
         AMG_ROW_CASE(OP_JACOBI)
         AMG_ROW_CASE(OP_GS)

@@ -40,7 +40,7 @@ struct RowArgs {
     double *partial = nullptr;      // per-block partial sums (SPMV_DOT)
     double *zero_out = nullptr;     // if set: zero_out_i = 0 for every row i written
     int xcd_chunks = 0;             // 1: each XCD takes one contiguous eighth of the rows
-    int pair = 0;                   // 1: two entries per lane and loop trip (not OP_SPMV_ADD)
+    int trip = 1;                   // entries per lane and loop trip: 1, 2 or 4 (OP_SPMV_ADD: 1)
 };
 
 // mode: 3 = 3x3 blocks; 1 = scalar entries applied to 3-component vectors.

@@ -28,7 +28,7 @@ struct RowArgsMP {
     float omega = 1.f;
     float *zero_out = nullptr;
     int xcd_chunks = 0;             // as RowArgs::xcd_chunks
-    int pair = 0;                   // OP_RESID / OP_JACOBI / OP_GS: two entries per lane and trip
+    int trip = 1;                   // OP_RESID / OP_JACOBI / OP_GS: 1, 2 or 4 entries per lane and trip
 };
 
 // Same operations as launch_row (OP_SPMV, OP_SPMV_ADD, OP_RESID, OP_JACOBI,

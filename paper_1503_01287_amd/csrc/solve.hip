@@ -77,7 +77,7 @@ void apply_level(amg_ctx *h, int l, const double *x, double *y) {
     a.x = x;
     a.y = y;
     ProfScope ps(h, tag("spmv", l), row_bytes(L.A, L.A.nnz, L.n) + 3.0 * L.n * 16.0);
-    a.pair = L.pair;
+    a.trip = L.trip;
     launch_row(L.mode, OP_SPMV, L.G, a, h->stream);
 }
 
@@ -88,7 +88,7 @@ static void residual(amg_ctx *h, int l, const double *b, const double *x, double
     a.b = b;
     a.y = r;
     ProfScope ps(h, tag("resid", l), row_bytes(L.A, L.A.nnz, L.n) + 3.0 * L.n * 24.0);
-    a.pair = L.pair;
+    a.trip = L.trip;
     launch_row(L.mode, OP_RESID, L.G, a, h->stream);
 }
 
@@ -116,7 +116,7 @@ static void jacobi_step(amg_ctx *h, int l, const double *b, double *x, bool zero
     a.omega = om;
     {
         ProfScope ps(h, tag("jacobi", l), row_bytes(L.A, L.A.nnz, L.n) + 3.0 * L.n * 24.0 + nb * 8.0 * L.n);
-        a.pair = L.pair;
+        a.trip = L.trip;
         launch_row(L.mode, OP_JACOBI, L.G, a, h->stream);
     }
     launch_copy(x, L.t.p, 3 * static_cast<int64_t>(L.n), h->stream);
@@ -156,7 +156,7 @@ static void gs_sweep(amg_ctx *h, int l, const double *b, double *x, bool forward
         const double bytes = static_cast<double>(L.colour_nnz[c]) * (L.Ag.np * 8.0 + 4.0) +
                              a.nrows * (8.0 + 24.0 + 48.0 + nb * 8.0);
         ProfScope ps(h, tag("gs", l), bytes);
-        a.pair = L.pairg;
+        a.trip = L.tripg;
         launch_row(L.mode, OP_GS, L.Gg, a, h->stream);
     }
 }
@@ -355,7 +355,7 @@ static void spmv_dot(amg_ctx *h, const double *p, double *q, int post) {
     a.partial = h->partial.p;
     {
         ProfScope ps(h, "spmv.L0", row_bytes(L.A, L.A.nnz, L.n) + 3.0 * L.n * 16.0);
-        a.pair = L.pair;
+        a.trip = L.trip;
         launch_row(L.mode, OP_SPMV_DOT, L.G, a, h->stream);
     }
     launch_reduce(h->partial.p, row_blocks(L.n, L.G), h->sc.p, SC_PQ, h->stream, post);

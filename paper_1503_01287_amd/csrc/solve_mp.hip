@@ -44,25 +44,28 @@ static void autotune_mp(amg_ctx *h, Level &L) {
         }
         return best_ms;
     };
-    // (lanes, loop form) pairs; the heuristic lane count in the plain form is
-    // kept unless another choice is at least 5% faster
-    auto pick = [&](int G0, int &pair_out, auto &&time_of) {
-        int bestG = G0, bestP = 0;
-        float best = time_of(G0, 0);
-        for (int P = 0; P < 2; ++P)
+    // (lanes G, entries per lane and trip T); the heuristic lane count with
+    // T = 1 is kept unless another choice is at least 5% faster. T > 1 is
+    // tried only where a trip of the row group (G T entries) is at most twice
+    // the mean row.
+    const double avg_row = static_cast<double>(L.A.nnz) / std::max(1, L.n);
+    auto pick = [&](int G0, int &trip_out, auto &&time_of) {
+        int bestG = G0, bestT = 1;
+        float best = time_of(G0, 1);
+        for (int T : {1, 2, 4})
             for (int G : cand) {
-                if (G == G0 && P == 0) continue;
-                const float ms = time_of(G, P);
+                if ((G == G0 && T == 1) || (T > 1 && G * T > 2.0 * avg_row)) continue;
+                const float ms = time_of(G, T);
                 if (ms < 0.95f * best) {
                     best = ms;
                     bestG = G;
-                    bestP = P;
+                    bestT = T;
                 }
             }
-        pair_out = bestP;
+        trip_out = bestT;
         return bestG;
     };
-    M.G = pick(M.G, M.pair, [&](int G, int P) {
+    M.G = pick(M.G, M.trip, [&](int G, int P) {
         RowArgsMP a;
         a.nrows = L.n;
         a.rowptr = L.A.rowptr.p;
@@ -73,7 +76,7 @@ static void autotune_mp(amg_ctx *h, Level &L) {
         a.x = M.x.p;
         a.b = M.b.p;
         a.y = M.r.p;
-        a.pair = P;
+        a.trip = P;
         return time_it([&] { launch_row_mp(L.mode, OP_RESID, G, M.kind, a, s); });
     });
     if (!L.cptr.empty()) {
@@ -97,13 +100,13 @@ static void autotune_mp(amg_ctx *h, Level &L) {
                     a.dinv = M.dinv.p;
                     a.dinv_n = L.n;
                     a.xcd_chunks = xcd;
-                    a.pair = P;
+                    a.trip = P;
                     launch_row_mp(L.mode, OP_GS, G, M.kind, a, s);
                 }
             });
         };
-        M.Gg = pick(M.Gg, M.pairg, [&](int G, int P) { return sweep_time(G, P, 0); });
-        M.xcd = sweep_time(M.Gg, M.pairg, 1) < 0.95f * sweep_time(M.Gg, M.pairg, 0) ? 1 : 0;
+        M.Gg = pick(M.Gg, M.tripg, [&](int G, int P) { return sweep_time(G, P, 0); });
+        M.xcd = sweep_time(M.Gg, M.tripg, 1) < 0.95f * sweep_time(M.Gg, M.tripg, 0) ? 1 : 0;
     }
     AMG_HIP(hipEventDestroy(e0));
     AMG_HIP(hipEventDestroy(e1));
@@ -221,7 +224,7 @@ static RowArgsMP args_natural(Level &L) {
     a.val = L.mp.aval();
     a.rscale = L.mp.scale.p;
     a.nnz = L.A.nnz;
-    a.pair = L.mp.pair;
+    a.trip = L.mp.trip;
     return a;
 }
 
@@ -291,7 +294,7 @@ static void gs_mp(amg_ctx *h, int l, const float *b, float *x, bool forward, boo
         a.dinv = L.mp.dinv.p;
         a.dinv_n = L.n;
         a.xcd_chunks = L.mp.xcd;
-        a.pair = L.mp.pairg;
+        a.trip = L.mp.tripg;
         ProfScope ps(h, tag("gs", l), mat_bytes(L, L.colour_nnz[c], a.nrows) + a.nrows * (4.0 + 12.0 + 24.0 + nb * 4.0));
         launch_row_mp(L.mode, OP_GS, L.mp.Gg, L.mp.kind, a, h->stream);
     }

@@ -128,7 +128,7 @@ static void a_resid(amg_ctx *h, int l, const double *b, const double *x, double 
     a.b = b;
     a.y = r;
     ProfScope ps(h, tag("resid", l), static_cast<double>(L.A.nnz) * 76.0 + L.n * 76.0);
-    a.pair = L.pair;
+    a.trip = L.trip;
     launch_row(3, OP_RESID, L.G, a, h->stream);
 }
 static void a_resid(amg_ctx *h, int l, const float *b, const float *x, float *r, int nrows) {
@@ -143,7 +143,7 @@ static void a_resid(amg_ctx *h, int l, const float *b, const float *x, float *r,
     a.x = x;
     a.b = b;
     a.y = r;
-    a.pair = L.mp.pair;
+    a.trip = L.mp.trip;
     ProfScope ps(h, tag("resid", l), static_cast<double>(L.A.nnz) * (9.0 * L.mp.vbytes() + 4.0) + L.n * 40.0);
     launch_row_mp(3, OP_RESID, L.mp.G, L.mp.kind, a, h->stream);
 }
@@ -242,7 +242,7 @@ void saddle_apply(amg_ctx *h, int l, const double *x, double *y) {
         a.x = x;
         a.y = y;
         ProfScope ps(h, tag("spmv", l), static_cast<double>(L.A.nnz) * 76.0 + L.n * 52.0);
-        a.pair = L.pair;
+        a.trip = L.trip;
         launch_row(3, OP_SPMV, L.G, a, h->stream);
     }
     BlkArgs bt = blk(L.Bt);

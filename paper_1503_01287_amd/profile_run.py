@@ -73,8 +73,8 @@ def main() -> int:
         s = AMGSolver(sysm, krylov=kry, precision=prec, fuse_coarse=bool(args.fuse_coarse), **kw)
         rhs = sysm.rhs
     i0 = s.level_info(0)
-    print(f"level 0: lanes {i0.lanes_A}/{i0.lanes_gs}, two entries per trip {i0.pair_A}/{i0.pair_gs}, "
-          f"per-XCD rows {i0.gs_xcd}, FP64 kernels lanes {i0.lanes64_A} two entries {i0.pair64_A}",
+    print(f"level 0: lanes {i0.lanes_A}/{i0.lanes_gs}, entries per trip {i0.trip_A}/{i0.trip_gs}, "
+          f"per-XCD rows {i0.gs_xcd}, FP64 kernels lanes {i0.lanes64_A} entries per trip {i0.trip64_A}",
           file=sys.stderr, flush=True)
     b = torch.from_numpy(rhs).to(dev)
     x = torch.zeros_like(b)

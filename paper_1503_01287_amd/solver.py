@@ -209,10 +209,11 @@ class AMGSolver:
                 "amg_get_level_matrix")
         return rowptr, col[:nnz], val[: nnz * width].reshape(nnz, width)
 
-    def set_launch_shape(self, level: int, kernels: str, lanes: int, pair: bool = False, xcd: bool = False) -> None:
+    def set_launch_shape(self, level: int, kernels: str, lanes: int, trip: int = 1, xcd: bool = False) -> None:
         """Override the tuner's launch shape of one kernel class on a level:
-        kernels 'natural', 'sweep', 'natural_rp' or 'sweep_rp'."""
-        C.check(C.lib().amg_set_launch_shape(self.h, level, C.SHAPE[kernels], int(lanes), 1 if pair else 0,
+        kernels 'natural', 'sweep', 'natural_rp' or 'sweep_rp'; lanes per
+        row; entries per lane and loop trip (1, 2 or 4)."""
+        C.check(C.lib().amg_set_launch_shape(self.h, level, C.SHAPE[kernels], int(lanes), int(trip),
                                              1 if xcd else 0), "amg_set_launch_shape")
 
     def set_level_omega(self, omega) -> None:

@@ -24,7 +24,7 @@ def test_every_traffic_summary_is_complete():
     lines = _traffic_lines()
     assert lines
     for name, kv in lines:
-        for key in ("kernel", "class", "precision", "lanes", "pair", "xcd", "bytes_per_launch"):
+        for key in ("kernel", "class", "precision", "lanes", "trip", "xcd", "bytes_per_launch"):
             assert key in kv, (name, key)
         assert int(kv["bytes_per_launch"]) > 0
         assert name.split("_")[0] in bench.WORKLOADS, name
@@ -33,12 +33,12 @@ def test_every_traffic_summary_is_complete():
 def test_traffic_only_for_the_measured_launch_shape():
     for name, kv in _traffic_lines():
         wl = name.split("_")[0]
-        args = (wl, kv["precision"], kv["class"], int(kv["lanes"]), int(kv["pair"]), int(kv["xcd"]))
+        args = (wl, kv["precision"], kv["class"], int(kv["lanes"]), int(kv["trip"]), int(kv["xcd"]))
         assert bench.measured_traffic(*args) == int(kv["bytes_per_launch"])
         other_lanes = 64 if int(kv["lanes"]) != 64 else 32
-        assert bench.measured_traffic(wl, kv["precision"], kv["class"], other_lanes, int(kv["pair"]),
+        assert bench.measured_traffic(wl, kv["precision"], kv["class"], other_lanes, int(kv["trip"]),
                                       int(kv["xcd"])) is None
-        assert bench.measured_traffic(wl, kv["precision"], kv["class"], int(kv["lanes"]), 1 - int(kv["pair"]),
+        assert bench.measured_traffic(wl, kv["precision"], kv["class"], int(kv["lanes"]), 2 if int(kv["trip"]) == 1 else 1,
                                       int(kv["xcd"])) is None
-        assert bench.measured_traffic(wl, "FP64", kv["class"], int(kv["lanes"]), int(kv["pair"]),
+        assert bench.measured_traffic(wl, "FP64", kv["class"], int(kv["lanes"]), int(kv["trip"]),
                                       int(kv["xcd"])) is None

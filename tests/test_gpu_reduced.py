@@ -99,7 +99,7 @@ def test_reduced_two_cycles_and_w_cycle(case, cycles, nu):
     s.close()
 
 
-SHAPES = list(itertools.product([4, 8, 16, 32, 64], [False, True]))
+SHAPES = list(itertools.product([4, 8, 16, 32, 64], [1, 2, 4]))
 
 
 @pytest.mark.parametrize("precision", ["FP64", "MIXED"])
@@ -121,17 +121,17 @@ def test_every_launch_shape_matches_oracle(case, precision):
         tol = RP_TOL
     Ax = o.A.matvec(r).ravel()
     levels = [l for l in range(s.num_levels) if not s.level_info(l).is_coarsest]
-    for (lanes, pair), xcd in itertools.product(SHAPES, [False, True]):
+    for (lanes, trip), xcd in itertools.product(SHAPES, [False, True]):
         for l in levels:
-            s.set_launch_shape(l, nat, lanes, pair)
-            s.set_launch_shape(l, swp, lanes, pair, xcd)
+            s.set_launch_shape(l, nat, lanes, trip)
+            s.set_launch_shape(l, swp, lanes, trip, xcd)
             if precision != "FP64":
-                s.set_launch_shape(l, "natural", lanes, pair)
+                s.set_launch_shape(l, "natural", lanes, trip)
         got = _gpu_cycle(s, r)
-        assert relmax(got, want) < tol, (name, precision, lanes, pair, xcd, relmax(got, want))
+        assert relmax(got, want) < tol, (name, precision, lanes, trip, xcd, relmax(got, want))
         y = torch.zeros(hsys.dofs, dtype=torch.float64, device=DEV)
         s.apply(0, dev(r), y)
-        assert relmax(host(y), Ax) < 1e-14, (name, lanes, pair)
+        assert relmax(host(y), Ax) < 1e-14, (name, lanes, trip)
     s.close()
 
 
@@ -142,5 +142,28 @@ def test_launch_shape_rejects_bad_arguments():
         with pytest.raises(amg.AmgError):
             s.set_launch_shape(*args)
     with pytest.raises(amg.AmgError):
-        s.set_launch_shape(0, "natural", 16, False, True)   # xcd is for colour sweeps
+        s.set_launch_shape(0, "natural", 16, 1, True)   # xcd is for colour sweeps
+    for trip in (0, 3, 8):
+        with pytest.raises(amg.AmgError):
+            s.set_launch_shape(0, "sweep", 16, trip)
+    s.close()
+
+
+@pytest.mark.parametrize("precision", ["FP64", "MIXED"])
+def test_entries_per_trip_do_not_change_the_bits(case, precision):
+    """A lane adds its entries in the same order for 1, 2 or 4 entries per
+    trip, so at fixed lanes the cycle is the same bit for bit."""
+    name, hsys, o, h = case
+    s = amg.AMGSolver(hsys, smoother="GS-1-1", krylov="FCG", precision=precision, autotune=False)
+    nat, swp = ("natural", "sweep") if precision == "FP64" else ("natural_rp", "sweep_rp")
+    r = np.random.default_rng(34).standard_normal(hsys.dofs)
+    levels = [l for l in range(s.num_levels) if not s.level_info(l).is_coarsest]
+    for lanes in (8, 32):
+        outs = []
+        for trip in (1, 2, 4):
+            for l in levels:
+                s.set_launch_shape(l, nat, lanes, trip)
+                s.set_launch_shape(l, swp, lanes, trip)
+            outs.append(_gpu_cycle(s, r))
+        assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2]), (name, precision, lanes)
     s.close()
