@@ -270,6 +270,7 @@ struct amg_ctx {
     bool mixed = false;
     amgp2::DevBuf<float> tail_dense32;     // FP32 cycles
     amgp2::DevBuf<uint16_t> tail_dense16;  // FP32/BF16 cycles (coarse levels in BF16)
+    int tail_ld = 0;                       // row stride of those copies (multiple of 8, zeros past tail_m)
     // setup-time tuners: a buffer larger than the 256 MB Infinity Cache,
     // written before every timed repetition (released after setup)
     amgp2::DevBuf<double> tune_flush;

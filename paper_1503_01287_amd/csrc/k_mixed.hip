@@ -383,51 +383,123 @@ void launch_diag_solve_mp(int mode, int nrows, const int *rowid, const float *di
     AMG_CHECK_LAUNCH();
 }
 
-// y = M x for a dense m x m operator applied to nc components, one
-// wavefront per row, four row loads in flight per lane; M in FP32 or BF16,
-// FP32 accumulation
-template <int KIND>
-__global__ void __launch_bounds__(MBLOCK) k_dense_gemv_mp(const void *M, int m, int nc, const float *X, float *Y) {
+// y = M x for a dense m x m operator applied to nc (1 or 3) components, M in
+// FP32 or BF16 with rows ld values apart (ld a multiple of 8, the values
+// past m zero), FP32 accumulation, one wavefront per row. A lane reads 16
+// bytes of the row (4 FP32 or 8 BF16 values) and the matching entries of x
+// as 16-byte loads per chunk, two chunks per trip.
+template <int KIND, int NC>
+__global__ void __launch_bounds__(MBLOCK) k_dense_gemv_mp(const void *M, int m, int ld, const float *X, float *Y) {
+    constexpr int CV = KIND == VAL_F32 ? 4 : 8;  // values per 16-byte chunk
+    constexpr int VB = KIND == VAL_F32 ? 4 : 2;  // bytes per value
     const int row = blockIdx.x * (MBLOCK / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (row >= m) return;
-    float a0 = 0.f, a1 = 0.f, a2 = 0.f;
-    const int64_t base = static_cast<int64_t>(row) * m;
-    int j = lane;
-    for (; j + 192 < m; j += 256) {
-        const float v0 = ld<KIND>(M, base + j), v1 = ld<KIND>(M, base + j + 64), v2 = ld<KIND>(M, base + j + 128),
-                    v3 = ld<KIND>(M, base + j + 192);
-        if (nc == 1) {
-            a0 += v0 * X[j] + v1 * X[j + 64] + v2 * X[j + 128] + v3 * X[j + 192];
-        } else {
-            a0 += v0 * X[3 * j] + v1 * X[3 * (j + 64)] + v2 * X[3 * (j + 128)] + v3 * X[3 * (j + 192)];
-            a1 += v0 * X[3 * j + 1] + v1 * X[3 * (j + 64) + 1] + v2 * X[3 * (j + 128) + 1] + v3 * X[3 * (j + 192) + 1];
-            a2 += v0 * X[3 * j + 2] + v1 * X[3 * (j + 64) + 2] + v2 * X[3 * (j + 128) + 2] + v3 * X[3 * (j + 192) + 2];
+    const unsigned char *Mr = static_cast<const unsigned char *>(M) + static_cast<int64_t>(row) * ld * VB;
+    float acc[NC];
+#pragma unroll
+    for (int q = 0; q < NC; ++q) acc[q] = 0.f;
+    for (int c0 = CV * lane; c0 < m; c0 += 2 * 64 * CV) {
+        uint4 w[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int c = c0 + h * 64 * CV;
+            if (c < m) w[h] = *reinterpret_cast<const uint4 *>(Mr + static_cast<int64_t>(c) * VB);
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int c = c0 + h * 64 * CV;
+            if (c >= m) continue;
+            const uint32_t u[4] = {w[h].x, w[h].y, w[h].z, w[h].w};
+            float v[CV];
+#pragma unroll
+            for (int e = 0; e < CV; ++e) {
+                if constexpr (KIND == VAL_F32)
+                    v[e] = __uint_as_float(u[e]);
+                else
+                    v[e] = __uint_as_float((e & 1) ? (u[e >> 1] & 0xffff0000u) : (u[e >> 1] << 16));
+            }
+            if (c + CV <= m) {
+                float xv[CV * NC];
+                const float4 *xp = reinterpret_cast<const float4 *>(X + static_cast<int64_t>(c) * NC);
+#pragma unroll
+                for (int t = 0; t < CV * NC / 4; ++t) {
+                    const float4 f = xp[t];
+                    xv[4 * t] = f.x;
+                    xv[4 * t + 1] = f.y;
+                    xv[4 * t + 2] = f.z;
+                    xv[4 * t + 3] = f.w;
+                }
+#pragma unroll
+                for (int e = 0; e < CV; ++e)
+#pragma unroll
+                    for (int q = 0; q < NC; ++q) acc[q] += v[e] * xv[e * NC + q];
+            } else {
+#pragma unroll
+                for (int e = 0; e < CV; ++e)
+                    if (c + e < m)
+#pragma unroll
+                        for (int q = 0; q < NC; ++q) acc[q] += v[e] * X[static_cast<int64_t>(c + e) * NC + q];
+            }
         }
     }
-    for (; j < m; j += 64) {
-        const float v = ld<KIND>(M, base + j);
-        a0 += v * X[j * nc];
-        if (nc > 1) {
-            a1 += v * X[j * nc + 1];
-            a2 += v * X[j * nc + 2];
-        }
+#pragma unroll
+    for (int q = 0; q < NC; ++q) acc[q] = group_sum_f<64>(acc[q]);
+    if (lane < NC) {
+        float out = acc[0];
+#pragma unroll
+        for (int q = 1; q < NC; ++q)
+            if (lane == q) out = acc[q];
+        Y[static_cast<int64_t>(row) * NC + lane] = out;
     }
-    a0 = group_sum_f<64>(a0);
-    a1 = group_sum_f<64>(a1);
-    a2 = group_sum_f<64>(a2);
-    if (lane < nc) Y[row * nc + lane] = lane == 0 ? a0 : (lane == 1 ? a1 : a2);
 }
 
-void launch_dense_gemv_f32(const float *M, int m, int nc, const float *X, float *Y, hipStream_t s) {
+template <int KIND>
+static void launch_dense_mp(const void *M, int m, int ld, int nc, const float *X, float *Y, hipStream_t s) {
     if (m <= 0) return;
-    k_dense_gemv_mp<VAL_F32><<<ceil_div(m, MBLOCK / 64), MBLOCK, 0, s>>>(M, m, nc, X, Y);
+    AMG_REQUIRE(nc == 1 || nc == 3, AMG_EINVAL, "dense GEMV: 1 or 3 components");
+    AMG_REQUIRE(ld >= m && ld % 8 == 0, AMG_EINVAL, "dense GEMV: row stride must be >= m and a multiple of 8");
+    AMG_REQUIRE((reinterpret_cast<uintptr_t>(M) | reinterpret_cast<uintptr_t>(X)) % 16 == 0, AMG_EINVAL,
+                "dense GEMV: operator and input must be 16-byte aligned");
+    if (nc == 1)
+        k_dense_gemv_mp<KIND, 1><<<ceil_div(m, MBLOCK / 64), MBLOCK, 0, s>>>(M, m, ld, X, Y);
+    else
+        k_dense_gemv_mp<KIND, 3><<<ceil_div(m, MBLOCK / 64), MBLOCK, 0, s>>>(M, m, ld, X, Y);
     AMG_CHECK_LAUNCH();
 }
 
-void launch_dense_gemv_bf16(const uint16_t *M, int m, int nc, const float *X, float *Y, hipStream_t s) {
-    if (m <= 0) return;
-    k_dense_gemv_mp<VAL_BF16><<<ceil_div(m, MBLOCK / 64), MBLOCK, 0, s>>>(M, m, nc, X, Y);
+void launch_dense_gemv_f32(const float *M, int m, int ld, int nc, const float *X, float *Y, hipStream_t s) {
+    launch_dense_mp<VAL_F32>(M, m, ld, nc, X, Y, s);
+}
+
+void launch_dense_gemv_bf16(const uint16_t *M, int m, int ld, int nc, const float *X, float *Y, hipStream_t s) {
+    launch_dense_mp<VAL_BF16>(M, m, ld, nc, X, Y, s);
+}
+
+// dst (rows ld apart, zero past m) = rounded copy of the FP64 m x m src
+template <int KIND>
+__global__ void k_dense_copy(const double *src, int m, int ld, void *dst) {
+    const int64_t n = static_cast<int64_t>(m) * ld;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * MBLOCK + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * MBLOCK) {
+        const int64_t r = i / ld;
+        const int c = static_cast<int>(i - r * ld);
+        const double v = c < m ? src[r * m + c] : 0.0;
+        if constexpr (KIND == VAL_F32)
+            static_cast<float *>(dst)[i] = static_cast<float>(v);
+        else
+            static_cast<uint16_t *>(dst)[i] = f64_to_bf16(v);
+    }
+}
+
+void launch_dense_copy(const double *src, int m, int ld, int kind, void *dst, hipStream_t s) {
+    const int64_t n = static_cast<int64_t>(m) * ld;
+    if (n <= 0) return;
+    const int nb = static_cast<int>(std::min<int64_t>(4096, (n + MBLOCK - 1) / MBLOCK));
+    if (kind == VAL_F32)
+        k_dense_copy<VAL_F32><<<nb, MBLOCK, 0, s>>>(src, m, ld, dst);
+    else
+        k_dense_copy<VAL_BF16><<<nb, MBLOCK, 0, s>>>(src, m, ld, dst);
     AMG_CHECK_LAUNCH();
 }
 

@@ -297,10 +297,10 @@ void launch_mdiag_solve(int mode, int kind, int K, int nrows, const int *rowid, 
 }
 
 // ---------------------------------------------------------------- dense coarse end
-// Y = M X with NC columns: one wavefront per row of M, lane j walks columns
-// j, j + 64, ... and keeps NC partial sums
+// Y = M X with NC columns (M's rows ld values apart): one wavefront per row
+// of M, lane j walks columns j, j + 64, ... and keeps NC partial sums
 template <int MK, int NC>
-__global__ void __launch_bounds__(TB) k_mdense(const void *M, int m, const void *Xv, void *Yv) {
+__global__ void __launch_bounds__(TB) k_mdense(const void *M, int m, int ld, const void *Xv, void *Yv) {
     using T = vec_t<MK>;
     const int row = blockIdx.x * (TB / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -309,7 +309,7 @@ __global__ void __launch_bounds__(TB) k_mdense(const void *M, int m, const void 
     T acc[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[c] = T(0);
-    const int64_t base = static_cast<int64_t>(row) * m;
+    const int64_t base = static_cast<int64_t>(row) * ld;
     for (int j = lane; j < m; j += 64) {
         const T v = ldv<MK>(M, base + j);
 #pragma unroll
@@ -324,25 +324,26 @@ __global__ void __launch_bounds__(TB) k_mdense(const void *M, int m, const void 
 }
 
 template <int MK>
-static void mdense_nc(const void *M, int m, int nc, const void *X, void *Y, hipStream_t s) {
+static void mdense_nc(const void *M, int m, int ld, int nc, const void *X, void *Y, hipStream_t s) {
     const int nb = ceil_div(m, TB / 64);
     switch (nc) {
-        case 2: k_mdense<MK, 2><<<nb, TB, 0, s>>>(M, m, X, Y); break;
-        case 4: k_mdense<MK, 4><<<nb, TB, 0, s>>>(M, m, X, Y); break;
-        case 6: k_mdense<MK, 6><<<nb, TB, 0, s>>>(M, m, X, Y); break;
-        case 8: k_mdense<MK, 8><<<nb, TB, 0, s>>>(M, m, X, Y); break;
-        case 12: k_mdense<MK, 12><<<nb, TB, 0, s>>>(M, m, X, Y); break;
-        case 24: k_mdense<MK, 24><<<nb, TB, 0, s>>>(M, m, X, Y); break;
+        case 2: k_mdense<MK, 2><<<nb, TB, 0, s>>>(M, m, ld, X, Y); break;
+        case 4: k_mdense<MK, 4><<<nb, TB, 0, s>>>(M, m, ld, X, Y); break;
+        case 6: k_mdense<MK, 6><<<nb, TB, 0, s>>>(M, m, ld, X, Y); break;
+        case 8: k_mdense<MK, 8><<<nb, TB, 0, s>>>(M, m, ld, X, Y); break;
+        case 12: k_mdense<MK, 12><<<nb, TB, 0, s>>>(M, m, ld, X, Y); break;
+        case 24: k_mdense<MK, 24><<<nb, TB, 0, s>>>(M, m, ld, X, Y); break;
         default: throw Error(AMG_EINVAL, "multi dense kernel: unsupported column count");
     }
 }
 
-void launch_mdense(int mkind, const void *M, int m, int nc, const void *X, void *Y, hipStream_t s) {
+void launch_mdense(int mkind, const void *M, int m, int ld, int nc, const void *X, void *Y, hipStream_t s) {
     if (m <= 0) return;
+    AMG_REQUIRE(ld >= m, AMG_EINVAL, "multi dense kernel: row stride below m");
     switch (mkind) {
-        case MK_F64: mdense_nc<MK_F64>(M, m, nc, X, Y, s); break;
-        case MK_F32: mdense_nc<MK_F32>(M, m, nc, X, Y, s); break;
-        default: mdense_nc<MK_BF16>(M, m, nc, X, Y, s); break;
+        case MK_F64: mdense_nc<MK_F64>(M, m, ld, nc, X, Y, s); break;
+        case MK_F32: mdense_nc<MK_F32>(M, m, ld, nc, X, Y, s); break;
+        default: mdense_nc<MK_BF16>(M, m, ld, nc, X, Y, s); break;
     }
     AMG_CHECK_LAUNCH();
 }

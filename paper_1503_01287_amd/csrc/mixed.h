@@ -53,9 +53,14 @@ void launch_jacobi_zero_mp(int mode, int64_t nn, const float *dinv, const float 
                            hipStream_t s);
 void launch_diag_solve_mp(int mode, int nrows, const int *rowid, const float *dinv, int64_t n, const float *b,
                           float *x, hipStream_t s);
-// Y = M X with an FP32 dense matrix (m x m), nc components
-void launch_dense_gemv_f32(const float *M, int m, int nc, const float *X, float *Y, hipStream_t s);
-void launch_dense_gemv_bf16(const uint16_t *M, int m, int nc, const float *X, float *Y, hipStream_t s);
+// Y = M X with an FP32 or BF16 dense matrix (m x m, rows ld values apart, ld
+// a multiple of 8 with zeros past m), nc = 1 or 3 components; M and X
+// 16-byte aligned
+void launch_dense_gemv_f32(const float *M, int m, int ld, int nc, const float *X, float *Y, hipStream_t s);
+void launch_dense_gemv_bf16(const uint16_t *M, int m, int ld, int nc, const float *X, float *Y, hipStream_t s);
+// dst = FP32 (kind VAL_F32) or BF16 (VAL_BF16, rounded once, ties to even)
+// copy of the FP64 m x m src with rows ld values apart and zeros past m
+void launch_dense_copy(const double *src, int m, int ld, int kind, void *dst, hipStream_t s);
 // BF16 (round to nearest even) copy of FP64 values
 void launch_to_bf16(const double *src, uint16_t *dst, int64_t n, hipStream_t s);
 

@@ -43,8 +43,9 @@ void launch_mjacobi_zero(int mode, int kind, int K, int64_t nn, const void *dinv
 // x_i = D_i^{-1} b_i for the nodes rowid[0..nrows) (first colour of a sweep from zero)
 void launch_mdiag_solve(int mode, int kind, int K, int nrows, const int *rowid, const void *dinv, int64_t n,
                         const void *b, void *x, hipStream_t s);
-// Y (m x nc) = M (m x m) X (m x nc): mkind 0 FP64 M with double X, Y; 1 FP32 M, 2 BF16 M with float X, Y
-void launch_mdense(int mkind, const void *M, int m, int nc, const void *X, void *Y, hipStream_t s);
+// Y (m x nc) = M (m x m, rows ld values apart) X (m x nc): mkind 0 FP64 M with
+// double X, Y; 1 FP32 M, 2 BF16 M with float X, Y
+void launch_mdense(int mkind, const void *M, int m, int ld, int nc, const void *X, void *Y, hipStream_t s);
 // Krylov vector work on interleaved FP64 blocks of n_dof x K values
 // out[p * K + r] = <a_p, b_p> over right-hand side r, for the np pairs (np <= 3), fixed order
 int mdot_blocks(int64_t nd);

@@ -201,14 +201,17 @@ void refresh_tail_f32(amg_ctx *h) {
     h->tail_dense16.release();
     if (h->mixed && h->tail_m > 0) {
         // the coarse end below the finest level, in the coarse levels' value
-        // type: BF16 in the FP32/BF16 cycle, FP32 in the FP32 cycle
-        const int64_t mm = static_cast<int64_t>(h->tail_m) * h->tail_m;
+        // type: BF16 in the FP32/BF16 cycle, FP32 in the FP32 cycle; rows
+        // padded to a multiple of 8 values for the GEMV's 16-byte loads
+        const int m = h->tail_m;
+        h->tail_ld = (m + 7) / 8 * 8;
+        const int64_t mm = static_cast<int64_t>(m) * h->tail_ld;
         if (h->prm.precision == AMG_PREC_MIXED) {
             h->tail_dense16.alloc(mm);
-            launch_to_bf16(h->tail_dense.p, h->tail_dense16.p, mm, h->stream);
+            launch_dense_copy(h->tail_dense.p, m, h->tail_ld, VAL_BF16, h->tail_dense16.p, h->stream);
         } else {
             h->tail_dense32.alloc(mm);
-            launch_to_f32(h->tail_dense.p, h->tail_dense32.p, mm, h->stream);
+            launch_dense_copy(h->tail_dense.p, m, h->tail_ld, VAL_F32, h->tail_dense32.p, h->stream);
         }
     }
     AMG_HIP(hipStreamSynchronize(h->stream));
@@ -336,9 +339,9 @@ static void cycle_mp(amg_ctx *h, int l, const float *b, float *x, bool x_zero, b
         const bool bf = h->tail_dense16.n > 0;
         ProfScope ps(h, "dense_tail", static_cast<double>(h->tail_m) * h->tail_m * (bf ? 2.0 : 4.0));
         if (bf)
-            launch_dense_gemv_bf16(h->tail_dense16.p, h->tail_m, h->tail_nc, b, x, h->stream);
+            launch_dense_gemv_bf16(h->tail_dense16.p, h->tail_m, h->tail_ld, h->tail_nc, b, x, h->stream);
         else
-            launch_dense_gemv_f32(h->tail_dense32.p, h->tail_m, h->tail_nc, b, x, h->stream);
+            launch_dense_gemv_f32(h->tail_dense32.p, h->tail_m, h->tail_ld, h->tail_nc, b, x, h->stream);
         return;
     }
     smooth_mp(h, l, b, x, true, x_zero, filled);

@@ -129,11 +129,11 @@ struct MCycle {
         const int64_t n = len(l);
         if (RP) {
             launch_to_f64(reinterpret_cast<const float *>(b), W.lv[l].b.p, n, h->stream);
-            launch_mdense(MK_F64, h->coarse_inv.p, h->coarse_m, h->coarse_nc * K, W.lv[l].b.p, W.lv[l].x.p,
-                          h->stream);
+            launch_mdense(MK_F64, h->coarse_inv.p, h->coarse_m, h->coarse_m, h->coarse_nc * K, W.lv[l].b.p,
+                          W.lv[l].x.p, h->stream);
             launch_to_f32(W.lv[l].x.p, reinterpret_cast<float *>(x), n, h->stream);
         } else {
-            launch_mdense(MK_F64, h->coarse_inv.p, h->coarse_m, h->coarse_nc * K, b, x, h->stream);
+            launch_mdense(MK_F64, h->coarse_inv.p, h->coarse_m, h->coarse_m, h->coarse_nc * K, b, x, h->stream);
         }
     }
 
@@ -146,11 +146,11 @@ struct MCycle {
         if (l == h->dense_start && x_zero) {
             const int nc = h->tail_nc * K;
             if (!RP)
-                launch_mdense(MK_F64, h->tail_dense.p, h->tail_m, nc, b, x, h->stream);
+                launch_mdense(MK_F64, h->tail_dense.p, h->tail_m, h->tail_m, nc, b, x, h->stream);
             else if (h->tail_dense16.n)
-                launch_mdense(MK_BF16, h->tail_dense16.p, h->tail_m, nc, b, x, h->stream);
+                launch_mdense(MK_BF16, h->tail_dense16.p, h->tail_m, h->tail_ld, nc, b, x, h->stream);
             else
-                launch_mdense(MK_F32, h->tail_dense32.p, h->tail_m, nc, b, x, h->stream);
+                launch_mdense(MK_F32, h->tail_dense32.p, h->tail_m, h->tail_ld, nc, b, x, h->stream);
             return;
         }
         smooth(l, b, x, true, x_zero);
