@@ -116,17 +116,26 @@ struct SchurHier {
 // patches' inverted local matrices.
 struct VankaData {
     int npatch = 0, max_nodes = 0;
+    double inv_bytes = 0.0;        // the patch inverses, read once per sweep
     DevBuf<int> pptr, pnode, order;
     DevBuf<int64_t> moff;
     DevBuf<double> inv;
     std::vector<int> cptr;
-    // two-kernel path for large patches (chosen at setup): residual buffer,
-    // per-colour prefix of the apply's 64-row tiles, tiles per colour
-    bool split = false;
-    DevBuf<int64_t> roff;
+    // sweep form (chosen at setup): 0 one kernel per colour; 1 residuals,
+    // then corrections over 64-row tiles; 2 residuals, partial corrections
+    // over 64-row x cc-column tiles, then their sum
+    int path = 0;
+    DevBuf<int64_t> roff;          // residual buffer offsets (paths 1, 2)
     DevBuf<double> rbuf;
-    DevBuf<int> tpre;
-    std::vector<int> ntiles;
+    DevBuf<int> tpre;              // per-colour prefix of the 64-row tiles
+    std::vector<int> ntiles;       // 64-row tiles per colour
+    int cc = 256;                  // path 2: columns per chunk
+    DevBuf<int> upre;              // path 2: per-colour prefix of the 2-D tiles
+    std::vector<int> nunits;       // path 2: 2-D tiles per colour
+    DevBuf<int64_t> poff;          // path 2: partial buffer offsets
+    DevBuf<double> pbuf;
+    DevBuf<int> rpre;              // path 2: per-colour prefix of the residual's 16-row units
+    std::vector<int> nrunits;      // path 2: residual units per colour
 };
 
 struct Level {

@@ -830,6 +830,7 @@ void setup_vanka(amg_ctx *h, int l) {
     V.order.upload(order, s);
     V.moff.upload(moff, s);
     V.inv.alloc(static_cast<size_t>(std::max<int64_t>(1, total)));
+    V.inv_bytes = 8.0 * static_cast<double>(total);
     const VankaView view = vanka_view(L);
     launch_vanka_assemble(view, V.max_nodes, s);
     DevBuf<int> flag(1);
@@ -857,9 +858,55 @@ void setup_vanka(amg_ctx *h, int l) {
     V.roff.upload(roff, s);
     V.tpre.upload(tpre, s);
     V.rbuf.alloc(static_cast<size_t>(std::max<int64_t>(1, rtot)));
-    // the faster path for this level's patch sizes (timed on a scratch
-    // vector pair; the fused kernel unless the split is 3% faster)
-    V.split = 3 * V.max_nodes + 1 > 256;
+    {
+        // the tiled path's residual: 16 node rows (and the pressure row) per unit
+        std::vector<int> rpre(std::max(1, np), 0);
+        V.nrunits.assign(nc, 0);
+        for (int c = 0; c < nc; ++c) {
+            int t = 0;
+            for (int k = V.cptr[c]; k < V.cptr[c + 1]; ++k) {
+                rpre[k] = t;
+                const int i = order[k];
+                t += (bp.rowptr[i + 1] - bp.rowptr[i] + 1 + 15) / 16;
+            }
+            V.nrunits[c] = t;
+        }
+        V.rpre.upload(rpre, s);
+    }
+    // three-kernel path: 64-row x cc-column tiles of the inverses and their
+    // partial sums, colour by colour, for a chunk width cc
+    auto tile_tables = [&](int cc) {
+        std::vector<int> upre(std::max(1, np), 0);
+        std::vector<int64_t> poff(std::max(1, np), 0);
+        V.nunits.assign(nc, 0);
+        int64_t ptot = 0;
+        for (int i = 0; i < np; ++i) {
+            const int64_t m = 3 * static_cast<int64_t>(bp.rowptr[i + 1] - bp.rowptr[i]) + 1;
+            poff[i] = ptot;
+            ptot += ((m + cc - 1) / cc) * m;
+        }
+        for (int c = 0; c < nc; ++c) {
+            int t = 0;
+            for (int k = V.cptr[c]; k < V.cptr[c + 1]; ++k) {
+                upre[k] = t;
+                const int i = order[k];
+                const int m = 3 * (bp.rowptr[i + 1] - bp.rowptr[i]) + 1;
+                t += ((m + 63) / 64) * ((m + cc - 1) / cc);
+            }
+            V.nunits[c] = t;
+        }
+        V.cc = cc;
+        V.upre.upload(upre, s);
+        V.poff.upload(poff, s);
+        if (static_cast<int64_t>(V.pbuf.n) < ptot) V.pbuf.alloc(static_cast<size_t>(std::max<int64_t>(1, ptot)));
+    };
+    // the sweep form for this level's patch sizes: one kernel per colour for
+    // patches up to 256 unknowns, the tiled form above, unless (with the
+    // tuners on) another form or chunk width is 3% faster on a scratch
+    // vector pair
+    const bool large = 3 * V.max_nodes + 1 > 256;
+    V.path = large ? 2 : 0;
+    tile_tables(256);
     if (h->prm.autotune) {
         const int64_t nv = L.vlen();
         DevBuf<double> xs(nv), bs(nv);
@@ -868,22 +915,27 @@ void setup_vanka(amg_ctx *h, int l) {
         hipEvent_t e0, e1;
         AMG_HIP(hipEventCreate(&e0));
         AMG_HIP(hipEventCreate(&e1));
-        auto sweep = [&](bool split) {
+        auto sweep = [&](int path) {
             for (int c = 0; c < nc; ++c) {
                 const int cnt = V.cptr[c + 1] - V.cptr[c];
-                if (split)
+                if (path == 2)
+                    launch_vanka_colour_tiled(view, V.order.p + V.cptr[c], V.tpre.p + V.cptr[c],
+                                              V.upre.p + V.cptr[c], V.rpre.p + V.cptr[c], cnt, V.ntiles[c],
+                                              V.nunits[c], V.nrunits[c], V.cc, V.roff.p, V.rbuf.p, V.poff.p,
+                                              V.pbuf.p, bs.p, xs.p, 0.5, s);
+                else if (path == 1)
                     launch_vanka_colour_split(view, V.order.p + V.cptr[c], V.tpre.p + V.cptr[c], cnt, V.ntiles[c],
                                               V.max_nodes, V.roff.p, V.rbuf.p, bs.p, xs.p, 0.5, s);
                 else
                     launch_vanka_colour(view, V.order.p + V.cptr[c], cnt, V.max_nodes, bs.p, xs.p, 0.5, s);
             }
         };
-        auto time_of = [&](bool split) {
-            sweep(split);
+        auto time_of = [&](int path) {
+            sweep(path);
             float best = 1e30f;
             for (int r = 0; r < 3; ++r) {
                 AMG_HIP(hipEventRecord(e0, s));
-                sweep(split);
+                sweep(path);
                 AMG_HIP(hipEventRecord(e1, s));
                 AMG_HIP(hipEventSynchronize(e1));
                 float ms = 0.f;
@@ -892,8 +944,28 @@ void setup_vanka(amg_ctx *h, int l) {
             }
             return best;
         };
-        const float tf = time_of(false), ts = time_of(true);
-        V.split = ts < 0.97f * tf;
+        float best = time_of(V.path);
+        int best_path = V.path, best_cc = 256;
+        for (const int path : {0, 1}) {
+            if (path == V.path) continue;
+            const float t = time_of(path);
+            if (t < 0.97f * best) {
+                best = t;
+                best_path = path;
+            }
+        }
+        for (const int cc : {128, 256, 512}) {
+            if (cc == 256 && V.path == 2) continue;
+            tile_tables(cc);
+            const float t = time_of(2);
+            if (t < 0.97f * best) {
+                best = t;
+                best_path = 2;
+                best_cc = cc;
+            }
+        }
+        tile_tables(best_cc);
+        V.path = best_path;
         AMG_HIP(hipEventDestroy(e0));
         AMG_HIP(hipEventDestroy(e1));
     }

@@ -348,6 +348,160 @@ __global__ void __launch_bounds__(VB) k_vanka_apply(const VankaView v, const int
     else x[3 * static_cast<int64_t>(v.n) + i] += d;
 }
 
+// Partial corrections of one colour's large patches, tiled in two dimensions
+// so that a colour of few, large patches still fills the GPU: workgroup u
+// takes 64 rows (row tile rt) and a chunk of cc columns (chunk q) of one
+// patch's inverse (upre: prefix of the units ceil(m_i / 64) ceil(m_i / cc)
+// over the colour's patches, rt fastest); its 4 wavefronts take a quarter of
+// the chunk each, eight column loads in flight per lane, and their sums are
+// added in a fixed order into pbuf (chunk q of patch i at pbuf + poff[i] +
+// q m_i).
+__global__ void __launch_bounds__(VB) k_vanka_apply_part(const VankaView v, const int *order, const int *upre,
+                                                         int count, int cc, const int64_t *roff, const double *rbuf,
+                                                         const int64_t *poff, double *pbuf) {
+    __shared__ double part[4][64];
+    int lo = 0, hi = count - 1;
+    const int u = blockIdx.x;
+    while (lo < hi) {  // last patch whose first unit is <= u
+        const int mid = (lo + hi + 1) >> 1;
+        if (upre[mid] <= u) lo = mid;
+        else hi = mid - 1;
+    }
+    const int i = order[lo];
+    const int m = 3 * (v.pptr[i + 1] - v.pptr[i]) + 1;
+    const int RT = (m + 63) / 64;
+    const int local = u - upre[lo];
+    const int rt = local % RT, q = local / RT;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int a = rt * 64 + lane;
+    const int c0 = q * cc, c1 = min(m, c0 + cc);
+    const int w0 = c0 + wave * (c1 - c0) / 4, w1 = c0 + (wave + 1) * (c1 - c0) / 4;
+    const double *r = rbuf + roff[i];
+    const double *M = v.inv + v.moff[i];
+    double acc = 0.0;
+    if (a < m) {
+        int c = w0;
+        for (; c + 8 <= w1; c += 8) {
+            double mv[8], rv[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                mv[t] = M[static_cast<int64_t>(c + t) * m + a];
+                rv[t] = r[c + t];
+            }
+#pragma unroll
+            for (int t = 0; t < 8; ++t) acc += mv[t] * rv[t];
+        }
+        for (; c < w1; ++c) acc += M[static_cast<int64_t>(c) * m + a] * r[c];
+    }
+    part[wave][lane] = acc;
+    __syncthreads();
+    if (wave == 0 && a < m) pbuf[poff[i] + static_cast<int64_t>(q) * m + a] = ((part[0][lane] + part[1][lane]) +
+                                                                               part[2][lane]) + part[3][lane];
+}
+
+// x_P += omega (sum of the chunks' partials, in chunk order) over 64-row tiles
+// (tpre: prefix of ceil(m_i / 64) over the colour's patches)
+__global__ void __launch_bounds__(64) k_vanka_reduce(const VankaView v, const int *order, const int *tpre,
+                                                     int count, int cc, const int64_t *poff, const double *pbuf,
+                                                     double *x, double omega) {
+    int lo = 0, hi = count - 1;
+    const int t = blockIdx.x;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tpre[mid] <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    const int i = order[lo];
+    const int p0 = v.pptr[i], nn = v.pptr[i + 1] - p0;
+    const int m = 3 * nn + 1;
+    const int a = (t - tpre[lo]) * 64 + threadIdx.x;
+    if (a >= m) return;
+    const int kc = (m + cc - 1) / cc;
+    double sum = 0.0;
+    for (int q = 0; q < kc; ++q) sum += pbuf[poff[i] + static_cast<int64_t>(q) * m + a];
+    const double d = omega * sum;
+    if (a < 3 * nn) x[3 * static_cast<int64_t>(v.pnode[p0 + a / 3]) + a % 3] += d;
+    else x[3 * static_cast<int64_t>(v.n) + i] += d;
+}
+
+// Residuals of one colour's patches, 16 node rows (16 lanes each) per
+// workgroup so that a colour of few, large patches still spreads over the
+// GPU (rpre: prefix of ceil((n_P + 1) / 16) over the colour's patches; the
+// last row of a patch is its pressure row); the same arithmetic as
+// k_vanka_resid.
+constexpr int VRW = VB / VG;  // node rows per workgroup
+__global__ void __launch_bounds__(VB) k_vanka_resid_rows(const VankaView v, const int *order, const int *rpre,
+                                                         int count, const int64_t *roff, double *rbuf,
+                                                         const double *b, const double *x) {
+    int lo = 0, hi = count - 1;
+    const int t = blockIdx.x;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (rpre[mid] <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    const int i = order[lo];
+    const int p0 = v.pptr[i], nn = v.pptr[i + 1] - p0;
+    const int grp = threadIdx.x / VG, lane = threadIdx.x % VG;
+    const int k = (t - rpre[lo]) * VRW + grp;
+    if (k > nn) return;  // whole 16-lane groups leave together
+    double *r = rbuf + roff[i];
+    const int64_t nu = 3 * static_cast<int64_t>(v.n);
+    const double *p = x + nu;
+    if (k < nn) {
+        const int u = v.pnode[p0 + k];
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        for (int q = v.arow[u] + lane; q < v.arow[u + 1]; q += VG) {
+            const int j = v.acol[q];
+            const double x0 = x[3 * j], x1 = x[3 * j + 1], x2 = x[3 * j + 2];
+            s0 += v.aval[0 * v.annz + q] * x0 + v.aval[1 * v.annz + q] * x1 + v.aval[2 * v.annz + q] * x2;
+            s1 += v.aval[3 * v.annz + q] * x0 + v.aval[4 * v.annz + q] * x1 + v.aval[5 * v.annz + q] * x2;
+            s2 += v.aval[6 * v.annz + q] * x0 + v.aval[7 * v.annz + q] * x1 + v.aval[8 * v.annz + q] * x2;
+        }
+        for (int q = v.btrow[u] + lane; q < v.btrow[u + 1]; q += VG) {
+            const double pq = p[v.btcol[q]];
+            s0 += v.btval[q] * pq;
+            s1 += v.btval[v.btnnz + q] * pq;
+            s2 += v.btval[2 * v.btnnz + q] * pq;
+        }
+#pragma unroll
+        for (int o = VG / 2; o > 0; o >>= 1) {
+            s0 += __shfl_xor(s0, o, VG);
+            s1 += __shfl_xor(s1, o, VG);
+            s2 += __shfl_xor(s2, o, VG);
+        }
+        if (lane == 0) {
+            r[3 * k] = b[3 * u] - s0;
+            r[3 * k + 1] = b[3 * u + 1] - s1;
+            r[3 * k + 2] = b[3 * u + 2] - s2;
+        }
+    } else {
+        double s = 0.0;
+        for (int q = v.brow[i] + lane; q < v.brow[i + 1]; q += VG) {
+            const int j = v.bcol[q];
+            s += v.bval[q] * x[3 * j] + v.bval[v.bnnz + q] * x[3 * j + 1] + v.bval[2 * v.bnnz + q] * x[3 * j + 2];
+        }
+        if (v.crow)
+            for (int q = v.crow[i] + lane; q < v.crow[i + 1]; q += VG) s -= v.cval[q] * p[v.ccol[q]];
+#pragma unroll
+        for (int o = VG / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, VG);
+        if (lane == 0) r[3 * nn] = b[nu + i] - s;
+    }
+}
+
+void launch_vanka_colour_tiled(const VankaView &v, const int *order, const int *tpre, const int *upre,
+                               const int *rpre, int count, int ntiles, int nunits, int nrunits, int cc,
+                               const int64_t *roff, double *rbuf, const int64_t *poff, double *pbuf, const double *b,
+                               double *x, double omega, hipStream_t s) {
+    if (count <= 0) return;
+    k_vanka_resid_rows<<<nrunits, VB, 0, s>>>(v, order, rpre, count, roff, rbuf, b, x);
+    AMG_CHECK_LAUNCH();
+    k_vanka_apply_part<<<nunits, VB, 0, s>>>(v, order, upre, count, cc, roff, rbuf, poff, pbuf);
+    AMG_CHECK_LAUNCH();
+    k_vanka_reduce<<<ntiles, 64, 0, s>>>(v, order, tpre, count, cc, poff, pbuf, x, omega);
+    AMG_CHECK_LAUNCH();
+}
+
 void launch_vanka_colour_split(const VankaView &v, const int *order, const int *tpre, int count, int ntiles,
                                int max_nodes, const int64_t *roff, double *rbuf, const double *b, double *x,
                                double omega, hipStream_t s) {

@@ -417,11 +417,15 @@ static void vanka_step(amg_ctx *h, int l, const double *b, double *x) {
     Level &L = h->lv[l];
     const VankaView v = vanka_view(L);
     const int nc = static_cast<int>(L.vanka.cptr.size()) - 1;
-    ProfScope ps(h, tag("vanka", l), 0.0);
+    ProfScope ps(h, tag("vanka", l), L.vanka.inv_bytes);  // algorithmic: the patch inverses
     VankaData &V = L.vanka;
     for (int c = 0; c < nc; ++c) {
         const int cnt = V.cptr[c + 1] - V.cptr[c];
-        if (V.split)
+        if (V.path == 2)
+            launch_vanka_colour_tiled(v, V.order.p + V.cptr[c], V.tpre.p + V.cptr[c], V.upre.p + V.cptr[c],
+                                      V.rpre.p + V.cptr[c], cnt, V.ntiles[c], V.nunits[c], V.nrunits[c], V.cc,
+                                      V.roff.p, V.rbuf.p, V.poff.p, V.pbuf.p, b, x, h->prm.vanka_omega, h->stream);
+        else if (V.path == 1)
             launch_vanka_colour_split(v, V.order.p + V.cptr[c], V.tpre.p + V.cptr[c], cnt, V.ntiles[c], V.max_nodes,
                                       V.roff.p, V.rbuf.p, b, x, h->prm.vanka_omega, h->stream);
         else
