@@ -338,10 +338,9 @@ void autotune_level(amg_ctx *h, Level &L) {
     };
     // Candidates (lanes G, entries per lane and trip T) are timed against
     // the heuristic's choice (T = 1), which another candidate replaces only
-    // when it is at least 5% faster (10% for T > 1, whose gain on some rows
-    // sits near 5%): timing noise then does not flip the choice from one
-    // setup to the next. T > 1 is tried only where a trip of the row group
-    // (G T entries) is at most twice the mean row.
+    // when it is at least 5% faster: timing noise then does not flip the
+    // choice from one setup to the next. T > 1 is tried only where a trip of
+    // the row group (G T entries) is at most twice the mean row.
     const double avg_row = static_cast<double>(L.A.nnz) / std::max(1, L.n);
     auto pick = [&](int G0, auto &&time_of) {
         int bestG = G0, bestT = 1;
@@ -350,7 +349,7 @@ void autotune_level(amg_ctx *h, Level &L) {
             for (int G : cand) {
                 if ((G == G0 && T == 1) || (T > 1 && G * T > 2.0 * avg_row)) continue;
                 const float ms = time_of(G, T);
-                if (ms < (T > 1 ? 0.90f : 0.95f) * best) {
+                if (ms < 0.95f * best) {
                     best = ms;
                     bestG = G;
                     bestT = T;
