@@ -313,13 +313,14 @@ def measure(name: str, sysm, rhs, steps: int, warmup: int, tol: float, precision
     x = torch.zeros_like(bs[0])
     model = learned.DampingModel.load() if os.path.exists(learned.MODEL_PATH) else None
 
-    def make(prec: str, krylov: str, with_model: bool, omega=None):
+    def make(prec: str, krylov: str, with_model: bool, omega=None, smoother=None):
+        sm = smoother or wl["smoother"]
         if batch:
-            return amg.BatchedSolver(sysm.systems, smoother=wl["smoother"], precision=prec)
+            return amg.BatchedSolver(sysm.systems, smoother=sm, precision=prec)
         kw = {"omega_model": model} if (with_model and model is not None) else {}
         if omega is not None:
             kw["level_omega"] = [omega]
-        return amg.AMGSolver(sysm, smoother=wl["smoother"], krylov=krylov, precision=prec, **kw)
+        return amg.AMGSolver(sysm, smoother=sm, krylov=krylov, precision=prec, **kw)
 
     def solve_once(solver, t, k=-1):
         x.zero_()
@@ -343,7 +344,7 @@ def measure(name: str, sysm, rhs, steps: int, warmup: int, tol: float, precision
     def run_variant(v: dict) -> dict:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        solver = make(v["precision"], v["krylov"], v.get("model", False), v.get("omega"))
+        solver = make(v["precision"], v["krylov"], v.get("model", False), v.get("omega"), v.get("smoother"))
         torch.cuda.synchronize()
         setup_ms = (time.perf_counter() - t0) * 1e3
         levels = levels_of(solver)
@@ -359,7 +360,8 @@ def measure(name: str, sysm, rhs, steps: int, warmup: int, tol: float, precision
         if not all(r[0] for r in results):
             raise SystemExit(f"# {name} {v['label']}: solve did not converge: {results}")
         ms = elapsed * 1e3 / steps
-        out = dict(label=v["label"], precision=v["precision"], krylov=v["krylov"], setup_ms=round(setup_ms, 1),
+        out = dict(label=v["label"], smoother=v.get("smoother") or wl["smoother"], precision=v["precision"],
+                   krylov=v["krylov"], setup_ms=round(setup_ms, 1),
                    setup_phases_ms=phases,
                    ms_per_step=round(ms, 3), value=sysm.dofs * steps / elapsed, iterations=results[-1][1],
                    relres=results[-1][2], levels=levels, solution=x.clone(),
@@ -542,6 +544,10 @@ def variants_for(name: str, precision: str, profile: bool, extras: bool) -> list
         v.append(dict(label="fp64", precision="FP64", krylov=fp64_kry, reference=True))
     else:
         v[0]["reference"] = True
+    if name == "mixed-elasticity-24" and extras:
+        # the other two saddle smoothers of Section 3.3 on the same system (FP64)
+        v.append(dict(label="bs_fp64", smoother="BS-1-1", precision="FP64", krylov="FGMRES"))
+        v.append(dict(label="vanka_fp64", smoother="Vanka-1-1", precision="FP64", krylov="FGMRES"))
     return v
 
 
@@ -632,13 +638,17 @@ def main() -> int:
             print(f"# assembled {xn} in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
 
     precision = WORKLOADS[name].get("precision", args.precision) if args.precision != "FP64" else "FP64"
-    vs = variants_for(name, args.precision, not args.no_profile, False)
+    vs = variants_for(name, args.precision, not args.no_profile, extras and name == "mixed-elasticity-24")
     if not full:
         vs = [dict(v, reference=False) for v in vs[:1]]
     prim_all = measure(name, sysm, rhs, args.steps, args.warmup, args.tol, precision, not args.no_profile, vs)
     labels = list(prim_all["variants"])
     prim = prim_all["variants"][labels[0]]
-    comp = prim_all["variants"][labels[-1]] if len(labels) > 1 else None
+    comp = prim_all["variants"].get("fp64") if len(labels) > 1 else None
+    smoothers = {lab: {k: (float(f"{v:.6g}") if isinstance(v, float) else v) for k, v in r.items()
+                       if k in ("smoother", "precision", "krylov", "ms_per_step", "iterations", "relres", "setup_ms",
+                                "error_vs_fp64_reference")}
+                 for lab, r in prim_all["variants"].items() if lab in ("bs_fp64", "vanka_fp64")}
 
     others = None
     if extras:
@@ -706,6 +716,8 @@ def main() -> int:
         "cpu_baseline": cpu,
         "other_workloads": others,
     }
+    if smoothers:
+        out["other_saddle_smoothers"] = smoothers
     print(json.dumps(out))
     return 0
 

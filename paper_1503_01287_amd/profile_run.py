@@ -44,6 +44,10 @@ def main() -> int:
                     help="0: no assembled coarse-end maps (the 64-cavity batch's map assembly issues"
                          " some 10^5-10^6 small dispatches, which the counter profiler does not survive;"
                          " the finest-level kernels and operators are the same)")
+    ap.add_argument("--shape", action="append", default=[],
+                    help="LEVEL:KERNELS:LANES:TRIP[:XCD] fixes a launch shape after the setup (kernels natural,"
+                         " sweep, natural_rp or sweep_rp), so that the runs of the two counters time the same"
+                         " kernel whatever the tuner picked")
     args = ap.parse_args()
 
     import torch
@@ -72,6 +76,9 @@ def main() -> int:
         kry = "FGMRES" if saddle else ("PCG" if prec == "FP64" else "FCG")
         s = AMGSolver(sysm, krylov=kry, precision=prec, fuse_coarse=bool(args.fuse_coarse), **kw)
         rhs = sysm.rhs
+    for spec in args.shape:
+        f = spec.split(":")
+        s.set_launch_shape(int(f[0]), f[1], int(f[2]), int(f[3]), bool(int(f[4])) if len(f) > 4 else False)
     i0 = s.level_info(0)
     print(f"level 0: lanes {i0.lanes_A}/{i0.lanes_gs}, entries per trip {i0.trip_A}/{i0.trip_gs}, "
           f"per-XCD rows {i0.gs_xcd}, FP64 kernels lanes {i0.lanes64_A} entries per trip {i0.trip64_A}",

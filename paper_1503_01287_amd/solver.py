@@ -317,6 +317,11 @@ class BatchedSolver:
                                           q.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))), "amg_batch_offsets")
         return u, q
 
+    def set_launch_shape(self, level: int, kernels: str, lanes: int, trip: int = 1, xcd: bool = False) -> None:
+        """As AMGSolver.set_launch_shape, on a merged level of the batch."""
+        C.check(C.lib().amg_set_launch_shape(self.h, level, C.SHAPE[kernels], int(lanes), int(trip),
+                                             1 if xcd else 0), "amg_set_launch_shape")
+
     def precondition(self, r, z) -> None:
         """One preconditioner application in the merged layout."""
         C.check(C.lib().amg_precondition(self.h, _dev_ptr(r, self.n, "r"), _dev_ptr(z, self.n, "z"),
