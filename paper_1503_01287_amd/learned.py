@@ -155,6 +155,58 @@ def sweep_targets(system, rhs_list, omega_grid=OMEGA_GRID, rounds: int = 2, log=
     return feats, omega[:L].copy(), solves
 
 
+def evaluate(sizes, tol: float = 1e-8, log=None) -> list:
+    """Learned per-level weights against the paper's fixed 0.5 and against
+    the best single weight for every level (grid up to the smallest level
+    bound, fewest iterations, ties broken by time), on vector Laplacians
+    with Dirichlet data from a workload id of their own (not the training
+    one); JA-1-1, FP64 PCG and the FP32/BF16 cycle in FCG; warm solves."""
+    import time
+    import torch
+    import synth
+    from . import problems
+    from .solver import AMGSolver
+    model = DampingModel.load()
+    dev = torch.device("cuda:0")
+    rows = []
+
+    def timed(s, b, x):
+        x.zero_()
+        s.solve(b, x, tol=tol, maxit=500)
+        x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = s.solve(b, x, tol=tol, maxit=500)
+        torch.cuda.synchronize()
+        return r.iters if r.converged else -1, round((time.perf_counter() - t0) * 1e3, 2)
+
+    for n in sizes:
+        sysm = problems.laplace(n, workload=synth.LAPLACE_SMALL, i=7)
+        b = torch.from_numpy(sysm.rhs).to(dev)
+        x = torch.zeros_like(b)
+        row = {"n": n, "dofs": sysm.dofs}
+        for prec, kry in (("FP64", "PCG"), ("MIXED", "FCG")):
+            fixed = AMGSolver(sysm, smoother="JA-1-1-0.5", krylov=kry, precision=prec)
+            row[f"fixed_{prec}"] = timed(fixed, b, x)
+            top = min(fixed.level_info(l).omega_max for l in range(fixed.num_levels - 1))
+            best = None
+            for w in [round(0.30 + 0.05 * i, 2) for i in range(40) if 0.30 + 0.05 * i <= top + 1e-9]:
+                fixed.set_level_omega([w])
+                it, ms = timed(fixed, b, x)
+                if it > 0 and (best is None or (it, ms) < (best[0], best[1])):
+                    best = (it, ms, w)
+            row[f"best_single_{prec}"] = best
+            fixed.close()
+            lw = AMGSolver(sysm, smoother="JA-1-1-0.5", krylov=kry, precision=prec, omega_model=model)
+            row[f"learned_{prec}"] = timed(lw, b, x)
+            row["learned_weights"] = [round(lw.level_info(l).omega, 3) for l in range(lw.num_levels - 1)]
+            lw.close()
+        if log:
+            log(str(row))
+        rows.append(row)
+    return rows
+
+
 def main() -> None:
     """Generate the training set, train the network on the GPU, save it."""
     import argparse
@@ -172,10 +224,17 @@ def main() -> None:
     ap.add_argument("--lr", type=float, default=3e-3)
     ap.add_argument("--out", default=MODEL_PATH)
     ap.add_argument("--data-out", default=None, help="also write the training set (.npz)")
+    ap.add_argument("--evaluate", type=int, nargs="*", default=None,
+                    help="no training: compare the stored network with the fixed and the best single weight "
+                         "on Laplacians of these sizes")
     args = ap.parse_args()
 
     def log(m):
         print(m, file=sys.stderr, flush=True)
+
+    if args.evaluate is not None:
+        print(json.dumps(evaluate(args.evaluate, log=log)))
+        return
 
     sizes = sorted(set(synth.training_sizes(args.systems)))
     X, y = [], []
