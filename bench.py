@@ -638,7 +638,8 @@ def main() -> int:
             print(f"# assembled {xn} in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
 
     precision = WORKLOADS[name].get("precision", args.precision) if args.precision != "FP64" else "FP64"
-    vs = variants_for(name, args.precision, not args.no_profile, extras and name == "mixed-elasticity-24")
+    vs = variants_for(name, args.precision, not args.no_profile,
+                      full and not args.no_extras and name == "mixed-elasticity-24")
     if not full:
         vs = [dict(v, reference=False) for v in vs[:1]]
     prim_all = measure(name, sysm, rhs, args.steps, args.warmup, args.tol, precision, not args.no_profile, vs)
