@@ -354,21 +354,30 @@ int amg_get_level_colors(amg_handle h, int32_t level, int32_t *colors);
 #define AMG_SHAPE_SWEEP_RP 3
 int amg_set_launch_shape(amg_handle h, int32_t level, int32_t kernels, int32_t lanes, int32_t trip, int32_t xcd);
 
-/* ---- batches of independent saddle point systems ----------------------
- * Many solves of uneven size in one set of launches. Each system gets the
- * hierarchy amg_setup would build for it alone; the hierarchies are merged
- * level by level into one block-diagonal hierarchy (systems ordered by
- * decreasing depth, so those still coarsening on a level lead it and those
- * ending on it are solved by their explicit inverses), and every kernel of a
- * V-cycle serves the whole batch. The outer method is flexible GMRES with
- * per-system inner products, Hessenberg matrices and convergence tests.
- * Saddle point systems only (sGS or Braess-Sarazin smoother, FGMRES; any
- * precision mode).
+/* ---- batches of independent systems ------------------------------------
+ * Many solves of uneven size in one set of launches (addition X2). Each
+ * system gets the hierarchy amg_setup would build for it alone; the
+ * hierarchies are merged level by level into one block-diagonal hierarchy
+ * (systems ordered by decreasing depth, so those still coarsening on a level
+ * lead it and those ending on it are solved by their explicit inverses),
+ * and every kernel of a cycle serves the whole batch. Every system of a
+ * batch is a saddle point system, or every one is SPD:
+ *  - saddle point systems: flexible GMRES with per-system inner products,
+ *    Hessenberg matrices and convergence tests (sGS or Braess-Sarazin
+ *    smoother; any precision mode);
+ *  - SPD systems (n_pres = 0, one bs for all): preconditioned CG with
+ *    per-system step lengths, residual norms and convergence tests, in
+ *    lockstep (JA or GS smoother, V or W cycles; FP64 cycle, the coarse
+ *    levels run level by level: fuse_coarse and the reduced precisions
+ *    are single-system features). Errors: AMG_EINVAL for mixed kinds or bs,
+ *    another Krylov method or smoother; AMG_EUNSUPPORTED for a reduced
+ *    precision.
+ * Both take host or device arrays (amg_system::memory).
  */
 int amg_setup_batched(int32_t nsys, const amg_system *systems, const amg_params *params, amg_stream stream,
                       amg_handle *out);
 /* b, x: DEVICE arrays holding the systems one after another in the order
- * given to amg_setup_batched, each as [u (3 N_i); p (Np_i)]; x is the initial
+ * given to amg_setup_batched, each as [u (3 N_i); p (Np_i)] (SPD: u); x is the initial
  * guess on entry and the solution on return. results: HOST array of nsys
  * (per-system iterations, status, true relative residual; solve_ms is the
  * whole batch's). Returns the worst status. */

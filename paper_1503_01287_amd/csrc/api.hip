@@ -212,11 +212,25 @@ int amg_setup_batched(int32_t nsys, const amg_system *systems, const amg_params 
         *out = nullptr;
         AMG_REQUIRE(systems && params && nsys >= 1, AMG_EINVAL, "amg_setup_batched: need systems and params");
         const amg_params &p = *params;
-        check_params(p, true);
-        AMG_REQUIRE(p.krylov == AMG_KRYLOV_FGMRES, AMG_EINVAL, "amg_setup_batched: batches run FGMRES");
-        AMG_REQUIRE(p.smoother != AMG_SMOOTH_VANKA, AMG_EUNSUPPORTED,
-                    "amg_setup_batched: batches run the sGS or Braess-Sarazin smoother");
-        AMG_REQUIRE(!p.omega_model, AMG_EINVAL, "amg_setup_batched: omega_model is for JA on SPD systems");
+        // every system saddle (n_pres > 0) or every system SPD
+        const bool spd = systems[0].n_pres == 0;
+        for (int i = 1; i < nsys; ++i)
+            AMG_REQUIRE((systems[i].n_pres == 0) == spd, AMG_EINVAL,
+                        "amg_setup_batched: SPD and saddle point systems in one batch");
+        check_params(p, !spd);
+        if (spd) {
+            AMG_REQUIRE(p.smoother == AMG_SMOOTH_JA || p.smoother == AMG_SMOOTH_GS, AMG_EINVAL,
+                        "amg_setup_batched: SPD batches run the JA or GS smoother");
+            AMG_REQUIRE(p.krylov == AMG_KRYLOV_PCG, AMG_EINVAL, "amg_setup_batched: SPD batches run PCG");
+            AMG_REQUIRE(p.precision == AMG_PREC_FP64, AMG_EUNSUPPORTED,
+                        "amg_setup_batched: SPD batches run the FP64 cycle");
+            AMG_REQUIRE(p.gs_post != 2, AMG_EINVAL, "amg_setup_batched: PCG needs the symmetric cycle");
+        } else {
+            AMG_REQUIRE(p.krylov == AMG_KRYLOV_FGMRES, AMG_EINVAL, "amg_setup_batched: saddle batches run FGMRES");
+            AMG_REQUIRE(p.smoother != AMG_SMOOTH_VANKA, AMG_EUNSUPPORTED,
+                        "amg_setup_batched: batches run the sGS or Braess-Sarazin smoother");
+        }
+        AMG_REQUIRE(!p.omega_model, AMG_EINVAL, "amg_setup_batched: omega_model is for single SPD systems");
         std::vector<StagedSystem> staged;
         std::vector<amg_system> host_sys(systems, systems + nsys);
         for (int i = 0; i < nsys; ++i) {
@@ -234,7 +248,10 @@ int amg_setup_batched(int32_t nsys, const amg_system *systems, const amg_params 
         h->prm.n_level_omega = 0;
         h->stream = static_cast<hipStream_t>(stream);
         try {
-            build_batch(h, nsys, host_sys.data());
+            if (spd)
+                build_batch_spd(h, nsys, host_sys.data());
+            else
+                build_batch(h, nsys, host_sys.data());
         } catch (...) {
             delete h;
             throw;
@@ -253,7 +270,8 @@ int amg_solve_batched(amg_handle h, const double *b, double *x, double tol, int3
         h->stream = static_cast<hipStream_t>(stream);
         launch_seg_copy(b, h->b_b.p, h->b_in.view(), h->b_in.dst.p, h->stream);
         launch_seg_copy(x, h->b_x.p, h->b_in.view(), h->b_in.dst.p, h->stream);
-        const int st = solve_fgmres_batched(h, h->b_b.p, h->b_x.p, tol, maxit, results);
+        const int st = h->saddle ? solve_fgmres_batched(h, h->b_b.p, h->b_x.p, tol, maxit, results)
+                                 : solve_pcg_batched(h, h->b_b.p, h->b_x.p, tol, maxit, results);
         launch_seg_copy(h->b_x.p, x, h->b_out.view(), h->b_out.dst.p, h->stream);
         AMG_HIP(hipStreamSynchronize(h->stream));
         return st;

@@ -41,6 +41,9 @@ void launch_seg_dcgs2_update(double *V, int64_t ld, int j, double *h, int stride
                              hipStream_t s);
 // y = coef[seg] * x
 void launch_seg_scale(const double *x, double *y, const double *coef, const ChunkView &t, hipStream_t s);
+// y = a[seg] x + b[seg] y
+void launch_seg_axpby(const double *x, double *y, const double *a, const double *b, const ChunkView &t,
+                      hipStream_t s);
 // x += sum_{j < cnt[seg]} y[seg * kmax + j] Z_j
 void launch_seg_multi_add(const double *Z, int64_t ld, const double *y, int kmax, const int *cnt, double *x,
                           const ChunkView &t, hipStream_t s);

@@ -413,6 +413,253 @@ void build_batch(amg_ctx *h, int nsys, const amg_system *sys) {
     AMG_HIP(hipStreamSynchronize(s));
 }
 
+// ---------------------------------------------------------------- SPD batches
+// Batches of independent SPD systems: every system gets the hierarchy
+// amg_setup builds for it alone (FP64, no assembled coarse end); level l of
+// the merged hierarchy concatenates the level-l operators of the systems
+// that reach l, ordered by decreasing depth, so that the systems still
+// coarsening lead it (nA rows: smoothed, restricted, corrected) and those
+// ending on l follow (their explicit coarsest inverses, one segmented
+// product). Greedy first-fit colouring in index order colours a
+// block-diagonal graph as each block alone, so the merged colour lists
+// (the leading systems' rows of each colour, in system order) sweep every
+// system exactly as its own hierarchy would.
+void build_batch_spd(amg_ctx *h, int nsys, const amg_system *sys) {
+    hipStream_t s = h->stream;
+    const amg_params &p = h->prm;
+    std::vector<std::unique_ptr<amg_ctx>> inst(nsys);
+    std::vector<int> depth(nsys);
+    const int mode = sys[0].bs;
+    for (int i = 0; i < nsys; ++i) {
+        AMG_REQUIRE(sys[i].n_pres == 0, AMG_EINVAL, "amg_setup_batched: SPD and saddle point systems in one batch");
+        AMG_REQUIRE(sys[i].bs == mode, AMG_EINVAL, "amg_setup_batched: SPD systems of one batch share bs");
+        inst[i].reset(new amg_ctx());
+        inst[i]->prm = p;
+        inst[i]->prm.autotune = 0;
+        inst[i]->prm.omega_model = nullptr;
+        inst[i]->prm.precision = AMG_PREC_FP64;
+        inst[i]->prm.fuse_coarse = 0;  // each system's coarse levels are merged, not assembled
+        inst[i]->batch_member = true;
+        inst[i]->stream = s;
+        build_hierarchy(inst[i].get(), &sys[i]);
+        depth[i] = static_cast<int>(inst[i]->lv.size()) - 1;
+        for (const auto &kv : inst[i]->setup_stats) {
+            ProfStat &st = h->setup_stats[kv.first];
+            st.launches += kv.second.launches;
+            st.ms += kv.second.ms;
+            st.bytes += kv.second.bytes;
+        }
+    }
+    auto ph_merge = std::make_unique<SetupPhase>(h, "merge");
+    std::vector<int> order(nsys);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return depth[a] > depth[b]; });
+    const int maxd = depth[order[0]];
+    const int nb = mode == 3 ? 9 : 1;
+    std::vector<Level> merged(maxd + 1);
+    for (int l = 0; l <= maxd; ++l) {
+        std::vector<int> P;
+        for (int i : order)
+            if (depth[i] >= l) P.push_back(i);
+        Level &M = merged[l];
+        M.mode = mode;
+        const size_t np_ = P.size();
+        std::vector<int> noff(np_), nrow(np_);
+        for (size_t j = 0; j < np_; ++j) {
+            const Level &V = inst[P[j]]->lv[l];
+            noff[j] = M.n;
+            nrow[j] = V.n;
+            M.n += V.n;
+            M.n_lin += V.n_lin;
+            M.n_quad += V.n_quad;
+            M.nnz_pat_A += V.pattern_nnz_A();
+            if (depth[P[j]] > l) M.nA += V.n;
+        }
+        M.coarsest = M.nA == 0;
+        M.sys_noff = noff;
+        M.sys_n = nrow;
+        std::vector<const DMat *> pa;
+        for (int i : P) pa.push_back(&inst[i]->lv[l].A);
+        merge_mats(M.A, pa, nrow, noff, M.n, nb, s);
+        {
+            std::vector<const double *> dv;
+            std::vector<int64_t> ln;
+            for (size_t j = 0; j < np_; ++j) {
+                const Level &V = inst[P[j]]->lv[l];
+                dv.push_back(depth[P[j]] > l ? V.dinv.p : nullptr);
+                ln.push_back(V.n);
+            }
+            merge_planes(M.dinv, dv, ln, nb, s);
+        }
+        if (M.nA > 0) {
+            std::vector<const DMat *> pp, pr;
+            std::vector<int> rows_p, rows_r, cp, cr;
+            int n1 = 0;
+            for (size_t j = 0; j < np_; ++j) {
+                if (depth[P[j]] <= l) continue;
+                const Level &V = inst[P[j]]->lv[l];
+                const Level &W = inst[P[j]]->lv[l + 1];
+                pp.push_back(&V.P);
+                rows_p.push_back(V.n);
+                cp.push_back(n1);
+                pr.push_back(&V.R);
+                rows_r.push_back(W.n);
+                cr.push_back(noff[j]);
+                n1 += W.n;
+            }
+            merge_mats(M.P, pp, rows_p, cp, n1, 1, s);
+            merge_mats(M.R, pr, rows_r, cr, M.n, 1, s);
+            // Gauss-Seidel: the leading systems' rows of each colour, in system order
+            if (p.smoother == AMG_SMOOTH_GS) {
+                int ncol = 0;
+                for (size_t j = 0; j < np_; ++j)
+                    if (depth[P[j]] > l) ncol = std::max(ncol, static_cast<int>(inst[P[j]]->lv[l].cptr.size()) - 1);
+                const std::vector<int> arp = M.A.rowptr.download(s);
+                std::vector<int> rows;
+                M.cptr.assign(1, 0);
+                M.colour_nnz.assign(ncol, 0);
+                M.colour.assign(M.n, -1);
+                for (int c = 0; c < ncol; ++c) {
+                    for (size_t j = 0; j < np_; ++j) {
+                        if (depth[P[j]] <= l) continue;
+                        const Level &V = inst[P[j]]->lv[l];
+                        for (int i = 0; i < V.n; ++i)
+                            if (V.colour[i] == c) {
+                                const int g = noff[j] + i;
+                                rows.push_back(g);
+                                M.colour[g] = c;
+                                M.colour_nnz[c] += arp[g + 1] - arp[g];
+                            }
+                    }
+                    M.cptr.push_back(static_cast<int>(rows.size()));
+                }
+                std::vector<int> grp(rows.size() + 1, 0);
+                for (size_t g = 0; g < rows.size(); ++g) grp[g + 1] = grp[g] + arp[rows[g] + 1] - arp[rows[g]];
+                M.Ag = DMat();
+                M.Ag.nrows = static_cast<int>(rows.size());
+                M.Ag.ncols = M.n;
+                M.Ag.np = M.A.np;
+                M.Ag.nnz = grp.back();
+                M.Ag.rowptr.upload(grp, s);
+                M.Ag.col.alloc(static_cast<size_t>(std::max<int64_t>(1, M.Ag.nnz)));
+                M.Ag.val.alloc(static_cast<size_t>(std::max<int64_t>(1, M.Ag.nnz * M.A.np)));
+                if (rows.empty()) rows.push_back(0);
+                M.g_rowid.upload(rows, s);
+                M.d_cptr.upload(M.cptr, s);
+                if (M.Ag.nrows > 0)
+                    launch_gather_rows(M.A.np, M.Ag.nrows, M.g_rowid.p, M.A.rowptr.p, M.A.col.p, M.A.val.p,
+                                       M.A.nnz, M.Ag.rowptr.p, M.Ag.col.p, M.Ag.val.p, M.Ag.nnz, s);
+            }
+        }
+        // systems ending on this level: their coarsest inverses, as 3 n x 3 n
+        // operators on their rows (A = A_s (x) I_3: the scalar inverse (x) I_3)
+        for (size_t j = 0; j < np_; ++j)
+            if (depth[P[j]] == l) {
+                const Level &V = inst[P[j]]->lv[l];
+                M.dseg.add(3 * V.n, 3 * noff[j], 3 * V.n, 0);
+            }
+        if (!M.dseg.h_m.empty()) {
+            M.dseg.finalize(s);
+            int k = 0;
+            for (size_t j = 0; j < np_; ++j) {
+                if (depth[P[j]] != l) continue;
+                const amg_ctx &I = *inst[P[j]];
+                const int m3 = M.dseg.h_m[k];
+                AMG_REQUIRE(I.coarse_nc * I.coarse_m == m3, AMG_EINVAL, "batch: coarsest inverse size mismatch");
+                std::vector<double> inv = I.coarse_inv.download(s), full;
+                if (I.coarse_nc == 1) {
+                    full.swap(inv);
+                } else {
+                    const int m = I.coarse_m;
+                    full.assign(static_cast<size_t>(m3) * m3, 0.0);
+                    for (int a = 0; a < m; ++a)
+                        for (int b2 = 0; b2 < m; ++b2)
+                            for (int c = 0; c < 3; ++c)
+                                full[static_cast<size_t>(3 * a + c) * m3 + 3 * b2 + c] =
+                                    inv[static_cast<size_t>(a) * m + b2];
+                }
+                AMG_HIP(hipMemcpyAsync(M.dseg.inv.p + M.dseg.h_moff[k], full.data(), full.size() * sizeof(double),
+                                       hipMemcpyHostToDevice, s));
+                AMG_HIP(hipStreamSynchronize(s));  // full is a local
+                ++k;
+            }
+        }
+        M.G = lanes_of(M.A.nnz, M.n);
+        M.Gg = M.G;
+        M.Gp = lanes_of(M.P.nnz, M.P.nrows);
+        M.Gr = lanes_of(M.R.nnz, M.R.nrows);
+        const size_t nv = 3 * static_cast<size_t>(std::max(1, M.n));
+        M.x.alloc(nv);
+        M.b.alloc(nv);
+        M.r.alloc(nv);
+        M.t.alloc(nv);
+    }
+    AMG_HIP(hipStreamSynchronize(s));
+    ph_merge.reset();
+    if (p.autotune) {
+        SetupPhase ph(h, "autotune");
+        for (Level &M : merged)
+            if (M.nA > 0) autotune_level(h, M);
+    }
+    // level-0 layout of every system (velocity ranges only), chunk tables
+    h->nsys = nsys;
+    h->b_order = order;
+    std::vector<int64_t> user(nsys + 1, 0);
+    for (int i = 0; i < nsys; ++i) user[i + 1] = user[i] + 3 * static_cast<int64_t>(sys[i].n_lin + sys[i].n_quad);
+    h->b_uoff.assign(nsys, 0);
+    h->b_poff.assign(nsys, 0);
+    h->b_nu.assign(nsys, 0);
+    h->b_np.assign(nsys, 0);
+    {
+        int64_t u = 0;
+        for (int j = 0; j < nsys; ++j) {
+            const amg_system &S = sys[order[j]];
+            h->b_uoff[j] = u;
+            h->b_nu[j] = 3 * static_cast<int64_t>(S.n_lin + S.n_quad);
+            u += h->b_nu[j];
+        }
+    }
+    std::vector<int64_t> st, ds_unused, st_in, ds_in, st_out, ds_out;
+    std::vector<int> ln, sg, ln_in, sg_in, ln_out, sg_out;
+    std::vector<int> c0(nsys), c1(nsys), c2(nsys), c3(nsys);
+    for (int j = 0; j < nsys; ++j) {
+        c0[j] = static_cast<int>(st.size());
+        add_chunks(h->b_uoff[j], h->b_nu[j], j, st, ln, sg, nullptr, 0);
+        c1[j] = static_cast<int>(st.size());
+    }
+    for (int j = 0; j < nsys; ++j) c2[j] = c3[j] = static_cast<int>(st.size());
+    for (int j = 0; j < nsys; ++j) {
+        const int64_t ub = user[order[j]];
+        add_chunks(ub, h->b_nu[j], j, st_in, ln_in, sg_in, &ds_in, h->b_uoff[j]);
+        add_chunks(h->b_uoff[j], h->b_nu[j], j, st_out, ln_out, sg_out, &ds_out, ub);
+    }
+    h->b_chunks.build(st, ln, sg, {}, s);
+    h->b_c0.upload(c0, s);
+    h->b_c1.upload(c1, s);
+    h->b_c2.upload(c2, s);
+    h->b_c3.upload(c3, s);
+    h->b_in.build(st_in, ln_in, sg_in, ds_in, s);
+    h->b_out.build(st_out, ln_out, sg_out, ds_out, s);
+    inst.clear();
+    h->lv = std::move(merged);
+    h->saddle = false;
+    h->pinned = -1;
+    h->n_dof = 3 * h->lv[0].n;
+    const size_t nd = static_cast<size_t>(h->n_dof);
+    h->b_b.alloc(nd);
+    h->b_x.alloc(nd);
+    h->kr.alloc(nd);
+    h->kz.alloc(nd);
+    h->kp.alloc(nd);
+    h->kq.alloc(nd);
+    h->kw.alloc(nd);
+    h->partial.alloc(static_cast<size_t>(std::max(1024 * 128, row_blocks(h->lv[0].n, 64))));
+    h->tune_flush.release();
+    h->sc.alloc(SC_COUNT);
+    if (!h->h_sc) AMG_HIP(hipHostMalloc(reinterpret_cast<void **>(&h->h_sc), SC_COUNT * sizeof(double)));
+    AMG_HIP(hipStreamSynchronize(s));
+}
+
 // ---------------------------------------------------------------- batched FGMRES
 // Per-system norms of a merged level-0 vector (host result).
 static void seg_norms(amg_ctx *h, const double *v, DevBuf<double> &partial, DevBuf<double> &hb, int kmax,
@@ -618,6 +865,119 @@ int solve_fgmres_batched(amg_ctx *h, const double *b, double *x, double tol, int
     int worst = AMG_OK;
     for (int j = 0; j < ns; ++j) {
         const double rel = r0[j] > 0.0 ? fin[j] / r0[j] : 0.0;
+        int st = status[j];
+        if (st == AMG_OK && !(rel == rel)) st = AMG_DIVERGED;
+        if (res) {
+            amg_result &o = res[h->b_order[j]];
+            o.iters = iters[j];
+            o.status = st;
+            o.relres = rel;
+            o.solve_ms = ms;
+        }
+        worst = std::max(worst, st);
+    }
+    profile_collect(h);
+    return worst;
+}
+
+// AMG-preconditioned CG on every system of an SPD batch, in lockstep: one
+// launch per operation serves all systems, and each system keeps its own
+// step lengths, residual norm, stopping test and iteration count (a system
+// that has converged, broken down or diverged takes zero steps from then
+// on; its iterate stays). Two host synchronisations per iteration: <p, Ap>,
+// then ||r|| and <r, z> in one pass.
+int solve_pcg_batched(amg_ctx *h, const double *b, double *x, double tol, int maxit, amg_result *res) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const int ns = h->nsys;
+    const int64_t n = h->n_dof;
+    hipStream_t s = h->stream;
+    const ChunkView t = h->b_chunks.view();
+    double *r = h->kr.p, *z = h->kz.p, *pv = h->kp.p, *q = h->kq.p;
+    DevBuf<double> partial(static_cast<size_t>(2) * std::max(1, t.n)), hb(static_cast<size_t>(2) * ns), da(ns),
+        dm(ns), dbeta(ns), dones(ns);
+    std::vector<double> hv(static_cast<size_t>(2) * ns), r0(ns), rz(ns), alpha(ns, 0.0), malpha(ns, 0.0),
+        beta(ns, 0.0), ones(ns, 1.0), pq(ns);
+    std::vector<int> status(ns, AMG_NOT_CONVERGED), iters(ns, 0);
+    std::vector<char> active(ns, 0);
+    // k = 1: <a, c> per system; k = 2: <a, a> and <a, c>
+    auto dots = [&](const double *a, const double *c, int k) {
+        if (k == 1)
+            launch_seg_multidot(a, 0, 1, c, t, partial.p, s);
+        else
+            launch_seg_multidot2(a, 0, 1, a, c, t, partial.p, s);
+        launch_seg_reduce(partial.p, t.n, k, ns, h->b_c0.p, h->b_c1.p, h->b_c2.p, h->b_c3.p, hb.p, k, s);
+        AMG_HIP(hipMemcpyAsync(hv.data(), hb.p, static_cast<size_t>(k) * ns * sizeof(double), hipMemcpyDeviceToHost,
+                               s));
+        AMG_HIP(hipStreamSynchronize(s));
+    };
+    auto put = [&](DevBuf<double> &d, const std::vector<double> &v) {
+        AMG_HIP(hipMemcpyAsync(d.p, v.data(), ns * sizeof(double), hipMemcpyHostToDevice, s));
+    };
+    auto any_active = [&] { return std::any_of(active.begin(), active.end(), [](char c) { return c != 0; }); };
+    put(dones, ones);
+    system_residual(h, b, x, r);
+    dots(r, r, 1);
+    for (int i = 0; i < ns; ++i) {
+        r0[i] = std::sqrt(hv[i]);
+        if (!(r0[i] == r0[i])) status[i] = AMG_DIVERGED;
+        else if (r0[i] == 0.0) status[i] = AMG_OK;
+        else active[i] = 1;
+    }
+    if (any_active()) {
+        precondition(h, r, z);
+        launch_copy(pv, z, n, s);
+        dots(r, z, 1);
+        for (int i = 0; i < ns; ++i) rz[i] = hv[i];
+    }
+    int it = 0;
+    while (any_active() && it < maxit) {
+        apply_level(h, 0, pv, q);
+        dots(pv, q, 1);
+        for (int i = 0; i < ns; ++i) {
+            pq[i] = hv[i];
+            alpha[i] = 0.0;
+            if (!active[i]) continue;
+            if (!(pq[i] > 0.0) || !(rz[i] == rz[i])) {
+                status[i] = AMG_BREAKDOWN;
+                active[i] = 0;
+                continue;
+            }
+            alpha[i] = rz[i] / pq[i];
+            ++iters[i];
+        }
+        for (int i = 0; i < ns; ++i) malpha[i] = -alpha[i];
+        put(da, alpha);
+        put(dm, malpha);
+        launch_seg_axpby(pv, x, da.p, dones.p, t, s);  // x += alpha p
+        launch_seg_axpby(q, r, dm.p, dones.p, t, s);   // r -= alpha q
+        ++it;
+        precondition(h, r, z);
+        dots(r, z, 2);
+        for (int i = 0; i < ns; ++i) {
+            beta[i] = 0.0;
+            if (!active[i]) continue;
+            const double rel = std::sqrt(hv[2 * i]) / r0[i];
+            if (!(rel == rel) || rel > 1e3) {
+                status[i] = AMG_DIVERGED;
+                active[i] = 0;
+            } else if (rel <= tol) {
+                status[i] = AMG_OK;
+                active[i] = 0;
+            } else {
+                beta[i] = hv[2 * i + 1] / rz[i];
+                rz[i] = hv[2 * i + 1];
+            }
+        }
+        put(dbeta, beta);
+        launch_seg_axpby(z, pv, dones.p, dbeta.p, t, s);  // p = z + beta p
+    }
+    // the true residual of every system
+    system_residual(h, b, x, h->kw.p);
+    dots(h->kw.p, h->kw.p, 1);
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    int worst = AMG_OK;
+    for (int j = 0; j < ns; ++j) {
+        const double rel = r0[j] > 0.0 ? std::sqrt(hv[j]) / r0[j] : 0.0;
         int st = status[j];
         if (st == AMG_OK && !(rel == rel)) st = AMG_DIVERGED;
         if (res) {

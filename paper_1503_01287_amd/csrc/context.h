@@ -385,6 +385,10 @@ void precondition_any(amg_ctx *h, const double *r, double *z);
 void precondition_staged(amg_ctx *h, const double *r, double *z);
 // batches
 void build_batch(amg_ctx *h, int nsys, const amg_system *sys);
+// batches of SPD systems (every n_pres = 0): the merged FP64 hierarchy and
+// its lockstep PCG
+void build_batch_spd(amg_ctx *h, int nsys, const amg_system *sys);
+int solve_pcg_batched(amg_ctx *h, const double *b, double *x, double tol, int maxit, amg_result *res);
 int solve_fgmres_batched(amg_ctx *h, const double *b, double *x, double tol, int maxit, amg_result *res);
 void saddle_apply(amg_ctx *h, int l, const double *x, double *y);
 void saddle_smooth(amg_ctx *h, int l, const double *b, double *x);

@@ -274,7 +274,7 @@ static void setup_smoother(amg_ctx *h, Level &L) {
     L.g_rowid.upload(order, s);
     L.d_cptr.upload(L.cptr, s);
     launch_gather_rows(L.A.np, L.n, L.g_rowid.p, L.A.rowptr.p, L.A.col.p, L.A.val.p, L.A.nnz, L.Ag.rowptr.p,
-                       L.Ag.col.p, L.Ag.val.p, s);
+                       L.Ag.col.p, L.Ag.val.p, L.Ag.nnz, s);
     AMG_HIP(hipStreamSynchronize(s));
     L.Gg = L.G;
 }
@@ -306,7 +306,7 @@ void group_schur_rows(SchurLevel &q, hipStream_t s) {
     q.Sg.col.alloc(std::max<int64_t>(1, q.Sg.nnz));
     q.Sg.val.alloc(std::max<int64_t>(1, q.Sg.nnz));
     launch_gather_rows(1, m, q.rowid.p, q.S.rowptr.p, q.S.col.p, q.S.val.p, q.S.nnz, q.Sg.rowptr.p, q.Sg.col.p,
-                       q.Sg.val.p, s);
+                       q.Sg.val.p, q.Sg.nnz, s);
     AMG_HIP(hipStreamSynchronize(s));
 }
 
@@ -1038,7 +1038,7 @@ double lambda_max_dinv_a(amg_ctx *h, Level &L) {
         a.x = v.p;
         a.y = y.p;
         launch_row(L.mode, OP_SPMV, L.G, a, s);                 // y = A v
-        launch_jacobi_zero(L.mode, L.n, L.dinv.p, y.p, 1.0, w.p, s);  // w = D^{-1} A v
+        launch_jacobi_zero(L.mode, L.n, L.dinv.p, L.n, y.p, 1.0, w.p, s);  // w = D^{-1} A v
         const double vav = dot(v.p, y.p), ydy = dot(y.p, w.p), ww = dot(w.p, w.p);
         if (!(vav > 0.0) || !(ww > 0.0)) break;
         lam = ydy / vav;

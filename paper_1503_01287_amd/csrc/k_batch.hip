@@ -215,6 +215,23 @@ void launch_seg_scale(const double *x, double *y, const double *coef, const Chun
     AMG_CHECK_LAUNCH();
 }
 
+// y = a[seg] x + b[seg] y
+__global__ void __launch_bounds__(CB) k_seg_axpby(const double *x, double *y, const double *a, const double *b,
+                                                  const ChunkView t) {
+    const int c = blockIdx.x;
+    const int64_t s0 = t.start[c];
+    const int len = t.len[c];
+    const double ca = a[t.seg[c]], cb = b[t.seg[c]];
+    for (int i = threadIdx.x; i < len; i += CB) y[s0 + i] = ca * x[s0 + i] + cb * y[s0 + i];
+}
+
+void launch_seg_axpby(const double *x, double *y, const double *a, const double *b, const ChunkView &t,
+                      hipStream_t s) {
+    if (t.n <= 0) return;
+    k_seg_axpby<<<t.n, CB, 0, s>>>(x, y, a, b, t);
+    AMG_CHECK_LAUNCH();
+}
+
 __global__ void __launch_bounds__(CB) k_seg_multi_add(const double *Z, int64_t ld, const double *y, int kmax,
                                                       const int *cnt, double *x, const ChunkView t) {
     const int c = blockIdx.x;

@@ -350,29 +350,30 @@ void launch_diag_solve(int mode, int nrows, const int *rowid, const double *dinv
 }
 
 template <int MODE>
-__global__ void k_jacobi_zero(int64_t nn, const double *dinv, const double *b, double omega, double *x) {
+__global__ void k_jacobi_zero(int64_t nn, int64_t dn, const double *dinv, const double *b, double omega,
+                              double *x) {
     const int64_t t = static_cast<int64_t>(blockIdx.x) * BLOCK + threadIdx.x;
     if (t >= 3 * nn) return;
     const int64_t i = t / 3;
     const int c = static_cast<int>(t % 3);
     double d;
     if constexpr (MODE == 3) {
-        d = dinv[(3 * c) * nn + i] * b[3 * i] + dinv[(3 * c + 1) * nn + i] * b[3 * i + 1] +
-            dinv[(3 * c + 2) * nn + i] * b[3 * i + 2];
+        d = dinv[(3 * c) * dn + i] * b[3 * i] + dinv[(3 * c + 1) * dn + i] * b[3 * i + 1] +
+            dinv[(3 * c + 2) * dn + i] * b[3 * i + 2];
     } else {
         d = dinv[i] * b[t];
     }
     x[t] = omega * d;
 }
 
-void launch_jacobi_zero(int mode, int64_t nn, const double *dinv, const double *b, double omega,
+void launch_jacobi_zero(int mode, int64_t nn, const double *dinv, int64_t dn, const double *b, double omega,
                         double *x, hipStream_t s) {
     if (nn <= 0) return;
     const int nb = ceil_div(3 * nn, BLOCK);
     if (mode == 3)
-        k_jacobi_zero<3><<<nb, BLOCK, 0, s>>>(nn, dinv, b, omega, x);
+        k_jacobi_zero<3><<<nb, BLOCK, 0, s>>>(nn, dn, dinv, b, omega, x);
     else
-        k_jacobi_zero<1><<<nb, BLOCK, 0, s>>>(nn, dinv, b, omega, x);
+        k_jacobi_zero<1><<<nb, BLOCK, 0, s>>>(nn, dn, dinv, b, omega, x);
     AMG_CHECK_LAUNCH();
 }
 
@@ -572,7 +573,7 @@ void launch_diag_inverse(int mode, int n, const int *rowptr, const int *col, con
 // one wavefront per grouped row
 __global__ void k_gather_rows(int np, int nrows, const int *order, const int *rowptr, const int *col,
                               const double *val, int64_t nnz, const int *g_rowptr, int *g_col,
-                              double *g_val) {
+                              double *g_val, int64_t g_nnz) {
     const int g = blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (g >= nrows) return;
@@ -581,16 +582,16 @@ __global__ void k_gather_rows(int np, int nrows, const int *order, const int *ro
     const int dst = g_rowptr[g];
     for (int q = lane; q < len; q += 64) {
         g_col[dst + q] = col[src + q];
-        for (int p = 0; p < np; ++p) g_val[p * nnz + dst + q] = val[p * nnz + src + q];
+        for (int p = 0; p < np; ++p) g_val[p * g_nnz + dst + q] = val[p * nnz + src + q];
     }
 }
 
 void launch_gather_rows(int np, int nrows, const int *order, const int *rowptr, const int *col,
                         const double *val, int64_t nnz, const int *g_rowptr, int *g_col, double *g_val,
-                        hipStream_t s) {
+                        int64_t g_nnz, hipStream_t s) {
     if (nrows <= 0) return;
     k_gather_rows<<<ceil_div(nrows, BLOCK / 64), BLOCK, 0, s>>>(np, nrows, order, rowptr, col, val, nnz,
-                                                                 g_rowptr, g_col, g_val);
+                                                                 g_rowptr, g_col, g_val, g_nnz);
     AMG_CHECK_LAUNCH();
 }
 

@@ -68,8 +68,9 @@ void launch_aos_to_planes(const double *aos, int np, int64_t nnz, double *planes
 // Gauss-Seidel sweep from x = 0); dinv planes of stride n
 void launch_diag_solve(int mode, int nrows, const int *rowid, const double *dinv, int64_t n, const double *b,
                        double *x, hipStream_t s);
-// x = omega D^{-1} b (first Jacobi step from x = 0)
-void launch_jacobi_zero(int mode, int64_t nnodes, const double *dinv, const double *b, double omega,
+// x = omega D^{-1} b (first Jacobi step from x = 0) on nodes 0 .. nnodes-1;
+// dinv: inverted diagonal blocks, planes dn apart
+void launch_jacobi_zero(int mode, int64_t nnodes, const double *dinv, int64_t dn, const double *b, double omega,
                         double *x, hipStream_t s);
 // per-block partial sums of <a, b> over n doubles; returns the number of blocks
 int launch_dot_partial(const double *a, const double *b, int64_t n, double *partial, hipStream_t s);
@@ -106,10 +107,11 @@ void launch_dense_gemv(const double *M, int m, int nc, const double *X, double *
 // written as planes of stride n. Fails (flag set) if a diagonal is missing.
 void launch_diag_inverse(int mode, int n, const int *rowptr, const int *col, const double *val,
                          int64_t nnz, double *dinv, int *flag, hipStream_t s);
-// Gather rows order[g] of (rowptr, col, val) into the grouped copy.
+// Gather rows order[g] of (rowptr, col, val; planes nnz apart) into the
+// grouped copy (g_rowptr, g_col, g_val; planes g_nnz apart).
 void launch_gather_rows(int np, int nrows, const int *order, const int *rowptr, const int *col,
                         const double *val, int64_t nnz, const int *g_rowptr, int *g_col,
-                        double *g_val, hipStream_t s);
+                        double *g_val, int64_t g_nnz, hipStream_t s);
 
 // Dropping numerically zero entries (all planes zero; the diagonal of a
 // square operator is always kept): count per row, then the kept entries in

@@ -81,9 +81,11 @@ void apply_level(amg_ctx *h, int l, const double *x, double *y) {
     launch_row(L.mode, OP_SPMV, L.G, a, h->stream);
 }
 
-static void residual(amg_ctx *h, int l, const double *b, const double *x, double *r) {
+// r = b - A x on the level's first `rows` rows (all of them: -1)
+static void residual(amg_ctx *h, int l, const double *b, const double *x, double *r, int rows = -1) {
     Level &L = h->lv[l];
     RowArgs a = row_args(L.A);
+    if (rows >= 0) a.nrows = rows;
     a.x = x;
     a.b = b;
     a.y = r;
@@ -98,16 +100,19 @@ static double level_omega(amg_ctx *h, int l) {
     return h->prm.omega;
 }
 
+// (on the level's leading nA rows: the systems of a batch that continue
+// below the level; every row outside batches)
 static void jacobi_step(amg_ctx *h, int l, const double *b, double *x, bool zero_init) {
     Level &L = h->lv[l];
     const double om = level_omega(h, l);
     const int nb = L.mode == 3 ? 9 : 1;
     if (zero_init) {
         ProfScope ps(h, tag("jacobi0", l), 3.0 * L.n * 16.0 + nb * 8.0 * L.n);
-        launch_jacobi_zero(L.mode, L.n, L.dinv.p, b, om, x, h->stream);
+        launch_jacobi_zero(L.mode, L.nA, L.dinv.p, L.n, b, om, x, h->stream);
         return;
     }
     RowArgs a = row_args(L.A);
+    a.nrows = L.nA;
     a.x = x;
     a.b = b;
     a.y = L.t.p;
@@ -119,7 +124,7 @@ static void jacobi_step(amg_ctx *h, int l, const double *b, double *x, bool zero
         a.trip = L.trip;
         launch_row(L.mode, OP_JACOBI, L.G, a, h->stream);
     }
-    launch_copy(x, L.t.p, 3 * static_cast<int64_t>(L.n), h->stream);
+    launch_copy(x, L.t.p, 3 * static_cast<int64_t>(L.nA), h->stream);
 }
 
 // One block Gauss-Seidel sweep by colours. x_zero: x is zero on entry (and
@@ -167,7 +172,7 @@ void smooth(amg_ctx *h, int l, const double *b, double *x, bool pre, bool zero_i
     const int steps = pre ? p.pre : p.post;
     Level &L = h->lv[l];
     const bool need_fill = zero_init && !filled && (steps == 0 || p.smoother != AMG_SMOOTH_JA);
-    if (need_fill) launch_fill(x, 0.0, 3 * static_cast<int64_t>(L.n), h->stream);
+    if (need_fill) launch_fill(x, 0.0, 3 * static_cast<int64_t>(L.nA), h->stream);
     for (int k = 0; k < steps; ++k) {
         if (p.smoother == AMG_SMOOTH_JA)
             jacobi_step(h, l, b, x, zero_init && k == 0);
@@ -179,6 +184,15 @@ void smooth(amg_ctx *h, int l, const double *b, double *x, bool pre, bool zero_i
 static void coarse_solve(amg_ctx *h, const double *b, double *x) {
     ProfScope ps(h, "coarse", static_cast<double>(h->coarse_m) * h->coarse_m * 8.0);
     launch_dense_gemv(h->coarse_inv.p, h->coarse_m, h->coarse_nc, b, x, h->stream);
+}
+
+// a batch of SPD systems: the systems ending on level l (its rows past nA)
+// by their explicit inverses
+static void ending_systems(amg_ctx *h, int l, const double *b, double *x) {
+    Level &L = h->lv[l];
+    if (L.dseg.count == 0) return;
+    ProfScope ps(h, "coarse", L.dseg.bytes);
+    launch_dense_segs<double>(L.dseg.view(), b, b, x, x, h->stream);
 }
 
 static void run_dense_tail(amg_ctx *h, const double *b, double *x) {
@@ -199,8 +213,9 @@ static void run_tail(amg_ctx *h, const double *b, double *x, bool x_zero) {
 // Jacobi step then needs no operator pass); filled: its buffer holds the zeros.
 static void cycle(amg_ctx *h, int l, const double *b, double *x, bool x_zero, bool filled) {
     Level &L = h->lv[l];
+    if (h->nsys > 0) ending_systems(h, l, b, x);
     if (L.coarsest) {
-        coarse_solve(h, b, x);
+        if (h->nsys == 0) coarse_solve(h, b, x);
         return;
     }
     if (l == h->tail_start) {
@@ -212,7 +227,7 @@ static void cycle(amg_ctx *h, int l, const double *b, double *x, bool x_zero, bo
         return;
     }
     smooth(h, l, b, x, true, x_zero, filled);
-    residual(h, l, b, x, L.r.p);
+    residual(h, l, b, x, L.r.p, L.nA);
     Level &C = h->lv[l + 1];
     {
         // b_{l+1} = P^T r; the same pass zeroes x_{l+1} for the recursion
@@ -224,7 +239,8 @@ static void cycle(amg_ctx *h, int l, const double *b, double *x, bool x_zero, bo
         launch_row(1, OP_SPMV, L.Gr, a, h->stream);
     }
     if (C.coarsest) {
-        coarse_solve(h, C.b.p, C.x.p);
+        if (h->nsys > 0) ending_systems(h, l + 1, C.b.p, C.x.p);
+        else coarse_solve(h, C.b.p, C.x.p);
     } else {
         // x_{l+1} = 0, then nu recursive calls (nu = 1: V-cycle, 2: W-cycle)
         const int nu = std::max(1, h->prm.nu);

@@ -264,22 +264,27 @@ class AMGSolver:
 
 
 class BatchedSolver:
-    """amg_setup_batched over several saddle point systems; vectors are the
-    systems' [u; p] one after another, in the order given."""
+    """amg_setup_batched over several saddle point systems (FGMRES) or
+    several SPD systems (PCG, FP64 cycle); vectors are the systems' [u; p]
+    (SPD: u) one after another, in the order given."""
 
-    def __init__(self, systems, smoother: str = "BS-1-1", cycles: int = 1, nu: int = 1,
+    def __init__(self, systems, smoother: str | None = None, cycles: int = 1, nu: int = 1,
                  coarse_max: int = 300, max_levels: int = 10, sgs_omega: float = 0.125,
                  sgs_damping: float = 0.5, restart: int = 100, graph: bool = True, precision: str = "FP64",
-                 fuse_coarse: bool = True, autotune: bool = True, stream=None, device_system: bool = False):
+                 fuse_coarse: bool = True, autotune: bool = True, stream=None, device_system: bool = False,
+                 krylov: str | None = None, omega: float | None = None):
         L = C.lib()
         p = C.default_params()
-        sm = parse_smoother(smoother)
+        systems = list(systems)
+        spd = bool(systems) and systems[0].n_pres == 0
+        sm = parse_smoother(smoother or ("GS-1-1" if spd else "BS-1-1"))
         p.smoother = C.SMOOTH[sm["smoother"]]
         p.pre, p.post = sm["pre"], sm["post"]
+        p.omega = omega if omega is not None else sm.get("omega", 0.5)
         p.sgs_omega, p.sgs_damping = sgs_omega, sgs_damping
         p.cycles, p.nu = cycles, nu
         p.coarse_max, p.max_levels = coarse_max, max_levels
-        p.krylov = C.KRYLOV["FGMRES"]
+        p.krylov = C.KRYLOV[krylov or ("PCG" if spd else "FGMRES")]
         p.restart = restart
         p.graph = 1 if graph else 0
         p.precision = C.PREC[precision]
