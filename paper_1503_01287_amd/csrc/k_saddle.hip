@@ -442,6 +442,76 @@ void launch_segment_store_column(const DenseSegView &d, int j, const double *xu,
     AMG_CHECK_LAUNCH();
 }
 
+// ---------------------------------------------------------------- blocks of columns
+// For pressure-only segments (nu = 0, as in the Schur maps): vectors of C
+// columns, row-major (row i of segment s, column c at (poff_s + i) C + c).
+
+// x[(poff_s + j0 + c) C + c] = 1 for every segment s and c < C with
+// j0 + c < m_s (x zero elsewhere beforehand)
+__global__ void k_segment_units_block(const DenseSegView d, int j0, int C, double *x) {
+    const int sg = blockIdx.x;
+    const int m = d.rstart[sg + 1] - d.rstart[sg];
+    for (int c = threadIdx.x; c < C; c += SB) {
+        const int j = j0 + c;
+        if (j < m) x[static_cast<int64_t>(d.poff[sg] + j) * C + c] = 1.0;
+    }
+}
+
+void launch_segment_units_block(const DenseSegView &d, int j0, int C, double *x, hipStream_t s) {
+    if (d.count <= 0) return;
+    k_segment_units_block<<<d.count, SB, 0, s>>>(d, j0, C, x);
+    AMG_CHECK_LAUNCH();
+}
+
+// columns j0 .. j0 + C - 1 of every segment's matrix (row-major):
+// M_s[i][j0 + c] = x[(poff_s + i) C + c]
+__global__ void k_segment_store_block(const DenseSegView d, int j0, int C, const double *x, double *inv) {
+    const int sg = blockIdx.x;
+    const int m = d.rstart[sg + 1] - d.rstart[sg];
+    const int64_t mc = static_cast<int64_t>(m) * C;
+    for (int64_t e = threadIdx.x; e < mc; e += SB) {
+        const int i = static_cast<int>(e / C), c = static_cast<int>(e % C);
+        const int j = j0 + c;
+        if (j < m) inv[d.moff[sg] + static_cast<int64_t>(i) * m + j] = x[static_cast<int64_t>(d.poff[sg] + i) * C + c];
+    }
+}
+
+void launch_segment_store_block(const DenseSegView &d, int j0, int C, const double *x, double *inv, hipStream_t s) {
+    if (d.count <= 0) return;
+    k_segment_store_block<<<d.count, SB, 0, s>>>(d, j0, C, x, inv);
+    AMG_CHECK_LAUNCH();
+}
+
+// y = M_s x on every segment for C columns: one wavefront per segment row,
+// lanes over the columns, FP64
+__global__ void __launch_bounds__(SB) k_dense_segs_block(const DenseSegView d, int C, const double *x, double *y) {
+    const int r = blockIdx.x * (SB / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (r >= d.rows) return;
+    int lo = 0, hi = d.count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (d.rstart[mid] <= r) lo = mid;
+        else hi = mid - 1;
+    }
+    const int sg = lo;
+    const int m = d.rstart[sg + 1] - d.rstart[sg];
+    const int i = r - d.rstart[sg];
+    const double *row = d.inv + d.moff[sg] + static_cast<int64_t>(i) * m;
+    const int64_t p0 = d.poff[sg];
+    for (int c = lane; c < C; c += 64) {
+        double acc = 0.0;
+        for (int j = 0; j < m; ++j) acc += row[j] * x[(p0 + j) * C + c];
+        y[(p0 + i) * C + c] = acc;
+    }
+}
+
+void launch_dense_segs_block(const DenseSegView &d, int C, const double *x, double *y, hipStream_t s) {
+    if (d.count <= 0 || d.rows <= 0) return;
+    k_dense_segs_block<<<ceil_div(d.rows, SB / 64), SB, 0, s>>>(d, C, x, y);
+    AMG_CHECK_LAUNCH();
+}
+
 // ---------------------------------------------------------------- FGMRES
 // Workgroup (c, g) dots the chunk c of the NR right-hand sides (MD_CHUNK
 // entries each, held in registers) with the same chunk of the basis vectors

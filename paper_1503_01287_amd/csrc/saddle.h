@@ -98,6 +98,13 @@ void launch_segment_units(const DenseSegView &d, int j, double *xu, double *xp, 
 // launch_segment_units: M_s[i][j] = x(row i of segment s)
 void launch_segment_store_column(const DenseSegView &d, int j, const double *xu, const double *xp, double *inv,
                                  hipStream_t s);
+// The same for blocks of C columns over pressure-only segments (nu = 0):
+// vectors row-major with C columns (segment s's row i, column c at
+// (poff_s + i) C + c). Units: x[(poff_s + j0 + c) C + c] = 1 for j0 + c <
+// m_s; store: M_s[i][j0 + c] from column c; y = M_s x on every segment, FP64.
+void launch_segment_units_block(const DenseSegView &d, int j0, int C, double *x, hipStream_t s);
+void launch_segment_store_block(const DenseSegView &d, int j0, int C, const double *x, double *inv, hipStream_t s);
+void launch_dense_segs_block(const DenseSegView &d, int C, const double *x, double *y, hipStream_t s);
 
 // FGMRES inner products: h[i] = <V_i, w> for i < k (V_i = V + i * ld) as
 // block partials partial[i * nb + block] (nb = multidot_blocks(n), the

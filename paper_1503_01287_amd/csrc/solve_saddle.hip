@@ -8,6 +8,7 @@
 #include <cmath>
 
 #include "context.h"
+#include "multi.h"
 
 namespace amgp2 {
 
@@ -339,6 +340,86 @@ static void schur_vcycle(amg_ctx *h, int l, int k, const T *b, T *x) {
 // colour sweeps it replaces, up to rounding order.
 constexpr int SCHUR_DENSE_MAX = 1500;
 
+// The Schur cycle of setup_schur_dense on SCHUR_COLS columns at once, for
+// its assembly: the scalar Schur levels run as the multi-right-hand-side
+// row kernels (multi.h) over 3 x SCHUR_K interleaved columns (S applied to
+// each column), so that the operators are read once for all of them. Same
+// steps as schur_vcycle (forward sweep by colours from zero, residual,
+// H^T, recursion, H, backward sweep; systems ending on a level by their
+// explicit inverses); the sweeps take the correction form x_i += (b_i -
+// sum_j S_ij x_j) / S_ii, equal to the direct form up to rounding.
+constexpr int SCHUR_K = 8;
+constexpr int SCHUR_COLS = 3 * SCHUR_K;
+
+struct SchurBlockWork {
+    std::vector<DevBuf<double>> x, b, r;
+};
+
+static void schur_block_cycle(amg_ctx *h, int l, int k, SchurBlockWork &W, const double *b, double *x) {
+    SchurHier &sh = h->lv[l].schur;
+    SchurLevel &q = sh.lv[k];
+    hipStream_t s = h->stream;
+    if (q.dseg.count > 0) launch_dense_segs_block(q.dseg.view(), SCHUR_COLS, b, x, s);
+    if (q.nA == 0) return;
+    launch_fill(x, 0.0, static_cast<int64_t>(q.nA) * SCHUR_COLS, s);
+    const int nc = static_cast<int>(q.cptr.size()) - 1;
+    auto sweep = [&](int c) {
+        const int rows = q.cptr[c + 1] - q.cptr[c];
+        if (rows == 0) return;
+        MRowArgs a;
+        a.nrows = rows;
+        a.rowptr = q.Sg.rowptr.p + q.cptr[c];
+        a.col = q.Sg.col.p;
+        a.val = q.Sg.val.p;
+        a.nnz = q.Sg.nnz;
+        a.rowid = q.rowid.p + q.cptr[c];
+        a.x = x;
+        a.b = b;
+        a.y = x;
+        a.dinv = q.dinv.p;
+        a.dinv_n = q.S.nrows;
+        launch_mrow(1, M_GS, MK_F64, SCHUR_K, a, s);
+    };
+    for (int c = 0; c < nc; ++c) sweep(c);
+    {
+        MRowArgs a;
+        a.nrows = q.nA;
+        a.rowptr = q.S.rowptr.p;
+        a.col = q.S.col.p;
+        a.val = q.S.val.p;
+        a.nnz = q.S.nnz;
+        a.x = x;
+        a.b = b;
+        a.y = W.r[k].p;
+        launch_mrow(1, M_RESID, MK_F64, SCHUR_K, a, s);
+    }
+    const Level &V = h->lv[l + k];
+    {
+        MRowArgs a;
+        a.nrows = V.Ht.nrows;
+        a.rowptr = V.Ht.rowptr.p;
+        a.col = V.Ht.col.p;
+        a.val = V.Ht.val.p;
+        a.nnz = V.Ht.nnz;
+        a.x = W.r[k].p;
+        a.y = W.b[k + 1].p;
+        launch_mrow(1, M_SPMV, MK_F64, SCHUR_K, a, s);
+    }
+    schur_block_cycle(h, l, k + 1, W, W.b[k + 1].p, W.x[k + 1].p);
+    {
+        MRowArgs a;
+        a.nrows = V.H.nrows;
+        a.rowptr = V.H.rowptr.p;
+        a.col = V.H.col.p;
+        a.val = V.H.val.p;
+        a.nnz = V.H.nnz;
+        a.x = W.x[k + 1].p;
+        a.y = x;
+        launch_mrow(1, M_SPMV_ADD, MK_F64, SCHUR_K, a, s);
+    }
+    for (int c = nc - 1; c >= 0; --c) sweep(c);
+}
+
 void setup_schur_dense(amg_ctx *h, int l) {
     SchurHier &sh = h->lv[l].schur;
     if (!h->prm.fuse_coarse) return;  // launch by launch (amg_params::fuse_coarse = 0)
@@ -364,13 +445,24 @@ void setup_schur_dense(amg_ctx *h, int l) {
     }
     sh.tdense.finalize(s);
     const DenseSegView v = sh.tdense.view();
-    const int n = std::max(1, q.S.nrows);
-    DevBuf<double> unit(n), col(n);
-    for (int j = 0; j < mmax; ++j) {
-        launch_fill(unit.p, 0.0, n, s);
-        launch_segment_units(v, j, unit.p, unit.p, s);
-        schur_vcycle<double>(h, l, k0, unit.p, col.p);
-        launch_segment_store_column(v, j, col.p, col.p, sh.tdense.inv.p, s);
+    // SCHUR_COLS unit columns of every system per blocked cycle
+    SchurBlockWork W;
+    const int nlev = static_cast<int>(sh.lv.size());
+    W.x.resize(nlev);
+    W.b.resize(nlev);
+    W.r.resize(nlev);
+    for (int k = k0; k < nlev; ++k) {
+        const size_t len = static_cast<size_t>(std::max(1, sh.lv[k].S.nrows)) * SCHUR_COLS;
+        W.x[k].alloc(len);
+        W.b[k].alloc(len);
+        W.r[k].alloc(len);
+    }
+    const int64_t n0 = static_cast<int64_t>(std::max(1, q.S.nrows)) * SCHUR_COLS;
+    for (int j0 = 0; j0 < mmax; j0 += SCHUR_COLS) {
+        launch_fill(W.b[k0].p, 0.0, n0, s);
+        launch_segment_units_block(v, j0, SCHUR_COLS, W.b[k0].p, s);
+        schur_block_cycle(h, l, k0, W, W.b[k0].p, W.x[k0].p);
+        launch_segment_store_block(v, j0, SCHUR_COLS, W.x[k0].p, sh.tdense.inv.p, s);
     }
     AMG_HIP(hipStreamSynchronize(s));
     sh.dense_from = k0;
