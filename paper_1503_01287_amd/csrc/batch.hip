@@ -320,11 +320,14 @@ void build_batch(amg_ctx *h, int nsys, const amg_system *sys) {
     }
     AMG_HIP(hipStreamSynchronize(s));
     ph_merge.reset();
-    // the merged levels' kernels see other shapes than the systems' own
+    // the merged levels' kernels see other shapes than the systems' own; a
+    // reduced-precision cycle runs only the finest level's natural-order
+    // FP64 kernels (the outer Krylov operator)
     if (p.autotune) {
         SetupPhase ph(h, "autotune");
-        for (Level &M : merged)
-            if (M.nA > 0) autotune_level(h, M);
+        const bool reduced = p.precision != AMG_PREC_FP64;
+        for (size_t l = 0; l < merged.size(); ++l)
+            if (merged[l].nA > 0 && (!reduced || l == 0)) autotune_level(h, merged[l], reduced);
     }
 
     // level-0 layout of every system, chunk tables

@@ -367,7 +367,10 @@ void setup_tail(amg_ctx *h);
 // lanes per row for a row kernel from the mean entries per row (4..64)
 int lanes_for(int64_t nnz, int nrows);
 // setup-time tuner of a level's FP64 kernels (lanes, loop form, XCD placement)
-void autotune_level(amg_ctx *h, Level &L);
+// natural_only: the natural-order kernels only (not the colour sweeps)
+void autotune_level(amg_ctx *h, Level &L, bool natural_only = false);
+// first level covered by the SPD hierarchy's assembled coarse end, or -1
+int dense_tail_level(const amg_ctx *h);
 // evict the GPU caches before a tuner's timed run: inside a cycle a level's
 // operator is read after the finer levels' passes have replaced it in the
 // caches, so the tuners time kernels on cold data

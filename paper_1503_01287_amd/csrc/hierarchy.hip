@@ -310,7 +310,7 @@ void group_schur_rows(SchurLevel &q, hipStream_t s) {
     AMG_HIP(hipStreamSynchronize(s));
 }
 
-void autotune_level(amg_ctx *h, Level &L) {
+void autotune_level(amg_ctx *h, Level &L, bool natural_only) {
     hipStream_t s = h->stream;
     const int cand[] = {8, 16, 32, 64};
     hipEvent_t e0, e1;
@@ -370,7 +370,7 @@ void autotune_level(amg_ctx *h, Level &L) {
         a.trip = P;
         return time_it([&] { launch_row(L.mode, OP_RESID, G, a, s); });
     });
-    if (!L.cptr.empty()) {
+    if (!L.cptr.empty() && !natural_only) {
         // a whole forward sweep, colour by colour, as the smoother runs it,
         // with round-robin or per-XCD contiguous workgroup placement
         auto sweep_time = [&](int G, int P, int xcd) {
@@ -578,26 +578,33 @@ static int tail_descriptors(amg_ctx *h, int t, DevBuf<TailLevel> &buf, TailArgs 
 //    workgroup of the tail kernel, and applied as a single GEMV.
 //  * LDS tail: if even the finest level is small, the whole V-cycle runs in
 //    one workgroup with the vectors in LDS.
+// The first level of an SPD hierarchy that the assembled coarse end
+// (setup_tail) will cover, or -1: the first level d >= 1 whose operator has
+// at most TAIL_DENSE_MAX rows, for the symmetric V-cycle with JA or GS
+int dense_tail_level(const amg_ctx *h) {
+    const amg_params &p = h->prm;
+    // (both forms implement the symmetric cycle: forward pre-, backward post-smoothing)
+    if (h->saddle || h->nsys > 0 || !p.fuse_coarse || p.nu != 1 || h->post_forward) return -1;
+    if (p.smoother != AMG_SMOOTH_JA && p.smoother != AMG_SMOOTH_GS) return -1;
+    const int L = static_cast<int>(h->lv.size()) - 1;
+    for (int k = 1; k < L; ++k) {
+        const int m = h->lv[k].mode == 3 ? 3 * h->lv[k].n : h->lv[k].n;
+        if (m <= TAIL_DENSE_MAX) return k;
+    }
+    return -1;
+}
+
 void setup_tail(amg_ctx *h) {
     h->tail_start = -1;
     h->dense_start = -1;
     h->tail_m = 0;
     h->tail_dense.release();
     const amg_params &p = h->prm;
-    // (both forms implement the symmetric cycle: forward pre-, backward post-smoothing)
     if (!p.fuse_coarse || p.nu != 1 || h->post_forward) return;
     if (p.smoother != AMG_SMOOTH_JA && p.smoother != AMG_SMOOTH_GS) return;
     const int L = static_cast<int>(h->lv.size()) - 1;
     if (L == 0) return;
-    // dense tail: the first level d >= 1 whose operator has at most TAIL_DENSE_MAX rows
-    int d = -1;
-    for (int k = 1; k < L; ++k) {
-        const int m = h->lv[k].mode == 3 ? 3 * h->lv[k].n : h->lv[k].n;
-        if (m <= TAIL_DENSE_MAX) {
-            d = k;
-            break;
-        }
-    }
+    const int d = dense_tail_level(h);
     if (d > 0) {
         TailArgs u;
         double algo = 0.0;
@@ -1170,7 +1177,14 @@ void build_hierarchy(amg_ctx *h, const amg_system *sys) {
             }
         }
     }
-    for (Level &L : h->lv) {
+    // The FP64 kernels' tuner runs where those kernels run in solves: with a
+    // reduced-precision cycle only the finest level's natural-order kernels
+    // (the outer Krylov operator); in the FP64 cycle every level above the
+    // assembled coarse end.
+    const bool reduced = p.precision != AMG_PREC_FP64;
+    const int tail_from = dense_tail_level(h);
+    for (size_t l = 0; l < h->lv.size(); ++l) {
+        Level &L = h->lv[l];
         const size_t nv = static_cast<size_t>(L.vlen());
         L.x.alloc(nv);
         L.b.alloc(nv);
@@ -1182,9 +1196,10 @@ void build_hierarchy(amg_ctx *h, const amg_system *sys) {
                 setup_smoother(h, L);
                 if (h->saddle) saddle_setup_level(h, L);
             }
-            if (p.autotune) {
+            const bool used = reduced ? l == 0 : (tail_from < 0 || static_cast<int>(l) < tail_from);
+            if (p.autotune && used) {
                 SetupPhase ph(h, "autotune");
-                autotune_level(h, L);
+                autotune_level(h, L, reduced);
             }
         }
     }

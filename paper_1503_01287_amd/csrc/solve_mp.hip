@@ -156,7 +156,9 @@ void build_mixed(amg_ctx *h) {
         // kernels' tuned choice, so that its result does not inherit their
         // timing noise
         M.G = M.Gg = lanes_for(L.A.nnz, L.n);
-        if (h->prm.autotune) autotune_mp(h, L);
+        // (not the levels inside the assembled coarse end: those kernels do
+        // not run in the cycle)
+        if (h->prm.autotune && (h->dense_start < 0 || static_cast<int>(l) < h->dense_start)) autotune_mp(h, L);
     }
     refresh_tail_f32(h);
 }
