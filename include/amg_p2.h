@@ -365,13 +365,15 @@ int amg_set_launch_shape(amg_handle h, int32_t level, int32_t kernels, int32_t l
  *  - saddle point systems: flexible GMRES with per-system inner products,
  *    Hessenberg matrices and convergence tests (sGS or Braess-Sarazin
  *    smoother; any precision mode);
- *  - SPD systems (n_pres = 0, one bs for all): preconditioned CG with
+ *  - SPD systems (n_pres = 0, one bs for all): preconditioned CG (PCG) or
+ *    its flexible form (FCG, for the reduced-precision cycles) with
  *    per-system step lengths, residual norms and convergence tests, in
- *    lockstep (JA or GS smoother, V or W cycles; FP64 cycle, the coarse
- *    levels run level by level: fuse_coarse and the reduced precisions
- *    are single-system features). Errors: AMG_EINVAL for mixed kinds or bs,
- *    another Krylov method or smoother; AMG_EUNSUPPORTED for a reduced
- *    precision.
+ *    lockstep (JA or GS smoother, V or W cycles; any precision mode: the
+ *    merged levels get the FP32 / BF16 copies of a single system, and
+ *    systems ending on a level keep their FP64 inverses; the coarse levels
+ *    run level by level: fuse_coarse is a single-system feature). Errors:
+ *    AMG_EINVAL for mixed kinds or bs, another Krylov method or smoother,
+ *    or gs_post = 2.
  * Both take host or device arrays (amg_system::memory).
  */
 int amg_setup_batched(int32_t nsys, const amg_system *systems, const amg_params *params, amg_stream stream,

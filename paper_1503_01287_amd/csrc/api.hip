@@ -221,10 +221,9 @@ int amg_setup_batched(int32_t nsys, const amg_system *systems, const amg_params 
         if (spd) {
             AMG_REQUIRE(p.smoother == AMG_SMOOTH_JA || p.smoother == AMG_SMOOTH_GS, AMG_EINVAL,
                         "amg_setup_batched: SPD batches run the JA or GS smoother");
-            AMG_REQUIRE(p.krylov == AMG_KRYLOV_PCG, AMG_EINVAL, "amg_setup_batched: SPD batches run PCG");
-            AMG_REQUIRE(p.precision == AMG_PREC_FP64, AMG_EUNSUPPORTED,
-                        "amg_setup_batched: SPD batches run the FP64 cycle");
-            AMG_REQUIRE(p.gs_post != 2, AMG_EINVAL, "amg_setup_batched: PCG needs the symmetric cycle");
+            AMG_REQUIRE(p.krylov == AMG_KRYLOV_PCG || p.krylov == AMG_KRYLOV_FCG, AMG_EINVAL,
+                        "amg_setup_batched: SPD batches run PCG or FCG");
+            AMG_REQUIRE(p.gs_post != 2, AMG_EINVAL, "amg_setup_batched: CG needs the symmetric cycle");
         } else {
             AMG_REQUIRE(p.krylov == AMG_KRYLOV_FGMRES, AMG_EINVAL, "amg_setup_batched: saddle batches run FGMRES");
             AMG_REQUIRE(p.smoother != AMG_SMOOTH_VANKA, AMG_EUNSUPPORTED,

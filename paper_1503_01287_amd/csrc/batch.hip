@@ -599,10 +599,13 @@ void build_batch_spd(amg_ctx *h, int nsys, const amg_system *sys) {
     }
     AMG_HIP(hipStreamSynchronize(s));
     ph_merge.reset();
+    // (a reduced-precision cycle runs only the finest level's natural-order
+    // FP64 kernels: the outer Krylov operator)
     if (p.autotune) {
         SetupPhase ph(h, "autotune");
-        for (Level &M : merged)
-            if (M.nA > 0) autotune_level(h, M);
+        const bool reduced = p.precision != AMG_PREC_FP64;
+        for (size_t l = 0; l < merged.size(); ++l)
+            if (merged[l].nA > 0 && (!reduced || l == 0)) autotune_level(h, merged[l], reduced);
     }
     // level-0 layout of every system (velocity ranges only), chunk tables
     h->nsys = nsys;
@@ -657,6 +660,12 @@ void build_batch_spd(amg_ctx *h, int nsys, const amg_system *sys) {
     h->kq.alloc(nd);
     h->kw.alloc(nd);
     h->partial.alloc(static_cast<size_t>(std::max(1024 * 128, row_blocks(h->lv[0].n, 64))));
+    if (p.precision != AMG_PREC_FP64) {
+        // FP32 finest / BF16 (FP32) coarse copies of the merged levels; the
+        // systems ending on a level keep their FP64 inverses
+        SetupPhase ph(h, "reduced_copies");
+        build_mixed(h);
+    }
     h->tune_flush.release();
     h->sc.alloc(SC_COUNT);
     if (!h->h_sc) AMG_HIP(hipHostMalloc(reinterpret_cast<void **>(&h->h_sc), SC_COUNT * sizeof(double)));
@@ -888,7 +897,10 @@ int solve_fgmres_batched(amg_ctx *h, const double *b, double *x, double tol, int
 // step lengths, residual norm, stopping test and iteration count (a system
 // that has converged, broken down or diverged takes zero steps from then
 // on; its iterate stays). Two host synchronisations per iteration: <p, Ap>,
-// then ||r|| and <r, z> in one pass.
+// then ||r|| and <r, z> in one pass. With the flexible variant (FCG(1), for
+// the reduced-precision cycle, as solve_fcg): alpha = <p, r> / <p, Ap> and
+// p = z - (<z, q_prev> / <p_prev, q_prev>) p_prev, three synchronisations
+// per iteration (<z, q_prev>; <p, Ap> with <p, r>; ||r||).
 int solve_pcg_batched(amg_ctx *h, const double *b, double *x, double tol, int maxit, amg_result *res) {
     const auto t0 = std::chrono::steady_clock::now();
     const int ns = h->nsys;
@@ -913,6 +925,14 @@ int solve_pcg_batched(amg_ctx *h, const double *b, double *x, double tol, int ma
                                s));
         AMG_HIP(hipStreamSynchronize(s));
     };
+    // <v, a> and <v, c> per system
+    auto dots_pair = [&](const double *v, const double *a, const double *c) {
+        launch_seg_multidot2(v, 0, 1, a, c, t, partial.p, s);
+        launch_seg_reduce(partial.p, t.n, 2, ns, h->b_c0.p, h->b_c1.p, h->b_c2.p, h->b_c3.p, hb.p, 2, s);
+        AMG_HIP(hipMemcpyAsync(hv.data(), hb.p, 2 * static_cast<size_t>(ns) * sizeof(double), hipMemcpyDeviceToHost,
+                               s));
+        AMG_HIP(hipStreamSynchronize(s));
+    };
     auto put = [&](DevBuf<double> &d, const std::vector<double> &v) {
         AMG_HIP(hipMemcpyAsync(d.p, v.data(), ns * sizeof(double), hipMemcpyHostToDevice, s));
     };
@@ -926,14 +946,57 @@ int solve_pcg_batched(amg_ctx *h, const double *b, double *x, double tol, int ma
         else if (r0[i] == 0.0) status[i] = AMG_OK;
         else active[i] = 1;
     }
-    if (any_active()) {
+    const bool flexible = h->prm.krylov == AMG_KRYLOV_FCG;
+    for (int it = 0; flexible && any_active() && it < maxit; ++it) {
+        precondition(h, r, z);
+        if (it == 0) {
+            launch_copy(pv, z, n, s);
+        } else {
+            dots(z, q, 1);  // <z, q_prev>
+            for (int i = 0; i < ns; ++i) beta[i] = active[i] && pq[i] > 0.0 ? -hv[i] / pq[i] : 0.0;
+            put(dbeta, beta);
+            launch_seg_axpby(z, pv, dones.p, dbeta.p, t, s);  // p = z + beta p
+        }
+        apply_level(h, 0, pv, q);
+        dots_pair(pv, q, r);  // <p, q>, <p, r>
+        for (int i = 0; i < ns; ++i) {
+            pq[i] = hv[2 * i];
+            alpha[i] = 0.0;
+            if (!active[i]) continue;
+            if (!(pq[i] > 0.0) || !(hv[2 * i + 1] == hv[2 * i + 1])) {
+                status[i] = AMG_BREAKDOWN;
+                active[i] = 0;
+                continue;
+            }
+            alpha[i] = hv[2 * i + 1] / pq[i];
+            ++iters[i];
+        }
+        for (int i = 0; i < ns; ++i) malpha[i] = -alpha[i];
+        put(da, alpha);
+        put(dm, malpha);
+        launch_seg_axpby(pv, x, da.p, dones.p, t, s);  // x += alpha p
+        launch_seg_axpby(q, r, dm.p, dones.p, t, s);   // r -= alpha q
+        dots(r, r, 1);
+        for (int i = 0; i < ns; ++i) {
+            if (!active[i]) continue;
+            const double rel = std::sqrt(hv[i]) / r0[i];
+            if (!(rel == rel) || rel > 1e3) {
+                status[i] = AMG_DIVERGED;
+                active[i] = 0;
+            } else if (rel <= tol) {
+                status[i] = AMG_OK;
+                active[i] = 0;
+            }
+        }
+    }
+    if (!flexible && any_active()) {
         precondition(h, r, z);
         launch_copy(pv, z, n, s);
         dots(r, z, 1);
         for (int i = 0; i < ns; ++i) rz[i] = hv[i];
     }
     int it = 0;
-    while (any_active() && it < maxit) {
+    while (!flexible && any_active() && it < maxit) {
         apply_level(h, 0, pv, q);
         dots(pv, q, 1);
         for (int i = 0; i < ns; ++i) {

@@ -333,29 +333,31 @@ void launch_planes_bf16(int mode, int nrows, const int *rowptr, const int *rowid
     AMG_CHECK_LAUNCH();
 }
 
+// x = omega D^{-1} b on rows [0, nn); dn is the plane stride of dinv
 template <int MODE>
-__global__ void k_jacobi_zero_mp(int64_t nn, const float *dinv, const float *b, float omega, float *x) {
+__global__ void k_jacobi_zero_mp(int64_t nn, int64_t dn, const float *dinv, const float *b, float omega, float *x) {
     const int64_t t = static_cast<int64_t>(blockIdx.x) * MBLOCK + threadIdx.x;
     if (t >= 3 * nn) return;
     const int64_t i = t / 3;
     const int c = static_cast<int>(t % 3);
     float d;
     if constexpr (MODE == 3)
-        d = dinv[(3 * c) * nn + i] * b[3 * i] + dinv[(3 * c + 1) * nn + i] * b[3 * i + 1] +
-            dinv[(3 * c + 2) * nn + i] * b[3 * i + 2];
+        d = dinv[(3 * c) * dn + i] * b[3 * i] + dinv[(3 * c + 1) * dn + i] * b[3 * i + 1] +
+            dinv[(3 * c + 2) * dn + i] * b[3 * i + 2];
     else
         d = dinv[i] * b[t];
     x[t] = omega * d;
 }
 
-void launch_jacobi_zero_mp(int mode, int64_t nn, const float *dinv, const float *b, float omega, float *x,
-                           hipStream_t s) {
+void launch_jacobi_zero_mp(int mode, int64_t nn, int64_t dn, const float *dinv, const float *b, float omega,
+                           float *x, hipStream_t s) {
     if (nn <= 0) return;
+    AMG_REQUIRE(dn >= nn, AMG_EINVAL, "jacobi_zero_mp: plane stride below the row count");
     const int nb = ceil_div(3 * nn, MBLOCK);
     if (mode == 3)
-        k_jacobi_zero_mp<3><<<nb, MBLOCK, 0, s>>>(nn, dinv, b, omega, x);
+        k_jacobi_zero_mp<3><<<nb, MBLOCK, 0, s>>>(nn, dn, dinv, b, omega, x);
     else
-        k_jacobi_zero_mp<1><<<nb, MBLOCK, 0, s>>>(nn, dinv, b, omega, x);
+        k_jacobi_zero_mp<1><<<nb, MBLOCK, 0, s>>>(nn, dn, dinv, b, omega, x);
     AMG_CHECK_LAUNCH();
 }
 

@@ -48,9 +48,10 @@ void launch_row_scales(int mode, int n, const int *rowptr, const int *col, const
 void launch_planes_f32(const double *src, float *dst, int64_t count, hipStream_t s);
 void launch_planes_bf16(int mode, int nrows, const int *rowptr, const int *rowid, const double *src,
                         int64_t nnz, const float *scale, uint16_t *dst, hipStream_t s);
-// x = omega D^{-1} b over all nodes / x_i = D_i^{-1} b_i over rowid
-void launch_jacobi_zero_mp(int mode, int64_t nn, const float *dinv, const float *b, float omega, float *x,
-                           hipStream_t s);
+// x = omega D^{-1} b over nodes [0, nn) (dinv planes dn apart) / x_i =
+// D_i^{-1} b_i over rowid
+void launch_jacobi_zero_mp(int mode, int64_t nn, int64_t dn, const float *dinv, const float *b, float omega,
+                           float *x, hipStream_t s);
 void launch_diag_solve_mp(int mode, int nrows, const int *rowid, const float *dinv, int64_t n, const float *b,
                           float *x, hipStream_t s);
 // Y = M X with an FP32 or BF16 dense matrix (m x m, rows ld values apart, ld

@@ -142,7 +142,7 @@ void build_mixed(amg_ctx *h) {
             launch_planes_bf16(L.mode, L.n, L.A.rowptr.p, nullptr, L.A.val.p, L.A.nnz, M.scale.p, M.a16.p, s);
             if (!L.cptr.empty()) {
                 M.ag16.alloc(np * L.Ag.nnz);
-                launch_planes_bf16(L.mode, L.n, L.Ag.rowptr.p, L.g_rowid.p, L.Ag.val.p, L.Ag.nnz, M.scale.p,
+                launch_planes_bf16(L.mode, L.Ag.nrows, L.Ag.rowptr.p, L.g_rowid.p, L.Ag.val.p, L.Ag.nnz, M.scale.p,
                                    M.ag16.p, s);
             }
         }
@@ -238,13 +238,15 @@ static double mat_bytes(const Level &L, int64_t nnz, int rows) {
            (L.mp.kind == VAL_BF16 ? rows * 4.0 * L.mode : 0.0);
 }
 
+// (on the leading nA rows: in a batch, the systems still coarsening)
 static void residual_mp(amg_ctx *h, int l, const float *b, const float *x, float *r) {
     Level &L = h->lv[l];
     RowArgsMP a = args_natural(L);
+    a.nrows = L.nA;
     a.x = x;
     a.b = b;
     a.y = r;
-    ProfScope ps(h, tag("resid", l), mat_bytes(L, L.A.nnz, L.n) + 3.0 * L.n * 12.0);
+    ProfScope ps(h, tag("resid", l), mat_bytes(L, L.A.nnz, L.nA) + 3.0 * L.nA * 12.0);
     launch_row_mp(L.mode, OP_RESID, L.mp.G, L.mp.kind, a, h->stream);
 }
 
@@ -254,11 +256,12 @@ static void jacobi_mp(amg_ctx *h, int l, const float *b, float *x, bool zero) {
         h->level_omega.empty() ? h->prm.omega : h->level_omega[std::min<size_t>(l, h->level_omega.size() - 1)]);
     const int nb = L.mode == 3 ? 9 : 1;
     if (zero) {
-        ProfScope ps(h, tag("jacobi0", l), 3.0 * L.n * 8.0 + nb * 4.0 * L.n);
-        launch_jacobi_zero_mp(L.mode, L.n, L.mp.dinv.p, b, om, x, h->stream);
+        ProfScope ps(h, tag("jacobi0", l), 3.0 * L.nA * 8.0 + nb * 4.0 * L.nA);
+        launch_jacobi_zero_mp(L.mode, L.nA, L.n, L.mp.dinv.p, b, om, x, h->stream);
         return;
     }
     RowArgsMP a = args_natural(L);
+    a.nrows = L.nA;
     a.x = x;
     a.b = b;
     a.y = L.mp.t.p;
@@ -266,10 +269,10 @@ static void jacobi_mp(amg_ctx *h, int l, const float *b, float *x, bool zero) {
     a.dinv_n = L.n;
     a.omega = om;
     {
-        ProfScope ps(h, tag("jacobi", l), mat_bytes(L, L.A.nnz, L.n) + 3.0 * L.n * 12.0 + nb * 4.0 * L.n);
+        ProfScope ps(h, tag("jacobi", l), mat_bytes(L, L.A.nnz, L.nA) + 3.0 * L.nA * 12.0 + nb * 4.0 * L.nA);
         launch_row_mp(L.mode, OP_JACOBI, L.mp.G, L.mp.kind, a, h->stream);
     }
-    launch_copy_f32(x, L.mp.t.p, 3 * static_cast<int64_t>(L.n), h->stream);
+    launch_copy_f32(x, L.mp.t.p, 3 * static_cast<int64_t>(L.nA), h->stream);
 }
 
 static void gs_mp(amg_ctx *h, int l, const float *b, float *x, bool forward, bool x_zero) {
@@ -310,7 +313,7 @@ static void smooth_mp(amg_ctx *h, int l, const float *b, float *x, bool pre, boo
     const int steps = pre ? p.pre : p.post;
     Level &L = h->lv[l];
     if (zero_init && !filled && (steps == 0 || p.smoother != AMG_SMOOTH_JA))
-        launch_fill_f32(x, 0.f, 3 * static_cast<int64_t>(L.n), h->stream);
+        launch_fill_f32(x, 0.f, 3 * static_cast<int64_t>(L.nA), h->stream);
     for (int k = 0; k < steps; ++k) {
         if (p.smoother == AMG_SMOOTH_JA)
             jacobi_mp(h, l, b, x, zero_init && k == 0);
@@ -331,10 +334,25 @@ static void coarse_mp(amg_ctx *h, int l, const float *b, float *x) {
     launch_to_f32(L.x.p, x, nv, h->stream);
 }
 
+// a batch of SPD systems: the systems ending on level l (its rows past nA)
+// by their FP64 explicit inverses, as the single-system coarsest level
+static void ending_systems_mp(amg_ctx *h, int l, const float *b, float *x) {
+    Level &L = h->lv[l];
+    if (L.dseg.count == 0) return;
+    const int64_t a0 = 3 * static_cast<int64_t>(L.nA), m = 3 * static_cast<int64_t>(L.n) - a0;
+    launch_to_f64(b + a0, L.b.p + a0, m, h->stream);
+    {
+        ProfScope ps(h, "coarse", L.dseg.bytes);
+        launch_dense_segs<double>(L.dseg.view(), L.b.p, L.b.p, L.x.p, L.x.p, h->stream);
+    }
+    launch_to_f32(L.x.p + a0, x + a0, m, h->stream);
+}
+
 static void cycle_mp(amg_ctx *h, int l, const float *b, float *x, bool x_zero, bool filled) {
     Level &L = h->lv[l];
+    if (h->nsys > 0) ending_systems_mp(h, l, b, x);
     if (L.coarsest) {
-        coarse_mp(h, l, b, x);
+        if (h->nsys == 0) coarse_mp(h, l, b, x);
         return;
     }
     if (l == h->dense_start && x_zero) {
@@ -363,7 +381,8 @@ static void cycle_mp(amg_ctx *h, int l, const float *b, float *x, bool x_zero, b
         launch_row_mp(1, OP_SPMV, L.Gr, VAL_F32, a, h->stream);
     }
     if (C.coarsest) {
-        coarse_mp(h, l + 1, C.mp.b.p, C.mp.x.p);
+        if (h->nsys > 0) ending_systems_mp(h, l + 1, C.mp.b.p, C.mp.x.p);
+        else coarse_mp(h, l + 1, C.mp.b.p, C.mp.x.p);
     } else {
         const int nu = std::max(1, h->prm.nu);
         for (int k = 0; k < nu; ++k) cycle_mp(h, l + 1, C.mp.b.p, C.mp.x.p, k == 0, k == 0);

@@ -265,7 +265,8 @@ class AMGSolver:
 
 class BatchedSolver:
     """amg_setup_batched over several saddle point systems (FGMRES) or
-    several SPD systems (PCG, FP64 cycle); vectors are the systems' [u; p]
+    several SPD systems (PCG with the FP64 cycle, FCG with a reduced-precision
+    one, unless `krylov` says otherwise); vectors are the systems' [u; p]
     (SPD: u) one after another, in the order given."""
 
     def __init__(self, systems, smoother: str | None = None, cycles: int = 1, nu: int = 1,
@@ -284,7 +285,7 @@ class BatchedSolver:
         p.sgs_omega, p.sgs_damping = sgs_omega, sgs_damping
         p.cycles, p.nu = cycles, nu
         p.coarse_max, p.max_levels = coarse_max, max_levels
-        p.krylov = C.KRYLOV[krylov or ("PCG" if spd else "FGMRES")]
+        p.krylov = C.KRYLOV[krylov or (("PCG" if precision == "FP64" else "FCG") if spd else "FGMRES")]
         p.restart = restart
         p.graph = 1 if graph else 0
         p.precision = C.PREC[precision]

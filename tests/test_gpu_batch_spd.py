@@ -1,9 +1,10 @@
 """Batches of independent SPD systems of different size and depth merged
 into one hierarchy (amg_setup_batched / amg_solve_batched with every
-n_pres = 0): the merged cycle equals each system's own cycle, the lockstep
-PCG reproduces each system's own solve (within one iteration) and the
-oracle's solution, systems that are solved directly on the finest level,
-zero right-hand sides and the rejected configurations."""
+n_pres = 0): the merged cycle equals each system's own cycle (FP64, and the
+FP32 / BF16 cycles up to FP32 summation order), the lockstep PCG and FCG
+reproduce each system's own solve (within one iteration) and the oracle's
+solution, systems that are solved directly on the finest level, zero
+right-hand sides and the rejected configurations."""
 import numpy as np
 import pytest
 import scipy.sparse.linalg as spla
@@ -135,9 +136,81 @@ def test_zero_rhs_and_initial_guess():
     bs.close()
 
 
+@pytest.mark.parametrize("precision", ["MIXED", "FP32"])
+@pytest.mark.parametrize("smoother,nu", [("GS-1-1", 1), ("JA-1-1-0.5", 1), ("GS-1-1", 2)])
+def test_merged_reduced_cycle_is_every_system_own_cycle(batch, precision, smoother, nu):
+    """The FP32 / BF16 merged cycle against each system's own reduced cycle
+    (no assembled coarse end, heuristic launch shapes): the same rounded
+    operators, so they agree up to FP32 summation order (the merged levels'
+    lane counts follow the batch's mean row, not each system's)."""
+    name, systems = batch
+    bs = amg.BatchedSolver(systems, smoother=smoother, nu=nu, precision=precision, autotune=False)
+    uoff, _ = bs.offsets()
+    rng = np.random.default_rng(4)
+    rs = [rng.standard_normal(s.dofs) for s in systems]
+    merged = np.zeros(bs.n)
+    for s, r, o in zip(systems, rs, uoff):
+        merged[o:o + s.dofs] = r
+    z = torch.zeros(bs.n, dtype=torch.float64, device=DEV)
+    bs.precondition(dev(merged), z)
+    zm = host(z)
+    for s, r, o in zip(systems, rs, uoff):
+        one = amg.AMGSolver(s, smoother=smoother, krylov="FCG", nu=nu, precision=precision, fuse_coarse=False,
+                            autotune=False)
+        zo = torch.zeros(s.dofs, dtype=torch.float64, device=DEV)
+        one.precondition(dev(r), zo)
+        assert rel(zm[o:o + s.dofs], host(zo)) < 1e-5, (name, precision, smoother, s.dofs)
+        one.close()
+    bs.close()
+
+
+@pytest.mark.parametrize("precision", ["MIXED", "FP32", "FP64"])
+def test_batched_fcg_matches_single_solves(batch, precision):
+    """Lockstep flexible CG (the default Krylov method of a reduced-precision
+    batch): each system within one iteration of its own FCG solve with the
+    same cycle, at its FP64 solution."""
+    name, systems = batch
+    bs = amg.BatchedSolver(systems, smoother="GS-1-1", precision=precision, krylov="FCG")
+    b = np.concatenate([s.rhs for s in systems])
+    x = torch.zeros(bs.n, dtype=torch.float64, device=DEV)
+    res = bs.solve(dev(b), x, tol=TOL, maxit=300)
+    X = host(x)
+    o = 0
+    for s, r in zip(systems, res):
+        assert r.converged and r.relres <= TOL * 1.01, (name, precision, s.dofs, r)
+        one = amg.AMGSolver(s, smoother="GS-1-1", krylov="FCG", precision=precision, fuse_coarse=False)
+        x1 = torch.zeros(s.dofs, dtype=torch.float64, device=DEV)
+        r1 = one.solve(dev(s.rhs), x1, tol=TOL, maxit=300)
+        assert abs(r1.iters - r.iters) <= 1, (name, precision, s.dofs, r1.iters, r.iters)
+        ref = amg.AMGSolver(s, smoother="GS-1-1", krylov="PCG")
+        x2 = torch.zeros(s.dofs, dtype=torch.float64, device=DEV)
+        ref.solve(dev(s.rhs), x2, tol=1e-12, maxit=300)
+        assert rel(X[o:o + s.dofs], host(x2)) < 1e-7, (name, precision, s.dofs)
+        one.close()
+        ref.close()
+        o += s.dofs
+    bs.close()
+
+
+def test_reduced_batch_default_krylov_and_zero_rhs():
+    systems = BATCHES["elasticity"]()
+    bs = amg.BatchedSolver(systems, precision="MIXED")
+    assert bs.params.krylov == amg._lib.KRYLOV["FCG"]
+    b = [s.rhs.copy() for s in systems]
+    b[2][:] = 0.0
+    x = torch.zeros(sum(s.dofs for s in systems), dtype=torch.float64, device=DEV)
+    res = bs.solve(dev(np.concatenate(b)), x, tol=1e-8, maxit=300)
+    X = host(x)
+    assert res[2].converged and res[2].iters == 0
+    o = sum(s.dofs for s in systems[:2])
+    assert np.all(X[o:o + systems[2].dofs] == 0.0)
+    assert all(r.converged for r in res)
+    bs.close()
+
+
 def test_rejected_configurations():
     el = [amg.problems.elasticity(3), amg.problems.elasticity(4)]
-    for kw in (dict(precision="MIXED"), dict(krylov="FCG"), dict(smoother="sGS-1-1")):
+    for kw in (dict(krylov="FGMRES"), dict(smoother="sGS-1-1")):
         with pytest.raises(amg.AmgError):
             amg.BatchedSolver(el, **kw)
     with pytest.raises(amg.AmgError):

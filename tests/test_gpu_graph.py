@@ -62,8 +62,10 @@ def test_recorded_solves_and_preconditioners_are_bitwise_eager(name):
 def test_recorded_batch_is_bitwise_eager():
     systems = [amg.problems.stokes_cavity(4, 1.3), amg.problems.mixed_elasticity(3, nu=0.3),
                amg.problems.stokes_cavity(6, 0.6)]
-    eager = amg.BatchedSolver(systems, smoother="BS-1-1", graph=False)
-    rec = amg.BatchedSolver(systems, smoother="BS-1-1", graph=True)
+    # (no setup tuner: two tuned setups may pick different launch shapes,
+    # which changes rounding; the comparison is of graph against eager)
+    eager = amg.BatchedSolver(systems, smoother="BS-1-1", graph=False, autotune=False)
+    rec = amg.BatchedSolver(systems, smoother="BS-1-1", graph=True, autotune=False)
     b = dev(np.concatenate([s.rhs for s in systems]))
     for rep in range(2):
         xe, xr = torch.zeros_like(b), torch.zeros_like(b)
