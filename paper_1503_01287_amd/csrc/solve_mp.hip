@@ -250,7 +250,11 @@ static void residual_mp(amg_ctx *h, int l, const float *b, const float *x, float
     launch_row_mp(L.mode, OP_RESID, L.mp.G, L.mp.kind, a, h->stream);
 }
 
-static void jacobi_mp(amg_ctx *h, int l, const float *b, float *x, bool zero) {
+// One damped Jacobi step. The step reads x and writes its result out of
+// place: into the other buffer of the level's pair (mp.x, mp.t), which the
+// cycle then carries on with (returned), or, on a batch level whose rows past
+// nA hold ending systems that live in x only, into mp.t and back to x.
+static float *jacobi_mp(amg_ctx *h, int l, const float *b, float *x, bool zero) {
     Level &L = h->lv[l];
     const float om = static_cast<float>(
         h->level_omega.empty() ? h->prm.omega : h->level_omega[std::min<size_t>(l, h->level_omega.size() - 1)]);
@@ -258,13 +262,16 @@ static void jacobi_mp(amg_ctx *h, int l, const float *b, float *x, bool zero) {
     if (zero) {
         ProfScope ps(h, tag("jacobi0", l), 3.0 * L.nA * 8.0 + nb * 4.0 * L.nA);
         launch_jacobi_zero_mp(L.mode, L.nA, L.n, L.mp.dinv.p, b, om, x, h->stream);
-        return;
+        return x;
     }
+    const bool swap = L.nA == L.n;
+    float *out = swap && x == L.mp.t.p ? L.mp.x.p : L.mp.t.p;
+    AMG_REQUIRE(out != x, AMG_EINVAL, "jacobi_mp: output aliases the input");
     RowArgsMP a = args_natural(L);
     a.nrows = L.nA;
     a.x = x;
     a.b = b;
-    a.y = L.mp.t.p;
+    a.y = out;
     a.dinv = L.mp.dinv.p;
     a.dinv_n = L.n;
     a.omega = om;
@@ -272,7 +279,9 @@ static void jacobi_mp(amg_ctx *h, int l, const float *b, float *x, bool zero) {
         ProfScope ps(h, tag("jacobi", l), mat_bytes(L, L.A.nnz, L.nA) + 3.0 * L.nA * 12.0 + nb * 4.0 * L.nA);
         launch_row_mp(L.mode, OP_JACOBI, L.mp.G, L.mp.kind, a, h->stream);
     }
-    launch_copy_f32(x, L.mp.t.p, 3 * static_cast<int64_t>(L.nA), h->stream);
+    if (swap) return out;
+    launch_copy_f32(x, out, 3 * static_cast<int64_t>(L.nA), h->stream);
+    return x;
 }
 
 static void gs_mp(amg_ctx *h, int l, const float *b, float *x, bool forward, bool x_zero) {
@@ -308,7 +317,8 @@ static void gs_mp(amg_ctx *h, int l, const float *b, float *x, bool forward, boo
     }
 }
 
-static void smooth_mp(amg_ctx *h, int l, const float *b, float *x, bool pre, bool zero_init, bool filled) {
+// returns the buffer holding x_l afterwards (Jacobi steps alternate buffers)
+static float *smooth_mp(amg_ctx *h, int l, const float *b, float *x, bool pre, bool zero_init, bool filled) {
     const amg_params &p = h->prm;
     const int steps = pre ? p.pre : p.post;
     Level &L = h->lv[l];
@@ -316,10 +326,11 @@ static void smooth_mp(amg_ctx *h, int l, const float *b, float *x, bool pre, boo
         launch_fill_f32(x, 0.f, 3 * static_cast<int64_t>(L.nA), h->stream);
     for (int k = 0; k < steps; ++k) {
         if (p.smoother == AMG_SMOOTH_JA)
-            jacobi_mp(h, l, b, x, zero_init && k == 0);
+            x = jacobi_mp(h, l, b, x, zero_init && k == 0);
         else
             gs_mp(h, l, b, x, pre || h->post_forward, pre && zero_init && k == 0);
     }
+    return x;
 }
 
 // coarsest level: the FP64 explicit inverse
@@ -348,12 +359,16 @@ static void ending_systems_mp(amg_ctx *h, int l, const float *b, float *x) {
     launch_to_f32(L.x.p + a0, x + a0, m, h->stream);
 }
 
-static void cycle_mp(amg_ctx *h, int l, const float *b, float *x, bool x_zero, bool filled) {
+// Algorithm 1 on level l from x (zero on entry if x_zero; filled: its
+// buffer holds the zeros). Returns the buffer that holds x_l on return: x,
+// or the other buffer of the level's pair after an odd number of Jacobi
+// steps.
+static float *cycle_mp(amg_ctx *h, int l, const float *b, float *x, bool x_zero, bool filled) {
     Level &L = h->lv[l];
     if (h->nsys > 0) ending_systems_mp(h, l, b, x);
     if (L.coarsest) {
         if (h->nsys == 0) coarse_mp(h, l, b, x);
-        return;
+        return x;
     }
     if (l == h->dense_start && x_zero) {
         const bool bf = h->tail_dense16.n > 0;
@@ -362,9 +377,9 @@ static void cycle_mp(amg_ctx *h, int l, const float *b, float *x, bool x_zero, b
             launch_dense_gemv_bf16(h->tail_dense16.p, h->tail_m, h->tail_ld, h->tail_nc, b, x, h->stream);
         else
             launch_dense_gemv_f32(h->tail_dense32.p, h->tail_m, h->tail_ld, h->tail_nc, b, x, h->stream);
-        return;
+        return x;
     }
-    smooth_mp(h, l, b, x, true, x_zero, filled);
+    x = smooth_mp(h, l, b, x, true, x_zero, filled);
     residual_mp(h, l, b, x, L.mp.r.p);
     Level &C = h->lv[l + 1];
     {
@@ -380,12 +395,13 @@ static void cycle_mp(amg_ctx *h, int l, const float *b, float *x, bool x_zero, b
         ProfScope ps(h, tag("restrict", l), L.R.nnz * 8.0 + 3.0 * (L.n + 2 * C.n) * 4.0);
         launch_row_mp(1, OP_SPMV, L.Gr, VAL_F32, a, h->stream);
     }
+    float *e = C.mp.x.p;
     if (C.coarsest) {
-        if (h->nsys > 0) ending_systems_mp(h, l + 1, C.mp.b.p, C.mp.x.p);
-        else coarse_mp(h, l + 1, C.mp.b.p, C.mp.x.p);
+        if (h->nsys > 0) ending_systems_mp(h, l + 1, C.mp.b.p, e);
+        else coarse_mp(h, l + 1, C.mp.b.p, e);
     } else {
         const int nu = std::max(1, h->prm.nu);
-        for (int k = 0; k < nu; ++k) cycle_mp(h, l + 1, C.mp.b.p, C.mp.x.p, k == 0, k == 0);
+        for (int k = 0; k < nu; ++k) e = cycle_mp(h, l + 1, C.mp.b.p, e, k == 0, k == 0);
     }
     {
         RowArgsMP a;
@@ -394,12 +410,12 @@ static void cycle_mp(amg_ctx *h, int l, const float *b, float *x, bool x_zero, b
         a.col = L.P.col.p;
         a.val = L.mp.pval.p;
         a.nnz = L.P.nnz;
-        a.x = C.mp.x.p;
+        a.x = e;
         a.y = x;
         ProfScope ps(h, tag("prolong", l), L.P.nnz * 8.0 + 3.0 * (2.0 * L.n + C.n) * 4.0);
         launch_row_mp(1, OP_SPMV_ADD, L.Gp, VAL_F32, a, h->stream);
     }
-    smooth_mp(h, l, b, x, false, false, false);
+    return smooth_mp(h, l, b, x, false, false, false);
 }
 
 void precondition_mp(amg_ctx *h, const double *r, double *z) {
@@ -407,8 +423,9 @@ void precondition_mp(amg_ctx *h, const double *r, double *z) {
     const int64_t nv = 3 * static_cast<int64_t>(L.n);
     launch_to_f32(r, L.mp.b.p, nv, h->stream);
     const int cyc = std::max(1, h->prm.cycles);
-    for (int k = 0; k < cyc; ++k) cycle_mp(h, 0, L.mp.b.p, L.mp.x.p, k == 0, false);
-    launch_to_f64(L.mp.x.p, z, nv, h->stream);
+    float *x = L.mp.x.p;
+    for (int k = 0; k < cyc; ++k) x = cycle_mp(h, 0, L.mp.b.p, x, k == 0, false);
+    launch_to_f64(x, z, nv, h->stream);
 }
 
 }  // namespace amgp2
