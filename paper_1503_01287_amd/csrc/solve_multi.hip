@@ -65,22 +65,25 @@ struct MCycle {
             launch_copy(reinterpret_cast<double *>(dst), reinterpret_cast<const double *>(src), n, h->stream);
     }
 
-    void jacobi(int l, const T *b, T *x, bool zero) {
+    // one damped Jacobi step, out of place into the other buffer of the
+    // level's pair (vt, or vx when x is vt); returns the buffer with the result
+    T *jacobi(int l, const T *b, T *x, bool zero) {
         Level &L = h->lv[l];
         const double om = mlevel_omega(h, l);
         if (zero) {
             launch_mjacobi_zero(L.mode, RP ? MK_F32 : MK_F64, K, L.n, dinv(L), b, om, x, h->stream);
-            return;
+            return x;
         }
+        T *out = x == vt(l) ? vx(l) : vt(l);
         MRowArgs a = natural(L);
         a.x = x;
         a.b = b;
-        a.y = vt(l);
+        a.y = out;
         a.dinv = dinv(L);
         a.dinv_n = L.n;
         a.omega = om;
         launch_mrow(L.mode, M_JACOBI, kind(L), K, a, h->stream);
-        copy(x, vt(l), len(l));
+        return out;
     }
 
     void gs(int l, const T *b, T *x, bool forward, bool x_zero) {
@@ -112,16 +115,17 @@ struct MCycle {
         }
     }
 
-    void smooth(int l, const T *b, T *x, bool pre, bool zero_init) {
+    T *smooth(int l, const T *b, T *x, bool pre, bool zero_init) {
         const amg_params &p = h->prm;
         const int steps = pre ? p.pre : p.post;
         if (zero_init && (steps == 0 || p.smoother != AMG_SMOOTH_JA)) fill0(x, len(l));
         for (int k = 0; k < steps; ++k) {
             if (p.smoother == AMG_SMOOTH_JA)
-                jacobi(l, b, x, zero_init && k == 0);
+                x = jacobi(l, b, x, zero_init && k == 0);
             else
                 gs(l, b, x, pre, pre && zero_init && k == 0);
         }
+        return x;
     }
 
     // the coarsest level: the FP64 explicit inverse on all K columns
@@ -137,11 +141,12 @@ struct MCycle {
         }
     }
 
-    void cycle(int l, const T *b, T *x, bool x_zero) {
+    // returns the buffer that holds x_l on return (Jacobi steps alternate)
+    T *cycle(int l, const T *b, T *x, bool x_zero) {
         Level &L = h->lv[l];
         if (L.coarsest) {
             coarse(l, b, x);
-            return;
+            return x;
         }
         if (l == h->dense_start && x_zero) {
             const int nc = h->tail_nc * K;
@@ -151,9 +156,9 @@ struct MCycle {
                 launch_mdense(MK_BF16, h->tail_dense16.p, h->tail_m, h->tail_ld, nc, b, x, h->stream);
             else
                 launch_mdense(MK_F32, h->tail_dense32.p, h->tail_m, h->tail_ld, nc, b, x, h->stream);
-            return;
+            return x;
         }
-        smooth(l, b, x, true, x_zero);
+        x = smooth(l, b, x, true, x_zero);
         {
             MRowArgs a = natural(L);
             a.x = x;
@@ -174,11 +179,12 @@ struct MCycle {
             a.zero_out = vx(l + 1);
             launch_mrow(1, M_SPMV, RP ? MK_F32 : MK_F64, K, a, h->stream);
         }
+        T *e = vx(l + 1);
         if (C.coarsest) {
-            coarse(l + 1, vb(l + 1), vx(l + 1));
+            coarse(l + 1, vb(l + 1), e);
         } else {
             const int nu = std::max(1, h->prm.nu);
-            for (int k = 0; k < nu; ++k) cycle(l + 1, vb(l + 1), vx(l + 1), k == 0);
+            for (int k = 0; k < nu; ++k) e = cycle(l + 1, vb(l + 1), e, k == 0);
         }
         {
             MRowArgs a;
@@ -187,11 +193,11 @@ struct MCycle {
             a.col = L.P.col.p;
             a.val = RP ? static_cast<const void *>(L.mp.pval.p) : static_cast<const void *>(L.P.val.p);
             a.nnz = L.P.nnz;
-            a.x = vx(l + 1);
+            a.x = e;
             a.y = x;
             launch_mrow(1, M_SPMV_ADD, RP ? MK_F32 : MK_F64, K, a, h->stream);
         }
-        smooth(l, b, x, false, false);
+        return smooth(l, b, x, false, false);
     }
 
     // z = M^{-1} r on FP64 blocks of the finest level
@@ -200,11 +206,14 @@ struct MCycle {
         const int cyc = std::max(1, h->prm.cycles);
         if (RP) {
             launch_to_f32(r, W.lv[0].b32.p, n, h->stream);
-            for (int k = 0; k < cyc; ++k)
-                cycle(0, reinterpret_cast<const T *>(W.lv[0].b32.p), reinterpret_cast<T *>(W.lv[0].x32.p), k == 0);
-            launch_to_f64(W.lv[0].x32.p, z, n, h->stream);
+            T *x = reinterpret_cast<T *>(W.lv[0].x32.p);
+            for (int k = 0; k < cyc; ++k) x = cycle(0, reinterpret_cast<const T *>(W.lv[0].b32.p), x, k == 0);
+            launch_to_f64(reinterpret_cast<const float *>(x), z, n, h->stream);
         } else {
-            for (int k = 0; k < cyc; ++k) cycle(0, reinterpret_cast<const T *>(r), reinterpret_cast<T *>(z), k == 0);
+            // (z pairs with the level's t buffer; the result ends in z)
+            T *x = reinterpret_cast<T *>(z);
+            for (int k = 0; k < cyc; ++k) x = cycle(0, reinterpret_cast<const T *>(r), x, k == 0);
+            if (x != reinterpret_cast<T *>(z)) copy(reinterpret_cast<T *>(z), x, n);
         }
     }
 };
