@@ -307,7 +307,6 @@ void build_batch(amg_ctx *h, int nsys, const amg_system *sys) {
         M.Gg = M.G;
         M.Gb = lanes_of(M.B.nnz, M.B.nrows);
         M.Gbt = lanes_of(M.Bt.nnz, M.Bt.nrows);
-        M.Gc = M.C.nnz > 0 ? lanes_of(M.C.nnz, M.C.nrows) : 4;
         M.Gp = lanes_of(M.P.nnz, M.P.nrows);
         M.Gr = lanes_of(M.R.nnz, M.R.nrows);
         M.Gh = lanes_of(M.H.nnz, M.H.nrows);

@@ -183,7 +183,7 @@ struct Level {
     std::vector<int> sys_noff, sys_n, sys_poff, sys_np;
     SchurHier schur;          // BS: scalar hierarchy of this level's Schur complement
     VankaData vanka;          // multiplicative Vanka patches
-    int Gb = 16, Gbt = 16, Gc = 8, Gh = 4, Ght = 8;
+    int Gb = 16, Gbt = 16, Gh = 4, Ght = 8;
     int64_t vlen() const { return 3 * static_cast<int64_t>(n) + n_pres; }
 };
 

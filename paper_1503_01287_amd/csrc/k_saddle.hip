@@ -53,23 +53,48 @@ __global__ void __launch_bounds__(SB) k_blk(const BlkArgsT<T> a) {
     }
 #pragma unroll
     for (int r = 0; r < BR; ++r) s[r] = gsum<G>(s[r]);
+    // the fused scalar C row (a uniform choice over the grid)
+    T sc = T(0);
+    if constexpr (BR == 1 && (OP == BLK_RESID || OP == BLK_SPMV)) {
+        if (a.c_rowptr) {
+            if (active) {
+                const int cb = a.c_rowptr[i], ce = a.c_rowptr[i + 1];
+                for (int k = cb + lane; k < ce; k += G) sc += a.c_val[k] * a.c_x[a.c_col[k]];
+            }
+            sc = gsum<G>(sc);
+        }
+    }
     if (!ep) return;
     const int r = lane;
     T sv = s[0];
 #pragma unroll
     for (int q = 1; q < BR; ++q)
         if (r == q) sv = s[q];
-    if constexpr (OP == BLK_SPMV) a.y[o] = sv;
-    else if constexpr (OP == BLK_ADD) a.y[o] = yo + sv;
-    else if constexpr (OP == BLK_SUB) a.y[o] = yo - sv;
-    else if constexpr (OP == BLK_RESID) a.y[o] = bo - sv;
-    else a.y[o] = yo + a.omega * ds * (sv - bo);
+    if constexpr (OP == BLK_SPMV) {
+        T v = sv;
+        if constexpr (BR == 1)
+            if (a.c_rowptr) v = v + a.c_sign * sc;
+        a.y[o] = v;
+    } else if constexpr (OP == BLK_ADD) {
+        a.y[o] = yo + sv;
+    } else if constexpr (OP == BLK_SUB) {
+        a.y[o] = yo - sv;
+    } else if constexpr (OP == BLK_RESID) {
+        T v = bo - sv;
+        if constexpr (BR == 1)
+            if (a.c_rowptr) v = v + a.c_sign * sc;
+        a.y[o] = v;
+    } else {
+        a.y[o] = yo + a.omega * ds * (sv - bo);
+    }
 }
 
 template <typename T, int BR, int BC, int G>
 static void launch_blk_g(int op, const BlkArgsT<T> &a, hipStream_t s) {
     const int nb = ceil_div(static_cast<int64_t>(a.nrows) * G, SB);
     if (nb == 0) return;
+    AMG_REQUIRE(!a.c_rowptr || (BR == 1 && (op == BLK_RESID || op == BLK_SPMV) && a.c_col && a.c_val && a.c_x),
+                AMG_EINVAL, "block kernel: a fused C row needs 1-row blocks and BLK_RESID or BLK_SPMV");
     switch (op) {
         case BLK_SPMV: k_blk<T, BR, BC, G, BLK_SPMV><<<nb, SB, 0, s>>>(a); break;
         case BLK_ADD: k_blk<T, BR, BC, G, BLK_ADD><<<nb, SB, 0, s>>>(a); break;

@@ -31,6 +31,13 @@ struct BlkArgsT {
     T *y = nullptr;
     const T *dscale = nullptr;
     T omega = 1;
+    // optional scalar operator on the same rows (1x3 B rows only, with
+    // BLK_RESID or BLK_SPMV): y_i = (result) + c_sign (C c_x)_i, the C row
+    // read by the same lanes after the B row
+    const int *c_rowptr = nullptr, *c_col = nullptr;
+    const T *c_val = nullptr;
+    const T *c_x = nullptr;
+    T c_sign = 1;
 };
 using BlkArgs = BlkArgsT<double>;
 using BlkArgsF = BlkArgsT<float>;

@@ -35,7 +35,6 @@ void saddle_setup_level(amg_ctx *h, Level &L) {
     hipStream_t s = h->stream;
     L.Gb = lanes(L.B.nnz, L.B.nrows);
     L.Gbt = lanes(L.Bt.nnz, L.Bt.nrows);
-    L.Gc = L.C.nnz > 0 ? lanes(L.C.nnz, L.C.nrows) : 4;
     L.sgs_scale.alloc(std::max(1, L.n_pres));
     launch_sgs_scale(L.n_pres, L.B.rowptr.p, L.B.col.p, L.B.val.p, L.B.nnz, L.dinv.p, L.n, h->prm.sgs_damping,
                      L.C.nnz > 0 ? L.C.rowptr.p : nullptr, L.C.col.p, L.C.val.p, L.C.nnz, L.sgs_scale.p, s);
@@ -210,19 +209,20 @@ static void saddle_residual_rows(amg_ctx *h, int l, const T *b, const T *x, T *r
     bt.x = x + nu;
     bt.y = r;
     launch_blk<T>(3, 1, BLK_SUB, L.Gbt, bt, h->stream);
+    // g - B u + C p in one pass over the pressure rows
     BlkArgsT<T> bb = blkT<T>(L.B, SV<T>::B(L));
     bb.nrows = nrows_p;
     bb.x = x;
     bb.b = b + nu;
     bb.y = r + nu;
-    launch_blk<T>(1, 3, BLK_RESID, L.Gb, bb, h->stream);
     if (L.C.nnz > 0) {
-        BlkArgsT<T> cc = blkT<T>(L.C, SV<T>::C(L));
-        cc.nrows = nrows_p;
-        cc.x = x + nu;
-        cc.y = r + nu;
-        launch_blk<T>(1, 1, BLK_ADD, L.Gc, cc, h->stream);
+        bb.c_rowptr = L.C.rowptr.p;
+        bb.c_col = L.C.col.p;
+        bb.c_val = SV<T>::C(L);
+        bb.c_x = x + nu;
+        bb.c_sign = T(1);
     }
+    launch_blk<T>(1, 3, BLK_RESID, L.Gb, bb, h->stream);
 }
 
 static void saddle_residual(amg_ctx *h, int l, const double *b, const double *x, double *r) {
@@ -250,16 +250,18 @@ void saddle_apply(amg_ctx *h, int l, const double *x, double *y) {
     bt.x = x + nu;
     bt.y = y;
     launch_blk(3, 1, BLK_ADD, L.Gbt, bt, h->stream);
+    // B u - C p in one pass over the pressure rows
     BlkArgs bb = blk(L.B);
     bb.x = x;
     bb.y = y + nu;
-    launch_blk(1, 3, BLK_SPMV, L.Gb, bb, h->stream);
     if (L.C.nnz > 0) {
-        BlkArgs cc = blk(L.C);
-        cc.x = x + nu;
-        cc.y = y + nu;
-        launch_blk(1, 1, BLK_SUB, L.Gc, cc, h->stream);
+        bb.c_rowptr = L.C.rowptr.p;
+        bb.c_col = L.C.col.p;
+        bb.c_val = L.C.val.p;
+        bb.c_x = x + nu;
+        bb.c_sign = -1.0;
     }
+    launch_blk(1, 3, BLK_SPMV, L.Gb, bb, h->stream);
 }
 
 // One segregated Gauss-Seidel step (reading of Section 3.3: K_hat =
