@@ -213,12 +213,23 @@ SETUP_PHASES = ("upload", "coarsen", "galerkin", "omega_network", "drop_zeros", 
 
 def setup_breakdown(solver) -> dict:
     """Wall ms per setup phase (the library records them at every setup) and
-    the Galerkin numeric kernels' rate."""
+    the Galerkin numeric kernels' rate. A batch sets its systems up on
+    several host threads: "systems" is that step's wall ms, and
+    "systems_summed" its systems' own phases summed over them."""
     out = {}
     for ph in SETUP_PHASES:
         r = solver.profile_read("setup." + ph)
         if r["launches"]:
             out[ph] = round(r["ms"], 1)
+    r = solver.profile_read("setup.systems")
+    if r["launches"]:
+        out["systems"] = round(r["ms"], 1)
+        summed = {}
+        for ph in SETUP_PHASES:
+            q = solver.profile_read("setup.systems." + ph)
+            if q["launches"]:
+                summed[ph] = round(q["ms"], 1)
+        out["systems_summed"] = summed
     g = solver.profile_read("setup.spgemm_numeric")
     if g["launches"]:
         gbps = g["bytes"] / max(g["ms"] * 1e-3, 1e-12) / 1e9

@@ -461,8 +461,10 @@ int amg_profile_enable(amg_handle h, int32_t enable);
  * host), galerkin (the Galerkin products), omega_network, drop_zeros,
  * smoother (diagonal inverses, colouring, colour-grouped copies, saddle
  * scalings), autotune, coarsest (dense inverse), omega_bound, schur,
- * schur_map, vanka, coarse_map, reduced_copies, saddle_map, merge (batches;
- * a batch also sums its systems' own phases): calls and wall ms.
+ * schur_map, vanka, coarse_map, reduced_copies, saddle_map, merge
+ * (batches): calls and wall ms. A batch sets its systems up concurrently on
+ * several host threads: "setup.systems" is the wall ms of that step and
+ * "setup.systems.<phase>" the systems' own phases, summed over them.
  * "setup.spgemm_numeric": the Galerkin numeric kernels' HIP-event ms and
  * algorithmic bytes (both factors and the product's pattern read once, its
  * values written once). */

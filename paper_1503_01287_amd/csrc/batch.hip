@@ -12,10 +12,13 @@
 // serves the whole batch. The outer flexible GMRES keeps per-system inner
 // products, Hessenberg matrices, convergence tests and iteration counts.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
+#include <exception>
 #include <memory>
 #include <numeric>
+#include <thread>
 
 #include "context.h"
 
@@ -100,6 +103,70 @@ static void add_chunks(int64_t base, int64_t len, int q, std::vector<int64_t> &s
     }
 }
 
+// Every system's own hierarchy (amg_setup's, with the batch's overrides in
+// `inst`), built by a pool of host threads, each with a stream of its own:
+// the systems' host passes (independent sets, colourings, dense inverses)
+// run on several cores and their kernels overlap on the GPU. Each build is
+// the same as alone (no timed choices: the systems' tuners are off), so the
+// result does not depend on the schedule. The first failing system (lowest
+// index) reports its error. The phase "systems" is the wall time of the
+// step; the systems' own phases are summed into h as "systems.<phase>"
+// (time summed over the threads), their Galerkin kernels' statistics as
+// the batch's own.
+static void build_instances(amg_ctx *h, int nsys, const amg_system *sys,
+                            std::vector<std::unique_ptr<amg_ctx>> &inst) {
+    SetupPhase ph(h, "systems");
+    const int hw = static_cast<int>(std::thread::hardware_concurrency());
+    const int nthreads = std::max(1, std::min({nsys, hw > 0 ? hw : 1, 16}));
+    int dev = 0;
+    AMG_HIP(hipGetDevice(&dev));
+    std::atomic<int> next{0};
+    std::vector<std::exception_ptr> err(nsys);
+    auto work = [&]() {
+        hipStream_t st = nullptr;
+        try {
+            AMG_HIP(hipSetDevice(dev));
+            AMG_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        } catch (...) {
+            const int i = next.fetch_add(1);
+            if (i < nsys) err[i] = std::current_exception();
+            next = nsys;
+            return;
+        }
+        for (int i; (i = next.fetch_add(1)) < nsys;) {
+            try {
+                inst[i]->stream = st;
+                build_hierarchy(inst[i].get(), &sys[i]);
+                AMG_HIP(hipStreamSynchronize(st));
+            } catch (...) {
+                err[i] = std::current_exception();
+                (void)hipStreamSynchronize(st);
+                next = nsys;  // the others stop taking systems
+            }
+            inst[i]->stream = h->stream;
+        }
+        (void)hipStreamDestroy(st);
+    };
+    if (nthreads == 1) {
+        work();
+    } else {
+        std::vector<std::thread> pool;
+        for (int t = 0; t < nthreads; ++t) pool.emplace_back(work);
+        for (auto &t : pool) t.join();
+    }
+    for (auto &e : err)
+        if (e) std::rethrow_exception(e);
+    const std::string pre = "setup.";
+    for (const auto &in : inst)
+        for (const auto &kv : in->setup_stats) {
+            const bool phase = kv.first.compare(0, pre.size(), pre) == 0 && kv.first != "setup.spgemm_numeric";
+            ProfStat &st = h->setup_stats[phase ? "setup.systems." + kv.first.substr(pre.size()) : kv.first];
+            st.launches += kv.second.launches;
+            st.ms += kv.second.ms;
+            st.bytes += kv.second.bytes;
+        }
+}
+
 void build_batch(amg_ctx *h, int nsys, const amg_system *sys) {
     hipStream_t s = h->stream;
     const amg_params &p = h->prm;
@@ -114,16 +181,9 @@ void build_batch(amg_ctx *h, int nsys, const amg_system *sys) {
         inst[i]->prm.precision = AMG_PREC_FP64;  // the merged hierarchy is converted once
         inst[i]->batch_member = true;            // explicit Schur tails are assembled once, merged
         inst[i]->stream = s;
-        build_hierarchy(inst[i].get(), &sys[i]);
-        depth[i] = static_cast<int>(inst[i]->lv.size()) - 1;
-        // the systems' own setup phases, summed
-        for (const auto &kv : inst[i]->setup_stats) {
-            ProfStat &st = h->setup_stats[kv.first];
-            st.launches += kv.second.launches;
-            st.ms += kv.second.ms;
-            st.bytes += kv.second.bytes;
-        }
     }
+    build_instances(h, nsys, sys, inst);
+    for (int i = 0; i < nsys; ++i) depth[i] = static_cast<int>(inst[i]->lv.size()) - 1;
     auto ph_merge = std::make_unique<SetupPhase>(h, "merge");
     std::vector<int> order(nsys);
     std::iota(order.begin(), order.end(), 0);
@@ -443,15 +503,9 @@ void build_batch_spd(amg_ctx *h, int nsys, const amg_system *sys) {
         inst[i]->prm.fuse_coarse = 0;  // each system's coarse levels are merged, not assembled
         inst[i]->batch_member = true;
         inst[i]->stream = s;
-        build_hierarchy(inst[i].get(), &sys[i]);
-        depth[i] = static_cast<int>(inst[i]->lv.size()) - 1;
-        for (const auto &kv : inst[i]->setup_stats) {
-            ProfStat &st = h->setup_stats[kv.first];
-            st.launches += kv.second.launches;
-            st.ms += kv.second.ms;
-            st.bytes += kv.second.bytes;
-        }
     }
+    build_instances(h, nsys, sys, inst);
+    for (int i = 0; i < nsys; ++i) depth[i] = static_cast<int>(inst[i]->lv.size()) - 1;
     auto ph_merge = std::make_unique<SetupPhase>(h, "merge");
     std::vector<int> order(nsys);
     std::iota(order.begin(), order.end(), 0);

@@ -9,7 +9,9 @@
 // segment, and the 3 partial sums are reduced across the group with
 // cross-lane shuffles.
 #include <cstring>
+#include <memory>
 #include <mutex>
+#include <vector>
 
 #include "common.h"
 #include "kernels.h"
@@ -270,32 +272,79 @@ __global__ void k_copy(double *d, const double *src, int64_t n) {
         d[i] = src[i];
 }
 
+// Pinned staging buffer pairs for copy_h2d, kept until the process ends:
+// one per concurrent caller (the batch setup uploads its systems from
+// several threads), created on first need. The events that order a pair's
+// reuse inside one call are the call's own: an event last recorded on
+// another caller's stream (which may since have been destroyed) is never
+// waited on.
+namespace {
+struct Staging {
+    char *pin[2] = {nullptr, nullptr};
+};
+constexpr size_t STAGING_CHUNK = 8u << 20;
+std::mutex staging_mu;
+std::vector<Staging *> staging_free;
+
+Staging *staging_acquire() {
+    {
+        std::lock_guard<std::mutex> lock(staging_mu);
+        if (!staging_free.empty()) {
+            Staging *st = staging_free.back();
+            staging_free.pop_back();
+            return st;
+        }
+    }
+    auto st = std::make_unique<Staging>();
+    for (int i = 0; i < 2; ++i)
+        AMG_HIP(hipHostMalloc(reinterpret_cast<void **>(&st->pin[i]), STAGING_CHUNK, hipHostMallocPortable));
+    return st.release();
+}
+
+void staging_release(Staging *st) {
+    std::lock_guard<std::mutex> lock(staging_mu);
+    staging_free.push_back(st);
+}
+}  // namespace
+
 void copy_h2d(void *dst, const void *src, size_t bytes, hipStream_t s) {
-    constexpr size_t SMALL = 1u << 18, CHUNK = 8u << 20;
+    constexpr size_t SMALL = 1u << 18;
     if (bytes == 0) return;
     if (bytes <= SMALL) {
         AMG_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
         AMG_HIP(hipStreamSynchronize(s));
         return;
     }
-    static std::mutex mu;
-    static char *pin[2] = {nullptr, nullptr};
-    static hipEvent_t done[2];
-    std::lock_guard<std::mutex> lock(mu);
-    if (!pin[0])
-        for (int i = 0; i < 2; ++i) {
-            AMG_HIP(hipHostMalloc(reinterpret_cast<void **>(&pin[i]), CHUNK, hipHostMallocPortable));
-            AMG_HIP(hipEventCreateWithFlags(&done[i], hipEventDisableTiming));
+    // (declared before the staging pair: destroyed after its release, which
+    // synchronises the stream first)
+    struct Events {
+        hipEvent_t e[2] = {nullptr, nullptr};
+        ~Events() {
+            for (hipEvent_t x : e)
+                if (x) (void)hipEventDestroy(x);
         }
+    } done;
+    for (int i = 0; i < 2; ++i) AMG_HIP(hipEventCreateWithFlags(&done.e[i], hipEventDisableTiming));
+    Staging *st = staging_acquire();
+    struct Release {
+        Staging *st;
+        hipStream_t s;
+        ~Release() {
+            (void)hipStreamSynchronize(s);  // no DMA from the pair is left in flight
+            staging_release(st);
+        }
+    } release{st, s};
     const char *from = static_cast<const char *>(src);
     char *to = static_cast<char *>(dst);
+    bool live[2] = {false, false};
     int half = 0;
-    for (size_t off = 0; off < bytes; off += CHUNK, half ^= 1) {
-        const size_t nb = std::min(CHUNK, bytes - off);
-        AMG_HIP(hipEventSynchronize(done[half]));  // this half's previous DMA has finished
-        std::memcpy(pin[half], from + off, nb);
-        AMG_HIP(hipMemcpyAsync(to + off, pin[half], nb, hipMemcpyHostToDevice, s));
-        AMG_HIP(hipEventRecord(done[half], s));
+    for (size_t off = 0; off < bytes; off += STAGING_CHUNK, half ^= 1) {
+        const size_t nb = std::min(STAGING_CHUNK, bytes - off);
+        if (live[half]) AMG_HIP(hipEventSynchronize(done.e[half]));  // this half's previous DMA has finished
+        std::memcpy(st->pin[half], from + off, nb);
+        AMG_HIP(hipMemcpyAsync(to + off, st->pin[half], nb, hipMemcpyHostToDevice, s));
+        AMG_HIP(hipEventRecord(done.e[half], s));
+        live[half] = true;
     }
     AMG_HIP(hipStreamSynchronize(s));
 }

@@ -217,3 +217,31 @@ def test_rejected_configurations():
         amg.BatchedSolver([amg.problems.elasticity(3), amg.problems.laplace(3)])
     with pytest.raises(amg.AmgError):
         amg.BatchedSolver([amg.problems.elasticity(3), amg.problems.stokes_cavity(3, 1.0)])
+
+
+def test_concurrent_setup_phases_and_repeatability():
+    """The systems of a batch are set up on several host threads: the setup
+    records the step's wall time and the systems' own phases summed, and two
+    setups of one batch (no tuner) give the same preconditioner bit for bit."""
+    systems = BATCHES["elasticity"]()
+    a = amg.BatchedSolver(systems, smoother="GS-1-1", autotune=False)
+    b = amg.BatchedSolver(systems, smoother="GS-1-1", autotune=False)
+    wall = a.profile_read("setup.systems")
+    assert wall["launches"] == 1 and wall["ms"] > 0.0
+    for ph in ("upload", "coarsest"):  # once per system
+        assert a.profile_read("setup.systems." + ph)["launches"] == len(systems), ph
+    for ph in ("coarsen", "galerkin", "smoother"):  # per level of the systems that coarsen
+        assert a.profile_read("setup.systems." + ph)["launches"] >= 1, ph
+        assert a.profile_read("setup." + ph)["launches"] == 0, ph
+    assert a.profile_read("setup.merge")["launches"] == 1
+    single = amg.AMGSolver(systems[0], smoother="GS-1-1", krylov="PCG")
+    assert single.profile_read("setup.systems")["launches"] == 0
+    single.close()
+    r = dev(np.random.default_rng(9).standard_normal(a.n))
+    za, zb = torch.zeros_like(r), torch.zeros_like(r)
+    a.precondition(r, za)
+    b.precondition(r, zb)
+    torch.cuda.synchronize()
+    assert torch.equal(za, zb)
+    a.close()
+    b.close()

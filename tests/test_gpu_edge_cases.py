@@ -151,3 +151,33 @@ def test_malformed_systems_are_rejected(case):
         bad = dataclasses.replace(hs, bs=2)
     with pytest.raises(amg.AmgError):
         amg.AMGSolver(bad, smoother="GS-1-1")
+
+
+def test_malformed_system_in_a_batch_is_rejected():
+    """The systems of a batch are set up concurrently; the error reported is
+    the one of the lowest-numbered failing system, as in a sequential setup."""
+    good = [amg.problems.laplace(3, i=k) for k in range(6)]
+    rp, col = good[1].A_rowptr, good[1].A_col.copy()
+    col[rp[3]] = good[1].nodes  # column out of range in system 1
+    out_of_range = dataclasses.replace(good[1], A_col=col)
+    rp, col = good[4].A_rowptr, good[4].A_col.copy()
+    for row in range(good[4].nodes):  # a row whose diagonal can move to a free column
+        k = rp[row] + int(np.nonzero(col[rp[row]:rp[row + 1]] == row)[0][0])
+        left = col[k - 1] if k > rp[row] else -1
+        right = col[k + 1] if k + 1 < rp[row + 1] else good[4].nodes
+        cand = [c for c in range(left + 1, right) if c != row]
+        if cand:
+            break
+    assert cand
+    col[k] = cand[0]  # the row stays sorted and unique, without its diagonal
+    no_diag = dataclasses.replace(good[4], A_col=col)
+    for systems, want in (([good[0], out_of_range, good[2], good[3], no_diag, good[5]], "column index out of range"),
+                          ([good[0], good[2], good[3], no_diag, good[5]], "missing diagonal")):
+        with pytest.raises(amg.AmgError, match=want):
+            amg.BatchedSolver(systems, smoother="GS-1-1")
+    # the well-formed ones still set up and solve afterwards
+    bs = amg.BatchedSolver(good, smoother="GS-1-1")
+    x = torch.zeros(bs.n, dtype=torch.float64, device=DEV)
+    res = bs.solve(dev(np.concatenate([s.rhs for s in good])), x, tol=1e-8)
+    assert all(r.converged for r in res)
+    bs.close()
