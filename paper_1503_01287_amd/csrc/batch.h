@@ -47,6 +47,8 @@ void launch_seg_axpby(const double *x, double *y, const double *a, const double 
 // x += sum_{j < cnt[seg]} y[seg * kmax + j] Z_j
 void launch_seg_multi_add(const double *Z, int64_t ld, const double *y, int kmax, const int *cnt, double *x,
                           const ChunkView &t, hipStream_t s);
+// dst[k] = src[k] + add for k < n (src null: dst[k] = add)
+void launch_copy_shift_i32(const int *src, int64_t n, int add, int *dst, hipStream_t s);
 // dst[dstart[c] + e] = src[start[c] + e] for e < len[c]
 void launch_seg_copy(const double *src, double *dst, const ChunkView &t, const int64_t *dstart, hipStream_t s);
 

@@ -35,35 +35,42 @@ static int lanes_of(int64_t nnz, int nrows) {
 // may be null or empty) with its columns shifted by coff[j].
 static void merge_mats(DMat &out, const std::vector<const DMat *> &parts, const std::vector<int> &rows,
                        const std::vector<int> &coff, int ncols, int np, hipStream_t s) {
+    // block-diagonal concatenation on the device: each part's row pointers
+    // shifted by the entries before it, its columns by its column offset,
+    // its value planes copied into the merged planes
     out = DMat();
     out.np = np;
     out.ncols = ncols;
-    std::vector<int> rp(1, 0), cl;
-    std::vector<int64_t> voff;
+    int64_t nrows = 0, nnz = 0;
     for (size_t j = 0; j < parts.size(); ++j) {
         const DMat *m = parts[j];
-        voff.push_back(static_cast<int64_t>(cl.size()));
+        nrows += rows[j];
         if (m && m->nnz > 0) {
             AMG_REQUIRE(m->nrows == rows[j] && m->np == np, AMG_EINVAL, "batch: inconsistent level operators");
-            std::vector<int> r = m->rowptr.download(s), c = m->col.download(s);
-            const int base = static_cast<int>(cl.size());
-            for (int i = 0; i < m->nrows; ++i) rp.push_back(base + r[i + 1]);
-            for (int64_t k = 0; k < m->nnz; ++k) cl.push_back(c[k] + coff[j]);
-        } else {
-            for (int i = 0; i < rows[j]; ++i) rp.push_back(static_cast<int>(cl.size()));
+            nnz += m->nnz;
         }
     }
-    out.nrows = static_cast<int>(rp.size()) - 1;
-    out.nnz = static_cast<int64_t>(cl.size());
-    out.rowptr.upload(rp, s);
-    out.col.upload(cl, s);
-    out.val.alloc(static_cast<size_t>(std::max<int64_t>(1, out.nnz * np)));
+    AMG_REQUIRE(nnz <= INT32_MAX && nrows < INT32_MAX, AMG_EINVAL, "batch: merged level exceeds 32-bit indices");
+    out.nrows = static_cast<int>(nrows);
+    out.nnz = nnz;
+    out.rowptr.alloc(static_cast<size_t>(nrows) + 1);
+    out.col.alloc(static_cast<size_t>(std::max<int64_t>(1, nnz)));
+    out.val.alloc(static_cast<size_t>(std::max<int64_t>(1, nnz * np)));
+    launch_copy_shift_i32(nullptr, 1, 0, out.rowptr.p, s);  // rowptr[0] = 0
+    int64_t r0 = 0, k0 = 0;
     for (size_t j = 0; j < parts.size(); ++j) {
         const DMat *m = parts[j];
-        if (!m || m->nnz == 0) continue;
-        for (int p = 0; p < np; ++p)
-            AMG_HIP(hipMemcpyAsync(out.val.p + p * out.nnz + voff[j], m->val.p + p * m->nnz,
-                                   m->nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
+        if (m && m->nnz > 0) {
+            launch_copy_shift_i32(m->rowptr.p + 1, m->nrows, static_cast<int>(k0), out.rowptr.p + r0 + 1, s);
+            launch_copy_shift_i32(m->col.p, m->nnz, coff[j], out.col.p + k0, s);
+            for (int p = 0; p < np; ++p)
+                AMG_HIP(hipMemcpyAsync(out.val.p + p * nnz + k0, m->val.p + p * m->nnz, m->nnz * sizeof(double),
+                                       hipMemcpyDeviceToDevice, s));
+            k0 += m->nnz;
+        } else {
+            launch_copy_shift_i32(nullptr, rows[j], static_cast<int>(k0), out.rowptr.p + r0 + 1, s);
+        }
+        r0 += rows[j];
     }
 }
 
@@ -575,17 +582,28 @@ void build_batch_spd(amg_ctx *h, int nsys, const amg_system *sys) {
                 M.cptr.assign(1, 0);
                 M.colour_nnz.assign(ncol, 0);
                 M.colour.assign(M.n, -1);
+                // each system's rows bucketed by colour (in index order)
+                std::vector<std::vector<int>> byc(np_), cst(np_);
+                for (size_t j = 0; j < np_; ++j) {
+                    if (depth[P[j]] <= l) continue;
+                    const Level &V = inst[P[j]]->lv[l];
+                    std::vector<int> &st = cst[j];
+                    st.assign(ncol + 1, 0);
+                    for (int i = 0; i < V.n; ++i) ++st[V.colour[i] + 1];
+                    std::partial_sum(st.begin(), st.end(), st.begin());
+                    std::vector<int> at(st.begin(), st.end() - 1);
+                    byc[j].resize(V.n);
+                    for (int i = 0; i < V.n; ++i) byc[j][at[V.colour[i]]++] = i;
+                }
                 for (int c = 0; c < ncol; ++c) {
                     for (size_t j = 0; j < np_; ++j) {
                         if (depth[P[j]] <= l) continue;
-                        const Level &V = inst[P[j]]->lv[l];
-                        for (int i = 0; i < V.n; ++i)
-                            if (V.colour[i] == c) {
-                                const int g = noff[j] + i;
-                                rows.push_back(g);
-                                M.colour[g] = c;
-                                M.colour_nnz[c] += arp[g + 1] - arp[g];
-                            }
+                        for (int t = cst[j][c]; t < cst[j][c + 1]; ++t) {
+                            const int g = noff[j] + byc[j][t];
+                            rows.push_back(g);
+                            M.colour[g] = c;
+                            M.colour_nnz[c] += arp[g + 1] - arp[g];
+                        }
                     }
                     M.cptr.push_back(static_cast<int>(rows.size()));
                 }

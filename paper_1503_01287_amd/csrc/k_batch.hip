@@ -268,4 +268,17 @@ void launch_seg_copy(const double *src, double *dst, const ChunkView &t, const i
     AMG_CHECK_LAUNCH();
 }
 
+__global__ void k_copy_shift_i32(const int *src, int64_t n, int add, int *dst) {
+    for (int64_t k = static_cast<int64_t>(blockIdx.x) * CB + threadIdx.x; k < n;
+         k += static_cast<int64_t>(gridDim.x) * CB)
+        dst[k] = (src ? src[k] : 0) + add;
+}
+
+void launch_copy_shift_i32(const int *src, int64_t n, int add, int *dst, hipStream_t s) {
+    if (n <= 0) return;
+    const int nb = static_cast<int>(std::min<int64_t>(4096, (n + CB - 1) / CB));
+    k_copy_shift_i32<<<nb, CB, 0, s>>>(src, n, add, dst);
+    AMG_CHECK_LAUNCH();
+}
+
 }  // namespace amgp2
