@@ -158,7 +158,13 @@ static void build_instances(amg_ctx *h, int nsys, const amg_system *sys,
         work();
     } else {
         std::vector<std::thread> pool;
-        for (int t = 0; t < nthreads; ++t) pool.emplace_back(work);
+        try {
+            for (int t = 0; t < nthreads; ++t) pool.emplace_back(work);
+        } catch (...) {
+            // no more threads: the started ones finish the systems (joined
+            // below); only if none started does the error surface
+            if (pool.empty()) throw;
+        }
         for (auto &t : pool) t.join();
     }
     for (auto &e : err)
