@@ -609,8 +609,9 @@ void saddle_smooth(amg_ctx *h, int l, const double *b, double *x) { saddle_step<
 // From the first level d >= 1 on which every system has at most
 // SADDLE_TAIL_MAX rows, the GEMV would beat the cycle and the assembly fits
 // the setup budget, it is assembled once, column by column from unit
-// right-hand sides (one per system at a time) through the FP64 cycle, and
-// applied as one segmented GEMV: the same map as the launches it replaces,
+// right-hand sides (one per system at a time) through the FP64 cycle (which
+// applies the map of level d + 1, assembled first, instead of recursing),
+// and applied as one segmented GEMV: the same map as the launches it replaces,
 // up to rounding order, kept where it measures faster than those launches. Visits
 // of level d from a nonzero guess (the second recursion of a W-cycle) still
 // run the cycle itself. Called after the reduced-precision copies exist.
@@ -676,28 +677,54 @@ void setup_saddle_tail(amg_ctx *h) {
         if (gemv_bytes / 5.0e9 >= 0.9 * sparse_ms) continue;
         const float asm_ms = h->mixed ? time_cycle(d, true) : sparse_ms;
         if (static_cast<double>(mmax) * asm_ms > SADDLE_TAIL_SETUP_MS) continue;
-        DenseSegs &T = h->saddle_tail;
-        for (size_t j = 0; j < L.sys_n.size(); ++j) {
-            const int m = 3 * L.sys_n[j] + L.sys_np[j];
-            if (m > 0) T.add(m, 3 * L.sys_noff[j], 3 * L.sys_n[j], L.sys_poff[j]);
+        // the map of level lev, column by column from unit right-hand sides
+        // through the FP64 cycle (as it stands: with the map of a coarser
+        // level in place, the cycle applies that map instead of recursing)
+        auto assemble = [&](int lev, DenseSegs &T) {
+            Level &V = h->lv[lev];
+            if (V.sys_n.empty()) {
+                V.sys_noff.assign(1, 0);
+                V.sys_n.assign(1, V.n);
+                V.sys_poff.assign(1, 0);
+                V.sys_np.assign(1, V.n_pres);
+            }
+            int mm = 0;
+            for (size_t j = 0; j < V.sys_n.size(); ++j) {
+                const int m = 3 * V.sys_n[j] + V.sys_np[j];
+                mm = std::max(mm, m);
+                if (m > 0) T.add(m, 3 * V.sys_noff[j], 3 * V.sys_n[j], V.sys_poff[j]);
+            }
+            T.finalize(s);
+            const DenseSegView v = T.view();
+            const int64_t nv = std::max<int64_t>(1, V.vlen()), nu = 3 * static_cast<int64_t>(V.n);
+            DevBuf<double> unit(nv), col(nv);
+            for (int j = 0; j < mm; ++j) {
+                launch_fill(unit.p, 0.0, nv, s);
+                launch_segment_units(v, j, unit.p, unit.p + nu, s);
+                saddle_cycle<double>(h, lev, unit.p, col.p, true);
+                launch_segment_store_column(v, j, col.p, col.p + nu, T.inv.p, s);
+            }
+            AMG_HIP(hipStreamSynchronize(s));
+        };
+        // A V-cycle from level d visits level d + 1 from a zero guess: if
+        // that level still coarsens, its own (smaller) map is assembled first
+        // and level d's column cycles apply it instead of recursing.
+        if (h->prm.nu == 1 && d + 1 < last && h->lv[d + 1].nA > 0) {
+            DenseSegs inner;
+            assemble(d + 1, inner);
+            h->saddle_tail = std::move(inner);
+            h->saddle_tail_from = d + 1;
         }
-        T.finalize(s);
-        const DenseSegView v = T.view();
-        const int64_t nv = std::max<int64_t>(1, L.vlen()), nu = 3 * static_cast<int64_t>(L.n);
-        DevBuf<double> unit(nv), col(nv);
-        for (int j = 0; j < mmax; ++j) {
-            launch_fill(unit.p, 0.0, nv, s);
-            launch_segment_units(v, j, unit.p, unit.p + nu, s);
-            saddle_cycle<double>(h, d, unit.p, col.p, true);
-            launch_segment_store_column(v, j, col.p, col.p + nu, T.inv.p, s);
-        }
+        DenseSegs T;
+        assemble(d, T);
         if (h->mixed) T.make_f32(s);  // the FP32 cycle reads an FP32 copy
         AMG_HIP(hipStreamSynchronize(s));
+        h->saddle_tail = std::move(T);
         h->saddle_tail_from = d;
         const float dense_ms = time_cycle(d, false);
         if (!(dense_ms < 0.95f * sparse_ms)) {
             h->saddle_tail_from = -1;
-            T = DenseSegs();
+            h->saddle_tail = DenseSegs();
         }
         break;
     }
