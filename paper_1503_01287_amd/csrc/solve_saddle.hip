@@ -677,10 +677,9 @@ void setup_saddle_tail(amg_ctx *h) {
         if (gemv_bytes / 5.0e9 >= 0.9 * sparse_ms) continue;
         const float asm_ms = h->mixed ? time_cycle(d, true) : sparse_ms;
         if (static_cast<double>(mmax) * asm_ms > SADDLE_TAIL_SETUP_MS) continue;
-        // the map of level lev, column by column from unit right-hand sides
-        // through the FP64 cycle (as it stands: with the map of a coarser
-        // level in place, the cycle applies that map instead of recursing)
-        auto assemble = [&](int lev, DenseSegs &T) {
+        // the maps' layout on level lev (one square block per system);
+        // returns the largest block
+        auto layout = [&](int lev, DenseSegs &T) {
             Level &V = h->lv[lev];
             if (V.sys_n.empty()) {
                 V.sys_noff.assign(1, 0);
@@ -695,6 +694,28 @@ void setup_saddle_tail(amg_ctx *h) {
                 if (m > 0) T.add(m, 3 * V.sys_noff[j], 3 * V.sys_n[j], V.sys_poff[j]);
             }
             T.finalize(s);
+            return mm;
+        };
+        // the GEMV's own time, on a zero map of the same layout, before the
+        // assembly (one FP64 cycle per column) is paid for
+        {
+            DenseSegs probe;
+            layout(d, probe);
+            if (probe.inv.n) launch_fill(probe.inv.p, 0.0, static_cast<int64_t>(probe.inv.n), s);
+            if (h->mixed) probe.make_f32(s);
+            h->saddle_tail = std::move(probe);
+            h->saddle_tail_from = d;
+            const float est_ms = time_cycle(d, false);
+            h->saddle_tail_from = -1;
+            h->saddle_tail = DenseSegs();
+            if (!(est_ms < 0.95f * sparse_ms)) continue;
+        }
+        // the map of level lev, column by column from unit right-hand sides
+        // through the FP64 cycle (as it stands: with the map of a coarser
+        // level in place, the cycle applies that map instead of recursing)
+        auto assemble = [&](int lev, DenseSegs &T) {
+            Level &V = h->lv[lev];
+            const int mm = layout(lev, T);
             const DenseSegView v = T.view();
             const int64_t nv = std::max<int64_t>(1, V.vlen()), nu = 3 * static_cast<int64_t>(V.n);
             DevBuf<double> unit(nv), col(nv);
