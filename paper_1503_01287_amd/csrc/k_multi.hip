@@ -223,7 +223,15 @@ static void mrow_k(int op, int K, const MRowArgs &a, hipStream_t s) {
         case 2: mrow_op<MODE, VK, 2>(op, a, s); break;
         case 4: mrow_op<MODE, VK, 4>(op, a, s); break;
         case 8: mrow_op<MODE, VK, 8>(op, a, s); break;
-        default: throw Error(AMG_EINVAL, "multi row kernel: K must be 2, 4 or 8");
+        case 16:
+            // (one entry slot per row: the scalar FP64 operators of the
+            // setup's blocked map assembly)
+            if constexpr (MODE == 1 && VK == MK_F64) {
+                mrow_op<MODE, VK, 16>(op, a, s);
+                break;
+            }
+            [[fallthrough]];
+        default: throw Error(AMG_EINVAL, "multi row kernel: K must be 2, 4 or 8 (16: scalar FP64 operators)");
     }
 }
 

@@ -35,7 +35,8 @@ struct MRowArgs {
     void *zero_out = nullptr;      // if set: zero_out at every written (node, component, rhs) = 0
 };
 
-// mode 3: 3x3 blocks; mode 1: scalar applied to 3 components
+// mode 3: 3x3 blocks; mode 1: scalar applied to 3 components; K in {2, 4, 8},
+// and 16 for scalar FP64 operators (mode 1, MK_F64)
 void launch_mrow(int mode, int op, int kind, int K, const MRowArgs &a, hipStream_t s);
 // x = omega D^{-1} b over all nodes (first Jacobi step from zero); T: double (kind F64) or float
 void launch_mjacobi_zero(int mode, int kind, int K, int64_t nn, const void *dinv, const void *b, double omega,

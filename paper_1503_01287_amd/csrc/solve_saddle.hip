@@ -350,7 +350,7 @@ constexpr int SCHUR_DENSE_MAX = 1500;
 // H^T, recursion, H, backward sweep; systems ending on a level by their
 // explicit inverses); the sweeps take the correction form x_i += (b_i -
 // sum_j S_ij x_j) / S_ii, equal to the direct form up to rounding.
-constexpr int SCHUR_K = 8;
+constexpr int SCHUR_K = 16;
 constexpr int SCHUR_COLS = 3 * SCHUR_K;
 
 struct SchurBlockWork {
