@@ -17,6 +17,7 @@
 #include <cmath>
 #include <exception>
 #include <memory>
+#include <mutex>
 #include <numeric>
 #include <thread>
 
@@ -129,7 +130,20 @@ static void build_instances(amg_ctx *h, int nsys, const amg_system *sys,
     AMG_HIP(hipGetDevice(&dev));
     std::atomic<int> next{0};
     std::vector<std::exception_ptr> err(nsys);
+    std::mutex held_mu;
+    std::vector<void *> held;  // buffers the builds released, freed after them
     auto work = [&]() {
+        std::vector<void *> mine;
+        deferred_frees = &mine;
+        struct Hand {
+            std::vector<void *> &mine, &held;
+            std::mutex &mu;
+            ~Hand() {
+                deferred_frees = nullptr;
+                std::lock_guard<std::mutex> lock(mu);
+                held.insert(held.end(), mine.begin(), mine.end());
+            }
+        } hand{mine, held, held_mu};
         hipStream_t st = nullptr;
         try {
             AMG_HIP(hipSetDevice(dev));
@@ -167,6 +181,7 @@ static void build_instances(amg_ctx *h, int nsys, const amg_system *sys,
         }
         for (auto &t : pool) t.join();
     }
+    for (void *q : held) (void)hipFree(q);
     for (auto &e : err)
         if (e) std::rethrow_exception(e);
     const std::string pre = "setup.";

@@ -44,6 +44,12 @@ void set_last_error(const std::string &msg);
 // the previous one; small ones copy from the source directly.
 void copy_h2d(void *dst, const void *src, size_t bytes, hipStream_t s);
 
+// When set (on a thread that builds one system of a batch), device buffers
+// released on this thread are not freed but collected here, and freed once
+// every system is built: a free waits for the whole device, so frees on
+// many threads would serialise their builds.
+inline thread_local std::vector<void *> *deferred_frees = nullptr;
+
 // Owning device allocation.
 template <typename T>
 struct DevBuf {
@@ -65,7 +71,12 @@ struct DevBuf {
         if (count) AMG_HIP(hipMalloc(reinterpret_cast<void **>(&p), count * sizeof(T)));
     }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p) {
+            if (deferred_frees)
+                deferred_frees->push_back(p);
+            else
+                (void)hipFree(p);
+        }
         p = nullptr;
         n = 0;
     }
