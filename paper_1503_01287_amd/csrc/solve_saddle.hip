@@ -699,11 +699,11 @@ void setup_saddle_tail(amg_ctx *h) {
         // the GEMV's own time, on a zero map of the same layout, before the
         // assembly (one FP64 cycle per column) is paid for
         {
-            DenseSegs probe;
-            layout(d, probe);
-            if (probe.inv.n) launch_fill(probe.inv.p, 0.0, static_cast<int64_t>(probe.inv.n), s);
-            if (h->mixed) probe.make_f32(s);
-            h->saddle_tail = std::move(probe);
+            DenseSegs trial;
+            layout(d, trial);
+            if (trial.inv.n) launch_fill(trial.inv.p, 0.0, static_cast<int64_t>(trial.inv.n), s);
+            if (h->mixed) trial.make_f32(s);
+            h->saddle_tail = std::move(trial);
             h->saddle_tail_from = d;
             const float est_ms = time_cycle(d, false);
             h->saddle_tail_from = -1;
