@@ -20,6 +20,7 @@ amg_ctx::~amg_ctx() {
         (void)hipEventDestroy(pe.b);
     }
     for (hipEvent_t e : event_pool) (void)hipEventDestroy(e);
+    if (sc_ready) (void)hipEventDestroy(sc_ready);
     if (h_sc) (void)hipHostFree(h_sc);
 }
 

@@ -318,6 +318,7 @@ struct amg_ctx {
     amgp2::MultiWork multi;  // amg_solve_multi
     amgp2::DevBuf<double> partial, sc;
     double *h_sc = nullptr;  // pinned host copy of the scalars
+    hipEvent_t sc_ready = nullptr;  // that copy has landed (overlapped stopping tests)
     int n_dof = 0;           // length of a solve vector
     // profiling
     bool prof = false;
