@@ -386,6 +386,12 @@ void system_residual(amg_ctx *h, const double *b, const double *x, double *r);
 int solve_fgmres(amg_ctx *h, const double *b, double *x, double tol, int maxit, amg_result *res);
 int solve_stationary_saddle(amg_ctx *h, const double *b, double *x, double tol, int maxit, amg_result *res);
 void precondition_any(amg_ctx *h, const double *r, double *z);
+// Krylov loops enqueue the next preconditioner application ahead of the
+// host's wait for an iteration's scalars while the last relative residual
+// estimate is above KRYLOV_AHEAD * tol (several iterations from the
+// tolerance at these convergence rates); the application only writes its
+// output, so a solve that stops there loses nothing but its GPU time.
+constexpr double KRYLOV_AHEAD = 50.0;
 void precondition_staged(amg_ctx *h, const double *r, double *z);
 // batches
 void build_batch(amg_ctx *h, int nsys, const amg_system *sys);

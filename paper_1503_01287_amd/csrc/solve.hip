@@ -366,12 +366,10 @@ static void scalars_begin(amg_ctx *h) {
 static void scalars_wait(amg_ctx *h) { AMG_HIP(hipEventSynchronize(h->sc_ready)); }
 
 // CG's stopping test waits for the scalars of iteration k on the host; while
-// the last test's relative residual is still above SPECULATE * tol (several
-// iterations from the tolerance at these convergence rates), the next
-// preconditioner application, which only reads r and writes z, is enqueued
-// before that wait, so the round trip overlaps the GPU's cycle. If the test
-// then stops the solve, that application has changed nothing else.
-constexpr double SPECULATE = 50.0;
+// the last test's relative residual is still above KRYLOV_AHEAD * tol, the
+// next preconditioner application, which only reads r and writes z, is
+// enqueued before that wait, so the round trip overlaps the GPU's cycle. If
+// the test then stops the solve, that application has changed nothing else.
 
 static void dot_into(amg_ctx *h, const double *a, const double *b, int dst, int post = RED_NONE) {
     ProfScope ps(h, "blas", 2.0 * h->n_dof * 8.0);
@@ -452,7 +450,7 @@ int solve_pcg(amg_ctx *h, const double *b, double *x, double tol, int maxit, amg
         cg_update(h, x, r, p, q, z);
         ++it;
         scalars_begin(h);
-        const bool ahead = it < maxit && rel > SPECULATE * tol;
+        const bool ahead = it < maxit && rel > KRYLOV_AHEAD * tol;
         if (ahead) precondition_impl(h, r, z, true);
         scalars_wait(h);
         const double rr = h->h_sc[SC_RR];
@@ -494,7 +492,7 @@ int solve_fcg(amg_ctx *h, const double *b, double *x, double tol, int maxit, amg
         cg_update(h, x, r, p, q, z);
         ++it;
         scalars_begin(h);
-        ahead = it < maxit && rel > SPECULATE * tol;
+        ahead = it < maxit && rel > KRYLOV_AHEAD * tol;
         if (ahead) precondition_impl(h, r, z, true);
         scalars_wait(h);
         const double rr = h->h_sc[SC_RR];

@@ -862,6 +862,7 @@ int solve_fgmres(amg_ctx *h, const double *b, double *x, double tol, int maxit, 
     if (!(r0 == r0)) return finish(0, AMG_DIVERGED);
     int it = 0;
     double beta = r0;
+    double est_last = 1.0;  // the last residual estimate (relative)
     int status = AMG_NOT_CONVERGED;
     // rotations 0..c-1 applied to raw column c, rotation c formed, g updated;
     // returns the residual estimate after c + 1 columns
@@ -904,11 +905,14 @@ int solve_fgmres(amg_ctx *h, const double *b, double *x, double tol, int maxit, 
         g[0] = beta;
         int nc = 0;  // complete, rotated columns
         bool stop = false;
+        bool ahead = false;  // this step's preconditioner already enqueued
         double *hd = h->gm_h.p;
+        if (!h->sc_ready) AMG_HIP(hipEventCreateWithFlags(&h->sc_ready, hipEventDisableTiming));
         for (int j = 0; j < m && it + j < maxit && !stop; ++j) {
             double *vj = V + static_cast<int64_t>(j) * n, *w = V + static_cast<int64_t>(j + 1) * n;
             double *zj = Z + static_cast<int64_t>(j) * n;
-            precondition_any(h, vj, zj);
+            if (!ahead) precondition_any(h, vj, zj);
+            ahead = false;
             system_matvec(h, zj, w);
             const int k = j + 2;
             int nb = launch_multidot2(V, n, k, vj, w, n, h->gm_part.p, h->stream);
@@ -916,7 +920,15 @@ int solve_fgmres(amg_ctx *h, const double *b, double *x, double tol, int maxit, 
             launch_dcgs2_update(V, n, j, hd, n, j > 0, h->stream);
             AMG_HIP(hipMemcpyAsync(hbuf.data(), hd, (2 * k + 3) * sizeof(double), hipMemcpyDeviceToHost,
                                    h->stream));
-            AMG_HIP(hipStreamSynchronize(h->stream));
+            AMG_HIP(hipEventRecord(h->sc_ready, h->stream));
+            // the pending vector u_{j+1} is final for step j + 1: its
+            // preconditioner goes ahead of the host's wait while the last
+            // estimate is far from the tolerance
+            if (j + 1 < m && it + j + 1 < maxit && est_last > KRYLOV_AHEAD * tol) {
+                precondition_any(h, w, Z + static_cast<int64_t>(j + 1) * n);
+                ahead = true;
+            }
+            AMG_HIP(hipEventSynchronize(h->sc_ready));
             const double *dA = hbuf.data(), *dB = hbuf.data() + k;
             const double gam = hbuf[2 * k], d = hbuf[2 * k + 1], et = hbuf[2 * k + 2];
             double est = 0.0;
@@ -927,6 +939,7 @@ int solve_fgmres(amg_ctx *h, const double *b, double *x, double tol, int maxit, 
                 c1[j] = eta[j] * gam;
                 done_col[j - 1] = 1;
                 est = rotate(j - 1);
+                est_last = est;
                 nc = j;
                 if (!(est == est) || est > 1e3) {
                     status = AMG_DIVERGED;
@@ -956,6 +969,7 @@ int solve_fgmres(amg_ctx *h, const double *b, double *x, double tol, int maxit, 
                 cj[j + 1] = et * (g2 > 0.0 ? std::sqrt(g2) : 0.0);
                 done_col[j] = 1;
                 est = rotate(j);
+                est_last = est;
                 nc = j + 1;
                 if (!(est == est) || est > 1e3) {
                     status = AMG_DIVERGED;
