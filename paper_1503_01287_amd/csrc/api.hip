@@ -21,6 +21,7 @@ amg_ctx::~amg_ctx() {
     }
     for (hipEvent_t e : event_pool) (void)hipEventDestroy(e);
     if (sc_ready) (void)hipEventDestroy(sc_ready);
+    if (gm_hpin) (void)hipHostFree(gm_hpin);
     if (h_sc) (void)hipHostFree(h_sc);
 }
 

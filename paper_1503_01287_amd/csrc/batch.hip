@@ -808,7 +808,18 @@ int solve_fgmres_batched(amg_ctx *h, const double *b, double *x, double tol, int
     const size_t hsz = static_cast<size_t>(m + 1) * m;
     std::vector<double> H(ns * hsz), Hr(ns * hsz), cs(static_cast<size_t>(ns) * m), sn(static_cast<size_t>(ns) * m),
         g(static_cast<size_t>(ns) * (m + 1)), eta(static_cast<size_t>(ns) * (m + 1), 1.0), hcol(m + 2),
-        hp(static_cast<size_t>(ns) * stride);
+        estl(ns, 1.0);
+    // the step's dots land in pinned host memory (asynchronous copies, so
+    // that the next step's preconditioner can be enqueued before the wait)
+    const size_t nh = static_cast<size_t>(ns) * stride;
+    if (h->gm_hpin_n < nh) {
+        if (h->gm_hpin) AMG_HIP(hipHostFree(h->gm_hpin));
+        h->gm_hpin = nullptr;
+        AMG_HIP(hipHostMalloc(reinterpret_cast<void **>(&h->gm_hpin), nh * sizeof(double)));
+        h->gm_hpin_n = nh;
+    }
+    double *hp = h->gm_hpin;
+    if (!h->sc_ready) AMG_HIP(hipEventCreateWithFlags(&h->sc_ready, hipEventDisableTiming));
     std::vector<double> beta, r0;
     std::vector<int> status(ns, AMG_NOT_CONVERGED), iters(ns, 0), jcnt(ns, 0), wanth(ns, 0);
     std::vector<char> active(ns, 0), running(ns, 0), done(static_cast<size_t>(ns) * m, 0);
@@ -847,6 +858,7 @@ int solve_fgmres_batched(amg_ctx *h, const double *b, double *x, double tol, int
     };
     // a completed column's test: false when system i stops taking steps
     auto judge = [&](int i, double est, bool breakdown) {
+        estl[i] = est;
         if (!(est == est) || est > 1e3) {
             status[i] = AMG_DIVERGED;
             running[i] = 0;
@@ -871,18 +883,33 @@ int solve_fgmres_batched(amg_ctx *h, const double *b, double *x, double tol, int
             running[i] = active[i];
             jcnt[i] = 0;
         }
+        bool ahead = false;  // this step's preconditioner already enqueued
         for (int j = 0; j < m && any(running) && it < maxit; ++j, ++it) {
             double *vj = V + static_cast<int64_t>(j) * n, *w = V + static_cast<int64_t>(j + 1) * n;
             double *zj = Z + static_cast<int64_t>(j) * n;
-            precondition_any(h, vj, zj);
+            if (!ahead) precondition_any(h, vj, zj);
+            ahead = false;
             system_matvec(h, zj, w);
             const int k = j + 2;
             launch_seg_multidot2(V, n, k, vj, w, t, partial.p, h->stream);
             launch_seg_reduce(partial.p, t.n, 2 * k, ns, h->b_c0.p, h->b_c1.p, h->b_c2.p, h->b_c3.p, hb.p, stride,
                               h->stream);
             launch_seg_dcgs2_update(V, n, j, hb.p, stride, t, j > 0, h->stream);
-            AMG_HIP(hipMemcpyAsync(hp.data(), hb.p, hp.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-            AMG_HIP(hipStreamSynchronize(h->stream));
+            AMG_HIP(hipMemcpyAsync(hp, hb.p, nh * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+            AMG_HIP(hipEventRecord(h->sc_ready, h->stream));
+            // the pending vectors u_{j+1} are final for step j + 1: their
+            // preconditioner goes ahead of the host's wait while every
+            // running system's last estimate is far from the tolerance
+            {
+                double emin = 1e300;
+                for (int i = 0; i < ns; ++i)
+                    if (running[i]) emin = std::min(emin, estl[i]);
+                if (j + 1 < m && it + 1 < maxit && emin > KRYLOV_AHEAD * tol) {
+                    precondition_any(h, w, Z + static_cast<int64_t>(j + 1) * n);
+                    ahead = true;
+                }
+            }
+            AMG_HIP(hipEventSynchronize(h->sc_ready));
             const bool last = j + 1 == m || it + 1 >= maxit;
             bool cleanup = false;
             for (int i = 0; i < ns; ++i) {
@@ -916,8 +943,7 @@ int solve_fgmres_batched(amg_ctx *h, const double *b, double *x, double tol, int
                 launch_seg_multidot_masked(V, n, k, w, t, want.p, partial.p, h->stream);
                 launch_seg_reduce(partial.p, t.n, k, ns, h->b_c0.p, h->b_c1.p, h->b_c2.p, h->b_c3.p, hb.p, stride,
                                   h->stream);
-                AMG_HIP(hipMemcpyAsync(hp.data(), hb.p, hp.size() * sizeof(double), hipMemcpyDeviceToHost,
-                                       h->stream));
+                AMG_HIP(hipMemcpyAsync(hp, hb.p, nh * sizeof(double), hipMemcpyDeviceToHost, h->stream));
                 AMG_HIP(hipStreamSynchronize(h->stream));
                 for (int i = 0; i < ns; ++i) {
                     if (!wanth[i]) continue;

@@ -293,6 +293,10 @@ struct amg_ctx {
     // flexible GMRES workspace: V ((m+1) x n), Z (m x n), device scalars
     amgp2::DevBuf<double> gm_V, gm_Z, gm_h, gm_y, gm_part;
     int gm_m = 0;
+    // pinned host copies of an FGMRES step's dots (asynchronous copies, so
+    // that the next step's preconditioner can be enqueued before the wait)
+    double *gm_hpin = nullptr;
+    size_t gm_hpin_n = 0;
     // batch of independent saddle systems merged level by level (nsys > 0):
     // merged position q holds caller system b_order[q]; systems are ordered
     // by decreasing depth so that those still coarsening on a level lead it

@@ -841,7 +841,15 @@ int solve_fgmres(amg_ctx *h, const double *b, double *x, double tol, int maxit, 
     // H: rotated (upper triangular) columns, row-major i * m + j; Hr: the
     // raw Hessenberg columns (column j at j * (m + 1))
     std::vector<double> H(static_cast<size_t>(m + 1) * m), Hr(static_cast<size_t>(m + 1) * m), cs(m), sn(m),
-        g(m + 1), hcol(m + 2), hbuf(static_cast<size_t>(2 * (m + 2) + 4)), eta(m + 1, 1.0);
+        g(m + 1), hcol(m + 2), eta(m + 1, 1.0);
+    const size_t nh = static_cast<size_t>(2 * (m + 2) + 4);
+    if (h->gm_hpin_n < nh) {
+        if (h->gm_hpin) AMG_HIP(hipHostFree(h->gm_hpin));
+        h->gm_hpin = nullptr;
+        AMG_HIP(hipHostMalloc(reinterpret_cast<void **>(&h->gm_hpin), nh * sizeof(double)));
+        h->gm_hpin_n = nh;
+    }
+    double *hbuf = h->gm_hpin;
     std::vector<char> done_col(m, 0);
     system_residual(h, b, x, V);
     const double r0 = norm2(h, V);
@@ -918,8 +926,7 @@ int solve_fgmres(amg_ctx *h, const double *b, double *x, double tol, int maxit, 
             int nb = launch_multidot2(V, n, k, vj, w, n, h->gm_part.p, h->stream);
             launch_multidot_reduce(h->gm_part.p, nb, 2 * k, hd, h->stream);
             launch_dcgs2_update(V, n, j, hd, n, j > 0, h->stream);
-            AMG_HIP(hipMemcpyAsync(hbuf.data(), hd, (2 * k + 3) * sizeof(double), hipMemcpyDeviceToHost,
-                                   h->stream));
+            AMG_HIP(hipMemcpyAsync(hbuf, hd, (2 * k + 3) * sizeof(double), hipMemcpyDeviceToHost, h->stream));
             AMG_HIP(hipEventRecord(h->sc_ready, h->stream));
             // the pending vector u_{j+1} is final for step j + 1: its
             // preconditioner goes ahead of the host's wait while the last
@@ -929,7 +936,7 @@ int solve_fgmres(amg_ctx *h, const double *b, double *x, double tol, int maxit, 
                 ahead = true;
             }
             AMG_HIP(hipEventSynchronize(h->sc_ready));
-            const double *dA = hbuf.data(), *dB = hbuf.data() + k;
+            const double *dA = hbuf, *dB = hbuf + k;
             const double gam = hbuf[2 * k], d = hbuf[2 * k + 1], et = hbuf[2 * k + 2];
             double est = 0.0;
             if (j > 0 && !done_col[j - 1]) {
@@ -958,7 +965,7 @@ int solve_fgmres(amg_ctx *h, const double *b, double *x, double tol, int maxit, 
                 // complete column j now: s = V_{0..j} . u_{j+1}, |u_{j+1}|^2
                 nb = launch_multidot(V, n, k, w, n, h->gm_part.p, h->stream);
                 launch_multidot_reduce(h->gm_part.p, nb, k, hd, h->stream);
-                AMG_HIP(hipMemcpyAsync(hbuf.data(), hd, k * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+                AMG_HIP(hipMemcpyAsync(hbuf, hd, k * sizeof(double), hipMemcpyDeviceToHost, h->stream));
                 AMG_HIP(hipStreamSynchronize(h->stream));
                 double ss = 0.0;
                 for (int i = 0; i <= j; ++i) {
