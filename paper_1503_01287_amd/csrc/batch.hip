@@ -1017,8 +1017,9 @@ int solve_fgmres_batched(amg_ctx *h, const double *b, double *x, double tol, int
 // on; its iterate stays). Two host synchronisations per iteration: <p, Ap>,
 // then ||r|| and <r, z> in one pass. With the flexible variant (FCG(1), for
 // the reduced-precision cycle, as solve_fcg): alpha = <p, r> / <p, Ap> and
-// p = z - (<z, q_prev> / <p_prev, q_prev>) p_prev, three synchronisations
-// per iteration (<z, q_prev>; <p, Ap> with <p, r>; ||r||).
+// p = z - (<z, q_prev> / <p_prev, q_prev>) p_prev, two synchronisations per
+// iteration (<p, Ap> with <p, r>; ||r|| with the next <z, q_prev>) while
+// every running system is far from the tolerance, three near it.
 int solve_pcg_batched(amg_ctx *h, const double *b, double *x, double tol, int maxit, amg_result *res) {
     const auto t0 = std::chrono::steady_clock::now();
     const int ns = h->nsys;
@@ -1065,12 +1066,21 @@ int solve_pcg_batched(amg_ctx *h, const double *b, double *x, double tol, int ma
         else active[i] = 1;
     }
     const bool flexible = h->prm.krylov == AMG_KRYLOV_FCG;
+    // FCG: while every running system's last relative residual is above
+    // KRYLOV_AHEAD * tol, the next preconditioner application goes ahead of
+    // the stopping test's read, and <z, q_prev> comes back in that read
+    double relmin = 1.0;
+    bool ahead = false;
+    std::vector<double> zq(ns);
     for (int it = 0; flexible && any_active() && it < maxit; ++it) {
-        precondition(h, r, z);
+        if (!ahead) precondition(h, r, z);
         if (it == 0) {
             launch_copy(pv, z, n, s);
         } else {
-            dots(z, q, 1);  // <z, q_prev>
+            if (ahead)
+                std::copy(zq.begin(), zq.end(), hv.begin());
+            else
+                dots(z, q, 1);  // <z, q_prev>
             for (int i = 0; i < ns; ++i) beta[i] = active[i] && pq[i] > 0.0 ? -hv[i] / pq[i] : 0.0;
             put(dbeta, beta);
             launch_seg_axpby(z, pv, dones.p, dbeta.p, t, s);  // p = z + beta p
@@ -1094,7 +1104,22 @@ int solve_pcg_batched(amg_ctx *h, const double *b, double *x, double tol, int ma
         put(dm, malpha);
         launch_seg_axpby(pv, x, da.p, dones.p, t, s);  // x += alpha p
         launch_seg_axpby(q, r, dm.p, dones.p, t, s);   // r -= alpha q
-        dots(r, r, 1);
+        ahead = it + 1 < maxit && relmin > KRYLOV_AHEAD * tol;
+        if (ahead) {
+            // <r, r> into hb[0, ns), then z and <z, q> into hb[ns, 2 ns): one read
+            launch_seg_multidot(r, 0, 1, r, t, partial.p, s);
+            launch_seg_reduce(partial.p, t.n, 1, ns, h->b_c0.p, h->b_c1.p, h->b_c2.p, h->b_c3.p, hb.p, 1, s);
+            precondition(h, r, z);
+            launch_seg_multidot(z, 0, 1, q, t, partial.p, s);
+            launch_seg_reduce(partial.p, t.n, 1, ns, h->b_c0.p, h->b_c1.p, h->b_c2.p, h->b_c3.p, hb.p + ns, 1, s);
+            AMG_HIP(hipMemcpyAsync(hv.data(), hb.p, 2 * static_cast<size_t>(ns) * sizeof(double),
+                                   hipMemcpyDeviceToHost, s));
+            AMG_HIP(hipStreamSynchronize(s));
+            std::copy(hv.begin() + ns, hv.begin() + 2 * ns, zq.begin());
+        } else {
+            dots(r, r, 1);
+        }
+        relmin = 1e300;
         for (int i = 0; i < ns; ++i) {
             if (!active[i]) continue;
             const double rel = std::sqrt(hv[i]) / r0[i];
@@ -1104,6 +1129,8 @@ int solve_pcg_batched(amg_ctx *h, const double *b, double *x, double tol, int ma
             } else if (rel <= tol) {
                 status[i] = AMG_OK;
                 active[i] = 0;
+            } else {
+                relmin = std::min(relmin, rel);
             }
         }
     }

@@ -347,14 +347,22 @@ int solve_multi(amg_ctx *h, int nrhs, const double *B, double *X, double tol, in
         for (int r = 0; r < K; ++r) rz[r] = d[r];
         launch_copy(W.P.p, W.Z.p, nd * K, s);
     }
+    // While every running column's last relative residual is above
+    // KRYLOV_AHEAD * tol, the next preconditioner application goes ahead of
+    // the stopping test's read, and its dot (<r, z> for CG, <z, q> for FCG)
+    // comes back in the same read: one host round trip less per iteration,
+    // the same arithmetic.
+    double relmin = 1.0;
+    bool ahead = false;             // z of this iteration already computed
+    std::vector<double> zdot(K);    // its dot, read with the last stopping test
     while (it < maxit && any_active()) {
         if (fcg) {
-            prec(W.R.p, W.Z.p);
+            if (!ahead) prec(W.R.p, W.Z.p);
             if (it == 0) {
                 launch_copy(W.P.p, W.Z.p, nd * K, s);
             } else {
                 // beta = -<z, q_prev> / <p_prev, q_prev>: p = z + beta p_prev
-                const std::vector<double> d = mdots(h, W, 1, W.Z.p, W.Q.p);
+                const std::vector<double> d = ahead ? zdot : mdots(h, W, 1, W.Z.p, W.Q.p);
                 for (int r = 0; r < K; ++r) beta[r] = active[r] && pq_prev[r] != 0.0 ? -d[r] / pq_prev[r] : 0.0;
                 mcomb(h, W, W.P.p, beta, W.Z.p, one);
             }
@@ -377,7 +385,16 @@ int solve_multi(amg_ctx *h, int nrhs, const double *B, double *X, double tol, in
         mcomb(h, W, W.X.p, one, W.P.p, alpha);
         mcomb(h, W, W.R.p, one, W.Q.p, malpha);
         ++it;
-        const std::vector<double> rrv = mdots(h, W, 1, W.R.p, W.R.p);
+        ahead = it < maxit && relmin > KRYLOV_AHEAD * tol;
+        std::vector<double> rrv;
+        if (ahead) {
+            prec(W.R.p, W.Z.p);
+            rrv = fcg ? mdots(h, W, 2, W.R.p, W.R.p, W.Z.p, W.Q.p) : mdots(h, W, 2, W.R.p, W.R.p, W.R.p, W.Z.p);
+            std::copy(rrv.begin() + K, rrv.end(), zdot.begin());
+        } else {
+            rrv = mdots(h, W, 1, W.R.p, W.R.p);
+        }
+        relmin = 1e300;
         for (int r = 0; r < K; ++r) {
             if (!active[r]) continue;
             iters[r] = it;
@@ -388,11 +405,13 @@ int solve_multi(amg_ctx *h, int nrhs, const double *B, double *X, double tol, in
             } else if (std::sqrt(rr / rr0[r]) <= tol) {
                 status[r] = AMG_OK;
                 active[r] = 0;
+            } else {
+                relmin = std::min(relmin, std::sqrt(rr / rr0[r]));
             }
         }
         if (!fcg && it < maxit && any_active()) {
-            prec(W.R.p, W.Z.p);
-            const std::vector<double> dz = mdots(h, W, 1, W.R.p, W.Z.p);
+            if (!ahead) prec(W.R.p, W.Z.p);
+            const std::vector<double> dz = ahead ? zdot : mdots(h, W, 1, W.R.p, W.Z.p);
             for (int r = 0; r < K; ++r) {
                 beta[r] = active[r] && rz[r] != 0.0 ? dz[r] / rz[r] : 0.0;
                 if (active[r]) rz[r] = dz[r];
