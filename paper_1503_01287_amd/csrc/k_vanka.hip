@@ -223,7 +223,28 @@ __global__ void __launch_bounds__(VCB) k_vanka_colour(const VankaView v, const i
         double acc[VR];
 #pragma unroll
         for (int t = 0; t < VR; ++t) acc[t] = 0.0;
-        for (int c = c0; c < c1; ++c) {
+        // four columns' loads in flight per lane before their products are
+        // added (still in column order)
+        int c = c0;
+        for (; c + 4 <= c1; c += 4) {
+            double mv[4][VR], rv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                rv[u] = r[c + u];
+                const double *col = M + static_cast<int64_t>(c + u) * m;
+#pragma unroll
+                for (int t = 0; t < VR; ++t) {
+                    const int a = a0 + wl + 64 * t;
+                    mv[u][t] = a < m ? col[a] : 0.0;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int t = 0; t < VR; ++t)
+                    if (a0 + wl + 64 * t < m) acc[t] += mv[u][t] * rv[u];
+        }
+        for (; c < c1; ++c) {
             const double rc = r[c];
             const double *col = M + static_cast<int64_t>(c) * m;
 #pragma unroll
@@ -337,8 +358,20 @@ __global__ void __launch_bounds__(VB) k_vanka_apply(const VankaView v, const int
     const double *M = v.inv + v.moff[i];
     const int c0 = wave * m / 4, c1 = (wave + 1) * m / 4;
     double acc = 0.0;
-    if (a < m)
-        for (int c = c0; c < c1; ++c) acc += M[static_cast<int64_t>(c) * m + a] * r[c];
+    if (a < m) {
+        int c = c0;
+        for (; c + 8 <= c1; c += 8) {  // eight column loads in flight per lane
+            double mv[8], rv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                mv[u] = M[static_cast<int64_t>(c + u) * m + a];
+                rv[u] = r[c + u];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc += mv[u] * rv[u];
+        }
+        for (; c < c1; ++c) acc += M[static_cast<int64_t>(c) * m + a] * r[c];
+    }
     part[wave][threadIdx.x & 63] = acc;
     __syncthreads();
     if (wave != 0 || a >= m) return;
