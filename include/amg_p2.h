@@ -345,6 +345,10 @@ int amg_get_level_colors(amg_handle h, int32_t level, int32_t *colors);
  * flight together; the sums do not depend on it; the prolongation kernels
  * always take 1). xcd (colour sweeps only): 1 = each XCD takes one
  * contiguous eighth of a colour's rows, 0 = round-robin placement.
+ * AMG_SHAPE_VANKA (Vanka smoother, any level but the coarsest): the
+ * level's sweeps take the tiled form (patch residuals, 64-row tiles of the
+ * patch inverses, their sum in order) with `lanes` lanes per residual row,
+ * 16, 32 or 64 (trip 1, xcd 0).
  * Recorded preconditioner graphs are dropped (they hold the old shapes).
  * Errors: AMG_EINVAL for a bad level, kernel class, lane count, trip or flag, or a
  * reduced-precision class on an FP64 hierarchy. */
@@ -352,6 +356,7 @@ int amg_get_level_colors(amg_handle h, int32_t level, int32_t *colors);
 #define AMG_SHAPE_SWEEP 1
 #define AMG_SHAPE_NATURAL_RP 2
 #define AMG_SHAPE_SWEEP_RP 3
+#define AMG_SHAPE_VANKA 4
 int amg_set_launch_shape(amg_handle h, int32_t level, int32_t kernels, int32_t lanes, int32_t trip, int32_t xcd);
 
 /* ---- batches of independent systems ------------------------------------

@@ -134,8 +134,12 @@ struct VankaData {
     std::vector<int> nunits;       // path 2: 2-D tiles per colour
     DevBuf<int64_t> poff;          // path 2: partial buffer offsets
     DevBuf<double> pbuf;
-    DevBuf<int> rpre;              // path 2: per-colour prefix of the residual's 16-row units
-    std::vector<int> nrunits;      // path 2: residual units per colour
+    int rg = 16;                   // path 2: lanes per residual row (16, 32 or 64)
+    // path 2, for rg = 16, 32, 64 (index rg_index): per-colour prefix of the
+    // residual's units (256 / rg node rows each) and units per colour
+    DevBuf<int> rpre[3];
+    std::vector<int> nrunits[3];
+    static int rg_index(int rg) { return rg == 16 ? 0 : (rg == 32 ? 1 : 2); }
 };
 
 struct Level {

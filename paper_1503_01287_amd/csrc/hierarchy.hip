@@ -864,21 +864,24 @@ void setup_vanka(amg_ctx *h, int l) {
     V.roff.upload(roff, s);
     V.tpre.upload(tpre, s);
     V.rbuf.alloc(static_cast<size_t>(std::max<int64_t>(1, rtot)));
-    {
-        // the tiled path's residual: 16 node rows (and the pressure row) per unit
+    // the tiled path's residual: rg lanes per row, 256 / rg node rows (and
+    // the pressure row) per unit, tables for every rg
+    for (const int rg : {16, 32, 64}) {
+        const int rows = 256 / rg, ri = VankaData::rg_index(rg);
         std::vector<int> rpre(std::max(1, np), 0);
-        V.nrunits.assign(nc, 0);
+        V.nrunits[ri].assign(nc, 0);
         for (int c = 0; c < nc; ++c) {
             int t = 0;
             for (int k = V.cptr[c]; k < V.cptr[c + 1]; ++k) {
                 rpre[k] = t;
                 const int i = order[k];
-                t += (bp.rowptr[i + 1] - bp.rowptr[i] + 1 + 15) / 16;
+                t += (bp.rowptr[i + 1] - bp.rowptr[i] + 1 + rows - 1) / rows;
             }
-            V.nrunits[c] = t;
+            V.nrunits[ri][c] = t;
         }
-        V.rpre.upload(rpre, s);
+        V.rpre[ri].upload(rpre, s);
     }
+    V.rg = 16;
     // three-kernel path: 64-row x cc-column tiles of the inverses and their
     // partial sums, colour by colour, for a chunk width cc
     auto tile_tables = [&](int cc) {
@@ -926,8 +929,9 @@ void setup_vanka(amg_ctx *h, int l) {
                 const int cnt = V.cptr[c + 1] - V.cptr[c];
                 if (path == 2)
                     launch_vanka_colour_tiled(view, V.order.p + V.cptr[c], V.tpre.p + V.cptr[c],
-                                              V.upre.p + V.cptr[c], V.rpre.p + V.cptr[c], cnt, V.ntiles[c],
-                                              V.nunits[c], V.nrunits[c], V.cc, V.roff.p, V.rbuf.p, V.poff.p,
+                                              V.upre.p + V.cptr[c], V.rpre[VankaData::rg_index(V.rg)].p + V.cptr[c],
+                                              cnt, V.ntiles[c], V.nunits[c],
+                                              V.nrunits[VankaData::rg_index(V.rg)][c], V.cc, V.rg, V.roff.p, V.rbuf.p, V.poff.p,
                                               V.pbuf.p, bs.p, xs.p, 0.5, s);
                 else if (path == 1)
                     launch_vanka_colour_split(view, V.order.p + V.cptr[c], V.tpre.p + V.cptr[c], cnt, V.ntiles[c],
@@ -972,6 +976,19 @@ void setup_vanka(amg_ctx *h, int l) {
         }
         tile_tables(best_cc);
         V.path = best_path;
+        if (best_path == 2) {
+            // the tiled form's residual: wider lane groups for long rows
+            int best_rg = 16;
+            for (const int rg : {32, 64}) {
+                V.rg = rg;
+                const float t = time_of(2);
+                if (t < 0.97f * best) {
+                    best = t;
+                    best_rg = rg;
+                }
+            }
+            V.rg = best_rg;
+        }
         AMG_HIP(hipEventDestroy(e0));
         AMG_HIP(hipEventDestroy(e1));
     }

@@ -457,15 +457,17 @@ __global__ void __launch_bounds__(64) k_vanka_reduce(const VankaView v, const in
     else x[3 * static_cast<int64_t>(v.n) + i] += d;
 }
 
-// Residuals of one colour's patches, 16 node rows (16 lanes each) per
+// Residuals of one colour's patches, VB / G node rows (G lanes each) per
 // workgroup so that a colour of few, large patches still spreads over the
-// GPU (rpre: prefix of ceil((n_P + 1) / 16) over the colour's patches; the
-// last row of a patch is its pressure row); the same arithmetic as
-// k_vanka_resid.
-constexpr int VRW = VB / VG;  // node rows per workgroup
+// GPU (rpre: prefix of ceil((n_P + 1) / (VB / G)) over the colour's
+// patches; the last row of a patch is its pressure row); with G = 16 the
+// same arithmetic as k_vanka_resid, wider groups for the long rows of
+// coarse levels.
+template <int G>
 __global__ void __launch_bounds__(VB) k_vanka_resid_rows(const VankaView v, const int *order, const int *rpre,
                                                          int count, const int64_t *roff, double *rbuf,
                                                          const double *b, const double *x) {
+    constexpr int VRW = VB / G;  // node rows per workgroup
     int lo = 0, hi = count - 1;
     const int t = blockIdx.x;
     while (lo < hi) {
@@ -475,33 +477,33 @@ __global__ void __launch_bounds__(VB) k_vanka_resid_rows(const VankaView v, cons
     }
     const int i = order[lo];
     const int p0 = v.pptr[i], nn = v.pptr[i + 1] - p0;
-    const int grp = threadIdx.x / VG, lane = threadIdx.x % VG;
+    const int grp = threadIdx.x / G, lane = threadIdx.x % G;
     const int k = (t - rpre[lo]) * VRW + grp;
-    if (k > nn) return;  // whole 16-lane groups leave together
+    if (k > nn) return;  // whole G-lane groups leave together
     double *r = rbuf + roff[i];
     const int64_t nu = 3 * static_cast<int64_t>(v.n);
     const double *p = x + nu;
     if (k < nn) {
         const int u = v.pnode[p0 + k];
         double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-        for (int q = v.arow[u] + lane; q < v.arow[u + 1]; q += VG) {
+        for (int q = v.arow[u] + lane; q < v.arow[u + 1]; q += G) {
             const int j = v.acol[q];
             const double x0 = x[3 * j], x1 = x[3 * j + 1], x2 = x[3 * j + 2];
             s0 += v.aval[0 * v.annz + q] * x0 + v.aval[1 * v.annz + q] * x1 + v.aval[2 * v.annz + q] * x2;
             s1 += v.aval[3 * v.annz + q] * x0 + v.aval[4 * v.annz + q] * x1 + v.aval[5 * v.annz + q] * x2;
             s2 += v.aval[6 * v.annz + q] * x0 + v.aval[7 * v.annz + q] * x1 + v.aval[8 * v.annz + q] * x2;
         }
-        for (int q = v.btrow[u] + lane; q < v.btrow[u + 1]; q += VG) {
+        for (int q = v.btrow[u] + lane; q < v.btrow[u + 1]; q += G) {
             const double pq = p[v.btcol[q]];
             s0 += v.btval[q] * pq;
             s1 += v.btval[v.btnnz + q] * pq;
             s2 += v.btval[2 * v.btnnz + q] * pq;
         }
 #pragma unroll
-        for (int o = VG / 2; o > 0; o >>= 1) {
-            s0 += __shfl_xor(s0, o, VG);
-            s1 += __shfl_xor(s1, o, VG);
-            s2 += __shfl_xor(s2, o, VG);
+        for (int o = G / 2; o > 0; o >>= 1) {
+            s0 += __shfl_xor(s0, o, G);
+            s1 += __shfl_xor(s1, o, G);
+            s2 += __shfl_xor(s2, o, G);
         }
         if (lane == 0) {
             r[3 * k] = b[3 * u] - s0;
@@ -510,24 +512,29 @@ __global__ void __launch_bounds__(VB) k_vanka_resid_rows(const VankaView v, cons
         }
     } else {
         double s = 0.0;
-        for (int q = v.brow[i] + lane; q < v.brow[i + 1]; q += VG) {
+        for (int q = v.brow[i] + lane; q < v.brow[i + 1]; q += G) {
             const int j = v.bcol[q];
             s += v.bval[q] * x[3 * j] + v.bval[v.bnnz + q] * x[3 * j + 1] + v.bval[2 * v.bnnz + q] * x[3 * j + 2];
         }
         if (v.crow)
-            for (int q = v.crow[i] + lane; q < v.crow[i + 1]; q += VG) s -= v.cval[q] * p[v.ccol[q]];
+            for (int q = v.crow[i] + lane; q < v.crow[i + 1]; q += G) s -= v.cval[q] * p[v.ccol[q]];
 #pragma unroll
-        for (int o = VG / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, VG);
+        for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, G);
         if (lane == 0) r[3 * nn] = b[nu + i] - s;
     }
 }
 
 void launch_vanka_colour_tiled(const VankaView &v, const int *order, const int *tpre, const int *upre,
-                               const int *rpre, int count, int ntiles, int nunits, int nrunits, int cc,
+                               const int *rpre, int count, int ntiles, int nunits, int nrunits, int cc, int rg,
                                const int64_t *roff, double *rbuf, const int64_t *poff, double *pbuf, const double *b,
                                double *x, double omega, hipStream_t s) {
     if (count <= 0) return;
-    k_vanka_resid_rows<<<nrunits, VB, 0, s>>>(v, order, rpre, count, roff, rbuf, b, x);
+    switch (rg) {
+        case 16: k_vanka_resid_rows<16><<<nrunits, VB, 0, s>>>(v, order, rpre, count, roff, rbuf, b, x); break;
+        case 32: k_vanka_resid_rows<32><<<nrunits, VB, 0, s>>>(v, order, rpre, count, roff, rbuf, b, x); break;
+        case 64: k_vanka_resid_rows<64><<<nrunits, VB, 0, s>>>(v, order, rpre, count, roff, rbuf, b, x); break;
+        default: throw Error(AMG_EINVAL, "Vanka residual: 16, 32 or 64 lanes per row");
+    }
     AMG_CHECK_LAUNCH();
     k_vanka_apply_part<<<nunits, VB, 0, s>>>(v, order, upre, count, cc, roff, rbuf, poff, pbuf);
     AMG_CHECK_LAUNCH();

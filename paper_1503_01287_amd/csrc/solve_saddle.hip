@@ -517,7 +517,8 @@ static void vanka_step(amg_ctx *h, int l, const double *b, double *x) {
         const int cnt = V.cptr[c + 1] - V.cptr[c];
         if (V.path == 2)
             launch_vanka_colour_tiled(v, V.order.p + V.cptr[c], V.tpre.p + V.cptr[c], V.upre.p + V.cptr[c],
-                                      V.rpre.p + V.cptr[c], cnt, V.ntiles[c], V.nunits[c], V.nrunits[c], V.cc,
+                                      V.rpre[VankaData::rg_index(V.rg)].p + V.cptr[c], cnt, V.ntiles[c], V.nunits[c],
+                                      V.nrunits[VankaData::rg_index(V.rg)][c], V.cc, V.rg,
                                       V.roff.p, V.rbuf.p, V.poff.p, V.pbuf.p, b, x, h->prm.vanka_omega, h->stream);
         else if (V.path == 1)
             launch_vanka_colour_split(v, V.order.p + V.cptr[c], V.tpre.p + V.cptr[c], cnt, V.ntiles[c], V.max_nodes,

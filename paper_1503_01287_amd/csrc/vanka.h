@@ -47,15 +47,16 @@ void launch_vanka_colour_split(const VankaView &v, const int *order, const int *
                                int max_nodes, const int64_t *roff, double *rbuf, const double *b, double *x,
                                double omega, hipStream_t s);
 // the same colour in three kernels for colours of few, large patches: the
-// residuals into rbuf, 16 node rows per workgroup (rpre: prefix of
-// ceil((n_P + 1) / 16) over the colour's patches, nrunits their total),
+// residuals into rbuf, rg lanes per row (16, 32 or 64) and 256 / rg node
+// rows per workgroup (rpre: prefix of ceil((n_P + 1) / (256 / rg)) over the
+// colour's patches, nrunits their total),
 // then partial corrections over 64-row x cc-column tiles of every inverse
 // into pbuf (patch i's ceil(m_i / cc) chunks of m_i values at pbuf +
 // poff[i]; upre: prefix of the tiles ceil(m_i / 64) ceil(m_i / cc) over the
 // colour's patches, nunits their total), then the chunks summed in order
 // into x over the 64-row tiles (tpre, ntiles)
 void launch_vanka_colour_tiled(const VankaView &v, const int *order, const int *tpre, const int *upre,
-                               const int *rpre, int count, int ntiles, int nunits, int nrunits, int cc,
+                               const int *rpre, int count, int ntiles, int nunits, int nrunits, int cc, int rg,
                                const int64_t *roff, double *rbuf, const int64_t *poff, double *pbuf, const double *b,
                                double *x, double omega, hipStream_t s);
 

@@ -58,6 +58,36 @@ def _mv(o):
     return mv
 
 
+def test_vanka_tiled_sweep_every_residual_width(case):
+    """The tiled form forced on every level with 16, 32 and 64 lanes per
+    residual row: each sweep equals the oracle's."""
+    name, hs, o, h = case
+    s = amg.AMGSolver(hs, smoother="Vanka-1-1", krylov="FGMRES", autotune=False)
+    sm = oamg.Smoother.parse("Vanka-1-1")
+    rng = np.random.default_rng(52)
+    for l in range(len(h.levels) - 1):
+        lev = h.levels[l]
+        nv = 3 * lev.n
+        n = nv + lev.npres
+        z, b = rng.standard_normal(n), rng.standard_normal(n)
+        u, p = oamg.vanka_step(lev, sm, b[:nv].reshape(-1, 3), b[nv:], z[:nv].reshape(-1, 3), z[nv:])
+        ref = np.concatenate([u.ravel(), p])
+        for lanes in (16, 32, 64):
+            s.set_launch_shape(l, "vanka", lanes)
+            xd = dev(z)
+            s.smooth(l, dev(b), xd)
+            assert rel(host(xd), ref) < 1e-11, (name, l, lanes)
+    with pytest.raises(amg.AmgError):
+        s.set_launch_shape(0, "vanka", 8)
+    with pytest.raises(amg.AmgError):
+        s.set_launch_shape(len(h.levels) - 1, "vanka", 16)
+    s.close()
+    spd = amg.AMGSolver(amg.problems.elasticity(3), smoother="GS-1-1", krylov="PCG")
+    with pytest.raises(amg.AmgError):
+        spd.set_launch_shape(0, "vanka", 16)
+    spd.close()
+
+
 @pytest.mark.parametrize("autotune", [True, False])
 def test_vanka_sweep(case, autotune):
     """Every level; without the tuner, patches above 256 unknowns take the
