@@ -414,7 +414,8 @@ def measure(name: str, sysm, rhs, steps: int, warmup: int, tol: float, precision
             traffic = measured_traffic(name, precision, dom, lanes, trip, xcd)
             res["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                               "kernel": dom, "launches_per_step": st["launches"] // steps,
+                               "kernel": dom, "launch_shape": {"lanes": lanes, "trip": trip, "xcd": xcd},
+                               "launches_per_step": st["launches"] // steps,
                                "bytes_per_launch": per_launch_bytes,
                                "mean_launch_us": round(per_launch_ms * 1e3, 2),
                                "profiled_ms_per_step": round(prof_ms, 2)}
