@@ -346,9 +346,10 @@ int amg_get_level_colors(amg_handle h, int32_t level, int32_t *colors);
  * always take 1). xcd (colour sweeps only): 1 = each XCD takes one
  * contiguous eighth of a colour's rows, 0 = round-robin placement.
  * AMG_SHAPE_VANKA (Vanka smoother, any level but the coarsest): the
- * level's sweeps take the tiled form (patch residuals, 64-row tiles of the
- * patch inverses, their sum in order) with `lanes` lanes per residual row,
- * 16, 32 or 64 (trip 1, xcd 0).
+ * level's sweeps compute the patch residuals with `lanes` lanes per row
+ * (16, 32 or 64), then, for trip 1, partial corrections over 64-row x
+ * chunk tiles of the patch inverses and their sum in chunk order, for
+ * trip 2, the corrections over 64-row tiles of the inverses (xcd 0).
  * Recorded preconditioner graphs are dropped (they hold the old shapes).
  * Errors: AMG_EINVAL for a bad level, kernel class, lane count, trip or flag, or a
  * reduced-precision class on an FP64 hierarchy. */

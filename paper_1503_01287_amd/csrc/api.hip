@@ -644,9 +644,9 @@ int amg_set_launch_shape(amg_handle h, int32_t level, int32_t kernels, int32_t l
             case AMG_SHAPE_VANKA:
                 AMG_REQUIRE(h->saddle && h->prm.smoother == AMG_SMOOTH_VANKA && !L.vanka.cptr.empty(), AMG_EINVAL,
                             "amg_set_launch_shape: no Vanka sweep on this level");
-                AMG_REQUIRE(lanes >= 16 && trip == 1 && xcd == 0, AMG_EINVAL,
-                            "amg_set_launch_shape: the Vanka residual takes 16, 32 or 64 lanes, trip 1, xcd 0");
-                L.vanka.path = 2;
+                AMG_REQUIRE(lanes >= 16 && (trip == 1 || trip == 2) && xcd == 0, AMG_EINVAL,
+                            "amg_set_launch_shape: the Vanka residual takes 16, 32 or 64 lanes, trip 1 or 2, xcd 0");
+                L.vanka.path = trip == 1 ? 2 : 3;
                 L.vanka.rg = lanes;
                 break;
             default: throw Error(AMG_EINVAL, "amg_set_launch_shape: unknown kernel class");

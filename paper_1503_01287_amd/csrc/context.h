@@ -122,10 +122,11 @@ struct VankaData {
     DevBuf<double> inv;
     std::vector<int> cptr;
     // sweep form (chosen at setup): 0 one kernel per colour; 1 residuals,
-    // then corrections over 64-row tiles; 2 residuals, partial corrections
-    // over 64-row x cc-column tiles, then their sum
+    // then corrections over 64-row tiles; 2 residuals spread over rows,
+    // partial corrections over 64-row x cc-column tiles, then their sum;
+    // 3 residuals spread over rows, then corrections over 64-row tiles
     int path = 0;
-    DevBuf<int64_t> roff;          // residual buffer offsets (paths 1, 2)
+    DevBuf<int64_t> roff;          // residual buffer offsets (paths 1, 2, 3)
     DevBuf<double> rbuf;
     DevBuf<int> tpre;              // per-colour prefix of the 64-row tiles
     std::vector<int> ntiles;       // 64-row tiles per colour
@@ -134,8 +135,8 @@ struct VankaData {
     std::vector<int> nunits;       // path 2: 2-D tiles per colour
     DevBuf<int64_t> poff;          // path 2: partial buffer offsets
     DevBuf<double> pbuf;
-    int rg = 16;                   // path 2: lanes per residual row (16, 32 or 64)
-    // path 2, for rg = 16, 32, 64 (index rg_index): per-colour prefix of the
+    int rg = 16;                   // paths 2, 3: lanes per residual row (16, 32 or 64)
+    // paths 2 and 3, for rg = 16, 32, 64 (index rg_index): per-colour prefix of the
     // residual's units (256 / rg node rows each) and units per colour
     DevBuf<int> rpre[3];
     std::vector<int> nrunits[3];

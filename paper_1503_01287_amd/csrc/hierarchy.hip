@@ -933,6 +933,11 @@ void setup_vanka(amg_ctx *h, int l) {
                                               cnt, V.ntiles[c], V.nunits[c],
                                               V.nrunits[VankaData::rg_index(V.rg)][c], V.cc, V.rg, V.roff.p, V.rbuf.p, V.poff.p,
                                               V.pbuf.p, bs.p, xs.p, 0.5, s);
+                else if (path == 3)
+                    launch_vanka_colour_rows(view, V.order.p + V.cptr[c], V.tpre.p + V.cptr[c],
+                                             V.rpre[VankaData::rg_index(V.rg)].p + V.cptr[c], cnt, V.ntiles[c],
+                                             V.nrunits[VankaData::rg_index(V.rg)][c], V.rg, V.roff.p, V.rbuf.p, bs.p,
+                                             xs.p, 0.5, s);
                 else if (path == 1)
                     launch_vanka_colour_split(view, V.order.p + V.cptr[c], V.tpre.p + V.cptr[c], cnt, V.ntiles[c],
                                               V.max_nodes, V.roff.p, V.rbuf.p, bs.p, xs.p, 0.5, s);
@@ -975,20 +980,23 @@ void setup_vanka(amg_ctx *h, int l) {
             }
         }
         tile_tables(best_cc);
-        V.path = best_path;
-        if (best_path == 2) {
-            // the tiled form's residual: wider lane groups for long rows
-            int best_rg = 16;
-            for (const int rg : {32, 64}) {
-                V.rg = rg;
-                const float t = time_of(2);
+        // the spread residual's width (wider lane groups for long rows), in
+        // the tiled form and in the two-kernel form with that residual
+        int best_rg = 16;
+        for (const int rg : {16, 32, 64}) {
+            V.rg = rg;
+            for (const int path : {2, 3}) {
+                if (path == 2 && rg == 16) continue;  // timed above
+                const float t = time_of(path);
                 if (t < 0.97f * best) {
                     best = t;
+                    best_path = path;
                     best_rg = rg;
                 }
             }
-            V.rg = best_rg;
         }
+        V.rg = best_rg;
+        V.path = best_path;
         AMG_HIP(hipEventDestroy(e0));
         AMG_HIP(hipEventDestroy(e1));
     }

@@ -524,11 +524,8 @@ __global__ void __launch_bounds__(VB) k_vanka_resid_rows(const VankaView v, cons
     }
 }
 
-void launch_vanka_colour_tiled(const VankaView &v, const int *order, const int *tpre, const int *upre,
-                               const int *rpre, int count, int ntiles, int nunits, int nrunits, int cc, int rg,
-                               const int64_t *roff, double *rbuf, const int64_t *poff, double *pbuf, const double *b,
-                               double *x, double omega, hipStream_t s) {
-    if (count <= 0) return;
+static void resid_rows(const VankaView &v, const int *order, const int *rpre, int count, int nrunits, int rg,
+                       const int64_t *roff, double *rbuf, const double *b, const double *x, hipStream_t s) {
     switch (rg) {
         case 16: k_vanka_resid_rows<16><<<nrunits, VB, 0, s>>>(v, order, rpre, count, roff, rbuf, b, x); break;
         case 32: k_vanka_resid_rows<32><<<nrunits, VB, 0, s>>>(v, order, rpre, count, roff, rbuf, b, x); break;
@@ -536,6 +533,23 @@ void launch_vanka_colour_tiled(const VankaView &v, const int *order, const int *
         default: throw Error(AMG_EINVAL, "Vanka residual: 16, 32 or 64 lanes per row");
     }
     AMG_CHECK_LAUNCH();
+}
+
+void launch_vanka_colour_rows(const VankaView &v, const int *order, const int *tpre, const int *rpre, int count,
+                              int ntiles, int nrunits, int rg, const int64_t *roff, double *rbuf, const double *b,
+                              double *x, double omega, hipStream_t s) {
+    if (count <= 0) return;
+    resid_rows(v, order, rpre, count, nrunits, rg, roff, rbuf, b, x, s);
+    k_vanka_apply<<<ntiles, VB, 0, s>>>(v, order, tpre, count, roff, rbuf, x, omega);
+    AMG_CHECK_LAUNCH();
+}
+
+void launch_vanka_colour_tiled(const VankaView &v, const int *order, const int *tpre, const int *upre,
+                               const int *rpre, int count, int ntiles, int nunits, int nrunits, int cc, int rg,
+                               const int64_t *roff, double *rbuf, const int64_t *poff, double *pbuf, const double *b,
+                               double *x, double omega, hipStream_t s) {
+    if (count <= 0) return;
+    resid_rows(v, order, rpre, count, nrunits, rg, roff, rbuf, b, x, s);
     k_vanka_apply_part<<<nunits, VB, 0, s>>>(v, order, upre, count, cc, roff, rbuf, poff, pbuf);
     AMG_CHECK_LAUNCH();
     k_vanka_reduce<<<ntiles, 64, 0, s>>>(v, order, tpre, count, cc, poff, pbuf, x, omega);

@@ -520,6 +520,11 @@ static void vanka_step(amg_ctx *h, int l, const double *b, double *x) {
                                       V.rpre[VankaData::rg_index(V.rg)].p + V.cptr[c], cnt, V.ntiles[c], V.nunits[c],
                                       V.nrunits[VankaData::rg_index(V.rg)][c], V.cc, V.rg,
                                       V.roff.p, V.rbuf.p, V.poff.p, V.pbuf.p, b, x, h->prm.vanka_omega, h->stream);
+        else if (V.path == 3)
+            launch_vanka_colour_rows(v, V.order.p + V.cptr[c], V.tpre.p + V.cptr[c],
+                                     V.rpre[VankaData::rg_index(V.rg)].p + V.cptr[c], cnt, V.ntiles[c],
+                                     V.nrunits[VankaData::rg_index(V.rg)][c], V.rg, V.roff.p, V.rbuf.p, b, x,
+                                     h->prm.vanka_omega, h->stream);
         else if (V.path == 1)
             launch_vanka_colour_split(v, V.order.p + V.cptr[c], V.tpre.p + V.cptr[c], cnt, V.ntiles[c], V.max_nodes,
                                       V.roff.p, V.rbuf.p, b, x, h->prm.vanka_omega, h->stream);

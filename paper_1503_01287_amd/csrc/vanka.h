@@ -46,6 +46,12 @@ void launch_vanka_colour(const VankaView &v, const int *order, int count, int ma
 void launch_vanka_colour_split(const VankaView &v, const int *order, const int *tpre, int count, int ntiles,
                                int max_nodes, const int64_t *roff, double *rbuf, const double *b, double *x,
                                double omega, hipStream_t s);
+// the residual spread as in the tiled form (rpre, nrunits, rg), then the
+// corrections over 64-row tiles of every inverse as the two-kernel form
+// (tpre, ntiles)
+void launch_vanka_colour_rows(const VankaView &v, const int *order, const int *tpre, const int *rpre, int count,
+                              int ntiles, int nrunits, int rg, const int64_t *roff, double *rbuf, const double *b,
+                              double *x, double omega, hipStream_t s);
 // the same colour in three kernels for colours of few, large patches: the
 // residuals into rbuf, rg lanes per row (16, 32 or 64) and 256 / rg node
 // rows per workgroup (rpre: prefix of ceil((n_P + 1) / (256 / rg)) over the

@@ -213,8 +213,9 @@ class AMGSolver:
         """Override the tuner's launch shape of one kernel class on a level:
         kernels 'natural', 'sweep', 'natural_rp' or 'sweep_rp'; lanes per
         row; entries per lane and loop trip (1, 2 or 4). 'vanka': the
-        level's Vanka sweeps in the tiled form with `lanes` (16, 32, 64)
-        lanes per residual row."""
+        level's Vanka sweeps with `lanes` (16, 32, 64) lanes per residual
+        row, then the corrections over 2-D tiles of the inverses (trip 1)
+        or over 64-row tiles (trip 2)."""
         C.check(C.lib().amg_set_launch_shape(self.h, level, C.SHAPE[kernels], int(lanes), int(trip),
                                              1 if xcd else 0), "amg_set_launch_shape")
 

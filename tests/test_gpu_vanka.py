@@ -59,8 +59,9 @@ def _mv(o):
 
 
 def test_vanka_tiled_sweep_every_residual_width(case):
-    """The tiled form forced on every level with 16, 32 and 64 lanes per
-    residual row: each sweep equals the oracle's."""
+    """The spread-residual forms (2-D tiles and their sum; 64-row tiles)
+    forced on every level with 16, 32 and 64 lanes per residual row: each
+    sweep equals the oracle's."""
     name, hs, o, h = case
     s = amg.AMGSolver(hs, smoother="Vanka-1-1", krylov="FGMRES", autotune=False)
     sm = oamg.Smoother.parse("Vanka-1-1")
@@ -72,13 +73,16 @@ def test_vanka_tiled_sweep_every_residual_width(case):
         z, b = rng.standard_normal(n), rng.standard_normal(n)
         u, p = oamg.vanka_step(lev, sm, b[:nv].reshape(-1, 3), b[nv:], z[:nv].reshape(-1, 3), z[nv:])
         ref = np.concatenate([u.ravel(), p])
-        for lanes in (16, 32, 64):
-            s.set_launch_shape(l, "vanka", lanes)
-            xd = dev(z)
-            s.smooth(l, dev(b), xd)
-            assert rel(host(xd), ref) < 1e-11, (name, l, lanes)
+        for form in (1, 2):
+            for lanes in (16, 32, 64):
+                s.set_launch_shape(l, "vanka", lanes, form)
+                xd = dev(z)
+                s.smooth(l, dev(b), xd)
+                assert rel(host(xd), ref) < 1e-11, (name, l, form, lanes)
     with pytest.raises(amg.AmgError):
         s.set_launch_shape(0, "vanka", 8)
+    with pytest.raises(amg.AmgError):
+        s.set_launch_shape(0, "vanka", 32, 4)
     with pytest.raises(amg.AmgError):
         s.set_launch_shape(len(h.levels) - 1, "vanka", 16)
     s.close()
