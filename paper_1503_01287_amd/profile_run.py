@@ -38,6 +38,8 @@ def main() -> int:
                     choices=["elasticity-32", "mixed-elasticity-24", "laplace-48", "stokes-batch-64"])
     ap.add_argument("--precision", default=None, choices=["FP64", "MIXED", "FP32"],
                     help="default: MIXED, FP32 for the Stokes batch")
+    ap.add_argument("--smoother", default=None,
+                    help="default: the workload's (GS-1-1, JA-1-1-0.5, sGS-1-1, BS-1-1)")
     ap.add_argument("--solves", type=int, default=1)
     ap.add_argument("--copy-mib", type=int, default=256)
     ap.add_argument("--fuse-coarse", type=int, default=1, choices=[0, 1],
@@ -59,7 +61,8 @@ def main() -> int:
     prec = args.precision or ("FP32" if wl == "stokes-batch-64" else "MIXED")
     if wl == "stokes-batch-64":
         systems = [problems.stokes_cavity(n, sp) for n, sp in synth.stokes_batch()]
-        s = BatchedSolver(systems, smoother="BS-1-1", precision=prec, fuse_coarse=bool(args.fuse_coarse))
+        s = BatchedSolver(systems, smoother=args.smoother or "BS-1-1", precision=prec,
+                          fuse_coarse=bool(args.fuse_coarse))
         rhs = __import__("numpy").concatenate([q.rhs for q in systems])
         kry = "FGMRES"
     else:
@@ -74,6 +77,8 @@ def main() -> int:
             sysm, kw["smoother"] = problems.mixed_elasticity(24), "sGS-1-1"
         saddle = sysm.n_pres > 0
         kry = "FGMRES" if saddle else ("PCG" if prec == "FP64" else "FCG")
+        if args.smoother:
+            kw["smoother"] = args.smoother
         s = AMGSolver(sysm, krylov=kry, precision=prec, fuse_coarse=bool(args.fuse_coarse), **kw)
         rhs = sysm.rhs
     for spec in args.shape:
