@@ -350,6 +350,8 @@ int amg_get_level_colors(amg_handle h, int32_t level, int32_t *colors);
  * (16, 32 or 64), then, for trip 1, partial corrections over 64-row x
  * chunk tiles of the patch inverses and their sum in chunk order, for
  * trip 2, the corrections over 64-row tiles of the inverses (xcd 0).
+ * AMG_SHAPE_VANKA_APPLY: the latter form, with `lanes` = 4, 8 or 16
+ * wavefronts per 64-row tile splitting its columns (trip 1, xcd 0).
  * Recorded preconditioner graphs are dropped (they hold the old shapes).
  * Errors: AMG_EINVAL for a bad level, kernel class, lane count, trip or flag, or a
  * reduced-precision class on an FP64 hierarchy. */
@@ -358,6 +360,7 @@ int amg_get_level_colors(amg_handle h, int32_t level, int32_t *colors);
 #define AMG_SHAPE_NATURAL_RP 2
 #define AMG_SHAPE_SWEEP_RP 3
 #define AMG_SHAPE_VANKA 4
+#define AMG_SHAPE_VANKA_APPLY 5
 int amg_set_launch_shape(amg_handle h, int32_t level, int32_t kernels, int32_t lanes, int32_t trip, int32_t xcd);
 
 /* ---- batches of independent systems ------------------------------------

@@ -22,7 +22,7 @@ AMG_MEM_HOST, AMG_MEM_DEVICE = 0, 1
 SMOOTH = {"JA": 0, "GS": 1, "SGS": 2, "BS": 3, "VANKA": 4}
 KRYLOV = {"PCG": 0, "FCG": 1, "FGMRES": 2, "NONE": 3}
 PREC = {"FP64": 0, "MIXED": 1, "FP32": 2}
-SHAPE = {"natural": 0, "sweep": 1, "natural_rp": 2, "sweep_rp": 3, "vanka": 4}
+SHAPE = {"natural": 0, "sweep": 1, "natural_rp": 2, "sweep_rp": 3, "vanka": 4, "vanka_apply": 5}
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _f64p = ctypes.POINTER(ctypes.c_double)

@@ -649,6 +649,14 @@ int amg_set_launch_shape(amg_handle h, int32_t level, int32_t kernels, int32_t l
                 L.vanka.path = trip == 1 ? 2 : 3;
                 L.vanka.rg = lanes;
                 break;
+            case AMG_SHAPE_VANKA_APPLY:
+                AMG_REQUIRE(h->saddle && h->prm.smoother == AMG_SMOOTH_VANKA && !L.vanka.cptr.empty(), AMG_EINVAL,
+                            "amg_set_launch_shape: no Vanka sweep on this level");
+                AMG_REQUIRE(lanes >= 4 && lanes <= 16 && trip == 1 && xcd == 0, AMG_EINVAL,
+                            "amg_set_launch_shape: 4, 8 or 16 wavefronts per Vanka correction tile, trip 1, xcd 0");
+                L.vanka.path = 3;
+                L.vanka.aw = lanes;
+                break;
             default: throw Error(AMG_EINVAL, "amg_set_launch_shape: unknown kernel class");
         }
         for (auto &g : h->graphs) (void)hipGraphExecDestroy(g.exec);

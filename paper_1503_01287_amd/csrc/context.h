@@ -136,6 +136,7 @@ struct VankaData {
     DevBuf<int64_t> poff;          // path 2: partial buffer offsets
     DevBuf<double> pbuf;
     int rg = 16;                   // paths 2, 3: lanes per residual row (16, 32 or 64)
+    int aw = 4;                    // path 3: wavefronts per 64-row correction tile (4, 8 or 16)
     // paths 2 and 3, for rg = 16, 32, 64 (index rg_index): per-colour prefix of the
     // residual's units (256 / rg node rows each) and units per colour
     DevBuf<int> rpre[3];

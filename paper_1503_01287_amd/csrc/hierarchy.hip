@@ -936,7 +936,7 @@ void setup_vanka(amg_ctx *h, int l) {
                 else if (path == 3)
                     launch_vanka_colour_rows(view, V.order.p + V.cptr[c], V.tpre.p + V.cptr[c],
                                              V.rpre[VankaData::rg_index(V.rg)].p + V.cptr[c], cnt, V.ntiles[c],
-                                             V.nrunits[VankaData::rg_index(V.rg)][c], V.rg, V.roff.p, V.rbuf.p, bs.p,
+                                             V.nrunits[VankaData::rg_index(V.rg)][c], V.rg, V.aw, V.roff.p, V.rbuf.p, bs.p,
                                              xs.p, 0.5, s);
                 else if (path == 1)
                     launch_vanka_colour_split(view, V.order.p + V.cptr[c], V.tpre.p + V.cptr[c], cnt, V.ntiles[c],
@@ -997,6 +997,19 @@ void setup_vanka(amg_ctx *h, int l) {
         }
         V.rg = best_rg;
         V.path = best_path;
+        if (best_path == 3) {
+            // wavefronts per correction tile: shorter column chains per lane
+            int best_aw = 4;
+            for (const int aw : {8, 16}) {
+                V.aw = aw;
+                const float t = time_of(3);
+                if (t < 0.97f * best) {
+                    best = t;
+                    best_aw = aw;
+                }
+            }
+            V.aw = best_aw;
+        }
         AMG_HIP(hipEventDestroy(e0));
         AMG_HIP(hipEventDestroy(e1));
     }

@@ -336,12 +336,14 @@ __global__ void __launch_bounds__(VCB) k_vanka_resid(const VankaView v, const in
     }
 }
 
-// 64 rows of one patch's correction per workgroup: lane = row, the 4
-// wavefronts take a quarter of the columns each, partial sums added in LDS.
-__global__ void __launch_bounds__(VB) k_vanka_apply(const VankaView v, const int *order, const int *tpre,
-                                                    int count, const int64_t *roff, const double *rbuf,
-                                                    double *x, double omega) {
-    __shared__ double part[4][64];
+// 64 rows of one patch's correction per workgroup: lane = row, the NW
+// wavefronts take 1 / NW of the columns each, partial sums added in LDS in
+// wavefront order.
+template <int NW>
+__global__ void __launch_bounds__(64 * NW) k_vanka_apply(const VankaView v, const int *order, const int *tpre,
+                                                         int count, const int64_t *roff, const double *rbuf,
+                                                         double *x, double omega) {
+    __shared__ double part[NW][64];
     int lo = 0, hi = count - 1;
     const int t = blockIdx.x;
     while (lo < hi) {  // last patch whose first tile is <= t
@@ -356,7 +358,7 @@ __global__ void __launch_bounds__(VB) k_vanka_apply(const VankaView v, const int
     const int wave = threadIdx.x >> 6;
     const double *r = rbuf + roff[i];
     const double *M = v.inv + v.moff[i];
-    const int c0 = wave * m / 4, c1 = (wave + 1) * m / 4;
+    const int c0 = wave * m / NW, c1 = (wave + 1) * m / NW;
     double acc = 0.0;
     if (a < m) {
         int c = c0;
@@ -376,7 +378,10 @@ __global__ void __launch_bounds__(VB) k_vanka_apply(const VankaView v, const int
     __syncthreads();
     if (wave != 0 || a >= m) return;
     const int l = threadIdx.x;
-    const double d = omega * (((part[0][l] + part[1][l]) + part[2][l]) + part[3][l]);
+    double sum = part[0][l];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) sum += part[w][l];
+    const double d = omega * sum;
     if (a < 3 * nn) x[3 * static_cast<int64_t>(v.pnode[p0 + a / 3]) + a % 3] += d;
     else x[3 * static_cast<int64_t>(v.n) + i] += d;
 }
@@ -536,11 +541,16 @@ static void resid_rows(const VankaView &v, const int *order, const int *rpre, in
 }
 
 void launch_vanka_colour_rows(const VankaView &v, const int *order, const int *tpre, const int *rpre, int count,
-                              int ntiles, int nrunits, int rg, const int64_t *roff, double *rbuf, const double *b,
-                              double *x, double omega, hipStream_t s) {
+                              int ntiles, int nrunits, int rg, int aw, const int64_t *roff, double *rbuf,
+                              const double *b, double *x, double omega, hipStream_t s) {
     if (count <= 0) return;
     resid_rows(v, order, rpre, count, nrunits, rg, roff, rbuf, b, x, s);
-    k_vanka_apply<<<ntiles, VB, 0, s>>>(v, order, tpre, count, roff, rbuf, x, omega);
+    switch (aw) {
+        case 4: k_vanka_apply<4><<<ntiles, 256, 0, s>>>(v, order, tpre, count, roff, rbuf, x, omega); break;
+        case 8: k_vanka_apply<8><<<ntiles, 512, 0, s>>>(v, order, tpre, count, roff, rbuf, x, omega); break;
+        case 16: k_vanka_apply<16><<<ntiles, 1024, 0, s>>>(v, order, tpre, count, roff, rbuf, x, omega); break;
+        default: throw Error(AMG_EINVAL, "Vanka corrections: 4, 8 or 16 wavefronts per tile");
+    }
     AMG_CHECK_LAUNCH();
 }
 
@@ -562,7 +572,7 @@ void launch_vanka_colour_split(const VankaView &v, const int *order, const int *
     if (count <= 0) return;
     k_vanka_resid<<<count, VCB, max_nodes * sizeof(int), s>>>(v, order, roff, rbuf, b, x);
     AMG_CHECK_LAUNCH();
-    k_vanka_apply<<<ntiles, VB, 0, s>>>(v, order, tpre, count, roff, rbuf, x, omega);
+    k_vanka_apply<4><<<ntiles, 256, 0, s>>>(v, order, tpre, count, roff, rbuf, x, omega);
     AMG_CHECK_LAUNCH();
 }
 

@@ -523,7 +523,7 @@ static void vanka_step(amg_ctx *h, int l, const double *b, double *x) {
         else if (V.path == 3)
             launch_vanka_colour_rows(v, V.order.p + V.cptr[c], V.tpre.p + V.cptr[c],
                                      V.rpre[VankaData::rg_index(V.rg)].p + V.cptr[c], cnt, V.ntiles[c],
-                                     V.nrunits[VankaData::rg_index(V.rg)][c], V.rg, V.roff.p, V.rbuf.p, b, x,
+                                     V.nrunits[VankaData::rg_index(V.rg)][c], V.rg, V.aw, V.roff.p, V.rbuf.p, b, x,
                                      h->prm.vanka_omega, h->stream);
         else if (V.path == 1)
             launch_vanka_colour_split(v, V.order.p + V.cptr[c], V.tpre.p + V.cptr[c], cnt, V.ntiles[c], V.max_nodes,

@@ -48,10 +48,10 @@ void launch_vanka_colour_split(const VankaView &v, const int *order, const int *
                                double omega, hipStream_t s);
 // the residual spread as in the tiled form (rpre, nrunits, rg), then the
 // corrections over 64-row tiles of every inverse as the two-kernel form
-// (tpre, ntiles)
+// (tpre, ntiles), aw (4, 8 or 16) wavefronts per tile splitting its columns
 void launch_vanka_colour_rows(const VankaView &v, const int *order, const int *tpre, const int *rpre, int count,
-                              int ntiles, int nrunits, int rg, const int64_t *roff, double *rbuf, const double *b,
-                              double *x, double omega, hipStream_t s);
+                              int ntiles, int nrunits, int rg, int aw, const int64_t *roff, double *rbuf,
+                              const double *b, double *x, double omega, hipStream_t s);
 // the same colour in three kernels for colours of few, large patches: the
 // residuals into rbuf, rg lanes per row (16, 32 or 64) and 256 / rg node
 // rows per workgroup (rpre: prefix of ceil((n_P + 1) / (256 / rg)) over the

@@ -215,7 +215,8 @@ class AMGSolver:
         row; entries per lane and loop trip (1, 2 or 4). 'vanka': the
         level's Vanka sweeps with `lanes` (16, 32, 64) lanes per residual
         row, then the corrections over 2-D tiles of the inverses (trip 1)
-        or over 64-row tiles (trip 2)."""
+        or over 64-row tiles (trip 2); 'vanka_apply': the latter with
+        `lanes` = 4, 8 or 16 wavefronts per tile."""
         C.check(C.lib().amg_set_launch_shape(self.h, level, C.SHAPE[kernels], int(lanes), int(trip),
                                              1 if xcd else 0), "amg_set_launch_shape")
 

@@ -76,13 +76,18 @@ def test_vanka_tiled_sweep_every_residual_width(case):
         for form in (1, 2):
             for lanes in (16, 32, 64):
                 s.set_launch_shape(l, "vanka", lanes, form)
-                xd = dev(z)
-                s.smooth(l, dev(b), xd)
-                assert rel(host(xd), ref) < 1e-11, (name, l, form, lanes)
+                for waves in ((4, 8, 16) if form == 2 else (None,)):
+                    if waves:
+                        s.set_launch_shape(l, "vanka_apply", waves)
+                    xd = dev(z)
+                    s.smooth(l, dev(b), xd)
+                    assert rel(host(xd), ref) < 1e-11, (name, l, form, lanes, waves)
     with pytest.raises(amg.AmgError):
         s.set_launch_shape(0, "vanka", 8)
     with pytest.raises(amg.AmgError):
         s.set_launch_shape(0, "vanka", 32, 4)
+    with pytest.raises(amg.AmgError):
+        s.set_launch_shape(0, "vanka_apply", 32)
     with pytest.raises(amg.AmgError):
         s.set_launch_shape(len(h.levels) - 1, "vanka", 16)
     s.close()
