@@ -31,7 +31,8 @@ __global__ void __launch_bounds__(SB) k_blk(const BlkArgsT<T> a) {
     T bo = T(0), yo = T(0), ds = T(0);
     if (ep) {
         if constexpr (OP == BLK_RESID || OP == BLK_SGS_P) bo = a.b[o];
-        if constexpr (OP == BLK_ADD || OP == BLK_SUB || OP == BLK_SGS_P) yo = a.y[o];
+        if constexpr (OP == BLK_ADD || OP == BLK_SUB) yo = a.y[o];
+        if constexpr (OP == BLK_SGS_P) yo = a.y_zero ? T(0) : a.y[o];
         if constexpr (OP == BLK_SGS_P) ds = a.dscale[i];
     }
     T s[BR];
@@ -135,7 +136,7 @@ template void launch_blk<double>(int, int, int, int, const BlkArgsT<double> &, h
 template void launch_blk<float>(int, int, int, int, const BlkArgsT<float> &, hipStream_t);
 
 template <typename T>
-__global__ void k_sgs_u(int64_t n, int64_t ld, const T *dinv, const T *r, T damping, T *t, T *u) {
+__global__ void k_sgs_u(int64_t n, int64_t ld, const T *dinv, const T *r, T damping, T *t, T *u, bool u_zero) {
     const int64_t q = static_cast<int64_t>(blockIdx.x) * SB + threadIdx.x;
     if (q >= 3 * n) return;
     const int64_t i = q / 3;
@@ -144,18 +145,19 @@ __global__ void k_sgs_u(int64_t n, int64_t ld, const T *dinv, const T *r, T damp
                 dinv[(3 * c + 2) * ld + i] * r[3 * i + 2];
     const T v = damping * d;
     t[q] = v;
-    u[q] += v;
+    u[q] = u_zero ? v : u[q] + v;
 }
 
 template <typename T>
-void launch_sgs_u(int64_t n, int64_t ld, const T *dinv, const T *r, T damping, T *t, T *u, hipStream_t s) {
+void launch_sgs_u(int64_t n, int64_t ld, const T *dinv, const T *r, T damping, T *t, T *u, bool u_zero,
+                  hipStream_t s) {
     if (n <= 0) return;
-    k_sgs_u<T><<<ceil_div(3 * n, SB), SB, 0, s>>>(n, ld, dinv, r, damping, t, u);
+    k_sgs_u<T><<<ceil_div(3 * n, SB), SB, 0, s>>>(n, ld, dinv, r, damping, t, u, u_zero);
     AMG_CHECK_LAUNCH();
 }
 template void launch_sgs_u<double>(int64_t, int64_t, const double *, const double *, double, double *, double *,
-                                   hipStream_t);
-template void launch_sgs_u<float>(int64_t, int64_t, const float *, const float *, float, float *, float *,
+                                   bool, hipStream_t);
+template void launch_sgs_u<float>(int64_t, int64_t, const float *, const float *, float, float *, float *, bool,
                                   hipStream_t);
 
 __global__ void k_sgs_scale(int np, const int *brow, const int *bcol, const double *bval, int64_t bnnz,

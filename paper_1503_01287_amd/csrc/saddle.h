@@ -38,6 +38,8 @@ struct BlkArgsT {
     const T *c_val = nullptr;
     const T *c_x = nullptr;
     T c_sign = 1;
+    // BLK_SGS_P: y starts from zero (y is written, not read)
+    int y_zero = 0;
 };
 using BlkArgs = BlkArgsT<double>;
 using BlkArgsF = BlkArgsT<float>;
@@ -47,9 +49,11 @@ template <typename T>
 void launch_blk(int br, int bc, int op, int G, const BlkArgsT<T> &a, hipStream_t s);
 
 // sGS velocity step on the first n nodes: t_i = damping * D_i^{-1} r_i;
-// u_i += t_i (3x3 blocks, dinv planes of stride ld >= n)
+// u_i += t_i, or u_i = t_i when u starts from zero (u_zero: u is not read)
+// (3x3 blocks, dinv planes of stride ld >= n)
 template <typename T>
-void launch_sgs_u(int64_t n, int64_t ld, const T *dinv, const T *r, T damping, T *t, T *u, hipStream_t s);
+void launch_sgs_u(int64_t n, int64_t ld, const T *dinv, const T *r, T damping, T *t, T *u, bool u_zero,
+                  hipStream_t s);
 // sGS pressure scaling 1 / (damping * sum_k b_k^T D_{col k}^{-1} b_k + C_pp)
 void launch_sgs_scale(int np, const int *brow, const int *bcol, const double *bval, int64_t bnnz,
                       const double *dinv, int64_t nv, double damping, const int *crow, const int *ccol,

@@ -278,12 +278,15 @@ static void sgs_step(amg_ctx *h, int l, const T *b, T *x, bool x_zero) {
         saddle_residual_rows<T>(h, l, b, x, SV<T>::r(L), L.nA, L.npA);
         r = SV<T>::r(L);
     }
-    launch_sgs_u<T>(L.nA, L.n, SV<T>::dinv(L), r, static_cast<T>(h->prm.sgs_damping), SV<T>::t(L), x, h->stream);
+    // from a zero guess the step writes x outright (no fill before it)
+    launch_sgs_u<T>(L.nA, L.n, SV<T>::dinv(L), r, static_cast<T>(h->prm.sgs_damping), SV<T>::t(L), x, x_zero,
+                    h->stream);
     BlkArgsT<T> bb = blkT<T>(L.B, SV<T>::B(L));
     bb.nrows = L.npA;
     bb.x = SV<T>::t(L);
     bb.b = r + nu;
     bb.y = x + nu;
+    bb.y_zero = x_zero ? 1 : 0;
     bb.dscale = SV<T>::sgs(L);
     bb.omega = static_cast<T>(h->prm.sgs_omega);
     launch_blk<T>(1, 3, BLK_SGS_P, L.Gb, bb, h->stream);
@@ -564,7 +567,9 @@ static void saddle_cycle(amg_ctx *h, int l, const T *b, T *x, bool x_zero) {
     }
     if (L.nA == 0) return;
     const amg_params &p = h->prm;
-    if (x_zero) {
+    // a zero guess is filled in unless the first smoothing step writes every
+    // row of x without reading it (sGS)
+    if (x_zero && !(p.smoother == AMG_SMOOTH_SGS && p.pre >= 1)) {
         fillv(x, 3 * static_cast<int64_t>(L.nA), h->stream);
         fillv(x + nu, L.npA, h->stream);
     }
