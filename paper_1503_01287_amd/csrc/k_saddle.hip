@@ -34,6 +34,11 @@ __global__ void __launch_bounds__(SB) k_blk(const BlkArgsT<T> a) {
         if constexpr (OP == BLK_ADD || OP == BLK_SUB) yo = a.y[o];
         if constexpr (OP == BLK_SGS_P) yo = a.y_zero ? T(0) : a.y[o];
         if constexpr (OP == BLK_SGS_P) ds = a.dscale[i];
+        if constexpr (OP == BLK_ADD_SCALED) {
+            bo = a.b[o];
+            yo = a.y_zero ? T(0) : a.y[o];
+            ds = a.dscale[o];
+        }
     }
     T s[BR];
 #pragma unroll
@@ -85,6 +90,8 @@ __global__ void __launch_bounds__(SB) k_blk(const BlkArgsT<T> a) {
         if constexpr (BR == 1)
             if (a.c_rowptr) v = v + a.c_sign * sc;
         a.y[o] = v;
+    } else if constexpr (OP == BLK_ADD_SCALED) {
+        a.y[o] = yo + ds * (bo + sv);
     } else {
         a.y[o] = yo + a.omega * ds * (sv - bo);
     }
@@ -106,7 +113,13 @@ static void launch_blk_g(int op, const BlkArgsT<T> &a, hipStream_t s) {
                 k_blk<T, BR, BC, G, BLK_SGS_P><<<nb, SB, 0, s>>>(a);
                 break;
             }
-            [[fallthrough]];
+            throw Error(AMG_EINVAL, "block kernel: BLK_SGS_P needs 1-row blocks");
+        case BLK_ADD_SCALED:
+            if constexpr (BR == 3 && BC == 1) {
+                k_blk<T, BR, BC, G, BLK_ADD_SCALED><<<nb, SB, 0, s>>>(a);
+                break;
+            }
+            throw Error(AMG_EINVAL, "block kernel: BLK_ADD_SCALED needs 3x1 blocks");
         default: throw Error(AMG_EINVAL, "block kernel: unsupported operation");
     }
     AMG_CHECK_LAUNCH();
@@ -357,6 +370,22 @@ __global__ void k_add_scaled(int64_t n, const T *d, const T *w, T *u) {
          i += static_cast<int64_t>(gridDim.x) * SB)
         u[i] += d[i] * w[i];
 }
+
+template <typename T>
+__global__ void k_neg(int64_t n, const T *x, T *y) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * SB + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * SB)
+        y[i] = -x[i];
+}
+
+template <typename T>
+void launch_neg(int64_t n, const T *x, T *y, hipStream_t s) {
+    if (n <= 0) return;
+    k_neg<T><<<grid_s(n), SB, 0, s>>>(n, x, y);
+    AMG_CHECK_LAUNCH();
+}
+template void launch_neg<double>(int64_t, const double *, double *, hipStream_t);
+template void launch_neg<float>(int64_t, const float *, float *, hipStream_t);
 
 template <typename T>
 void launch_add_scaled(int64_t n, const T *d, const T *w, T *u, hipStream_t s) {

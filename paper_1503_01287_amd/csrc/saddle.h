@@ -16,6 +16,7 @@ enum BlkOp : int {
     BLK_SUB = 2,    // y -= s
     BLK_RESID = 3,  // y = b - s
     BLK_SGS_P = 4,  // (1x3 rows of B) y_p += omega * dscale_p * (s - b_p)
+    BLK_ADD_SCALED = 5,  // (3x1 rows of B^T) y_o += dscale_o * (b_o + s_o), per component o
 };
 
 // T = double (FP64 path) or float (reduced-precision cycle: FP32 values,
@@ -38,11 +39,15 @@ struct BlkArgsT {
     const T *c_val = nullptr;
     const T *c_x = nullptr;
     T c_sign = 1;
-    // BLK_SGS_P: y starts from zero (y is written, not read)
+    // BLK_SGS_P, BLK_ADD_SCALED: y starts from zero (y is written, not read)
     int y_zero = 0;
 };
 using BlkArgs = BlkArgsT<double>;
 using BlkArgsF = BlkArgsT<float>;
+
+// y = -x
+template <typename T>
+void launch_neg(int64_t n, const T *x, T *y, hipStream_t s);
 
 // br, bc in {1, 3}; G lanes per row
 template <typename T>

@@ -106,8 +106,6 @@ static BlkArgsT<T> blkT(const DMat &m, const T *val) {
 
 static void fillv(double *x, int64_t n, hipStream_t s) { launch_fill(x, 0.0, n, s); }
 static void fillv(float *x, int64_t n, hipStream_t s) { launch_fill_f32(x, 0.f, n, s); }
-static void copyv(double *d, const double *x, int64_t n, hipStream_t s) { launch_copy(d, x, n, s); }
-static void copyv(float *d, const float *x, int64_t n, hipStream_t s) { launch_copy_f32(d, x, n, s); }
 static void axpbyv(double *y, const double *x, double a, double b, int64_t n, hipStream_t s) {
     launch_axpby(y, x, a, b, n, s);
 }
@@ -484,11 +482,12 @@ static void bs_step(amg_ctx *h, int l, const T *b, T *x, bool x_zero) {
     Level &L = h->lv[l];
     hipStream_t s = h->stream;
     const int64_t nu = 3 * static_cast<int64_t>(L.n);
-    T *r = SV<T>::r(L);
-    if (x_zero)
-        copyv(r, b, L.vlen(), s);
-    else
-        saddle_residual_rows<T>(h, l, b, x, r, L.nA, L.npA);
+    // from a zero guess the residual is b and the step writes x outright
+    const T *r = b;
+    if (!x_zero) {
+        saddle_residual_rows<T>(h, l, b, x, SV<T>::r(L), L.nA, L.npA);
+        r = SV<T>::r(L);
+    }
     launch_scale<T>(3 * static_cast<int64_t>(L.nA), SV<T>::ahat(L), r, SV<T>::t(L), s);
     SchurLevel &q0 = L.schur.lv[0];
     BlkArgsT<T> bb = blkT<T>(L.B, SV<T>::B(L));
@@ -498,13 +497,19 @@ static void bs_step(amg_ctx *h, int l, const T *b, T *x, bool x_zero) {
     bb.y = SV<T>::sb(q0);
     launch_blk<T>(1, 3, BLK_RESID, L.Gb, bb, s);
     schur_vcycle<T>(h, l, 0, SV<T>::sb(q0), SV<T>::sx(q0));
-    axpbyv(x + nu, SV<T>::sx(q0), T(-1), T(1), L.npA, s);
+    if (x_zero)
+        launch_neg<T>(L.npA, SV<T>::sx(q0), x + nu, s);
+    else
+        axpbyv(x + nu, SV<T>::sx(q0), T(-1), T(1), L.npA, s);
+    // u += ahat (r_u + B^T s_x), one pass
     BlkArgsT<T> bt = blkT<T>(L.Bt, SV<T>::Bt(L));
     bt.nrows = L.nA;
     bt.x = SV<T>::sx(q0);
-    bt.y = r;
-    launch_blk<T>(3, 1, BLK_ADD, L.Gbt, bt, s);
-    launch_add_scaled<T>(3 * static_cast<int64_t>(L.nA), SV<T>::ahat(L), r, x, s);
+    bt.b = r;
+    bt.y = x;
+    bt.dscale = SV<T>::ahat(L);
+    bt.y_zero = x_zero ? 1 : 0;
+    launch_blk<T>(3, 1, BLK_ADD_SCALED, L.Gbt, bt, s);
 }
 
 // One multiplicative Vanka sweep (Section 3.3): the patches colour by
@@ -568,8 +573,8 @@ static void saddle_cycle(amg_ctx *h, int l, const T *b, T *x, bool x_zero) {
     if (L.nA == 0) return;
     const amg_params &p = h->prm;
     // a zero guess is filled in unless the first smoothing step writes every
-    // row of x without reading it (sGS)
-    if (x_zero && !(p.smoother == AMG_SMOOTH_SGS && p.pre >= 1)) {
+    // row of x without reading it (sGS, Braess-Sarazin)
+    if (x_zero && !((p.smoother == AMG_SMOOTH_SGS || p.smoother == AMG_SMOOTH_BS) && p.pre >= 1)) {
         fillv(x, 3 * static_cast<int64_t>(L.nA), h->stream);
         fillv(x + nu, L.npA, h->stream);
     }
